@@ -1,0 +1,899 @@
+/*
+ * iugkp_oracle.c -- plain single-threaded FP64 CPU oracle of the IUGKP
+ * steady gray phonon iteration (arXiv 2506.09465, Sections 2 and 3).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+ * baseline of the benchmark.  It shares no code with the HIP library.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fPIC -shared.
+ * Every floating-point operation is a plain IEEE-754 binary64 operation in
+ * round-to-nearest-even, written in the order that the readings below fix.
+ *
+ * Readings of points the paper leaves open (each is a fixed rule here):
+ *  R1 Walls are black, diffusely emitting equilibrium walls (the boundary
+ *     distribution is an equilibrium, Sec. 2).  A wall face of area A at
+ *     energy E_w emits E_w * lambda_min * A / 4 per iteration (the hemispherical
+ *     flux E_w |V_g| / 4 times the common time scale tau_min), with
+ *     cosine-law (Lambertian) directions: cosine to the inward normal sqrt(u).
+ *  R2 Directions are 3D unit vectors (Sec. 2); in 1D and 2D the particle
+ *     moves along the in-plane projection, the free path is the 3D length.
+ *  R3 Stateless emitters: every cell and every wall face emits the same
+ *     number N of particles per iteration from fresh samples (Sec. 3.1 steps
+ *     (1)-(3) resample every particle from the local equilibrium).
+ *  R4 Null collisions (Sec. 3.2) are followed in the same iteration (delta
+ *     tracking): a rejected candidate tallies W and flies on from where it
+ *     stopped with a new free path; the accepted one tallies both W and W^h.
+ *     The macroscopic energy comes from W, re-emission from W^h (= D here).
+ *  R5 Energies are int64 fixed-point numbers with scale 2^F; each emitter's
+ *     integer energy is split over its N particles with an exact remainder,
+ *     so every tally is an exact, order-independent integer sum.
+ *  R6 Newton (Sec. 3.3) is read as E^{n+1} = E^{n+1/2} + A^{-1}(E^{n+1/2} - E^n),
+ *     A the conservative 3/5-point discretisation of -div(D grad .) with
+ *     Robin wall terms, D per cell given as problem data.
+ *  R7 Residual: res_n = ||E^{n+1} - E^n||_2 / ||E^1 - E^0||_2.
+ */
+#include "iugkp_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_SEGMENTS (1u << 20)   /* a flight's last allowed segment always ends real */
+#define ORC_TWO62 4611686018427387904.0
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10: Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11.  Ten rounds of the 4x32 Philox S-box with the    */
+/* published multipliers and Weyl key increments.                            */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 53-bit uniform on [0,1): the top 27 bits of hi and top 26 bits of lo. */
+double orc_u53(uint32_t hi, uint32_t lo)
+{
+  uint64_t m = ((uint64_t)(hi >> 5) << 26) | (uint64_t)(lo >> 6);
+  return (double)m * 0x1p-53;
+}
+
+/* Draw d of particle k of emitter e in Philox slot s:
+ * counter = (d, k, e, s), key = (seed low word, seed high word). */
+static void orc_draw(uint64_t seed, uint32_t slot, uint32_t e, uint32_t k, uint32_t d,
+                     double *u0, double *u1)
+{
+  uint32_t ctr[4] = {d, k, e, slot};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t o[4];
+  orc_philox4x32_10(ctr, key, o);
+  *u0 = orc_u53(o[0], o[1]);
+  *u1 = orc_u53(o[2], o[3]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Natural logarithm from + - * / only (so that it is reproducible bit for   */
+/* bit): x = m 2^e with m in (sqrt(2)/2, sqrt(2)], f = m - 1 (exact),        */
+/* s = f / (2 + f), ln m = 2 atanh(s) = f - s (f - R) with                   */
+/* R = 2 (z/3 + z^2/5 + ... + z^10/21), z = s^2 (the atanh Taylor series;    */
+/* 2s = f - f s).  ln 2 is split in a high part with trailing zero bits and  */
+/* a low part (Cody-Waite).  Defined for finite normal x > 0.                */
+/* ------------------------------------------------------------------------ */
+double orc_log(double x)
+{
+  const double ln2_hi = 6.93147180369123816490e-01;
+  const double ln2_lo = 1.90821492927058770002e-10;
+  const double sqrt2 = 1.41421356237309504880;
+  uint64_t bits;
+  memcpy(&bits, &x, sizeof bits);
+  int e = (int)((bits >> 52) & 0x7ffu) - 1023;
+  uint64_t mbits = (bits & 0x000fffffffffffffull) | (0x3ffull << 52);
+  double m;
+  memcpy(&m, &mbits, sizeof m);            /* m in [1, 2) */
+  if (m > sqrt2) {
+    m = m * 0.5;
+    e = e + 1;
+  }
+  double f = m - 1.0;
+  double s = f / (2.0 + f);
+  double z = s * s;
+  double R = 2.0 / 21.0;
+  R = R * z + 2.0 / 19.0;
+  R = R * z + 2.0 / 17.0;
+  R = R * z + 2.0 / 15.0;
+  R = R * z + 2.0 / 13.0;
+  R = R * z + 2.0 / 11.0;
+  R = R * z + 2.0 / 9.0;
+  R = R * z + 2.0 / 7.0;
+  R = R * z + 2.0 / 5.0;
+  R = R * z + 2.0 / 3.0;
+  R = R * z;
+  double corr = s * (f - R);
+  double de = (double)e;
+  return de * ln2_hi + ((de * ln2_lo - corr) + f);
+}
+
+/* ------------------------------------------------------------------------ */
+/* cos(2 pi u) for u in [0, 1): exact quarter-turn reduction t = 4u,         */
+/* q = floor(t), f = t - q, fold f > 1/2 to 1 - f, then Taylor polynomials   */
+/* of sin and cos on [0, pi/4] (to x^19 and x^18).                           */
+/* ------------------------------------------------------------------------ */
+double orc_cos2pi(double u)
+{
+  const double half_pi = 1.57079632679489661923;
+  double t = 4.0 * u;
+  int q = (int)t;
+  double f = t - (double)q;
+  int folded = 0;
+  double g = f;
+  if (f > 0.5) {
+    g = 1.0 - f;
+    folded = 1;
+  }
+  double x = half_pi * g;
+  double z = x * x;
+  double c = -1.0 / 6402373705728000.0;        /* -1/18! */
+  c = c * z + 1.0 / 20922789888000.0;          /*  1/16! */
+  c = c * z - 1.0 / 87178291200.0;             /* -1/14! */
+  c = c * z + 1.0 / 479001600.0;               /*  1/12! */
+  c = c * z - 1.0 / 3628800.0;                 /* -1/10! */
+  c = c * z + 1.0 / 40320.0;                   /*  1/8!  */
+  c = c * z - 1.0 / 720.0;                     /* -1/6!  */
+  c = c * z + 1.0 / 24.0;                      /*  1/4!  */
+  c = c * z - 1.0 / 2.0;                       /* -1/2!  */
+  c = c * z + 1.0;
+  double s = -1.0 / 121645100408832000.0;      /* -1/19! */
+  s = s * z + 1.0 / 355687428096000.0;         /*  1/17! */
+  s = s * z - 1.0 / 1307674368000.0;           /* -1/15! */
+  s = s * z + 1.0 / 6227020800.0;              /*  1/13! */
+  s = s * z - 1.0 / 39916800.0;                /* -1/11! */
+  s = s * z + 1.0 / 362880.0;                  /*  1/9!  */
+  s = s * z - 1.0 / 5040.0;                    /* -1/7!  */
+  s = s * z + 1.0 / 120.0;                     /*  1/5!  */
+  s = s * z - 1.0 / 6.0;                       /* -1/3!  */
+  s = s * z + 1.0;
+  s = x * s;
+  /* cos(f pi/2) and sin(f pi/2) */
+  double cf = folded ? s : c;
+  double sf = folded ? c : s;
+  switch (q) {
+    case 0: return cf;
+    case 1: return -sf;
+    case 2: return -cf;
+    default: return sf;
+  }
+}
+
+/* Particle k's share of an emitter's integer energy G over n particles:
+ * floor(G/n) plus one for the first (G - n floor(G/n)) particles. */
+int64_t orc_split_weight(int64_t G, uint64_t n, uint64_t k)
+{
+  int64_t nn = (int64_t)n;
+  int64_t base = G / nn;
+  if ((G % nn) != 0 && G < 0) base -= 1;
+  int64_t rem = G - base * nn;
+  return base + ((int64_t)k < rem ? 1 : 0);
+}
+
+/* Fixed-order sum: zero-padded blocks of 256 in index order, each reduced by
+ * halving strides (v[i] += v[i+s], s = 128, 64, ..., 1); the block sums are
+ * reduced the same way, recursively, until one value is left. */
+static double orc_tree256(const double *v, uint64_t n)
+{
+  double buf[256];
+  for (uint64_t i = 0; i < 256; ++i) buf[i] = (i < n) ? v[i] : 0.0;
+  for (int s = 128; s >= 1; s /= 2)
+    for (int i = 0; i < s; ++i) buf[i] = buf[i] + buf[i + s];
+  return buf[0];
+}
+
+double orc_tree_sum(const double *v, uint64_t n)
+{
+  if (n == 0) return 0.0;
+  uint64_t nb = (n + 255) / 256;
+  double *part = (double *)malloc(nb * sizeof(double));
+  for (uint64_t b = 0; b < nb; ++b) {
+    uint64_t len = n - 256 * b;
+    if (len > 256) len = 256;
+    part[b] = orc_tree256(v + 256 * b, len);
+  }
+  double r = (nb == 1) ? part[0] : orc_tree_sum(part, nb);
+  free(part);
+  return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Problem set-up                                                            */
+/* ------------------------------------------------------------------------ */
+static int orc_nb(const orc_problem *p) { return 2 * p->ny + (p->dim == 2 ? 2 * p->nx : 0); }
+
+static int orc_validate(const orc_problem *p)
+{
+  if (!p || !p->tau || !p->wall_T) return ORC_E_INVALID_ARG;
+  if (p->dim != 1 && p->dim != 2) return ORC_E_INVALID_ARG;
+  if (p->nx < 1 || p->ny < 1 || (p->dim == 1 && p->ny != 1)) return ORC_E_INVALID_ARG;
+  if (!(p->dx > 0.0) || !(p->dy > 0.0) || !isfinite(p->dx) || !isfinite(p->dy))
+    return ORC_E_INVALID_ARG;
+  if (!(p->cv > 0.0) || !(p->vg > 0.0) || !isfinite(p->cv) || !isfinite(p->vg) ||
+      !isfinite(p->t_ref))
+    return ORC_E_INVALID_ARG;
+  int nc = p->nx * p->ny;
+  double tmin = INFINITY, tmax = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    if (!(p->tau[c] > 0.0) || !isfinite(p->tau[c])) return ORC_E_INVALID_ARG;
+    if (p->tau[c] < tmin) tmin = p->tau[c];
+    if (p->tau[c] > tmax) tmax = p->tau[c];
+  }
+  if (tmax > 1e6 * tmin) return ORC_E_INVALID_ARG;
+  for (int b = 0; b < orc_nb(p); ++b)
+    if (!isfinite(p->wall_T[b])) return ORC_E_INVALID_ARG;
+  if (p->T_init)
+    for (int c = 0; c < nc; ++c)
+      if (!isfinite(p->T_init[c])) return ORC_E_INVALID_ARG;
+  return ORC_OK;
+}
+
+/* Scale exponent F = 62 - ceil(log2 B) with
+ * B = 4 max(|E_wall|, |E_0|) (sum of cell volumes + lambda_min * (sum of wall areas) / 4),
+ * the bound on one iteration's total |emission| times a safety factor 4. */
+int orc_fixed_exponent(const orc_problem *p, double *tau_min_out)
+{
+  int nc = p->nx * p->ny;
+  double tmin = p->tau[0];
+  for (int c = 1; c < nc; ++c)
+    if (p->tau[c] < tmin) tmin = p->tau[c];
+  if (tau_min_out) *tau_min_out = tmin;
+  double lam_min = p->vg * tmin;
+  double maxabs = 0.0;
+  for (int b = 0; b < orc_nb(p); ++b) {
+    double ew = fabs(p->cv * (p->wall_T[b] - p->t_ref));
+    if (ew > maxabs) maxabs = ew;
+  }
+  if (p->T_init)
+    for (int c = 0; c < nc; ++c) {
+      double e0 = fabs(p->cv * (p->T_init[c] - p->t_ref));
+      if (e0 > maxabs) maxabs = e0;
+    }
+  double vol = (double)nc * (p->dx * p->dy);
+  double area = (p->dim == 2) ? ((2.0 * (double)p->ny) * p->dy + (2.0 * (double)p->nx) * p->dx)
+                              : 2.0;
+  double total = vol + (lam_min * area) / 4.0;
+  double B = (4.0 * maxabs) * total;
+  if (!(B > 0.0)) return 62;
+  int e;
+  double m = frexp(B, &e);          /* B = m 2^e, m in [0.5, 1) */
+  int ceil_log2 = (m == 0.5) ? e - 1 : e;
+  return 62 - ceil_log2;
+}
+
+/* ------------------------------------------------------------------------ */
+/* State                                                                     */
+/* ------------------------------------------------------------------------ */
+struct orc_state {
+  orc_problem p;
+  orc_options o;
+  double *tau, *wall_T, *diff_x, *diff_y;
+  int nc, nb, ne, nfx, nfy;
+  uint64_t N;
+  int F;
+  double tau_min, lam_min, V;
+  double *ratio;       /* tau_min / tau_c */
+  double *E;           /* E^n */
+  double *E_half;      /* W / V of the last iteration */
+  int64_t *G;          /* emission energies of the next iteration, per emitter */
+  int64_t *D, *W, *Phix, *Phiy, *B;
+  double *gx, *gy, *diag;
+  uint32_t iter;
+  double d0, res;
+  double *res_hist;
+  int res_cap;
+  uint64_t flights, segments, crossings, tot_flights, tot_segments, tot_crossings;
+  int cg_last, cg_total;
+};
+
+typedef struct {
+  int64_t *D, *W, *Phix, *Phiy, *B;
+  int faces;
+  uint64_t crossings;
+  int32_t *events;     /* optional crossing log */
+  int n_events, max_events;
+} orc_tally;
+
+/* int64 of round-to-nearest-even(ldexp(v, F)); returns 0 and sets *ok = 0 on overflow. */
+static int64_t orc_to_fixed(double v, int F, int *ok)
+{
+  double s = ldexp(v, F);
+  if (!(fabs(s) <= ORC_TWO62)) {
+    *ok = 0;
+    return 0;
+  }
+  return (int64_t)rint(s);
+}
+
+static int orc_check_budget(const int64_t *G, int n)
+{
+  uint64_t acc = 0;
+  const uint64_t lim = (uint64_t)1 << 62;
+  for (int i = 0; i < n; ++i) {
+    uint64_t a = (G[i] < 0) ? (uint64_t)0 - (uint64_t)G[i] : (uint64_t)G[i];
+    if (a > lim) return 0;
+    acc += a;
+    if (acc > lim) return 0;
+  }
+  return 1;
+}
+
+/* Newton operator (reading R6): face conductances and diagonal.
+ * Interior face between cells a|b: H(D_a, D_b) / d^2, H the harmonic mean;
+ * wall face of cell c: D_c / (d (d/2 + 2 lambda_c / 3)), lambda_c = |V_g| tau_c
+ * (extrapolated wall distance 2 lambda / 3). */
+int orc_newton_operator(const orc_problem *p, double *gx, double *gy, double *diag)
+{
+  int nx = p->nx, ny = p->ny;
+  if (!p->diff_x || (p->dim == 2 && !p->diff_y)) return ORC_E_INVALID_ARG;
+  for (int iy = 0; iy < ny; ++iy)
+    for (int kx = 0; kx <= nx; ++kx) {
+      double g;
+      if (kx == 0 || kx == nx) {
+        int c = iy * nx + (kx == 0 ? 0 : nx - 1);
+        double lam = p->vg * p->tau[c];
+        double den = p->dx * (p->dx / 2.0 + (2.0 * lam) / 3.0);
+        g = p->diff_x[c] / den;
+      } else {
+        double a = p->diff_x[iy * nx + kx - 1], b = p->diff_x[iy * nx + kx];
+        double h = ((2.0 * a) * b) / (a + b);
+        g = h / (p->dx * p->dx);
+      }
+      gx[iy * (nx + 1) + kx] = g;
+    }
+  if (p->dim == 2)
+    for (int ky = 0; ky <= ny; ++ky)
+      for (int ix = 0; ix < nx; ++ix) {
+        double g;
+        if (ky == 0 || ky == ny) {
+          int c = (ky == 0 ? 0 : ny - 1) * nx + ix;
+          double lam = p->vg * p->tau[c];
+          double den = p->dy * (p->dy / 2.0 + (2.0 * lam) / 3.0);
+          g = p->diff_y[c] / den;
+        } else {
+          double a = p->diff_y[(ky - 1) * nx + ix], b = p->diff_y[ky * nx + ix];
+          double h = ((2.0 * a) * b) / (a + b);
+          g = h / (p->dy * p->dy);
+        }
+        gy[ky * nx + ix] = g;
+      }
+  for (int iy = 0; iy < ny; ++iy)
+    for (int ix = 0; ix < nx; ++ix) {
+      double d = gx[iy * (nx + 1) + ix] + gx[iy * (nx + 1) + ix + 1];
+      if (p->dim == 2) {
+        d = d + gy[iy * nx + ix];
+        d = d + gy[(iy + 1) * nx + ix];
+      }
+      diag[iy * nx + ix] = d;
+    }
+  return ORC_OK;
+}
+
+static void orc_apply(const orc_problem *p, const double *gx, const double *gy,
+                      const double *diag, const double *x, double *y)
+{
+  int nx = p->nx, ny = p->ny;
+  for (int iy = 0; iy < ny; ++iy)
+    for (int ix = 0; ix < nx; ++ix) {
+      int c = iy * nx + ix;
+      double acc = diag[c] * x[c];
+      if (ix > 0) acc = acc - gx[iy * (nx + 1) + ix] * x[c - 1];
+      if (ix < nx - 1) acc = acc - gx[iy * (nx + 1) + ix + 1] * x[c + 1];
+      if (p->dim == 2) {
+        if (iy > 0) acc = acc - gy[iy * nx + ix] * x[c - nx];
+        if (iy < ny - 1) acc = acc - gy[(iy + 1) * nx + ix] * x[c + nx];
+      }
+      y[c] = acc;
+    }
+}
+
+static double orc_dot(const double *a, const double *b, int n, double *tmp)
+{
+  for (int i = 0; i < n; ++i) tmp[i] = a[i] * b[i];
+  return orc_tree_sum(tmp, (uint64_t)n);
+}
+
+/* Conjugate gradients (Hestenes-Stiefel), x0 = 0, stop when
+ * r.r <= tol^2 (b.b). */
+int orc_cg(const orc_problem *p, const double *gx, const double *gy, const double *diag,
+           const double *b, double *x, double tol, int max_iters, int *iters_out)
+{
+  int n = p->nx * p->ny;
+  double *r = (double *)malloc(sizeof(double) * n);
+  double *pp = (double *)malloc(sizeof(double) * n);
+  double *Ap = (double *)malloc(sizeof(double) * n);
+  double *tmp = (double *)malloc(sizeof(double) * n);
+  for (int i = 0; i < n; ++i) {
+    x[i] = 0.0;
+    r[i] = b[i];
+    pp[i] = b[i];
+  }
+  double rr = orc_dot(r, r, n, tmp);
+  double thr = (tol * tol) * rr;
+  int it = 0, rc = ORC_OK, done = (rr == 0.0);
+  while (!done && it < max_iters) {
+    orc_apply(p, gx, gy, diag, pp, Ap);
+    double pAp = orc_dot(pp, Ap, n, tmp);
+    if (!(pAp > 0.0)) {
+      rc = ORC_E_CG_BREAKDOWN;
+      break;
+    }
+    double alpha = rr / pAp;
+    for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * pp[i];
+    for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * Ap[i];
+    double rr_new = orc_dot(r, r, n, tmp);
+    ++it;
+    if (rr_new <= thr) {
+      done = 1;
+      break;
+    }
+    double beta = rr_new / rr;
+    for (int i = 0; i < n; ++i) pp[i] = r[i] + beta * pp[i];
+    rr = rr_new;
+  }
+  if (rc == ORC_OK && !done) rc = ORC_E_CG_NOT_CONVERGED;
+  if (iters_out) *iters_out = it;
+  free(r);
+  free(pp);
+  free(Ap);
+  free(tmp);
+  return rc;
+}
+
+void orc_destroy(orc_state *s)
+{
+  if (!s) return;
+  free(s->tau); free(s->wall_T); free(s->diff_x); free(s->diff_y);
+  free(s->ratio); free(s->E); free(s->E_half); free(s->G);
+  free(s->D); free(s->W); free(s->Phix); free(s->Phiy); free(s->B);
+  free(s->gx); free(s->gy); free(s->diag); free(s->res_hist);
+  free(s);
+}
+
+static double *orc_dup(const double *a, int n)
+{
+  if (!a) return NULL;
+  double *r = (double *)malloc(sizeof(double) * (size_t)n);
+  memcpy(r, a, sizeof(double) * (size_t)n);
+  return r;
+}
+
+int orc_create(const orc_problem *p, const orc_options *o, orc_state **out)
+{
+  *out = NULL;
+  int rc = orc_validate(p);
+  if (rc) return rc;
+  if (!o || o->particles_per_iter < 1 || o->max_iters < 0 || o->avg_iters < 0)
+    return ORC_E_INVALID_ARG;
+  if (o->newton && (!p->diff_x || (p->dim == 2 && !p->diff_y) || !(o->cg_tol > 0.0) ||
+                    o->cg_max_iters < 1))
+    return ORC_E_INVALID_ARG;
+  orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
+  s->p = *p;
+  s->o = *o;
+  s->nc = p->nx * p->ny;
+  s->nb = orc_nb(p);
+  s->ne = s->nc + s->nb;
+  s->nfx = p->ny * (p->nx + 1);
+  s->nfy = (p->dim == 2) ? (p->ny + 1) * p->nx : 0;
+  s->tau = orc_dup(p->tau, s->nc);
+  s->wall_T = orc_dup(p->wall_T, s->nb);
+  s->diff_x = orc_dup(p->diff_x, s->nc);
+  s->diff_y = orc_dup(p->diff_y, s->nc);
+  s->p.tau = s->tau;
+  s->p.wall_T = s->wall_T;
+  s->p.diff_x = s->diff_x;
+  s->p.diff_y = s->diff_y;
+  s->p.T_init = NULL;
+  s->N = o->particles_per_iter / (uint64_t)s->ne;
+  if (s->N < 1) s->N = 1;
+  s->F = orc_fixed_exponent(p, &s->tau_min);
+  s->lam_min = p->vg * s->tau_min;
+  s->V = p->dx * p->dy;
+  s->ratio = (double *)malloc(sizeof(double) * s->nc);
+  s->E = (double *)malloc(sizeof(double) * s->nc);
+  s->E_half = (double *)calloc((size_t)s->nc, sizeof(double));
+  s->G = (int64_t *)calloc((size_t)s->ne, sizeof(int64_t));
+  s->D = (int64_t *)calloc((size_t)s->nc, sizeof(int64_t));
+  s->W = (int64_t *)calloc((size_t)s->nc, sizeof(int64_t));
+  s->Phix = (int64_t *)calloc((size_t)s->nfx, sizeof(int64_t));
+  s->Phiy = (int64_t *)calloc((size_t)(s->nfy ? s->nfy : 1), sizeof(int64_t));
+  s->B = (int64_t *)calloc((size_t)s->nb, sizeof(int64_t));
+  s->res_cap = o->max_iters + o->avg_iters + 8;
+  s->res_hist = (double *)calloc((size_t)s->res_cap, sizeof(double));
+  for (int c = 0; c < s->nc; ++c) {
+    s->ratio[c] = s->tau_min / s->tau[c];
+    double T0 = p->T_init ? p->T_init[c] : p->t_ref;
+    s->E[c] = p->cv * (T0 - p->t_ref);
+  }
+  int ok = 1;
+  /* cell emission: (E V) tau_min/tau (Sec. 3.2, candidate rate tau_min) */
+  for (int c = 0; c < s->nc; ++c) s->G[c] = orc_to_fixed((s->E[c] * s->V) * s->ratio[c], s->F, &ok);
+  /* wall emission, reading R1 */
+  for (int b = 0; b < s->nb; ++b) {
+    double A = (b < 2 * p->ny) ? p->dy : p->dx;
+    double ew = p->cv * (s->wall_T[b] - p->t_ref);
+    s->G[s->nc + b] = orc_to_fixed((ew * (s->lam_min * A)) / 4.0, s->F, &ok);
+  }
+  if (!ok || !orc_check_budget(s->G, s->ne)) {
+    orc_destroy(s);
+    return ORC_E_FIXED_OVERFLOW;
+  }
+  if (o->newton) {
+    s->gx = (double *)malloc(sizeof(double) * s->nfx);
+    s->gy = (double *)malloc(sizeof(double) * (s->nfy ? s->nfy : 1));
+    s->diag = (double *)malloc(sizeof(double) * s->nc);
+    orc_newton_operator(&s->p, s->gx, s->gy, s->diag);
+  }
+  *out = s;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The flight of one particle (Sec. 3.1 step (2), Sec. 3.2 steps (3)-(6))    */
+/* ------------------------------------------------------------------------ */
+
+/* March one straight segment of length ell from (x0,y0) in cell (*ix,*iy).
+ * Next x-face k (k = ix+1 moving +x, k = ix moving -x) is reached at
+ * t = (k dx - x0) * (1/sx); likewise y.  The earlier face is crossed while
+ * t < ell (strict); at equal t the x-face goes first.  Crossing a boundary
+ * face absorbs the particle.  Returns 1 if absorbed (b index in *bface). */
+static int orc_march(const orc_problem *p, double x0, double y0, int *ix, int *iy, double sx,
+                     double sy, double inv_sx, double inv_sy, double ell, int64_t q,
+                     orc_tally *t, int *bface)
+{
+  int nx = p->nx, ny = p->ny;
+  int stepx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+  int stepy = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+  int kx = (stepx > 0) ? *ix + 1 : *ix;
+  int ky = (stepy > 0) ? *iy + 1 : *iy;
+  for (;;) {
+    double tx = stepx ? ((double)kx * p->dx - x0) * inv_sx : INFINITY;
+    double ty = stepy ? ((double)ky * p->dy - y0) * inv_sy : INFINITY;
+    int axis_x = (tx <= ty);
+    double tt = axis_x ? tx : ty;
+    if (!(tt < ell)) return 0;
+    t->crossings++;
+    if (axis_x) {
+      int f = *iy * (nx + 1) + kx;
+      if (t->faces) t->Phix[f] += (stepx > 0) ? q : -q;
+      if (t->events && t->n_events < t->max_events) {
+        t->events[3 * t->n_events] = 0;
+        t->events[3 * t->n_events + 1] = f;
+        t->events[3 * t->n_events + 2] = stepx;
+        t->n_events++;
+      }
+      if (kx == 0 || kx == nx) {
+        *bface = (kx == 0) ? *iy : ny + *iy;
+        return 1;
+      }
+      *ix += stepx;
+      kx += stepx;
+    } else {
+      int f = ky * nx + *ix;
+      if (t->faces) t->Phiy[f] += (stepy > 0) ? q : -q;
+      if (t->events && t->n_events < t->max_events) {
+        t->events[3 * t->n_events] = 1;
+        t->events[3 * t->n_events + 1] = f;
+        t->events[3 * t->n_events + 2] = stepy;
+        t->n_events++;
+      }
+      if (ky == 0 || ky == ny) {
+        *bface = (ky == 0) ? 2 * ny + *ix : 2 * ny + nx + *ix;
+        return 1;
+      }
+      *iy += stepy;
+      ky += stepy;
+    }
+  }
+}
+
+static double orc_clamp(double v, double lo, double hi)
+{
+  if (v < lo) return lo;
+  if (v > hi) return hi;
+  return v;
+}
+
+/* Fly particle k of emitter e carrying q (q != 0). */
+static void orc_fly(orc_state *s, uint32_t slot, int e, uint32_t k, int64_t q, orc_tally *t,
+                    uint64_t *segs)
+{
+  const orc_problem *p = &s->p;
+  int nx = p->nx, ny = p->ny;
+  double ua, ub, uc, ud;
+  orc_draw(s->o.seed, slot, (uint32_t)e, k, 0u, &ua, &ub);
+  orc_draw(s->o.seed, slot, (uint32_t)e, k, 1u, &uc, &ud);
+  int ix, iy;
+  double x0, y0, sx, sy;
+  if (e < s->nc) {
+    /* equilibrium emission from a cell: uniform position, isotropic 3D direction */
+    ix = e % nx;
+    iy = e / nx;
+    x0 = ((double)ix + ua) * p->dx;
+    y0 = ((double)iy + ub) * p->dy;
+    double mu = 2.0 * uc - 1.0;
+    sx = mu;
+    sy = (p->dim == 2) ? sqrt((1.0 - mu) * (1.0 + mu)) * orc_cos2pi(ud) : 0.0;
+  } else {
+    /* wall emission (reading R1): cosine-law direction into the domain */
+    int b = e - s->nc;
+    double cn = sqrt(uc);
+    double tg = (p->dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * orc_cos2pi(ud) : 0.0;
+    if (b < ny) {                       /* left wall, row b */
+      ix = 0; iy = b;
+      x0 = 0.0; y0 = ((double)iy + ua) * p->dy;
+      sx = cn; sy = tg;
+    } else if (b < 2 * ny) {            /* right wall */
+      ix = nx - 1; iy = b - ny;
+      x0 = (double)nx * p->dx; y0 = ((double)iy + ua) * p->dy;
+      sx = -cn; sy = tg;
+    } else if (b < 2 * ny + nx) {       /* bottom wall, column */
+      ix = b - 2 * ny; iy = 0;
+      x0 = ((double)ix + ua) * p->dx; y0 = 0.0;
+      sx = tg; sy = cn;
+    } else {                            /* top wall */
+      ix = b - 2 * ny - nx; iy = ny - 1;
+      x0 = ((double)ix + ua) * p->dx; y0 = (double)ny * p->dy;
+      sx = tg; sy = -cn;
+    }
+  }
+  double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+  double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+  for (uint32_t j = 0;; ++j) {
+    double ulen, uacc;
+    orc_draw(s->o.seed, slot, (uint32_t)e, k, 2u + j, &ulen, &uacc);
+    /* candidate free path on the common time scale: -|V_g| tau_min ln(eta) */
+    double ell = -(s->lam_min * orc_log(1.0 - ulen));
+    (*segs)++;
+    int bface = -1;
+    if (orc_march(p, x0, y0, &ix, &iy, sx, sy, inv_sx, inv_sy, ell, q, t, &bface)) {
+      t->B[bface] += q;
+      return;
+    }
+    int c = ix + nx * iy;
+    t->W[c] += q;
+    /* accept as a real collision with probability sigma/sigma_max = tau_min/tau */
+    if (uacc < s->ratio[c] || j == ORC_MAX_SEGMENTS - 1) {
+      t->D[c] += q;
+      return;
+    }
+    /* null collision: same direction, new free path from the stopping point */
+    x0 = orc_clamp(x0 + ell * sx, (double)ix * p->dx, (double)(ix + 1) * p->dx);
+    if (p->dim == 2) y0 = orc_clamp(y0 + ell * sy, (double)iy * p->dy, (double)(iy + 1) * p->dy);
+  }
+}
+
+int orc_trace_ray(const orc_problem *p, double x0, double y0, int ix, int iy, double sx,
+                  double sy, double ell, int32_t *events, int max_events, int *end_kind,
+                  int *end_cell)
+{
+  orc_tally t;
+  memset(&t, 0, sizeof t);
+  t.events = events;
+  t.max_events = max_events;
+  double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+  double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+  int b = -1;
+  int absorbed = orc_march(p, x0, y0, &ix, &iy, sx, sy, inv_sx, inv_sy, ell, 1, &t, &b);
+  *end_kind = absorbed;
+  *end_cell = absorbed ? b : ix + p->nx * iy;
+  return t.n_events;
+}
+
+/* One iteration (Sec. 3.1 steps (1)-(3); Sec. 3.2 steps (1)-(6); Sec. 3.3). */
+static int orc_iterate(orc_state *s, int faces)
+{
+  const orc_problem *p = &s->p;
+  uint32_t slot = (s->o.rng_mode == ORC_RNG_CRN) ? s->o.rng_epoch : s->iter;
+  memset(s->D, 0, sizeof(int64_t) * s->nc);
+  memset(s->W, 0, sizeof(int64_t) * s->nc);
+  memset(s->Phix, 0, sizeof(int64_t) * s->nfx);
+  if (s->nfy) memset(s->Phiy, 0, sizeof(int64_t) * s->nfy);
+  memset(s->B, 0, sizeof(int64_t) * s->nb);
+  orc_tally t;
+  memset(&t, 0, sizeof t);
+  t.D = s->D; t.W = s->W; t.Phix = s->Phix; t.Phiy = s->Phiy; t.B = s->B;
+  t.faces = faces;
+  if (faces) {
+    /* every wall particle enters through its wall face: inward crossing of G_f */
+    int nx = p->nx, ny = p->ny;
+    for (int b = 0; b < s->nb; ++b) {
+      int64_t g = s->G[s->nc + b];
+      if (b < ny) s->Phix[b * (nx + 1)] += g;
+      else if (b < 2 * ny) s->Phix[(b - ny) * (nx + 1) + nx] -= g;
+      else if (b < 2 * ny + nx) s->Phiy[b - 2 * ny] += g;
+      else s->Phiy[ny * nx + (b - 2 * ny - nx)] -= g;
+    }
+  }
+  uint64_t flights = 0, segs = 0;
+  for (int e = 0; e < s->ne; ++e)
+    for (uint64_t k = 0; k < s->N; ++k) {
+      int64_t q = orc_split_weight(s->G[e], s->N, k);
+      if (q == 0) continue;
+      flights++;
+      orc_fly(s, slot, e, (uint32_t)k, q, &t, &segs);
+    }
+  s->flights = flights;
+  s->segments = segs;
+  s->crossings = t.crossings;
+  s->tot_flights += flights;
+  s->tot_segments += segs;
+  s->tot_crossings += t.crossings;
+
+  /* macroscopic update: E^{n+1/2} from the total tally W */
+  double *E_new = (double *)malloc(sizeof(double) * s->nc);
+  double *tmp = (double *)malloc(sizeof(double) * s->nc);
+  for (int c = 0; c < s->nc; ++c) s->E_half[c] = ldexp((double)s->W[c], -s->F) / s->V;
+  int rc = ORC_OK;
+  int ok = 1;
+  if (s->o.newton) {
+    double *r = (double *)malloc(sizeof(double) * s->nc);
+    double *x = (double *)malloc(sizeof(double) * s->nc);
+    for (int c = 0; c < s->nc; ++c) r[c] = s->E_half[c] - s->E[c];
+    int its = 0;
+    rc = orc_cg(p, s->gx, s->gy, s->diag, r, x, s->o.cg_tol, s->o.cg_max_iters, &its);
+    s->cg_last = its;
+    s->cg_total += its;
+    for (int c = 0; c < s->nc; ++c) E_new[c] = s->E_half[c] + x[c];
+    for (int c = 0; c < s->nc; ++c) s->G[c] = orc_to_fixed((E_new[c] * s->V) * s->ratio[c], s->F, &ok);
+    free(r);
+    free(x);
+  } else {
+    for (int c = 0; c < s->nc; ++c) E_new[c] = s->E_half[c];
+    for (int c = 0; c < s->nc; ++c) s->G[c] = s->D[c];   /* re-emit W^h */
+  }
+  for (int c = 0; c < s->nc; ++c) {
+    double d = E_new[c] - s->E[c];
+    tmp[c] = d * d;
+  }
+  double dn = sqrt(orc_tree_sum(tmp, (uint64_t)s->nc));
+  if (s->iter == 0) s->d0 = dn;
+  s->res = (s->d0 > 0.0) ? dn / s->d0 : 0.0;
+  for (int c = 0; c < s->nc; ++c) {
+    if (!isfinite(E_new[c]) && rc == ORC_OK) rc = ORC_E_NONFINITE;
+    s->E[c] = E_new[c];
+  }
+  if ((int)s->iter < s->res_cap) s->res_hist[s->iter] = s->res;
+  s->iter++;
+  free(E_new);
+  free(tmp);
+  if (rc == ORC_OK && (!ok || !orc_check_budget(s->G, s->ne))) rc = ORC_E_FIXED_OVERFLOW;
+  if (rc == ORC_OK && s->iter > 1 && s->res > 1e3) rc = ORC_E_DIVERGED;
+  return rc;
+}
+
+int orc_step(orc_state *s, int n_iters, int faces)
+{
+  for (int i = 0; i < n_iters; ++i) {
+    int rc = orc_iterate(s, faces);
+    if (rc) return rc;
+  }
+  return ORC_OK;
+}
+
+int orc_solve(orc_state *s, double *T_out, double *qx_out, double *qy_out)
+{
+  const orc_problem *p = &s->p;
+  int faces_each = (s->o.tally_faces == ORC_FACES_EVERY);
+  int converged = 0, rc;
+  while ((int)s->iter < s->o.max_iters) {
+    rc = orc_iterate(s, faces_each);
+    if (rc) return rc;
+    if (s->res < s->o.res_tol) {
+      converged = 1;
+      break;
+    }
+  }
+  int faces_out = (s->o.tally_faces != ORC_FACES_OFF);
+  double *Eo = (double *)calloc((size_t)s->nc, sizeof(double));
+  double *fx = (double *)calloc((size_t)s->nfx, sizeof(double));
+  double *fy = (double *)calloc((size_t)(s->nfy ? s->nfy : 1), sizeof(double));
+  if (s->o.avg_iters > 0) {
+    for (int a = 0; a < s->o.avg_iters; ++a) {
+      rc = orc_iterate(s, faces_out);
+      if (rc) { free(Eo); free(fx); free(fy); return rc; }
+      for (int c = 0; c < s->nc; ++c) Eo[c] = Eo[c] + s->E[c];
+      for (int f = 0; f < s->nfx; ++f) fx[f] = fx[f] + ldexp((double)s->Phix[f], -s->F);
+      for (int f = 0; f < s->nfy; ++f) fy[f] = fy[f] + ldexp((double)s->Phiy[f], -s->F);
+    }
+    double na = (double)s->o.avg_iters;
+    for (int c = 0; c < s->nc; ++c) Eo[c] = Eo[c] / na;
+    for (int f = 0; f < s->nfx; ++f) fx[f] = fx[f] / na;
+    for (int f = 0; f < s->nfy; ++f) fy[f] = fy[f] / na;
+  } else {
+    if (s->o.tally_faces == ORC_FACES_FINAL) {
+      rc = orc_iterate(s, 1);
+      if (rc) { free(Eo); free(fx); free(fy); return rc; }
+    }
+    for (int c = 0; c < s->nc; ++c) Eo[c] = s->E[c];
+    for (int f = 0; f < s->nfx; ++f) fx[f] = ldexp((double)s->Phix[f], -s->F);
+    for (int f = 0; f < s->nfy; ++f) fy[f] = ldexp((double)s->Phiy[f], -s->F);
+  }
+  if (T_out)
+    for (int c = 0; c < s->nc; ++c) T_out[c] = p->t_ref + Eo[c] / p->cv;
+  if (qx_out) {
+    double den = p->dy * s->tau_min;
+    for (int f = 0; f < s->nfx; ++f) qx_out[f] = faces_out ? fx[f] / den : 0.0;
+  }
+  if (qy_out && s->nfy) {
+    double den = p->dx * s->tau_min;
+    for (int f = 0; f < s->nfy; ++f) qy_out[f] = faces_out ? fy[f] / den : 0.0;
+  }
+  free(Eo);
+  free(fx);
+  free(fy);
+  return converged ? ORC_OK : ORC_W_NOT_CONVERGED;
+}
+
+void orc_get_info(const orc_state *s, orc_info *info)
+{
+  info->iter = s->iter;
+  info->F = s->F;
+  info->n_per_emitter = s->N;
+  info->n_cells = s->nc;
+  info->n_bfaces = s->nb;
+  info->n_emitters = s->ne;
+  info->tau_min = s->tau_min;
+  info->lam_min = s->lam_min;
+  info->d0 = s->d0;
+  info->res = s->res;
+  info->flights = s->flights;
+  info->segments = s->segments;
+  info->crossings = s->crossings;
+  info->tot_flights = s->tot_flights;
+  info->tot_segments = s->tot_segments;
+  info->tot_crossings = s->tot_crossings;
+  info->cg_iters_last = s->cg_last;
+  info->cg_iters_total = s->cg_total;
+}
+
+void orc_get_tallies(const orc_state *s, int64_t *D, int64_t *W, int64_t *Phix, int64_t *Phiy,
+                     int64_t *B)
+{
+  if (D) memcpy(D, s->D, sizeof(int64_t) * s->nc);
+  if (W) memcpy(W, s->W, sizeof(int64_t) * s->nc);
+  if (Phix) memcpy(Phix, s->Phix, sizeof(int64_t) * s->nfx);
+  if (Phiy && s->nfy) memcpy(Phiy, s->Phiy, sizeof(int64_t) * s->nfy);
+  if (B) memcpy(B, s->B, sizeof(int64_t) * s->nb);
+}
+
+void orc_get_E(const orc_state *s, double *E) { memcpy(E, s->E, sizeof(double) * s->nc); }
+
+void orc_get_G(const orc_state *s, int64_t *G) { memcpy(G, s->G, sizeof(int64_t) * s->ne); }
+
+void orc_get_residuals(const orc_state *s, double *res, int max_n)
+{
+  for (int i = 0; i < max_n && i < s->res_cap; ++i) res[i] = s->res_hist[i];
+}
+
+int orc_set_state(orc_state *s, uint32_t iter, double d0, const double *E, const int64_t *G)
+{
+  s->iter = iter;
+  s->d0 = d0;
+  memcpy(s->E, E, sizeof(double) * s->nc);
+  memcpy(s->G, G, sizeof(int64_t) * s->ne);
+  return orc_check_budget(s->G, s->ne) ? ORC_OK : ORC_E_FIXED_OVERFLOW;
+}

@@ -1,0 +1,129 @@
+/*
+ * iugkp_oracle.h -- plain single-threaded FP64 CPU oracle for the implicit
+ * unified gas-kinetic particle (IUGKP) steady gray phonon BTE iteration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include,
+ * link or call this code; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark do.  It shares no code with the HIP path.
+ *
+ * What it computes (paper: Liu, Yang, Zhang, Ji, Xu, "Implicit unified gas
+ * kinetic particle method for steady-state solution of multiscale phonon
+ * transport", arXiv 2506.09465):
+ *   - Sec. 2, linearised gray BGK model: e_eq = C (T - T_ref) / 4 pi,
+ *     E = integral of e over the sphere, T = E / C + T_ref;
+ *   - Sec. 3.1, one iteration = resample every particle from its cell's
+ *     equilibrium, fly an exponential free path lambda = -u tau ln(eta),
+ *     count the energy deposited per cell (eq. for W_i as a sum of particle
+ *     weights);
+ *   - Sec. 3.2, spatially varying tau: a common time scale tau_min, candidate
+ *     collisions with free path -u tau_min ln(eta), accepted as real with
+ *     probability sigma(x)/sigma_max = tau_min/tau(x), total tally W (null +
+ *     real) and real tally W^h, re-emission from W^h;
+ *   - Sec. 3.3, inexact Newton with the diffusion-type operator
+ *     div(-kappa grad dT) on the energy residual between iterations.
+ * Every point the paper leaves open is fixed by a reading stated next to the
+ * function that implements it.
+ */
+#ifndef IUGKP_ORACLE_H
+#define IUGKP_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ORC_OK = 0,
+  ORC_W_NOT_CONVERGED = 1,
+  ORC_E_INVALID_ARG = -1,
+  ORC_E_NOMEM = -2,
+  ORC_E_FIXED_OVERFLOW = -4,
+  ORC_E_NONFINITE = -5,
+  ORC_E_CG_BREAKDOWN = -6,
+  ORC_E_CG_NOT_CONVERGED = -7,
+  ORC_E_DIVERGED = -8
+};
+
+enum { ORC_RNG_FRESH = 0, ORC_RNG_CRN = 1 };
+enum { ORC_FACES_OFF = 0, ORC_FACES_EVERY = 1, ORC_FACES_FINAL = 2 };
+
+typedef struct orc_problem {
+  int dim;              /* 1 or 2 */
+  int nx, ny;           /* cells; ny == 1 in 1D */
+  double dx, dy;        /* cell sizes; dy == 1 in 1D (unit area) */
+  double t_ref, cv, vg; /* reference temperature, volumetric heat capacity, |V_g| */
+  const double *tau;    /* [nx*ny] relaxation time per cell, c = ix + nx*iy */
+  const double *wall_T; /* [n_b] wall temperatures: left rows, right rows, bottom cols, top cols */
+  const double *T_init; /* [nx*ny] initial temperature or NULL (-> t_ref) */
+  const double *diff_x; /* [nx*ny] per-iteration diffusion coefficient along x (Newton), or NULL */
+  const double *diff_y; /* [nx*ny] along y (2D Newton), or NULL */
+} orc_problem;
+
+typedef struct orc_options {
+  uint64_t seed;
+  uint64_t particles_per_iter;
+  int rng_mode;         /* ORC_RNG_FRESH: Philox slot = iteration; ORC_RNG_CRN: slot = rng_epoch */
+  uint32_t rng_epoch;
+  int max_iters;
+  double res_tol;
+  int newton;           /* 0/1 */
+  double cg_tol;
+  int cg_max_iters;
+  int tally_faces;      /* ORC_FACES_* */
+  int avg_iters;
+} orc_options;
+
+typedef struct orc_info {
+  uint32_t iter;        /* iterations done */
+  int F;                /* fixed-point exponent */
+  uint64_t n_per_emitter;
+  int n_cells, n_bfaces, n_emitters;
+  double tau_min, lam_min;
+  double d0, res;       /* first-iteration update norm, last relative residual */
+  uint64_t flights, segments, crossings;         /* last iteration */
+  uint64_t tot_flights, tot_segments, tot_crossings;
+  int cg_iters_last, cg_iters_total;
+} orc_info;
+
+typedef struct orc_state orc_state;
+
+/* ---- building blocks (exported for unit tests) ---- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_u53(uint32_t hi, uint32_t lo);
+double orc_log(double x);
+double orc_cos2pi(double u);
+int64_t orc_split_weight(int64_t G, uint64_t n, uint64_t k);
+double orc_tree_sum(const double *v, uint64_t n);
+int orc_fixed_exponent(const orc_problem *p, double *tau_min_out);
+
+/* One ray, recorded: march from (x0,y0) in cell (ix,iy) along (sx,sy) a length
+ * ell (no null collisions).  events[3*i] = axis (0 x, 1 y), [3*i+1] = face
+ * index in its tally array, [3*i+2] = sign.  Returns the number of crossings;
+ * *end_kind = 0 stopped in cell *end_cell, 1 absorbed by boundary face *end_cell. */
+int orc_trace_ray(const orc_problem *p, double x0, double y0, int ix, int iy, double sx,
+                  double sy, double ell, int32_t *events, int max_events, int *end_kind,
+                  int *end_cell);
+
+/* Unpreconditioned CG on the Newton operator assembled from diff_x/diff_y. */
+int orc_newton_operator(const orc_problem *p, double *gx, double *gy, double *diag);
+int orc_cg(const orc_problem *p, const double *gx, const double *gy, const double *diag,
+           const double *b, double *x, double tol, int max_iters, int *iters_out);
+
+/* ---- the iteration ---- */
+int orc_create(const orc_problem *p, const orc_options *o, orc_state **out);
+void orc_destroy(orc_state *s);
+int orc_step(orc_state *s, int n_iters, int faces);
+int orc_solve(orc_state *s, double *T_out, double *qx_out, double *qy_out);
+void orc_get_info(const orc_state *s, orc_info *info);
+void orc_get_tallies(const orc_state *s, int64_t *D, int64_t *W, int64_t *Phix, int64_t *Phiy,
+                     int64_t *B);
+void orc_get_E(const orc_state *s, double *E);
+void orc_get_G(const orc_state *s, int64_t *G);
+void orc_get_residuals(const orc_state *s, double *res, int max_n);
+int orc_set_state(orc_state *s, uint32_t iter, double d0, const double *E, const int64_t *G);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

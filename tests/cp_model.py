@@ -1,0 +1,191 @@
+"""Deterministic collision-probability (CP) model of one IUGKP iteration in 1D.
+
+Test-side pin for the oracle.  For a slab of flat cells with isotropic,
+uniform-in-cell emission, black walls with cosine-law emission and analog
+collision tallies, the expected result of one particle iteration is exactly a
+linear map built from the exponential integral E_3 (first-flight collision
+probabilities of slab geometry).  This is the discrete form of the paper's
+integral solution (Sec. 2: survival probability P_f, collision density P_c,
+and the convex-combination form of the cell energies).
+
+Notation: a_c = dx / lambda_c is the optical thickness of cell c,
+lambda_c = |V_g| tau_c.  Real collisions follow the true optical depths
+(delta tracking reproduces them, Sec. 3.2); candidate events in cell c are
+1/r_c times the real ones, r_c = tau_min / tau_c.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import expn
+
+
+def E3(x):
+    return expn(3, np.asarray(x, dtype=np.float64))
+
+
+def cp_1d(tau: np.ndarray, dx: float, vg: float = 1.0):
+    """Return (K, Pw, Pesc, Pww).
+
+    K[j, i]   : probability that a particle emitted uniformly/isotropically in cell j
+                has its real collision in cell i;
+    Pw[f, i]  : same for a cosine-law particle entering from wall f (0 left, 1 right);
+    Pesc[j, f]: probability that a particle from cell j is absorbed by wall f;
+    Pww[f, g] : wall f to wall g (g != f) without collision.
+    """
+    tau = np.asarray(tau, dtype=np.float64)
+    n = tau.size
+    a = dx / (vg * tau)
+    cum = np.concatenate([[0.0], np.cumsum(a)])  # optical coordinate of face k
+    K = np.zeros((n, n))
+    for j in range(n):
+        for i in range(n):
+            if i == j:
+                K[j, i] = 1.0 - (1.0 / a[j]) * (0.5 - E3(a[j]))
+            else:
+                lo, hi = (j, i) if j < i else (i, j)
+                gap = cum[hi] - cum[lo + 1]
+                K[j, i] = (1.0 / (2.0 * a[j])) * (E3(gap) - E3(gap + a[i]) - E3(gap + a[j])
+                                                  + E3(gap + a[i] + a[j]))
+    Pw = np.zeros((2, n))
+    for i in range(n):
+        Pw[0, i] = 2.0 * (E3(cum[i]) - E3(cum[i + 1]))
+        Pw[1, i] = 2.0 * (E3(cum[n] - cum[i + 1]) - E3(cum[n] - cum[i]))
+    Pesc = np.zeros((n, 2))
+    for j in range(n):
+        Pesc[j, 0] = (1.0 / (2.0 * a[j])) * (E3(cum[j]) - E3(cum[j + 1]))
+        Pesc[j, 1] = (1.0 / (2.0 * a[j])) * (E3(cum[n] - cum[j + 1]) - E3(cum[n] - cum[j]))
+    Pww = np.zeros((2, 2))
+    Pww[0, 1] = Pww[1, 0] = 2.0 * E3(cum[n])
+    return K, Pw, Pesc, Pww
+
+
+class Slab:
+    """Expected one-iteration map of a 1D workload, in floating point energy units."""
+
+    def __init__(self, w):
+        self.w = w
+        self.tau = np.asarray(w.tau, dtype=np.float64)
+        self.tau_min = self.tau.min()
+        self.lam_min = w.vg * self.tau_min
+        self.r = self.tau_min / self.tau
+        self.V = w.dx * w.dy
+        self.K, self.Pw, self.Pesc, self.Pww = cp_1d(self.tau, w.dx, w.vg)
+        self.Ew = w.cv * (np.asarray(w.wall_T) - w.t_ref)
+        self.Gw = self.Ew * self.lam_min * 1.0 / 4.0
+
+    def cell_emission(self, E):
+        return self.r * np.asarray(E) * self.V
+
+    def expected_D(self, Gc):
+        return Gc @ self.K + self.Gw @ self.Pw
+
+    def expected_B(self, Gc):
+        return Gc @ self.Pesc + self.Gw @ self.Pww
+
+    def expected_W(self, Gc):
+        return self.expected_D(Gc) / self.r
+
+    def step(self, E):
+        """E^{n+1} = E[W]/V for emission from E (no Newton)."""
+        return self.expected_W(self.cell_emission(E)) / self.V
+
+    def fixed_point(self):
+        """Steady state of the D re-emission map G -> D, returned as E = W/V."""
+        n = self.tau.size
+        A = np.eye(n) - self.K.T
+        G = np.linalg.solve(A, self.Gw @ self.Pw)
+        return self.expected_W(G) / self.V, G
+
+    def heat_flux_left(self, G):
+        """Net energy flux through the left wall face per unit area and time."""
+        absorbed = self.expected_B(G)[0]
+        return (self.Gw[0] - absorbed) / (1.0 * self.tau_min)
+
+    def psi(self):
+        """Heat-flux ratio q / (|V_g| (E_H - E_L) / 4) at the fixed point."""
+        _, G = self.fixed_point()
+        return self.heat_flux_left(G) / (self.w.vg * (self.Ew[0] - self.Ew[1]) / 4.0)
+
+    def variance_D(self, Gc, n_per):
+        """Variance of the D tally for one iteration (multinomial per emitter)."""
+        var = np.zeros(self.tau.size)
+        for j, g in enumerate(Gc):
+            q = g / n_per
+            p = self.K[j]
+            var += n_per * q * q * p * (1 - p)
+        for f in range(2):
+            q = self.Gw[f] / n_per
+            p = self.Pw[f]
+            var += n_per * q * q * p * (1 - p)
+        return var
+
+    def variance_W(self, Gc, n_per):
+        """Variance of W for delta tracking: per-emitter variance of sum over
+        candidate events (geometric count 1/r per real collision in a cell)."""
+        # For each particle, W contribution to cell i is q * N_i with N_i the number of
+        # candidate events in i; E[N_i^2] <= E[N_i] (2/r_i - 1) for the geometric count
+        # when the real collision happens in i; used only as an upper bound.
+        var = np.zeros(self.tau.size)
+        for j, g in enumerate(Gc):
+            q = g / n_per
+            m = self.K[j] / self.r
+            var += n_per * q * q * m * (2.0 / self.r)
+        for f in range(2):
+            q = self.Gw[f] / n_per
+            m = self.Pw[f] / self.r
+            var += n_per * q * q * m * (2.0 / self.r)
+        return var
+
+
+def d_eff(lam: float, delta: float, tol: float = 1e-18) -> float:
+    """Per-iteration diffusion coefficient of the flat-cell 1D kernel:
+    half the second moment of the cell-to-cell jump,
+    D = sum_{m>=1} m^2 delta^2 P_m  =  (lam delta / 2) (1/2 + 2 sum_{j>=1} E_3(j delta/lam)).
+    Tends to lam^2/3 for lam >> delta and to lam delta / 4 for lam << delta."""
+    a = delta / lam
+    jmax = int(np.ceil(60.0 / a)) + 2
+    j = np.arange(1, jmax + 1, dtype=np.float64)
+    s = np.sum(E3(j * a)[::-1])
+    return (lam * delta / 2.0) * (0.5 + 2.0 * s)
+
+
+def d_eff_second_moment(lam: float, delta: float, mmax: int = 20000) -> float:
+    """Same quantity from its definition, sum_m m^2 delta^2 P_m (slower; used to check d_eff)."""
+    a = delta / lam
+    m = np.arange(1, mmax + 1, dtype=np.float64)
+    P = (1.0 / (2.0 * a)) * (E3((m - 1) * a) - 2.0 * E3(m * a) + E3((m + 1) * a))
+    return float(np.sum((m * m * delta * delta * P)[::-1]))
+
+
+def newton_matrix_1d(n: int, dx: float, lam: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """Dense conservative 3-point operator -d/dx(D d/dx) with Robin walls
+    (extrapolation distance 2 lam / 3), per-iteration units."""
+    A = np.zeros((n, n))
+    for k in range(n + 1):
+        if k == 0 or k == n:
+            c = 0 if k == 0 else n - 1
+            g = D[c] / (dx * (dx / 2 + 2 * lam[c] / 3))
+            A[c, c] += g
+        else:
+            a, b = D[k - 1], D[k]
+            g = 2 * a * b / (a + b) / dx ** 2
+            A[k - 1, k - 1] += g
+            A[k, k] += g
+            A[k - 1, k] -= g
+            A[k, k - 1] -= g
+    return A
+
+
+def dsa_spectral_radius(w, D=None) -> float:
+    """Spectral radius of the deterministic accelerated iteration
+    E -> E_half + A^{-1} (E_half - E), E_half = K-map(E) (error propagation)."""
+    s = Slab(w)
+    n = w.nx
+    lam = w.vg * s.tau
+    if D is None:
+        D = np.array([d_eff(l, w.dx) for l in lam])
+    A = newton_matrix_1d(n, w.dx, lam, D)
+    M = (s.K.T * (s.r[None, :] * s.V)) / (s.r[:, None] * s.V)   # E -> E_half (homogeneous part)
+    I = np.eye(n)
+    T = M + np.linalg.solve(A, M - I)
+    return float(np.max(np.abs(np.linalg.eigvals(T))))
