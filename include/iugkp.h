@@ -1,0 +1,213 @@
+/*
+ * iugkp.h -- C ABI of the MI355X (gfx950) implicit unified gas-kinetic
+ * particle (IUGKP) solver for the steady linearised gray phonon BTE.
+ *
+ * Method: Liu, Yang, Zhang, Ji, Xu, "Implicit unified gas kinetic particle
+ * method for steady-state solution of multiscale phonon transport",
+ * arXiv 2506.09465.
+ *   Sec. 2   model: V_g . grad e = (e_eq - e) / tau, e_eq = C (T - T_ref) / 4 pi,
+ *            E = integral of e over the sphere, T = E / C + T_ref, q = integral of V_g e.
+ *   Sec. 3.1 iteration for constant tau: resample every particle from its
+ *            cell's equilibrium, fly the exponential free path
+ *            lambda = -|V_g| tau ln(eta), count the energy that lands in each cell.
+ *   Sec. 3.2 variable tau: common time scale tau_min, candidate collisions
+ *            accepted with probability tau_min / tau(x) (null collisions); the
+ *            macroscopic energy from all candidates (W), re-emission from the
+ *            real ones (W^h).
+ *   Sec. 3.3 inexact Newton: a diffusion-type linear operator on the energy
+ *            change between iterations predicts the next equilibrium.
+ *
+ * Conventions shared by every call
+ *   - Uniform Cartesian mesh, cell c = ix + nx * iy, sizes dx, dy (1D: ny = 1,
+ *     dy = 1, unit face area).
+ *   - Wall faces b = 0 .. n_b-1 in the order: left wall rows (ny), right wall
+ *     rows (ny), bottom wall columns (nx), top wall columns (nx); 1D has the
+ *     two end walls only (n_b = 2).
+ *   - Emitters: the n_cells cells then the n_b wall faces; every emitter emits
+ *     the same number N = max(1, particles_per_iter / (n_cells + n_b)) of
+ *     particles per iteration.
+ *   - Face arrays: x-faces [ny][nx+1] (face k of row iy at index iy*(nx+1)+k),
+ *     y-faces [ny+1][nx] (face k of column ix at index k*nx+ix); 1D has no
+ *     y-faces.
+ *   - Energies are int64 fixed-point numbers with scale 2^F; tallies are exact
+ *     integer sums, identical for any launch shape or order.
+ *   - Every entry point returns IUGKP_OK (0) on success, a negative error code
+ *     on failure (nothing is written to outputs then), or the positive warning
+ *     IUGKP_W_NOT_CONVERGED (outputs written).  iugkp_last_error() gives a
+ *     message for the last failing call on the calling thread.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently.
+ *   - All device work is issued on the HIP stream given at creation; calls
+ *     returning host data synchronise that stream.
+ */
+#ifndef IUGKP_H
+#define IUGKP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IUGKP_OK 0
+#define IUGKP_W_NOT_CONVERGED 1
+#define IUGKP_E_INVALID_ARG (-1)
+#define IUGKP_E_NOMEM (-2)
+#define IUGKP_E_DEVICE (-3)
+#define IUGKP_E_FIXED_OVERFLOW (-4)
+#define IUGKP_E_NONFINITE (-5)
+#define IUGKP_E_CG_BREAKDOWN (-6)
+#define IUGKP_E_CG_NOT_CONVERGED (-7)
+#define IUGKP_E_DIVERGED (-8)
+
+/* where caller arrays live */
+#define IUGKP_MEM_HOST 0
+#define IUGKP_MEM_DEVICE 1
+
+/* Philox slot per iteration: FRESH = iteration index, CRN = rng_epoch (fixed) */
+#define IUGKP_RNG_FRESH 0
+#define IUGKP_RNG_CRN 1
+
+/* face (heat-flux) tallies: never, every iteration, or only in the output iteration(s) */
+#define IUGKP_FACES_OFF 0
+#define IUGKP_FACES_EVERY 1
+#define IUGKP_FACES_FINAL 2
+
+typedef struct iugkp_problem {
+  int dim;              /* 1 or 2 */
+  int nx, ny;           /* cell counts, ny == 1 in 1D */
+  double dx, dy;        /* cell sizes (> 0); dy is the unit face area in 1D */
+  double t_ref;         /* reference temperature of the linearisation (Sec. 2) */
+  double cv;            /* volumetric heat capacity C (> 0) */
+  double vg;            /* group velocity magnitude |V_g| (> 0) */
+  const double *tau;    /* [n_cells] relaxation time (> 0, finite, max/min <= 1e6) */
+  const double *wall_T; /* [n_b] wall temperatures */
+  const double *T_init; /* [n_cells] initial temperature, or NULL for t_ref everywhere */
+  const double *diff_x; /* [n_cells] Newton diffusion coefficient along x per iteration, or
+                           NULL: the library uses D_eff(|V_g| tau_c, dx) (iugkp_d_eff) */
+  const double *diff_y; /* [n_cells] the same along y (2D), or NULL */
+  int mem_kind;         /* IUGKP_MEM_HOST or IUGKP_MEM_DEVICE for the arrays above */
+} iugkp_problem;
+
+typedef struct iugkp_options {
+  uint64_t seed;                /* Philox key = (seed low 32 bits, seed high 32 bits) */
+  uint64_t particles_per_iter;  /* requested particles per iteration (>= 1) */
+  int rng_mode;                 /* IUGKP_RNG_FRESH or IUGKP_RNG_CRN */
+  uint32_t rng_epoch;           /* slot used in CRN mode */
+  int max_iters;                /* iteration cap of iugkp_solve (>= 0) */
+  double res_tol;               /* stop when ||E^{n+1}-E^n|| / ||E^1-E^0|| < res_tol */
+  int newton;                   /* 0/1: inexact-Newton (diffusion) correction, Sec. 3.3 */
+  double cg_tol;                /* CG stop: ||r||^2 <= cg_tol^2 ||b||^2 */
+  int cg_max_iters;             /* CG iteration cap per Newton step (>= 1 if newton) */
+  int tally_faces;              /* IUGKP_FACES_* */
+  int avg_iters;                /* iterations averaged for the outputs after stopping (>= 0) */
+  int block_size;               /* transport kernel workgroup size: 0 (= 256), 64..1024 */
+} iugkp_options;
+
+typedef struct iugkp_stats {
+  int iters;                    /* iterations done since creation (or the restored state) */
+  double res;                   /* last relative update norm */
+  uint64_t flights;             /* particles flown in the last iteration (weight != 0) */
+  uint64_t segments;            /* free-path segments in the last iteration */
+  uint64_t crossings;           /* face crossings in the last iteration */
+  uint64_t tot_flights, tot_segments, tot_crossings;
+  double ms_march, ms_update, ms_cg;  /* accumulated GPU time per phase (HIP events) */
+  int cg_iters_last, cg_iters_total;
+  int fixed_point_F;            /* fixed-point exponent */
+  uint64_t n_per_emitter;       /* N */
+  int n_emitters;
+} iugkp_stats;
+
+typedef struct iugkp_handle iugkp_handle;
+typedef struct iugkp_batch iugkp_batch;
+
+/* Create a solver for one problem.  Copies every problem array into library-owned
+ * device memory (the caller may free its arrays on return), computes the
+ * fixed-point exponent F = 62 - ceil(log2 B), B = 4 max|E| (sum of cell volumes
+ * + lambda_min (sum of wall areas) / 4), the wall emission energies
+ * E_w lambda_min A / 4 (cosine-law black walls) and the initial cell emission.
+ * stream: a hipStream_t (NULL = default stream).
+ * Errors: INVALID_ARG (bad sizes, tau <= 0 or not finite, NULL arrays, Newton
+ * options out of range), NOMEM, DEVICE, FIXED_OVERFLOW. */
+int iugkp_create(const iugkp_problem *problem, const iugkp_options *options, void *stream,
+                 iugkp_handle **out);
+
+void iugkp_destroy(iugkp_handle *h);
+
+/* Run n_iters iterations (Sec. 3.1 steps (1)-(3) / Sec. 3.2 steps (1)-(6), then
+ * the macroscopic update and, if enabled, the Newton correction of Sec. 3.3).
+ * Face tallies are taken when tally_faces == IUGKP_FACES_EVERY.
+ * Errors: FIXED_OVERFLOW, NONFINITE, CG_BREAKDOWN, CG_NOT_CONVERGED, DIVERGED, DEVICE. */
+int iugkp_step(iugkp_handle *h, int n_iters);
+
+/* Same with the face tallies forced on (faces = 1) or off (faces = 0). */
+int iugkp_step_faces(iugkp_handle *h, int n_iters, int faces);
+
+/* Iterate until res < res_tol or max_iters, then produce the outputs: with
+ * avg_iters > 0 the mean of that many further iterations, otherwise the last
+ * state (plus one face-tally iteration in FACES_FINAL mode).
+ *   T_out  [n_cells]            T = t_ref + E / cv
+ *   qx_out [ny*(nx+1)] or NULL  x heat flux per face (energy / (area * tau_min))
+ *   qy_out [(ny+1)*nx] or NULL  y heat flux per face (2D)
+ * Output arrays are caller-owned, in the problem's mem_kind.
+ * Returns OK, W_NOT_CONVERGED, or an error as iugkp_step. */
+int iugkp_solve(iugkp_handle *h, double *T_out, double *qx_out, double *qy_out,
+                iugkp_stats *stats);
+
+/* Tallies of the last iteration (int64, exact): D = real-collision energy per
+ * cell (W^h), W = all candidate-collision energy per cell, Phi_x / Phi_y = net
+ * energy through each face along +x / +y, B = energy absorbed per wall face.
+ * Any pointer may be NULL.  Arrays in the problem's mem_kind. */
+int iugkp_get_tallies(iugkp_handle *h, int64_t *D, int64_t *W, int64_t *Phi_x,
+                      int64_t *Phi_y, int64_t *B);
+
+/* Resumable state: iteration count, first-iteration update norm, E^n [n_cells]
+ * and the next emission energies G [n_cells + n_b] (int64).  set_state restores
+ * it (resume is bitwise identical to an uninterrupted run).  Arrays in the
+ * problem's mem_kind. */
+int iugkp_get_state(iugkp_handle *h, uint32_t *iter, double *d0, double *E, int64_t *G);
+int iugkp_set_state(iugkp_handle *h, uint32_t iter, double d0, const double *E,
+                    const int64_t *G);
+
+/* Relative residual history (host array, up to max_n entries); returns the count. */
+int iugkp_get_residuals(iugkp_handle *h, double *res, int max_n);
+
+int iugkp_get_stats(iugkp_handle *h, iugkp_stats *stats);
+
+/* Per-iteration diffusion coefficient of the flat-cell kernel used by the Newton
+ * operator when none is given: half the second moment of one cell-to-cell jump,
+ * D_eff = (lam delta / 2) (1/2 + 2 sum_{j>=1} E_3(j delta / lam)); tends to
+ * lam^2 / 3 for lam >> delta and lam delta / 4 for lam << delta.  Host function. */
+double iugkp_d_eff(double lam, double delta);
+
+/* Batched solves: n independent problems advanced together, one launch per phase
+ * for all of them (work queue over instances and particle chunks), the
+ * per-iteration sequence replayed from a captured HIP graph.  Every instance's
+ * results are bitwise those of iugkp_solve on the same problem and options.
+ * All problems must use the same mem_kind; outputs per instance as iugkp_solve
+ * (T_out[i], qx_out[i], qy_out[i] may be NULL; stats may be NULL or an array of n). */
+int iugkp_batch_create(const iugkp_problem *const *problems,
+                       const iugkp_options *const *options, int n, void *stream,
+                       iugkp_batch **out);
+int iugkp_batch_solve(iugkp_batch *b, double *const *T_out, double *const *qx_out,
+                      double *const *qy_out, iugkp_stats *stats);
+void iugkp_batch_destroy(iugkp_batch *b);
+
+const char *iugkp_strerror(int code);
+const char *iugkp_last_error(void);
+
+/* ---- device building blocks, exposed for bitwise verification ----
+ * All pointers are device pointers; work is issued on `stream` and completed
+ * before return.
+ * iugkp_dev_philox: out[4i..4i+3] = Philox4x32-10(counter = ctr[4i..4i+3], key). */
+int iugkp_dev_philox(const uint32_t *ctr, uint32_t key0, uint32_t key1, uint32_t *out,
+                     int64_t n, void *stream);
+/* iugkp_dev_math: op 0 = log(x), 1 = cos(2 pi x) for x in [0,1), 2 = sqrt(x),
+ * 3 = x / y, 4 = (double) of the int64 bits of x, 5 = rint(ldexp(x, k)) as int64 bits
+ * with k = (int)y; out[i] = op(x[i], y[i]). */
+int iugkp_dev_math(int op, const double *x, const double *y, double *out, int64_t n,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

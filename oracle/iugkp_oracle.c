@@ -181,6 +181,37 @@ double orc_cos2pi(double u)
   }
 }
 
+/* Vectorised probes of the building blocks (for element-wise comparisons). */
+void orc_philox_batch(const uint32_t *ctr, uint64_t n, uint32_t k0, uint32_t k1, uint32_t *out)
+{
+  uint32_t key[2] = {k0, k1};
+  for (uint64_t i = 0; i < n; ++i) orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+void orc_math_batch(int op, const double *x, const double *y, double *out, uint64_t n)
+{
+  for (uint64_t i = 0; i < n; ++i) {
+    switch (op) {
+      case 0: out[i] = orc_log(x[i]); break;
+      case 1: out[i] = orc_cos2pi(x[i]); break;
+      case 2: out[i] = sqrt(x[i]); break;
+      case 3: out[i] = x[i] / y[i]; break;
+      case 4: {
+        int64_t v;
+        memcpy(&v, &x[i], 8);
+        out[i] = (double)v;
+        break;
+      }
+      case 5: {
+        int64_t v = (int64_t)rint(ldexp(x[i], (int)y[i]));
+        memcpy(&out[i], &v, 8);
+        break;
+      }
+      default: out[i] = 0.0;
+    }
+  }
+}
+
 /* Particle k's share of an emitter's integer energy G over n particles:
  * floor(G/n) plus one for the first (G - n floor(G/n)) particles. */
 int64_t orc_split_weight(int64_t G, uint64_t n, uint64_t k)

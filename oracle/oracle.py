@@ -81,6 +81,8 @@ def lib():
         L.orc_log.restype = C.c_double
         L.orc_cos2pi.argtypes = [C.c_double]
         L.orc_cos2pi.restype = C.c_double
+        L.orc_philox_batch.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, P]
+        L.orc_math_batch.argtypes = [C.c_int, P, P, P, C.c_uint64]
         L.orc_split_weight.argtypes = [C.c_int64, C.c_uint64, C.c_uint64]
         L.orc_split_weight.restype = C.c_int64
         L.orc_tree_sum.argtypes = [P, C.c_uint64]
@@ -120,6 +122,21 @@ def philox(ctr: np.ndarray, key) -> np.ndarray:
     L = lib()
     for i in range(ctr.shape[0]):
         L.orc_philox4x32_10(ctr[i].ctypes.data, k.ctypes.data, out[i].ctypes.data)
+    return out
+
+
+def philox_batch(ctr: np.ndarray, key) -> np.ndarray:
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(ctr)
+    lib().orc_philox_batch(ctr.ctypes.data, ctr.shape[0], int(key[0]), int(key[1]), out.ctypes.data)
+    return out
+
+
+def math_batch(op: int, x: np.ndarray, y: Optional[np.ndarray] = None) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = None if y is None else np.ascontiguousarray(y, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_math_batch(op, x.ctypes.data, _ptr(y), out.ctypes.data, x.size)
     return out
 
 

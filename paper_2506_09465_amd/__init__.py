@@ -1,0 +1,22 @@
+"""MI355X (gfx950) implementation of the implicit unified gas-kinetic particle
+(IUGKP) steady-state solver for multiscale gray phonon transport.
+
+The compute path is the HIP library libiugkp.so (C ABI in include/iugkp.h);
+this package only marshals arguments to it.
+"""
+from ._lib import (FACES_EVERY, FACES_FINAL, FACES_OFF, RNG_CRN, RNG_FRESH, IugkpError,
+                   lib as library)
+
+__all__ = ["Solver", "BatchSolver", "d_eff", "dev_philox", "dev_math", "FACES_EVERY",
+           "FACES_FINAL", "FACES_OFF", "RNG_CRN", "RNG_FRESH", "IugkpError", "library"]
+
+
+def __getattr__(name):
+    # torch is imported lazily so that the C-ABI declarations load without it
+    if name in ("Solver", "d_eff", "dev_philox", "dev_math"):
+        from . import solver
+        return getattr(solver, name)
+    if name == "BatchSolver":
+        from . import batch
+        return batch.BatchSolver
+    raise AttributeError(name)

@@ -1,0 +1,671 @@
+// kernels.hpp -- gfx950 kernels of one IUGKP iteration.
+//
+//   prepare_kernel   zero the tallies, split every emitter's integer energy over
+//                    its N particles (floor + remainder), put the wall emission on
+//                    the wall faces
+//   march_kernel     Sec. 3.1 step (2) / Sec. 3.2 steps (3)-(5): sample, fly, tally
+//   update kernels   Sec. 3.1 step (3) / Sec. 3.3: E^{n+1/2} = W / V, Newton RHS,
+//                    next emission, squared update per cell, fixed-order partials
+//   finish_kernel    fixed-order totals -> relative residual, status flags
+//   newton_operator_kernel / cg_kernel   the diffusion correction of Sec. 3.3
+//
+// Reductions that feed floating-point results use one fixed order: blocks of 256
+// consecutive values (zero-padded), each reduced by halving strides
+// (v[i] += v[i + s], s = 128 ... 1); the block sums are reduced the same way.
+// Integer tallies use 64-bit atomics: exact, so any order gives the same bits.
+#pragma once
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_core.hpp"
+
+namespace iugkp {
+
+constexpr int kTree = 256;                       // fixed reduction block
+constexpr uint32_t kMaxSegments = 1u << 20;      // last allowed segment always ends real
+constexpr unsigned long long kBudgetCap = (1ull << 62) + 1ull;
+
+struct Mesh {
+  int dim, nx, ny;
+  int n_cells, n_b, n_emit;
+  int n_fx, n_fy;
+  double dx, dy;
+};
+
+struct Tallies {
+  long long *D, *W, *Phix, *Phiy, *B;
+};
+
+// Device-side per-iteration scalars (one struct per solve).
+struct DevScalars {
+  unsigned long long flights, segments, crossings;
+  unsigned long long gsum;      // saturating sum of |G| (Newton emission budget)
+  double dn, d0, res;
+  int flags;                    // bit 0: non-finite energy, bit 1: fixed-point overflow
+  int cg_iters, cg_status;
+};
+
+// ---------------------------------------------------------------------------
+// fixed-order block tree in LDS; every thread of a 256-wide block participates
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_tree256(double v, double *lds)
+{
+  const int t = threadIdx.x;
+  lds[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kTree / 2; s >= 1; s >>= 1) {
+    if (t < s) lds[t] = lds[t] + lds[t + s];
+    __syncthreads();
+  }
+  const double r = lds[0];
+  __syncthreads();
+  return r;
+}
+
+// Reduce n (<= 65536) block sums with the same tree (two levels at most);
+// blockDim.x >= 256, all threads call it, all get the result.
+__device__ double tree_all(const double *part, int n, double *lds, double *lds2)
+{
+  const int t = threadIdx.x;
+  const int nb = (n + kTree - 1) / kTree;
+  for (int b = 0; b < nb; ++b) {
+    double v = 0.0;
+    if (t < kTree) {
+      const int i = b * kTree + t;
+      v = (i < n) ? part[i] : 0.0;
+      lds[t] = v;
+    }
+    __syncthreads();
+    for (int s = kTree / 2; s >= 1; s >>= 1) {
+      if (t < s) lds[t] = lds[t] + lds[t + s];
+      __syncthreads();
+    }
+    if (t == 0) lds2[b] = lds[0];
+    __syncthreads();
+  }
+  if (nb == 1) {
+    const double r = lds2[0];
+    __syncthreads();
+    return r;
+  }
+  if (t < kTree) lds[t] = (t < nb) ? lds2[t] : 0.0;
+  __syncthreads();
+  for (int s = kTree / 2; s >= 1; s >>= 1) {
+    if (t < s) lds[t] = lds[t] + lds[t + s];
+    __syncthreads();
+  }
+  const double r = lds[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// prepare: zero tallies, per-emitter split, wall emission on the wall faces
+// ---------------------------------------------------------------------------
+__global__ void prepare_kernel(Mesh m, const long long *__restrict__ G, uint32_t N,
+                               long long *__restrict__ base, uint32_t *__restrict__ rem,
+                               Tallies t, int faces, DevScalars *sc)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    sc->flights = 0;
+    sc->segments = 0;
+    sc->crossings = 0;
+    sc->gsum = 0;
+    sc->flags = 0;
+  }
+  if (i < m.n_cells) {
+    t.D[i] = 0;
+    t.W[i] = 0;
+  }
+  if (i < m.n_b) t.B[i] = 0;
+  if (i < m.n_emit) {
+    // floor division of a signed energy by N with a non-negative remainder
+    const long long g = G[i];
+    const long long n = static_cast<long long>(N);
+    long long b = g / n;
+    if (g % n != 0 && g < 0) b -= 1;
+    base[i] = b;
+    rem[i] = static_cast<uint32_t>(g - b * n);
+  }
+  if (i < m.n_fx) {
+    long long v = 0;
+    if (faces) {
+      const int row = i / (m.nx + 1), k = i - row * (m.nx + 1);
+      if (k == 0) v = G[m.n_cells + row];                 // left wall emits along +x
+      else if (k == m.nx) v = -G[m.n_cells + m.ny + row];  // right wall emits along -x
+    }
+    t.Phix[i] = v;
+  }
+  if (i < m.n_fy) {
+    long long v = 0;
+    if (faces) {
+      const int k = i / m.nx, col = i - k * m.nx;
+      if (k == 0) v = G[m.n_cells + 2 * m.ny + col];
+      else if (k == m.ny) v = -G[m.n_cells + 2 * m.ny + m.nx + col];
+    }
+    t.Phiy[i] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The particle step.  One lane per particle; particle p belongs to emitter
+// e = p mod n_emit (emitter index runs fastest, so a wavefront's lanes start in
+// 64 different cells and their first face tallies hit different addresses),
+// its index within the emitter is k = p / n_emit.
+// ---------------------------------------------------------------------------
+struct MarchArgs {
+  Mesh m;
+  double lam_min;
+  uint32_t N, slot, key0, key1;
+  uint32_t n_particles;
+  int faces, has_null;
+  const long long *base;
+  const uint32_t *rem;
+  const double *ratio;
+  Tallies t;
+  DevScalars *sc;
+};
+
+__device__ __forceinline__ void tally_add(long long *a, long long v)
+{
+  atomicAdd(reinterpret_cast<unsigned long long *>(a), static_cast<unsigned long long>(v));
+}
+
+__device__ __forceinline__ double clamp_to(double v, double lo, double hi)
+{
+  return (v < lo) ? lo : ((v > hi) ? hi : v);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void march_kernel(MarchArgs a)
+{
+  __shared__ unsigned long long s_cnt[3];
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+
+  const Mesh &m = a.m;
+  const uint32_t p = blockIdx.x * BS + threadIdx.x;
+  unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
+  if (p < a.n_particles) {
+    const uint32_t e = p % static_cast<uint32_t>(m.n_emit);
+    const uint32_t k = p / static_cast<uint32_t>(m.n_emit);
+    const long long q = a.base[e] + ((k < a.rem[e]) ? 1 : 0);
+    if (q != 0) {
+      n_fl = 1;
+      const double2 uab = draw2(0u, k, e, a.slot, a.key0, a.key1);
+      const double2 ucd = draw2(1u, k, e, a.slot, a.key0, a.key1);
+      int ix, iy;
+      double x0, y0, sx, sy;
+      if (e < static_cast<uint32_t>(m.n_cells)) {
+        // isotropic emission from a uniformly sampled point of the cell
+        iy = static_cast<int>(e) / m.nx;
+        ix = static_cast<int>(e) - iy * m.nx;
+        x0 = (static_cast<double>(ix) + uab.x) * m.dx;
+        y0 = (static_cast<double>(iy) + uab.y) * m.dy;
+        const double mu = 2.0 * ucd.x - 1.0;
+        sx = mu;
+        sy = (m.dim == 2) ? sqrt((1.0 - mu) * (1.0 + mu)) * cos2pi_own(ucd.y) : 0.0;
+      } else {
+        // cosine-law emission from a black wall face into the domain
+        const int b = static_cast<int>(e) - m.n_cells;
+        const double cn = sqrt(ucd.x);
+        const double tg = (m.dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * cos2pi_own(ucd.y) : 0.0;
+        if (b < m.ny) {
+          ix = 0; iy = b;
+          x0 = 0.0; y0 = (static_cast<double>(iy) + uab.x) * m.dy;
+          sx = cn; sy = tg;
+        } else if (b < 2 * m.ny) {
+          ix = m.nx - 1; iy = b - m.ny;
+          x0 = static_cast<double>(m.nx) * m.dx; y0 = (static_cast<double>(iy) + uab.x) * m.dy;
+          sx = -cn; sy = tg;
+        } else if (b < 2 * m.ny + m.nx) {
+          ix = b - 2 * m.ny; iy = 0;
+          x0 = (static_cast<double>(ix) + uab.x) * m.dx; y0 = 0.0;
+          sx = tg; sy = cn;
+        } else {
+          ix = b - 2 * m.ny - m.nx; iy = m.ny - 1;
+          x0 = (static_cast<double>(ix) + uab.x) * m.dx; y0 = static_cast<double>(m.ny) * m.dy;
+          sx = tg; sy = -cn;
+        }
+      }
+      const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+      const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+      const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+      const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+      const long long qx = (stx > 0) ? q : -q;
+      const long long qy = (sty > 0) ? q : -q;
+      for (uint32_t j = 0;; ++j) {
+        const double2 us = draw2(2u + j, k, e, a.slot, a.key0, a.key1);
+        // candidate free path on the common time scale tau_min: -|V_g| tau_min ln(eta)
+        const double ell = -(a.lam_min * log_own(1.0 - us.x));
+        ++n_seg;
+        int kx = (stx > 0) ? ix + 1 : ix;
+        int ky = (sty > 0) ? iy + 1 : iy;
+        int bface = -1;
+        for (;;) {
+          const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
+          const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
+          const bool along_x = tx <= ty;
+          const double tt = along_x ? tx : ty;
+          if (!(tt < ell)) break;
+          ++n_cross;
+          if (along_x) {
+            if (a.faces) tally_add(&a.t.Phix[iy * (m.nx + 1) + kx], qx);
+            if (kx == 0 || kx == m.nx) {
+              bface = (kx == 0) ? iy : m.ny + iy;
+              break;
+            }
+            ix += stx;
+            kx += stx;
+          } else {
+            if (a.faces) tally_add(&a.t.Phiy[ky * m.nx + ix], qy);
+            if (ky == 0 || ky == m.ny) {
+              bface = (ky == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
+              break;
+            }
+            iy += sty;
+            ky += sty;
+          }
+        }
+        if (bface >= 0) {
+          tally_add(&a.t.B[bface], q);
+          break;
+        }
+        const int c = ix + m.nx * iy;
+        if (!a.has_null) {
+          tally_add(&a.t.D[c], q);   // every candidate is real: W == D
+          break;
+        }
+        tally_add(&a.t.W[c], q);
+        // accept with probability sigma / sigma_max = tau_min / tau_c
+        if (us.y < a.ratio[c] || j == kMaxSegments - 1) {
+          tally_add(&a.t.D[c], q);
+          break;
+        }
+        // null collision: keep the direction, restart from the stopping point
+        x0 = clamp_to(x0 + ell * sx, static_cast<double>(ix) * m.dx,
+                      static_cast<double>(ix + 1) * m.dx);
+        if (m.dim == 2)
+          y0 = clamp_to(y0 + ell * sy, static_cast<double>(iy) * m.dy,
+                        static_cast<double>(iy + 1) * m.dy);
+      }
+    }
+  }
+  if (n_fl) {
+    atomicAdd(&s_cnt[0], n_fl);
+    atomicAdd(&s_cnt[1], n_seg);
+    atomicAdd(&s_cnt[2], n_cross);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cnt[0]) {
+    atomicAdd(&a.sc->flights, s_cnt[0]);
+    atomicAdd(&a.sc->segments, s_cnt[1]);
+    atomicAdd(&a.sc->crossings, s_cnt[2]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// macroscopic update (256-wide blocks, block b owns cells [256 b, 256 b + 256))
+// ---------------------------------------------------------------------------
+struct UpdateArgs {
+  int n_cells, F, has_null, newton;
+  double V;
+  const long long *D, *W;
+  double *E, *E_half, *rhs;
+  long long *G;
+  double *part;         // per-block partial of the squared update (plain path)
+  DevScalars *sc;
+};
+
+// Plain path: E^{n+1} = E^{n+1/2} = W / V, next emission = D (Sec. 3.2 step (2)).
+// Newton path: E^{n+1/2} and the right-hand side E^{n+1/2} - E^n only.
+__global__ __launch_bounds__(256) void update_kernel(UpdateArgs a)
+{
+  __shared__ double lds[kTree];
+  const int c = blockIdx.x * kTree + threadIdx.x;
+  double sq = 0.0;
+  int bad = 0;
+  if (c < a.n_cells) {
+    const long long w = a.has_null ? a.W[c] : a.D[c];
+    const double eh = ldexp(static_cast<double>(w), -a.F) / a.V;
+    a.E_half[c] = eh;
+    if (a.newton) {
+      a.rhs[c] = eh - a.E[c];
+    } else {
+      const double d = eh - a.E[c];
+      sq = d * d;
+      bad = !isfinite(eh);
+      a.E[c] = eh;
+      a.G[c] = a.D[c];
+    }
+  }
+  if (a.newton) return;
+  if (bad) atomicOr(&a.sc->flags, 1);
+  const double s = block_tree256(sq, lds);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+}
+
+struct NewtonFinishArgs {
+  int n_cells, n_emit, F;
+  double V;
+  const double *E_half, *x, *ratio;
+  double *E;
+  long long *G;
+  double *part;
+  unsigned long long *gpart;
+  DevScalars *sc;
+};
+
+// E^{n+1} = E^{n+1/2} + dE, next emission rint(2^F (E^{n+1} V) tau_min / tau_c),
+// squared update partials and the saturating |G| budget partials.
+__global__ __launch_bounds__(256) void newton_finish_kernel(NewtonFinishArgs a)
+{
+  __shared__ double lds[kTree];
+  __shared__ unsigned long long lg[kTree];
+  const int c = blockIdx.x * kTree + threadIdx.x;
+  double sq = 0.0;
+  unsigned long long ag = 0;
+  int flags = 0;
+  if (c < a.n_cells) {
+    const double en = a.E_half[c] + a.x[c];
+    const double d = en - a.E[c];
+    sq = d * d;
+    if (!isfinite(en)) flags |= 1;
+    a.E[c] = en;
+    const double v = ldexp((en * a.V) * a.ratio[c], a.F);
+    if (!(fabs(v) <= 4611686018427387904.0)) {
+      flags |= 2;
+      a.G[c] = 0;
+    } else {
+      const long long g = static_cast<long long>(rint(v));
+      a.G[c] = g;
+      ag = static_cast<unsigned long long>(g < 0 ? -g : g);
+    }
+  }
+  // wall emitters count toward the budget as well
+  if (c >= a.n_cells && c < a.n_emit) {
+    const long long g = a.G[c];
+    ag = static_cast<unsigned long long>(g < 0 ? -g : g);
+  }
+  if (flags) atomicOr(&a.sc->flags, flags);
+  const double s = block_tree256(sq, lds);
+  lg[threadIdx.x] = ag > kBudgetCap ? kBudgetCap : ag;
+  __syncthreads();
+  for (int st = kTree / 2; st >= 1; st >>= 1) {
+    if (threadIdx.x < st) {
+      const unsigned long long u = lg[threadIdx.x] + lg[threadIdx.x + st];
+      lg[threadIdx.x] = u > kBudgetCap ? kBudgetCap : u;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.part[blockIdx.x] = s;
+    a.gpart[blockIdx.x] = lg[0];
+  }
+}
+
+// Totals of the partials (fixed order), relative residual, budget.
+__global__ __launch_bounds__(256) void finish_kernel(const double *part, int n_part,
+                                                     const unsigned long long *gpart, int n_gpart,
+                                                     int first, DevScalars *sc)
+{
+  __shared__ double lds[kTree];
+  __shared__ double lds2[kTree];
+  const double dsq = tree_all(part, n_part, lds, lds2);
+  if (threadIdx.x == 0) {
+    unsigned long long g = 0;
+    for (int i = 0; i < n_gpart; ++i) {
+      g += gpart[i];
+      if (g > kBudgetCap) g = kBudgetCap;
+    }
+    sc->gsum = g;
+    const double dn = sqrt(dsq);
+    sc->dn = dn;
+    if (first) sc->d0 = dn;
+    const double d0 = sc->d0;
+    sc->res = (d0 > 0.0) ? dn / d0 : 0.0;
+  }
+}
+
+// Initial cell emission from E (creation / restored state): G = rint(2^F (E V) r).
+__global__ void emission_from_E_kernel(int n_cells, int F, double V, const double *E,
+                                       const double *ratio, long long *G, int *flag)
+{
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  const double v = ldexp((E[c] * V) * ratio[c], F);
+  if (!(fabs(v) <= 4611686018427387904.0)) {
+    atomicOr(flag, 2);
+    G[c] = 0;
+    return;
+  }
+  G[c] = static_cast<long long>(rint(v));
+}
+
+// E0 = cv (T0 - t_ref), ratio = tau_min / tau.
+__global__ void init_cells_kernel(int n_cells, double cv, double t_ref, double tau_min,
+                                  const double *T0, const double *tau, double *E, double *ratio)
+{
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  const double T = T0 ? T0[c] : t_ref;
+  E[c] = cv * (T - t_ref);
+  ratio[c] = tau_min / tau[c];
+}
+
+// ---------------------------------------------------------------------------
+// Newton operator (Sec. 3.3): conservative -div(D grad) on the mesh, interior
+// face conductance H(D_a, D_b) / d^2 (harmonic mean), wall faces
+// D_c / (d (d/2 + 2 lambda_c / 3)) (extrapolation length 2 lambda / 3).
+// ---------------------------------------------------------------------------
+__global__ void newton_operator_kernel(Mesh m, double vg, const double *tau, const double *Dx,
+                                       const double *Dy, double *gx, double *gy, double *diag)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m.n_fx) {
+    const int iy = i / (m.nx + 1), kx = i - iy * (m.nx + 1);
+    double g;
+    if (kx == 0 || kx == m.nx) {
+      const int c = iy * m.nx + (kx == 0 ? 0 : m.nx - 1);
+      const double lam = vg * tau[c];
+      const double den = m.dx * (m.dx / 2.0 + (2.0 * lam) / 3.0);
+      g = Dx[c] / den;
+    } else {
+      const double da = Dx[iy * m.nx + kx - 1], db = Dx[iy * m.nx + kx];
+      const double h = ((2.0 * da) * db) / (da + db);
+      g = h / (m.dx * m.dx);
+    }
+    gx[i] = g;
+  }
+  if (m.dim == 2 && i < m.n_fy) {
+    const int ky = i / m.nx, ix = i - ky * m.nx;
+    double g;
+    if (ky == 0 || ky == m.ny) {
+      const int c = (ky == 0 ? 0 : m.ny - 1) * m.nx + ix;
+      const double lam = vg * tau[c];
+      const double den = m.dy * (m.dy / 2.0 + (2.0 * lam) / 3.0);
+      g = Dy[c] / den;
+    } else {
+      const double da = Dy[(ky - 1) * m.nx + ix], db = Dy[ky * m.nx + ix];
+      const double h = ((2.0 * da) * db) / (da + db);
+      g = h / (m.dy * m.dy);
+    }
+    gy[i] = g;
+  }
+}
+
+__global__ void newton_diag_kernel(Mesh m, const double *gx, const double *gy, double *diag)
+{
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m.n_cells) return;
+  const int iy = c / m.nx, ix = c - iy * m.nx;
+  double d = gx[iy * (m.nx + 1) + ix] + gx[iy * (m.nx + 1) + ix + 1];
+  if (m.dim == 2) {
+    d = d + gy[iy * m.nx + ix];
+    d = d + gy[(iy + 1) * m.nx + ix];
+  }
+  diag[c] = d;
+}
+
+// ---------------------------------------------------------------------------
+// Conjugate gradients (Hestenes-Stiefel, x0 = 0, stop at r.r <= tol^2 b.b) as
+// one persistent cooperative kernel.  Workgroup j owns the 256-cell tree
+// blocks j, j + grid, ...  Two grid barriers per iteration: the search
+// direction p = r + beta p_old is formed on the fly inside the operator
+// application (also for the neighbours, from r and p_old which no one writes
+// in that phase), with p double-buffered.
+// ---------------------------------------------------------------------------
+struct CGArgs {
+  Mesh m;
+  const double *gx, *gy, *diag, *b;
+  double *x, *r, *p0, *p1, *Ap;
+  double *part_a, *part_b;
+  double tol2;
+  int max_iters;
+  DevScalars *sc;
+};
+
+__device__ __forceinline__ double cg_dir(const double *r, const double *pold, double beta,
+                                         int first, int c)
+{
+  return first ? r[c] : r[c] + beta * pold[c];
+}
+
+__global__ __launch_bounds__(256) void cg_kernel(CGArgs a)
+{
+  namespace cgs = cooperative_groups;
+  cgs::grid_group grid = cgs::this_grid();
+  __shared__ double lds[kTree];
+  __shared__ double lds2[kTree];
+  const Mesh &m = a.m;
+  const int n = m.n_cells;
+  const int nb = (n + kTree - 1) / kTree;
+  const int t = threadIdx.x;
+  for (int tb = blockIdx.x; tb < nb; tb += gridDim.x) {
+    const int c = tb * kTree + t;
+    double v = 0.0;
+    if (c < n) {
+      const double bc = a.b[c];
+      a.x[c] = 0.0;
+      a.r[c] = bc;
+      v = bc * bc;
+    }
+    v = block_tree256(v, lds);
+    if (t == 0) a.part_b[tb] = v;
+  }
+  __threadfence();
+  grid.sync();
+  double rr = tree_all(a.part_b, nb, lds, lds2);
+  const double thr = a.tol2 * rr;
+  int status = -7;     // not converged unless proven otherwise
+  int it = 0;
+  double beta = 0.0;
+  double *pold = a.p0, *pnew = a.p1;
+  if (rr == 0.0) status = 0;
+  while (status == -7 && it < a.max_iters) {
+    const int first = (it == 0);
+    for (int tb = blockIdx.x; tb < nb; tb += gridDim.x) {
+      const int c = tb * kTree + t;
+      double v = 0.0;
+      if (c < n) {
+        const int iy = c / m.nx, ix = c - iy * m.nx;
+        const double pc = cg_dir(a.r, pold, beta, first, c);
+        double acc = a.diag[c] * pc;
+        if (ix > 0) acc = acc - a.gx[iy * (m.nx + 1) + ix] * cg_dir(a.r, pold, beta, first, c - 1);
+        if (ix < m.nx - 1)
+          acc = acc - a.gx[iy * (m.nx + 1) + ix + 1] * cg_dir(a.r, pold, beta, first, c + 1);
+        if (m.dim == 2) {
+          if (iy > 0) acc = acc - a.gy[iy * m.nx + ix] * cg_dir(a.r, pold, beta, first, c - m.nx);
+          if (iy < m.ny - 1)
+            acc = acc - a.gy[(iy + 1) * m.nx + ix] * cg_dir(a.r, pold, beta, first, c + m.nx);
+        }
+        pnew[c] = pc;
+        a.Ap[c] = acc;
+        v = pc * acc;
+      }
+      v = block_tree256(v, lds);
+      if (t == 0) a.part_a[tb] = v;
+    }
+    __threadfence();
+    grid.sync();
+    const double pAp = tree_all(a.part_a, nb, lds, lds2);
+    if (!(pAp > 0.0)) {
+      status = -6;
+      break;
+    }
+    const double alpha = rr / pAp;
+    for (int tb = blockIdx.x; tb < nb; tb += gridDim.x) {
+      const int c = tb * kTree + t;
+      double v = 0.0;
+      if (c < n) {
+        a.x[c] = a.x[c] + alpha * pnew[c];
+        const double rc = a.r[c] - alpha * a.Ap[c];
+        a.r[c] = rc;
+        v = rc * rc;
+      }
+      v = block_tree256(v, lds);
+      if (t == 0) a.part_b[tb] = v;
+    }
+    __threadfence();
+    grid.sync();
+    const double rr_new = tree_all(a.part_b, nb, lds, lds2);
+    ++it;
+    if (rr_new <= thr) {
+      status = 0;
+      break;
+    }
+    beta = rr_new / rr;
+    rr = rr_new;
+    double *tmp = pold;
+    pold = pnew;
+    pnew = tmp;
+  }
+  if (blockIdx.x == 0 && t == 0) {
+    a.sc->cg_iters = it;
+    a.sc->cg_status = status;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// building-block probes
+// ---------------------------------------------------------------------------
+__global__ void philox_probe_kernel(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
+                                    long long n)
+{
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint4 o = philox4x32_10(make_uint4(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2],
+                                           ctr[4 * i + 3]), k0, k1);
+  out[4 * i] = o.x;
+  out[4 * i + 1] = o.y;
+  out[4 * i + 2] = o.z;
+  out[4 * i + 3] = o.w;
+}
+
+__global__ void math_probe_kernel(int op, const double *x, const double *y, double *out,
+                                  long long n)
+{
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = x[i];
+  double r = 0.0;
+  switch (op) {
+    case 0: r = log_own(a); break;
+    case 1: r = cos2pi_own(a); break;
+    case 2: r = sqrt(a); break;
+    case 3: r = a / y[i]; break;
+    case 4: r = static_cast<double>(__double_as_longlong(a)); break;
+    case 5: {
+      const long long v = static_cast<long long>(rint(ldexp(a, static_cast<int>(y[i]))));
+      r = __longlong_as_double(v);
+      break;
+    }
+    default: break;
+  }
+  out[i] = r;
+}
+
+}  // namespace iugkp

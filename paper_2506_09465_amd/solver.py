@@ -1,0 +1,183 @@
+"""Python front end of the gfx950 IUGKP library.
+
+torch provides device memory and the current HIP stream; every step of the
+method runs in the library's kernels.  A problem is any object with the
+attributes dim, nx, ny, dx, dy, t_ref, cv, vg, tau, wall_T and optionally
+T_init (for example a `synth.Workload`).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _dev_f64(a, device) -> Optional[torch.Tensor]:
+    if a is None:
+        return None
+    t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64) if not torch.is_tensor(a) else a)
+    return t.to(device=device, dtype=torch.float64).contiguous()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class _Marshal:
+    """Device copies of a problem's arrays plus the Problem/Options structs."""
+
+    def __init__(self, w, device, *, seed, particles, rng_mode, epoch, max_iters, res_tol,
+                 newton, diff_x, diff_y, cg_tol, cg_max_iters, tally_faces, avg_iters,
+                 block_size, T_init=None):
+        self.tau = _dev_f64(w.tau, device)
+        self.wall = _dev_f64(w.wall_T, device)
+        Ti = T_init if T_init is not None else getattr(w, "T_init", None)
+        self.T_init = _dev_f64(Ti, device)
+        self.dx_arr = _dev_f64(diff_x, device)
+        self.dy_arr = _dev_f64(diff_y, device)
+        self.problem = L.Problem(int(w.dim), int(w.nx), int(w.ny), float(w.dx), float(w.dy),
+                                 float(w.t_ref), float(w.cv), float(w.vg), _ptr(self.tau),
+                                 _ptr(self.wall), _ptr(self.T_init), _ptr(self.dx_arr),
+                                 _ptr(self.dy_arr), L.MEM_DEVICE)
+        self.options = L.Options(int(seed), int(particles), int(rng_mode), int(epoch),
+                                 int(max_iters), float(res_tol), int(bool(newton)),
+                                 float(cg_tol), int(cg_max_iters), int(tally_faces),
+                                 int(avg_iters), int(block_size))
+
+
+def _defaults(w, kw):
+    return dict(seed=kw.pop("seed", getattr(w, "seed", 0)),
+                particles=kw.pop("particles", getattr(w, "particles_per_iter", 100_000)),
+                rng_mode=kw.pop("rng_mode", L.RNG_FRESH), epoch=kw.pop("epoch", 0),
+                max_iters=kw.pop("max_iters", getattr(w, "max_iters", 200)),
+                res_tol=kw.pop("res_tol", getattr(w, "res_tol", 1e-6)),
+                newton=kw.pop("newton", getattr(w, "newton", False)),
+                diff_x=kw.pop("diff_x", None), diff_y=kw.pop("diff_y", None),
+                cg_tol=kw.pop("cg_tol", getattr(w, "cg_tol", 1e-10)),
+                cg_max_iters=kw.pop("cg_max_iters", 200_000),
+                tally_faces=kw.pop("tally_faces", L.FACES_EVERY),
+                avg_iters=kw.pop("avg_iters", 0), block_size=kw.pop("block_size", 0),
+                T_init=kw.pop("T_init", None))
+
+
+class Solver:
+    """One problem on one GPU: create, step, read tallies/state, solve."""
+
+    def __init__(self, w, device="cuda", **kw):
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("the IUGKP library needs a ROCm GPU (torch.cuda) device")
+        opts = _defaults(w, kw)
+        if kw:
+            raise TypeError(f"unknown options {sorted(kw)}")
+        self.w = w
+        self.nc = int(w.nx * w.ny)
+        self.nb = 2 * int(w.ny) + (2 * int(w.nx) if w.dim == 2 else 0)
+        self.ne = self.nc + self.nb
+        self.nfx = int(w.ny) * (int(w.nx) + 1)
+        self.nfy = (int(w.ny) + 1) * int(w.nx) if w.dim == 2 else 0
+        with torch.cuda.device(self.device):
+            self._m = _Marshal(w, self.device, **opts)
+            h = C.c_void_p()
+            L.check(L.lib().iugkp_create(C.byref(self._m.problem), C.byref(self._m.options),
+                                         C.c_void_p(_stream_handle(self.device)), C.byref(h)),
+                    "iugkp_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().iugkp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ stepping
+    def step(self, n: int = 1, faces: Optional[bool] = None) -> int:
+        with torch.cuda.device(self.device):
+            if faces is None:
+                rc = L.lib().iugkp_step(self.h, int(n))
+            else:
+                rc = L.lib().iugkp_step_faces(self.h, int(n), int(bool(faces)))
+        return rc
+
+    def solve(self):
+        T = torch.empty(self.nc, dtype=torch.float64, device=self.device)
+        qx = torch.empty(self.nfx, dtype=torch.float64, device=self.device)
+        qy = torch.empty(max(self.nfy, 1), dtype=torch.float64, device=self.device)
+        st = L.Stats()
+        with torch.cuda.device(self.device):
+            rc = L.lib().iugkp_solve(self.h, T.data_ptr(), qx.data_ptr(), qy.data_ptr(),
+                                     C.byref(st))
+        L.check(rc, "iugkp_solve", allow_warning=True)
+        return rc, T, qx, qy[:self.nfy], st.as_dict()
+
+    # ------------------------------------------------------------------ readers
+    def tallies(self):
+        z = lambda n: torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        D, W, Px, Py, B = z(self.nc), z(self.nc), z(self.nfx), z(self.nfy), z(self.nb)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().iugkp_get_tallies(self.h, D.data_ptr(), W.data_ptr(), Px.data_ptr(),
+                                              Py.data_ptr(), B.data_ptr()), "iugkp_get_tallies")
+        return {"D": D, "W": W, "Phix": Px, "Phiy": Py[:self.nfy], "B": B}
+
+    def state(self):
+        it = C.c_uint32(0)
+        d0 = C.c_double(0.0)
+        E = torch.empty(self.nc, dtype=torch.float64, device=self.device)
+        G = torch.empty(self.ne, dtype=torch.int64, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().iugkp_get_state(self.h, C.addressof(it), C.addressof(d0),
+                                            E.data_ptr(), G.data_ptr()), "iugkp_get_state")
+        return it.value, d0.value, E, G
+
+    def set_state(self, it: int, d0: float, E, G) -> int:
+        E = _dev_f64(E, self.device)
+        G = torch.as_tensor(G).to(device=self.device, dtype=torch.int64).contiguous()
+        with torch.cuda.device(self.device):
+            return L.lib().iugkp_set_state(self.h, int(it), float(d0), E.data_ptr(), G.data_ptr())
+
+    def stats(self) -> dict:
+        st = L.Stats()
+        L.check(L.lib().iugkp_get_stats(self.h, C.byref(st)), "iugkp_get_stats")
+        return st.as_dict()
+
+    def residuals(self) -> np.ndarray:
+        n = self.stats()["iters"]
+        r = np.zeros(max(n, 1))
+        k = L.lib().iugkp_get_residuals(self.h, r.ctypes.data, n)
+        return r[:max(k, 0)]
+
+
+def d_eff(lam: float, delta: float) -> float:
+    return L.lib().iugkp_d_eff(float(lam), float(delta))
+
+
+def dev_philox(ctr: torch.Tensor, key0: int, key1: int) -> torch.Tensor:
+    """Philox4x32-10 blocks for an (n, 4) int32-bit-pattern counter tensor on the GPU."""
+    ctr = ctr.contiguous()
+    out = torch.empty_like(ctr)
+    L.check(L.lib().iugkp_dev_philox(ctr.data_ptr(), int(key0) & 0xFFFFFFFF,
+                                     int(key1) & 0xFFFFFFFF, out.data_ptr(), ctr.shape[0],
+                                     C.c_void_p(_stream_handle(ctr.device))), "iugkp_dev_philox")
+    return out
+
+
+def dev_math(op: int, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    L.check(L.lib().iugkp_dev_math(int(op), x.data_ptr(), None if y is None else y.contiguous().data_ptr(),
+                                   out.data_ptr(), x.numel(),
+                                   C.c_void_p(_stream_handle(x.device))), "iugkp_dev_math")
+    return out
