@@ -1,0 +1,272 @@
+#!/usr/bin/env python3
+"""Benchmark of the IUGKP particle step on one MI355X.
+
+Workload: the 2D gray square cavity, 256 x 256 uniform cells, hot top wall
+T = 1.01, other walls 0.99, constant relaxation time at Kn = 0.01, 0.1, 1 and
+10, 1e7 particles per iteration, inexact-Newton diffusion acceleration (FP64
+CG, tol 1e-10), int64 fixed-point tallies, face (heat-flux) tallies every
+iteration.  Inputs are synthetic and seeded (seed 0).
+
+One step = one full iteration of the hot path for each of the four Kn
+problems: emitter split, sampling + flight + tallies, macroscopic update,
+Newton CG, residual.  Printed: one JSON line with flights/s over the timed
+steps, per-Kn breakdown, roofline of the dominant kernel (timed with HIP
+events on the library's stream), time-to-steady at residual 1e-6 (common
+random numbers, faces tallied on the output iteration) and the CPU oracle
+baseline on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+KNS = (0.01, 0.1, 1.0, 10.0)
+N_SIDE = 256
+PARTICLES = 10_000_000
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tts", action="store_true", help="skip time-to-steady")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="also time N batched vs sequential uneven cavity solves")
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
+                    help="particles per iteration in the CPU oracle sample")
+    return ap.parse_args()
+
+
+def march_bytes(flights, crossings, segments, n_emit, has_null):
+    """Algorithmic bytes of the particle step: 8 B read-modify-write per face
+    crossing and per final deposit/absorption, the emitter split (12 B per
+    emitter), and per null segment the relaxation-ratio gather plus the W tally
+    (16 B)."""
+    b = 8 * (crossings + flights) + 12 * n_emit
+    if has_null:
+        b += 16 * segments
+    return b
+
+
+def cg_bytes(cg_iters, n_cells):
+    """Per CG iteration: operator application reading r, p_old and three
+    coefficient arrays and writing p and Ap, then x, r updates reading x, p, r,
+    Ap and writing x, r: 13 doubles per cell."""
+    return 13 * 8 * n_cells * cg_iters
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "device_core.hpp", "iugkp.hip"):
+        with open(os.path.join(ROOT, "paper_2506_09465_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, src_hash):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != src_hash:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(sample):
+    """The CPU oracle on a bounded sample of the same step: for each Kn one
+    iteration with `sample` particles, once with and once without the Newton
+    CG, on one core.  The particle part is scaled to the full particle count;
+    the CG part is at full size already."""
+    import numpy as np
+    from oracle import oracle as O
+    from synth import cavity_2d
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import cp_model as cp
+    O.build()
+    t_total = 0.0
+    flights_full = 0
+    detail = {}
+    for kn in KNS:
+        w = cavity_2d(n=N_SIDE, kn=kn, particles=sample, newton=True)
+        lam = w.vg * w.tau
+        D = np.full(w.n_cells, cp.d_eff(float(lam[0]), w.dx))
+        # the Newton-accelerated state: every cell emits after the first iteration
+        o = O.Oracle(w, newton=True, diff_x=D, diff_y=D, tally_faces=O.FACES_EVERY)
+        o.step(2)
+        t0 = time.perf_counter()
+        o.step(1)
+        t_newton = time.perf_counter() - t0
+        fl = o.info().flights
+        # the same state without the CG: particle part alone
+        o_plain = O.Oracle(w, newton=False, tally_faces=O.FACES_EVERY)
+        it, d0, E, G = o.info().iter, o.info().d0, o.E(), o.G()
+        o_plain.set_state(it, d0, E, G)
+        t0 = time.perf_counter()
+        o_plain.step(1)
+        t_march = time.perf_counter() - t0
+        t_cg = max(0.0, t_newton - t_march)
+        scale = PARTICLES / sample
+        t_full = t_march * scale + t_cg
+        t_total += t_full
+        flights_full += fl * scale
+        detail[str(kn)] = {"s_particles_sampled": round(t_march, 3), "s_cg": round(t_cg, 3),
+                           "flights_sampled": fl, "s_full_iteration_est": round(t_full, 2)}
+    return {"value": flights_full / t_total, "unit": "flights/s", "cores": 1, "kind": "oracle",
+            "sample": f"one iteration per Kn of the 256x256 cavity with {sample} particles "
+                      f"(particle time scaled x{PARTICLES // sample} to 1e7) plus the full-size "
+                      f"Newton CG, single thread", "detail": detail}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2506_09465_amd as P
+    from synth import cavity_2d
+    assert torch.cuda.is_available(), "needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    solvers = []
+    for kn in KNS:
+        w = cavity_2d(n=N_SIDE, kn=kn, particles=PARTICLES, newton=True, seed=0)
+        solvers.append((kn, w, P.Solver(w, device=dev, tally_faces=P.FACES_EVERY)))
+
+    for _ in range(args.warmup):
+        for _, _, s in solvers:
+            s.step(1)
+    st0 = [s.stats() for _, _, s in solvers]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for _, _, s in solvers:
+            rc = s.step(1)
+            assert rc == 0, f"step failed with {rc}"
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = [s.stats() for _, _, s in solvers]
+
+    elapsed = t1 - t0
+    K = args.steps
+    per_kn = {}
+    tot = dict(flights=0, crossings=0, segments=0, ms_march=0.0, ms_cg=0.0, march_bytes=0,
+               cg_bytes=0, cg_iters=0, launches=0)
+    for (kn, w, s), a, b in zip(solvers, st0, st1):
+        fl = b["tot_flights"] - a["tot_flights"]
+        cr = b["tot_crossings"] - a["tot_crossings"]
+        sg = b["tot_segments"] - a["tot_segments"]
+        ms_m = b["ms_march"] - a["ms_march"]
+        ms_c = b["ms_cg"] - a["ms_cg"]
+        cgi = b["cg_iters_total"] - a["cg_iters_total"]
+        mb = march_bytes(fl, cr, sg, b["n_emitters"] * K, False)
+        cb = cg_bytes(cgi, w.n_cells)
+        per_kn[str(kn)] = {
+            "flights_per_iter": fl // K, "crossings_per_flight": round(cr / max(fl, 1), 2),
+            "ms_march": round(ms_m / K, 3), "ms_cg": round(ms_c / K, 3),
+            "cg_iters": cgi // K, "flights_per_s_march": fl / (ms_m / 1e3) if ms_m else None,
+            "march_GBs_algorithmic": mb / (ms_m / 1e3) / 1e9 if ms_m else None,
+        }
+        for k, v in (("flights", fl), ("crossings", cr), ("segments", sg), ("ms_march", ms_m),
+                     ("ms_cg", ms_c), ("march_bytes", mb), ("cg_bytes", cb), ("cg_iters", cgi)):
+            tot[k] += v
+        tot["launches"] += K
+
+    src = source_hash()
+    kernels = {
+        "march_kernel": {"ms": tot["ms_march"], "bytes": tot["march_bytes"], "launches": tot["launches"]},
+        "cg_kernel": {"ms": tot["ms_cg"], "bytes": tot["cg_bytes"], "launches": tot["launches"]},
+    }
+    rooflines = {}
+    for name, k in kernels.items():
+        avg_ms = k["ms"] / k["launches"]
+        per_launch = k["bytes"] / k["launches"]
+        achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+        traffic = traffic_from_profiles(name, src)
+        rooflines[name] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                           "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),
+                           "algorithmic_bytes_per_launch": int(per_launch),
+                           "share_of_step": round(k["ms"] / (elapsed * 1e3), 3)}
+    dominant = max(kernels, key=lambda n: kernels[n]["ms"])
+    roof = dict(rooflines[dominant])
+    roof["kernel"] = dominant
+
+    out = {
+        "metric": "flights/s + time-to-steady (res<1e-6); batched vs sequential, same GPU",
+        "value": tot["flights"] / elapsed, "unit": "flights/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / K * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+int64",
+        "data": "synthetic",
+        "config": {"workload": "2D gray square cavity 256x256, hot top wall, Kn in {0.01,0.1,1,10}, "
+                               "1e7 particles/iteration, Newton (FP64 CG tol 1e-10), int64 "
+                               "fixed-point tallies, face tallies every iteration; one step = one "
+                               "iteration of each Kn", "seed": 0, "parallelism": "single GPU"},
+        "per_kn": per_kn,
+        "roofline": roof,
+        "kernels": rooflines,
+        "source_hash": src,
+    }
+
+    if not args.no_tts:
+        tts = {}
+        for kn in KNS:
+            w = cavity_2d(n=N_SIDE, kn=kn, particles=PARTICLES, newton=True, seed=0)
+            s = P.Solver(w, device=dev, rng_mode=P.RNG_CRN, tally_faces=P.FACES_FINAL,
+                         max_iters=100, res_tol=1e-6)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            rc, T, qx, qy, st = s.solve()
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            tts[str(kn)] = {"seconds": round(b - a, 4), "iterations": st["iters"], "rc": rc,
+                            "final_res": st["res"], "cg_iters_total": st["cg_iters_total"]}
+            s.close()
+        out["time_to_steady"] = tts
+
+    if args.batch:
+        from synth import batch_workloads
+        ws = batch_workloads(count=args.batch)
+        kw = dict(rng_mode=P.RNG_CRN, tally_faces=P.FACES_FINAL, max_iters=60, res_tol=1e-6)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for w in ws:
+            s = P.Solver(w, device=dev, **kw)
+            s.solve()
+            s.close()
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - a
+        bs = P.BatchSolver(ws, device=dev, **kw)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        bs.solve()
+        torch.cuda.synchronize()
+        bat = time.perf_counter() - a
+        out["batched"] = {"instances": len(ws), "sequential_s": round(seq, 3),
+                          "batched_s": round(bat, 3), "speedup": round(seq / bat, 3)}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

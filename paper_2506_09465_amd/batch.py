@@ -1,0 +1,65 @@
+"""Batched solves of many independent problems through iugkp_batch_*."""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+from .solver import _Marshal, _defaults, _stream_handle
+
+
+class BatchSolver:
+    """Solve a list of problems together; outputs per instance as Solver.solve()."""
+
+    def __init__(self, workloads, device="cuda", **kw):
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("the IUGKP library needs a ROCm GPU (torch.cuda) device")
+        self.ws = list(workloads)
+        self._m = []
+        for w in self.ws:
+            opts = _defaults(w, dict(kw))
+            self._m.append(_Marshal(w, self.device, **opts))
+        n = len(self.ws)
+        probs = (C.c_void_p * n)(*[C.addressof(m.problem) for m in self._m])
+        opts = (C.c_void_p * n)(*[C.addressof(m.options) for m in self._m])
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().iugkp_batch_create(probs, opts, n,
+                                               C.c_void_p(_stream_handle(self.device)),
+                                               C.byref(h)), "iugkp_batch_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().iugkp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self):
+        n = len(self.ws)
+        Ts, qxs, qys = [], [], []
+        for w in self.ws:
+            nfx = w.ny * (w.nx + 1)
+            nfy = (w.ny + 1) * w.nx if w.dim == 2 else 0
+            Ts.append(torch.empty(w.nx * w.ny, dtype=torch.float64, device=self.device))
+            qxs.append(torch.empty(nfx, dtype=torch.float64, device=self.device))
+            qys.append(torch.empty(max(nfy, 1), dtype=torch.float64, device=self.device))
+        pT = (C.c_void_p * n)(*[t.data_ptr() for t in Ts])
+        px = (C.c_void_p * n)(*[t.data_ptr() for t in qxs])
+        py = (C.c_void_p * n)(*[t.data_ptr() for t in qys])
+        st = (L.Stats * n)()
+        with torch.cuda.device(self.device):
+            rc = L.lib().iugkp_batch_solve(self.h, pT, px, py, st)
+        L.check(rc, "iugkp_batch_solve", allow_warning=True)
+        out = []
+        for i, w in enumerate(self.ws):
+            nfy = (w.ny + 1) * w.nx if w.dim == 2 else 0
+            out.append((Ts[i], qxs[i], qys[i][:nfy], st[i].as_dict()))
+        return rc, out

@@ -35,6 +35,13 @@ int fail(int code, const std::string &msg)
       return fail(IUGKP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));   \
   } while (0)
 
+constexpr int kCgGridMax = 64;
+constexpr int kTileX = 8, kTileY = 8;        // emitter tile of one workgroup (cells)
+constexpr int kWallSeg = 8;                  // wall faces per workgroup
+constexpr int kWindowHalo = 12;              // window margin around a tile (cells)
+constexpr size_t kLdsWordsMax = 6144;        // 48 KB of 64-bit tallies per workgroup
+constexpr int kLdsWallsMax = 1024;
+
 inline int cdiv(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
 
 template <class T>
@@ -67,9 +74,14 @@ struct iugkp_handle {
   double *cg_x = nullptr, *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *cg_Ap = nullptr;
   double *part = nullptr, *part_a = nullptr, *part_b = nullptr;
   unsigned long long *gpart = nullptr;
+  unsigned int *cg_barrier = nullptr;
   long long *G = nullptr, *base = nullptr;
   uint32_t *rem = nullptr;
   long long *D = nullptr, *W = nullptr, *Phix = nullptr, *Phiy = nullptr, *B = nullptr;
+  long long *dB = nullptr;
+  iugkp::TileDesc *tiles = nullptr;
+  int n_tiles = 0, WX = 1, WY = 1, lds_walls = 0;
+  size_t lds_bytes = 0;
   double *acc_E = nullptr, *acc_x = nullptr, *acc_y = nullptr;
   double *out_T = nullptr, *out_qx = nullptr, *out_qy = nullptr;
   DevScalars *dsc = nullptr;
@@ -155,8 +167,8 @@ void free_handle(iugkp_handle *h)
   if (!h) return;
   void *bufs[] = {h->tau, h->ratio, h->E, h->E_half, h->rhs, h->Dx, h->Dy, h->gx, h->gy,
                   h->diag, h->cg_x, h->cg_r, h->cg_p0, h->cg_p1, h->cg_Ap, h->part, h->part_a,
-                  h->part_b, h->gpart, h->G, h->base, h->rem, h->D, h->W, h->Phix, h->Phiy,
-                  h->B, h->acc_E, h->acc_x, h->acc_y, h->out_T, h->out_qx, h->out_qy, h->dsc};
+                  h->part_b, h->gpart, h->cg_barrier, h->G, h->base, h->rem, h->D, h->W, h->Phix, h->Phiy,
+                  h->B, h->dB, h->tiles, h->acc_E, h->acc_x, h->acc_y, h->out_T, h->out_qx, h->out_qy, h->dsc};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (h->hsc) (void)hipHostFree(h->hsc);
@@ -174,24 +186,106 @@ int launch_march(iugkp_handle *h, uint32_t slot, int faces)
   a.slot = slot;
   a.key0 = static_cast<uint32_t>(h->opt.seed);
   a.key1 = static_cast<uint32_t>(h->opt.seed >> 32);
-  a.n_particles = h->n_particles;
   a.faces = faces;
   a.has_null = h->has_null;
+  a.WX = h->WX;
+  a.WY = h->WY;
+  a.lds_walls = h->lds_walls;
+  a.tiles = h->tiles;
   a.base = h->base;
   a.rem = h->rem;
   a.ratio = h->ratio;
-  a.t = iugkp::Tallies{h->D, h->W, h->Phix, h->Phiy, h->B};
+  a.D = h->D;
+  a.W = h->W;
+  a.Phiy = h->Phiy;
+  a.dB = h->dB;
+  a.B = h->B;
   a.sc = h->dsc;
-  const int grid = cdiv(h->n_particles, h->block);
+  const int grid = h->n_tiles;
+  const size_t sh = h->lds_bytes;
+  HIP_TRY(hipEventRecord(h->ev[0], h->stream));
   switch (h->block) {
-    case 64: iugkp::march_kernel<64><<<grid, 64, 0, h->stream>>>(a); break;
-    case 128: iugkp::march_kernel<128><<<grid, 128, 0, h->stream>>>(a); break;
-    case 512: iugkp::march_kernel<512><<<grid, 512, 0, h->stream>>>(a); break;
-    case 1024: iugkp::march_kernel<1024><<<grid, 1024, 0, h->stream>>>(a); break;
-    default: iugkp::march_kernel<256><<<grid, 256, 0, h->stream>>>(a); break;
+    case 64: iugkp::march_kernel<64><<<grid, 64, sh, h->stream>>>(a); break;
+    case 128: iugkp::march_kernel<128><<<grid, 128, sh, h->stream>>>(a); break;
+    case 512: iugkp::march_kernel<512><<<grid, 512, sh, h->stream>>>(a); break;
+    case 1024: iugkp::march_kernel<1024><<<grid, 1024, sh, h->stream>>>(a); break;
+    default: iugkp::march_kernel<256><<<grid, 256, sh, h->stream>>>(a); break;
   }
   HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(h->ev[1], h->stream));
+  if (faces) {
+    if (h->m.dim == 2)
+      iugkp::reconstruct_y_kernel<<<cdiv(h->m.nx, 256), 256, 0, h->stream>>>(h->m, h->dB, h->Phiy);
+    iugkp::reconstruct_x_kernel<<<cdiv(h->m.ny, 256), 256, 0, h->stream>>>(h->m, h->G, h->D, h->Phiy,
+                                                                         h->B, h->Phix);
+    HIP_TRY(hipGetLastError());
+  }
   return IUGKP_OK;
+}
+
+// Tile table and LDS window: the whole domain when its tallies fit in LDS,
+// otherwise a window of the tile plus a margin, placed inside the domain.
+void plan_tiles(iugkp_handle *h, std::vector<iugkp::TileDesc> &tiles)
+{
+  const Mesh &m = h->m;
+  h->lds_walls = (m.n_b <= kLdsWallsMax) ? 1 : 0;
+  const size_t whole = iugkp::window_words(m.nx, m.ny, h->has_null, h->lds_walls, m.n_b);
+  bool whole_domain = whole <= kLdsWordsMax;
+  if (whole_domain) {
+    h->WX = m.nx;
+    h->WY = m.ny;
+  } else {
+    h->WX = std::min(m.nx, kTileX + 2 * kWindowHalo);
+    h->WY = std::min(m.ny, kTileY + 2 * kWindowHalo);
+  }
+  auto place = [](int lo, int extent, int W, int n) {
+    // window of size W covering [lo, lo + extent) as centrally as the domain allows
+    int w0 = lo - (W - extent) / 2;
+    if (w0 > n - W) w0 = n - W;
+    if (w0 < 0) w0 = 0;
+    return w0;
+  };
+  for (int ty = 0; ty < m.ny; ty += kTileY)
+    for (int tx = 0; tx < m.nx; tx += kTileX) {
+      iugkp::TileDesc t{};
+      t.kind = 0;
+      t.x0 = tx;
+      t.y0 = ty;
+      t.ex = std::min(kTileX, m.nx - tx);
+      t.ey = std::min(kTileY, m.ny - ty);
+      t.wx0 = whole_domain ? 0 : place(tx, t.ex, h->WX, m.nx);
+      t.wy0 = whole_domain ? 0 : place(ty, t.ey, h->WY, m.ny);
+      tiles.push_back(t);
+    }
+  // wall segments: left rows, right rows, bottom columns, top columns
+  auto wall = [&](int b_first, int count, int along_x, int side_hi) {
+    for (int s0 = 0; s0 < count; s0 += kWallSeg) {
+      iugkp::TileDesc t{};
+      t.kind = 1;
+      t.x0 = b_first + s0;
+      t.ex = std::min(kWallSeg, count - s0);
+      t.ey = 1;
+      if (whole_domain) {
+        t.wx0 = 0;
+        t.wy0 = 0;
+      } else if (along_x) {   // bottom / top wall: segment along x
+        t.wx0 = place(s0, t.ex, h->WX, m.nx);
+        t.wy0 = side_hi ? m.ny - h->WY : 0;
+      } else {                // left / right wall: segment along y
+        t.wy0 = place(s0, t.ex, h->WY, m.ny);
+        t.wx0 = side_hi ? m.nx - h->WX : 0;
+      }
+      tiles.push_back(t);
+    }
+  };
+  wall(0, m.ny, 0, 0);
+  wall(m.ny, m.ny, 0, 1);
+  if (m.dim == 2) {
+    wall(2 * m.ny, m.nx, 1, 0);
+    wall(2 * m.ny + m.nx, m.nx, 1, 1);
+  }
+  h->n_tiles = static_cast<int>(tiles.size());
+  h->lds_bytes = iugkp::window_words(h->WX, h->WY, h->has_null, h->lds_walls, m.n_b) * sizeof(long long);
 }
 
 // One iteration on the handle's stream; leaves the new scalars in h->hsc.
@@ -199,15 +293,14 @@ int iterate(iugkp_handle *h, int faces)
 {
   const Mesh &m = h->m;
   const uint32_t slot = (h->opt.rng_mode == IUGKP_RNG_CRN) ? h->opt.rng_epoch : h->iter;
-  const int nprep = std::max(std::max(m.n_emit, m.n_fx), std::max(m.n_fy, m.n_cells));
+  const int nprep = std::max(std::max(std::max(m.n_emit, m.n_fx), std::max(m.n_fy, m.n_cells)),
+                             (m.ny + 2) * m.nx);
   iugkp::Tallies t{h->D, h->W, h->Phix, h->Phiy, h->B};
-  HIP_TRY(hipEventRecord(h->ev[0], h->stream));
   iugkp::prepare_kernel<<<cdiv(nprep, 256), 256, 0, h->stream>>>(m, h->G, h->N, h->base, h->rem,
-                                                                  t, faces, h->dsc);
+                                                                  t, h->dB, faces, h->dsc);
   HIP_TRY(hipGetLastError());
-  int rc = launch_march(h, slot, faces);
+  int rc = launch_march(h, slot, faces);   // records ev[0] / ev[1] around the march kernel
   if (rc) return rc;
-  HIP_TRY(hipEventRecord(h->ev[1], h->stream));
   const int nbc = cdiv(m.n_cells, iugkp::kTree);
   iugkp::UpdateArgs ua{m.n_cells, h->F, h->has_null, h->opt.newton, h->V, h->D, h->W,
                        h->E, h->E_half, h->rhs, h->G, h->part, h->dsc};
@@ -215,7 +308,6 @@ int iterate(iugkp_handle *h, int faces)
   HIP_TRY(hipGetLastError());
   const int first = (h->iter == 0);
   if (h->opt.newton) {
-    HIP_TRY(hipEventRecord(h->ev[2], h->stream));
     iugkp::CGArgs ca;
     ca.m = m;
     ca.gx = h->gx;
@@ -231,10 +323,16 @@ int iterate(iugkp_handle *h, int faces)
     ca.part_b = h->part_b;
     ca.tol2 = h->opt.cg_tol * h->opt.cg_tol;
     ca.max_iters = h->opt.cg_max_iters;
+    ca.barrier = h->cg_barrier;
     ca.sc = h->dsc;
+    iugkp::zero_u32_kernel<<<1, 64, 0, h->stream>>>(h->cg_barrier, 2);
+    HIP_TRY(hipEventRecord(h->ev[2], h->stream));
+    // every workgroup must be resident for the grid barrier: the cooperative
+    // launch refuses a grid that does not fit instead of letting it hang
     void *args[] = {&ca};
     HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<void *>(iugkp::cg_kernel),
-                                       dim3(h->cg_grid), dim3(256), args, 0, h->stream));
+                                       dim3(h->cg_grid), dim3(iugkp::kCgThreads), args, 0,
+                                       h->stream));
     HIP_TRY(hipEventRecord(h->ev[3], h->stream));
     const int nbe = cdiv(m.n_emit, iugkp::kTree);
     iugkp::NewtonFinishArgs na{m.n_cells, m.n_emit, h->F, h->V, h->E_half, h->cg_x,
@@ -273,6 +371,8 @@ int iterate(iugkp_handle *h, int faces)
   h->last_faces = faces != 0;
   h->st.iters = static_cast<int>(h->iter);
   h->st.res = h->res;
+  if (h->opt.newton && s.cg_status == -3)
+    return fail(IUGKP_E_DEVICE, "CG grid barrier timed out");
   if (h->opt.newton && s.cg_status == -6) return fail(IUGKP_E_CG_BREAKDOWN, "CG breakdown");
   if (h->opt.newton && s.cg_status == -7)
     return fail(IUGKP_E_CG_NOT_CONVERGED, "CG did not converge within cg_max_iters");
@@ -412,6 +512,7 @@ int create_impl(const iugkp_problem *p, const iugkp_options *o, void *stream, iu
   ALLOC(h->Phix, m.n_fx);
   ALLOC(h->Phiy, m.n_fy);
   ALLOC(h->B, nb);
+  ALLOC(h->dB, (p->ny + 2) * p->nx);
   ALLOC(h->acc_E, nc);
   ALLOC(h->acc_x, m.n_fx);
   ALLOC(h->acc_y, m.n_fy);
@@ -438,10 +539,19 @@ int create_impl(const iugkp_problem *p, const iugkp_options *o, void *stream, iu
     ALLOC(h->part_a, cdiv(nc, iugkp::kTree));
     ALLOC(h->part_b, cdiv(nc, iugkp::kTree));
     ALLOC(h->gpart, nbe);
+    ALLOC(h->cg_barrier, 2);
   }
 #undef ALLOC
   hipStream_t s = h->stream;
   if (copy_in(h->tau, tau.data(), nc * sizeof(double), IUGKP_MEM_HOST, s)) return bail(IUGKP_E_DEVICE);
+  {
+    std::vector<iugkp::TileDesc> tiles;
+    plan_tiles(h, tiles);
+    if (dalloc(&h->tiles, tiles.size()) != hipSuccess) return bail(fail(IUGKP_E_NOMEM, "hipMalloc failed"));
+    if (copy_in(h->tiles, tiles.data(), tiles.size() * sizeof(iugkp::TileDesc), IUGKP_MEM_HOST, s))
+      return bail(IUGKP_E_DEVICE);
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   double *dT0 = nullptr;
   if (!T0.empty()) {
     if (dalloc(&dT0, nc) != hipSuccess) return bail(fail(IUGKP_E_NOMEM, "hipMalloc failed"));
@@ -512,9 +622,11 @@ int create_impl(const iugkp_problem *p, const iugkp_options *o, void *stream, iu
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(iugkp::cg_kernel), 256, 0));
-    const int nbt = cdiv(nc, iugkp::kTree);
-    h->cg_grid = std::max(1, std::min(nbt, std::max(1, per_cu) * n_cu));
+        &per_cu, reinterpret_cast<const void *>(iugkp::cg_kernel), iugkp::kCgThreads, 0));
+    // a small grid keeps the barrier cheap (its cost grows with the number of
+    // arriving workgroups); at most one workgroup per CU
+    const int nwg = cdiv(nc, iugkp::kCgThreads);
+    h->cg_grid = std::max(1, std::min(std::min(nwg, kCgGridMax), std::max(1, per_cu) * n_cu));
   }
   std::vector<long long> g(ne);
   int hflag = 0;

@@ -14,7 +14,6 @@
 // (v[i] += v[i + s], s = 128 ... 1); the block sums are reduced the same way.
 // Integer tallies use 64-bit atomics: exact, so any order gives the same bits.
 #pragma once
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -47,58 +46,70 @@ struct DevScalars {
 };
 
 // ---------------------------------------------------------------------------
-// fixed-order block tree in LDS; every thread of a 256-wide block participates
+// Fixed-order tree over 256 values held by 256 consecutive threads (one
+// "slice"; a workgroup may hold several slices).  Levels s = 128 and 64 go
+// through LDS, the last six (s = 32 .. 1) inside the first wavefront of the
+// slice with shuffles; every level adds v[i] + v[i + s], exactly the pairs and
+// the operand order of the reference tree.  Returns the sum in the slice's
+// thread 0 (other threads: unspecified).  All threads of the workgroup call it.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double block_tree256(double v, double *lds)
+__device__ __forceinline__ double slice_tree256(double v, double *lds)
 {
-  const int t = threadIdx.x;
-  lds[t] = v;
+  const int t = threadIdx.x & (kTree - 1);
+  double *sl = lds + (threadIdx.x - t);
+  sl[t] = v;
   __syncthreads();
+  if (t < 128) sl[t] = sl[t] + sl[t + 128];
+  __syncthreads();
+  double r = 0.0;
+  if (t < 64) {
+    r = sl[t] + sl[t + 64];
 #pragma unroll
-  for (int s = kTree / 2; s >= 1; s >>= 1) {
-    if (t < s) lds[t] = lds[t] + lds[t + s];
-    __syncthreads();
+    for (int s = 32; s >= 1; s >>= 1) r = r + __shfl_down(r, s, 64);
   }
-  const double r = lds[0];
   __syncthreads();
   return r;
 }
 
+// Whole-workgroup version for 256-wide workgroups: result broadcast to all threads.
+__device__ __forceinline__ double block_tree256(double v, double *lds)
+{
+  const double r = slice_tree256(v, lds);
+  if (threadIdx.x == 0) lds[0] = r;
+  __syncthreads();
+  const double out = lds[0];
+  __syncthreads();
+  return out;
+}
+
 // Reduce n (<= 65536) block sums with the same tree (two levels at most);
-// blockDim.x >= 256, all threads call it, all get the result.
+// blockDim.x >= 256, all threads call it, all get the result.  lds needs
+// blockDim.x doubles, lds2 256.
 __device__ double tree_all(const double *part, int n, double *lds, double *lds2)
 {
-  const int t = threadIdx.x;
   const int nb = (n + kTree - 1) / kTree;
-  for (int b = 0; b < nb; ++b) {
-    double v = 0.0;
-    if (t < kTree) {
-      const int i = b * kTree + t;
-      v = (i < n) ? part[i] : 0.0;
-      lds[t] = v;
-    }
-    __syncthreads();
-    for (int s = kTree / 2; s >= 1; s >>= 1) {
-      if (t < s) lds[t] = lds[t] + lds[t + s];
-      __syncthreads();
-    }
-    if (t == 0) lds2[b] = lds[0];
-    __syncthreads();
+  const int slices = blockDim.x / kTree;
+  const int sl = threadIdx.x / kTree, t = threadIdx.x & (kTree - 1);
+  for (int b0 = 0; b0 < nb; b0 += slices) {
+    const int b = b0 + sl;
+    const int i = b * kTree + t;
+    const double v = (b < nb && i < n) ? part[i] : 0.0;
+    const double r = slice_tree256(v, lds);
+    if (t == 0 && b < nb) lds2[b] = r;
   }
+  __syncthreads();
+  double out;
   if (nb == 1) {
-    const double r = lds2[0];
+    out = lds2[0];
+  } else {
+    const double v = (threadIdx.x < nb) ? lds2[threadIdx.x] : 0.0;
+    const double r = slice_tree256(threadIdx.x < kTree ? v : 0.0, lds);
+    if (threadIdx.x == 0) lds2[0] = r;
     __syncthreads();
-    return r;
+    out = lds2[0];
   }
-  if (t < kTree) lds[t] = (t < nb) ? lds2[t] : 0.0;
   __syncthreads();
-  for (int s = kTree / 2; s >= 1; s >>= 1) {
-    if (t < s) lds[t] = lds[t] + lds[t + s];
-    __syncthreads();
-  }
-  const double r = lds[0];
-  __syncthreads();
-  return r;
+  return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -106,7 +117,7 @@ __device__ double tree_all(const double *part, int n, double *lds, double *lds2)
 // ---------------------------------------------------------------------------
 __global__ void prepare_kernel(Mesh m, const long long *__restrict__ G, uint32_t N,
                                long long *__restrict__ base, uint32_t *__restrict__ rem,
-                               Tallies t, int faces, DevScalars *sc)
+                               Tallies t, long long *__restrict__ dB, int faces, DevScalars *sc)
 {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
@@ -130,15 +141,8 @@ __global__ void prepare_kernel(Mesh m, const long long *__restrict__ G, uint32_t
     base[i] = b;
     rem[i] = static_cast<uint32_t>(g - b * n);
   }
-  if (i < m.n_fx) {
-    long long v = 0;
-    if (faces) {
-      const int row = i / (m.nx + 1), k = i - row * (m.nx + 1);
-      if (k == 0) v = G[m.n_cells + row];                 // left wall emits along +x
-      else if (k == m.nx) v = -G[m.n_cells + m.ny + row];  // right wall emits along -x
-    }
-    t.Phix[i] = v;
-  }
+  if (i < m.n_fx) t.Phix[i] = 0;   // rebuilt from the balance when faces are on
+  if (m.dim == 2 && i < (m.ny + 2) * m.nx) dB[i] = 0;
   if (i < m.n_fy) {
     long long v = 0;
     if (faces) {
@@ -151,25 +155,48 @@ __global__ void prepare_kernel(Mesh m, const long long *__restrict__ G, uint32_t
 }
 
 // ---------------------------------------------------------------------------
-// The particle step.  One lane per particle; particle p belongs to emitter
-// e = p mod n_emit (emitter index runs fastest, so a wavefront's lanes start in
-// 64 different cells and their first face tallies hit different addresses),
-// its index within the emitter is k = p / n_emit.
+// The particle step.
+//
+// Work decomposition: workgroup = one emitter tile (a TX x TY block of cells, or
+// a segment of one wall) and all N particles of its emitters; particle p of the
+// tile belongs to emitter p mod n_e (emitters run fastest, so the lanes of a
+// wavefront start in different cells) and has index k = p / n_e within it.
+// Each lane flies its particles one after the other, which evens out the
+// lanes' total work.
+//
+// Tallies: the workgroup keeps the cell tallies (D, W), the y-face tallies and
+// the column-run differences of a window of cells around its tile in LDS
+// (64-bit LDS atomics), and flushes the window with row-contiguous (coalesced)
+// global atomics at the end; events outside the window go to global atomics.
+// x-face tallies are not taken at all: they follow exactly from the per-cell
+// identity  net face inflow = D - G  (reconstruct_faces_kernel).  For steep
+// segments the y-faces crossed inside one column form a run [lo, hi]; it is
+// recorded as +q at lo and -q at hi + 1 of a per-column difference array,
+// two updates instead of one per face.
 // ---------------------------------------------------------------------------
+struct TileDesc {
+  int kind;        // 0 = cell tile, 1 = wall segment
+  int x0, y0;      // cell tile: first cell; wall segment: first wall index in x0
+  int ex, ey;      // cell tile: extent; wall segment: face count in ex
+  int wx0, wy0;    // window origin (cells)
+};
+
 struct MarchArgs {
   Mesh m;
   double lam_min;
   uint32_t N, slot, key0, key1;
-  uint32_t n_particles;
   int faces, has_null;
+  int WX, WY;            // window size (cells)
+  int lds_walls;         // wall-absorption tally kept in LDS (n_b small enough)
+  const TileDesc *tiles;
   const long long *base;
   const uint32_t *rem;
   const double *ratio;
-  Tallies t;
+  long long *D, *W, *Phiy, *dB, *B;   // dB: [(ny + 2) * nx] column-run differences
   DevScalars *sc;
 };
 
-__device__ __forceinline__ void tally_add(long long *a, long long v)
+__device__ __forceinline__ void atom_add(long long *a, long long v)
 {
   atomicAdd(reinterpret_cast<unsigned long long *>(a), static_cast<unsigned long long>(v));
 }
@@ -179,119 +206,205 @@ __device__ __forceinline__ double clamp_to(double v, double lo, double hi)
   return (v < lo) ? lo : ((v > hi) ? hi : v);
 }
 
+struct Window {
+  long long *D, *W, *By, *dB, *B;   // LDS arrays
+  int wx0, wy0, WX, WY;
+};
+
+// LDS layout of one window: D [WY][WX], W [WY][WX] (null collisions only),
+// By [WY+1][WX], dB [WY+2][WX], B [n_b] (if kept in LDS).
+__host__ __device__ inline size_t window_words(int WX, int WY, int has_null, int lds_walls, int n_b)
+{
+  return static_cast<size_t>(WX) * WY * (has_null ? 2 : 1) + static_cast<size_t>(WX) * (WY + 1) +
+         static_cast<size_t>(WX) * (WY + 2) + (lds_walls ? n_b : 0);
+}
+
 template <int BS>
 __global__ __launch_bounds__(BS) void march_kernel(MarchArgs a)
 {
+  extern __shared__ long long lds_words[];
   __shared__ unsigned long long s_cnt[3];
+  const Mesh &m = a.m;
+  const TileDesc td = a.tiles[blockIdx.x];
+  Window win;
+  win.WX = a.WX;
+  win.WY = a.WY;
+  win.wx0 = td.wx0;
+  win.wy0 = td.wy0;
+  {
+    long long *p = lds_words;
+    win.D = p;
+    p += win.WX * win.WY;
+    win.W = a.has_null ? p : nullptr;
+    if (a.has_null) p += win.WX * win.WY;
+    win.By = p;
+    p += win.WX * (win.WY + 1);
+    win.dB = p;
+    p += win.WX * (win.WY + 2);
+    win.B = a.lds_walls ? p : nullptr;
+  }
+  const int nwords = static_cast<int>(window_words(win.WX, win.WY, a.has_null, a.lds_walls, m.n_b));
+  for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
   if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
   __syncthreads();
 
-  const Mesh &m = a.m;
-  const uint32_t p = blockIdx.x * BS + threadIdx.x;
+  auto add_cell = [&](long long *lds_arr, long long *glob, int ix, int iy, long long v) {
+    const unsigned lx = static_cast<unsigned>(ix - win.wx0), ly = static_cast<unsigned>(iy - win.wy0);
+    if (lx < static_cast<unsigned>(win.WX) && ly < static_cast<unsigned>(win.WY))
+      atomicAdd(reinterpret_cast<unsigned long long *>(&lds_arr[ly * win.WX + lx]),
+                static_cast<unsigned long long>(v));
+    else
+      atom_add(&glob[iy * m.nx + ix], v);
+  };
+  auto add_yface = [&](int ky, int ix, long long v) {
+    const unsigned lx = static_cast<unsigned>(ix - win.wx0), ly = static_cast<unsigned>(ky - win.wy0);
+    if (lx < static_cast<unsigned>(win.WX) && ly <= static_cast<unsigned>(win.WY))
+      atomicAdd(reinterpret_cast<unsigned long long *>(&win.By[ly * win.WX + lx]),
+                static_cast<unsigned long long>(v));
+    else
+      atom_add(&a.Phiy[ky * m.nx + ix], v);
+  };
+  auto add_diff = [&](int k, int ix, long long v) {
+    const unsigned lx = static_cast<unsigned>(ix - win.wx0), ly = static_cast<unsigned>(k - win.wy0);
+    if (lx < static_cast<unsigned>(win.WX) && ly <= static_cast<unsigned>(win.WY + 1))
+      atomicAdd(reinterpret_cast<unsigned long long *>(&win.dB[ly * win.WX + lx]),
+                static_cast<unsigned long long>(v));
+    else
+      atom_add(&a.dB[k * m.nx + ix], v);
+  };
+  auto add_wall = [&](int b, long long v) {
+    if (win.B)
+      atomicAdd(reinterpret_cast<unsigned long long *>(&win.B[b]), static_cast<unsigned long long>(v));
+    else
+      atom_add(&a.B[b], v);
+  };
+
+  const int n_e = (td.kind == 0) ? td.ex * td.ey : td.ex;
+  const uint32_t P = static_cast<uint32_t>(n_e) * a.N;
   unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
-  if (p < a.n_particles) {
-    const uint32_t e = p % static_cast<uint32_t>(m.n_emit);
-    const uint32_t k = p / static_cast<uint32_t>(m.n_emit);
+  for (uint32_t p = threadIdx.x; p < P; p += BS) {
+    const uint32_t ei = p % static_cast<uint32_t>(n_e);
+    const uint32_t k = p / static_cast<uint32_t>(n_e);
+    uint32_t e;
+    if (td.kind == 0) {
+      const int ty = static_cast<int>(ei) / td.ex;
+      e = static_cast<uint32_t>((td.y0 + ty) * m.nx + td.x0 + (static_cast<int>(ei) - ty * td.ex));
+    } else {
+      e = static_cast<uint32_t>(m.n_cells + td.x0) + ei;
+    }
     const long long q = a.base[e] + ((k < a.rem[e]) ? 1 : 0);
-    if (q != 0) {
-      n_fl = 1;
-      const double2 uab = draw2(0u, k, e, a.slot, a.key0, a.key1);
-      const double2 ucd = draw2(1u, k, e, a.slot, a.key0, a.key1);
-      int ix, iy;
-      double x0, y0, sx, sy;
-      if (e < static_cast<uint32_t>(m.n_cells)) {
-        // isotropic emission from a uniformly sampled point of the cell
-        iy = static_cast<int>(e) / m.nx;
-        ix = static_cast<int>(e) - iy * m.nx;
-        x0 = (static_cast<double>(ix) + uab.x) * m.dx;
-        y0 = (static_cast<double>(iy) + uab.y) * m.dy;
-        const double mu = 2.0 * ucd.x - 1.0;
-        sx = mu;
-        sy = (m.dim == 2) ? sqrt((1.0 - mu) * (1.0 + mu)) * cos2pi_own(ucd.y) : 0.0;
+    if (q == 0) continue;
+    ++n_fl;
+    const double2 uab = draw2(0u, k, e, a.slot, a.key0, a.key1);
+    const double2 ucd = draw2(1u, k, e, a.slot, a.key0, a.key1);
+    int ix, iy;
+    double x0, y0, sx, sy;
+    if (e < static_cast<uint32_t>(m.n_cells)) {
+      // isotropic emission from a uniformly sampled point of the cell
+      iy = static_cast<int>(e) / m.nx;
+      ix = static_cast<int>(e) - iy * m.nx;
+      x0 = (static_cast<double>(ix) + uab.x) * m.dx;
+      y0 = (static_cast<double>(iy) + uab.y) * m.dy;
+      const double mu = 2.0 * ucd.x - 1.0;
+      sx = mu;
+      sy = (m.dim == 2) ? sqrt((1.0 - mu) * (1.0 + mu)) * cos2pi_own(ucd.y) : 0.0;
+    } else {
+      // cosine-law emission from a black wall face into the domain
+      const int b = static_cast<int>(e) - m.n_cells;
+      const double cn = sqrt(ucd.x);
+      const double tg = (m.dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * cos2pi_own(ucd.y) : 0.0;
+      if (b < m.ny) {
+        ix = 0; iy = b;
+        x0 = 0.0; y0 = (static_cast<double>(iy) + uab.x) * m.dy;
+        sx = cn; sy = tg;
+      } else if (b < 2 * m.ny) {
+        ix = m.nx - 1; iy = b - m.ny;
+        x0 = static_cast<double>(m.nx) * m.dx; y0 = (static_cast<double>(iy) + uab.x) * m.dy;
+        sx = -cn; sy = tg;
+      } else if (b < 2 * m.ny + m.nx) {
+        ix = b - 2 * m.ny; iy = 0;
+        x0 = (static_cast<double>(ix) + uab.x) * m.dx; y0 = 0.0;
+        sx = tg; sy = cn;
       } else {
-        // cosine-law emission from a black wall face into the domain
-        const int b = static_cast<int>(e) - m.n_cells;
-        const double cn = sqrt(ucd.x);
-        const double tg = (m.dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * cos2pi_own(ucd.y) : 0.0;
-        if (b < m.ny) {
-          ix = 0; iy = b;
-          x0 = 0.0; y0 = (static_cast<double>(iy) + uab.x) * m.dy;
-          sx = cn; sy = tg;
-        } else if (b < 2 * m.ny) {
-          ix = m.nx - 1; iy = b - m.ny;
-          x0 = static_cast<double>(m.nx) * m.dx; y0 = (static_cast<double>(iy) + uab.x) * m.dy;
-          sx = -cn; sy = tg;
-        } else if (b < 2 * m.ny + m.nx) {
-          ix = b - 2 * m.ny; iy = 0;
-          x0 = (static_cast<double>(ix) + uab.x) * m.dx; y0 = 0.0;
-          sx = tg; sy = cn;
-        } else {
-          ix = b - 2 * m.ny - m.nx; iy = m.ny - 1;
-          x0 = (static_cast<double>(ix) + uab.x) * m.dx; y0 = static_cast<double>(m.ny) * m.dy;
-          sx = tg; sy = -cn;
-        }
+        ix = b - 2 * m.ny - m.nx; iy = m.ny - 1;
+        x0 = (static_cast<double>(ix) + uab.x) * m.dx; y0 = static_cast<double>(m.ny) * m.dy;
+        sx = tg; sy = -cn;
       }
-      const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
-      const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
-      const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
-      const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
-      const long long qx = (stx > 0) ? q : -q;
-      const long long qy = (sty > 0) ? q : -q;
-      for (uint32_t j = 0;; ++j) {
-        const double2 us = draw2(2u + j, k, e, a.slot, a.key0, a.key1);
-        // candidate free path on the common time scale tau_min: -|V_g| tau_min ln(eta)
-        const double ell = -(a.lam_min * log_own(1.0 - us.x));
-        ++n_seg;
-        int kx = (stx > 0) ? ix + 1 : ix;
-        int ky = (sty > 0) ? iy + 1 : iy;
-        int bface = -1;
-        for (;;) {
-          const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
-          const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
-          const bool along_x = tx <= ty;
-          const double tt = along_x ? tx : ty;
-          if (!(tt < ell)) break;
-          ++n_cross;
-          if (along_x) {
-            if (a.faces) tally_add(&a.t.Phix[iy * (m.nx + 1) + kx], qx);
-            if (kx == 0 || kx == m.nx) {
-              bface = (kx == 0) ? iy : m.ny + iy;
-              break;
-            }
-            ix += stx;
-            kx += stx;
-          } else {
-            if (a.faces) tally_add(&a.t.Phiy[ky * m.nx + ix], qy);
-            if (ky == 0 || ky == m.ny) {
-              bface = (ky == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
-              break;
-            }
-            iy += sty;
-            ky += sty;
+    }
+    const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+    const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+    const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+    const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+    const long long qy = (sty > 0) ? q : -q;
+    // steep segments record their y-faces as runs per column
+    const bool runs = a.faces && (fabs(sy) > 2.0 * fabs(sx));
+    for (uint32_t j = 0;; ++j) {
+      const double2 us = draw2(2u + j, k, e, a.slot, a.key0, a.key1);
+      // candidate free path on the common time scale tau_min: -|V_g| tau_min ln(eta)
+      const double ell = -(a.lam_min * log_own(1.0 - us.x));
+      ++n_seg;
+      int kx = (stx > 0) ? ix + 1 : ix;
+      int ky = (sty > 0) ? iy + 1 : iy;
+      int bface = -1;
+      int run_a = -1, run_b = -1;   // first and last y-face of the open run
+      for (;;) {
+        const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
+        const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
+        const bool along_x = tx <= ty;
+        const double tt = along_x ? tx : ty;
+        if (!(tt < ell)) break;
+        ++n_cross;
+        if (along_x) {
+          if (run_a >= 0) {
+            add_diff(min(run_a, run_b), ix, qy);
+            add_diff(max(run_a, run_b) + 1, ix, -qy);
+            run_a = -1;
           }
+          if (kx == 0 || kx == m.nx) {
+            bface = (kx == 0) ? iy : m.ny + iy;
+            break;
+          }
+          ix += stx;
+          kx += stx;
+        } else {
+          if (runs) {
+            if (run_a < 0) run_a = ky;
+            run_b = ky;
+          } else if (a.faces) {
+            add_yface(ky, ix, qy);
+          }
+          if (ky == 0 || ky == m.ny) {
+            bface = (ky == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
+            break;
+          }
+          iy += sty;
+          ky += sty;
         }
-        if (bface >= 0) {
-          tally_add(&a.t.B[bface], q);
-          break;
-        }
-        const int c = ix + m.nx * iy;
-        if (!a.has_null) {
-          tally_add(&a.t.D[c], q);   // every candidate is real: W == D
-          break;
-        }
-        tally_add(&a.t.W[c], q);
-        // accept with probability sigma / sigma_max = tau_min / tau_c
-        if (us.y < a.ratio[c] || j == kMaxSegments - 1) {
-          tally_add(&a.t.D[c], q);
-          break;
-        }
-        // null collision: keep the direction, restart from the stopping point
-        x0 = clamp_to(x0 + ell * sx, static_cast<double>(ix) * m.dx,
-                      static_cast<double>(ix + 1) * m.dx);
-        if (m.dim == 2)
-          y0 = clamp_to(y0 + ell * sy, static_cast<double>(iy) * m.dy,
-                        static_cast<double>(iy + 1) * m.dy);
       }
+      if (run_a >= 0) {
+        add_diff(min(run_a, run_b), ix, qy);
+        add_diff(max(run_a, run_b) + 1, ix, -qy);
+      }
+      if (bface >= 0) {
+        add_wall(bface, q);
+        break;
+      }
+      if (!a.has_null) {
+        add_cell(win.D, a.D, ix, iy, q);   // every candidate is real: W == D
+        break;
+      }
+      add_cell(win.W, a.W, ix, iy, q);
+      // accept with probability sigma / sigma_max = tau_min / tau_c
+      const int c = ix + m.nx * iy;
+      if (us.y < a.ratio[c] || j == kMaxSegments - 1) {
+        add_cell(win.D, a.D, ix, iy, q);
+        break;
+      }
+      // null collision: keep the direction, restart from the stopping point
+      x0 = clamp_to(x0 + ell * sx, static_cast<double>(ix) * m.dx, static_cast<double>(ix + 1) * m.dx);
+      if (m.dim == 2)
+        y0 = clamp_to(y0 + ell * sy, static_cast<double>(iy) * m.dy,
+                      static_cast<double>(iy + 1) * m.dy);
     }
   }
   if (n_fl) {
@@ -300,10 +413,66 @@ __global__ __launch_bounds__(BS) void march_kernel(MarchArgs a)
     atomicAdd(&s_cnt[2], n_cross);
   }
   __syncthreads();
+  // flush the window: row-contiguous, so neighbouring lanes update one cache line
+  auto flush = [&](const long long *src, long long *dst, int rows, int row0, int nrows_glob) {
+    for (int i = threadIdx.x; i < rows * win.WX; i += BS) {
+      const long long v = src[i];
+      if (v == 0) continue;
+      const int ly = i / win.WX, lx = i - ly * win.WX;
+      const int gx = win.wx0 + lx, gy = row0 + ly;
+      if (gx >= 0 && gx < m.nx && gy >= 0 && gy < nrows_glob) atom_add(&dst[gy * m.nx + gx], v);
+    }
+  };
+  flush(win.D, a.D, win.WY, win.wy0, m.ny);
+  if (a.has_null) flush(win.W, a.W, win.WY, win.wy0, m.ny);
+  if (a.faces && m.dim == 2) {
+    flush(win.By, a.Phiy, win.WY + 1, win.wy0, m.ny + 1);
+    flush(win.dB, a.dB, win.WY + 2, win.wy0, m.ny + 2);
+  }
+  if (win.B)
+    for (int b = threadIdx.x; b < m.n_b; b += BS)
+      if (win.B[b]) atom_add(&a.B[b], win.B[b]);
   if (threadIdx.x == 0 && s_cnt[0]) {
     atomicAdd(&a.sc->flights, s_cnt[0]);
     atomicAdd(&a.sc->segments, s_cnt[1]);
     atomicAdd(&a.sc->crossings, s_cnt[2]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Face fluxes from the tallies (faces on).  Column prefix of the run
+// differences completes the y-face tallies; the x-face tallies follow row by
+// row from the per-cell balance (net inflow = D - G):
+//   Phix[j][0]   = G_left[j] - B_left[j]
+//   Phix[j][i+1] = Phix[j][i] + Phiy[j][i] - Phiy[j+1][i] - D[c] + G[c]
+// Integer arithmetic modulo 2^64: exact, since every true value fits in int64.
+// ---------------------------------------------------------------------------
+__global__ void reconstruct_y_kernel(Mesh m, const long long *dB, long long *Phiy)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m.nx) return;
+  unsigned long long acc = 0;
+  for (int k = 0; k <= m.ny; ++k) {
+    acc += static_cast<unsigned long long>(dB[k * m.nx + i]);
+    Phiy[k * m.nx + i] = static_cast<long long>(static_cast<unsigned long long>(Phiy[k * m.nx + i]) + acc);
+  }
+}
+
+__global__ void reconstruct_x_kernel(Mesh m, const long long *G, const long long *D,
+                                     const long long *Phiy, const long long *B, long long *Phix)
+{
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m.ny) return;
+  unsigned long long a = static_cast<unsigned long long>(G[m.n_cells + j]) -
+                         static_cast<unsigned long long>(B[j]);
+  Phix[j * (m.nx + 1)] = static_cast<long long>(a);
+  for (int i = 0; i < m.nx; ++i) {
+    const int c = j * m.nx + i;
+    if (m.dim == 2)
+      a += static_cast<unsigned long long>(Phiy[j * m.nx + i]) -
+           static_cast<unsigned long long>(Phiy[(j + 1) * m.nx + i]);
+    a += static_cast<unsigned long long>(G[c]) - static_cast<unsigned long long>(D[c]);
+    Phix[j * (m.nx + 1) + i + 1] = static_cast<long long>(a);
   }
 }
 
@@ -511,12 +680,54 @@ __global__ void newton_diag_kernel(Mesh m, const double *gx, const double *gy, d
 }
 
 // ---------------------------------------------------------------------------
+// Grid barrier for a persistent kernel whose workgroups are all resident (the
+// grid is sized from the occupancy query, at most one workgroup per CU).  A
+// monotone arrival counter at agent scope: barrier number k completes when the
+// counter reaches k * gridDim.x.  The release fence before arriving and the
+// acquire fence after leaving make the partial sums written before the barrier
+// visible to every workgroup, whichever XCD it runs on.
+// ---------------------------------------------------------------------------
+// counter[0] = arrivals, counter[1] = abort flag.  A wait longer than ~1 s sets
+// the abort flag; every workgroup then leaves its next barrier at once and the
+// kernel reports the failure, so a broken barrier can never hang the device.
+constexpr long kBarrierSpinLimit = 1l << 24;
+
+__device__ __forceinline__ bool grid_barrier(unsigned int *counter, unsigned int &epoch)
+{
+  __shared__ int s_abort;
+  __syncthreads();
+  epoch += 1;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int target = epoch * gridDim.x;
+    long spins = 0;
+    int abort = __hip_atomic_load(counter + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (!abort &&
+           __hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kBarrierSpinLimit) {
+        __hip_atomic_store(counter + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        abort = 1;
+      } else if ((spins & 1023) == 0) {
+        abort = __hip_atomic_load(counter + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __threadfence();
+    s_abort = abort;
+  }
+  __syncthreads();
+  return s_abort == 0;
+}
+
+// ---------------------------------------------------------------------------
 // Conjugate gradients (Hestenes-Stiefel, x0 = 0, stop at r.r <= tol^2 b.b) as
-// one persistent cooperative kernel.  Workgroup j owns the 256-cell tree
-// blocks j, j + grid, ...  Two grid barriers per iteration: the search
-// direction p = r + beta p_old is formed on the fly inside the operator
-// application (also for the neighbours, from r and p_old which no one writes
-// in that phase), with p double-buffered.
+// one persistent kernel.  Workgroup j owns the 256-cell tree blocks j, j + grid,
+// ...  Two grid barriers per iteration: the search direction
+// p = r + beta p_old is formed on the fly inside the operator application (also
+// for the neighbours, from r and p_old which no one writes in that phase), with
+// p double-buffered.  Every workgroup reduces all block partials itself in the
+// fixed order, so all take identical decisions.
 // ---------------------------------------------------------------------------
 struct CGArgs {
   Mesh m;
@@ -525,6 +736,7 @@ struct CGArgs {
   double *part_a, *part_b;
   double tol2;
   int max_iters;
+  unsigned int *barrier;     // [2], zeroed before the launch
   DevScalars *sc;
 };
 
@@ -534,30 +746,37 @@ __device__ __forceinline__ double cg_dir(const double *r, const double *pold, do
   return first ? r[c] : r[c] + beta * pold[c];
 }
 
-__global__ __launch_bounds__(256) void cg_kernel(CGArgs a)
+constexpr int kCgThreads = 1024;
+
+__global__ __launch_bounds__(kCgThreads) void cg_kernel(CGArgs a)
 {
-  namespace cgs = cooperative_groups;
-  cgs::grid_group grid = cgs::this_grid();
-  __shared__ double lds[kTree];
+  __shared__ double lds[kCgThreads];
   __shared__ double lds2[kTree];
+  unsigned int epoch = 0;
   const Mesh &m = a.m;
   const int n = m.n_cells;
   const int nb = (n + kTree - 1) / kTree;
-  const int t = threadIdx.x;
-  for (int tb = blockIdx.x; tb < nb; tb += gridDim.x) {
+  const int slices = kCgThreads / kTree;
+  const int sl = threadIdx.x / kTree, t = threadIdx.x & (kTree - 1);
+  // pass g covers tree blocks (g * gridDim.x + blockIdx.x) * slices + sl
+  const int npass = (nb + gridDim.x * slices - 1) / (gridDim.x * slices);
+  for (int g = 0; g < npass; ++g) {
+    const int tb = (g * gridDim.x + blockIdx.x) * slices + sl;
     const int c = tb * kTree + t;
     double v = 0.0;
-    if (c < n) {
+    if (tb < nb && c < n) {
       const double bc = a.b[c];
       a.x[c] = 0.0;
       a.r[c] = bc;
       v = bc * bc;
     }
-    v = block_tree256(v, lds);
-    if (t == 0) a.part_b[tb] = v;
+    v = slice_tree256(v, lds);
+    if (t == 0 && tb < nb) a.part_b[tb] = v;
   }
-  __threadfence();
-  grid.sync();
+  if (!grid_barrier(a.barrier, epoch)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.sc->cg_status = -3;
+    return;
+  }
   double rr = tree_all(a.part_b, nb, lds, lds2);
   const double thr = a.tol2 * rr;
   int status = -7;     // not converged unless proven otherwise
@@ -567,10 +786,11 @@ __global__ __launch_bounds__(256) void cg_kernel(CGArgs a)
   if (rr == 0.0) status = 0;
   while (status == -7 && it < a.max_iters) {
     const int first = (it == 0);
-    for (int tb = blockIdx.x; tb < nb; tb += gridDim.x) {
+    for (int g = 0; g < npass; ++g) {
+      const int tb = (g * gridDim.x + blockIdx.x) * slices + sl;
       const int c = tb * kTree + t;
       double v = 0.0;
-      if (c < n) {
+      if (tb < nb && c < n) {
         const int iy = c / m.nx, ix = c - iy * m.nx;
         const double pc = cg_dir(a.r, pold, beta, first, c);
         double acc = a.diag[c] * pc;
@@ -586,31 +806,36 @@ __global__ __launch_bounds__(256) void cg_kernel(CGArgs a)
         a.Ap[c] = acc;
         v = pc * acc;
       }
-      v = block_tree256(v, lds);
-      if (t == 0) a.part_a[tb] = v;
+      v = slice_tree256(v, lds);
+      if (t == 0 && tb < nb) a.part_a[tb] = v;
     }
-    __threadfence();
-    grid.sync();
+    if (!grid_barrier(a.barrier, epoch)) {
+      status = -3;
+      break;
+    }
     const double pAp = tree_all(a.part_a, nb, lds, lds2);
     if (!(pAp > 0.0)) {
       status = -6;
       break;
     }
     const double alpha = rr / pAp;
-    for (int tb = blockIdx.x; tb < nb; tb += gridDim.x) {
+    for (int g = 0; g < npass; ++g) {
+      const int tb = (g * gridDim.x + blockIdx.x) * slices + sl;
       const int c = tb * kTree + t;
       double v = 0.0;
-      if (c < n) {
+      if (tb < nb && c < n) {
         a.x[c] = a.x[c] + alpha * pnew[c];
         const double rc = a.r[c] - alpha * a.Ap[c];
         a.r[c] = rc;
         v = rc * rc;
       }
-      v = block_tree256(v, lds);
-      if (t == 0) a.part_b[tb] = v;
+      v = slice_tree256(v, lds);
+      if (t == 0 && tb < nb) a.part_b[tb] = v;
     }
-    __threadfence();
-    grid.sync();
+    if (!grid_barrier(a.barrier, epoch)) {
+      status = -3;
+      break;
+    }
     const double rr_new = tree_all(a.part_b, nb, lds, lds2);
     ++it;
     if (rr_new <= thr) {
@@ -623,10 +848,18 @@ __global__ __launch_bounds__(256) void cg_kernel(CGArgs a)
     pold = pnew;
     pnew = tmp;
   }
-  if (blockIdx.x == 0 && t == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.sc->cg_iters = it;
     a.sc->cg_status = status;
   }
+}
+
+// zero a small integer array (used instead of a memset node so the sequence can
+// be captured in a graph)
+__global__ void zero_u32_kernel(unsigned int *p, int n)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
