@@ -446,49 +446,71 @@ static double orc_dot(const double *a, const double *b, int n, double *tmp)
   return orc_tree_sum(tmp, (uint64_t)n);
 }
 
-/* Conjugate gradients (Hestenes-Stiefel), x0 = 0, stop when
- * r.r <= tol^2 (b.b). */
+/* Conjugate gradients in the single-reduction form of Chronopoulos and Gear
+ * (J. Comput. Appl. Math. 25, 1989): with w = A r and s = A p carried by
+ * recurrence, both inner products of an iteration, (r, r) and (w, r), come
+ * from the same vectors, so one global reduction per iteration suffices.
+ *   x = 0, r = b, w = A r, gamma = (r, r), delta = (w, r), alpha = gamma / delta
+ *   repeat: p = r + beta p, s = w + beta s (p = r, s = w the first time)
+ *           x = x + alpha p, r = r - alpha s, w = A r
+ *           gamma' = (r, r), delta = (w, r); stop if gamma' <= tol^2 (b, b)
+ *           beta = gamma' / gamma, alpha = gamma' / (delta - beta gamma' / alpha)
+ * In exact arithmetic the iterates are those of Hestenes-Stiefel CG. */
 int orc_cg(const orc_problem *p, const double *gx, const double *gy, const double *diag,
            const double *b, double *x, double tol, int max_iters, int *iters_out)
 {
   int n = p->nx * p->ny;
   double *r = (double *)malloc(sizeof(double) * n);
+  double *w = (double *)malloc(sizeof(double) * n);
   double *pp = (double *)malloc(sizeof(double) * n);
-  double *Ap = (double *)malloc(sizeof(double) * n);
+  double *sv = (double *)malloc(sizeof(double) * n);
   double *tmp = (double *)malloc(sizeof(double) * n);
   for (int i = 0; i < n; ++i) {
     x[i] = 0.0;
     r[i] = b[i];
-    pp[i] = b[i];
   }
-  double rr = orc_dot(r, r, n, tmp);
-  double thr = (tol * tol) * rr;
-  int it = 0, rc = ORC_OK, done = (rr == 0.0);
-  while (!done && it < max_iters) {
-    orc_apply(p, gx, gy, diag, pp, Ap);
-    double pAp = orc_dot(pp, Ap, n, tmp);
-    if (!(pAp > 0.0)) {
-      rc = ORC_E_CG_BREAKDOWN;
-      break;
+  orc_apply(p, gx, gy, diag, r, w);
+  double gamma = orc_dot(r, r, n, tmp);
+  double delta = orc_dot(w, r, n, tmp);
+  double thr = (tol * tol) * gamma;
+  int it = 0, rc = ORC_OK, done = (gamma == 0.0);
+  double alpha = 0.0, beta = 0.0;
+  if (!done) {
+    if (!(delta > 0.0)) rc = ORC_E_CG_BREAKDOWN;
+    else alpha = gamma / delta;
+  }
+  while (!done && rc == ORC_OK && it < max_iters) {
+    for (int i = 0; i < n; ++i) {
+      pp[i] = (it == 0) ? r[i] : r[i] + beta * pp[i];
+      sv[i] = (it == 0) ? w[i] : w[i] + beta * sv[i];
+      x[i] = x[i] + alpha * pp[i];
+      r[i] = r[i] - alpha * sv[i];
     }
-    double alpha = rr / pAp;
-    for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * pp[i];
-    for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * Ap[i];
-    double rr_new = orc_dot(r, r, n, tmp);
+    orc_apply(p, gx, gy, diag, r, w);
+    double gamma_new = orc_dot(r, r, n, tmp);
+    delta = orc_dot(w, r, n, tmp);
     ++it;
-    if (rr_new <= thr) {
+    if (gamma_new <= thr) {
       done = 1;
       break;
     }
-    double beta = rr_new / rr;
-    for (int i = 0; i < n; ++i) pp[i] = r[i] + beta * pp[i];
-    rr = rr_new;
+    beta = gamma_new / gamma;
+    double t = beta * gamma_new;
+    t = t / alpha;
+    double den = delta - t;
+    if (!(den > 0.0)) {
+      rc = ORC_E_CG_BREAKDOWN;
+      break;
+    }
+    alpha = gamma_new / den;
+    gamma = gamma_new;
   }
   if (rc == ORC_OK && !done) rc = ORC_E_CG_NOT_CONVERGED;
   if (iters_out) *iters_out = it;
   free(r);
+  free(w);
   free(pp);
-  free(Ap);
+  free(sv);
   free(tmp);
   return rc;
 }

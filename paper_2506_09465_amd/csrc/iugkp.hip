@@ -36,6 +36,17 @@ int fail(int code, const std::string &msg)
   } while (0)
 
 constexpr int kCgGridMax = 64;
+constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of the CG kernel
+
+void *cg_kernel_for(int J)
+{
+  switch (J) {
+    case 1: return reinterpret_cast<void *>(iugkp::cg_kernel<1>);
+    case 2: return reinterpret_cast<void *>(iugkp::cg_kernel<2>);
+    case 4: return reinterpret_cast<void *>(iugkp::cg_kernel<4>);
+    default: return reinterpret_cast<void *>(iugkp::cg_kernel<0>);
+  }
+}
 constexpr int kTileX = 8, kTileY = 8;        // emitter tile of one workgroup (cells)
 constexpr int kWallSeg = 8;                  // wall faces per workgroup
 constexpr int kWindowHalo = 12;              // window margin around a tile (cells)
@@ -71,7 +82,8 @@ struct iugkp_handle {
   // device memory
   double *tau = nullptr, *ratio = nullptr, *E = nullptr, *E_half = nullptr, *rhs = nullptr;
   double *Dx = nullptr, *Dy = nullptr, *gx = nullptr, *gy = nullptr, *diag = nullptr;
-  double *cg_x = nullptr, *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *cg_Ap = nullptr;
+  double *cg_x = nullptr, *cg_r = nullptr, *cg_w = nullptr, *cg_p = nullptr, *cg_s = nullptr;
+  double *cg_pub = nullptr;
   double *part = nullptr, *part_a = nullptr, *part_b = nullptr;
   unsigned long long *gpart = nullptr;
   unsigned int *cg_barrier = nullptr;
@@ -86,7 +98,8 @@ struct iugkp_handle {
   double *out_T = nullptr, *out_qx = nullptr, *out_qy = nullptr;
   DevScalars *dsc = nullptr;
   DevScalars *hsc = nullptr;   // pinned host mirror
-  int cg_grid = 1;
+  int cg_grid = 1, cg_tb = 1, cg_j = 1;
+  size_t cg_lds = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   // host state
   uint32_t iter = 0;
@@ -166,8 +179,8 @@ void free_handle(iugkp_handle *h)
 {
   if (!h) return;
   void *bufs[] = {h->tau, h->ratio, h->E, h->E_half, h->rhs, h->Dx, h->Dy, h->gx, h->gy,
-                  h->diag, h->cg_x, h->cg_r, h->cg_p0, h->cg_p1, h->cg_Ap, h->part, h->part_a,
-                  h->part_b, h->gpart, h->cg_barrier, h->G, h->base, h->rem, h->D, h->W, h->Phix, h->Phiy,
+                  h->diag, h->cg_x, h->cg_r, h->cg_w, h->cg_p, h->cg_s, h->cg_pub, h->part,
+                  h->part_a, h->gpart, h->cg_barrier, h->G, h->base, h->rem, h->D, h->W, h->Phix, h->Phiy,
                   h->B, h->dB, h->tiles, h->acc_E, h->acc_x, h->acc_y, h->out_T, h->out_qx, h->out_qy, h->dsc};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -315,12 +328,13 @@ int iterate(iugkp_handle *h, int faces)
     ca.diag = h->diag;
     ca.b = h->rhs;
     ca.x = h->cg_x;
-    ca.r = h->cg_r;
-    ca.p0 = h->cg_p0;
-    ca.p1 = h->cg_p1;
-    ca.Ap = h->cg_Ap;
-    ca.part_a = h->part_a;
-    ca.part_b = h->part_b;
+    ca.gr = h->cg_r;
+    ca.gw = h->cg_w;
+    ca.gp = h->cg_p;
+    ca.gs = h->cg_s;
+    ca.pub = h->cg_pub;
+    ca.part = h->part_a;
+    ca.TB = h->cg_tb;
     ca.tol2 = h->opt.cg_tol * h->opt.cg_tol;
     ca.max_iters = h->opt.cg_max_iters;
     ca.barrier = h->cg_barrier;
@@ -330,9 +344,8 @@ int iterate(iugkp_handle *h, int faces)
     // every workgroup must be resident for the grid barrier: the cooperative
     // launch refuses a grid that does not fit instead of letting it hang
     void *args[] = {&ca};
-    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<void *>(iugkp::cg_kernel),
-                                       dim3(h->cg_grid), dim3(iugkp::kCgThreads), args, 0,
-                                       h->stream));
+    HIP_TRY(hipLaunchCooperativeKernel(cg_kernel_for(h->cg_j), dim3(h->cg_grid),
+                                       dim3(iugkp::kCgThreads), args, h->cg_lds, h->stream));
     HIP_TRY(hipEventRecord(h->ev[3], h->stream));
     const int nbe = cdiv(m.n_emit, iugkp::kTree);
     iugkp::NewtonFinishArgs na{m.n_cells, m.n_emit, h->F, h->V, h->E_half, h->cg_x,
@@ -533,11 +546,11 @@ int create_impl(const iugkp_problem *p, const iugkp_options *o, void *stream, iu
     ALLOC(h->diag, nc);
     ALLOC(h->cg_x, nc);
     ALLOC(h->cg_r, nc);
-    ALLOC(h->cg_p0, nc);
-    ALLOC(h->cg_p1, nc);
-    ALLOC(h->cg_Ap, nc);
-    ALLOC(h->part_a, cdiv(nc, iugkp::kTree));
-    ALLOC(h->part_b, cdiv(nc, iugkp::kTree));
+    ALLOC(h->cg_w, nc);
+    ALLOC(h->cg_p, nc);
+    ALLOC(h->cg_s, nc);
+    ALLOC(h->cg_pub, 6 * static_cast<size_t>(nc));
+    ALLOC(h->part_a, 4 * static_cast<size_t>(cdiv(nc, iugkp::kTree)));
     ALLOC(h->gpart, nbe);
     ALLOC(h->cg_barrier, 2);
   }
@@ -618,15 +631,30 @@ int create_impl(const iugkp_problem *p, const iugkp_options *o, void *stream, iu
     iugkp::newton_operator_kernel<<<cdiv(nf, 256), 256, 0, s>>>(m, h->vg, h->tau, h->Dx, h->Dy,
                                                                  h->gx, h->gy, h->diag);
     iugkp::newton_diag_kernel<<<cdiv(nc, 256), 256, 0, s>>>(m, h->gx, h->gy, h->diag);
-    int per_cu = 0, dev = 0, n_cu = 0;
+    // CG layout: at most kCgGridMax resident workgroups (the barrier cost grows
+    // with the number of arrivals), whole 256-cell tree blocks per workgroup,
+    // cell state in registers when four-block passes and LDS staging allow
+    int dev = 0, n_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(iugkp::cg_kernel), iugkp::kCgThreads, 0));
-    // a small grid keeps the barrier cheap (its cost grows with the number of
-    // arriving workgroups); at most one workgroup per CU
-    const int nwg = cdiv(nc, iugkp::kCgThreads);
-    h->cg_grid = std::max(1, std::min(std::min(nwg, kCgGridMax), std::max(1, per_cu) * n_cu));
+    const int nbt = cdiv(nc, iugkp::kTree);
+    int G = std::max(1, std::min(std::min(nbt, kCgGridMax), n_cu));
+    const int TB = cdiv(nbt, G);
+    G = cdiv(nbt, TB);
+    const int passes = cdiv(TB, iugkp::kCgSlices);
+    int J = passes <= 1 ? 1 : passes <= 2 ? 2 : passes <= 4 ? 4 : 0;
+    size_t lds = (static_cast<size_t>(TB) * iugkp::kTree + 2 * static_cast<size_t>(p->nx)) * sizeof(double);
+    if (J > 0 && lds > kCgLdsMax) J = 0;
+    if (J == 0) lds = 2 * static_cast<size_t>(p->nx) * sizeof(double);
+    if (lds > kCgLdsMax) return bail(fail(IUGKP_E_INVALID_ARG, "mesh rows too long for the Newton CG"));
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cg_kernel_for(J), iugkp::kCgThreads, lds));
+    if (per_cu < 1 || G > per_cu * n_cu)
+      return bail(fail(IUGKP_E_DEVICE, "CG workgroups cannot all be resident"));
+    h->cg_grid = G;
+    h->cg_tb = TB;
+    h->cg_j = J;
+    h->cg_lds = lds;
   }
   std::vector<long long> g(ne);
   int hflag = 0;

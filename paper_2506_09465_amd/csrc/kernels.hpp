@@ -721,132 +721,282 @@ __device__ __forceinline__ bool grid_barrier(unsigned int *counter, unsigned int
 }
 
 // ---------------------------------------------------------------------------
-// Conjugate gradients (Hestenes-Stiefel, x0 = 0, stop at r.r <= tol^2 b.b) as
-// one persistent kernel.  Workgroup j owns the 256-cell tree blocks j, j + grid,
-// ...  Two grid barriers per iteration: the search direction
-// p = r + beta p_old is formed on the fly inside the operator application (also
-// for the neighbours, from r and p_old which no one writes in that phase), with
-// p double-buffered.  Every workgroup reduces all block partials itself in the
-// fixed order, so all take identical decisions.
+// Conjugate gradients, single-reduction form (Chronopoulos & Gear 1989):
+//   x = 0, r = b, w = A r, gamma = (r, r), delta = (w, r), alpha = gamma / delta
+//   repeat: p = r + beta p, s = w + beta s (p = r, s = w the first time)
+//           x += alpha p, r -= alpha s, w = A r
+//           gamma' = (r, r), delta = (w, r); stop if gamma' <= tol^2 (b, b)
+//           beta = gamma' / gamma, alpha = gamma' / (delta - beta gamma' / alpha)
+// One persistent kernel, one grid barrier per iteration.  Workgroup g owns the
+// contiguous tree blocks [g TB, (g+1) TB) (cells [c0, c1)); its cells' x, r, w,
+// p, s stay in registers (J > 0: J passes of four 256-cell tree blocks per
+// 1024-thread workgroup) or in global arrays (J == 0).  The operator needs r
+// one mesh row beyond the own range: before each barrier every workgroup
+// publishes (r, w, s) of its first and last nx cells (double-buffered by
+// iteration parity); after it, each workgroup recomputes the neighbours' new r
+// on that halo with the owner's exact operations, s = w + beta s_old,
+// r = r - alpha s, so the halo values are bit-identical to the owner's.
 // ---------------------------------------------------------------------------
+constexpr int kCgThreads = 1024;
+constexpr int kCgSlices = kCgThreads / kTree;
+
 struct CGArgs {
   Mesh m;
   const double *gx, *gy, *diag, *b;
-  double *x, *r, *p0, *p1, *Ap;
-  double *part_a, *part_b;
+  double *x;                 // solution
+  double *gr, *gw, *gp, *gs; // own-state arrays (J == 0 only)
+  double *pub;               // [2][3][n] published (r, w, s)
+  double *part;              // [2][2][nb] partials of (r, r) and (w, r)
+  int TB;                    // tree blocks per workgroup
   double tol2;
   int max_iters;
   unsigned int *barrier;     // [2], zeroed before the launch
   DevScalars *sc;
 };
 
-__device__ __forceinline__ double cg_dir(const double *r, const double *pold, double beta,
-                                         int first, int c)
+struct CellCoef {
+  double d, l, r, dn, up;    // diagonal and the four face conductances (0 if absent)
+};
+
+__device__ __forceinline__ CellCoef load_coef(const CGArgs &a, int c)
 {
-  return first ? r[c] : r[c] + beta * pold[c];
+  const Mesh &m = a.m;
+  const int iy = c / m.nx, ix = c - iy * m.nx;
+  CellCoef k;
+  k.d = a.diag[c];
+  k.l = (ix > 0) ? a.gx[iy * (m.nx + 1) + ix] : 0.0;
+  k.r = (ix < m.nx - 1) ? a.gx[iy * (m.nx + 1) + ix + 1] : 0.0;
+  k.dn = (m.dim == 2 && iy > 0) ? a.gy[iy * m.nx + ix] : 0.0;
+  k.up = (m.dim == 2 && iy < m.ny - 1) ? a.gy[(iy + 1) * m.nx + ix] : 0.0;
+  return k;
 }
 
-constexpr int kCgThreads = 1024;
+// (A v)_c with the reference operation order: diag v_c - g_l v_{c-1} - g_r v_{c+1}
+// - g_dn v_{c-nx} - g_up v_{c+nx}, absent neighbours skipped.
+template <class Get>
+__device__ __forceinline__ double apply_cell(const Mesh &m, const CellCoef &k, int c, Get v)
+{
+  const int iy = c / m.nx, ix = c - iy * m.nx;
+  double acc = k.d * v(c);
+  if (ix > 0) acc = acc - k.l * v(c - 1);
+  if (ix < m.nx - 1) acc = acc - k.r * v(c + 1);
+  if (m.dim == 2) {
+    if (iy > 0) acc = acc - k.dn * v(c - m.nx);
+    if (iy < m.ny - 1) acc = acc - k.up * v(c + m.nx);
+  }
+  return acc;
+}
 
+template <int J>
 __global__ __launch_bounds__(kCgThreads) void cg_kernel(CGArgs a)
 {
+  extern __shared__ double stage[];       // r on [h0, h1) (J > 0) or on the halo (J == 0)
   __shared__ double lds[kCgThreads];
   __shared__ double lds2[kTree];
   unsigned int epoch = 0;
   const Mesh &m = a.m;
-  const int n = m.n_cells;
+  const int n = m.n_cells, nx = m.nx;
   const int nb = (n + kTree - 1) / kTree;
-  const int slices = kCgThreads / kTree;
+  const int tb0 = blockIdx.x * a.TB;
+  const int tb1 = min(tb0 + a.TB, nb);
+  const int c0 = min(tb0 * kTree, n), c1 = min(tb1 * kTree, n);
+  const int h0 = max(0, c0 - nx), h1 = min(n, c1 + nx);
+  const int nlo = c0 - h0;                // halo cells below the own range
   const int sl = threadIdx.x / kTree, t = threadIdx.x & (kTree - 1);
-  // pass g covers tree blocks (g * gridDim.x + blockIdx.x) * slices + sl
-  const int npass = (nb + gridDim.x * slices - 1) / (gridDim.x * slices);
-  for (int g = 0; g < npass; ++g) {
-    const int tb = (g * gridDim.x + blockIdx.x) * slices + sl;
+  const int npass = (a.TB + kCgSlices - 1) / kCgSlices;
+  double *const pub[2] = {a.pub, a.pub + 3 * static_cast<size_t>(n)};
+  double *const part[2] = {a.part, a.part + 2 * static_cast<size_t>(nb)};
+
+  // own cell of pass j for this thread (or -1)
+  auto own_cell = [&](int j) {
+    const int tb = tb0 + j * kCgSlices + sl;
     const int c = tb * kTree + t;
-    double v = 0.0;
-    if (tb < nb && c < n) {
-      const double bc = a.b[c];
-      a.x[c] = 0.0;
-      a.r[c] = bc;
-      v = bc * bc;
+    return (tb < tb1 && c < n) ? c : -1;
+  };
+  auto in_boundary = [&](int c) { return c < c0 + nx || c >= c1 - nx; };
+  // r value seen by the operator: staged in LDS (J > 0) or own global / halo LDS (J == 0)
+  auto rget = [&](int c) -> double {
+    if constexpr (J > 0) {
+      return stage[c - h0];
+    } else {
+      if (c < c0) return stage[c - h0];
+      if (c >= c1) return stage[nlo + (c - c1)];
+      return a.gr[c];
     }
-    v = slice_tree256(v, lds);
-    if (t == 0 && tb < nb) a.part_b[tb] = v;
+  };
+
+  double xr[J > 0 ? J : 1], rr_[J > 0 ? J : 1], wr[J > 0 ? J : 1], pr[J > 0 ? J : 1],
+      sr[J > 0 ? J : 1];
+  CellCoef kr[J > 0 ? J : 1];
+
+  // ---- start: x = 0, r = b, w = A b
+  if constexpr (J > 0) {
+    for (int i = threadIdx.x; i < h1 - h0; i += kCgThreads) stage[i] = a.b[h0 + i];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int c = own_cell(j);
+      xr[j] = 0.0;
+      pr[j] = 0.0;
+      sr[j] = 0.0;
+      if (c >= 0) {
+        kr[j] = load_coef(a, c);
+        rr_[j] = a.b[c];
+      } else {
+        rr_[j] = 0.0;
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < nlo; i += kCgThreads) stage[i] = a.b[h0 + i];
+    for (int i = threadIdx.x; i < h1 - c1; i += kCgThreads) stage[nlo + i] = a.b[c1 + i];
+    for (int j = 0; j < npass; ++j) {
+      const int c = own_cell(j);
+      if (c >= 0) {
+        a.x[c] = 0.0;
+        a.gr[c] = a.b[c];
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j < (J > 0 ? J : npass); ++j) {
+    const int c = own_cell(j);
+    double g = 0.0, d = 0.0;
+    if (c >= 0) {
+      double wv;
+      if constexpr (J > 0) {
+        wv = apply_cell(m, kr[j], c, rget);
+        wr[j] = wv;
+        g = rr_[j] * rr_[j];
+        d = wv * rr_[j];
+      } else {
+        const CellCoef k = load_coef(a, c);
+        wv = apply_cell(m, k, c, rget);
+        a.gw[c] = wv;
+        const double rv = a.gr[c];
+        g = rv * rv;
+        d = wv * rv;
+      }
+      if (in_boundary(c)) {
+        const double rv = (J > 0) ? rr_[j] : a.gr[c];
+        pub[0][c] = rv;
+        pub[0][n + c] = wv;
+        pub[0][2 * static_cast<size_t>(n) + c] = 0.0;
+      }
+    }
+    g = slice_tree256(g, lds);
+    d = slice_tree256(d, lds);
+    const int tb = tb0 + j * kCgSlices + sl;
+    if (t == 0 && tb < tb1) {
+      part[0][tb] = g;
+      part[0][nb + tb] = d;
+    }
   }
   if (!grid_barrier(a.barrier, epoch)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.sc->cg_status = -3;
     return;
   }
-  double rr = tree_all(a.part_b, nb, lds, lds2);
-  const double thr = a.tol2 * rr;
-  int status = -7;     // not converged unless proven otherwise
-  int it = 0;
-  double beta = 0.0;
-  double *pold = a.p0, *pnew = a.p1;
-  if (rr == 0.0) status = 0;
+  double gamma = tree_all(part[0], nb, lds, lds2);
+  double delta = tree_all(part[0] + nb, nb, lds, lds2);
+  const double thr = a.tol2 * gamma;
+  int status = -7;
+  int it = 0, par = 0;
+  double alpha = 0.0, beta = 0.0;
+  if (gamma == 0.0) status = 0;
+  else if (!(delta > 0.0)) status = -6;
+  else alpha = gamma / delta;
   while (status == -7 && it < a.max_iters) {
     const int first = (it == 0);
-    for (int g = 0; g < npass; ++g) {
-      const int tb = (g * gridDim.x + blockIdx.x) * slices + sl;
-      const int c = tb * kTree + t;
-      double v = 0.0;
-      if (tb < nb && c < n) {
-        const int iy = c / m.nx, ix = c - iy * m.nx;
-        const double pc = cg_dir(a.r, pold, beta, first, c);
-        double acc = a.diag[c] * pc;
-        if (ix > 0) acc = acc - a.gx[iy * (m.nx + 1) + ix] * cg_dir(a.r, pold, beta, first, c - 1);
-        if (ix < m.nx - 1)
-          acc = acc - a.gx[iy * (m.nx + 1) + ix + 1] * cg_dir(a.r, pold, beta, first, c + 1);
-        if (m.dim == 2) {
-          if (iy > 0) acc = acc - a.gy[iy * m.nx + ix] * cg_dir(a.r, pold, beta, first, c - m.nx);
-          if (iy < m.ny - 1)
-            acc = acc - a.gy[(iy + 1) * m.nx + ix] * cg_dir(a.r, pold, beta, first, c + m.nx);
+    const double *pp = pub[par];
+    double *pn = pub[par ^ 1];
+    // own cells: direction, x and r updates; stage the new r
+    for (int j = 0; j < (J > 0 ? J : npass); ++j) {
+      const int c = own_cell(j);
+      if (c < 0) continue;
+      if constexpr (J > 0) {
+        pr[j] = first ? rr_[j] : rr_[j] + beta * pr[j];
+        sr[j] = first ? wr[j] : wr[j] + beta * sr[j];
+        xr[j] = xr[j] + alpha * pr[j];
+        rr_[j] = rr_[j] - alpha * sr[j];
+        stage[c - h0] = rr_[j];
+      } else {
+        const double pv = first ? a.gr[c] : a.gr[c] + beta * a.gp[c];
+        const double sv = first ? a.gw[c] : a.gw[c] + beta * a.gs[c];
+        a.gp[c] = pv;
+        a.gs[c] = sv;
+        a.x[c] = a.x[c] + alpha * pv;
+        a.gr[c] = a.gr[c] - alpha * sv;
+      }
+    }
+    // halo: the neighbours' new r from their published (r, w, s)
+    for (int i = threadIdx.x; i < (h1 - h0) - (c1 - c0); i += kCgThreads) {
+      const int c = (i < nlo) ? h0 + i : c1 + (i - nlo);
+      const double sv = first ? pp[n + c] : pp[n + c] + beta * pp[2 * static_cast<size_t>(n) + c];
+      const double rv = pp[c] - alpha * sv;
+      if constexpr (J > 0) stage[c - h0] = rv;
+      else stage[i] = rv;
+    }
+    __syncthreads();
+    for (int j = 0; j < (J > 0 ? J : npass); ++j) {
+      const int c = own_cell(j);
+      double g = 0.0, d = 0.0;
+      if (c >= 0) {
+        double wv, rv, sv;
+        if constexpr (J > 0) {
+          wv = apply_cell(m, kr[j], c, rget);
+          wr[j] = wv;
+          rv = rr_[j];
+          sv = sr[j];
+        } else {
+          const CellCoef k = load_coef(a, c);
+          wv = apply_cell(m, k, c, rget);
+          a.gw[c] = wv;
+          rv = a.gr[c];
+          sv = a.gs[c];
         }
-        pnew[c] = pc;
-        a.Ap[c] = acc;
-        v = pc * acc;
+        g = rv * rv;
+        d = wv * rv;
+        if (in_boundary(c)) {
+          pn[c] = rv;
+          pn[n + c] = wv;
+          pn[2 * static_cast<size_t>(n) + c] = sv;
+        }
       }
-      v = slice_tree256(v, lds);
-      if (t == 0 && tb < nb) a.part_a[tb] = v;
+      g = slice_tree256(g, lds);
+      d = slice_tree256(d, lds);
+      const int tb = tb0 + j * kCgSlices + sl;
+      if (t == 0 && tb < tb1) {
+        part[par ^ 1][tb] = g;
+        part[par ^ 1][nb + tb] = d;
+      }
     }
     if (!grid_barrier(a.barrier, epoch)) {
       status = -3;
       break;
     }
-    const double pAp = tree_all(a.part_a, nb, lds, lds2);
-    if (!(pAp > 0.0)) {
-      status = -6;
-      break;
-    }
-    const double alpha = rr / pAp;
-    for (int g = 0; g < npass; ++g) {
-      const int tb = (g * gridDim.x + blockIdx.x) * slices + sl;
-      const int c = tb * kTree + t;
-      double v = 0.0;
-      if (tb < nb && c < n) {
-        a.x[c] = a.x[c] + alpha * pnew[c];
-        const double rc = a.r[c] - alpha * a.Ap[c];
-        a.r[c] = rc;
-        v = rc * rc;
-      }
-      v = slice_tree256(v, lds);
-      if (t == 0 && tb < nb) a.part_b[tb] = v;
-    }
-    if (!grid_barrier(a.barrier, epoch)) {
-      status = -3;
-      break;
-    }
-    const double rr_new = tree_all(a.part_b, nb, lds, lds2);
+    par ^= 1;
     ++it;
-    if (rr_new <= thr) {
+    const double gamma_new = tree_all(part[par], nb, lds, lds2);
+    delta = tree_all(part[par] + nb, nb, lds, lds2);
+    if (gamma_new <= thr) {
       status = 0;
       break;
     }
-    beta = rr_new / rr;
-    rr = rr_new;
-    double *tmp = pold;
-    pold = pnew;
-    pnew = tmp;
+    beta = gamma_new / gamma;
+    double tq = beta * gamma_new;
+    tq = tq / alpha;
+    const double den = delta - tq;
+    if (!(den > 0.0)) {
+      status = -6;
+      break;
+    }
+    alpha = gamma_new / den;
+    gamma = gamma_new;
+  }
+  if constexpr (J > 0) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int c = own_cell(j);
+      if (c >= 0) a.x[c] = xr[j];
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.sc->cg_iters = it;

@@ -223,3 +223,28 @@ def test_gpu_error_paths(gpu):
     w = slab_1d(n=30, kn=0.01, particles=5000)
     s = gpu.Solver(w, newton=True, cg_max_iters=1)
     assert s.step(1) == -7
+
+
+NEWTON_LAYOUTS = {
+    # name: (workload factory) -- exercises the CG workgroup layouts
+    "strip_1x9": lambda: cavity_2d(n=1, ny=9, kn=0.05, particles=5000),
+    "slab_100": lambda: slab_1d(n=100, kn=0.003, particles=20_000),
+    "ragged_37x23": lambda: cavity_2d(n=37, ny=23, kn=0.01, particles=50_000),
+    "two_passes_300": lambda: cavity_2d(n=300, kn=0.01, particles=200_000),
+    "four_passes_512": lambda: cavity_2d(n=512, kn=0.005, particles=300_000),
+    "global_state_600": lambda: cavity_2d(n=600, kn=0.005, particles=300_000),
+}
+
+
+@pytest.mark.parametrize("name", list(NEWTON_LAYOUTS))
+def test_newton_cg_layouts_bitwise(oracle_mod, gpu, name):
+    """One Newton iteration: CG iteration count, E and G bit-identical for every
+    workgroup layout of the CG kernel (one workgroup, ragged tree blocks,
+    one/two/four register passes, state in global memory)."""
+    w = NEWTON_LAYOUTS[name]()
+    Dx, Dy = _diff(w)
+    o, s = _pair(oracle_mod, gpu, w, newton=True, diff_x=Dx, diff_y=Dy,
+                 tally_faces=oracle_mod.FACES_EVERY)
+    assert o.step(2) == 0 and s.step(2) == 0
+    _same_iteration(o, s, name)
+    assert o.info().cg_iters_total == s.stats()["cg_iters_total"]
