@@ -115,6 +115,8 @@ typedef struct iugkp_stats {
   int fixed_point_F;            /* fixed-point exponent */
   uint64_t n_per_emitter;       /* N */
   int n_emitters;
+  int status;                   /* result of the solve: IUGKP_OK, IUGKP_W_NOT_CONVERGED or an
+                                   error code (per instance in a batch) */
 } iugkp_stats;
 
 typedef struct iugkp_handle iugkp_handle;
@@ -180,11 +182,18 @@ int iugkp_get_stats(iugkp_handle *h, iugkp_stats *stats);
 double iugkp_d_eff(double lam, double delta);
 
 /* Batched solves: n independent problems advanced together, one launch per phase
- * for all of them (work queue over instances and particle chunks), the
- * per-iteration sequence replayed from a captured HIP graph.  Every instance's
- * results are bitwise those of iugkp_solve on the same problem and options.
- * All problems must use the same mem_kind; outputs per instance as iugkp_solve
- * (T_out[i], qx_out[i], qy_out[i] may be NULL; stats may be NULL or an array of n). */
+ * for all of them (the particle step over the emitter tiles of every instance,
+ * one workgroup per instance for the Newton CG), the per-iteration sequence
+ * captured once in a HIP graph on a stream of the batch's own (ordered after
+ * `stream` with events) and replayed until every instance is done.  Every
+ * instance's results are bitwise those of iugkp_solve on the same problem and
+ * options, including the iteration at which it stops or fails.  All problems
+ * must use the same mem_kind; outputs per instance as iugkp_solve (T_out[i]
+ * required, qx_out[i], qy_out[i] may be NULL; qx_out, qy_out, stats may be NULL,
+ * stats otherwise an array of n).  iugkp_batch_solve may be called once per batch;
+ * it returns the most severe per-instance status (the most negative error, else
+ * IUGKP_W_NOT_CONVERGED, else IUGKP_OK); outputs are written for every instance
+ * that did not fail, and stats[i].status holds each instance's own status. */
 int iugkp_batch_create(const iugkp_problem *const *problems,
                        const iugkp_options *const *options, int n, void *stream,
                        iugkp_batch **out);

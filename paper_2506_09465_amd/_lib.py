@@ -46,7 +46,7 @@ class Stats(C.Structure):
                 ("tot_crossings", C.c_uint64), ("ms_march", C.c_double),
                 ("ms_update", C.c_double), ("ms_cg", C.c_double), ("cg_iters_last", C.c_int),
                 ("cg_iters_total", C.c_int), ("fixed_point_F", C.c_int),
-                ("n_per_emitter", C.c_uint64), ("n_emitters", C.c_int)]
+                ("n_per_emitter", C.c_uint64), ("n_emitters", C.c_int), ("status", C.c_int)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}

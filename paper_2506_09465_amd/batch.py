@@ -12,14 +12,23 @@ from .solver import _Marshal, _defaults, _stream_handle
 class BatchSolver:
     """Solve a list of problems together; outputs per instance as Solver.solve()."""
 
-    def __init__(self, workloads, device="cuda", **kw):
+    def __init__(self, workloads, device="cuda", per_instance=None, **kw):
+        """per_instance: optional list of option dicts, one per workload, each
+        overriding the shared keyword options for its instance."""
         self.device = torch.device(device)
         if self.device.type != "cuda" or not torch.cuda.is_available():
             raise RuntimeError("the IUGKP library needs a ROCm GPU (torch.cuda) device")
         self.ws = list(workloads)
+        if per_instance is not None and len(per_instance) != len(self.ws):
+            raise ValueError("per_instance needs one option dict per workload")
         self._m = []
-        for w in self.ws:
-            opts = _defaults(w, dict(kw))
+        for i, w in enumerate(self.ws):
+            o = dict(kw)
+            if per_instance is not None:
+                o.update(per_instance[i])
+            opts = _defaults(w, o)
+            if o:
+                raise TypeError(f"unknown options {sorted(o)}")
             self._m.append(_Marshal(w, self.device, **opts))
         n = len(self.ws)
         probs = (C.c_void_p * n)(*[C.addressof(m.problem) for m in self._m])
@@ -57,7 +66,10 @@ class BatchSolver:
         st = (L.Stats * n)()
         with torch.cuda.device(self.device):
             rc = L.lib().iugkp_batch_solve(self.h, pT, px, py, st)
-        L.check(rc, "iugkp_batch_solve", allow_warning=True)
+        # per-instance failures are reported in each instance's stats["status"];
+        # only argument and memory errors concern the whole batch
+        if rc in (L.E_INVALID_ARG, L.E_NOMEM):
+            L.check(rc, "iugkp_batch_solve")
         out = []
         for i, w in enumerate(self.ws):
             nfy = (w.ny + 1) * w.nx if w.dim == 2 else 0

@@ -1,9 +1,15 @@
 // iugkp.hip -- C ABI of the gfx950 IUGKP solver (declarations in include/iugkp.h).
 //
 // One translation unit: device kernels (kernels.hpp), set-up arithmetic
-// (host_math.hpp), the single-problem driver and the batched driver
-// (batch.hpp).  Built with -ffp-contract=off and no fast-math so that every
-// floating-point result is fixed by IEEE binary64 semantics.
+// (host_math.hpp), the single-problem driver and the batched driver.  Built
+// with -ffp-contract=off and no fast-math so that every floating-point result
+// is fixed by IEEE binary64 semantics.
+//
+// Every per-iteration kernel reads its problem from a device-side descriptor
+// (iugkp::Inst).  A single solve is a batch of one driven from the host; a
+// batch advances all its instances with one launch per phase, the sequence
+// captured once in a HIP graph and replayed until every instance is done (the
+// per-instance iteration control lives on the device).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +42,14 @@ int fail(int code, const std::string &msg)
   } while (0)
 
 constexpr int kCgGridMax = 64;
-constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of the CG kernel
+constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of the multi-workgroup CG
+constexpr int kTileX = 8, kTileY = 8;        // emitter tile of one workgroup (cells)
+constexpr int kWallSeg = 8;                  // wall faces per workgroup
+constexpr int kWindowHalo = 12;              // window margin around a tile (cells)
+constexpr size_t kLdsWordsMax = 6144;        // 48 KB of 64-bit tallies per workgroup
+constexpr int kLdsWallsMax = 1024;
+
+inline int cdiv(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
 
 void *cg_kernel_for(int J)
 {
@@ -47,69 +60,48 @@ void *cg_kernel_for(int J)
     default: return reinterpret_cast<void *>(iugkp::cg_kernel<0>);
   }
 }
-constexpr int kTileX = 8, kTileY = 8;        // emitter tile of one workgroup (cells)
-constexpr int kWallSeg = 8;                  // wall faces per workgroup
-constexpr int kWindowHalo = 12;              // window margin around a tile (cells)
-constexpr size_t kLdsWordsMax = 6144;        // 48 KB of 64-bit tallies per workgroup
-constexpr int kLdsWallsMax = 1024;
-
-inline int cdiv(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
-
-template <class T>
-hipError_t dalloc(T **p, size_t n)
-{
-  *p = nullptr;
-  if (n == 0) n = 1;
-  return hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T));
-}
 
 }  // namespace
 
 using iugkp::DevScalars;
+using iugkp::Inst;
 using iugkp::Mesh;
-
-struct iugkp_handle {
-  hipStream_t stream = nullptr;
-  Mesh m{};
-  double t_ref = 0, cv = 0, vg = 0, tau_min = 0, lam_min = 0, V = 0;
-  int F = 0;
-  uint32_t N = 1;
-  uint32_t n_particles = 0;
-  int has_null = 0;
-  int mem_kind = IUGKP_MEM_HOST;
-  iugkp_options opt{};
-  int block = 256;
-  // device memory
-  double *tau = nullptr, *ratio = nullptr, *E = nullptr, *E_half = nullptr, *rhs = nullptr;
-  double *Dx = nullptr, *Dy = nullptr, *gx = nullptr, *gy = nullptr, *diag = nullptr;
-  double *cg_x = nullptr, *cg_r = nullptr, *cg_w = nullptr, *cg_p = nullptr, *cg_s = nullptr;
-  double *cg_pub = nullptr;
-  double *part = nullptr, *part_a = nullptr, *part_b = nullptr;
-  unsigned long long *gpart = nullptr;
-  unsigned int *cg_barrier = nullptr;
-  long long *G = nullptr, *base = nullptr;
-  uint32_t *rem = nullptr;
-  long long *D = nullptr, *W = nullptr, *Phix = nullptr, *Phiy = nullptr, *B = nullptr;
-  long long *dB = nullptr;
-  iugkp::TileDesc *tiles = nullptr;
-  int n_tiles = 0, WX = 1, WY = 1, lds_walls = 0;
-  size_t lds_bytes = 0;
-  double *acc_E = nullptr, *acc_x = nullptr, *acc_y = nullptr;
-  double *out_T = nullptr, *out_qx = nullptr, *out_qy = nullptr;
-  DevScalars *dsc = nullptr;
-  DevScalars *hsc = nullptr;   // pinned host mirror
-  int cg_grid = 1, cg_tb = 1, cg_j = 1;
-  size_t cg_lds = 0;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  // host state
-  uint32_t iter = 0;
-  double d0 = 0.0, res = 0.0;
-  std::vector<double> res_hist;
-  iugkp_stats st{};
-  bool last_faces = false;
-};
+using iugkp::TileDesc;
 
 namespace {
+
+// Host-side record of one problem instance and the device memory it owns.
+struct InstHost {
+  Inst d{};                          // descriptor (device pointers) as uploaded
+  iugkp_options opt{};
+  int mem_kind = IUGKP_MEM_HOST;
+  std::vector<TileDesc> tiles;       // inst field filled by the owner
+  size_t lds_bytes = 0;              // march window
+  std::vector<void *> allocs;
+  double *tau = nullptr, *Dx = nullptr, *Dy = nullptr, *gx = nullptr, *gy = nullptr,
+         *diag = nullptr;
+  double *out_T = nullptr, *out_qx = nullptr, *out_qy = nullptr;
+  // multi-workgroup CG (single solves)
+  double *cg_pub = nullptr, *cg_mpart = nullptr;
+  unsigned int *cg_barrier = nullptr;
+  int cg_grid = 1, cg_tb = 1, cg_j = 1;
+  size_t cg_lds = 0;
+
+  template <class T>
+  hipError_t alloc(T **p, size_t n)
+  {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T));
+    if (e == hipSuccess) allocs.push_back(*p);
+    return e;
+  }
+  void release()
+  {
+    for (void *p : allocs) (void)hipFree(p);
+    allocs.clear();
+  }
+};
 
 int check_problem(const iugkp_problem *p)
 {
@@ -175,105 +167,45 @@ int scale_exponent(const iugkp_problem *p, double tau_min, const std::vector<dou
   return 62 - ((mant == 0.5) ? e - 1 : e);
 }
 
-void free_handle(iugkp_handle *h)
-{
-  if (!h) return;
-  void *bufs[] = {h->tau, h->ratio, h->E, h->E_half, h->rhs, h->Dx, h->Dy, h->gx, h->gy,
-                  h->diag, h->cg_x, h->cg_r, h->cg_w, h->cg_p, h->cg_s, h->cg_pub, h->part,
-                  h->part_a, h->gpart, h->cg_barrier, h->G, h->base, h->rem, h->D, h->W, h->Phix, h->Phiy,
-                  h->B, h->dB, h->tiles, h->acc_E, h->acc_x, h->acc_y, h->out_T, h->out_qx, h->out_qy, h->dsc};
-  for (void *b : bufs)
-    if (b) (void)hipFree(b);
-  if (h->hsc) (void)hipHostFree(h->hsc);
-  for (auto &e : h->ev)
-    if (e) (void)hipEventDestroy(e);
-  delete h;
-}
-
-int launch_march(iugkp_handle *h, uint32_t slot, int faces)
-{
-  iugkp::MarchArgs a;
-  a.m = h->m;
-  a.lam_min = h->lam_min;
-  a.N = h->N;
-  a.slot = slot;
-  a.key0 = static_cast<uint32_t>(h->opt.seed);
-  a.key1 = static_cast<uint32_t>(h->opt.seed >> 32);
-  a.faces = faces;
-  a.has_null = h->has_null;
-  a.WX = h->WX;
-  a.WY = h->WY;
-  a.lds_walls = h->lds_walls;
-  a.tiles = h->tiles;
-  a.base = h->base;
-  a.rem = h->rem;
-  a.ratio = h->ratio;
-  a.D = h->D;
-  a.W = h->W;
-  a.Phiy = h->Phiy;
-  a.dB = h->dB;
-  a.B = h->B;
-  a.sc = h->dsc;
-  const int grid = h->n_tiles;
-  const size_t sh = h->lds_bytes;
-  HIP_TRY(hipEventRecord(h->ev[0], h->stream));
-  switch (h->block) {
-    case 64: iugkp::march_kernel<64><<<grid, 64, sh, h->stream>>>(a); break;
-    case 128: iugkp::march_kernel<128><<<grid, 128, sh, h->stream>>>(a); break;
-    case 512: iugkp::march_kernel<512><<<grid, 512, sh, h->stream>>>(a); break;
-    case 1024: iugkp::march_kernel<1024><<<grid, 1024, sh, h->stream>>>(a); break;
-    default: iugkp::march_kernel<256><<<grid, 256, sh, h->stream>>>(a); break;
-  }
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipEventRecord(h->ev[1], h->stream));
-  if (faces) {
-    if (h->m.dim == 2)
-      iugkp::reconstruct_y_kernel<<<cdiv(h->m.nx, 256), 256, 0, h->stream>>>(h->m, h->dB, h->Phiy);
-    iugkp::reconstruct_x_kernel<<<cdiv(h->m.ny, 256), 256, 0, h->stream>>>(h->m, h->G, h->D, h->Phiy,
-                                                                         h->B, h->Phix);
-    HIP_TRY(hipGetLastError());
-  }
-  return IUGKP_OK;
-}
-
 // Tile table and LDS window: the whole domain when its tallies fit in LDS,
 // otherwise a window of the tile plus a margin, placed inside the domain.
-void plan_tiles(iugkp_handle *h, std::vector<iugkp::TileDesc> &tiles)
+void plan_tiles(InstHost &ih)
 {
-  const Mesh &m = h->m;
-  h->lds_walls = (m.n_b <= kLdsWallsMax) ? 1 : 0;
-  const size_t whole = iugkp::window_words(m.nx, m.ny, h->has_null, h->lds_walls, m.n_b);
-  bool whole_domain = whole <= kLdsWordsMax;
+  Inst &d = ih.d;
+  const Mesh &m = d.m;
+  d.lds_walls = (m.n_b <= kLdsWallsMax) ? 1 : 0;
+  const size_t whole = iugkp::window_words(m.nx, m.ny, d.has_null, d.lds_walls, m.n_b);
+  const bool whole_domain = whole <= kLdsWordsMax;
   if (whole_domain) {
-    h->WX = m.nx;
-    h->WY = m.ny;
+    d.WX = m.nx;
+    d.WY = m.ny;
   } else {
-    h->WX = std::min(m.nx, kTileX + 2 * kWindowHalo);
-    h->WY = std::min(m.ny, kTileY + 2 * kWindowHalo);
+    d.WX = std::min(m.nx, kTileX + 2 * kWindowHalo);
+    d.WY = std::min(m.ny, kTileY + 2 * kWindowHalo);
   }
   auto place = [](int lo, int extent, int W, int n) {
-    // window of size W covering [lo, lo + extent) as centrally as the domain allows
     int w0 = lo - (W - extent) / 2;
     if (w0 > n - W) w0 = n - W;
     if (w0 < 0) w0 = 0;
     return w0;
   };
+  ih.tiles.clear();
   for (int ty = 0; ty < m.ny; ty += kTileY)
     for (int tx = 0; tx < m.nx; tx += kTileX) {
-      iugkp::TileDesc t{};
+      TileDesc t{};
       t.kind = 0;
       t.x0 = tx;
       t.y0 = ty;
       t.ex = std::min(kTileX, m.nx - tx);
       t.ey = std::min(kTileY, m.ny - ty);
-      t.wx0 = whole_domain ? 0 : place(tx, t.ex, h->WX, m.nx);
-      t.wy0 = whole_domain ? 0 : place(ty, t.ey, h->WY, m.ny);
-      tiles.push_back(t);
+      t.wx0 = whole_domain ? 0 : place(tx, t.ex, d.WX, m.nx);
+      t.wy0 = whole_domain ? 0 : place(ty, t.ey, d.WY, m.ny);
+      ih.tiles.push_back(t);
     }
   // wall segments: left rows, right rows, bottom columns, top columns
   auto wall = [&](int b_first, int count, int along_x, int side_hi) {
     for (int s0 = 0; s0 < count; s0 += kWallSeg) {
-      iugkp::TileDesc t{};
+      TileDesc t{};
       t.kind = 1;
       t.x0 = b_first + s0;
       t.ex = std::min(kWallSeg, count - s0);
@@ -281,14 +213,14 @@ void plan_tiles(iugkp_handle *h, std::vector<iugkp::TileDesc> &tiles)
       if (whole_domain) {
         t.wx0 = 0;
         t.wy0 = 0;
-      } else if (along_x) {   // bottom / top wall: segment along x
-        t.wx0 = place(s0, t.ex, h->WX, m.nx);
-        t.wy0 = side_hi ? m.ny - h->WY : 0;
-      } else {                // left / right wall: segment along y
-        t.wy0 = place(s0, t.ex, h->WY, m.ny);
-        t.wx0 = side_hi ? m.nx - h->WX : 0;
+      } else if (along_x) {
+        t.wx0 = place(s0, t.ex, d.WX, m.nx);
+        t.wy0 = side_hi ? m.ny - d.WY : 0;
+      } else {
+        t.wy0 = place(s0, t.ex, d.WY, m.ny);
+        t.wx0 = side_hi ? m.nx - d.WX : 0;
       }
-      tiles.push_back(t);
+      ih.tiles.push_back(t);
     }
   };
   wall(0, m.ny, 0, 0);
@@ -297,159 +229,13 @@ void plan_tiles(iugkp_handle *h, std::vector<iugkp::TileDesc> &tiles)
     wall(2 * m.ny, m.nx, 1, 0);
     wall(2 * m.ny + m.nx, m.nx, 1, 1);
   }
-  h->n_tiles = static_cast<int>(tiles.size());
-  h->lds_bytes = iugkp::window_words(h->WX, h->WY, h->has_null, h->lds_walls, m.n_b) * sizeof(long long);
+  ih.lds_bytes = iugkp::window_words(d.WX, d.WY, d.has_null, d.lds_walls, m.n_b) * sizeof(long long);
 }
 
-// One iteration on the handle's stream; leaves the new scalars in h->hsc.
-int iterate(iugkp_handle *h, int faces)
-{
-  const Mesh &m = h->m;
-  const uint32_t slot = (h->opt.rng_mode == IUGKP_RNG_CRN) ? h->opt.rng_epoch : h->iter;
-  const int nprep = std::max(std::max(std::max(m.n_emit, m.n_fx), std::max(m.n_fy, m.n_cells)),
-                             (m.ny + 2) * m.nx);
-  iugkp::Tallies t{h->D, h->W, h->Phix, h->Phiy, h->B};
-  iugkp::prepare_kernel<<<cdiv(nprep, 256), 256, 0, h->stream>>>(m, h->G, h->N, h->base, h->rem,
-                                                                  t, h->dB, faces, h->dsc);
-  HIP_TRY(hipGetLastError());
-  int rc = launch_march(h, slot, faces);   // records ev[0] / ev[1] around the march kernel
-  if (rc) return rc;
-  const int nbc = cdiv(m.n_cells, iugkp::kTree);
-  iugkp::UpdateArgs ua{m.n_cells, h->F, h->has_null, h->opt.newton, h->V, h->D, h->W,
-                       h->E, h->E_half, h->rhs, h->G, h->part, h->dsc};
-  iugkp::update_kernel<<<nbc, 256, 0, h->stream>>>(ua);
-  HIP_TRY(hipGetLastError());
-  const int first = (h->iter == 0);
-  if (h->opt.newton) {
-    iugkp::CGArgs ca;
-    ca.m = m;
-    ca.gx = h->gx;
-    ca.gy = h->gy;
-    ca.diag = h->diag;
-    ca.b = h->rhs;
-    ca.x = h->cg_x;
-    ca.gr = h->cg_r;
-    ca.gw = h->cg_w;
-    ca.gp = h->cg_p;
-    ca.gs = h->cg_s;
-    ca.pub = h->cg_pub;
-    ca.part = h->part_a;
-    ca.TB = h->cg_tb;
-    ca.tol2 = h->opt.cg_tol * h->opt.cg_tol;
-    ca.max_iters = h->opt.cg_max_iters;
-    ca.barrier = h->cg_barrier;
-    ca.sc = h->dsc;
-    iugkp::zero_u32_kernel<<<1, 64, 0, h->stream>>>(h->cg_barrier, 2);
-    HIP_TRY(hipEventRecord(h->ev[2], h->stream));
-    // every workgroup must be resident for the grid barrier: the cooperative
-    // launch refuses a grid that does not fit instead of letting it hang
-    void *args[] = {&ca};
-    HIP_TRY(hipLaunchCooperativeKernel(cg_kernel_for(h->cg_j), dim3(h->cg_grid),
-                                       dim3(iugkp::kCgThreads), args, h->cg_lds, h->stream));
-    HIP_TRY(hipEventRecord(h->ev[3], h->stream));
-    const int nbe = cdiv(m.n_emit, iugkp::kTree);
-    iugkp::NewtonFinishArgs na{m.n_cells, m.n_emit, h->F, h->V, h->E_half, h->cg_x,
-                               h->ratio, h->E, h->G, h->part, h->gpart, h->dsc};
-    iugkp::newton_finish_kernel<<<nbe, 256, 0, h->stream>>>(na);
-    HIP_TRY(hipGetLastError());
-    iugkp::finish_kernel<<<1, 256, 0, h->stream>>>(h->part, nbc, h->gpart, nbe, first, h->dsc);
-  } else {
-    iugkp::finish_kernel<<<1, 256, 0, h->stream>>>(h->part, nbc, nullptr, 0, first, h->dsc);
-  }
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(h->hsc, h->dsc, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(hipStreamSynchronize(h->stream));
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
-  h->st.ms_march += ms;
-  if (h->opt.newton) {
-    HIP_TRY(hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
-    h->st.ms_cg += ms;
-  }
-  const DevScalars &s = *h->hsc;
-  h->st.flights = s.flights;
-  h->st.segments = s.segments;
-  h->st.crossings = s.crossings;
-  h->st.tot_flights += s.flights;
-  h->st.tot_segments += s.segments;
-  h->st.tot_crossings += s.crossings;
-  if (h->opt.newton) {
-    h->st.cg_iters_last = s.cg_iters;
-    h->st.cg_iters_total += s.cg_iters;
-  }
-  if (first) h->d0 = s.d0;
-  h->res = s.res;
-  h->res_hist.push_back(s.res);
-  h->iter++;
-  h->last_faces = faces != 0;
-  h->st.iters = static_cast<int>(h->iter);
-  h->st.res = h->res;
-  if (h->opt.newton && s.cg_status == -3)
-    return fail(IUGKP_E_DEVICE, "CG grid barrier timed out");
-  if (h->opt.newton && s.cg_status == -6) return fail(IUGKP_E_CG_BREAKDOWN, "CG breakdown");
-  if (h->opt.newton && s.cg_status == -7)
-    return fail(IUGKP_E_CG_NOT_CONVERGED, "CG did not converge within cg_max_iters");
-  if (s.flags & 1) return fail(IUGKP_E_NONFINITE, "non-finite energy");
-  if ((s.flags & 2) || (h->opt.newton && s.gsum > (1ull << 62)))
-    return fail(IUGKP_E_FIXED_OVERFLOW, "emission energy exceeds the fixed-point budget");
-  if (h->iter > 1 && h->res > 1e3) return fail(IUGKP_E_DIVERGED, "residual grew above 1e3");
-  return IUGKP_OK;
-}
-
-__global__ void accumulate_kernel(int n_cells, int n_fx, int n_fy, int F, int reset,
-                                  const double *E, const long long *Phix, const long long *Phiy,
-                                  double *aE, double *ax, double *ay)
-{
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_cells) aE[i] = reset ? E[i] : aE[i] + E[i];
-  if (i < n_fx) {
-    const double v = ldexp(static_cast<double>(Phix[i]), -F);
-    ax[i] = reset ? v : ax[i] + v;
-  }
-  if (i < n_fy) {
-    const double v = ldexp(static_cast<double>(Phiy[i]), -F);
-    ay[i] = reset ? v : ay[i] + v;
-  }
-}
-
-__global__ void output_kernel(int n_cells, int n_fx, int n_fy, double n_avg, int faces,
-                              double t_ref, double cv, double den_x, double den_y,
-                              const double *aE, const double *ax, const double *ay, double *T,
-                              double *qx, double *qy)
-{
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_cells) {
-    const double e = (n_avg > 0.0) ? aE[i] / n_avg : aE[i];
-    T[i] = t_ref + e / cv;
-  }
-  if (qx && i < n_fx) {
-    const double f = (n_avg > 0.0) ? ax[i] / n_avg : ax[i];
-    qx[i] = faces ? f / den_x : 0.0;
-  }
-  if (qy && i < n_fy) {
-    const double f = (n_avg > 0.0) ? ay[i] / n_avg : ay[i];
-    qy[i] = faces ? f / den_y : 0.0;
-  }
-}
-
-int copy_out(void *dst, const void *src, size_t bytes, int kind, hipStream_t s)
-{
-  if (!dst) return IUGKP_OK;
-  HIP_TRY(hipMemcpyAsync(dst, src, bytes,
-                         kind == IUGKP_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                         s));
-  return IUGKP_OK;
-}
-
-int copy_in(void *dst, const void *src, size_t bytes, int kind, hipStream_t s)
-{
-  HIP_TRY(hipMemcpyAsync(dst, src, bytes,
-                         kind == IUGKP_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
-                         s));
-  return IUGKP_OK;
-}
-
-int create_impl(const iugkp_problem *p, const iugkp_options *o, void *stream, iugkp_handle **out)
+// Validate, allocate and initialise one instance on `s`.  multi_cg: also lay
+// out the multi-workgroup CG used by single solves.
+int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, bool multi_cg,
+                   InstHost &ih)
 {
   int rc = check_problem(p);
   if (rc) return rc;
@@ -478,12 +264,10 @@ int create_impl(const iugkp_problem *p, const iugkp_options *o, void *stream, iu
   if (N * static_cast<uint64_t>(ne) > 0xFFFFFFFFull)
     return fail(IUGKP_E_INVALID_ARG, "particles per iteration must stay below 2^32");
 
-  iugkp_handle *h = new iugkp_handle();
-  h->stream = static_cast<hipStream_t>(stream);
-  h->opt = *o;
-  h->block = o->block_size ? o->block_size : 256;
-  h->mem_kind = p->mem_kind;
-  Mesh &m = h->m;
+  ih.opt = *o;
+  ih.mem_kind = p->mem_kind;
+  Inst &d = ih.d;
+  Mesh &m = d.m;
   m.dim = p->dim;
   m.nx = p->nx;
   m.ny = p->ny;
@@ -494,189 +278,402 @@ int create_impl(const iugkp_problem *p, const iugkp_options *o, void *stream, iu
   m.n_fy = (p->dim == 2) ? (p->ny + 1) * p->nx : 0;
   m.dx = p->dx;
   m.dy = p->dy;
-  h->t_ref = p->t_ref;
-  h->cv = p->cv;
-  h->vg = p->vg;
-  h->tau_min = tmin;
-  h->lam_min = p->vg * tmin;
-  h->V = p->dx * p->dy;
-  h->N = static_cast<uint32_t>(N);
-  h->n_particles = static_cast<uint32_t>(N * ne);
-  h->has_null = (tmax != tmin);
-  h->F = scale_exponent(p, tmin, wall, T0);
+  d.t_ref = p->t_ref;
+  d.cv = p->cv;
+  d.tau_min = tmin;
+  d.lam_min = p->vg * tmin;
+  d.V = p->dx * p->dy;
+  d.N = static_cast<uint32_t>(N);
+  d.key0 = static_cast<uint32_t>(o->seed);
+  d.key1 = static_cast<uint32_t>(o->seed >> 32);
+  d.crn = (o->rng_mode == IUGKP_RNG_CRN);
+  d.epoch = o->rng_epoch;
+  d.has_null = (tmax != tmin);
+  d.newton = o->newton ? 1 : 0;
+  d.faces_each = (o->tally_faces == IUGKP_FACES_EVERY);
+  d.faces_out = (o->tally_faces != IUGKP_FACES_OFF);
+  d.final_iter = (o->tally_faces == IUGKP_FACES_FINAL);
+  d.avg_iters = o->avg_iters;
+  d.max_iters = o->max_iters;
+  d.res_tol = o->res_tol;
+  d.tol2 = o->cg_tol * o->cg_tol;
+  d.cg_max = o->cg_max_iters;
+  d.F = scale_exponent(p, tmin, wall, T0);
+  plan_tiles(ih);
 
-  auto bail = [&](int code) {
-    free_handle(h);
-    return code;
-  };
-#define ALLOC(ptr, n)                                                          \
-  if (dalloc(&(ptr), (n)) != hipSuccess) return bail(fail(IUGKP_E_NOMEM, "hipMalloc failed"));
+#define ALLOC(ptr, n) \
+  if (ih.alloc(&(ptr), (n)) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
   const int nbe = cdiv(ne, iugkp::kTree);
-  ALLOC(h->tau, nc);
-  ALLOC(h->ratio, nc);
-  ALLOC(h->E, nc);
-  ALLOC(h->E_half, nc);
-  ALLOC(h->part, nbe);
-  ALLOC(h->G, ne);
-  ALLOC(h->base, ne);
-  ALLOC(h->rem, ne);
-  ALLOC(h->D, nc);
-  ALLOC(h->W, nc);
-  ALLOC(h->Phix, m.n_fx);
-  ALLOC(h->Phiy, m.n_fy);
-  ALLOC(h->B, nb);
-  ALLOC(h->dB, (p->ny + 2) * p->nx);
-  ALLOC(h->acc_E, nc);
-  ALLOC(h->acc_x, m.n_fx);
-  ALLOC(h->acc_y, m.n_fy);
-  ALLOC(h->out_T, nc);
-  ALLOC(h->out_qx, m.n_fx);
-  ALLOC(h->out_qy, m.n_fy);
-  ALLOC(h->dsc, 1);
-  if (hipHostMalloc(reinterpret_cast<void **>(&h->hsc), sizeof(DevScalars)) != hipSuccess)
-    return bail(fail(IUGKP_E_NOMEM, "hipHostMalloc failed"));
-  for (auto &e : h->ev)
-    if (hipEventCreate(&e) != hipSuccess) return bail(fail(IUGKP_E_DEVICE, "hipEventCreate failed"));
+  double *ratio = nullptr;
+  ALLOC(ih.tau, nc);
+  ALLOC(ratio, nc);
+  d.ratio = ratio;
+  ALLOC(d.E, nc);
+  ALLOC(d.E_half, nc);
+  ALLOC(d.part, nbe);
+  ALLOC(d.G, ne);
+  ALLOC(d.base, ne);
+  ALLOC(d.rem, ne);
+  ALLOC(d.D, nc);
+  ALLOC(d.W, nc);
+  ALLOC(d.Phix, m.n_fx);
+  ALLOC(d.Phiy, m.n_fy);
+  ALLOC(d.dB, (p->ny + 2) * p->nx);
+  ALLOC(d.B, nb);
+  ALLOC(d.acc_E, nc);
+  ALLOC(d.acc_x, m.n_fx);
+  ALLOC(d.acc_y, m.n_fy);
+  ALLOC(ih.out_T, nc);
+  ALLOC(ih.out_qx, m.n_fx);
+  ALLOC(ih.out_qy, m.n_fy);
+  ALLOC(d.sc, 1);
   if (o->newton) {
-    ALLOC(h->rhs, nc);
-    ALLOC(h->Dx, nc);
-    ALLOC(h->Dy, nc);
-    ALLOC(h->gx, m.n_fx);
-    ALLOC(h->gy, m.n_fy);
-    ALLOC(h->diag, nc);
-    ALLOC(h->cg_x, nc);
-    ALLOC(h->cg_r, nc);
-    ALLOC(h->cg_w, nc);
-    ALLOC(h->cg_p, nc);
-    ALLOC(h->cg_s, nc);
-    ALLOC(h->cg_pub, 6 * static_cast<size_t>(nc));
-    ALLOC(h->part_a, 4 * static_cast<size_t>(cdiv(nc, iugkp::kTree)));
-    ALLOC(h->gpart, nbe);
-    ALLOC(h->cg_barrier, 2);
+    const int nbt = cdiv(nc, iugkp::kTree);
+    ALLOC(d.rhs, nc);
+    ALLOC(ih.Dx, nc);
+    ALLOC(ih.Dy, nc);
+    ALLOC(ih.gx, m.n_fx);
+    ALLOC(ih.gy, m.n_fy);
+    ALLOC(ih.diag, nc);
+    d.gx = ih.gx;
+    d.gy = ih.gy;
+    d.diag = ih.diag;
+    ALLOC(d.cg_x, nc);
+    ALLOC(d.cg_r, nc);
+    ALLOC(d.cg_w, nc);
+    ALLOC(d.cg_p, nc);
+    ALLOC(d.cg_s, nc);
+    ALLOC(d.cg_part, 2 * static_cast<size_t>(nbt));
+    ALLOC(d.gpart, nbe);
+    if (multi_cg) {
+      ALLOC(ih.cg_pub, 6 * static_cast<size_t>(nc));
+      ALLOC(ih.cg_mpart, 4 * static_cast<size_t>(nbt));
+      ALLOC(ih.cg_barrier, 2);
+    }
   }
 #undef ALLOC
-  hipStream_t s = h->stream;
-  if (copy_in(h->tau, tau.data(), nc * sizeof(double), IUGKP_MEM_HOST, s)) return bail(IUGKP_E_DEVICE);
-  {
-    std::vector<iugkp::TileDesc> tiles;
-    plan_tiles(h, tiles);
-    if (dalloc(&h->tiles, tiles.size()) != hipSuccess) return bail(fail(IUGKP_E_NOMEM, "hipMalloc failed"));
-    if (copy_in(h->tiles, tiles.data(), tiles.size() * sizeof(iugkp::TileDesc), IUGKP_MEM_HOST, s))
-      return bail(IUGKP_E_DEVICE);
-    HIP_TRY(hipStreamSynchronize(s));
-  }
+  HIP_TRY(hipMemcpyAsync(ih.tau, tau.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
   double *dT0 = nullptr;
   if (!T0.empty()) {
-    if (dalloc(&dT0, nc) != hipSuccess) return bail(fail(IUGKP_E_NOMEM, "hipMalloc failed"));
-    if (copy_in(dT0, T0.data(), nc * sizeof(double), IUGKP_MEM_HOST, s)) return bail(IUGKP_E_DEVICE);
+    if (ih.alloc(&dT0, nc) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
+    HIP_TRY(hipMemcpyAsync(dT0, T0.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
   }
-  iugkp::init_cells_kernel<<<cdiv(nc, 256), 256, 0, s>>>(nc, h->cv, h->t_ref, h->tau_min, dT0,
-                                                          h->tau, h->E, h->ratio);
+  iugkp::init_cells_kernel<<<cdiv(nc, 256), 256, 0, s>>>(nc, d.cv, d.t_ref, d.tau_min, dT0,
+                                                          ih.tau, d.E, ratio);
   // wall emission E_w lambda_min A / 4 (cosine-law black walls), computed once
   std::vector<long long> gw(nb);
-  bool ok = true;
   for (int b = 0; b < nb; ++b) {
     const double A = (b < 2 * p->ny) ? p->dy : p->dx;
     const double ew = p->cv * (wall[b] - p->t_ref);
-    const double v = std::ldexp((ew * (h->lam_min * A)) / 4.0, h->F);
-    if (!(std::fabs(v) <= 4611686018427387904.0)) {
-      ok = false;
-      break;
-    }
+    const double v = std::ldexp((ew * (d.lam_min * A)) / 4.0, d.F);
+    if (!(std::fabs(v) <= 4611686018427387904.0))
+      return fail(IUGKP_E_FIXED_OVERFLOW, "wall emission exceeds the fixed-point range");
     gw[b] = static_cast<long long>(std::rint(v));
   }
-  if (!ok) {
-    if (dT0) (void)hipFree(dT0);
-    return bail(fail(IUGKP_E_FIXED_OVERFLOW, "wall emission exceeds the fixed-point range"));
-  }
-  if (copy_in(h->G + nc, gw.data(), nb * sizeof(long long), IUGKP_MEM_HOST, s)) return bail(IUGKP_E_DEVICE);
+  HIP_TRY(hipMemcpyAsync(d.G + nc, gw.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
   int *dflag = nullptr;
-  if (dalloc(&dflag, 1) != hipSuccess) return bail(fail(IUGKP_E_NOMEM, "hipMalloc failed"));
-  (void)hipMemsetAsync(dflag, 0, sizeof(int), s);
-  iugkp::emission_from_E_kernel<<<cdiv(nc, 256), 256, 0, s>>>(nc, h->F, h->V, h->E, h->ratio,
-                                                              h->G, dflag);
+  if (ih.alloc(&dflag, 1) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
+  HIP_TRY(hipMemsetAsync(dflag, 0, sizeof(int), s));
+  iugkp::emission_from_E_kernel<<<cdiv(nc, 256), 256, 0, s>>>(nc, d.F, d.V, d.E, ratio, d.G, dflag);
   if (o->newton) {
     std::vector<double> dxv(nc), dyv(nc);
-    if (p->diff_x) {
-      if ((rc = fetch_host(p->diff_x, nc, p->mem_kind, dxv))) return bail(rc);
-    } else {
+    auto fill = [&](const double *given, double delta, std::vector<double> &out) -> int {
+      if (given) return fetch_host(given, nc, p->mem_kind, out);
       std::map<double, double> cache;
       for (int c = 0; c < nc; ++c) {
         auto it = cache.find(tau[c]);
-        if (it == cache.end()) it = cache.emplace(tau[c], iugkp::d_eff(p->vg * tau[c], p->dx)).first;
-        dxv[c] = it->second;
+        if (it == cache.end()) it = cache.emplace(tau[c], iugkp::d_eff(p->vg * tau[c], delta)).first;
+        out[c] = it->second;
       }
-    }
+      return IUGKP_OK;
+    };
+    if ((rc = fill(p->diff_x, p->dx, dxv))) return rc;
     if (p->dim == 2) {
-      if (p->diff_y) {
-        if ((rc = fetch_host(p->diff_y, nc, p->mem_kind, dyv))) return bail(rc);
-      } else {
-        std::map<double, double> cache;
-        for (int c = 0; c < nc; ++c) {
-          auto it = cache.find(tau[c]);
-          if (it == cache.end()) it = cache.emplace(tau[c], iugkp::d_eff(p->vg * tau[c], p->dy)).first;
-          dyv[c] = it->second;
-        }
-      }
+      if ((rc = fill(p->diff_y, p->dy, dyv))) return rc;
     } else {
       dyv = dxv;
     }
     for (int c = 0; c < nc; ++c)
       if (!(dxv[c] > 0.0) || !std::isfinite(dxv[c]) || !(dyv[c] > 0.0) || !std::isfinite(dyv[c]))
-        return bail(fail(IUGKP_E_INVALID_ARG, "Newton diffusion coefficients must be > 0"));
-    if (copy_in(h->Dx, dxv.data(), nc * sizeof(double), IUGKP_MEM_HOST, s)) return bail(IUGKP_E_DEVICE);
-    if (copy_in(h->Dy, dyv.data(), nc * sizeof(double), IUGKP_MEM_HOST, s)) return bail(IUGKP_E_DEVICE);
+        return fail(IUGKP_E_INVALID_ARG, "Newton diffusion coefficients must be > 0");
+    HIP_TRY(hipMemcpyAsync(ih.Dx, dxv.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ih.Dy, dyv.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     const int nf = std::max(m.n_fx, m.n_fy);
-    iugkp::newton_operator_kernel<<<cdiv(nf, 256), 256, 0, s>>>(m, h->vg, h->tau, h->Dx, h->Dy,
-                                                                 h->gx, h->gy, h->diag);
-    iugkp::newton_diag_kernel<<<cdiv(nc, 256), 256, 0, s>>>(m, h->gx, h->gy, h->diag);
-    // CG layout: at most kCgGridMax resident workgroups (the barrier cost grows
-    // with the number of arrivals), whole 256-cell tree blocks per workgroup,
-    // cell state in registers when four-block passes and LDS staging allow
-    int dev = 0, n_cu = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int nbt = cdiv(nc, iugkp::kTree);
-    int G = std::max(1, std::min(std::min(nbt, kCgGridMax), n_cu));
-    const int TB = cdiv(nbt, G);
-    G = cdiv(nbt, TB);
-    const int passes = cdiv(TB, iugkp::kCgSlices);
-    int J = passes <= 1 ? 1 : passes <= 2 ? 2 : passes <= 4 ? 4 : 0;
-    size_t lds = (static_cast<size_t>(TB) * iugkp::kTree + 2 * static_cast<size_t>(p->nx)) * sizeof(double);
-    if (J > 0 && lds > kCgLdsMax) J = 0;
-    if (J == 0) lds = 2 * static_cast<size_t>(p->nx) * sizeof(double);
-    if (lds > kCgLdsMax) return bail(fail(IUGKP_E_INVALID_ARG, "mesh rows too long for the Newton CG"));
-    int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cg_kernel_for(J), iugkp::kCgThreads, lds));
-    if (per_cu < 1 || G > per_cu * n_cu)
-      return bail(fail(IUGKP_E_DEVICE, "CG workgroups cannot all be resident"));
-    h->cg_grid = G;
-    h->cg_tb = TB;
-    h->cg_j = J;
-    h->cg_lds = lds;
+    iugkp::newton_operator_kernel<<<cdiv(nf, 256), 256, 0, s>>>(m, p->vg, ih.tau, ih.Dx, ih.Dy,
+                                                                 ih.gx, ih.gy, ih.diag);
+    iugkp::newton_diag_kernel<<<cdiv(nc, 256), 256, 0, s>>>(m, ih.gx, ih.gy, ih.diag);
+    if (multi_cg) {
+      // at most kCgGridMax resident workgroups (the barrier cost grows with the
+      // number of arrivals), whole 256-cell tree blocks per workgroup, cell
+      // state in registers when four-block passes and LDS staging allow
+      int dev = 0, n_cu = 0;
+      HIP_TRY(hipGetDevice(&dev));
+      HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+      const int nbt = cdiv(nc, iugkp::kTree);
+      int G = std::max(1, std::min(std::min(nbt, kCgGridMax), n_cu));
+      const int TB = cdiv(nbt, G);
+      G = cdiv(nbt, TB);
+      const int passes = cdiv(TB, iugkp::kCgSlices);
+      int J = passes <= 1 ? 1 : passes <= 2 ? 2 : passes <= 4 ? 4 : 0;
+      size_t lds = (static_cast<size_t>(TB) * iugkp::kTree + 2 * static_cast<size_t>(p->nx)) *
+                   sizeof(double);
+      if (J > 0 && lds > kCgLdsMax) J = 0;
+      if (J == 0) lds = 2 * static_cast<size_t>(p->nx) * sizeof(double);
+      if (lds > kCgLdsMax) return fail(IUGKP_E_INVALID_ARG, "mesh rows too long for the Newton CG");
+      int per_cu = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cg_kernel_for(J),
+                                                           iugkp::kCgThreads, lds));
+      if (per_cu < 1 || G > per_cu * n_cu)
+        return fail(IUGKP_E_DEVICE, "CG workgroups cannot all be resident");
+      ih.cg_grid = G;
+      ih.cg_tb = TB;
+      ih.cg_j = J;
+      ih.cg_lds = lds;
+    }
   }
   std::vector<long long> g(ne);
   int hflag = 0;
-  HIP_TRY(hipMemcpyAsync(g.data(), h->G, ne * sizeof(long long), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(g.data(), d.G, ne * sizeof(long long), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  DevScalars sc0{};
+  // iteration control: nothing to iterate -> straight to the output iterations
+  if (o->max_iters <= 0) {
+    if (o->avg_iters > 0) {
+      sc0.state = 1;
+      sc0.out_left = o->avg_iters;
+      sc0.faces_now = d.faces_out;
+    } else if (d.final_iter) {
+      sc0.state = 1;
+      sc0.out_left = 1;
+      sc0.faces_now = 1;
+    } else {
+      sc0.state = 2;
+    }
+  } else {
+    sc0.faces_now = d.faces_each;
+  }
+  HIP_TRY(hipMemcpyAsync(d.sc, &sc0, sizeof(DevScalars), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (dT0) (void)hipFree(dT0);
-  (void)hipFree(dflag);
   unsigned long long acc = 0;
   for (long long v : g) {
     const unsigned long long a = static_cast<unsigned long long>(v < 0 ? -v : v);
     acc += a;
     if (a > (1ull << 62) || acc > (1ull << 62)) hflag |= 2;
   }
-  if (hflag & 2) return bail(fail(IUGKP_E_FIXED_OVERFLOW, "initial emission exceeds the fixed-point budget"));
-  std::memset(h->hsc, 0, sizeof(DevScalars));
-  HIP_TRY(hipMemcpyAsync(h->dsc, h->hsc, sizeof(DevScalars), hipMemcpyHostToDevice, s));
+  if (hflag & 2) return fail(IUGKP_E_FIXED_OVERFLOW, "initial emission exceeds the fixed-point budget");
+  return IUGKP_OK;
+}
+
+int launch_march(const Inst *d_insts, const TileDesc *d_tiles, int n_tiles, size_t lds, int block,
+                 int faces_mode, int batch, hipStream_t s)
+{
+  switch (block) {
+    case 64: iugkp::march_kernel<64><<<n_tiles, 64, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+    case 128: iugkp::march_kernel<128><<<n_tiles, 128, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+    case 512: iugkp::march_kernel<512><<<n_tiles, 512, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+    case 1024: iugkp::march_kernel<1024><<<n_tiles, 1024, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+    default: iugkp::march_kernel<256><<<n_tiles, 256, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+  }
+  HIP_TRY(hipGetLastError());
+  return IUGKP_OK;
+}
+
+__global__ void output_kernel(int n_cells, int n_fx, int n_fy, double n_avg, int faces,
+                              double t_ref, double cv, double den_x, double den_y,
+                              const double *aE, const double *ax, const double *ay, double *T,
+                              double *qx, double *qy)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_cells) {
+    const double e = (n_avg > 0.0) ? aE[i] / n_avg : aE[i];
+    T[i] = t_ref + e / cv;
+  }
+  if (qx && i < n_fx) {
+    const double f = (n_avg > 0.0) ? ax[i] / n_avg : ax[i];
+    qx[i] = faces ? f / den_x : 0.0;
+  }
+  if (qy && i < n_fy) {
+    const double f = (n_avg > 0.0) ? ay[i] / n_avg : ay[i];
+    qy[i] = faces ? f / den_y : 0.0;
+  }
+}
+
+// T = t_ref + E / cv and q = flux / (A tau_min) from the output accumulators.
+int write_outputs(const InstHost &ih, double n_avg, double *T_out, double *qx_out, double *qy_out,
+                  hipStream_t s)
+{
+  const Inst &d = ih.d;
+  const Mesh &m = d.m;
+  const int nmax = std::max(std::max(m.n_cells, m.n_fx), m.n_fy);
+  const bool dev = (ih.mem_kind == IUGKP_MEM_DEVICE);
+  double *T = dev ? T_out : ih.out_T;
+  double *qx = qx_out ? (dev ? qx_out : ih.out_qx) : nullptr;
+  double *qy = (qy_out && m.n_fy) ? (dev ? qy_out : ih.out_qy) : nullptr;
+  output_kernel<<<cdiv(nmax, 256), 256, 0, s>>>(m.n_cells, m.n_fx, m.n_fy, n_avg, d.faces_out,
+                                               d.t_ref, d.cv, m.dy * d.tau_min, m.dx * d.tau_min,
+                                               d.acc_E, d.acc_x, d.acc_y, T, qx, qy);
+  HIP_TRY(hipGetLastError());
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(T_out, ih.out_T, m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (qx_out)
+      HIP_TRY(hipMemcpyAsync(qx_out, ih.out_qx, m.n_fx * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (qy_out && m.n_fy)
+      HIP_TRY(hipMemcpyAsync(qy_out, ih.out_qy, m.n_fy * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  return IUGKP_OK;
+}
+
+int copy_out(void *dst, const void *src, size_t bytes, int kind, hipStream_t s)
+{
+  if (!dst) return IUGKP_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes,
+                         kind == IUGKP_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                         s));
+  return IUGKP_OK;
+}
+
+int copy_in(void *dst, const void *src, size_t bytes, int kind, hipStream_t s)
+{
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes,
+                         kind == IUGKP_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                         s));
+  return IUGKP_OK;
+}
+
+int upload_inst(const InstHost &ih, int inst_index, Inst *d_inst, TileDesc *d_tiles, int tile0,
+                hipStream_t s)
+{
+  std::vector<TileDesc> t = ih.tiles;
+  for (auto &x : t) x.inst = inst_index;
+  HIP_TRY(hipMemcpyAsync(d_inst + inst_index, &ih.d, sizeof(Inst), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_tiles + tile0, t.data(), t.size() * sizeof(TileDesc),
+                         hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  h->st.fixed_point_F = h->F;
-  h->st.n_per_emitter = h->N;
-  h->st.n_emitters = ne;
-  *out = h;
+  return IUGKP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// single solves
+// ---------------------------------------------------------------------------
+struct iugkp_handle {
+  hipStream_t stream = nullptr;
+  InstHost ih;
+  Inst *d_inst = nullptr;
+  TileDesc *d_tiles = nullptr;
+  int n_tiles = 0;
+  int block = 256;
+  DevScalars *hsc = nullptr;   // pinned host mirror
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint32_t iter = 0;
+  double d0 = 0.0, res = 0.0;
+  std::vector<double> res_hist;
+  iugkp_stats st{};
+};
+
+namespace {
+
+void free_handle(iugkp_handle *h)
+{
+  if (!h) return;
+  h->ih.release();
+  if (h->d_inst) (void)hipFree(h->d_inst);
+  if (h->d_tiles) (void)hipFree(h->d_tiles);
+  if (h->hsc) (void)hipHostFree(h->hsc);
+  for (auto &e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete h;
+}
+
+// One iteration on the handle's stream; leaves the new scalars in h->hsc.
+int iterate(iugkp_handle *h, int faces)
+{
+  const InstHost &ih = h->ih;
+  const Mesh &m = ih.d.m;
+  hipStream_t s = h->stream;
+  const int nprep = std::max(std::max(std::max(m.n_emit, m.n_fx), std::max(m.n_fy, m.n_cells)),
+                             (m.ny + 2) * m.nx);
+  iugkp::prepare_kernel<<<dim3(cdiv(nprep, 256), 1), 256, 0, s>>>(h->d_inst, faces, 0);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(h->ev[0], s));
+  int rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, ih.lds_bytes, h->block, faces, 0, s);
+  if (rc) return rc;
+  HIP_TRY(hipEventRecord(h->ev[1], s));
+  if (faces) {
+    iugkp::reconstruct_y_kernel<<<dim3(cdiv(m.nx, 256), 1), 256, 0, s>>>(h->d_inst, faces, 0);
+    iugkp::reconstruct_x_kernel<<<dim3(cdiv(m.ny, 256), 1), 256, 0, s>>>(h->d_inst, faces, 0);
+  }
+  const int nbc = cdiv(m.n_cells, iugkp::kTree);
+  iugkp::update_kernel<<<dim3(nbc, 1), 256, 0, s>>>(h->d_inst, 0);
+  HIP_TRY(hipGetLastError());
+  if (ih.d.newton) {
+    iugkp::CGArgs ca;
+    ca.m = m;
+    ca.gx = ih.gx;
+    ca.gy = ih.gy;
+    ca.diag = ih.diag;
+    ca.b = ih.d.rhs;
+    ca.x = ih.d.cg_x;
+    ca.gr = ih.d.cg_r;
+    ca.gw = ih.d.cg_w;
+    ca.gp = ih.d.cg_p;
+    ca.gs = ih.d.cg_s;
+    ca.pub = ih.cg_pub;
+    ca.part = ih.cg_mpart;
+    ca.TB = ih.cg_tb;
+    ca.tol2 = ih.d.tol2;
+    ca.max_iters = ih.d.cg_max;
+    ca.barrier = ih.cg_barrier;
+    ca.sc = ih.d.sc;
+    iugkp::zero_u32_kernel<<<1, 64, 0, s>>>(ih.cg_barrier, 2);
+    HIP_TRY(hipEventRecord(h->ev[2], s));
+    // every workgroup must be resident for the grid barrier: the cooperative
+    // launch refuses a grid that does not fit instead of letting it hang
+    void *args[] = {&ca};
+    HIP_TRY(hipLaunchCooperativeKernel(cg_kernel_for(ih.cg_j), dim3(ih.cg_grid),
+                                       dim3(iugkp::kCgThreads), args, ih.cg_lds, s));
+    HIP_TRY(hipEventRecord(h->ev[3], s));
+    const int nbe = cdiv(m.n_emit, iugkp::kTree);
+    iugkp::newton_finish_kernel<<<dim3(nbe, 1), 256, 0, s>>>(h->d_inst, 0);
+  }
+  iugkp::finish_kernel<<<1, 256, 0, s>>>(h->d_inst, 0);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h->hsc, ih.d.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+  h->st.ms_march += ms;
+  if (ih.d.newton) {
+    HIP_TRY(hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
+    h->st.ms_cg += ms;
+  }
+  const DevScalars &sc = *h->hsc;
+  h->st.flights = sc.flights;
+  h->st.segments = sc.segments;
+  h->st.crossings = sc.crossings;
+  h->st.tot_flights = sc.tot_flights;
+  h->st.tot_segments = sc.tot_segments;
+  h->st.tot_crossings = sc.tot_crossings;
+  if (ih.d.newton) {
+    h->st.cg_iters_last = sc.cg_iters;
+    h->st.cg_iters_total = sc.cg_iters_total;
+  }
+  h->iter = sc.iter;
+  h->d0 = sc.d0;
+  h->res = sc.res;
+  h->res_hist.push_back(sc.res);
+  h->st.iters = static_cast<int>(h->iter);
+  h->st.res = h->res;
+  if (ih.d.newton && sc.cg_status == -3) return fail(IUGKP_E_DEVICE, "CG grid barrier timed out");
+  if (ih.d.newton && sc.cg_status == -6) return fail(IUGKP_E_CG_BREAKDOWN, "CG breakdown");
+  if (ih.d.newton && sc.cg_status == -7)
+    return fail(IUGKP_E_CG_NOT_CONVERGED, "CG did not converge within cg_max_iters");
+  if (sc.flags & 1) return fail(IUGKP_E_NONFINITE, "non-finite energy");
+  if ((sc.flags & 2) || (ih.d.newton && sc.gsum > (1ull << 62)))
+    return fail(IUGKP_E_FIXED_OVERFLOW, "emission energy exceeds the fixed-point budget");
+  if (h->iter > 1 && h->res > 1e3) return fail(IUGKP_E_DIVERGED, "residual grew above 1e3");
   return IUGKP_OK;
 }
 
@@ -689,7 +686,35 @@ int iugkp_create(const iugkp_problem *problem, const iugkp_options *options, voi
 {
   if (!out) return fail(IUGKP_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  return create_impl(problem, options, stream, out);
+  iugkp_handle *h = new iugkp_handle();
+  h->stream = static_cast<hipStream_t>(stream);
+  int rc = setup_instance(problem, options, h->stream, true, h->ih);
+  if (rc) {
+    free_handle(h);
+    return rc;
+  }
+  h->block = options->block_size ? options->block_size : 256;
+  h->n_tiles = static_cast<int>(h->ih.tiles.size());
+  if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), sizeof(Inst)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&h->d_tiles), h->n_tiles * sizeof(TileDesc)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&h->hsc), sizeof(DevScalars)) != hipSuccess) {
+    free_handle(h);
+    return fail(IUGKP_E_NOMEM, "allocation failed");
+  }
+  for (auto &e : h->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      free_handle(h);
+      return fail(IUGKP_E_DEVICE, "hipEventCreate failed");
+    }
+  if ((rc = upload_inst(h->ih, 0, h->d_inst, h->d_tiles, 0, h->stream))) {
+    free_handle(h);
+    return rc;
+  }
+  h->st.fixed_point_F = h->ih.d.F;
+  h->st.n_per_emitter = h->ih.d.N;
+  h->st.n_emitters = h->ih.d.m.n_emit;
+  *out = h;
+  return IUGKP_OK;
 }
 
 void iugkp_destroy(iugkp_handle *h)
@@ -711,76 +736,61 @@ int iugkp_step_faces(iugkp_handle *h, int n_iters, int faces)
 int iugkp_step(iugkp_handle *h, int n_iters)
 {
   if (!h) return fail(IUGKP_E_INVALID_ARG, "handle is NULL");
-  return iugkp_step_faces(h, n_iters, h->opt.tally_faces == IUGKP_FACES_EVERY);
+  return iugkp_step_faces(h, n_iters, h->ih.d.faces_each);
 }
 
 int iugkp_solve(iugkp_handle *h, double *T_out, double *qx_out, double *qy_out,
                 iugkp_stats *stats)
 {
   if (!h || !T_out) return fail(IUGKP_E_INVALID_ARG, "bad handle or T_out");
-  const Mesh &m = h->m;
-  const int faces_each = (h->opt.tally_faces == IUGKP_FACES_EVERY);
+  const Inst &d = h->ih.d;
+  const Mesh &m = d.m;
+  hipStream_t s = h->stream;
   bool converged = false;
   int rc;
-  while (static_cast<int>(h->iter) < h->opt.max_iters) {
-    if ((rc = iterate(h, faces_each))) return rc;
-    if (h->res < h->opt.res_tol) {
+  while (static_cast<int>(h->iter) < d.max_iters) {
+    if ((rc = iterate(h, d.faces_each))) return rc;
+    if (h->res < d.res_tol) {
       converged = true;
       break;
     }
   }
-  const int faces_out = (h->opt.tally_faces != IUGKP_FACES_OFF);
   const int nmax = std::max(std::max(m.n_cells, m.n_fx), m.n_fy);
-  const int grid = cdiv(nmax, 256);
+  const dim3 grid(cdiv(nmax, 256), 1);
   double n_avg = 0.0;
-  if (h->opt.avg_iters > 0) {
-    for (int a = 0; a < h->opt.avg_iters; ++a) {
-      if ((rc = iterate(h, faces_out))) return rc;
-      accumulate_kernel<<<grid, 256, 0, h->stream>>>(m.n_cells, m.n_fx, m.n_fy, h->F, a == 0,
-                                                    h->E, h->Phix, h->Phiy, h->acc_E, h->acc_x,
-                                                    h->acc_y);
+  if (d.avg_iters > 0) {
+    for (int a = 0; a < d.avg_iters; ++a) {
+      if ((rc = iterate(h, d.faces_out))) return rc;
+      iugkp::accumulate_kernel<<<grid, 256, 0, s>>>(h->d_inst, 0, a == 0 ? 2 : 1);
     }
-    n_avg = static_cast<double>(h->opt.avg_iters);
+    n_avg = static_cast<double>(d.avg_iters);
   } else {
-    if (h->opt.tally_faces == IUGKP_FACES_FINAL && (rc = iterate(h, 1))) return rc;
-    accumulate_kernel<<<grid, 256, 0, h->stream>>>(m.n_cells, m.n_fx, m.n_fy, h->F, 1, h->E,
-                                                  h->Phix, h->Phiy, h->acc_E, h->acc_x, h->acc_y);
+    if (d.final_iter && (rc = iterate(h, 1))) return rc;
+    iugkp::accumulate_kernel<<<grid, 256, 0, s>>>(h->d_inst, 0, 2);
   }
-  const bool dev = (h->mem_kind == IUGKP_MEM_DEVICE);
-  double *T = dev ? T_out : h->out_T;
-  double *qx = qx_out ? (dev ? qx_out : h->out_qx) : nullptr;
-  double *qy = (qy_out && m.n_fy) ? (dev ? qy_out : h->out_qy) : nullptr;
-  output_kernel<<<grid, 256, 0, h->stream>>>(m.n_cells, m.n_fx, m.n_fy, n_avg, faces_out, h->t_ref,
-                                            h->cv, m.dy * h->tau_min, m.dx * h->tau_min, h->acc_E,
-                                            h->acc_x, h->acc_y, T, qx, qy);
   HIP_TRY(hipGetLastError());
-  if (!dev) {
-    HIP_TRY(hipMemcpyAsync(T_out, h->out_T, m.n_cells * sizeof(double), hipMemcpyDeviceToHost,
-                           h->stream));
-    if (qx_out)
-      HIP_TRY(hipMemcpyAsync(qx_out, h->out_qx, m.n_fx * sizeof(double), hipMemcpyDeviceToHost,
-                             h->stream));
-    if (qy_out && m.n_fy)
-      HIP_TRY(hipMemcpyAsync(qy_out, h->out_qy, m.n_fy * sizeof(double), hipMemcpyDeviceToHost,
-                             h->stream));
-  }
-  HIP_TRY(hipStreamSynchronize(h->stream));
+  if ((rc = write_outputs(h->ih, n_avg, T_out, qx_out, qy_out, s))) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  h->st.status = converged ? IUGKP_OK : IUGKP_W_NOT_CONVERGED;
   if (stats) *stats = h->st;
-  return converged ? IUGKP_OK : IUGKP_W_NOT_CONVERGED;
+  return h->st.status;
 }
 
 int iugkp_get_tallies(iugkp_handle *h, int64_t *D, int64_t *W, int64_t *Phi_x, int64_t *Phi_y,
                       int64_t *B)
 {
   if (!h) return fail(IUGKP_E_INVALID_ARG, "handle is NULL");
-  const Mesh &m = h->m;
+  const Inst &d = h->ih.d;
+  const Mesh &m = d.m;
+  const int k = h->ih.mem_kind;
+  hipStream_t s = h->stream;
   int rc;
-  if ((rc = copy_out(D, h->D, m.n_cells * 8, h->mem_kind, h->stream))) return rc;
-  if ((rc = copy_out(W, h->has_null ? h->W : h->D, m.n_cells * 8, h->mem_kind, h->stream))) return rc;
-  if ((rc = copy_out(Phi_x, h->Phix, m.n_fx * 8, h->mem_kind, h->stream))) return rc;
-  if (m.n_fy && (rc = copy_out(Phi_y, h->Phiy, m.n_fy * 8, h->mem_kind, h->stream))) return rc;
-  if ((rc = copy_out(B, h->B, m.n_b * 8, h->mem_kind, h->stream))) return rc;
-  HIP_TRY(hipStreamSynchronize(h->stream));
+  if ((rc = copy_out(D, d.D, m.n_cells * 8, k, s))) return rc;
+  if ((rc = copy_out(W, d.has_null ? d.W : d.D, m.n_cells * 8, k, s))) return rc;
+  if ((rc = copy_out(Phi_x, d.Phix, m.n_fx * 8, k, s))) return rc;
+  if (m.n_fy && (rc = copy_out(Phi_y, d.Phiy, m.n_fy * 8, k, s))) return rc;
+  if ((rc = copy_out(B, d.B, m.n_b * 8, k, s))) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
   return IUGKP_OK;
 }
 
@@ -789,9 +799,10 @@ int iugkp_get_state(iugkp_handle *h, uint32_t *iter, double *d0, double *E, int6
   if (!h) return fail(IUGKP_E_INVALID_ARG, "handle is NULL");
   if (iter) *iter = h->iter;
   if (d0) *d0 = h->d0;
+  const Inst &d = h->ih.d;
   int rc;
-  if ((rc = copy_out(E, h->E, h->m.n_cells * 8, h->mem_kind, h->stream))) return rc;
-  if ((rc = copy_out(G, h->G, h->m.n_emit * 8, h->mem_kind, h->stream))) return rc;
+  if ((rc = copy_out(E, d.E, d.m.n_cells * 8, h->ih.mem_kind, h->stream))) return rc;
+  if ((rc = copy_out(G, d.G, d.m.n_emit * 8, h->ih.mem_kind, h->stream))) return rc;
   HIP_TRY(hipStreamSynchronize(h->stream));
   return IUGKP_OK;
 }
@@ -799,9 +810,10 @@ int iugkp_get_state(iugkp_handle *h, uint32_t *iter, double *d0, double *E, int6
 int iugkp_set_state(iugkp_handle *h, uint32_t iter, double d0, const double *E, const int64_t *G)
 {
   if (!h || !E || !G) return fail(IUGKP_E_INVALID_ARG, "bad arguments");
-  const Mesh &m = h->m;
+  const Inst &d = h->ih.d;
+  const Mesh &m = d.m;
   std::vector<long long> g(m.n_emit);
-  if (h->mem_kind == IUGKP_MEM_HOST) {
+  if (h->ih.mem_kind == IUGKP_MEM_HOST) {
     std::memcpy(g.data(), G, m.n_emit * 8);
   } else {
     HIP_TRY(hipMemcpy(g.data(), G, m.n_emit * 8, hipMemcpyDeviceToHost));
@@ -814,11 +826,13 @@ int iugkp_set_state(iugkp_handle *h, uint32_t iter, double d0, const double *E, 
       return fail(IUGKP_E_FIXED_OVERFLOW, "restored emission exceeds the fixed-point budget");
   }
   int rc;
-  if ((rc = copy_in(h->E, E, m.n_cells * 8, h->mem_kind, h->stream))) return rc;
-  HIP_TRY(hipMemcpyAsync(h->G, g.data(), m.n_emit * 8, hipMemcpyHostToDevice, h->stream));
+  if ((rc = copy_in(d.E, E, m.n_cells * 8, h->ih.mem_kind, h->stream))) return rc;
+  HIP_TRY(hipMemcpyAsync(d.G, g.data(), m.n_emit * 8, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(h->hsc, d.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->hsc->iter = iter;
   h->hsc->d0 = d0;
-  HIP_TRY(hipMemcpyAsync(&h->dsc->d0, &h->hsc->d0, sizeof(double), hipMemcpyHostToDevice,
-                         h->stream));
+  HIP_TRY(hipMemcpyAsync(d.sc, h->hsc, sizeof(DevScalars), hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->iter = iter;
   h->d0 = d0;
@@ -867,8 +881,7 @@ int iugkp_dev_philox(const uint32_t *ctr, uint32_t key0, uint32_t key1, uint32_t
 {
   if (!ctr || !out || n < 0) return fail(IUGKP_E_INVALID_ARG, "bad arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (n > 0)
-    iugkp::philox_probe_kernel<<<cdiv(n, 256), 256, 0, s>>>(ctr, key0, key1, out, n);
+  if (n > 0) iugkp::philox_probe_kernel<<<cdiv(n, 256), 256, 0, s>>>(ctr, key0, key1, out, n);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   return IUGKP_OK;
@@ -891,9 +904,61 @@ int iugkp_dev_math(int op, const double *x, const double *y, double *out, int64_
 // batched solves
 // ---------------------------------------------------------------------------
 struct iugkp_batch {
-  std::vector<iugkp_handle *> h;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;      // the caller's stream
+  hipStream_t own = nullptr;         // capture/replay stream (the legacy default stream cannot be captured)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<InstHost> insts;
+  Inst *d_insts = nullptr;
+  TileDesc *d_tiles = nullptr;
+  int n_tiles = 0;
+  size_t lds_max = 0;
+  int any_newton = 0;
+  int max_prep = 1, max_nx = 1, max_ny = 1, max_nbc = 1, max_nbe = 1, max_out = 1;
+  DevScalars *hsc = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool solved = false;
 };
+
+namespace {
+
+void free_batch(iugkp_batch *b)
+{
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto &ih : b->insts) ih.release();
+  if (b->d_insts) (void)hipFree(b->d_insts);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->hsc) (void)hipHostFree(b->hsc);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->own) (void)hipStreamDestroy(b->own);
+  delete b;
+}
+
+// The per-iteration sequence of a batch; every kernel skips finished instances.
+int enqueue_batch_iteration(iugkp_batch *b)
+{
+  hipStream_t s = b->own;
+  const int n = static_cast<int>(b->insts.size());
+  iugkp::prepare_kernel<<<dim3(cdiv(b->max_prep, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
+  int rc = launch_march(b->d_insts, b->d_tiles, b->n_tiles, b->lds_max, 256, -1, 1, s);
+  if (rc) return rc;
+  iugkp::reconstruct_y_kernel<<<dim3(cdiv(b->max_nx, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
+  iugkp::reconstruct_x_kernel<<<dim3(cdiv(b->max_ny, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
+  iugkp::update_kernel<<<dim3(b->max_nbc, n), 256, 0, s>>>(b->d_insts, 1);
+  if (b->any_newton) {
+    iugkp::cg_wg_kernel<<<n, iugkp::kCgThreads, 0, s>>>(b->d_insts, 1);
+    iugkp::newton_finish_kernel<<<dim3(b->max_nbe, n), 256, 0, s>>>(b->d_insts, 1);
+  }
+  iugkp::finish_kernel<<<n, 256, 0, s>>>(b->d_insts, 1);
+  iugkp::accumulate_kernel<<<dim3(cdiv(b->max_out, 256), n), 256, 0, s>>>(b->d_insts, 1, -1);
+  HIP_TRY(hipGetLastError());
+  return IUGKP_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -904,15 +969,61 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
   *out = nullptr;
   iugkp_batch *b = new iugkp_batch();
   b->stream = static_cast<hipStream_t>(stream);
+  b->insts.resize(n);
+  int mem_kind = -1;
   for (int i = 0; i < n; ++i) {
-    iugkp_handle *h = nullptr;
-    const int rc = create_impl(problems[i], options[i], stream, &h);
+    if (!problems[i] || !options[i]) {
+      free_batch(b);
+      return fail(IUGKP_E_INVALID_ARG, "NULL problem or options in the batch");
+    }
+    if (mem_kind < 0) mem_kind = problems[i]->mem_kind;
+    if (problems[i]->mem_kind != mem_kind) {
+      free_batch(b);
+      return fail(IUGKP_E_INVALID_ARG, "all problems of a batch must use the same mem_kind");
+    }
+    const int rc = setup_instance(problems[i], options[i], b->stream, false, b->insts[i]);
     if (rc) {
-      for (auto *x : b->h) free_handle(x);
-      delete b;
+      free_batch(b);
       return rc;
     }
-    b->h.push_back(h);
+    const InstHost &ih = b->insts[i];
+    const Mesh &m = ih.d.m;
+    b->n_tiles += static_cast<int>(ih.tiles.size());
+    b->lds_max = std::max(b->lds_max, ih.lds_bytes);
+    b->any_newton |= ih.d.newton;
+    b->max_prep = std::max({b->max_prep, m.n_emit, m.n_fx, m.n_fy, m.n_cells, (m.ny + 2) * m.nx});
+    b->max_nx = std::max(b->max_nx, m.nx);
+    b->max_ny = std::max(b->max_ny, m.ny);
+    b->max_nbc = std::max(b->max_nbc, cdiv(m.n_cells, iugkp::kTree));
+    b->max_nbe = std::max(b->max_nbe, cdiv(m.n_emit, iugkp::kTree));
+    b->max_out = std::max({b->max_out, m.n_cells, m.n_fx, m.n_fy});
+  }
+  if (hipMalloc(reinterpret_cast<void **>(&b->d_insts), n * sizeof(Inst)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&b->d_tiles), b->n_tiles * sizeof(TileDesc)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&b->hsc), n * sizeof(DevScalars)) != hipSuccess) {
+    free_batch(b);
+    return fail(IUGKP_E_NOMEM, "allocation failed");
+  }
+  if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+    free_batch(b);
+    return fail(IUGKP_E_DEVICE, "stream or event creation failed");
+  }
+  // the largest instances first in the tile table, so their workgroups start early
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return b->insts[a].tiles.size() * b->insts[a].d.N > b->insts[c].tiles.size() * b->insts[c].d.N;
+  });
+  int tile0 = 0;
+  for (int i : order) {
+    const int rc = upload_inst(b->insts[i], i, b->d_insts, b->d_tiles, tile0, b->stream);
+    if (rc) {
+      free_batch(b);
+      return rc;
+    }
+    tile0 += static_cast<int>(b->insts[i].tiles.size());
   }
   *out = b;
   return IUGKP_OK;
@@ -922,21 +1033,88 @@ int iugkp_batch_solve(iugkp_batch *b, double *const *T_out, double *const *qx_ou
                       double *const *qy_out, iugkp_stats *stats)
 {
   if (!b || !T_out) return fail(IUGKP_E_INVALID_ARG, "bad batch arguments");
-  int worst = IUGKP_OK;
-  for (size_t i = 0; i < b->h.size(); ++i) {
-    const int rc = iugkp_solve(b->h[i], T_out[i], qx_out ? qx_out[i] : nullptr,
-                               qy_out ? qy_out[i] : nullptr, stats ? &stats[i] : nullptr);
-    if (rc < 0) return rc;
-    if (rc > 0) worst = rc;
+  if (b->solved) return fail(IUGKP_E_INVALID_ARG, "a batch is solved once");
+  const int n = static_cast<int>(b->insts.size());
+  hipStream_t s = b->own;
+  for (int i = 0; i < n; ++i)
+    if (!T_out[i]) return fail(IUGKP_E_INVALID_ARG, "T_out entries must not be NULL");
+  // the batch stream starts after everything already queued on the caller's stream
+  HIP_TRY(hipEventRecord(b->ev_in, b->stream));
+  HIP_TRY(hipStreamWaitEvent(s, b->ev_in, 0));
+  // capture one iteration of the whole batch, replay until every instance is done
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_batch_iteration(b);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(s, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
   }
+  HIP_TRY(ce);
+  b->graph = g;
+  HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  int cap = 0;
+  for (const auto &ih : b->insts) cap = std::max(cap, ih.d.max_iters + ih.d.avg_iters + 2);
+  for (int it = 0; it <= cap; ++it) {
+    for (int i = 0; i < n; ++i)
+      HIP_TRY(hipMemcpyAsync(&b->hsc[i], b->insts[i].d.sc, sizeof(DevScalars),
+                             hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    bool all_done = true;
+    for (int i = 0; i < n; ++i) all_done = all_done && (b->hsc[i].state == 2);
+    if (all_done) break;
+    HIP_TRY(hipGraphLaunch(b->exec, s));
+  }
+  int worst = IUGKP_OK;
+  for (int i = 0; i < n; ++i) {
+    const InstHost &ih = b->insts[i];
+    const DevScalars &sc = b->hsc[i];
+    int status = IUGKP_OK;
+    if (sc.state != 2) status = IUGKP_E_DEVICE;       // iteration cap of the replay loop
+    else if (sc.err < 0) status = sc.err;
+    else if (!sc.converged) status = IUGKP_W_NOT_CONVERGED;
+    if (status < 0) {
+      if (worst >= 0 || status < worst) worst = status;
+    } else if (status > 0 && worst == IUGKP_OK) {
+      worst = status;
+    }
+    if (status >= 0) {
+      const double n_avg = ih.d.avg_iters > 0 ? static_cast<double>(ih.d.avg_iters) : 0.0;
+      if ((rc = write_outputs(ih, n_avg, T_out[i], qx_out ? qx_out[i] : nullptr,
+                              qy_out ? qy_out[i] : nullptr, s)))
+        return rc;
+    }
+    if (stats) {
+      iugkp_stats &st = stats[i];
+      st = iugkp_stats{};
+      st.status = status;
+      st.iters = static_cast<int>(sc.iter);
+      st.res = sc.res;
+      st.flights = sc.flights;
+      st.segments = sc.segments;
+      st.crossings = sc.crossings;
+      st.tot_flights = sc.tot_flights;
+      st.tot_segments = sc.tot_segments;
+      st.tot_crossings = sc.tot_crossings;
+      st.cg_iters_last = sc.cg_iters;
+      st.cg_iters_total = sc.cg_iters_total;
+      st.fixed_point_F = ih.d.F;
+      st.n_per_emitter = ih.d.N;
+      st.n_emitters = ih.d.m.n_emit;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipEventRecord(b->ev_out, s));
+  HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_out, 0));
+  b->solved = true;
+  if (worst < 0) fail(worst, "at least one instance of the batch failed (see stats[i].status)");
   return worst;
 }
 
 void iugkp_batch_destroy(iugkp_batch *b)
 {
-  if (!b) return;
-  for (auto *h : b->h) iugkp_destroy(h);
-  delete b;
+  if (b && b->stream) (void)hipStreamSynchronize(b->stream);
+  free_batch(b);
 }
 
 }  // extern "C"

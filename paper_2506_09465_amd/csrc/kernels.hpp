@@ -32,17 +32,43 @@ struct Mesh {
   double dx, dy;
 };
 
-struct Tallies {
-  long long *D, *W, *Phix, *Phiy, *B;
-};
-
-// Device-side per-iteration scalars (one struct per solve).
+// Device-side scalars of one solve: the last iteration's counters and norms,
+// and the iteration control used when a batch advances on its own.
 struct DevScalars {
   unsigned long long flights, segments, crossings;
+  unsigned long long tot_flights, tot_segments, tot_crossings;
   unsigned long long gsum;      // saturating sum of |G| (Newton emission budget)
   double dn, d0, res;
   int flags;                    // bit 0: non-finite energy, bit 1: fixed-point overflow
-  int cg_iters, cg_status;
+  int cg_iters, cg_status, cg_iters_total;
+  unsigned int iter;            // iterations done
+  int state;                    // 0 iterating, 1 output iterations, 2 done
+  int out_left;                 // output iterations still to run (state 1)
+  int faces_now;                // face tallies in the next iteration
+  int acc_mode;                 // last iteration feeds the outputs: 0 no, 1 add, 2 restart
+  int converged;
+  int err;                      // first error of the solve (negative code) or 0
+};
+
+// Everything the per-iteration kernels need about one problem instance.
+struct Inst {
+  Mesh m;
+  double lam_min, V, t_ref, cv, tau_min, res_tol, tol2;
+  int F;
+  uint32_t N, key0, key1, epoch;
+  int crn, has_null, newton, faces_each, faces_out, final_iter, avg_iters, max_iters, cg_max;
+  int WX, WY, lds_walls;
+  const double *ratio;
+  double *E, *E_half, *rhs;
+  long long *G, *base;
+  uint32_t *rem;
+  long long *D, *W, *Phix, *Phiy, *dB, *B;
+  double *part;                 // squared-update partials [ceil(n_emit / 256)]
+  unsigned long long *gpart;    // |G| budget partials
+  const double *gx, *gy, *diag;
+  double *cg_x, *cg_r, *cg_w, *cg_p, *cg_s, *cg_part;   // one-workgroup CG state
+  double *acc_E, *acc_x, *acc_y;
+  DevScalars *sc;
 };
 
 // ---------------------------------------------------------------------------
@@ -113,44 +139,59 @@ __device__ double tree_all(const double *part, int n, double *lds, double *lds2)
 }
 
 // ---------------------------------------------------------------------------
-// prepare: zero tallies, per-emitter split, wall emission on the wall faces
+// prepare: zero tallies, per-emitter split, wall emission on the wall faces.
+// Grid (x: elements, y: instance).  faces_mode >= 0 forces the face tallies,
+// -1 takes them from the instance's iteration control; with `batch` set,
+// finished instances are skipped.
 // ---------------------------------------------------------------------------
-__global__ void prepare_kernel(Mesh m, const long long *__restrict__ G, uint32_t N,
-                               long long *__restrict__ base, uint32_t *__restrict__ rem,
-                               Tallies t, long long *__restrict__ dB, int faces, DevScalars *sc)
+__device__ __forceinline__ bool inst_idle(const Inst &in, int batch)
 {
+  return batch && in.sc->state == 2;
+}
+
+__device__ __forceinline__ int inst_faces(const Inst &in, int faces_mode)
+{
+  return faces_mode >= 0 ? faces_mode : in.sc->faces_now;
+}
+
+__global__ void prepare_kernel(const Inst *__restrict__ insts, int faces_mode, int batch)
+{
+  const Inst &in = insts[blockIdx.y];
+  if (inst_idle(in, batch)) return;
+  const Mesh &m = in.m;
+  const int faces = inst_faces(in, faces_mode);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
-    sc->flights = 0;
-    sc->segments = 0;
-    sc->crossings = 0;
-    sc->gsum = 0;
-    sc->flags = 0;
+    in.sc->flights = 0;
+    in.sc->segments = 0;
+    in.sc->crossings = 0;
+    in.sc->gsum = 0;
+    in.sc->flags = 0;
   }
   if (i < m.n_cells) {
-    t.D[i] = 0;
-    t.W[i] = 0;
+    in.D[i] = 0;
+    in.W[i] = 0;
   }
-  if (i < m.n_b) t.B[i] = 0;
+  if (i < m.n_b) in.B[i] = 0;
   if (i < m.n_emit) {
     // floor division of a signed energy by N with a non-negative remainder
-    const long long g = G[i];
-    const long long n = static_cast<long long>(N);
+    const long long g = in.G[i];
+    const long long n = static_cast<long long>(in.N);
     long long b = g / n;
     if (g % n != 0 && g < 0) b -= 1;
-    base[i] = b;
-    rem[i] = static_cast<uint32_t>(g - b * n);
+    in.base[i] = b;
+    in.rem[i] = static_cast<uint32_t>(g - b * n);
   }
-  if (i < m.n_fx) t.Phix[i] = 0;   // rebuilt from the balance when faces are on
-  if (m.dim == 2 && i < (m.ny + 2) * m.nx) dB[i] = 0;
+  if (i < m.n_fx) in.Phix[i] = 0;   // rebuilt from the balance when faces are on
+  if (m.dim == 2 && i < (m.ny + 2) * m.nx) in.dB[i] = 0;
   if (i < m.n_fy) {
     long long v = 0;
     if (faces) {
       const int k = i / m.nx, col = i - k * m.nx;
-      if (k == 0) v = G[m.n_cells + 2 * m.ny + col];
-      else if (k == m.ny) v = -G[m.n_cells + 2 * m.ny + m.nx + col];
+      if (k == 0) v = in.G[m.n_cells + 2 * m.ny + col];
+      else if (k == m.ny) v = -in.G[m.n_cells + 2 * m.ny + m.nx + col];
     }
-    t.Phiy[i] = v;
+    in.Phiy[i] = v;
   }
 }
 
@@ -175,25 +216,11 @@ __global__ void prepare_kernel(Mesh m, const long long *__restrict__ G, uint32_t
 // two updates instead of one per face.
 // ---------------------------------------------------------------------------
 struct TileDesc {
+  int inst;        // instance of the batch
   int kind;        // 0 = cell tile, 1 = wall segment
   int x0, y0;      // cell tile: first cell; wall segment: first wall index in x0
   int ex, ey;      // cell tile: extent; wall segment: face count in ex
   int wx0, wy0;    // window origin (cells)
-};
-
-struct MarchArgs {
-  Mesh m;
-  double lam_min;
-  uint32_t N, slot, key0, key1;
-  int faces, has_null;
-  int WX, WY;            // window size (cells)
-  int lds_walls;         // wall-absorption tally kept in LDS (n_b small enough)
-  const TileDesc *tiles;
-  const long long *base;
-  const uint32_t *rem;
-  const double *ratio;
-  long long *D, *W, *Phiy, *dB, *B;   // dB: [(ny + 2) * nx] column-run differences
-  DevScalars *sc;
 };
 
 __device__ __forceinline__ void atom_add(long long *a, long long v)
@@ -220,15 +247,32 @@ __host__ __device__ inline size_t window_words(int WX, int WY, int has_null, int
 }
 
 template <int BS>
-__global__ __launch_bounds__(BS) void march_kernel(MarchArgs a)
+__global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ insts,
+                                                   const TileDesc *__restrict__ tiles,
+                                                   int faces_mode, int batch)
 {
   extern __shared__ long long lds_words[];
   __shared__ unsigned long long s_cnt[3];
+  const TileDesc td = tiles[blockIdx.x];
+  const Inst &in = insts[td.inst];
+  if (inst_idle(in, batch)) return;
+  struct {
+    Mesh m;
+    double lam_min;
+    uint32_t N, slot, key0, key1;
+    int faces, has_null;
+    const long long *base;
+    const uint32_t *rem;
+    const double *ratio;
+    long long *D, *W, *Phiy, *dB, *B;
+    DevScalars *sc;
+  } a = {in.m, in.lam_min, in.N, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1,
+         inst_faces(in, faces_mode), in.has_null, in.base, in.rem, in.ratio, in.D, in.W,
+         in.Phiy, in.dB, in.B, in.sc};
   const Mesh &m = a.m;
-  const TileDesc td = a.tiles[blockIdx.x];
   Window win;
-  win.WX = a.WX;
-  win.WY = a.WY;
+  win.WX = in.WX;
+  win.WY = in.WY;
   win.wx0 = td.wx0;
   win.wy0 = td.wy0;
   {
@@ -241,9 +285,9 @@ __global__ __launch_bounds__(BS) void march_kernel(MarchArgs a)
     p += win.WX * (win.WY + 1);
     win.dB = p;
     p += win.WX * (win.WY + 2);
-    win.B = a.lds_walls ? p : nullptr;
+    win.B = in.lds_walls ? p : nullptr;
   }
-  const int nwords = static_cast<int>(window_words(win.WX, win.WY, a.has_null, a.lds_walls, m.n_b));
+  const int nwords = static_cast<int>(window_words(win.WX, win.WY, a.has_null, in.lds_walls, m.n_b));
   for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
   if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -447,119 +491,112 @@ __global__ __launch_bounds__(BS) void march_kernel(MarchArgs a)
 //   Phix[j][i+1] = Phix[j][i] + Phiy[j][i] - Phiy[j+1][i] - D[c] + G[c]
 // Integer arithmetic modulo 2^64: exact, since every true value fits in int64.
 // ---------------------------------------------------------------------------
-__global__ void reconstruct_y_kernel(Mesh m, const long long *dB, long long *Phiy)
+__global__ void reconstruct_y_kernel(const Inst *__restrict__ insts, int faces_mode, int batch)
 {
+  const Inst &in = insts[blockIdx.y];
+  if (inst_idle(in, batch) || !inst_faces(in, faces_mode) || in.m.dim != 2) return;
+  const Mesh &m = in.m;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m.nx) return;
   unsigned long long acc = 0;
   for (int k = 0; k <= m.ny; ++k) {
-    acc += static_cast<unsigned long long>(dB[k * m.nx + i]);
-    Phiy[k * m.nx + i] = static_cast<long long>(static_cast<unsigned long long>(Phiy[k * m.nx + i]) + acc);
+    acc += static_cast<unsigned long long>(in.dB[k * m.nx + i]);
+    in.Phiy[k * m.nx + i] =
+        static_cast<long long>(static_cast<unsigned long long>(in.Phiy[k * m.nx + i]) + acc);
   }
 }
 
-__global__ void reconstruct_x_kernel(Mesh m, const long long *G, const long long *D,
-                                     const long long *Phiy, const long long *B, long long *Phix)
+__global__ void reconstruct_x_kernel(const Inst *__restrict__ insts, int faces_mode, int batch)
 {
+  const Inst &in = insts[blockIdx.y];
+  if (inst_idle(in, batch) || !inst_faces(in, faces_mode)) return;
+  const Mesh &m = in.m;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m.ny) return;
-  unsigned long long a = static_cast<unsigned long long>(G[m.n_cells + j]) -
-                         static_cast<unsigned long long>(B[j]);
-  Phix[j * (m.nx + 1)] = static_cast<long long>(a);
+  unsigned long long a = static_cast<unsigned long long>(in.G[m.n_cells + j]) -
+                         static_cast<unsigned long long>(in.B[j]);
+  in.Phix[j * (m.nx + 1)] = static_cast<long long>(a);
   for (int i = 0; i < m.nx; ++i) {
     const int c = j * m.nx + i;
     if (m.dim == 2)
-      a += static_cast<unsigned long long>(Phiy[j * m.nx + i]) -
-           static_cast<unsigned long long>(Phiy[(j + 1) * m.nx + i]);
-    a += static_cast<unsigned long long>(G[c]) - static_cast<unsigned long long>(D[c]);
-    Phix[j * (m.nx + 1) + i + 1] = static_cast<long long>(a);
+      a += static_cast<unsigned long long>(in.Phiy[j * m.nx + i]) -
+           static_cast<unsigned long long>(in.Phiy[(j + 1) * m.nx + i]);
+    a += static_cast<unsigned long long>(in.G[c]) - static_cast<unsigned long long>(in.D[c]);
+    in.Phix[j * (m.nx + 1) + i + 1] = static_cast<long long>(a);
   }
 }
 
 // ---------------------------------------------------------------------------
-// macroscopic update (256-wide blocks, block b owns cells [256 b, 256 b + 256))
-// ---------------------------------------------------------------------------
-struct UpdateArgs {
-  int n_cells, F, has_null, newton;
-  double V;
-  const long long *D, *W;
-  double *E, *E_half, *rhs;
-  long long *G;
-  double *part;         // per-block partial of the squared update (plain path)
-  DevScalars *sc;
-};
-
+// macroscopic update (256-wide blocks; block x owns cells [256 x, 256 x + 256))
 // Plain path: E^{n+1} = E^{n+1/2} = W / V, next emission = D (Sec. 3.2 step (2)).
 // Newton path: E^{n+1/2} and the right-hand side E^{n+1/2} - E^n only.
-__global__ __launch_bounds__(256) void update_kernel(UpdateArgs a)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void update_kernel(const Inst *__restrict__ insts, int batch)
 {
   __shared__ double lds[kTree];
+  const Inst &in = insts[blockIdx.y];
+  if (inst_idle(in, batch)) return;
+  const int nbc = (in.m.n_cells + kTree - 1) / kTree;
+  if (static_cast<int>(blockIdx.x) >= nbc) return;
   const int c = blockIdx.x * kTree + threadIdx.x;
   double sq = 0.0;
   int bad = 0;
-  if (c < a.n_cells) {
-    const long long w = a.has_null ? a.W[c] : a.D[c];
-    const double eh = ldexp(static_cast<double>(w), -a.F) / a.V;
-    a.E_half[c] = eh;
-    if (a.newton) {
-      a.rhs[c] = eh - a.E[c];
+  if (c < in.m.n_cells) {
+    const long long w = in.has_null ? in.W[c] : in.D[c];
+    const double eh = ldexp(static_cast<double>(w), -in.F) / in.V;
+    in.E_half[c] = eh;
+    if (in.newton) {
+      in.rhs[c] = eh - in.E[c];
     } else {
-      const double d = eh - a.E[c];
+      const double d = eh - in.E[c];
       sq = d * d;
       bad = !isfinite(eh);
-      a.E[c] = eh;
-      a.G[c] = a.D[c];
+      in.E[c] = eh;
+      in.G[c] = in.D[c];
     }
   }
-  if (a.newton) return;
-  if (bad) atomicOr(&a.sc->flags, 1);
+  if (in.newton) return;
+  if (bad) atomicOr(&in.sc->flags, 1);
   const double s = block_tree256(sq, lds);
-  if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+  if (threadIdx.x == 0) in.part[blockIdx.x] = s;
 }
-
-struct NewtonFinishArgs {
-  int n_cells, n_emit, F;
-  double V;
-  const double *E_half, *x, *ratio;
-  double *E;
-  long long *G;
-  double *part;
-  unsigned long long *gpart;
-  DevScalars *sc;
-};
 
 // E^{n+1} = E^{n+1/2} + dE, next emission rint(2^F (E^{n+1} V) tau_min / tau_c),
 // squared update partials and the saturating |G| budget partials.
-__global__ __launch_bounds__(256) void newton_finish_kernel(NewtonFinishArgs a)
+__global__ __launch_bounds__(256) void newton_finish_kernel(const Inst *__restrict__ insts,
+                                                            int batch)
 {
   __shared__ double lds[kTree];
   __shared__ unsigned long long lg[kTree];
+  const Inst &in = insts[blockIdx.y];
+  if (inst_idle(in, batch) || !in.newton) return;
+  const int nbe = (in.m.n_emit + kTree - 1) / kTree;
+  if (static_cast<int>(blockIdx.x) >= nbe) return;
   const int c = blockIdx.x * kTree + threadIdx.x;
   double sq = 0.0;
   unsigned long long ag = 0;
   int flags = 0;
-  if (c < a.n_cells) {
-    const double en = a.E_half[c] + a.x[c];
-    const double d = en - a.E[c];
+  if (c < in.m.n_cells) {
+    const double en = in.E_half[c] + in.cg_x[c];
+    const double d = en - in.E[c];
     sq = d * d;
     if (!isfinite(en)) flags |= 1;
-    a.E[c] = en;
-    const double v = ldexp((en * a.V) * a.ratio[c], a.F);
+    in.E[c] = en;
+    const double v = ldexp((en * in.V) * in.ratio[c], in.F);
     if (!(fabs(v) <= 4611686018427387904.0)) {
       flags |= 2;
-      a.G[c] = 0;
+      in.G[c] = 0;
     } else {
       const long long g = static_cast<long long>(rint(v));
-      a.G[c] = g;
+      in.G[c] = g;
       ag = static_cast<unsigned long long>(g < 0 ? -g : g);
     }
   }
-  // wall emitters count toward the budget as well
-  if (c >= a.n_cells && c < a.n_emit) {
-    const long long g = a.G[c];
+  if (c >= in.m.n_cells && c < in.m.n_emit) {   // wall emitters count toward the budget
+    const long long g = in.G[c];
     ag = static_cast<unsigned long long>(g < 0 ? -g : g);
   }
-  if (flags) atomicOr(&a.sc->flags, flags);
+  if (flags) atomicOr(&in.sc->flags, flags);
   const double s = block_tree256(sq, lds);
   lg[threadIdx.x] = ag > kBudgetCap ? kBudgetCap : ag;
   __syncthreads();
@@ -571,32 +608,109 @@ __global__ __launch_bounds__(256) void newton_finish_kernel(NewtonFinishArgs a)
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    a.part[blockIdx.x] = s;
-    a.gpart[blockIdx.x] = lg[0];
+    in.part[blockIdx.x] = s;
+    in.gpart[blockIdx.x] = lg[0];
   }
 }
 
-// Totals of the partials (fixed order), relative residual, budget.
-__global__ __launch_bounds__(256) void finish_kernel(const double *part, int n_part,
-                                                     const unsigned long long *gpart, int n_gpart,
-                                                     int first, DevScalars *sc)
+// Error codes stored in DevScalars::err (same values as the C ABI).
+constexpr int kErrDevice = -3, kErrOverflow = -4, kErrNonfinite = -5, kErrBreakdown = -6,
+              kErrCgNotConverged = -7, kErrDiverged = -8;
+
+// One workgroup per instance: totals of the partials (fixed order), relative
+// residual, counters, status; with `batch` set also the iteration control:
+//   state 0: iterate with faces_each until res < res_tol or max_iters,
+//   then state 1: avg_iters averaged iterations, or one face-tally iteration
+//   in FACES_FINAL mode, or nothing; state 2: done (outputs ready).
+__global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ insts, int batch)
 {
   __shared__ double lds[kTree];
   __shared__ double lds2[kTree];
-  const double dsq = tree_all(part, n_part, lds, lds2);
-  if (threadIdx.x == 0) {
-    unsigned long long g = 0;
-    for (int i = 0; i < n_gpart; ++i) {
-      g += gpart[i];
+  const Inst &in = insts[blockIdx.x];
+  if (inst_idle(in, batch)) {
+    // finished in an earlier replay: nothing more to accumulate
+    if (threadIdx.x == 0) in.sc->acc_mode = 0;
+    return;
+  }
+  DevScalars *sc = in.sc;
+  const int nbc = (in.m.n_cells + kTree - 1) / kTree;
+  const int nbe = (in.m.n_emit + kTree - 1) / kTree;
+  const double dsq = tree_all(in.part, nbc, lds, lds2);
+  if (threadIdx.x != 0) return;
+  unsigned long long g = 0;
+  if (in.newton)
+    for (int i = 0; i < nbe; ++i) {
+      g += in.gpart[i];
       if (g > kBudgetCap) g = kBudgetCap;
     }
-    sc->gsum = g;
-    const double dn = sqrt(dsq);
-    sc->dn = dn;
-    if (first) sc->d0 = dn;
-    const double d0 = sc->d0;
-    sc->res = (d0 > 0.0) ? dn / d0 : 0.0;
+  sc->gsum = g;
+  const double dn = sqrt(dsq);
+  sc->dn = dn;
+  const int first = (sc->iter == 0);
+  if (first) sc->d0 = dn;
+  const double d0 = sc->d0;
+  const double res = (d0 > 0.0) ? dn / d0 : 0.0;
+  sc->res = res;
+  sc->iter += 1;
+  sc->tot_flights += sc->flights;
+  sc->tot_segments += sc->segments;
+  sc->tot_crossings += sc->crossings;
+  if (in.newton) sc->cg_iters_total += sc->cg_iters;
+  if (!batch) return;
+  // error precedence as in the single-solve driver
+  int err = 0;
+  if (in.newton && sc->cg_status == -3) err = kErrDevice;
+  else if (in.newton && sc->cg_status == -6) err = kErrBreakdown;
+  else if (in.newton && sc->cg_status == -7) err = kErrCgNotConverged;
+  else if (sc->flags & 1) err = kErrNonfinite;
+  else if ((sc->flags & 2) || (in.newton && g > (1ull << 62))) err = kErrOverflow;
+  else if (sc->iter > 1 && res > 1e3) err = kErrDiverged;
+  sc->acc_mode = 0;
+  if (err) {
+    sc->err = err;
+    sc->state = 2;
+    return;
   }
+  if (sc->state == 1) {                  // an output iteration just ended
+    sc->acc_mode = (in.avg_iters > 0 && sc->out_left < in.avg_iters) ? 1 : 2;
+    if (--sc->out_left == 0) sc->state = 2;
+    return;
+  }
+  const bool conv = res < in.res_tol;
+  if (!conv && static_cast<int>(sc->iter) < in.max_iters) return;
+  sc->converged = conv ? 1 : 0;
+  if (in.avg_iters > 0) {
+    sc->state = 1;
+    sc->out_left = in.avg_iters;
+    sc->faces_now = in.faces_out;
+  } else if (in.final_iter) {
+    sc->state = 1;
+    sc->out_left = 1;
+    sc->faces_now = 1;
+  } else {
+    sc->state = 2;
+    sc->acc_mode = 2;
+  }
+}
+
+__global__ void accumulate_kernel(const Inst *__restrict__ insts, int batch, int force_mode)
+{
+  const Inst &in = insts[blockIdx.y];
+  const int mode = force_mode >= 0 ? force_mode : in.sc->acc_mode;
+  if (mode == 0) return;
+  const Mesh &m = in.m;
+  const int reset = (mode == 2);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m.n_cells) in.acc_E[i] = reset ? in.E[i] : in.acc_E[i] + in.E[i];
+  if (i < m.n_fx) {
+    const double v = ldexp(static_cast<double>(in.Phix[i]), -in.F);
+    in.acc_x[i] = reset ? v : in.acc_x[i] + v;
+  }
+  if (i < m.n_fy) {
+    const double v = ldexp(static_cast<double>(in.Phiy[i]), -in.F);
+    in.acc_y[i] = reset ? v : in.acc_y[i] + v;
+  }
+  (void)batch;
 }
 
 // Initial cell emission from E (creation / restored state): G = rint(2^F (E V) r).
@@ -758,17 +872,22 @@ struct CellCoef {
   double d, l, r, dn, up;    // diagonal and the four face conductances (0 if absent)
 };
 
-__device__ __forceinline__ CellCoef load_coef(const CGArgs &a, int c)
+__device__ __forceinline__ CellCoef load_coef(const Mesh &m, const double *gx, const double *gy,
+                                              const double *diag, int c)
 {
-  const Mesh &m = a.m;
   const int iy = c / m.nx, ix = c - iy * m.nx;
   CellCoef k;
-  k.d = a.diag[c];
-  k.l = (ix > 0) ? a.gx[iy * (m.nx + 1) + ix] : 0.0;
-  k.r = (ix < m.nx - 1) ? a.gx[iy * (m.nx + 1) + ix + 1] : 0.0;
-  k.dn = (m.dim == 2 && iy > 0) ? a.gy[iy * m.nx + ix] : 0.0;
-  k.up = (m.dim == 2 && iy < m.ny - 1) ? a.gy[(iy + 1) * m.nx + ix] : 0.0;
+  k.d = diag[c];
+  k.l = (ix > 0) ? gx[iy * (m.nx + 1) + ix] : 0.0;
+  k.r = (ix < m.nx - 1) ? gx[iy * (m.nx + 1) + ix + 1] : 0.0;
+  k.dn = (m.dim == 2 && iy > 0) ? gy[iy * m.nx + ix] : 0.0;
+  k.up = (m.dim == 2 && iy < m.ny - 1) ? gy[(iy + 1) * m.nx + ix] : 0.0;
   return k;
+}
+
+__device__ __forceinline__ CellCoef load_coef(const CGArgs &a, int c)
+{
+  return load_coef(a.m, a.gx, a.gy, a.diag, c);
 }
 
 // (A v)_c with the reference operation order: diag v_c - g_l v_{c-1} - g_r v_{c+1}
@@ -1001,6 +1120,99 @@ __global__ __launch_bounds__(kCgThreads) void cg_kernel(CGArgs a)
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.sc->cg_iters = it;
     a.sc->cg_status = status;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same CG for one instance per 1024-thread workgroup (batched solves): the
+// state lives in the instance's global arrays, phases are separated by
+// workgroup barriers, partials go through the instance's cg_part array.
+// Identical recurrences and reduction order, hence identical results.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kCgThreads) void cg_wg_kernel(const Inst *__restrict__ insts, int batch)
+{
+  __shared__ double lds[kCgThreads];
+  __shared__ double lds2[kTree];
+  const Inst &in = insts[blockIdx.x];
+  if (inst_idle(in, batch) || !in.newton) return;
+  const Mesh &m = in.m;
+  const int n = m.n_cells;
+  const int nb = (n + kTree - 1) / kTree;
+  const int npass = (nb + kCgSlices - 1) / kCgSlices;
+  const int sl = threadIdx.x / kTree, t = threadIdx.x & (kTree - 1);
+  double *x = in.cg_x, *r = in.cg_r, *w = in.cg_w, *p = in.cg_p, *sv = in.cg_s;
+  double *pg = in.cg_part, *pd = in.cg_part + nb;
+  auto rget = [&](int c) -> double { return r[c]; };
+  auto spmv_partials = [&]() {
+    for (int j = 0; j < npass; ++j) {
+      const int tb = j * kCgSlices + sl;
+      const int c = tb * kTree + t;
+      double g = 0.0, d = 0.0;
+      if (tb < nb && c < n) {
+        const CellCoef k = load_coef(m, in.gx, in.gy, in.diag, c);
+        const double wv = apply_cell(m, k, c, rget);
+        w[c] = wv;
+        const double rv = r[c];
+        g = rv * rv;
+        d = wv * rv;
+      }
+      g = slice_tree256(g, lds);
+      d = slice_tree256(d, lds);
+      if (t == 0 && tb < nb) {
+        pg[tb] = g;
+        pd[tb] = d;
+      }
+    }
+    __syncthreads();
+  };
+  for (int c = threadIdx.x; c < n; c += kCgThreads) {
+    x[c] = 0.0;
+    r[c] = in.rhs[c];
+  }
+  __syncthreads();
+  spmv_partials();
+  double gamma = tree_all(pg, nb, lds, lds2);
+  double delta = tree_all(pd, nb, lds, lds2);
+  const double thr = in.tol2 * gamma;
+  int status = -7;
+  int it = 0;
+  double alpha = 0.0, beta = 0.0;
+  if (gamma == 0.0) status = 0;
+  else if (!(delta > 0.0)) status = -6;
+  else alpha = gamma / delta;
+  while (status == -7 && it < in.cg_max) {
+    const int first = (it == 0);
+    for (int c = threadIdx.x; c < n; c += kCgThreads) {
+      const double pv = first ? r[c] : r[c] + beta * p[c];
+      const double s_ = first ? w[c] : w[c] + beta * sv[c];
+      p[c] = pv;
+      sv[c] = s_;
+      x[c] = x[c] + alpha * pv;
+      r[c] = r[c] - alpha * s_;
+    }
+    __syncthreads();
+    spmv_partials();
+    ++it;
+    const double gamma_new = tree_all(pg, nb, lds, lds2);
+    delta = tree_all(pd, nb, lds, lds2);
+    if (gamma_new <= thr) {
+      status = 0;
+      break;
+    }
+    beta = gamma_new / gamma;
+    double tq = beta * gamma_new;
+    tq = tq / alpha;
+    const double den = delta - tq;
+    if (!(den > 0.0)) {
+      status = -6;
+      break;
+    }
+    alpha = gamma_new / den;
+    gamma = gamma_new;
+  }
+  if (threadIdx.x == 0) {
+    in.sc->cg_iters = it;
+    in.sc->cg_status = status;
   }
 }
 

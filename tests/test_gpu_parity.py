@@ -248,3 +248,70 @@ def test_newton_cg_layouts_bitwise(oracle_mod, gpu, name):
     assert o.step(2) == 0 and s.step(2) == 0
     _same_iteration(o, s, name)
     assert o.info().cg_iters_total == s.stats()["cg_iters_total"]
+
+
+def _batch_cases():
+    ws = []
+    kw = []
+    w = cavity_2d(n=40, ny=33, kn=0.05, particles=150_000)
+    ws.append(w); kw.append(dict(rng_mode=1, tally_faces=2, newton=True, max_iters=40, res_tol=1e-6))
+    w = cavity_2d(n=17, kn=2.0, particles=40_000, newton=False, seed=5)
+    ws.append(w); kw.append(dict(rng_mode=0, tally_faces=1, newton=False, max_iters=4, res_tol=0.0, avg_iters=3))
+    w = slab_1d(kn=1.0, particles=100_000)
+    ws.append(w); kw.append(dict(rng_mode=1, tally_faces=2, newton=False, max_iters=60, res_tol=1e-6))
+    w = two_material_2d(n=24, kn_right=0.05, ratio=20.0, particles=80_000, seed=9)
+    ws.append(w); kw.append(dict(rng_mode=0, tally_faces=0, newton=True, max_iters=3, res_tol=0.0))
+    w = cavity_2d(n=64, kn=0.003, particles=400_000, seed=2)
+    ws.append(w); kw.append(dict(rng_mode=1, tally_faces=2, newton=True, max_iters=40, res_tol=1e-6))
+    w = cavity_2d(n=9, ny=31, kn=0.5, particles=30_000, newton=False, seed=77)
+    ws.append(w); kw.append(dict(rng_mode=1, tally_faces=1, newton=False, max_iters=0, res_tol=1e-6, avg_iters=2))
+    return ws, kw
+
+
+def test_batch_equals_single_solves(gpu):
+    """The batched driver (one launch per phase for all instances, replayed from
+    a captured graph, one-workgroup CG) gives every instance the bits of its
+    own single solve: same iteration count, T and q."""
+    ws, kws = _batch_cases()
+    singles = []
+    for w, k in zip(ws, kws):
+        s = gpu.Solver(w, **k)
+        rc, T, qx, qy, st = s.solve()
+        singles.append((rc, T, qx, qy, st))
+    bs = gpu.BatchSolver(ws, per_instance=kws)
+    rc, outs = bs.solve()
+    assert rc >= 0
+    for i, ((rc_s, T, qx, qy, sst), (Tb, qxb, qyb, stb)) in enumerate(zip(singles, outs)):
+        assert stb["iters"] == sst["iters"], f"instance {i} iterations"
+        assert torch.equal(Tb, T), f"instance {i} T"
+        assert torch.equal(qxb, qx), f"instance {i} qx"
+        assert torch.equal(qyb, qy), f"instance {i} qy"
+        assert stb["cg_iters_total"] == sst["cg_iters_total"]
+
+
+def test_batch_solver_wrapper(gpu):
+    """Uneven synthetic batch (sizes, Kn, walls drawn as for the benchmark, fewer
+    particles): per-instance status, iterations and outputs equal the single
+    solves, including instances whose Newton iteration diverges."""
+    from synth import batch_workloads
+    ws = batch_workloads(count=6, seed=11)
+    for w in ws:
+        w.particles_per_iter = min(w.particles_per_iter, 100_000)
+    kw = dict(rng_mode=gpu.RNG_CRN, tally_faces=gpu.FACES_FINAL, max_iters=30, res_tol=1e-5)
+    bs = gpu.BatchSolver(ws, **kw)
+    rc, outs = bs.solve()
+    statuses = []
+    for i, (w, (T, qx, qy, st)) in enumerate(zip(ws, outs)):
+        s = gpu.Solver(w, **kw)
+        try:
+            rc1, T1, qx1, qy1, st1 = s.solve()
+        except gpu.IugkpError as e:
+            assert st["status"] == e.code, f"instance {i}"
+            assert st["iters"] == s.stats()["iters"]
+            statuses.append(e.code)
+            continue
+        statuses.append(rc1)
+        assert st["status"] == rc1
+        assert torch.equal(T, T1) and torch.equal(qx, qx1) and torch.equal(qy, qy1)
+        assert st["iters"] == st1["iters"]
+    assert rc == (min(statuses) if min(statuses) < 0 else max(statuses))
