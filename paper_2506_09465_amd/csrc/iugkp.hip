@@ -345,11 +345,12 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
     ALLOC(d.cg_s, nc);
     ALLOC(d.cg_part, 2 * static_cast<size_t>(nbt));
     ALLOC(d.gpart, nbe);
-    if (multi_cg) {
-      ALLOC(ih.cg_pub, 6 * static_cast<size_t>(nc));
-      ALLOC(ih.cg_mpart, 4 * static_cast<size_t>(nbt));
-      ALLOC(ih.cg_barrier, 2);
-    }
+    ALLOC(ih.cg_pub, 6 * static_cast<size_t>(nc));
+    ALLOC(ih.cg_mpart, 4 * static_cast<size_t>(nbt));
+    ALLOC(ih.cg_barrier, 2);
+    d.cg_pub = ih.cg_pub;
+    d.cg_mpart = ih.cg_mpart;
+    d.cg_barrier = ih.cg_barrier;
   }
 #undef ALLOC
   HIP_TRY(hipMemcpyAsync(ih.tau, tau.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
@@ -914,6 +915,8 @@ struct iugkp_batch {
   size_t lds_max = 0;
   int any_newton = 0;
   int max_prep = 1, max_nx = 1, max_ny = 1, max_nbc = 1, max_nbe = 1, max_out = 1;
+  int cg_pool = 1;          // resident workgroups shared by the instances' CG solves
+  size_t cg_lds = 0;
   DevScalars *hsc = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -949,7 +952,8 @@ int enqueue_batch_iteration(iugkp_batch *b)
   iugkp::reconstruct_x_kernel<<<dim3(cdiv(b->max_ny, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
   iugkp::update_kernel<<<dim3(b->max_nbc, n), 256, 0, s>>>(b->d_insts, 1);
   if (b->any_newton) {
-    iugkp::cg_wg_kernel<<<n, iugkp::kCgThreads, 0, s>>>(b->d_insts, 1);
+    iugkp::assign_cg_kernel<<<1, 1, 0, s>>>(b->d_insts, n, b->cg_pool, 1);
+    iugkp::cg_batch_kernel<<<b->cg_pool, iugkp::kCgThreads, b->cg_lds, s>>>(b->d_insts, n, 1);
     iugkp::newton_finish_kernel<<<dim3(b->max_nbe, n), 256, 0, s>>>(b->d_insts, 1);
   }
   iugkp::finish_kernel<<<n, 256, 0, s>>>(b->d_insts, 1);
@@ -997,6 +1001,25 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
     b->max_nbc = std::max(b->max_nbc, cdiv(m.n_cells, iugkp::kTree));
     b->max_nbe = std::max(b->max_nbe, cdiv(m.n_emit, iugkp::kTree));
     b->max_out = std::max({b->max_out, m.n_cells, m.n_fx, m.n_fy});
+    if (ih.d.newton) b->cg_lds = std::max(b->cg_lds, 2 * static_cast<size_t>(m.nx) * sizeof(double));
+  }
+  if (b->any_newton) {
+    // the pool: every workgroup resident at once (occupancy times CUs), so the
+    // instance groups' barriers always make progress
+    if (b->cg_lds > kCgLdsMax) {
+      free_batch(b);
+      return fail(IUGKP_E_INVALID_ARG, "mesh rows too long for the Newton CG");
+    }
+    int dev = 0, n_cu = 0, per_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(iugkp::cg_batch_kernel), iugkp::kCgThreads, b->cg_lds));
+    if (per_cu < 1) {
+      free_batch(b);
+      return fail(IUGKP_E_DEVICE, "the batched CG kernel does not fit on a CU");
+    }
+    b->cg_pool = per_cu * n_cu;
   }
   if (hipMalloc(reinterpret_cast<void **>(&b->d_insts), n * sizeof(Inst)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&b->d_tiles), b->n_tiles * sizeof(TileDesc)) != hipSuccess ||

@@ -66,7 +66,10 @@ struct Inst {
   double *part;                 // squared-update partials [ceil(n_emit / 256)]
   unsigned long long *gpart;    // |G| budget partials
   const double *gx, *gy, *diag;
-  double *cg_x, *cg_r, *cg_w, *cg_p, *cg_s, *cg_part;   // one-workgroup CG state
+  double *cg_x, *cg_r, *cg_w, *cg_p, *cg_s, *cg_part;   // CG state (global-memory layout)
+  double *cg_pub, *cg_mpart;                            // published rows, partials
+  unsigned int *cg_barrier;                             // [2] barrier of the instance's group
+  int cg_first, cg_count;                               // workgroups of the batch pool (device-set)
   double *acc_E, *acc_x, *acc_y;
   DevScalars *sc;
 };
@@ -806,7 +809,8 @@ __global__ void newton_diag_kernel(Mesh m, const double *gx, const double *gy, d
 // kernel reports the failure, so a broken barrier can never hang the device.
 constexpr long kBarrierSpinLimit = 1l << 24;
 
-__device__ __forceinline__ bool grid_barrier(unsigned int *counter, unsigned int &epoch)
+__device__ __forceinline__ bool grid_barrier(unsigned int *counter, unsigned int &epoch,
+                                             unsigned int group)
 {
   __shared__ int s_abort;
   __syncthreads();
@@ -814,7 +818,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned int *counter, unsigned int
   if (threadIdx.x == 0) {
     __threadfence();
     __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned int target = epoch * gridDim.x;
+    const unsigned int target = epoch * group;
     long spins = 0;
     int abort = __hip_atomic_load(counter + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     while (!abort &&
@@ -906,8 +910,10 @@ __device__ __forceinline__ double apply_cell(const Mesh &m, const CellCoef &k, i
   return acc;
 }
 
+// The solve as seen by one workgroup of rank `rank` in a group of G workgroups
+// (all resident) sharing the barrier counter a.barrier.
 template <int J>
-__global__ __launch_bounds__(kCgThreads) void cg_kernel(CGArgs a)
+__device__ void cg_solve(const CGArgs &a, int rank, int G)
 {
   extern __shared__ double stage[];       // r on [h0, h1) (J > 0) or on the halo (J == 0)
   __shared__ double lds[kCgThreads];
@@ -916,7 +922,7 @@ __global__ __launch_bounds__(kCgThreads) void cg_kernel(CGArgs a)
   const Mesh &m = a.m;
   const int n = m.n_cells, nx = m.nx;
   const int nb = (n + kTree - 1) / kTree;
-  const int tb0 = blockIdx.x * a.TB;
+  const int tb0 = rank * a.TB;
   const int tb1 = min(tb0 + a.TB, nb);
   const int c0 = min(tb0 * kTree, n), c1 = min(tb1 * kTree, n);
   const int h0 = max(0, c0 - nx), h1 = min(n, c1 + nx);
@@ -1009,8 +1015,8 @@ __global__ __launch_bounds__(kCgThreads) void cg_kernel(CGArgs a)
       part[0][nb + tb] = d;
     }
   }
-  if (!grid_barrier(a.barrier, epoch)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.sc->cg_status = -3;
+  if (!grid_barrier(a.barrier, epoch, G)) {
+    if (rank == 0 && threadIdx.x == 0) a.sc->cg_status = -3;
     return;
   }
   double gamma = tree_all(part[0], nb, lds, lds2);
@@ -1087,7 +1093,7 @@ __global__ __launch_bounds__(kCgThreads) void cg_kernel(CGArgs a)
         part[par ^ 1][nb + tb] = d;
       }
     }
-    if (!grid_barrier(a.barrier, epoch)) {
+    if (!grid_barrier(a.barrier, epoch, G)) {
       status = -3;
       break;
     }
@@ -1117,102 +1123,104 @@ __global__ __launch_bounds__(kCgThreads) void cg_kernel(CGArgs a)
       if (c >= 0) a.x[c] = xr[j];
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (rank == 0 && threadIdx.x == 0) {
     a.sc->cg_iters = it;
     a.sc->cg_status = status;
   }
 }
 
-// ---------------------------------------------------------------------------
-// The same CG for one instance per 1024-thread workgroup (batched solves): the
-// state lives in the instance's global arrays, phases are separated by
-// workgroup barriers, partials go through the instance's cg_part array.
-// Identical recurrences and reduction order, hence identical results.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kCgThreads) void cg_wg_kernel(const Inst *__restrict__ insts, int batch)
+template <int J>
+__global__ __launch_bounds__(kCgThreads) void cg_kernel(CGArgs a)
 {
-  __shared__ double lds[kCgThreads];
-  __shared__ double lds2[kTree];
-  const Inst &in = insts[blockIdx.x];
-  if (inst_idle(in, batch) || !in.newton) return;
-  const Mesh &m = in.m;
-  const int n = m.n_cells;
-  const int nb = (n + kTree - 1) / kTree;
-  const int npass = (nb + kCgSlices - 1) / kCgSlices;
-  const int sl = threadIdx.x / kTree, t = threadIdx.x & (kTree - 1);
-  double *x = in.cg_x, *r = in.cg_r, *w = in.cg_w, *p = in.cg_p, *sv = in.cg_s;
-  double *pg = in.cg_part, *pd = in.cg_part + nb;
-  auto rget = [&](int c) -> double { return r[c]; };
-  auto spmv_partials = [&]() {
-    for (int j = 0; j < npass; ++j) {
-      const int tb = j * kCgSlices + sl;
-      const int c = tb * kTree + t;
-      double g = 0.0, d = 0.0;
-      if (tb < nb && c < n) {
-        const CellCoef k = load_coef(m, in.gx, in.gy, in.diag, c);
-        const double wv = apply_cell(m, k, c, rget);
-        w[c] = wv;
-        const double rv = r[c];
-        g = rv * rv;
-        d = wv * rv;
-      }
-      g = slice_tree256(g, lds);
-      d = slice_tree256(d, lds);
-      if (t == 0 && tb < nb) {
-        pg[tb] = g;
-        pd[tb] = d;
-      }
-    }
-    __syncthreads();
-  };
-  for (int c = threadIdx.x; c < n; c += kCgThreads) {
-    x[c] = 0.0;
-    r[c] = in.rhs[c];
+  cg_solve<J>(a, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched CG over a pool of P resident workgroups.  assign_cg_kernel (one
+// thread) hands every active Newton instance a contiguous group of
+// workgroups, one plus a share of the rest proportional to its cell count,
+// at most one per 256-cell tree block and kCgGroupMax; when the instances
+// outnumber the pool, each gets one workgroup and workgroup j serves the
+// active instances j, j + P, ... one after the other.  It also clears the
+// group barriers.  cg_batch_kernel then runs cg_solve<0> for every
+// (instance, rank) that names it.
+// ---------------------------------------------------------------------------
+constexpr int kCgGroupMax = 64;
+
+__global__ void assign_cg_kernel(Inst *insts, int n, int P, int batch)
+{
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  long long total = 0;
+  int active = 0;
+  for (int i = 0; i < n; ++i) {
+    Inst &in = insts[i];
+    in.cg_count = 0;
+    if (!in.newton || inst_idle(in, batch)) continue;
+    in.cg_barrier[0] = 0u;
+    in.cg_barrier[1] = 0u;
+    total += in.m.n_cells;
+    ++active;
   }
-  __syncthreads();
-  spmv_partials();
-  double gamma = tree_all(pg, nb, lds, lds2);
-  double delta = tree_all(pd, nb, lds, lds2);
-  const double thr = in.tol2 * gamma;
-  int status = -7;
-  int it = 0;
-  double alpha = 0.0, beta = 0.0;
-  if (gamma == 0.0) status = 0;
-  else if (!(delta > 0.0)) status = -6;
-  else alpha = gamma / delta;
-  while (status == -7 && it < in.cg_max) {
-    const int first = (it == 0);
-    for (int c = threadIdx.x; c < n; c += kCgThreads) {
-      const double pv = first ? r[c] : r[c] + beta * p[c];
-      const double s_ = first ? w[c] : w[c] + beta * sv[c];
-      p[c] = pv;
-      sv[c] = s_;
-      x[c] = x[c] + alpha * pv;
-      r[c] = r[c] - alpha * s_;
+  if (active == 0) return;
+  if (active > P) {
+    int k = 0;
+    for (int i = 0; i < n; ++i) {
+      Inst &in = insts[i];
+      if (!in.newton || inst_idle(in, batch)) continue;
+      in.cg_first = k % P;
+      in.cg_count = 1;
+      ++k;
     }
-    __syncthreads();
-    spmv_partials();
-    ++it;
-    const double gamma_new = tree_all(pg, nb, lds, lds2);
-    delta = tree_all(pd, nb, lds, lds2);
-    if (gamma_new <= thr) {
-      status = 0;
-      break;
-    }
-    beta = gamma_new / gamma;
-    double tq = beta * gamma_new;
-    tq = tq / alpha;
-    const double den = delta - tq;
-    if (!(den > 0.0)) {
-      status = -6;
-      break;
-    }
-    alpha = gamma_new / den;
-    gamma = gamma_new;
+    return;
   }
-  if (threadIdx.x == 0) {
-    in.sc->cg_iters = it;
-    in.sc->cg_status = status;
+  const long long spare = P - active;
+  int next = 0;
+  for (int i = 0; i < n; ++i) {
+    Inst &in = insts[i];
+    if (!in.newton || inst_idle(in, batch)) continue;
+    long long g = 1 + (spare * in.m.n_cells) / total;
+    const int nbt = (in.m.n_cells + kTree - 1) / kTree;
+    if (g > nbt) g = nbt;
+    if (g > kCgGroupMax) g = kCgGroupMax;
+    const long long tb = (nbt + g - 1) / g;      // no workgroup left without tree blocks
+    g = (nbt + tb - 1) / tb;
+    in.cg_first = next;
+    in.cg_count = static_cast<int>(g);
+    next += static_cast<int>(g);
+  }
+}
+
+__global__ __launch_bounds__(kCgThreads) void cg_batch_kernel(const Inst *__restrict__ insts, int n,
+                                                              int batch)
+{
+  const int j = blockIdx.x;
+  for (int i = 0; i < n; ++i) {
+    const Inst &in = insts[i];
+    if (in.cg_count == 0 || !in.newton || inst_idle(in, batch)) continue;
+    const int rank = j - in.cg_first;
+    if (rank < 0 || rank >= in.cg_count) continue;
+    const int G = in.cg_count;
+    const int nbt = (in.m.n_cells + kTree - 1) / kTree;
+    CGArgs a;
+    a.m = in.m;
+    a.gx = in.gx;
+    a.gy = in.gy;
+    a.diag = in.diag;
+    a.b = in.rhs;
+    a.x = in.cg_x;
+    a.gr = in.cg_r;
+    a.gw = in.cg_w;
+    a.gp = in.cg_p;
+    a.gs = in.cg_s;
+    a.pub = in.cg_pub;
+    a.part = in.cg_mpart;
+    a.TB = (nbt + G - 1) / G;
+    a.tol2 = in.tol2;
+    a.max_iters = in.cg_max;
+    a.barrier = in.cg_barrier;
+    a.sc = in.sc;
+    cg_solve<0>(a, rank, G);
+    __syncthreads();
   }
 }
 
