@@ -74,7 +74,7 @@ extern "C" {
 
 typedef struct iugkp_problem {
   int dim;              /* 1 or 2 */
-  int nx, ny;           /* cell counts, ny == 1 in 1D */
+  int nx, ny;           /* cell counts, ny == 1 in 1D, nx * ny <= 2^24 */
   double dx, dy;        /* cell sizes (> 0); dy is the unit face area in 1D */
   double t_ref;         /* reference temperature of the linearisation (Sec. 2) */
   double cv;            /* volumetric heat capacity C (> 0) */
@@ -101,6 +101,9 @@ typedef struct iugkp_options {
   int tally_faces;              /* IUGKP_FACES_* */
   int avg_iters;                /* iterations averaged for the outputs after stopping (>= 0) */
   int block_size;               /* transport kernel workgroup size: 0 (= 256), 64..1024 */
+  int cg_waves;                 /* single solves: 256-cell tree blocks per CG workgroup, 0
+                                   (= 8) or 1..12 with the CG state in registers, -1..-12 with
+                                   it in global memory; the result does not depend on it */
 } iugkp_options;
 
 typedef struct iugkp_stats {

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <string>
 #include <vector>
@@ -41,8 +42,9 @@ int fail(int code, const std::string &msg)
       return fail(IUGKP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));   \
   } while (0)
 
-constexpr int kCgGridMax = 64;
-constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of the multi-workgroup CG
+constexpr int kCgGridMax = 64;               // workgroups of one CG group (barrier arrivals)
+constexpr int kCgWavesDefault = 8;           // tree blocks per CG workgroup of a single solve
+constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of a CG workgroup
 constexpr int kTileX = 8, kTileY = 8;        // emitter tile of one workgroup (cells)
 constexpr int kWallSeg = 8;                  // wall faces per workgroup
 constexpr int kWindowHalo = 12;              // window margin around a tile (cells)
@@ -51,14 +53,10 @@ constexpr int kLdsWallsMax = 1024;
 
 inline int cdiv(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
 
-void *cg_kernel_for(int J)
+void *cg_kernel_for(int reg)
 {
-  switch (J) {
-    case 1: return reinterpret_cast<void *>(iugkp::cg_kernel<1>);
-    case 2: return reinterpret_cast<void *>(iugkp::cg_kernel<2>);
-    case 4: return reinterpret_cast<void *>(iugkp::cg_kernel<4>);
-    default: return reinterpret_cast<void *>(iugkp::cg_kernel<0>);
-  }
+  return reg ? reinterpret_cast<void *>(iugkp::cg_kernel<true>)
+             : reinterpret_cast<void *>(iugkp::cg_kernel<false>);
 }
 
 }  // namespace
@@ -84,7 +82,7 @@ struct InstHost {
   // multi-workgroup CG (single solves)
   double *cg_pub = nullptr, *cg_mpart = nullptr;
   unsigned int *cg_barrier = nullptr;
-  int cg_grid = 1, cg_tb = 1, cg_j = 1;
+  int cg_grid = 1, cg_tb = 1, cg_reg = 1, cg_threads = 64;
   size_t cg_lds = 0;
 
   template <class T>
@@ -109,7 +107,8 @@ int check_problem(const iugkp_problem *p)
   if (p->dim != 1 && p->dim != 2) return fail(IUGKP_E_INVALID_ARG, "dim must be 1 or 2");
   if (p->nx < 1 || p->ny < 1 || (p->dim == 1 && p->ny != 1))
     return fail(IUGKP_E_INVALID_ARG, "bad mesh size");
-  if ((long long)p->nx * p->ny > (1ll << 30)) return fail(IUGKP_E_INVALID_ARG, "mesh too large");
+  // the two-level fixed-order reductions cover 256 * 256 tree blocks
+  if ((long long)p->nx * p->ny > (1ll << 24)) return fail(IUGKP_E_INVALID_ARG, "mesh too large");
   if (!(p->dx > 0) || !(p->dy > 0) || !std::isfinite(p->dx) || !std::isfinite(p->dy))
     return fail(IUGKP_E_INVALID_ARG, "cell sizes must be positive and finite");
   if (!(p->cv > 0) || !(p->vg > 0) || !std::isfinite(p->cv) || !std::isfinite(p->vg) ||
@@ -134,6 +133,8 @@ int check_options(const iugkp_options *o)
   const int bs = o->block_size;
   if (bs != 0 && bs != 64 && bs != 128 && bs != 256 && bs != 512 && bs != 1024)
     return fail(IUGKP_E_INVALID_ARG, "block_size must be 0, 64, 128, 256, 512 or 1024");
+  if (o->cg_waves < -iugkp::kCgWavesMax || o->cg_waves > iugkp::kCgWavesMax)
+    return fail(IUGKP_E_INVALID_ARG, "cg_waves must be -12..12");
   return IUGKP_OK;
 }
 
@@ -343,7 +344,6 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
     ALLOC(d.cg_w, nc);
     ALLOC(d.cg_p, nc);
     ALLOC(d.cg_s, nc);
-    ALLOC(d.cg_part, 2 * static_cast<size_t>(nbt));
     ALLOC(d.gpart, nbe);
     ALLOC(ih.cg_pub, 6 * static_cast<size_t>(nc));
     ALLOC(ih.cg_mpart, 4 * static_cast<size_t>(nbt));
@@ -405,31 +405,35 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
                                                                  ih.gx, ih.gy, ih.diag);
     iugkp::newton_diag_kernel<<<cdiv(nc, 256), 256, 0, s>>>(m, ih.gx, ih.gy, ih.diag);
     if (multi_cg) {
-      // at most kCgGridMax resident workgroups (the barrier cost grows with the
-      // number of arrivals), whole 256-cell tree blocks per workgroup, cell
-      // state in registers when four-block passes and LDS staging allow
+      // a group of at most kCgGridMax resident workgroups (the barrier cost
+      // grows with the arrivals) of cg_waves tree blocks each; the register
+      // form when every block has its own wave and the rows fit in LDS
       int dev = 0, n_cu = 0;
       HIP_TRY(hipGetDevice(&dev));
       HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
       const int nbt = cdiv(nc, iugkp::kTree);
-      int G = std::max(1, std::min(std::min(nbt, kCgGridMax), n_cu));
+      const int hw = (p->dim == 2) ? p->nx : 1;
+      const int want = o->cg_waves != 0 ? std::abs(o->cg_waves) : kCgWavesDefault;
+      int G = std::max(1, std::min(std::min(cdiv(nbt, want), kCgGridMax), n_cu));
+      // more workgroups rather than the global form, while one per CU suffices
+      if (cdiv(nbt, G) > iugkp::kCgWavesMax && cdiv(nbt, iugkp::kCgWavesMax) <= n_cu)
+        G = cdiv(nbt, iugkp::kCgWavesMax);
       const int TB = cdiv(nbt, G);
       G = cdiv(nbt, TB);
-      const int passes = cdiv(TB, iugkp::kCgSlices);
-      int J = passes <= 1 ? 1 : passes <= 2 ? 2 : passes <= 4 ? 4 : 0;
-      size_t lds = (static_cast<size_t>(TB) * iugkp::kTree + 2 * static_cast<size_t>(p->nx)) *
+      size_t lds = (static_cast<size_t>(TB) * iugkp::kTree + 2 * static_cast<size_t>(hw)) *
                    sizeof(double);
-      if (J > 0 && lds > kCgLdsMax) J = 0;
-      if (J == 0) lds = 2 * static_cast<size_t>(p->nx) * sizeof(double);
+      int reg = (o->cg_waves >= 0 && TB <= iugkp::kCgWavesMax && lds <= kCgLdsMax) ? 1 : 0;
+      if (!reg) lds = 2 * static_cast<size_t>(hw) * sizeof(double);
       if (lds > kCgLdsMax) return fail(IUGKP_E_INVALID_ARG, "mesh rows too long for the Newton CG");
+      const int threads = 64 * (reg ? TB : std::min(TB, iugkp::kCgWavesMax));
       int per_cu = 0;
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cg_kernel_for(J),
-                                                           iugkp::kCgThreads, lds));
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cg_kernel_for(reg), threads, lds));
       if (per_cu < 1 || G > per_cu * n_cu)
         return fail(IUGKP_E_DEVICE, "CG workgroups cannot all be resident");
       ih.cg_grid = G;
       ih.cg_tb = TB;
-      ih.cg_j = J;
+      ih.cg_reg = reg;
+      ih.cg_threads = threads;
       ih.cg_lds = lds;
     }
   }
@@ -633,8 +637,8 @@ int iterate(iugkp_handle *h, int faces)
     // every workgroup must be resident for the grid barrier: the cooperative
     // launch refuses a grid that does not fit instead of letting it hang
     void *args[] = {&ca};
-    HIP_TRY(hipLaunchCooperativeKernel(cg_kernel_for(ih.cg_j), dim3(ih.cg_grid),
-                                       dim3(iugkp::kCgThreads), args, ih.cg_lds, s));
+    HIP_TRY(hipLaunchCooperativeKernel(cg_kernel_for(ih.cg_reg), dim3(ih.cg_grid),
+                                       dim3(ih.cg_threads), args, ih.cg_lds, s));
     HIP_TRY(hipEventRecord(h->ev[3], s));
     const int nbe = cdiv(m.n_emit, iugkp::kTree);
     iugkp::newton_finish_kernel<<<dim3(nbe, 1), 256, 0, s>>>(h->d_inst, 0);
@@ -915,8 +919,16 @@ struct iugkp_batch {
   size_t lds_max = 0;
   int any_newton = 0;
   int max_prep = 1, max_nx = 1, max_ny = 1, max_nbc = 1, max_nbe = 1, max_out = 1;
-  int cg_pool = 1;          // resident workgroups shared by the instances' CG solves
+  // batched CG: a pool of resident workgroups and, per replay, the host's
+  // schedule of (instance, rank) jobs on it
+  int cg_pool = 1;
   size_t cg_lds = 0;
+  std::vector<int> cg_G, cg_tb;      // per instance: group size, blocks per workgroup | form bit
+  int *d_off = nullptr, *h_off = nullptr;
+  iugkp::CgJob *d_jobs = nullptr, *h_jobs = nullptr;
+  int max_jobs = 0;
+  DevScalars *d_scs = nullptr;       // every instance's scalars, contiguous
+  unsigned int *d_bars = nullptr;    // every instance's CG barrier [2]
   DevScalars *hsc = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -934,6 +946,12 @@ void free_batch(iugkp_batch *b)
   if (b->d_insts) (void)hipFree(b->d_insts);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->hsc) (void)hipHostFree(b->hsc);
+  if (b->h_off) (void)hipHostFree(b->h_off);
+  if (b->h_jobs) (void)hipHostFree(b->h_jobs);
+  if (b->d_off) (void)hipFree(b->d_off);
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_scs) (void)hipFree(b->d_scs);
+  if (b->d_bars) (void)hipFree(b->d_bars);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->own) (void)hipStreamDestroy(b->own);
@@ -952,14 +970,74 @@ int enqueue_batch_iteration(iugkp_batch *b)
   iugkp::reconstruct_x_kernel<<<dim3(cdiv(b->max_ny, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
   iugkp::update_kernel<<<dim3(b->max_nbc, n), 256, 0, s>>>(b->d_insts, 1);
   if (b->any_newton) {
-    iugkp::assign_cg_kernel<<<1, 1, 0, s>>>(b->d_insts, n, b->cg_pool, 1);
-    iugkp::cg_batch_kernel<<<b->cg_pool, iugkp::kCgThreads, b->cg_lds, s>>>(b->d_insts, n, 1);
+    iugkp::zero_u32_kernel<<<cdiv(2 * n, 256), 256, 0, s>>>(b->d_bars, 2 * n);
+    iugkp::cg_batch_kernel<<<b->cg_pool, iugkp::kCgThreadsMax, b->cg_lds, s>>>(b->d_insts, b->d_off,
+                                                                               b->d_jobs);
     iugkp::newton_finish_kernel<<<dim3(b->max_nbe, n), 256, 0, s>>>(b->d_insts, 1);
   }
   iugkp::finish_kernel<<<n, 256, 0, s>>>(b->d_insts, 1);
   iugkp::accumulate_kernel<<<dim3(cdiv(b->max_out, 256), n), 256, 0, s>>>(b->d_insts, 1, -1);
   HIP_TRY(hipGetLastError());
   return IUGKP_OK;
+}
+
+// List scheduling of the CG jobs of the instances still iterating onto the
+// pool, longest first: each job takes the G contiguous workgroups that free up
+// earliest (estimated from the previous CG iteration count of the instance, or
+// four CG iterations per mesh row before the first one), and is appended to
+// their job lists in that global order.  Returns the number of entries.
+int schedule_cg(iugkp_batch *b)
+{
+  const int n = static_cast<int>(b->insts.size());
+  const int P = b->cg_pool;
+  struct Job {
+    double cost;
+    int inst;
+  };
+  std::vector<Job> jobs;
+  for (int i = 0; i < n; ++i) {
+    const InstHost &ih = b->insts[i];
+    const DevScalars &sc = b->hsc[i];
+    if (!ih.d.newton || sc.state == 2) continue;
+    const int prior = 4 * std::max(ih.d.m.nx, ih.d.m.ny);
+    const double its = sc.iter > 0 ? std::max(sc.cg_iters, 1) : std::min(prior, ih.d.cg_max);
+    jobs.push_back({its * (b->cg_G[i] > 1 ? 3.0 : 1.0), i});
+  }
+  std::stable_sort(jobs.begin(), jobs.end(), [](const Job &x, const Job &y) { return x.cost > y.cost; });
+  std::vector<double> load(P, 0.0);
+  std::vector<std::vector<iugkp::CgJob>> lists(P);
+  std::deque<int> dq;
+  for (const Job &jb : jobs) {
+    const int G = b->cg_G[jb.inst];
+    // window of G workgroups whose latest free time is smallest (sliding maximum)
+    int best = 0;
+    double best_t = 0.0;
+    dq.clear();
+    for (int k = 0; k < P; ++k) {
+      while (!dq.empty() && load[dq.back()] <= load[k]) dq.pop_back();
+      dq.push_back(k);
+      if (dq.front() <= k - G) dq.pop_front();
+      if (k >= G - 1) {
+        const double t = load[dq.front()];
+        if (k == G - 1 || t < best_t) {
+          best_t = t;
+          best = k - G + 1;
+        }
+      }
+    }
+    const double fin = best_t + jb.cost;
+    for (int r = 0; r < G; ++r) {
+      load[best + r] = fin;
+      lists[best + r].push_back({jb.inst, r, G, b->cg_tb[jb.inst]});
+    }
+  }
+  int e = 0;
+  for (int k = 0; k < P; ++k) {
+    b->h_off[k] = e;
+    for (const auto &x : lists[k]) b->h_jobs[e++] = x;
+  }
+  b->h_off[P] = e;
+  return e;
 }
 
 }  // namespace
@@ -1001,32 +1079,82 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
     b->max_nbc = std::max(b->max_nbc, cdiv(m.n_cells, iugkp::kTree));
     b->max_nbe = std::max(b->max_nbe, cdiv(m.n_emit, iugkp::kTree));
     b->max_out = std::max({b->max_out, m.n_cells, m.n_fx, m.n_fy});
-    if (ih.d.newton) b->cg_lds = std::max(b->cg_lds, 2 * static_cast<size_t>(m.nx) * sizeof(double));
   }
+  b->cg_G.assign(n, 0);
+  b->cg_tb.assign(n, 0);
   if (b->any_newton) {
     // the pool: every workgroup resident at once (occupancy times CUs), so the
-    // instance groups' barriers always make progress
-    if (b->cg_lds > kCgLdsMax) {
-      free_batch(b);
-      return fail(IUGKP_E_INVALID_ARG, "mesh rows too long for the Newton CG");
-    }
+    // instance groups' barriers always make progress.  An instance's group:
+    // one wave per tree block and at most kCgWavesMax blocks per workgroup
+    // (register form), or, for rows too long for the LDS staging or groups
+    // beyond one workgroup per CU, the global form on kCgGridMax workgroups.
     int dev = 0, n_cu = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int i = 0; i < n; ++i) {
+      const InstHost &ih = b->insts[i];
+      if (!ih.d.newton) continue;
+      const Mesh &m = ih.d.m;
+      const int nbt = cdiv(m.n_cells, iugkp::kTree);
+      const size_t hw = (m.dim == 2) ? m.nx : 1;
+      int G = cdiv(nbt, iugkp::kCgWavesMax);
+      int TB = cdiv(nbt, G);
+      size_t lds = (static_cast<size_t>(TB) * iugkp::kTree + 2 * hw) * sizeof(double);
+      int reg = 1;
+      if (G > n_cu || lds > kCgLdsMax) {
+        reg = 0;
+        G = std::min(nbt, kCgGridMax);
+        TB = cdiv(nbt, G);
+        lds = 2 * hw * sizeof(double);
+      }
+      G = cdiv(nbt, TB);
+      if (lds > kCgLdsMax) {
+        free_batch(b);
+        return fail(IUGKP_E_INVALID_ARG, "mesh rows too long for the Newton CG");
+      }
+      b->cg_G[i] = G;
+      b->cg_tb[i] = TB | (reg ? iugkp::kCgJobReg : 0);
+      b->cg_lds = std::max(b->cg_lds, lds);
+      b->max_jobs += G;
+    }
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(iugkp::cg_batch_kernel), iugkp::kCgThreads, b->cg_lds));
+        &per_cu, reinterpret_cast<const void *>(iugkp::cg_batch_kernel), iugkp::kCgThreadsMax,
+        b->cg_lds));
     if (per_cu < 1) {
       free_batch(b);
       return fail(IUGKP_E_DEVICE, "the batched CG kernel does not fit on a CU");
     }
     b->cg_pool = per_cu * n_cu;
+    for (int i = 0; i < n; ++i)
+      if (b->cg_G[i] > b->cg_pool) {
+        free_batch(b);
+        return fail(IUGKP_E_DEVICE, "a CG group exceeds the resident workgroups");
+      }
   }
   if (hipMalloc(reinterpret_cast<void **>(&b->d_insts), n * sizeof(Inst)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&b->d_tiles), b->n_tiles * sizeof(TileDesc)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void **>(&b->hsc), n * sizeof(DevScalars)) != hipSuccess) {
+      hipMalloc(reinterpret_cast<void **>(&b->d_scs), n * sizeof(DevScalars)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&b->d_bars), 2 * n * sizeof(unsigned int)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&b->d_off), (b->cg_pool + 1) * sizeof(int)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&b->d_jobs),
+                std::max(b->max_jobs, 1) * sizeof(iugkp::CgJob)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&b->hsc), n * sizeof(DevScalars)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&b->h_off), (b->cg_pool + 1) * sizeof(int)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&b->h_jobs),
+                    std::max(b->max_jobs, 1) * sizeof(iugkp::CgJob)) != hipSuccess) {
     free_batch(b);
     return fail(IUGKP_E_NOMEM, "allocation failed");
   }
+  // gather the instances' scalars into one array (one copy per replay) and
+  // give every instance its slot of the barrier array
+  for (int i = 0; i < n; ++i) {
+    InstHost &ih = b->insts[i];
+    HIP_TRY(hipMemcpyAsync(b->d_scs + i, ih.d.sc, sizeof(DevScalars), hipMemcpyDeviceToDevice,
+                           b->stream));
+    ih.d.sc = b->d_scs + i;
+    ih.d.cg_barrier = b->d_bars + 2 * i;
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream));
   if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
@@ -1079,13 +1207,19 @@ int iugkp_batch_solve(iugkp_batch *b, double *const *T_out, double *const *qx_ou
   int cap = 0;
   for (const auto &ih : b->insts) cap = std::max(cap, ih.d.max_iters + ih.d.avg_iters + 2);
   for (int it = 0; it <= cap; ++it) {
-    for (int i = 0; i < n; ++i)
-      HIP_TRY(hipMemcpyAsync(&b->hsc[i], b->insts[i].d.sc, sizeof(DevScalars),
-                             hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(b->hsc, b->d_scs, n * sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     bool all_done = true;
     for (int i = 0; i < n; ++i) all_done = all_done && (b->hsc[i].state == 2);
     if (all_done) break;
+    if (b->any_newton) {
+      const int ne = schedule_cg(b);
+      HIP_TRY(hipMemcpyAsync(b->d_off, b->h_off, (b->cg_pool + 1) * sizeof(int),
+                             hipMemcpyHostToDevice, s));
+      if (ne > 0)
+        HIP_TRY(hipMemcpyAsync(b->d_jobs, b->h_jobs, ne * sizeof(iugkp::CgJob),
+                               hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(hipGraphLaunch(b->exec, s));
   }
   int worst = IUGKP_OK;

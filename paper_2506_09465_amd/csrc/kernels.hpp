@@ -69,7 +69,6 @@ struct Inst {
   double *cg_x, *cg_r, *cg_w, *cg_p, *cg_s, *cg_part;   // CG state (global-memory layout)
   double *cg_pub, *cg_mpart;                            // published rows, partials
   unsigned int *cg_barrier;                             // [2] barrier of the instance's group
-  int cg_first, cg_count;                               // workgroups of the batch pool (device-set)
   double *acc_E, *acc_x, *acc_y;
   DevScalars *sc;
 };
@@ -800,9 +799,10 @@ __global__ void newton_diag_kernel(Mesh m, const double *gx, const double *gy, d
 // Grid barrier for a persistent kernel whose workgroups are all resident (the
 // grid is sized from the occupancy query, at most one workgroup per CU).  A
 // monotone arrival counter at agent scope: barrier number k completes when the
-// counter reaches k * gridDim.x.  The release fence before arriving and the
-// acquire fence after leaving make the partial sums written before the barrier
-// visible to every workgroup, whichever XCD it runs on.
+// counter reaches k * group (the group's workgroup count).  The release fence
+// before arriving and the acquire fence after leaving make the partial sums
+// written before the barrier visible to every workgroup, whichever XCD it runs
+// on.
 // ---------------------------------------------------------------------------
 // counter[0] = arrivals, counter[1] = abort flag.  A wait longer than ~1 s sets
 // the abort flag; every workgroup then leaves its next barrier at once and the
@@ -816,22 +816,31 @@ __device__ __forceinline__ bool grid_barrier(unsigned int *counter, unsigned int
   __syncthreads();
   epoch += 1;
   if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // release: the workgroup's writes (ordered before by the workgroup
+    // barrier) become visible at agent scope before the arrival counts
     const unsigned int target = epoch * group;
+    const unsigned int old =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     long spins = 0;
-    int abort = __hip_atomic_load(counter + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (!abort &&
-           __hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kBarrierSpinLimit) {
-        __hip_atomic_store(counter + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        abort = 1;
-      } else if ((spins & 1023) == 0) {
-        abort = __hip_atomic_load(counter + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int abort = 0;
+    if (old + 1u < target) {
+      while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kBarrierSpinLimit) {
+          __hip_atomic_store(counter + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          abort = 1;
+          break;
+        }
+        if ((spins & 1023) == 0 &&
+            __hip_atomic_load(counter + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          abort = 1;
+          break;
+        }
       }
     }
-    __threadfence();
+    // acquire: the other workgroups' writes are visible to this workgroup's
+    // loads after the workgroup barrier below
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_abort = abort;
   }
   __syncthreads();
@@ -845,30 +854,37 @@ __device__ __forceinline__ bool grid_barrier(unsigned int *counter, unsigned int
 //           x += alpha p, r -= alpha s, w = A r
 //           gamma' = (r, r), delta = (w, r); stop if gamma' <= tol^2 (b, b)
 //           beta = gamma' / gamma, alpha = gamma' / (delta - beta gamma' / alpha)
-// One persistent kernel, one grid barrier per iteration.  Workgroup g owns the
-// contiguous tree blocks [g TB, (g+1) TB) (cells [c0, c1)); its cells' x, r, w,
-// p, s stay in registers (J > 0: J passes of four 256-cell tree blocks per
-// 1024-thread workgroup) or in global arrays (J == 0).  The operator needs r
-// one mesh row beyond the own range: before each barrier every workgroup
-// publishes (r, w, s) of its first and last nx cells (double-buffered by
-// iteration parity); after it, each workgroup recomputes the neighbours' new r
-// on that halo with the owner's exact operations, s = w + beta s_old,
-// r = r - alpha s, so the halo values are bit-identical to the owner's.
+// One persistent group of G workgroups, one group barrier per iteration (none
+// when G = 1).  Rank g owns the contiguous tree blocks [g TB, (g+1) TB), cells
+// [c0, c1).  Register form (TB <= waves per workgroup): wave w owns block
+// g TB + w and lane l keeps x, r, w, p, s and the operator row of cells
+// l, l + 64, l + 128, l + 192 of it, so the block's pairwise tree
+// ((v_l + v_{l+128}) + (v_{l+64} + v_{l+192}), then halving strides across the
+// lanes) runs inside the wave.  Global form: the waves take the blocks round
+// robin and the state lives in global arrays.  Block sums are published as
+// (g, d) pairs; after the barrier every wave reduces all of them itself, in
+// the same fixed order, so no workgroup-wide step is needed for the scalars.
+// The operator needs r one mesh row (one cell in 1D) beyond the own range:
+// before each barrier every workgroup publishes (r, w, s) of the cells its
+// neighbours read (double-buffered by iteration parity); after it, each
+// workgroup recomputes the neighbours' new r on that halo with the owner's
+// exact operations, s = w + beta s_old, r = r - alpha s, so the halo values
+// are bit-identical to the owner's.
 // ---------------------------------------------------------------------------
-constexpr int kCgThreads = 1024;
-constexpr int kCgSlices = kCgThreads / kTree;
+constexpr int kCgWavesMax = 12;        // 768 threads: about 170 VGPRs per lane for the register form
+constexpr int kCgThreadsMax = 64 * kCgWavesMax;
 
 struct CGArgs {
   Mesh m;
   const double *gx, *gy, *diag, *b;
   double *x;                 // solution
-  double *gr, *gw, *gp, *gs; // own-state arrays (J == 0 only)
+  double *gr, *gw, *gp, *gs; // own-state arrays (global form only)
   double *pub;               // [2][3][n] published (r, w, s)
-  double *part;              // [2][2][nb] partials of (r, r) and (w, r)
+  double *part;              // [2][nb][2] block sums of (r, r) and (w, r)
   int TB;                    // tree blocks per workgroup
   double tol2;
   int max_iters;
-  unsigned int *barrier;     // [2], zeroed before the launch
+  unsigned int *barrier;     // [2], zero at the start of the solve
   DevScalars *sc;
 };
 
@@ -889,11 +905,6 @@ __device__ __forceinline__ CellCoef load_coef(const Mesh &m, const double *gx, c
   return k;
 }
 
-__device__ __forceinline__ CellCoef load_coef(const CGArgs &a, int c)
-{
-  return load_coef(a.m, a.gx, a.gy, a.diag, c);
-}
-
 // (A v)_c with the reference operation order: diag v_c - g_l v_{c-1} - g_r v_{c+1}
 // - g_dn v_{c-nx} - g_up v_{c+nx}, absent neighbours skipped.
 template <class Get>
@@ -910,38 +921,105 @@ __device__ __forceinline__ double apply_cell(const Mesh &m, const CellCoef &k, i
   return acc;
 }
 
-// The solve as seen by one workgroup of rank `rank` in a group of G workgroups
-// (all resident) sharing the barrier counter a.barrier.
-template <int J>
-__device__ void cg_solve(const CGArgs &a, int rank, int G)
+// The same with the neighbour tests precomputed: bits 0..3 of nbm = left,
+// right, down, up neighbour present.
+template <class Get>
+__device__ __forceinline__ double apply_masked(const CellCoef &k, int c, int nx, unsigned nbm, Get v)
 {
-  extern __shared__ double stage[];       // r on [h0, h1) (J > 0) or on the halo (J == 0)
-  __shared__ double lds[kCgThreads];
-  __shared__ double lds2[kTree];
+  double acc = k.d * v(c);
+  if (nbm & 1u) acc = acc - k.l * v(c - 1);
+  if (nbm & 2u) acc = acc - k.r * v(c + 1);
+  if (nbm & 4u) acc = acc - k.dn * v(c - nx);
+  if (nbm & 8u) acc = acc - k.up * v(c + nx);
+  return acc;
+}
+
+__device__ __forceinline__ unsigned neighbour_mask(const Mesh &m, int c)
+{
+  const int iy = c / m.nx, ix = c - iy * m.nx;
+  unsigned b = 0u;
+  if (ix > 0) b |= 1u;
+  if (ix < m.nx - 1) b |= 2u;
+  if (m.dim == 2 && iy > 0) b |= 4u;
+  if (m.dim == 2 && iy < m.ny - 1) b |= 8u;
+  return b;
+}
+
+// Pairwise tree of one 256-element block whose element l + 64 q sits in lane l
+// as v_q; the sum is valid in lane 0.
+__device__ __forceinline__ double wave_tree256(double v0, double v1, double v2, double v3)
+{
+  double r = (v0 + v2) + (v1 + v3);
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) r = r + __shfl_down(r, s, 64);
+  return r;
+}
+
+// Sums of the nb published (g, d) pairs in the fixed order of the host-side
+// definition: the 256-element tree over each chunk of pairs, then the same
+// tree over the chunk sums (nb <= 65536).  Every lane of the calling wave gets
+// both results.
+__device__ __forceinline__ void wave_tree_pairs(const double *part, int nb, double &sg, double &sd)
+{
+  const int lane = threadIdx.x & 63;
+  const int nch = (nb + kTree - 1) / kTree;
+  double cg[4] = {0.0, 0.0, 0.0, 0.0}, cd[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < nch; ++k) {
+    double g[4], d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = k * kTree + lane + 64 * q;
+      const bool in = i < nb;
+      g[q] = in ? part[2 * i] : 0.0;
+      d[q] = in ? part[2 * i + 1] : 0.0;
+    }
+    const double rg = __shfl(wave_tree256(g[0], g[1], g[2], g[3]), 0, 64);
+    const double rd = __shfl(wave_tree256(d[0], d[1], d[2], d[3]), 0, 64);
+    if (nch == 1) {
+      sg = rg;
+      sd = rd;
+      return;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if ((k >> 6) == q && (k & 63) == lane) {
+        cg[q] = rg;
+        cd[q] = rd;
+      }
+  }
+  sg = __shfl(wave_tree256(cg[0], cg[1], cg[2], cg[3]), 0, 64);
+  sd = __shfl(wave_tree256(cd[0], cd[1], cd[2], cd[3]), 0, 64);
+}
+
+// The solve as seen by one workgroup of rank `rank` in a group of G resident
+// workgroups sharing the barrier counter a.barrier.  REG selects the register
+// form (requires a.TB <= blockDim.x / 64).
+template <bool REG>
+__device__ void cg_run(const CGArgs &a, int rank, int G)
+{
+  extern __shared__ double stage[];       // r on [h0, h1) (register form) or on the halo
   unsigned int epoch = 0;
   const Mesh &m = a.m;
-  const int n = m.n_cells, nx = m.nx;
+  const int n = m.n_cells;
   const int nb = (n + kTree - 1) / kTree;
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tb0 = rank * a.TB;
   const int tb1 = min(tb0 + a.TB, nb);
   const int c0 = min(tb0 * kTree, n), c1 = min(tb1 * kTree, n);
-  const int h0 = max(0, c0 - nx), h1 = min(n, c1 + nx);
-  const int nlo = c0 - h0;                // halo cells below the own range
-  const int sl = threadIdx.x / kTree, t = threadIdx.x & (kTree - 1);
-  const int npass = (a.TB + kCgSlices - 1) / kCgSlices;
+  const int hw = (m.dim == 2) ? m.nx : 1;
+  const int h0 = max(0, c0 - hw), h1 = min(n, c1 + hw);
+  const int nlo = c0 - h0;                          // halo cells below the own range
+  const int nhalo = (h1 - h0) - (c1 - c0);
+  const bool nb_lo = c0 > 0, nb_hi = c1 < n;       // a neighbour below / above exists
   double *const pub[2] = {a.pub, a.pub + 3 * static_cast<size_t>(n)};
   double *const part[2] = {a.part, a.part + 2 * static_cast<size_t>(nb)};
+  const int tbr = tb0 + wave;                       // the register form's block
+  const bool own = REG && wave < a.TB && tbr < tb1;
 
-  // own cell of pass j for this thread (or -1)
-  auto own_cell = [&](int j) {
-    const int tb = tb0 + j * kCgSlices + sl;
-    const int c = tb * kTree + t;
-    return (tb < tb1 && c < n) ? c : -1;
-  };
-  auto in_boundary = [&](int c) { return c < c0 + nx || c >= c1 - nx; };
-  // r value seen by the operator: staged in LDS (J > 0) or own global / halo LDS (J == 0)
+  auto halo_cell = [&](int i) { return i < nlo ? h0 + i : c1 + (i - nlo); };
+  auto published = [&](int c) { return (nb_lo && c < c0 + hw) || (nb_hi && c >= c1 - hw); };
   auto rget = [&](int c) -> double {
-    if constexpr (J > 0) {
+    if constexpr (REG) {
       return stage[c - h0];
     } else {
       if (c < c0) return stage[c - h0];
@@ -950,99 +1028,161 @@ __device__ void cg_solve(const CGArgs &a, int rank, int G)
     }
   };
 
-  double xr[J > 0 ? J : 1], rr_[J > 0 ? J : 1], wr[J > 0 ? J : 1], pr[J > 0 ? J : 1],
-      sr[J > 0 ? J : 1];
-  CellCoef kr[J > 0 ? J : 1];
-
-  // ---- start: x = 0, r = b, w = A b
-  if constexpr (J > 0) {
-    for (int i = threadIdx.x; i < h1 - h0; i += kCgThreads) stage[i] = a.b[h0 + i];
+  double xr[4], rr[4], wr[4], pr[4], sr[4];
+  CellCoef kr[4];
+  // the first kHaloRegs halo slots of this thread: published (r, w, s), loaded
+  // right after the barrier together with the block sums
+  constexpr int kHaloRegs = 1;
+  double hr[kHaloRegs], hwv[kHaloRegs], hs[kHaloRegs];
+  auto preload_halo = [&](const double *pp) {
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int c = own_cell(j);
-      xr[j] = 0.0;
-      pr[j] = 0.0;
-      sr[j] = 0.0;
-      if (c >= 0) {
-        kr[j] = load_coef(a, c);
-        rr_[j] = a.b[c];
-      } else {
-        rr_[j] = 0.0;
+    for (int k = 0; k < kHaloRegs; ++k) {
+      const int i = threadIdx.x + k * blockDim.x;
+      hr[k] = 0.0;
+      hwv[k] = 0.0;
+      hs[k] = 0.0;
+      if (i < nhalo) {
+        const int c = halo_cell(i);
+        hr[k] = pp[c];
+        hwv[k] = pp[n + c];
+        hs[k] = pp[2 * static_cast<size_t>(n) + c];
+      }
+    }
+  };
+  unsigned cm = 0u;        // register form: per cell q, bits 5q..5q+3 neighbours, 5q+4 published
+
+  // w = A r on the own cells, block sums of (r, r) and (w, r) into pt, (r, w, s)
+  // of the published cells into pn
+  auto apply_pass = [&](double *pn, double *pt, bool start) {
+    if constexpr (REG) {
+      if (!own) return;
+      double g[4], d[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = tbr * kTree + lane + 64 * q;
+        g[q] = 0.0;
+        d[q] = 0.0;
+        if (c < n) {
+          const unsigned bits = cm >> (5 * q);
+          const double wv = apply_masked(kr[q], c, m.nx, bits, rget);
+          wr[q] = wv;
+          g[q] = rr[q] * rr[q];
+          d[q] = wv * rr[q];
+          if (bits & 16u) {
+            pn[c] = rr[q];
+            pn[n + c] = wv;
+            pn[2 * static_cast<size_t>(n) + c] = sr[q];
+          }
+        }
+      }
+      const double sg = wave_tree256(g[0], g[1], g[2], g[3]);
+      const double sd = wave_tree256(d[0], d[1], d[2], d[3]);
+      if (lane == 0) {
+        pt[2 * tbr] = sg;
+        pt[2 * tbr + 1] = sd;
+      }
+    } else {
+      for (int tb = tb0 + wave; tb < tb1; tb += nw) {
+        double g[4], d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = tb * kTree + lane + 64 * q;
+          g[q] = 0.0;
+          d[q] = 0.0;
+          if (c < n) {
+            const CellCoef k = load_coef(m, a.gx, a.gy, a.diag, c);
+            const double wv = apply_cell(m, k, c, rget);
+            a.gw[c] = wv;
+            const double rv = a.gr[c];
+            g[q] = rv * rv;
+            d[q] = wv * rv;
+            if (published(c)) {
+              pn[c] = rv;
+              pn[n + c] = wv;
+              pn[2 * static_cast<size_t>(n) + c] = start ? 0.0 : a.gs[c];
+            }
+          }
+        }
+        const double sg = wave_tree256(g[0], g[1], g[2], g[3]);
+        const double sd = wave_tree256(d[0], d[1], d[2], d[3]);
+        if (lane == 0) {
+          pt[2 * tb] = sg;
+          pt[2 * tb + 1] = sd;
+        }
+      }
+    }
+  };
+  auto group_barrier = [&]() -> bool {
+    if (G == 1) {
+      __syncthreads();
+      return true;
+    }
+    return grid_barrier(a.barrier, epoch, G);
+  };
+
+  // ---- start: x = 0, r = b, w = A r
+  if constexpr (REG) {
+    for (int i = threadIdx.x; i < h1 - h0; i += blockDim.x) stage[i] = a.b[h0 + i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tbr * kTree + lane + 64 * q;
+      xr[q] = 0.0;
+      pr[q] = 0.0;
+      sr[q] = 0.0;
+      wr[q] = 0.0;
+      rr[q] = 0.0;
+      kr[q] = CellCoef{0.0, 0.0, 0.0, 0.0, 0.0};
+      if (own && c < n) {
+        kr[q] = load_coef(m, a.gx, a.gy, a.diag, c);
+        rr[q] = a.b[c];
+        cm |= (neighbour_mask(m, c) | (published(c) ? 16u : 0u)) << (5 * q);
       }
     }
   } else {
-    for (int i = threadIdx.x; i < nlo; i += kCgThreads) stage[i] = a.b[h0 + i];
-    for (int i = threadIdx.x; i < h1 - c1; i += kCgThreads) stage[nlo + i] = a.b[c1 + i];
-    for (int j = 0; j < npass; ++j) {
-      const int c = own_cell(j);
-      if (c >= 0) {
-        a.x[c] = 0.0;
-        a.gr[c] = a.b[c];
-      }
+    for (int i = threadIdx.x; i < nhalo; i += blockDim.x) stage[i] = a.b[halo_cell(i)];
+    for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+      a.x[c] = 0.0;
+      a.gr[c] = a.b[c];
     }
   }
   __syncthreads();
-  for (int j = 0; j < (J > 0 ? J : npass); ++j) {
-    const int c = own_cell(j);
-    double g = 0.0, d = 0.0;
-    if (c >= 0) {
-      double wv;
-      if constexpr (J > 0) {
-        wv = apply_cell(m, kr[j], c, rget);
-        wr[j] = wv;
-        g = rr_[j] * rr_[j];
-        d = wv * rr_[j];
-      } else {
-        const CellCoef k = load_coef(a, c);
-        wv = apply_cell(m, k, c, rget);
-        a.gw[c] = wv;
-        const double rv = a.gr[c];
-        g = rv * rv;
-        d = wv * rv;
-      }
-      if (in_boundary(c)) {
-        const double rv = (J > 0) ? rr_[j] : a.gr[c];
-        pub[0][c] = rv;
-        pub[0][n + c] = wv;
-        pub[0][2 * static_cast<size_t>(n) + c] = 0.0;
-      }
-    }
-    g = slice_tree256(g, lds);
-    d = slice_tree256(d, lds);
-    const int tb = tb0 + j * kCgSlices + sl;
-    if (t == 0 && tb < tb1) {
-      part[0][tb] = g;
-      part[0][nb + tb] = d;
-    }
-  }
-  if (!grid_barrier(a.barrier, epoch, G)) {
-    if (rank == 0 && threadIdx.x == 0) a.sc->cg_status = -3;
-    return;
-  }
-  double gamma = tree_all(part[0], nb, lds, lds2);
-  double delta = tree_all(part[0] + nb, nb, lds, lds2);
-  const double thr = a.tol2 * gamma;
+  apply_pass(pub[0], part[0], true);
   int status = -7;
+  if (!group_barrier()) status = -3;
+  preload_halo(pub[0]);
+  double gamma = 0.0, delta = 0.0;
+  wave_tree_pairs(part[0], nb, gamma, delta);
+  const double thr = a.tol2 * gamma;
   int it = 0, par = 0;
   double alpha = 0.0, beta = 0.0;
-  if (gamma == 0.0) status = 0;
-  else if (!(delta > 0.0)) status = -6;
-  else alpha = gamma / delta;
+  if (status == -3) {
+  } else if (gamma == 0.0) {
+    status = 0;
+  } else if (!(delta > 0.0)) {
+    status = -6;
+  } else {
+    alpha = gamma / delta;
+  }
   while (status == -7 && it < a.max_iters) {
-    const int first = (it == 0);
+    const bool first = (it == 0);
     const double *pp = pub[par];
-    double *pn = pub[par ^ 1];
-    // own cells: direction, x and r updates; stage the new r
-    for (int j = 0; j < (J > 0 ? J : npass); ++j) {
-      const int c = own_cell(j);
-      if (c < 0) continue;
-      if constexpr (J > 0) {
-        pr[j] = first ? rr_[j] : rr_[j] + beta * pr[j];
-        sr[j] = first ? wr[j] : wr[j] + beta * sr[j];
-        xr[j] = xr[j] + alpha * pr[j];
-        rr_[j] = rr_[j] - alpha * sr[j];
-        stage[c - h0] = rr_[j];
-      } else {
+    // own cells: direction, x and r updates (register form: stage the new r)
+    if constexpr (REG) {
+      if (own) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = tbr * kTree + lane + 64 * q;
+          if (c < n) {
+            pr[q] = first ? rr[q] : rr[q] + beta * pr[q];
+            sr[q] = first ? wr[q] : wr[q] + beta * sr[q];
+            xr[q] = xr[q] + alpha * pr[q];
+            rr[q] = rr[q] - alpha * sr[q];
+            stage[c - h0] = rr[q];
+          }
+        }
+      }
+    } else {
+      for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
         const double pv = first ? a.gr[c] : a.gr[c] + beta * a.gp[c];
         const double sv = first ? a.gw[c] : a.gw[c] + beta * a.gs[c];
         a.gp[c] = pv;
@@ -1052,55 +1192,35 @@ __device__ void cg_solve(const CGArgs &a, int rank, int G)
       }
     }
     // halo: the neighbours' new r from their published (r, w, s)
-    for (int i = threadIdx.x; i < (h1 - h0) - (c1 - c0); i += kCgThreads) {
-      const int c = (i < nlo) ? h0 + i : c1 + (i - nlo);
+#pragma unroll
+    for (int k = 0; k < kHaloRegs; ++k) {
+      const int i = threadIdx.x + k * blockDim.x;
+      if (i < nhalo) {
+        const int c = halo_cell(i);
+        const double sv = first ? hwv[k] : hwv[k] + beta * hs[k];
+        const double rv = hr[k] - alpha * sv;
+        if constexpr (REG) stage[c - h0] = rv;
+        else stage[i] = rv;
+      }
+    }
+    for (int i = threadIdx.x + kHaloRegs * blockDim.x; i < nhalo; i += blockDim.x) {
+      const int c = halo_cell(i);
       const double sv = first ? pp[n + c] : pp[n + c] + beta * pp[2 * static_cast<size_t>(n) + c];
       const double rv = pp[c] - alpha * sv;
-      if constexpr (J > 0) stage[c - h0] = rv;
+      if constexpr (REG) stage[c - h0] = rv;
       else stage[i] = rv;
     }
     __syncthreads();
-    for (int j = 0; j < (J > 0 ? J : npass); ++j) {
-      const int c = own_cell(j);
-      double g = 0.0, d = 0.0;
-      if (c >= 0) {
-        double wv, rv, sv;
-        if constexpr (J > 0) {
-          wv = apply_cell(m, kr[j], c, rget);
-          wr[j] = wv;
-          rv = rr_[j];
-          sv = sr[j];
-        } else {
-          const CellCoef k = load_coef(a, c);
-          wv = apply_cell(m, k, c, rget);
-          a.gw[c] = wv;
-          rv = a.gr[c];
-          sv = a.gs[c];
-        }
-        g = rv * rv;
-        d = wv * rv;
-        if (in_boundary(c)) {
-          pn[c] = rv;
-          pn[n + c] = wv;
-          pn[2 * static_cast<size_t>(n) + c] = sv;
-        }
-      }
-      g = slice_tree256(g, lds);
-      d = slice_tree256(d, lds);
-      const int tb = tb0 + j * kCgSlices + sl;
-      if (t == 0 && tb < tb1) {
-        part[par ^ 1][tb] = g;
-        part[par ^ 1][nb + tb] = d;
-      }
-    }
-    if (!grid_barrier(a.barrier, epoch, G)) {
+    apply_pass(pub[par ^ 1], part[par ^ 1], false);
+    if (!group_barrier()) {
       status = -3;
       break;
     }
     par ^= 1;
     ++it;
-    const double gamma_new = tree_all(part[par], nb, lds, lds2);
-    delta = tree_all(part[par] + nb, nb, lds, lds2);
+    preload_halo(pub[par]);
+    double gamma_new = 0.0;
+    wave_tree_pairs(part[par], nb, gamma_new, delta);
     if (gamma_new <= thr) {
       status = 0;
       break;
@@ -1116,11 +1236,13 @@ __device__ void cg_solve(const CGArgs &a, int rank, int G)
     alpha = gamma_new / den;
     gamma = gamma_new;
   }
-  if constexpr (J > 0) {
+  if constexpr (REG) {
+    if (own) {
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int c = own_cell(j);
-      if (c >= 0) a.x[c] = xr[j];
+      for (int q = 0; q < 4; ++q) {
+        const int c = tbr * kTree + lane + 64 * q;
+        if (c < n) a.x[c] = xr[q];
+      }
     }
   }
   if (rank == 0 && threadIdx.x == 0) {
@@ -1129,78 +1251,33 @@ __device__ void cg_solve(const CGArgs &a, int rank, int G)
   }
 }
 
-template <int J>
-__global__ __launch_bounds__(kCgThreads) void cg_kernel(CGArgs a)
+template <bool REG>
+__global__ __launch_bounds__(kCgThreadsMax) void cg_kernel(CGArgs a)
 {
-  cg_solve<J>(a, blockIdx.x, gridDim.x);
+  cg_run<REG>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
-// Batched CG over a pool of P resident workgroups.  assign_cg_kernel (one
-// thread) hands every active Newton instance a contiguous group of
-// workgroups, one plus a share of the rest proportional to its cell count,
-// at most one per 256-cell tree block and kCgGroupMax; when the instances
-// outnumber the pool, each gets one workgroup and workgroup j serves the
-// active instances j, j + P, ... one after the other.  It also clears the
-// group barriers.  cg_batch_kernel then runs cg_solve<0> for every
-// (instance, rank) that names it.
+// Batched CG over a pool of resident workgroups.  The host hands every active
+// Newton instance a group of workgroups and writes, per workgroup, the list of
+// (instance, rank) jobs it takes part in; all lists follow one global job
+// order, so the earliest unfinished job always has every member at hand and
+// the pool cannot deadlock.  The solve of an instance does not depend on how
+// many workgroups serve it or where.
 // ---------------------------------------------------------------------------
-constexpr int kCgGroupMax = 64;
+struct CgJob {
+  int inst, rank, G, tb;     // tb: blocks per workgroup, bit 30 = register form
+};
+constexpr int kCgJobReg = 1 << 30;
 
-__global__ void assign_cg_kernel(Inst *insts, int n, int P, int batch)
+__global__ __launch_bounds__(kCgThreadsMax) void cg_batch_kernel(const Inst *__restrict__ insts,
+                                                                 const int *__restrict__ off,
+                                                                 const CgJob *__restrict__ jobs)
 {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  long long total = 0;
-  int active = 0;
-  for (int i = 0; i < n; ++i) {
-    Inst &in = insts[i];
-    in.cg_count = 0;
-    if (!in.newton || inst_idle(in, batch)) continue;
-    in.cg_barrier[0] = 0u;
-    in.cg_barrier[1] = 0u;
-    total += in.m.n_cells;
-    ++active;
-  }
-  if (active == 0) return;
-  if (active > P) {
-    int k = 0;
-    for (int i = 0; i < n; ++i) {
-      Inst &in = insts[i];
-      if (!in.newton || inst_idle(in, batch)) continue;
-      in.cg_first = k % P;
-      in.cg_count = 1;
-      ++k;
-    }
-    return;
-  }
-  const long long spare = P - active;
-  int next = 0;
-  for (int i = 0; i < n; ++i) {
-    Inst &in = insts[i];
-    if (!in.newton || inst_idle(in, batch)) continue;
-    long long g = 1 + (spare * in.m.n_cells) / total;
-    const int nbt = (in.m.n_cells + kTree - 1) / kTree;
-    if (g > nbt) g = nbt;
-    if (g > kCgGroupMax) g = kCgGroupMax;
-    const long long tb = (nbt + g - 1) / g;      // no workgroup left without tree blocks
-    g = (nbt + tb - 1) / tb;
-    in.cg_first = next;
-    in.cg_count = static_cast<int>(g);
-    next += static_cast<int>(g);
-  }
-}
-
-__global__ __launch_bounds__(kCgThreads) void cg_batch_kernel(const Inst *__restrict__ insts, int n,
-                                                              int batch)
-{
-  const int j = blockIdx.x;
-  for (int i = 0; i < n; ++i) {
-    const Inst &in = insts[i];
-    if (in.cg_count == 0 || !in.newton || inst_idle(in, batch)) continue;
-    const int rank = j - in.cg_first;
-    if (rank < 0 || rank >= in.cg_count) continue;
-    const int G = in.cg_count;
-    const int nbt = (in.m.n_cells + kTree - 1) / kTree;
+  const int e0 = off[blockIdx.x], e1 = off[blockIdx.x + 1];
+  for (int e = e0; e < e1; ++e) {
+    const CgJob jb = jobs[e];
+    const Inst &in = insts[jb.inst];
     CGArgs a;
     a.m = in.m;
     a.gx = in.gx;
@@ -1214,12 +1291,13 @@ __global__ __launch_bounds__(kCgThreads) void cg_batch_kernel(const Inst *__rest
     a.gs = in.cg_s;
     a.pub = in.cg_pub;
     a.part = in.cg_mpart;
-    a.TB = (nbt + G - 1) / G;
+    a.TB = jb.tb & (kCgJobReg - 1);
     a.tol2 = in.tol2;
     a.max_iters = in.cg_max;
     a.barrier = in.cg_barrier;
     a.sc = in.sc;
-    cg_solve<0>(a, rank, G);
+    if (jb.tb & kCgJobReg) cg_run<true>(a, jb.rank, jb.G);
+    else cg_run<false>(a, jb.rank, jb.G);
     __syncthreads();
   }
 }

@@ -33,9 +33,11 @@ def _diff(w):
     return Dx, Dy
 
 
+_LAUNCH_KEYS = ("cg_waves", "block_size")   # GPU launch shape only, no effect on results
+
+
 def _pair(oracle_mod, gpu, w, **kw):
-    o = oracle_mod.Oracle(w, **kw)
-    kw = dict(kw)
+    o = oracle_mod.Oracle(w, **{k: v for k, v in kw.items() if k not in _LAUNCH_KEYS})
     s = gpu.Solver(w, **kw)
     return o, s
 
@@ -226,25 +228,35 @@ def test_gpu_error_paths(gpu):
 
 
 NEWTON_LAYOUTS = {
-    # name: (workload factory) -- exercises the CG workgroup layouts
-    "strip_1x9": lambda: cavity_2d(n=1, ny=9, kn=0.05, particles=5000),
-    "slab_100": lambda: slab_1d(n=100, kn=0.003, particles=20_000),
-    "ragged_37x23": lambda: cavity_2d(n=37, ny=23, kn=0.01, particles=50_000),
-    "two_passes_300": lambda: cavity_2d(n=300, kn=0.01, particles=200_000),
-    "four_passes_512": lambda: cavity_2d(n=512, kn=0.005, particles=300_000),
-    "global_state_600": lambda: cavity_2d(n=600, kn=0.005, particles=300_000),
+    # name: (workload factory, cg_waves) -- the CG group layouts: one workgroup,
+    # ragged tree blocks, groups whose workgroups own less than a mesh row (the
+    # halo spans several owners), 1D halos, state in registers (cg_waves > 0)
+    # or in global memory (cg_waves < 0)
+    "strip_1x9": (lambda: cavity_2d(n=1, ny=9, kn=0.05, particles=5000), 0),
+    "slab_100": (lambda: slab_1d(n=100, kn=0.003, particles=20_000), 0),
+    "slab_1000_w1": (lambda: slab_1d(n=1000, kn=0.003, particles=50_000), 1),
+    "slab_1000_g1": (lambda: slab_1d(n=1000, kn=0.003, particles=50_000), -1),
+    "ragged_37x23": (lambda: cavity_2d(n=37, ny=23, kn=0.01, particles=50_000), 0),
+    "ragged_37x23_g3": (lambda: cavity_2d(n=37, ny=23, kn=0.01, particles=50_000), -3),
+    "wide_300x50_w1": (lambda: cavity_2d(n=300, ny=50, kn=0.01, particles=100_000), 1),
+    "wide_300x50_g1": (lambda: cavity_2d(n=300, ny=50, kn=0.01, particles=100_000), -1),
+    "groups_300": (lambda: cavity_2d(n=300, kn=0.01, particles=200_000), 0),
+    "groups_300_w12": (lambda: cavity_2d(n=300, kn=0.01, particles=200_000), 12),
+    "groups_300_g12": (lambda: cavity_2d(n=300, kn=0.01, particles=200_000), -12),
+    "groups_512": (lambda: cavity_2d(n=512, kn=0.005, particles=300_000), 0),
+    "groups_600": (lambda: cavity_2d(n=600, kn=0.005, particles=300_000), 0),
 }
 
 
 @pytest.mark.parametrize("name", list(NEWTON_LAYOUTS))
 def test_newton_cg_layouts_bitwise(oracle_mod, gpu, name):
     """One Newton iteration: CG iteration count, E and G bit-identical for every
-    workgroup layout of the CG kernel (one workgroup, ragged tree blocks,
-    one/two/four register passes, state in global memory)."""
-    w = NEWTON_LAYOUTS[name]()
+    workgroup layout of the CG kernel."""
+    make, waves = NEWTON_LAYOUTS[name]
+    w = make()
     Dx, Dy = _diff(w)
     o, s = _pair(oracle_mod, gpu, w, newton=True, diff_x=Dx, diff_y=Dy,
-                 tally_faces=oracle_mod.FACES_EVERY)
+                 tally_faces=oracle_mod.FACES_EVERY, cg_waves=waves)
     assert o.step(2) == 0 and s.step(2) == 0
     _same_iteration(o, s, name)
     assert o.info().cg_iters_total == s.stats()["cg_iters_total"]
