@@ -44,6 +44,7 @@ int fail(int code, const std::string &msg)
 
 constexpr int kCgGridMax = 64;               // workgroups of one CG group (barrier arrivals)
 constexpr int kCgWavesDefault = 8;           // tree blocks per CG workgroup of a single solve
+constexpr int kBarStride = 64;               // batched CG barriers 256 bytes apart (no shared lines)
 constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of a CG workgroup
 constexpr int kTileX = 8, kTileY = 8;        // emitter tile of one workgroup (cells)
 constexpr int kWallSeg = 8;                  // wall faces per workgroup
@@ -928,7 +929,7 @@ struct iugkp_batch {
   iugkp::CgJob *d_jobs = nullptr, *h_jobs = nullptr;
   int max_jobs = 0;
   DevScalars *d_scs = nullptr;       // every instance's scalars, contiguous
-  unsigned int *d_bars = nullptr;    // every instance's CG barrier [2]
+  unsigned int *d_bars = nullptr;    // every instance's CG barrier [2], kBarStride apart
   DevScalars *hsc = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -970,7 +971,7 @@ int enqueue_batch_iteration(iugkp_batch *b)
   iugkp::reconstruct_x_kernel<<<dim3(cdiv(b->max_ny, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
   iugkp::update_kernel<<<dim3(b->max_nbc, n), 256, 0, s>>>(b->d_insts, 1);
   if (b->any_newton) {
-    iugkp::zero_u32_kernel<<<cdiv(2 * n, 256), 256, 0, s>>>(b->d_bars, 2 * n);
+    iugkp::zero_u32_kernel<<<cdiv(kBarStride * n, 256), 256, 0, s>>>(b->d_bars, kBarStride * n);
     iugkp::cg_batch_kernel<<<b->cg_pool, iugkp::kCgThreadsMax, b->cg_lds, s>>>(b->d_insts, b->d_off,
                                                                                b->d_jobs);
     iugkp::newton_finish_kernel<<<dim3(b->max_nbe, n), 256, 0, s>>>(b->d_insts, 1);
@@ -1134,7 +1135,7 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
   if (hipMalloc(reinterpret_cast<void **>(&b->d_insts), n * sizeof(Inst)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&b->d_tiles), b->n_tiles * sizeof(TileDesc)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&b->d_scs), n * sizeof(DevScalars)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void **>(&b->d_bars), 2 * n * sizeof(unsigned int)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&b->d_bars), kBarStride * n * sizeof(unsigned int)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&b->d_off), (b->cg_pool + 1) * sizeof(int)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&b->d_jobs),
                 std::max(b->max_jobs, 1) * sizeof(iugkp::CgJob)) != hipSuccess ||
@@ -1152,7 +1153,7 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
     HIP_TRY(hipMemcpyAsync(b->d_scs + i, ih.d.sc, sizeof(DevScalars), hipMemcpyDeviceToDevice,
                            b->stream));
     ih.d.sc = b->d_scs + i;
-    ih.d.cg_barrier = b->d_bars + 2 * i;
+    ih.d.cg_barrier = b->d_bars + kBarStride * i;
   }
   HIP_TRY(hipStreamSynchronize(b->stream));
   if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||

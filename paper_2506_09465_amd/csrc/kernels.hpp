@@ -796,31 +796,42 @@ __global__ void newton_diag_kernel(Mesh m, const double *gx, const double *gy, d
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier for a persistent kernel whose workgroups are all resident (the
-// grid is sized from the occupancy query, at most one workgroup per CU).  A
-// monotone arrival counter at agent scope: barrier number k completes when the
-// counter reaches k * group (the group's workgroup count).  The release fence
-// before arriving and the acquire fence after leaving make the partial sums
-// written before the barrier visible to every workgroup, whichever XCD it runs
-// on.
-// ---------------------------------------------------------------------------
+// Data shared between the workgroups of a persistent group (published rows,
+// block sums) is only ever accessed with agent-scope atomic loads and stores
+// (xst / xld), which are coherent across the XCDs' L2 caches on their own.
+// The group barrier therefore needs no L2 writeback or invalidate: every wave
+// waits until its own stores have completed, the workgroup synchronises, and
+// one thread bumps a monotone arrival counter (agent-scope RMW); barrier
+// number k completes when the counter reaches k * group.  Readers poll the
+// counter and only then issue their (coherent) loads.  Ordinary accesses
+// stay private to one workgroup or cross kernel boundaries only.
 // counter[0] = arrivals, counter[1] = abort flag.  A wait longer than ~1 s sets
 // the abort flag; every workgroup then leaves its next barrier at once and the
 // kernel reports the failure, so a broken barrier can never hang the device.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void xst(double *p, double v)
+{
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double xld(const double *p)
+{
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr long kBarrierSpinLimit = 1l << 24;
 
 __device__ __forceinline__ bool grid_barrier(unsigned int *counter, unsigned int &epoch,
                                              unsigned int group)
 {
   __shared__ int s_abort;
+  __builtin_amdgcn_s_waitcnt(0);          // this wave's coherent stores have completed
   __syncthreads();
   epoch += 1;
   if (threadIdx.x == 0) {
-    // release: the workgroup's writes (ordered before by the workgroup
-    // barrier) become visible at agent scope before the arrival counts
     const unsigned int target = epoch * group;
     const unsigned int old =
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     long spins = 0;
     int abort = 0;
     if (old + 1u < target) {
@@ -838,9 +849,6 @@ __device__ __forceinline__ bool grid_barrier(unsigned int *counter, unsigned int
         }
       }
     }
-    // acquire: the other workgroups' writes are visible to this workgroup's
-    // loads after the workgroup barrier below
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_abort = abort;
   }
   __syncthreads();
@@ -945,50 +953,101 @@ __device__ __forceinline__ unsigned neighbour_mask(const Mesh &m, int c)
   return b;
 }
 
+// Lane l gets the value of lane l + s (s = 8, 4, 2, 1: DPP row shift within
+// the 16-lane row; 16 and 32: the gfx950 permlane swaps).  Only the lanes the
+// tree below reads are meaningful.
+template <int S>
+__device__ __forceinline__ double from_lane_plus(double v)
+{
+  const unsigned lo = static_cast<unsigned>(__double2loint(v));
+  const unsigned hi = static_cast<unsigned>(__double2hiint(v));
+  unsigned l2, h2;
+  if constexpr (S == 32) {
+    l2 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false)[1];
+    h2 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false)[1];
+  } else if constexpr (S == 16) {
+    l2 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false)[1];
+    h2 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false)[1];
+  } else {
+    static_assert(S == 8 || S == 4 || S == 2 || S == 1, "row shift");
+    l2 = static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(lo), 0x100 + S, 0xf, 0xf, false));
+    h2 = static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(hi), 0x100 + S, 0xf, 0xf, false));
+  }
+  return __hiloint2double(static_cast<int>(h2), static_cast<int>(l2));
+}
+
 // Pairwise tree of one 256-element block whose element l + 64 q sits in lane l
-// as v_q; the sum is valid in lane 0.
+// as v_q: (v_l + v_{l+128}) + (v_{l+64} + v_{l+192}), then r_l + r_{l+s} for
+// s = 32, 16, ..., 1.  The sum is valid in lane 0.
 __device__ __forceinline__ double wave_tree256(double v0, double v1, double v2, double v3)
 {
   double r = (v0 + v2) + (v1 + v3);
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) r = r + __shfl_down(r, s, 64);
+  r = r + from_lane_plus<32>(r);
+  r = r + from_lane_plus<16>(r);
+  r = r + from_lane_plus<8>(r);
+  r = r + from_lane_plus<4>(r);
+  r = r + from_lane_plus<2>(r);
+  r = r + from_lane_plus<1>(r);
   return r;
+}
+
+// lane 0's value in every lane
+__device__ __forceinline__ double lane0(double v)
+{
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 0);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 0);
+  return __hiloint2double(hi, lo);
 }
 
 // Sums of the nb published (g, d) pairs in the fixed order of the host-side
 // definition: the 256-element tree over each chunk of pairs, then the same
-// tree over the chunk sums (nb <= 65536).  Every lane of the calling wave gets
-// both results.
-__device__ __forceinline__ void wave_tree_pairs(const double *part, int nb, double &sg, double &sd)
+// tree over the chunk sums (nb <= 65536).  Every thread of the workgroup gets
+// both results.  One chunk: each wave reduces it itself.  More: wave w
+// reduces chunks w, w + nw, ... into LDS (red, 2 * 256 doubles), then every
+// wave reduces the chunk sums.
+__device__ __forceinline__ void group_tree_pairs(const double *part, int nb, double *red,
+                                                 double &sg, double &sd)
 {
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int nch = (nb + kTree - 1) / kTree;
-  double cg[4] = {0.0, 0.0, 0.0, 0.0}, cd[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = 0; k < nch; ++k) {
+  auto chunk = [&](int k, double &rg, double &rd) {
     double g[4], d[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = k * kTree + lane + 64 * q;
       const bool in = i < nb;
-      g[q] = in ? part[2 * i] : 0.0;
-      d[q] = in ? part[2 * i + 1] : 0.0;
+      g[q] = in ? xld(&part[2 * i]) : 0.0;
+      d[q] = in ? xld(&part[2 * i + 1]) : 0.0;
     }
-    const double rg = __shfl(wave_tree256(g[0], g[1], g[2], g[3]), 0, 64);
-    const double rd = __shfl(wave_tree256(d[0], d[1], d[2], d[3]), 0, 64);
-    if (nch == 1) {
-      sg = rg;
-      sd = rd;
-      return;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if ((k >> 6) == q && (k & 63) == lane) {
-        cg[q] = rg;
-        cd[q] = rd;
-      }
+    rg = wave_tree256(g[0], g[1], g[2], g[3]);
+    rd = wave_tree256(d[0], d[1], d[2], d[3]);
+  };
+  if (nch == 1) {
+    double rg, rd;
+    chunk(0, rg, rd);
+    sg = lane0(rg);
+    sd = lane0(rd);
+    return;
   }
-  sg = __shfl(wave_tree256(cg[0], cg[1], cg[2], cg[3]), 0, 64);
-  sd = __shfl(wave_tree256(cd[0], cd[1], cd[2], cd[3]), 0, 64);
+  for (int k = wave; k < nch; k += nw) {
+    double rg, rd;
+    chunk(k, rg, rd);
+    if (lane == 0) {
+      red[k] = rg;
+      red[kTree + k] = rd;
+    }
+  }
+  __syncthreads();
+  double g[4], d[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = lane + 64 * q;
+    g[q] = k < nch ? red[k] : 0.0;
+    d[q] = k < nch ? red[kTree + k] : 0.0;
+  }
+  sg = lane0(wave_tree256(g[0], g[1], g[2], g[3]));
+  sd = lane0(wave_tree256(d[0], d[1], d[2], d[3]));
+  __syncthreads();
 }
 
 // The solve as seen by one workgroup of rank `rank` in a group of G resident
@@ -998,6 +1057,7 @@ template <bool REG>
 __device__ void cg_run(const CGArgs &a, int rank, int G)
 {
   extern __shared__ double stage[];       // r on [h0, h1) (register form) or on the halo
+  __shared__ double red[2 * kTree];        // chunk sums when nb > 256
   unsigned int epoch = 0;
   const Mesh &m = a.m;
   const int n = m.n_cells;
@@ -1043,9 +1103,9 @@ __device__ void cg_run(const CGArgs &a, int rank, int G)
       hs[k] = 0.0;
       if (i < nhalo) {
         const int c = halo_cell(i);
-        hr[k] = pp[c];
-        hwv[k] = pp[n + c];
-        hs[k] = pp[2 * static_cast<size_t>(n) + c];
+        hr[k] = xld(&pp[c]);
+        hwv[k] = xld(&pp[n + c]);
+        hs[k] = xld(&pp[2 * static_cast<size_t>(n) + c]);
       }
     }
   };
@@ -1069,17 +1129,17 @@ __device__ void cg_run(const CGArgs &a, int rank, int G)
           g[q] = rr[q] * rr[q];
           d[q] = wv * rr[q];
           if (bits & 16u) {
-            pn[c] = rr[q];
-            pn[n + c] = wv;
-            pn[2 * static_cast<size_t>(n) + c] = sr[q];
+            xst(&pn[c], rr[q]);
+            xst(&pn[n + c], wv);
+            xst(&pn[2 * static_cast<size_t>(n) + c], sr[q]);
           }
         }
       }
       const double sg = wave_tree256(g[0], g[1], g[2], g[3]);
       const double sd = wave_tree256(d[0], d[1], d[2], d[3]);
       if (lane == 0) {
-        pt[2 * tbr] = sg;
-        pt[2 * tbr + 1] = sd;
+        xst(&pt[2 * tbr], sg);
+        xst(&pt[2 * tbr + 1], sd);
       }
     } else {
       for (int tb = tb0 + wave; tb < tb1; tb += nw) {
@@ -1097,23 +1157,24 @@ __device__ void cg_run(const CGArgs &a, int rank, int G)
             g[q] = rv * rv;
             d[q] = wv * rv;
             if (published(c)) {
-              pn[c] = rv;
-              pn[n + c] = wv;
-              pn[2 * static_cast<size_t>(n) + c] = start ? 0.0 : a.gs[c];
+              xst(&pn[c], rv);
+              xst(&pn[n + c], wv);
+              xst(&pn[2 * static_cast<size_t>(n) + c], start ? 0.0 : a.gs[c]);
             }
           }
         }
         const double sg = wave_tree256(g[0], g[1], g[2], g[3]);
         const double sd = wave_tree256(d[0], d[1], d[2], d[3]);
         if (lane == 0) {
-          pt[2 * tb] = sg;
-          pt[2 * tb + 1] = sd;
+          xst(&pt[2 * tb], sg);
+          xst(&pt[2 * tb + 1], sd);
         }
       }
     }
   };
   auto group_barrier = [&]() -> bool {
     if (G == 1) {
+      __builtin_amdgcn_s_waitcnt(0);      // coherent stores complete before other waves read
       __syncthreads();
       return true;
     }
@@ -1151,7 +1212,7 @@ __device__ void cg_run(const CGArgs &a, int rank, int G)
   if (!group_barrier()) status = -3;
   preload_halo(pub[0]);
   double gamma = 0.0, delta = 0.0;
-  wave_tree_pairs(part[0], nb, gamma, delta);
+  group_tree_pairs(part[0], nb, red, gamma, delta);
   const double thr = a.tol2 * gamma;
   int it = 0, par = 0;
   double alpha = 0.0, beta = 0.0;
@@ -1205,8 +1266,9 @@ __device__ void cg_run(const CGArgs &a, int rank, int G)
     }
     for (int i = threadIdx.x + kHaloRegs * blockDim.x; i < nhalo; i += blockDim.x) {
       const int c = halo_cell(i);
-      const double sv = first ? pp[n + c] : pp[n + c] + beta * pp[2 * static_cast<size_t>(n) + c];
-      const double rv = pp[c] - alpha * sv;
+      const double sw = xld(&pp[n + c]);
+      const double sv = first ? sw : sw + beta * xld(&pp[2 * static_cast<size_t>(n) + c]);
+      const double rv = xld(&pp[c]) - alpha * sv;
       if constexpr (REG) stage[c - h0] = rv;
       else stage[i] = rv;
     }
@@ -1220,7 +1282,7 @@ __device__ void cg_run(const CGArgs &a, int rank, int G)
     ++it;
     preload_halo(pub[par]);
     double gamma_new = 0.0;
-    wave_tree_pairs(part[par], nb, gamma_new, delta);
+    group_tree_pairs(part[par], nb, red, gamma_new, delta);
     if (gamma_new <= thr) {
       status = 0;
       break;
