@@ -40,8 +40,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true", help="skip time-to-steady")
-    ap.add_argument("--batch", type=int, default=0,
-                    help="also time N batched vs sequential uneven cavity solves")
+    ap.add_argument("--batch", type=int, default=256,
+                    help="instances of the batched vs sequential comparison (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="particles per iteration in the CPU oracle sample")
     return ap.parse_args()
@@ -144,18 +144,19 @@ def bench_batch(P, dev, count):
     ws = batch_workloads(count=count)
     kw = dict(rng_mode=P.RNG_CRN, tally_faces=P.FACES_FINAL, max_iters=60, res_tol=1e-6)
     seq_status = []
+    solvers = [P.Solver(w, device=dev, **kw) for w in ws]
     torch.cuda.synchronize()
     a = time.perf_counter()
-    for w in ws:
-        s = P.Solver(w, device=dev, **kw)
+    for s in solvers:
         try:
             rc = s.solve()[0]
         except P.IugkpError as e:
             rc = e.code
         seq_status.append(rc)
-        s.close()
     torch.cuda.synchronize()
     seq = time.perf_counter() - a
+    for s in solvers:
+        s.close()
     bs = P.BatchSolver(ws, device=dev, **kw)
     torch.cuda.synchronize()
     a = time.perf_counter()
