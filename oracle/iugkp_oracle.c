@@ -278,12 +278,19 @@ static int orc_validate(const orc_problem *p)
   if (p->T_init)
     for (int c = 0; c < nc; ++c)
       if (!isfinite(p->T_init[c])) return ORC_E_INVALID_ARG;
+  if (p->source)
+    for (int c = 0; c < nc; ++c)
+      if (!isfinite(p->source[c])) return ORC_E_INVALID_ARG;
   return ORC_OK;
 }
 
 /* Scale exponent F = 62 - ceil(log2 B) with
  * B = 4 max(|E_wall|, |E_0|) (sum of cell volumes + lambda_min * (sum of wall areas) / 4),
- * the bound on one iteration's total |emission| times a safety factor 4. */
+ * the bound on one iteration's total |emission| times a safety factor 4.
+ * With a volumetric source the energy level is raised by at most about
+ * S_max tau_min times the number of iterations energy stays in the domain,
+ * bounded by 1 + 3 (L / lambda_min)^2 (L the longer side): B uses
+ * max(|E_wall|, |E_0|) + S_max tau_min (1 + 3 (L / lambda_min)^2) instead. */
 int orc_fixed_exponent(const orc_problem *p, double *tau_min_out)
 {
   int nc = p->nx * p->ny;
@@ -307,6 +314,17 @@ int orc_fixed_exponent(const orc_problem *p, double *tau_min_out)
                               : 2.0;
   double total = vol + (lam_min * area) / 4.0;
   double B = (4.0 * maxabs) * total;
+  double smax = 0.0;
+  if (p->source)
+    for (int c = 0; c < nc; ++c)
+      if (fabs(p->source[c]) > smax) smax = fabs(p->source[c]);
+  if (smax > 0.0) {
+    double L = (double)p->nx * p->dx;
+    if (p->dim == 2 && (double)p->ny * p->dy > L) L = (double)p->ny * p->dy;
+    double rl = L / lam_min;
+    double esrc = (smax * tmin) * (1.0 + 3.0 * (rl * rl));
+    B = (4.0 * (maxabs + esrc)) * total;
+  }
   if (!(B > 0.0)) return 62;
   int e;
   double m = frexp(B, &e);          /* B = m 2^e, m in [0.5, 1) */
@@ -326,6 +344,8 @@ struct orc_state {
   int F;
   double tau_min, lam_min, V;
   double *ratio;       /* tau_min / tau_c */
+  double *source;      /* volumetric source per cell or NULL */
+  int64_t *Gs;         /* its emission per iteration, fixed point */
   double *E;           /* E^n */
   double *E_half;      /* W / V of the last iteration */
   int64_t *G;          /* emission energies of the next iteration, per emitter */
@@ -341,6 +361,7 @@ struct orc_state {
 
 typedef struct {
   int64_t *D, *W, *Phix, *Phiy, *B;
+  int end;             /* where the last particle ended: cell, or -1 - wall face */
   int faces;
   uint64_t crossings;
   int32_t *events;     /* optional crossing log */
@@ -356,6 +377,14 @@ static int64_t orc_to_fixed(double v, int F, int *ok)
     return 0;
   }
   return (int64_t)rint(s);
+}
+
+/* a + b for |a|, |b| <= 2^62 without signed overflow; *ok = 0 if |a + b| > 2^62 */
+static int64_t orc_add(int64_t a, int64_t b, int *ok)
+{
+  int64_t r = (int64_t)((uint64_t)a + (uint64_t)b);
+  if (r > ((int64_t)1 << 62) || r < -((int64_t)1 << 62)) *ok = 0;
+  return r;
 }
 
 static int orc_check_budget(const int64_t *G, int n)
@@ -522,6 +551,7 @@ void orc_destroy(orc_state *s)
   free(s->ratio); free(s->E); free(s->E_half); free(s->G);
   free(s->D); free(s->W); free(s->Phix); free(s->Phiy); free(s->B);
   free(s->gx); free(s->gy); free(s->diag); free(s->res_hist);
+  free(s->source); free(s->Gs);
   free(s);
 }
 
@@ -560,6 +590,8 @@ int orc_create(const orc_problem *p, const orc_options *o, orc_state **out)
   s->p.diff_x = s->diff_x;
   s->p.diff_y = s->diff_y;
   s->p.T_init = NULL;
+  s->source = orc_dup(p->source, s->nc);
+  s->p.source = s->source;
   s->N = o->particles_per_iter / (uint64_t)s->ne;
   if (s->N < 1) s->N = 1;
   s->F = orc_fixed_exponent(p, &s->tau_min);
@@ -582,8 +614,14 @@ int orc_create(const orc_problem *p, const orc_options *o, orc_state **out)
     s->E[c] = p->cv * (T0 - p->t_ref);
   }
   int ok = 1;
-  /* cell emission: (E V) tau_min/tau (Sec. 3.2, candidate rate tau_min) */
-  for (int c = 0; c < s->nc; ++c) s->G[c] = orc_to_fixed((s->E[c] * s->V) * s->ratio[c], s->F, &ok);
+  /* source emission per iteration: S V tau_min */
+  s->Gs = (int64_t *)calloc((size_t)s->nc, sizeof(int64_t));
+  if (s->source)
+    for (int c = 0; c < s->nc; ++c)
+      s->Gs[c] = orc_to_fixed((s->source[c] * s->V) * s->tau_min, s->F, &ok);
+  /* cell emission: (E V) tau_min/tau (Sec. 3.2, candidate rate tau_min), plus the source */
+  for (int c = 0; c < s->nc; ++c)
+    s->G[c] = orc_add(orc_to_fixed((s->E[c] * s->V) * s->ratio[c], s->F, &ok), s->Gs[c], &ok);
   /* wall emission, reading R1 */
   for (int b = 0; b < s->nb; ++b) {
     double A = (b < 2 * p->ny) ? p->dy : p->dx;
@@ -724,6 +762,7 @@ static void orc_fly(orc_state *s, uint32_t slot, int e, uint32_t k, int64_t q, o
     int bface = -1;
     if (orc_march(p, x0, y0, &ix, &iy, sx, sy, inv_sx, inv_sy, ell, q, t, &bface)) {
       t->B[bface] += q;
+      t->end = -1 - bface;
       return;
     }
     int c = ix + nx * iy;
@@ -731,6 +770,7 @@ static void orc_fly(orc_state *s, uint32_t slot, int e, uint32_t k, int64_t q, o
     /* accept as a real collision with probability sigma/sigma_max = tau_min/tau */
     if (uacc < s->ratio[c] || j == ORC_MAX_SEGMENTS - 1) {
       t->D[c] += q;
+      t->end = c;
       return;
     }
     /* null collision: same direction, new free path from the stopping point */
@@ -811,12 +851,13 @@ static int orc_iterate(orc_state *s, int faces)
     s->cg_last = its;
     s->cg_total += its;
     for (int c = 0; c < s->nc; ++c) E_new[c] = s->E_half[c] + x[c];
-    for (int c = 0; c < s->nc; ++c) s->G[c] = orc_to_fixed((E_new[c] * s->V) * s->ratio[c], s->F, &ok);
+    for (int c = 0; c < s->nc; ++c)
+      s->G[c] = orc_add(orc_to_fixed((E_new[c] * s->V) * s->ratio[c], s->F, &ok), s->Gs[c], &ok);
     free(r);
     free(x);
   } else {
     for (int c = 0; c < s->nc; ++c) E_new[c] = s->E_half[c];
-    for (int c = 0; c < s->nc; ++c) s->G[c] = s->D[c];   /* re-emit W^h */
+    for (int c = 0; c < s->nc; ++c) s->G[c] = orc_add(s->D[c], s->Gs[c], &ok);   /* re-emit W^h */
   }
   for (int c = 0; c < s->nc; ++c) {
     double d = E_new[c] - s->E[c];
@@ -949,4 +990,124 @@ int orc_set_state(orc_state *s, uint32_t iter, double d0, const double *E, const
   memcpy(s->E, E, sizeof(double) * s->nc);
   memcpy(s->G, G, sizeof(int64_t) * s->ne);
   return orc_check_budget(s->G, s->ne) ? ORC_OK : ORC_E_FIXED_OVERFLOW;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the steady state                                               */
+/* ------------------------------------------------------------------------ */
+/* With a uniform relaxation time every candidate collision is real, and with
+ * common random numbers the particle paths depend only on their counters, not
+ * on the weights: one iteration is the linear map
+ *   D = T_cc G_cells + T_cw G_walls,   T_xe = (1/N) #{k : particle (e,k) ends in x},
+ * and re-emission G_cells = D + G_src gives the steady state
+ *   D* = (I - T_cc)^-1 (T_cc G_src + T_cw G_walls),  T = t_ref + ldexp(D*, -F) / (V C).
+ * For a loss L(T), with u = dL/dD* and psi = (I - T_cc^T)^-1 u,
+ *   dL/dG_src = T_cc^T psi,  dL/dG_walls = T_cw^T psi.
+ * (T^T psi)_e is the mean of psi over the cells where emitter e's N particles
+ * end: the same paths used in reverse.  psi is the fixed point of
+ * psi <- T^T psi + u, each pass optionally followed by the diffusion
+ * correction of the forward solve (same operator, same CG).  Chain rule to
+ * the inputs: G_src = ldexp(S V tau_min, F), G_f = ldexp(C (T_f - t_ref)
+ * lambda_min A_f / 4, F). */
+static void orc_gather(const orc_state *s, const int32_t *end, const double *psi, double *vals,
+                       double *g)
+{
+  uint64_t N = s->N;
+  for (int e = 0; e < s->ne; ++e) {
+    for (uint64_t k = 0; k < N; ++k) {
+      int32_t a = end[(uint64_t)e * N + k];
+      vals[k] = (a >= 0) ? psi[a] : 0.0;
+    }
+    g[e] = orc_tree_sum(vals, N) / (double)N;
+  }
+}
+
+int orc_adjoint(orc_state *s, const double *dLdT, double *grad_wall, double *grad_source,
+                int max_iters, double tol, int *iters_out)
+{
+  const orc_problem *p = &s->p;
+  if (iters_out) *iters_out = 0;
+  if (s->o.rng_mode != ORC_RNG_CRN || max_iters < 1 || !(tol >= 0.0) || !dLdT)
+    return ORC_E_INVALID_ARG;
+  for (int c = 0; c < s->nc; ++c)
+    if (s->ratio[c] != 1.0 || !isfinite(dLdT[c])) return ORC_E_INVALID_ARG;
+  int nc = s->nc, ne = s->ne;
+  uint64_t N = s->N;
+  uint32_t slot = s->o.rng_epoch;
+  /* where every particle ends (the weight does not change the path) */
+  int32_t *end = (int32_t *)malloc(sizeof(int32_t) * (size_t)ne * N);
+  int64_t *sD = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+  int64_t *sW = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+  int64_t *sB = (int64_t *)calloc((size_t)s->nb, sizeof(int64_t));
+  orc_tally t;
+  memset(&t, 0, sizeof t);
+  t.D = sD; t.W = sW; t.B = sB; t.faces = 0;
+  uint64_t segs = 0;
+  for (int e = 0; e < ne; ++e)
+    for (uint64_t k = 0; k < N; ++k) {
+      orc_fly(s, slot, e, (uint32_t)k, 1, &t, &segs);
+      end[(uint64_t)e * N + k] = (t.end >= 0) ? t.end : -1;
+    }
+  double *u = (double *)malloc(sizeof(double) * nc);
+  double *psi = (double *)malloc(sizeof(double) * nc);
+  double *half = (double *)malloc(sizeof(double) * nc);
+  double *nw = (double *)malloc(sizeof(double) * nc);
+  double *tmp = (double *)malloc(sizeof(double) * nc);
+  double *r = (double *)malloc(sizeof(double) * nc);
+  double *x = (double *)malloc(sizeof(double) * nc);
+  double *vals = (double *)malloc(sizeof(double) * N);
+  double *g = (double *)malloc(sizeof(double) * ne);
+  /* u = dL/dD* since T_c = t_ref + ldexp(D_c, -F) / V / C */
+  for (int c = 0; c < nc; ++c) u[c] = ldexp((dLdT[c] / p->cv) / s->V, -s->F);
+  for (int c = 0; c < nc; ++c) psi[c] = u[c];
+  int rc = ORC_W_NOT_CONVERGED, passes = 0;
+  double d0 = 0.0;
+  for (int m = 0; m < max_iters; ++m) {
+    orc_gather(s, end, psi, vals, g);
+    for (int c = 0; c < nc; ++c) half[c] = g[c] + u[c];
+    if (s->o.newton) {
+      for (int c = 0; c < nc; ++c) r[c] = half[c] - psi[c];
+      int its = 0;
+      int crc = orc_cg(p, s->gx, s->gy, s->diag, r, x, s->o.cg_tol, s->o.cg_max_iters, &its);
+      if (crc) {
+        rc = crc;
+        break;
+      }
+      for (int c = 0; c < nc; ++c) nw[c] = half[c] + x[c];
+    } else {
+      for (int c = 0; c < nc; ++c) nw[c] = half[c];
+    }
+    for (int c = 0; c < nc; ++c) {
+      double d = nw[c] - psi[c];
+      tmp[c] = d * d;
+    }
+    double dn = sqrt(orc_tree_sum(tmp, (uint64_t)nc));
+    if (m == 0) d0 = dn;
+    double res = (d0 > 0.0) ? dn / d0 : 0.0;
+    for (int c = 0; c < nc; ++c) psi[c] = nw[c];
+    passes = m + 1;
+    if (!isfinite(res)) {
+      rc = ORC_E_NONFINITE;
+      break;
+    }
+    if (res < tol) {
+      rc = ORC_OK;
+      break;
+    }
+  }
+  if (rc >= 0) {
+    orc_gather(s, end, psi, vals, g);
+    double fs = ldexp(s->V * s->tau_min, s->F);
+    if (grad_source)
+      for (int c = 0; c < nc; ++c) grad_source[c] = g[c] * fs;
+    if (grad_wall)
+      for (int b = 0; b < s->nb; ++b) {
+        double A = (b < 2 * p->ny) ? p->dy : p->dx;
+        grad_wall[b] = g[nc + b] * ldexp((p->cv * (s->lam_min * A)) / 4.0, s->F);
+      }
+  }
+  if (iters_out) *iters_out = passes;
+  free(end); free(sD); free(sW); free(sB);
+  free(u); free(psi); free(half); free(nw); free(tmp); free(r); free(x); free(vals); free(g);
+  return rc;
 }

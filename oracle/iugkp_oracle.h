@@ -20,7 +20,10 @@
  *     probability sigma(x)/sigma_max = tau_min/tau(x), total tally W (null +
  *     real) and real tally W^h, re-emission from W^h;
  *   - Sec. 3.3, inexact Newton with the diffusion-type operator
- *     div(-kappa grad dT) on the energy residual between iterations.
+ *     div(-kappa grad dT) on the energy residual between iterations;
+ *   - beyond the paper: a volumetric heat source (extra isotropic emission
+ *     S V tau_min per cell and iteration) and the adjoint of the steady state
+ *     with respect to the wall temperatures and the source (orc_adjoint).
  * Every point the paper leaves open is fixed by a reading stated next to the
  * function that implements it.
  */
@@ -58,6 +61,7 @@ typedef struct orc_problem {
   const double *T_init; /* [nx*ny] initial temperature or NULL (-> t_ref) */
   const double *diff_x; /* [nx*ny] per-iteration diffusion coefficient along x (Newton), or NULL */
   const double *diff_y; /* [nx*ny] along y (2D Newton), or NULL */
+  const double *source; /* [nx*ny] volumetric heat source S (energy per volume and time), or NULL */
 } orc_problem;
 
 typedef struct orc_options {
@@ -126,6 +130,15 @@ void orc_get_E(const orc_state *s, double *E);
 void orc_get_G(const orc_state *s, int64_t *G);
 void orc_get_residuals(const orc_state *s, double *res, int max_n);
 int orc_set_state(orc_state *s, uint32_t iter, double d0, const double *E, const int64_t *G);
+
+/* Adjoint of the steady state (uniform relaxation time, common random numbers):
+ * given dL/dT per cell, the gradient of L with respect to every wall face's
+ * temperature (grad_wall [n_b]) and every cell's source (grad_source [nc]),
+ * for the particle paths of slot rng_epoch.  Iterates to a relative change
+ * below tol (at most max_iters passes), with the forward solve's diffusion
+ * correction when the state was created with newton.  *iters_out = passes. */
+int orc_adjoint(orc_state *s, const double *dLdT, double *grad_wall, double *grad_source,
+                int max_iters, double tol, int *iters_out);
 
 #ifdef __cplusplus
 }

@@ -46,7 +46,8 @@ class _Problem(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("dx", C.c_double),
                 ("dy", C.c_double), ("t_ref", C.c_double), ("cv", C.c_double),
                 ("vg", C.c_double), ("tau", C.c_void_p), ("wall_T", C.c_void_p),
-                ("T_init", C.c_void_p), ("diff_x", C.c_void_p), ("diff_y", C.c_void_p)]
+                ("T_init", C.c_void_p), ("diff_x", C.c_void_p), ("diff_y", C.c_void_p),
+                ("source", C.c_void_p)]
 
 
 class _Options(C.Structure):
@@ -105,6 +106,7 @@ def lib():
         L.orc_get_G.argtypes = [P, P]
         L.orc_get_residuals.argtypes = [P, P, C.c_int]
         L.orc_set_state.argtypes = [P, C.c_uint32, C.c_double, P, P]
+        L.orc_adjoint.argtypes = [P, P, P, P, C.c_int, C.c_double, P]
         _lib = L
     return _lib
 
@@ -172,9 +174,11 @@ class _Keep:
         self.T_init = None if Ti is None else np.ascontiguousarray(Ti, dtype=np.float64)
         self.dxa = None if diff_x is None else np.ascontiguousarray(diff_x, dtype=np.float64)
         self.dya = None if diff_y is None else np.ascontiguousarray(diff_y, dtype=np.float64)
+        S = getattr(w, "source", None)
+        self.src = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
         self.p = _Problem(w.dim, w.nx, w.ny, w.dx, w.dy, w.t_ref, w.cv, w.vg,
                           self.tau.ctypes.data, self.wall.ctypes.data, _ptr(self.T_init),
-                          _ptr(self.dxa), _ptr(self.dya))
+                          _ptr(self.dxa), _ptr(self.dya), _ptr(self.src))
 
 
 def fixed_exponent(w) -> int:
@@ -310,6 +314,17 @@ class Oracle:
         E = np.ascontiguousarray(E, dtype=np.float64)
         G = np.ascontiguousarray(G, dtype=np.int64)
         return lib().orc_set_state(self.h, it, d0, E.ctypes.data, G.ctypes.data)
+
+    def adjoint(self, dLdT, max_iters=200, tol=1e-10):
+        """Gradient of L with respect to every wall face temperature and every
+        cell source, given dL/dT per cell (steady state, CRN paths)."""
+        g = np.ascontiguousarray(dLdT, dtype=np.float64)
+        gw = np.zeros(self.nb)
+        gs = np.zeros(self.nc)
+        its = C.c_int(0)
+        rc = lib().orc_adjoint(self.h, g.ctypes.data, gw.ctypes.data, gs.ctypes.data,
+                               int(max_iters), float(tol), C.addressof(its))
+        return rc, gw, gs, its.value
 
     def solve(self):
         T = np.zeros(self.nc)

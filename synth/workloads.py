@@ -41,6 +41,7 @@ class Workload:
     tau: np.ndarray            # (ny*nx,) float64, cell c = ix + nx*iy
     wall_T: np.ndarray         # (n_bfaces,) float64: left rows, right rows, bottom cols, top cols
     T_init: Optional[np.ndarray] = None   # (ny*nx,) or None -> t_ref everywhere
+    source: Optional[np.ndarray] = None   # (ny*nx,) volumetric heat source or None
     # run options
     seed: int = 0
     particles_per_iter: int = 100_000
@@ -189,3 +190,37 @@ def batch_workloads(count: int = 256, seed: int = 2506, newton: bool = True) -> 
         w.wall_T = _walls_2d(inst.n, inst.n, *inst.walls)
         ws.append(w)
     return ws
+
+
+def gaussian_source(nx: int, ny: int, dx: float, dy: float, amp: float,
+                    width: float) -> np.ndarray:
+    """amp * exp(-r^2 / (2 width^2)) at the cell centres, r from the domain centre."""
+    x = (np.arange(nx) + 0.5) * dx - 0.5 * nx * dx
+    y = (np.arange(ny) + 0.5) * dy - 0.5 * ny * dy
+    r2 = x[None, :] ** 2 + y[:, None] ** 2
+    return (amp * np.exp(-r2 / (2.0 * width * width))).reshape(-1).astype(np.float64)
+
+
+@dataclasses.dataclass
+class AdjointCase:
+    """Probe-misfit problem: a cavity with a Gaussian source, probe cells and
+    the target temperatures there; loss = sum over probes (T_p - target_p)^2."""
+
+    workload: Workload
+    probes: np.ndarray          # (n_probes,) int64 cell indices, distinct
+    target: np.ndarray          # (n_probes,) float64
+    walls4: np.ndarray          # (4,) left, right, bottom, top wall temperatures
+
+
+def adjoint_case(n: int = 256, kn: float = 0.1, n_probes: int = 64, particles: int = 10_000_000,
+                 amp: float = 0.01, width: float = 0.05, seed: int = 0) -> AdjointCase:
+    """The 2D cavity (top 1.01, others 0.99) with a Gaussian source of width
+    0.05 L at the centre, n_probes distinct random probe cells and target
+    temperatures drawn uniformly in [0.99, 1.01] (numpy default_rng(seed))."""
+    w = cavity_2d(n=n, kn=kn, particles=particles, seed=seed, newton=True,
+                  name=f"adjoint{n}_kn{kn}")
+    w.source = gaussian_source(n, n, w.dx, w.dy, amp, width * n * w.dx)
+    rng = np.random.default_rng(seed)
+    probes = np.sort(rng.choice(n * n, size=n_probes, replace=False)).astype(np.int64)
+    target = rng.uniform(0.99, 1.01, size=n_probes)
+    return AdjointCase(w, probes, target, np.array([0.99, 0.99, 0.99, 1.01]))

@@ -89,11 +89,13 @@ class Slab:
         """E^{n+1} = E[W]/V for emission from E (no Newton)."""
         return self.expected_W(self.cell_emission(E)) / self.V
 
-    def fixed_point(self):
-        """Steady state of the D re-emission map G -> D, returned as E = W/V."""
+    def fixed_point(self, source=None):
+        """Steady state of the re-emission map G -> D + G_src (G_src = S V tau_min
+        per iteration, zero without a source), returned as E = W/V."""
         n = self.tau.size
         A = np.eye(n) - self.K.T
-        G = np.linalg.solve(A, self.Gw @ self.Pw)
+        Gs = np.zeros(n) if source is None else np.asarray(source) * self.V * self.tau_min
+        G = np.linalg.solve(A, self.Gw @ self.Pw + Gs)
         return self.expected_W(G) / self.V, G
 
     def heat_flux_left(self, G):
