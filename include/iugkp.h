@@ -85,7 +85,11 @@ typedef struct iugkp_problem {
   const double *diff_x; /* [n_cells] Newton diffusion coefficient along x per iteration, or
                            NULL: the library uses D_eff(|V_g| tau_c, dx) (iugkp_d_eff) */
   const double *diff_y; /* [n_cells] the same along y (2D), or NULL */
-  int mem_kind;         /* IUGKP_MEM_HOST or IUGKP_MEM_DEVICE for the arrays above */
+  int mem_kind;         /* IUGKP_MEM_HOST or IUGKP_MEM_DEVICE for the arrays above and below */
+  const double *source; /* [n_cells] volumetric heat source S (energy per volume and time), or
+                           NULL.  Each cell emits S V tau_min more per iteration, isotropically
+                           from uniform positions like its equilibrium emission (an addition to
+                           the gray model of Sec. 2-3) */
 } iugkp_problem;
 
 typedef struct iugkp_options {
@@ -177,6 +181,31 @@ int iugkp_set_state(iugkp_handle *h, uint32_t iter, double d0, const double *E,
 int iugkp_get_residuals(iugkp_handle *h, double *res, int max_n);
 
 int iugkp_get_stats(iugkp_handle *h, iugkp_stats *stats);
+
+/* Adjoint of the steady state reached by this handle (an addition to the
+ * paper, which has no adjoint): given dL/dT per cell for a loss L(T), the
+ * gradient of L with respect to every wall face's temperature and every
+ * cell's source S.  Needs rng_mode CRN (the particle paths of slot rng_epoch)
+ * and a uniform relaxation time; at most 65536 particles per emitter.
+ * With fixed counters one iteration is linear in the emission energies,
+ *   D = T_cc G_cells + T_cw G_walls   (T_xe = share of emitter e's particles
+ *                                      ending in cell x),
+ * so with psi = (I - T_cc^T)^-1 dL/dD the gradients are T_cc^T psi (source)
+ * and T_cw^T psi (walls), chained through G_src = 2^F S V tau_min and
+ * G_f = 2^F C (T_f - t_ref) lambda_min A_f / 4.  T^T psi at an emitter is the
+ * mean of psi over the cells where its particles end: the forward paths
+ * traced again and used in reverse.  psi is iterated as psi <- T^T psi + u
+ * (with the handle's diffusion correction when newton is on) until the
+ * relative change ||psi' - psi|| / ||first change|| < tol, at most max_iters
+ * passes.  dLdT [n_cells] is read and grad_wall [n_b], grad_source [n_cells]
+ * (either may be NULL) are written in the problem's mem_kind; *iters_out
+ * (optional) = passes.  Returns IUGKP_OK, IUGKP_W_NOT_CONVERGED (gradients
+ * written from the last psi), or an error: INVALID_ARG (arguments, FRESH
+ * mode, varying tau, N > 65536), NOMEM, DEVICE, CG_BREAKDOWN,
+ * CG_NOT_CONVERGED, NONFINITE.  Enqueued on the handle's stream and
+ * synchronised before returning. */
+int iugkp_adjoint(iugkp_handle *h, const double *dLdT, double *grad_wall, double *grad_source,
+                  int max_iters, double tol, int *iters_out);
 
 /* Per-iteration diffusion coefficient of the flat-cell kernel used by the Newton
  * operator when none is given: half the second moment of one cell-to-cell jump,

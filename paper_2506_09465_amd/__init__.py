@@ -7,7 +7,8 @@ this package only marshals arguments to it.
 from ._lib import (FACES_EVERY, FACES_FINAL, FACES_OFF, RNG_CRN, RNG_FRESH, IugkpError,
                    lib as library)
 
-__all__ = ["Solver", "BatchSolver", "d_eff", "dev_philox", "dev_math", "FACES_EVERY",
+__all__ = ["Solver", "BatchSolver", "steady_temperature", "d_eff", "dev_philox", "dev_math",
+           "FACES_EVERY",
            "FACES_FINAL", "FACES_OFF", "RNG_CRN", "RNG_FRESH", "IugkpError", "library"]
 
 
@@ -19,4 +20,7 @@ def __getattr__(name):
     if name == "BatchSolver":
         from . import batch
         return batch.BatchSolver
+    if name == "steady_temperature":
+        from . import adjoint
+        return adjoint.steady_temperature
     raise AttributeError(name)

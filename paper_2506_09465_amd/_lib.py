@@ -28,7 +28,7 @@ class Problem(C.Structure):
                 ("dy", C.c_double), ("t_ref", C.c_double), ("cv", C.c_double),
                 ("vg", C.c_double), ("tau", C.c_void_p), ("wall_T", C.c_void_p),
                 ("T_init", C.c_void_p), ("diff_x", C.c_void_p), ("diff_y", C.c_void_p),
-                ("mem_kind", C.c_int)]
+                ("mem_kind", C.c_int), ("source", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -66,6 +66,7 @@ SIGNATURES = [
     ("iugkp_get_residuals", C.c_int, [P, P, C.c_int]),
     ("iugkp_get_stats", C.c_int, [P, C.POINTER(Stats)]),
     ("iugkp_d_eff", C.c_double, [C.c_double, C.c_double]),
+    ("iugkp_adjoint", C.c_int, [P, P, P, P, C.c_int, C.c_double, P]),
     ("iugkp_batch_create", C.c_int, [P, P, C.c_int, P, C.POINTER(P)]),
     ("iugkp_batch_solve", C.c_int, [P, P, P, P, P]),
     ("iugkp_batch_destroy", None, [P]),

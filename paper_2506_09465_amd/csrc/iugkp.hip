@@ -153,7 +153,7 @@ int fetch_host(const double *src, size_t n, int kind, std::vector<double> &dst)
 // Scale exponent F = 62 - ceil(log2 B), B = 4 max(|E_wall|, |E_0|) total, with
 // total = sum of cell volumes + lambda_min (sum of wall-face areas) / 4.
 int scale_exponent(const iugkp_problem *p, double tau_min, const std::vector<double> &wall_T,
-                   const std::vector<double> &T0)
+                   const std::vector<double> &T0, const std::vector<double> &src)
 {
   double maxabs = 0.0;
   for (double tw : wall_T) maxabs = std::max(maxabs, std::fabs(p->cv * (tw - p->t_ref)));
@@ -162,7 +162,18 @@ int scale_exponent(const iugkp_problem *p, double tau_min, const std::vector<dou
   const double vol = static_cast<double>(p->nx * p->ny) * (p->dx * p->dy);
   const double area = (p->dim == 2) ? ((2.0 * p->ny) * p->dy + (2.0 * p->nx) * p->dx) : 2.0;
   const double total = vol + (lam_min * area) / 4.0;
-  const double B = (4.0 * maxabs) * total;
+  double B = (4.0 * maxabs) * total;
+  // a source raises the energy level by at most about S_max tau_min times the
+  // iterations energy stays inside, bounded by 1 + 3 (L / lambda_min)^2
+  double smax = 0.0;
+  for (double sv : src) smax = std::max(smax, std::fabs(sv));
+  if (smax > 0.0) {
+    double L = static_cast<double>(p->nx) * p->dx;
+    if (p->dim == 2 && static_cast<double>(p->ny) * p->dy > L) L = static_cast<double>(p->ny) * p->dy;
+    const double rl = L / lam_min;
+    const double esrc = (smax * tau_min) * (1.0 + 3.0 * (rl * rl));
+    B = (4.0 * (maxabs + esrc)) * total;
+  }
   if (!(B > 0.0)) return 62;
   int e = 0;
   const double mant = std::frexp(B, &e);
@@ -245,8 +256,9 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   if (rc) return rc;
   const int nc = p->nx * p->ny;
   const int nb = 2 * p->ny + (p->dim == 2 ? 2 * p->nx : 0);
-  std::vector<double> tau, wall, T0;
+  std::vector<double> tau, wall, T0, src;
   if ((rc = fetch_host(p->tau, nc, p->mem_kind, tau))) return rc;
+  if (p->source && (rc = fetch_host(p->source, nc, p->mem_kind, src))) return rc;
   if ((rc = fetch_host(p->wall_T, nb, p->mem_kind, wall))) return rc;
   if (p->T_init && (rc = fetch_host(p->T_init, nc, p->mem_kind, T0))) return rc;
   double tmin = INFINITY, tmax = 0.0;
@@ -260,6 +272,8 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
     if (!std::isfinite(t)) return fail(IUGKP_E_INVALID_ARG, "wall_T must be finite");
   for (double t : T0)
     if (!std::isfinite(t)) return fail(IUGKP_E_INVALID_ARG, "T_init must be finite");
+  for (double v : src)
+    if (!std::isfinite(v)) return fail(IUGKP_E_INVALID_ARG, "source must be finite");
   const int ne = nc + nb;
   uint64_t N = o->particles_per_iter / static_cast<uint64_t>(ne);
   if (N < 1) N = 1;
@@ -300,7 +314,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   d.res_tol = o->res_tol;
   d.tol2 = o->cg_tol * o->cg_tol;
   d.cg_max = o->cg_max_iters;
-  d.F = scale_exponent(p, tmin, wall, T0);
+  d.F = scale_exponent(p, tmin, wall, T0, src);
   plan_tiles(ih);
 
 #define ALLOC(ptr, n) \
@@ -329,6 +343,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   ALLOC(ih.out_qx, m.n_fx);
   ALLOC(ih.out_qy, m.n_fy);
   ALLOC(d.sc, 1);
+  ALLOC(d.gpart, nbe);
   if (o->newton) {
     const int nbt = cdiv(nc, iugkp::kTree);
     ALLOC(d.rhs, nc);
@@ -345,7 +360,6 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
     ALLOC(d.cg_w, nc);
     ALLOC(d.cg_p, nc);
     ALLOC(d.cg_s, nc);
-    ALLOC(d.gpart, nbe);
     ALLOC(ih.cg_pub, 6 * static_cast<size_t>(nc));
     ALLOC(ih.cg_mpart, 4 * static_cast<size_t>(nbt));
     ALLOC(ih.cg_barrier, 2);
@@ -364,6 +378,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
                                                           ih.tau, d.E, ratio);
   // wall emission E_w lambda_min A / 4 (cosine-law black walls), computed once
   std::vector<long long> gw(nb);
+  d.wall_budget = 0;
   for (int b = 0; b < nb; ++b) {
     const double A = (b < 2 * p->ny) ? p->dy : p->dx;
     const double ew = p->cv * (wall[b] - p->t_ref);
@@ -371,12 +386,31 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
     if (!(std::fabs(v) <= 4611686018427387904.0))
       return fail(IUGKP_E_FIXED_OVERFLOW, "wall emission exceeds the fixed-point range");
     gw[b] = static_cast<long long>(std::rint(v));
+    const unsigned long long a = static_cast<unsigned long long>(gw[b] < 0 ? -gw[b] : gw[b]);
+    d.wall_budget = std::min(d.wall_budget + a, iugkp::kBudgetCap);
   }
   HIP_TRY(hipMemcpyAsync(d.G + nc, gw.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
+  // source emission S V tau_min per iteration
+  d.Gs = nullptr;
+  if (!src.empty()) {
+    std::vector<long long> gs(nc);
+    for (int c = 0; c < nc; ++c) {
+      const double v = std::ldexp((src[c] * d.V) * d.tau_min, d.F);
+      if (!(std::fabs(v) <= 4611686018427387904.0))
+        return fail(IUGKP_E_FIXED_OVERFLOW, "source emission exceeds the fixed-point range");
+      gs[c] = static_cast<long long>(std::rint(v));
+    }
+    long long *dgs = nullptr;
+    if (ih.alloc(&dgs, nc) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
+    HIP_TRY(hipMemcpyAsync(dgs, gs.data(), nc * sizeof(long long), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    d.Gs = dgs;
+  }
   int *dflag = nullptr;
   if (ih.alloc(&dflag, 1) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
   HIP_TRY(hipMemsetAsync(dflag, 0, sizeof(int), s));
-  iugkp::emission_from_E_kernel<<<cdiv(nc, 256), 256, 0, s>>>(nc, d.F, d.V, d.E, ratio, d.G, dflag);
+  iugkp::emission_from_E_kernel<<<cdiv(nc, 256), 256, 0, s>>>(nc, d.F, d.V, d.E, ratio, d.Gs, d.G,
+                                                              dflag);
   if (o->newton) {
     std::vector<double> dxv(nc), dyv(nc);
     auto fill = [&](const double *given, double delta, std::vector<double> &out) -> int {
@@ -593,6 +627,61 @@ void free_handle(iugkp_handle *h)
   delete h;
 }
 
+// Device allocations of one call, freed (after the stream drains) when it goes
+// out of scope.
+struct DevScratch {
+  hipStream_t s;
+  std::vector<void *> p;
+  explicit DevScratch(hipStream_t st) : s(st) {}
+  ~DevScratch()
+  {
+    (void)hipStreamSynchronize(s);
+    for (void *q : p) (void)hipFree(q);
+  }
+  template <class T>
+  T *get(size_t n)
+  {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    p.push_back(q);
+    return static_cast<T *>(q);
+  }
+};
+
+// The single solve's CG on A x = b (persistent cooperative launch, status and
+// iteration count into *sc); bracketed by ev_a / ev_b when given.
+int enqueue_cg(const InstHost &ih, const double *b, double *x, DevScalars *sc, hipStream_t s,
+               hipEvent_t ev_a, hipEvent_t ev_b)
+{
+  iugkp::CGArgs ca;
+  ca.m = ih.d.m;
+  ca.gx = ih.gx;
+  ca.gy = ih.gy;
+  ca.diag = ih.diag;
+  ca.b = b;
+  ca.x = x;
+  ca.gr = ih.d.cg_r;
+  ca.gw = ih.d.cg_w;
+  ca.gp = ih.d.cg_p;
+  ca.gs = ih.d.cg_s;
+  ca.pub = ih.cg_pub;
+  ca.part = ih.cg_mpart;
+  ca.TB = ih.cg_tb;
+  ca.tol2 = ih.d.tol2;
+  ca.max_iters = ih.d.cg_max;
+  ca.barrier = ih.cg_barrier;
+  ca.sc = sc;
+  iugkp::zero_u32_kernel<<<1, 64, 0, s>>>(ih.cg_barrier, 2);
+  if (ev_a) HIP_TRY(hipEventRecord(ev_a, s));
+  // every workgroup must be resident for the grid barrier: the cooperative
+  // launch refuses a grid that does not fit instead of letting it hang
+  void *args[] = {&ca};
+  HIP_TRY(hipLaunchCooperativeKernel(cg_kernel_for(ih.cg_reg), dim3(ih.cg_grid),
+                                     dim3(ih.cg_threads), args, ih.cg_lds, s));
+  if (ev_b) HIP_TRY(hipEventRecord(ev_b, s));
+  return IUGKP_OK;
+}
+
 // One iteration on the handle's stream; leaves the new scalars in h->hsc.
 int iterate(iugkp_handle *h, int faces)
 {
@@ -615,32 +704,8 @@ int iterate(iugkp_handle *h, int faces)
   iugkp::update_kernel<<<dim3(nbc, 1), 256, 0, s>>>(h->d_inst, 0);
   HIP_TRY(hipGetLastError());
   if (ih.d.newton) {
-    iugkp::CGArgs ca;
-    ca.m = m;
-    ca.gx = ih.gx;
-    ca.gy = ih.gy;
-    ca.diag = ih.diag;
-    ca.b = ih.d.rhs;
-    ca.x = ih.d.cg_x;
-    ca.gr = ih.d.cg_r;
-    ca.gw = ih.d.cg_w;
-    ca.gp = ih.d.cg_p;
-    ca.gs = ih.d.cg_s;
-    ca.pub = ih.cg_pub;
-    ca.part = ih.cg_mpart;
-    ca.TB = ih.cg_tb;
-    ca.tol2 = ih.d.tol2;
-    ca.max_iters = ih.d.cg_max;
-    ca.barrier = ih.cg_barrier;
-    ca.sc = ih.d.sc;
-    iugkp::zero_u32_kernel<<<1, 64, 0, s>>>(ih.cg_barrier, 2);
-    HIP_TRY(hipEventRecord(h->ev[2], s));
-    // every workgroup must be resident for the grid barrier: the cooperative
-    // launch refuses a grid that does not fit instead of letting it hang
-    void *args[] = {&ca};
-    HIP_TRY(hipLaunchCooperativeKernel(cg_kernel_for(ih.cg_reg), dim3(ih.cg_grid),
-                                       dim3(ih.cg_threads), args, ih.cg_lds, s));
-    HIP_TRY(hipEventRecord(h->ev[3], s));
+    rc = enqueue_cg(ih, ih.d.rhs, ih.d.cg_x, ih.d.sc, s, h->ev[2], h->ev[3]);
+    if (rc) return rc;
     const int nbe = cdiv(m.n_emit, iugkp::kTree);
     iugkp::newton_finish_kernel<<<dim3(nbe, 1), 256, 0, s>>>(h->d_inst, 0);
   }
@@ -677,7 +742,7 @@ int iterate(iugkp_handle *h, int faces)
   if (ih.d.newton && sc.cg_status == -7)
     return fail(IUGKP_E_CG_NOT_CONVERGED, "CG did not converge within cg_max_iters");
   if (sc.flags & 1) return fail(IUGKP_E_NONFINITE, "non-finite energy");
-  if ((sc.flags & 2) || (ih.d.newton && sc.gsum > (1ull << 62)))
+  if ((sc.flags & 2) || ((ih.d.newton || ih.d.Gs) && sc.gsum > (1ull << 62)))
     return fail(IUGKP_E_FIXED_OVERFLOW, "emission energy exceeds the fixed-point budget");
   if (h->iter > 1 && h->res > 1e3) return fail(IUGKP_E_DIVERGED, "residual grew above 1e3");
   return IUGKP_OK;
@@ -859,6 +924,84 @@ int iugkp_get_stats(iugkp_handle *h, iugkp_stats *stats)
   if (!h || !stats) return fail(IUGKP_E_INVALID_ARG, "bad arguments");
   *stats = h->st;
   return IUGKP_OK;
+}
+
+int iugkp_adjoint(iugkp_handle *h, const double *dLdT, double *grad_wall, double *grad_source,
+                  int max_iters, double tol, int *iters_out)
+{
+  if (iters_out) *iters_out = 0;
+  if (!h || !dLdT || max_iters < 1 || !(tol >= 0.0))
+    return fail(IUGKP_E_INVALID_ARG, "bad adjoint arguments");
+  InstHost &ih = h->ih;
+  const Inst &d = ih.d;
+  const Mesh &m = d.m;
+  if (!d.crn) return fail(IUGKP_E_INVALID_ARG, "the adjoint needs common random numbers (rng_mode CRN)");
+  if (d.has_null) return fail(IUGKP_E_INVALID_ARG, "the adjoint needs a uniform relaxation time");
+  if (d.N > 65536u) return fail(IUGKP_E_INVALID_ARG, "the adjoint allows at most 65536 particles per emitter");
+  hipStream_t s = h->stream;
+  const int nc = m.n_cells, ne = m.n_emit, nbc = cdiv(nc, iugkp::kTree);
+  const long long np = static_cast<long long>(ne) * d.N;
+  DevScratch sc(s);   // freed when the call returns
+  int *end = sc.get<int>(static_cast<size_t>(np));
+  double *u = sc.get<double>(nc), *psi = sc.get<double>(nc), *half = sc.get<double>(nc);
+  double *g = sc.get<double>(ne), *part = sc.get<double>(nbc), *dn = sc.get<double>(1);
+  double *dl = sc.get<double>(nc);
+  double *gw = sc.get<double>(m.n_b), *gs = sc.get<double>(nc);
+  DevScalars *asc = sc.get<DevScalars>(1);
+  if (!end || !u || !psi || !half || !g || !part || !dn || !dl || !gw || !gs || !asc)
+    return fail(IUGKP_E_NOMEM, "hipMalloc failed");
+  HIP_TRY(hipMemcpyAsync(dl, dLdT, nc * sizeof(double),
+                         ih.mem_kind == IUGKP_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                         : hipMemcpyHostToDevice, s));
+  const iugkp::FlyIn fa = {m, d.lam_min, d.epoch, d.key0, d.key1, 0, 0, d.ratio};
+  iugkp::adjoint_paths_kernel<<<cdiv(np, 256), 256, 0, s>>>(fa, ne, d.N, end);
+  iugkp::adjoint_init_kernel<<<cdiv(nc, 256), 256, 0, s>>>(nc, d.cv, d.V, d.F, dl, u, psi);
+  HIP_TRY(hipGetLastError());
+  const int gather_blocks = cdiv(static_cast<long long>(ne) * 64, 256);
+  int passes = 0, rc = IUGKP_W_NOT_CONVERGED;
+  double d0 = 0.0;
+  for (int it = 0; it < max_iters; ++it) {
+    iugkp::adjoint_gather_kernel<<<gather_blocks, 256, 0, s>>>(end, psi, ne, d.N, g);
+    iugkp::adjoint_half_kernel<<<nbc, 256, 0, s>>>(nc, g, u, half, psi, d.rhs, d.newton, part);
+    if (d.newton) {
+      if ((rc = enqueue_cg(ih, d.rhs, d.cg_x, asc, s, nullptr, nullptr))) return rc;
+      iugkp::adjoint_newton_kernel<<<nbc, 256, 0, s>>>(nc, half, d.cg_x, psi, part);
+    }
+    iugkp::adjoint_norm_kernel<<<1, 256, 0, s>>>(part, nbc, dn);
+    HIP_TRY(hipGetLastError());
+    double hdn = 0.0;
+    DevScalars hs{};
+    HIP_TRY(hipMemcpyAsync(&hdn, dn, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (d.newton) HIP_TRY(hipMemcpyAsync(&hs, asc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    passes = it + 1;
+    if (d.newton && hs.cg_status == -3) return fail(IUGKP_E_DEVICE, "CG grid barrier timed out");
+    if (d.newton && hs.cg_status == -6) return fail(IUGKP_E_CG_BREAKDOWN, "adjoint CG breakdown");
+    if (d.newton && hs.cg_status == -7)
+      return fail(IUGKP_E_CG_NOT_CONVERGED, "adjoint CG did not converge within cg_max_iters");
+    if (it == 0) d0 = hdn;
+    const double res = (d0 > 0.0) ? hdn / d0 : 0.0;
+    if (!std::isfinite(res)) return fail(IUGKP_E_NONFINITE, "non-finite adjoint");
+    if (res < tol) {
+      rc = IUGKP_OK;
+      break;
+    }
+  }
+  // gradients from the converged psi: one more reverse pass
+  iugkp::adjoint_gather_kernel<<<gather_blocks, 256, 0, s>>>(end, psi, ne, d.N, g);
+  const double fs = std::ldexp(d.V * d.tau_min, d.F);
+  const double fw_lr = std::ldexp((d.cv * (d.lam_min * m.dy)) / 4.0, d.F);
+  const double fw_bt = std::ldexp((d.cv * (d.lam_min * m.dx)) / 4.0, d.F);
+  iugkp::adjoint_grad_kernel<<<cdiv(std::max(nc, m.n_b), 256), 256, 0, s>>>(
+      nc, m.n_b, m.ny, g, fs, fw_lr, fw_bt, gs, gw);
+  HIP_TRY(hipGetLastError());
+  const hipMemcpyKind out_kind =
+      ih.mem_kind == IUGKP_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (grad_wall) HIP_TRY(hipMemcpyAsync(grad_wall, gw, m.n_b * sizeof(double), out_kind, s));
+  if (grad_source) HIP_TRY(hipMemcpyAsync(grad_source, gs, nc * sizeof(double), out_kind, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (iters_out) *iters_out = passes;
+  return rc;
 }
 
 double iugkp_d_eff(double lam, double delta) { return iugkp::d_eff(lam, delta); }

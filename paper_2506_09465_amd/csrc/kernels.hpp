@@ -70,8 +70,20 @@ struct Inst {
   double *cg_pub, *cg_mpart;                            // published rows, partials
   unsigned int *cg_barrier;                             // [2] barrier of the instance's group
   double *acc_E, *acc_x, *acc_y;
+  const long long *Gs;          // per-cell source emission per iteration, or null
+  unsigned long long wall_budget;   // saturating sum of |G| over the wall emitters
   DevScalars *sc;
 };
+
+// a + b for |a|, |b| <= 2^62 (two's complement, no overflow trap); sets
+// *bad when |a + b| exceeds the 2^62 budget
+__device__ __forceinline__ long long add_budget(long long a, long long b, int *bad)
+{
+  const long long r = static_cast<long long>(static_cast<unsigned long long>(a) +
+                                             static_cast<unsigned long long>(b));
+  if (r > (1ll << 62) || r < -(1ll << 62)) *bad = 1;
+  return r;
+}
 
 // ---------------------------------------------------------------------------
 // Fixed-order tree over 256 values held by 256 consecutive threads (one
@@ -248,6 +260,144 @@ __host__ __device__ inline size_t window_words(int WX, int WY, int has_null, int
          static_cast<size_t>(WX) * (WY + 2) + (lds_walls ? n_b : 0);
 }
 
+// The flight of particle k of emitter e carrying q: sampling (start point,
+// direction), free paths on the common time scale, the DDA walk through the
+// uniform grid and the candidate/real collision decisions.  The tallies are
+// callbacks, so the particle step and the adjoint's path tracing share one
+// definition of the path:
+//   add_diff(k, ix, v)   column-run difference of y-faces in column ix
+//   add_yface(ky, ix, v) one y-face crossing
+//   add_wall(b, q)       absorbed by boundary face b
+//   add_cand(ix, iy, q)  candidate collision (null-collision runs only)
+//   add_real(ix, iy, q)  real collision (deposit)
+struct FlyIn {
+  Mesh m;
+  double lam_min;
+  uint32_t slot, key0, key1;
+  int faces, has_null;
+  const double *ratio;
+};
+
+template <class Diff, class YFace, class Wall, class Cand, class Real>
+__device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long long q,
+                                    Diff &&add_diff, YFace &&add_yface, Wall &&add_wall,
+                                    Cand &&add_cand, Real &&add_real, unsigned long long &n_seg,
+                                    unsigned long long &n_cross)
+{
+  const Mesh &m = a.m;
+  const double2 uab = draw2(0u, k, e, a.slot, a.key0, a.key1);
+  const double2 ucd = draw2(1u, k, e, a.slot, a.key0, a.key1);
+  int ix, iy;
+  double x0, y0, sx, sy;
+  if (e < static_cast<uint32_t>(m.n_cells)) {
+    // isotropic emission from a uniformly sampled point of the cell
+    iy = static_cast<int>(e) / m.nx;
+    ix = static_cast<int>(e) - iy * m.nx;
+    x0 = (static_cast<double>(ix) + uab.x) * m.dx;
+    y0 = (static_cast<double>(iy) + uab.y) * m.dy;
+    const double mu = 2.0 * ucd.x - 1.0;
+    sx = mu;
+    sy = (m.dim == 2) ? sqrt((1.0 - mu) * (1.0 + mu)) * cos2pi_own(ucd.y) : 0.0;
+  } else {
+    // cosine-law emission from a black wall face into the domain
+    const int b = static_cast<int>(e) - m.n_cells;
+    const double cn = sqrt(ucd.x);
+    const double tg = (m.dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * cos2pi_own(ucd.y) : 0.0;
+    if (b < m.ny) {
+      ix = 0; iy = b;
+      x0 = 0.0; y0 = (static_cast<double>(iy) + uab.x) * m.dy;
+      sx = cn; sy = tg;
+    } else if (b < 2 * m.ny) {
+      ix = m.nx - 1; iy = b - m.ny;
+      x0 = static_cast<double>(m.nx) * m.dx; y0 = (static_cast<double>(iy) + uab.x) * m.dy;
+      sx = -cn; sy = tg;
+    } else if (b < 2 * m.ny + m.nx) {
+      ix = b - 2 * m.ny; iy = 0;
+      x0 = (static_cast<double>(ix) + uab.x) * m.dx; y0 = 0.0;
+      sx = tg; sy = cn;
+    } else {
+      ix = b - 2 * m.ny - m.nx; iy = m.ny - 1;
+      x0 = (static_cast<double>(ix) + uab.x) * m.dx; y0 = static_cast<double>(m.ny) * m.dy;
+      sx = tg; sy = -cn;
+    }
+  }
+  const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+  const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+  const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+  const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+  const long long qy = (sty > 0) ? q : -q;
+  // steep segments record their y-faces as runs per column
+  const bool runs = a.faces && (fabs(sy) > 2.0 * fabs(sx));
+  for (uint32_t j = 0;; ++j) {
+    const double2 us = draw2(2u + j, k, e, a.slot, a.key0, a.key1);
+    // candidate free path on the common time scale tau_min: -|V_g| tau_min ln(eta)
+    const double ell = -(a.lam_min * log_own(1.0 - us.x));
+    ++n_seg;
+    int kx = (stx > 0) ? ix + 1 : ix;
+    int ky = (sty > 0) ? iy + 1 : iy;
+    int bface = -1;
+    int run_a = -1, run_b = -1;   // first and last y-face of the open run
+    for (;;) {
+      const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
+      const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
+      const bool along_x = tx <= ty;
+      const double tt = along_x ? tx : ty;
+      if (!(tt < ell)) break;
+      ++n_cross;
+      if (along_x) {
+        if (run_a >= 0) {
+          add_diff(min(run_a, run_b), ix, qy);
+          add_diff(max(run_a, run_b) + 1, ix, -qy);
+          run_a = -1;
+        }
+        if (kx == 0 || kx == m.nx) {
+          bface = (kx == 0) ? iy : m.ny + iy;
+          break;
+        }
+        ix += stx;
+        kx += stx;
+      } else {
+        if (runs) {
+          if (run_a < 0) run_a = ky;
+          run_b = ky;
+        } else if (a.faces) {
+          add_yface(ky, ix, qy);
+        }
+        if (ky == 0 || ky == m.ny) {
+          bface = (ky == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
+          break;
+        }
+        iy += sty;
+        ky += sty;
+      }
+    }
+    if (run_a >= 0) {
+      add_diff(min(run_a, run_b), ix, qy);
+      add_diff(max(run_a, run_b) + 1, ix, -qy);
+    }
+    if (bface >= 0) {
+      add_wall(bface, q);
+      break;
+    }
+    if (!a.has_null) {
+      add_real(ix, iy, q);   // every candidate is real: W == D
+      break;
+    }
+    add_cand(ix, iy, q);
+    // accept with probability sigma / sigma_max = tau_min / tau_c
+    const int c = ix + m.nx * iy;
+    if (us.y < a.ratio[c] || j == kMaxSegments - 1) {
+      add_real(ix, iy, q);
+      break;
+    }
+    // null collision: keep the direction, restart from the stopping point
+    x0 = clamp_to(x0 + ell * sx, static_cast<double>(ix) * m.dx, static_cast<double>(ix + 1) * m.dx);
+    if (m.dim == 2)
+      y0 = clamp_to(y0 + ell * sy, static_cast<double>(iy) * m.dy,
+                    static_cast<double>(iy + 1) * m.dy);
+  }
+}
+
 template <int BS>
 __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ insts,
                                                    const TileDesc *__restrict__ tiles,
@@ -325,6 +475,7 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
       atom_add(&a.B[b], v);
   };
 
+  const FlyIn fa = {a.m, a.lam_min, a.slot, a.key0, a.key1, a.faces, a.has_null, a.ratio};
   const int n_e = (td.kind == 0) ? td.ex * td.ey : td.ex;
   const uint32_t P = static_cast<uint32_t>(n_e) * a.N;
   unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
@@ -341,117 +492,9 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
     const long long q = a.base[e] + ((k < a.rem[e]) ? 1 : 0);
     if (q == 0) continue;
     ++n_fl;
-    const double2 uab = draw2(0u, k, e, a.slot, a.key0, a.key1);
-    const double2 ucd = draw2(1u, k, e, a.slot, a.key0, a.key1);
-    int ix, iy;
-    double x0, y0, sx, sy;
-    if (e < static_cast<uint32_t>(m.n_cells)) {
-      // isotropic emission from a uniformly sampled point of the cell
-      iy = static_cast<int>(e) / m.nx;
-      ix = static_cast<int>(e) - iy * m.nx;
-      x0 = (static_cast<double>(ix) + uab.x) * m.dx;
-      y0 = (static_cast<double>(iy) + uab.y) * m.dy;
-      const double mu = 2.0 * ucd.x - 1.0;
-      sx = mu;
-      sy = (m.dim == 2) ? sqrt((1.0 - mu) * (1.0 + mu)) * cos2pi_own(ucd.y) : 0.0;
-    } else {
-      // cosine-law emission from a black wall face into the domain
-      const int b = static_cast<int>(e) - m.n_cells;
-      const double cn = sqrt(ucd.x);
-      const double tg = (m.dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * cos2pi_own(ucd.y) : 0.0;
-      if (b < m.ny) {
-        ix = 0; iy = b;
-        x0 = 0.0; y0 = (static_cast<double>(iy) + uab.x) * m.dy;
-        sx = cn; sy = tg;
-      } else if (b < 2 * m.ny) {
-        ix = m.nx - 1; iy = b - m.ny;
-        x0 = static_cast<double>(m.nx) * m.dx; y0 = (static_cast<double>(iy) + uab.x) * m.dy;
-        sx = -cn; sy = tg;
-      } else if (b < 2 * m.ny + m.nx) {
-        ix = b - 2 * m.ny; iy = 0;
-        x0 = (static_cast<double>(ix) + uab.x) * m.dx; y0 = 0.0;
-        sx = tg; sy = cn;
-      } else {
-        ix = b - 2 * m.ny - m.nx; iy = m.ny - 1;
-        x0 = (static_cast<double>(ix) + uab.x) * m.dx; y0 = static_cast<double>(m.ny) * m.dy;
-        sx = tg; sy = -cn;
-      }
-    }
-    const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
-    const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
-    const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
-    const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
-    const long long qy = (sty > 0) ? q : -q;
-    // steep segments record their y-faces as runs per column
-    const bool runs = a.faces && (fabs(sy) > 2.0 * fabs(sx));
-    for (uint32_t j = 0;; ++j) {
-      const double2 us = draw2(2u + j, k, e, a.slot, a.key0, a.key1);
-      // candidate free path on the common time scale tau_min: -|V_g| tau_min ln(eta)
-      const double ell = -(a.lam_min * log_own(1.0 - us.x));
-      ++n_seg;
-      int kx = (stx > 0) ? ix + 1 : ix;
-      int ky = (sty > 0) ? iy + 1 : iy;
-      int bface = -1;
-      int run_a = -1, run_b = -1;   // first and last y-face of the open run
-      for (;;) {
-        const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
-        const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
-        const bool along_x = tx <= ty;
-        const double tt = along_x ? tx : ty;
-        if (!(tt < ell)) break;
-        ++n_cross;
-        if (along_x) {
-          if (run_a >= 0) {
-            add_diff(min(run_a, run_b), ix, qy);
-            add_diff(max(run_a, run_b) + 1, ix, -qy);
-            run_a = -1;
-          }
-          if (kx == 0 || kx == m.nx) {
-            bface = (kx == 0) ? iy : m.ny + iy;
-            break;
-          }
-          ix += stx;
-          kx += stx;
-        } else {
-          if (runs) {
-            if (run_a < 0) run_a = ky;
-            run_b = ky;
-          } else if (a.faces) {
-            add_yface(ky, ix, qy);
-          }
-          if (ky == 0 || ky == m.ny) {
-            bface = (ky == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
-            break;
-          }
-          iy += sty;
-          ky += sty;
-        }
-      }
-      if (run_a >= 0) {
-        add_diff(min(run_a, run_b), ix, qy);
-        add_diff(max(run_a, run_b) + 1, ix, -qy);
-      }
-      if (bface >= 0) {
-        add_wall(bface, q);
-        break;
-      }
-      if (!a.has_null) {
-        add_cell(win.D, a.D, ix, iy, q);   // every candidate is real: W == D
-        break;
-      }
-      add_cell(win.W, a.W, ix, iy, q);
-      // accept with probability sigma / sigma_max = tau_min / tau_c
-      const int c = ix + m.nx * iy;
-      if (us.y < a.ratio[c] || j == kMaxSegments - 1) {
-        add_cell(win.D, a.D, ix, iy, q);
-        break;
-      }
-      // null collision: keep the direction, restart from the stopping point
-      x0 = clamp_to(x0 + ell * sx, static_cast<double>(ix) * m.dx, static_cast<double>(ix + 1) * m.dx);
-      if (m.dim == 2)
-        y0 = clamp_to(y0 + ell * sy, static_cast<double>(iy) * m.dy,
-                      static_cast<double>(iy + 1) * m.dy);
-    }
+    fly(fa, e, k, q, add_diff, add_yface, add_wall,
+        [&](int cx, int cy, long long v) { add_cell(win.W, a.W, cx, cy, v); },
+        [&](int cx, int cy, long long v) { add_cell(win.D, a.D, cx, cy, v); }, n_seg, n_cross);
   }
   if (n_fl) {
     atomicAdd(&s_cnt[0], n_fl);
@@ -542,7 +585,8 @@ __global__ __launch_bounds__(256) void update_kernel(const Inst *__restrict__ in
   if (static_cast<int>(blockIdx.x) >= nbc) return;
   const int c = blockIdx.x * kTree + threadIdx.x;
   double sq = 0.0;
-  int bad = 0;
+  int bad = 0, over = 0;
+  unsigned long long ag = 0;
   if (c < in.m.n_cells) {
     const long long w = in.has_null ? in.W[c] : in.D[c];
     const double eh = ldexp(static_cast<double>(w), -in.F) / in.V;
@@ -554,13 +598,30 @@ __global__ __launch_bounds__(256) void update_kernel(const Inst *__restrict__ in
       sq = d * d;
       bad = !isfinite(eh);
       in.E[c] = eh;
-      in.G[c] = in.D[c];
+      // re-emission of the real-collision energy, plus the source
+      const long long g = in.Gs ? add_budget(in.D[c], in.Gs[c], &over) : in.D[c];
+      in.G[c] = g;
+      ag = static_cast<unsigned long long>(g < 0 ? -g : g);
     }
   }
   if (in.newton) return;
-  if (bad) atomicOr(&in.sc->flags, 1);
+  if (bad || over) atomicOr(&in.sc->flags, (bad ? 1 : 0) | (over ? 2 : 0));
   const double s = block_tree256(sq, lds);
   if (threadIdx.x == 0) in.part[blockIdx.x] = s;
+  if (in.Gs) {
+    // |G| budget partials of the cells (the walls' sum is constant)
+    __shared__ unsigned long long lg[kTree];
+    lg[threadIdx.x] = ag > kBudgetCap ? kBudgetCap : ag;
+    __syncthreads();
+    for (int st = kTree / 2; st >= 1; st >>= 1) {
+      if (threadIdx.x < st) {
+        const unsigned long long u = lg[threadIdx.x] + lg[threadIdx.x + st];
+        lg[threadIdx.x] = u > kBudgetCap ? kBudgetCap : u;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) in.gpart[blockIdx.x] = lg[0];
+  }
 }
 
 // E^{n+1} = E^{n+1/2} + dE, next emission rint(2^F (E^{n+1} V) tau_min / tau_c),
@@ -589,7 +650,10 @@ __global__ __launch_bounds__(256) void newton_finish_kernel(const Inst *__restri
       flags |= 2;
       in.G[c] = 0;
     } else {
-      const long long g = static_cast<long long>(rint(v));
+      int over = 0;
+      long long g = static_cast<long long>(rint(v));
+      if (in.Gs) g = add_budget(g, in.Gs[c], &over);
+      if (over) flags |= 2;
       in.G[c] = g;
       ag = static_cast<unsigned long long>(g < 0 ? -g : g);
     }
@@ -640,11 +704,18 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
   const double dsq = tree_all(in.part, nbc, lds, lds2);
   if (threadIdx.x != 0) return;
   unsigned long long g = 0;
-  if (in.newton)
+  if (in.newton) {
     for (int i = 0; i < nbe; ++i) {
       g += in.gpart[i];
       if (g > kBudgetCap) g = kBudgetCap;
     }
+  } else if (in.Gs) {
+    g = in.wall_budget;
+    for (int i = 0; i < nbc; ++i) {
+      g += in.gpart[i];
+      if (g > kBudgetCap) g = kBudgetCap;
+    }
+  }
   sc->gsum = g;
   const double dn = sqrt(dsq);
   sc->dn = dn;
@@ -665,7 +736,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
   else if (in.newton && sc->cg_status == -6) err = kErrBreakdown;
   else if (in.newton && sc->cg_status == -7) err = kErrCgNotConverged;
   else if (sc->flags & 1) err = kErrNonfinite;
-  else if ((sc->flags & 2) || (in.newton && g > (1ull << 62))) err = kErrOverflow;
+  else if ((sc->flags & 2) || ((in.newton || in.Gs) && g > (1ull << 62))) err = kErrOverflow;
   else if (sc->iter > 1 && res > 1e3) err = kErrDiverged;
   sc->acc_mode = 0;
   if (err) {
@@ -717,7 +788,8 @@ __global__ void accumulate_kernel(const Inst *__restrict__ insts, int batch, int
 
 // Initial cell emission from E (creation / restored state): G = rint(2^F (E V) r).
 __global__ void emission_from_E_kernel(int n_cells, int F, double V, const double *E,
-                                       const double *ratio, long long *G, int *flag)
+                                       const double *ratio, const long long *Gs, long long *G,
+                                       int *flag)
 {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cells) return;
@@ -727,7 +799,13 @@ __global__ void emission_from_E_kernel(int n_cells, int F, double V, const doubl
     G[c] = 0;
     return;
   }
-  G[c] = static_cast<long long>(rint(v));
+  long long g = static_cast<long long>(rint(v));
+  if (Gs) {
+    int over = 0;
+    g = add_budget(g, Gs[c], &over);
+    if (over) atomicOr(flag, 2);
+  }
+  G[c] = g;
 }
 
 // E0 = cv (T0 - t_ref), ratio = tau_min / tau.
@@ -1362,6 +1440,143 @@ __global__ __launch_bounds__(kCgThreadsMax) void cg_batch_kernel(const Inst *__r
     else cg_run<false>(a, jb.rank, jb.G);
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the steady state (uniform relaxation time, common random numbers).
+// For fixed counters the paths do not depend on the weights, so one
+// iteration is linear in the emission energies, D = T_cc G_cells + T_cw G_walls
+// with T_xe the fraction of emitter e's N particles ending in cell x, and the
+// steady state with re-emission G_cells = D + G_src is
+// D* = (I - T_cc)^-1 (T_cc G_src + T_cw G_walls).  For a loss L(T), with
+// u = dL/dD* and psi = (I - T_cc^T)^-1 u,
+//   dL/dG_src = T_cc^T psi,   dL/dG_walls = T_cw^T psi,
+// and (T^T psi)_e is the mean of psi over the cells where e's particles end:
+// the forward paths used in reverse.  psi is the fixed point of
+// psi <- T^T psi + u, each pass followed by the forward solve's diffusion
+// correction when Newton is on.
+// ---------------------------------------------------------------------------
+// where particle (e, k) ends: end[e N + k] = its deposit cell, or -1 when a
+// wall absorbs it (one thread per particle)
+__global__ void adjoint_paths_kernel(FlyIn fa, int n_emit, uint32_t N, int *end)
+{
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<long long>(n_emit) * N) return;
+  const uint32_t e = static_cast<uint32_t>(i / N);
+  const uint32_t k = static_cast<uint32_t>(i - static_cast<long long>(e) * N);
+  int out = -1;
+  unsigned long long n_seg = 0, n_cross = 0;
+  auto none = [](int, int, long long) {};
+  fly(fa, e, k, 1ll, none, none, [&](int, long long) { out = -1; }, none,
+      [&](int cx, int cy, long long) { out = cx + fa.m.nx * cy; }, n_seg, n_cross);
+  end[i] = out;
+}
+
+// g_e = (sum over k of psi at end(e, k), 0 for walls) / N; the sum in the
+// fixed order of the host definition (256-element pairwise trees, then the
+// same tree over the chunk sums; N <= 65536).  One wave per emitter.
+__global__ void adjoint_gather_kernel(const int *__restrict__ end, const double *__restrict__ psi,
+                                      int n_emit, uint32_t N, double *__restrict__ g)
+{
+  const int e = static_cast<int>((static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (e >= n_emit) return;                    // whole waves only
+  const int *en = end + static_cast<size_t>(e) * N;
+  auto val = [&](uint32_t k) -> double {
+    if (k >= N) return 0.0;
+    const int a = en[k];
+    return a >= 0 ? psi[a] : 0.0;
+  };
+  const uint32_t nch = (N + kTree - 1) / kTree;
+  double c[4] = {0.0, 0.0, 0.0, 0.0};
+  double total = 0.0;
+  for (uint32_t ch = 0; ch < nch; ++ch) {
+    const uint32_t b = ch * kTree + lane;
+    const double r = lane0(wave_tree256(val(b), val(b + 64), val(b + 128), val(b + 192)));
+    if (nch == 1) {
+      total = r;
+      break;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (static_cast<int>(ch >> 6) == q && static_cast<int>(ch & 63) == lane) c[q] = r;
+  }
+  if (nch > 1) total = lane0(wave_tree256(c[0], c[1], c[2], c[3]));
+  if (lane == 0) g[e] = total / static_cast<double>(N);
+}
+
+// u = dL/dD* = ldexp((dL/dT / C) / V, -F) (T = t_ref + ldexp(D, -F) / V / C); psi = u
+__global__ void adjoint_init_kernel(int n, double cv, double V, int F, const double *dLdT,
+                                    double *u, double *psi)
+{
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const double v = ldexp((dLdT[c] / cv) / V, -F);
+  u[c] = v;
+  psi[c] = v;
+}
+
+// half = T^T psi + u.  Without Newton psi <- half directly (squared change
+// partials per 256-cell block); with Newton rhs = half - psi for the CG.
+__global__ __launch_bounds__(256) void adjoint_half_kernel(int n, const double *g, const double *u,
+                                                           double *half, double *psi, double *rhs,
+                                                           int newton, double *part)
+{
+  __shared__ double lds[kTree];
+  const int c = blockIdx.x * kTree + threadIdx.x;
+  double sq = 0.0;
+  if (c < n) {
+    const double h = g[c] + u[c];
+    if (newton) {
+      half[c] = h;
+      rhs[c] = h - psi[c];
+    } else {
+      const double d = h - psi[c];
+      sq = d * d;
+      psi[c] = h;
+    }
+  }
+  if (newton) return;
+  const double s = block_tree256(sq, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// with Newton: psi <- half + x (the CG correction), squared change partials
+__global__ __launch_bounds__(256) void adjoint_newton_kernel(int n, const double *half,
+                                                             const double *x, double *psi,
+                                                             double *part)
+{
+  __shared__ double lds[kTree];
+  const int c = blockIdx.x * kTree + threadIdx.x;
+  double sq = 0.0;
+  if (c < n) {
+    const double nv = half[c] + x[c];
+    const double d = nv - psi[c];
+    sq = d * d;
+    psi[c] = nv;
+  }
+  const double s = block_tree256(sq, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// one workgroup: out = sqrt(fixed-order sum of the partials)
+__global__ __launch_bounds__(256) void adjoint_norm_kernel(const double *part, int nb, double *out)
+{
+  __shared__ double lds[kTree];
+  __shared__ double lds2[kTree];
+  const double s = tree_all(part, nb, lds, lds2);
+  if (threadIdx.x == 0) out[0] = sqrt(s);
+}
+
+// chain rule to the inputs: dL/dS_c = g_c ldexp(V tau_min, F), dL/dT_f = g_f
+// ldexp(C lambda_min A_f / 4, F) (A_f = dy on the left/right walls, dx else)
+__global__ void adjoint_grad_kernel(int n_cells, int n_b, int ny, const double *g, double fs,
+                                    double fw_lr, double fw_bt, double *grad_source,
+                                    double *grad_wall)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_cells && grad_source) grad_source[i] = g[i] * fs;
+  if (i < n_b && grad_wall) grad_wall[i] = g[n_cells + i] * ((i < 2 * ny) ? fw_lr : fw_bt);
 }
 
 // zero a small integer array (used instead of a memset node so the sequence can

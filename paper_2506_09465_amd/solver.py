@@ -3,7 +3,7 @@
 torch provides device memory and the current HIP stream; every step of the
 method runs in the library's kernels.  A problem is any object with the
 attributes dim, nx, ny, dx, dy, t_ref, cv, vg, tau, wall_T and optionally
-T_init (for example a `synth.Workload`).
+T_init and source (for example a `synth.Workload`).
 """
 from __future__ import annotations
 
@@ -43,10 +43,11 @@ class _Marshal:
         self.T_init = _dev_f64(Ti, device)
         self.dx_arr = _dev_f64(diff_x, device)
         self.dy_arr = _dev_f64(diff_y, device)
+        self.src = _dev_f64(getattr(w, "source", None), device)
         self.problem = L.Problem(int(w.dim), int(w.nx), int(w.ny), float(w.dx), float(w.dy),
                                  float(w.t_ref), float(w.cv), float(w.vg), _ptr(self.tau),
                                  _ptr(self.wall), _ptr(self.T_init), _ptr(self.dx_arr),
-                                 _ptr(self.dy_arr), L.MEM_DEVICE)
+                                 _ptr(self.dy_arr), L.MEM_DEVICE, _ptr(self.src))
         self.options = L.Options(int(seed), int(particles), int(rng_mode), int(epoch),
                                  int(max_iters), float(res_tol), int(bool(newton)),
                                  float(cg_tol), int(cg_max_iters), int(tally_faces),
@@ -147,6 +148,21 @@ class Solver:
         G = torch.as_tensor(G).to(device=self.device, dtype=torch.int64).contiguous()
         with torch.cuda.device(self.device):
             return L.lib().iugkp_set_state(self.h, int(it), float(d0), E.data_ptr(), G.data_ptr())
+
+    def adjoint(self, dLdT, max_iters: int = 200, tol: float = 1e-10):
+        """Gradients of a loss L(T) of the steady state reached by this solver
+        (CRN, uniform tau) with respect to every wall face temperature and every
+        cell source, given dL/dT per cell.  Returns (rc, grad_wall, grad_source,
+        passes); rc is 0 or the not-converged warning."""
+        g = _dev_f64(dLdT, self.device)
+        gw = torch.empty(self.nb, dtype=torch.float64, device=self.device)
+        gs = torch.empty(self.nc, dtype=torch.float64, device=self.device)
+        its = C.c_int(0)
+        with torch.cuda.device(self.device):
+            rc = L.lib().iugkp_adjoint(self.h, g.data_ptr(), gw.data_ptr(), gs.data_ptr(),
+                                       int(max_iters), float(tol), C.addressof(its))
+        L.check(rc, "iugkp_adjoint", allow_warning=True)
+        return rc, gw, gs, its.value
 
     def stats(self) -> dict:
         st = L.Stats()
