@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-tts", action="store_true", help="skip time-to-steady")
     ap.add_argument("--batch", type=int, default=256,
                     help="instances of the batched vs sequential comparison (0: skip)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient timing")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="particles per iteration in the CPU oracle sample")
     return ap.parse_args()
@@ -176,6 +177,33 @@ def bench_batch(P, dev, count):
             "note": "per-instance setup (allocation, Newton operator) excluded from both timings"}
 
 
+def bench_adjoint(P, dev):
+    """The adjoint workload: 256 x 256 cavity at Kn = 0.1 with a Gaussian source,
+    squared misfit at 64 random probes; forward CRN solve (Newton, residual
+    1e-9) and the backward pass (adjoint to relative change 1e-10) timed
+    separately."""
+    import torch
+    from synth import adjoint_case
+    case = adjoint_case(n=N_SIDE, kn=0.1, n_probes=64, particles=PARTICLES)
+    w = case.workload
+    probes = torch.tensor(case.probes, device=dev)
+    target = torch.tensor(case.target, device=dev)
+    walls = torch.tensor(case.walls4, device=dev, requires_grad=True)
+    src = torch.tensor(w.source, device=dev, requires_grad=True)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    T = P.steady_temperature(walls, src, w, max_iters=200, res_tol=1e-9, newton=True)
+    loss = ((T[probes] - target) ** 2).sum()
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    c = time.perf_counter()
+    return {"forward_s": round(b - a, 4), "backward_s": round(c - b, 4),
+            "loss": loss.item(), "grad_walls": [round(x, 12) for x in walls.grad.tolist()],
+            "grad_source_norm": src.grad.norm().item()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -287,6 +315,9 @@ def main():
 
     if args.batch:
         out["batched"] = bench_batch(P, dev, args.batch)
+
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(P, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
