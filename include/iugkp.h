@@ -247,6 +247,13 @@ int iugkp_dev_philox(const uint32_t *ctr, uint32_t key0, uint32_t key1, uint32_t
  * with k = (int)y; out[i] = op(x[i], y[i]). */
 int iugkp_dev_math(int op, const double *x, const double *y, double *out, int64_t n,
                    void *stream);
+/* iugkp_dev_segments: the closed-form segment walk used when no face is tallied,
+ * on a dim/nx/ny/dx/dy mesh.  rays[7i..7i+6] = x0, y0, ix, iy (cell of the start
+ * point, as doubles), sx, sy, ell; out[3i..3i+2] = 1 if a boundary face absorbs
+ * the segment else 0, that face's wall index or the final cell ix + nx iy, and
+ * the number of faces crossed (the wall face included). */
+int iugkp_dev_segments(int dim, int nx, int ny, double dx, double dy, const double *rays,
+                       int64_t n, int64_t *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -8,13 +8,14 @@ from ._lib import (FACES_EVERY, FACES_FINAL, FACES_OFF, RNG_CRN, RNG_FRESH, Iugk
                    lib as library)
 
 __all__ = ["Solver", "BatchSolver", "steady_temperature", "d_eff", "dev_philox", "dev_math",
+           "dev_segments",
            "FACES_EVERY",
            "FACES_FINAL", "FACES_OFF", "RNG_CRN", "RNG_FRESH", "IugkpError", "library"]
 
 
 def __getattr__(name):
     # torch is imported lazily so that the C-ABI declarations load without it
-    if name in ("Solver", "d_eff", "dev_philox", "dev_math"):
+    if name in ("Solver", "d_eff", "dev_philox", "dev_math", "dev_segments"):
         from . import solver
         return getattr(solver, name)
     if name == "BatchSolver":

@@ -1047,6 +1047,32 @@ int iugkp_dev_math(int op, const double *x, const double *y, double *out, int64_
   return IUGKP_OK;
 }
 
+int iugkp_dev_segments(int dim, int nx, int ny, double dx, double dy, const double *rays,
+                       int64_t n, int64_t *out, void *stream)
+{
+  if (!rays || !out || n < 0 || (dim != 1 && dim != 2) || nx < 1 || ny < 1 ||
+      (dim == 1 && ny != 1) || !(dx > 0.0) || !(dy > 0.0))
+    return fail(IUGKP_E_INVALID_ARG, "bad arguments");
+  Mesh m{};
+  m.dim = dim;
+  m.nx = nx;
+  m.ny = ny;
+  m.n_cells = nx * ny;
+  m.n_b = 2 * ny + (dim == 2 ? 2 * nx : 0);
+  m.n_emit = m.n_cells + m.n_b;
+  m.n_fx = ny * (nx + 1);
+  m.n_fy = (dim == 2) ? (ny + 1) * nx : 0;
+  m.dx = dx;
+  m.dy = dy;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n > 0)
+    iugkp::segment_probe_kernel<<<cdiv(n, 256), 256, 0, s>>>(m, rays, n,
+                                                             reinterpret_cast<long long *>(out));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return IUGKP_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

@@ -270,6 +270,66 @@ __host__ __device__ inline size_t window_words(int WX, int WY, int has_null, int
 //   add_wall(b, q)       absorbed by boundary face b
 //   add_cand(ix, iy, q)  candidate collision (null-collision runs only)
 //   add_real(ix, iy, q)  real collision (deposit)
+// Number of faces j = 0..jmax of the sequence k(j) = k0 + j st reached before
+// T: t(j) = (k(j) d - p0) * inv < T (STRICT) or <= T.  t(j) is the walk's own
+// expression and is non-decreasing in j (each rounding step is monotone), so
+// the faces reached form a prefix and a binary search finds its length.
+template <bool STRICT>
+__device__ __forceinline__ int faces_before(int k0, int st, int jmax, double d, double p0,
+                                            double inv, double T)
+{
+  int lo = 0, hi = jmax + 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const double t = (static_cast<double>(k0 + mid * st) * d - p0) * inv;
+    if (STRICT ? (t < T) : (t <= T)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// The walk of one segment of length ell from (x0, y0) in cell (ix, iy) with
+// no face tallies, in closed form.  Crossings before ell in each direction are
+// prefixes of the face sequences (faces_before); the walk ends at the first
+// wall face in time order (x first on ties) or in the cell reached after all
+// crossings.  Same final cell, wall face (bface, else left at -1) and crossing
+// count as the face-by-face walk.  kx, ky: the first faces ahead.
+__device__ __forceinline__ void segment_jump(const Mesh &m, double x0, double y0, int &ix, int &iy,
+                                             int stx, int sty, double inv_sx, double inv_sy, int kx,
+                                             int ky, double ell, int &bface,
+                                             unsigned long long &n_cross)
+{
+  const int jwx = (stx > 0) ? m.nx - kx : kx;   // position of the x wall in the sequence
+  const int jwy = (sty > 0) ? m.ny - ky : ky;
+  const int nxc = stx ? faces_before<true>(kx, stx, jwx, m.dx, x0, inv_sx, ell) : 0;
+  const int nyc = sty ? faces_before<true>(ky, sty, jwy, m.dy, y0, inv_sy, ell) : 0;
+  const bool wx = stx && nxc > jwx, wy = sty && nyc > jwy;
+  if (wx || wy) {
+    const int kwx = kx + jwx * stx, kwy = ky + jwy * sty;
+    const double Tx = wx ? (static_cast<double>(kwx) * m.dx - x0) * inv_sx : INFINITY;
+    const double Ty = wy ? (static_cast<double>(kwy) * m.dy - y0) * inv_sy : INFINITY;
+    if (wx && Tx <= Ty) {
+      const int nb = sty ? faces_before<true>(ky, sty, jwy, m.dy, y0, inv_sy, Tx) : 0;
+      iy += sty * nb;
+      n_cross += static_cast<unsigned long long>(jwx + 1 + nb);
+      bface = (kwx == 0) ? iy : m.ny + iy;
+    } else {
+      const int nb = stx ? faces_before<false>(kx, stx, jwx, m.dx, x0, inv_sx, Ty) : 0;
+      ix += stx * nb;
+      n_cross += static_cast<unsigned long long>(jwy + 1 + nb);
+      bface = (kwy == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
+    }
+  } else {
+    ix += stx * nxc;
+    iy += sty * nyc;
+    n_cross += static_cast<unsigned long long>(nxc + nyc);
+  }
+}
+
+// A segment expected to cross more faces than this is resolved in closed form
+// when no face is tallied (same outcome as the walk, see fly()).
+constexpr double kJumpMinFaces = 6.0;
+
 struct FlyIn {
   Mesh m;
   double lam_min;
@@ -337,6 +397,9 @@ __device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long
     int ky = (sty > 0) ? iy + 1 : iy;
     int bface = -1;
     int run_a = -1, run_b = -1;   // first and last y-face of the open run
+    if (!a.faces && ell * (fabs(sx) / m.dx + fabs(sy) / m.dy) > kJumpMinFaces) {
+      segment_jump(m, x0, y0, ix, iy, stx, sty, inv_sx, inv_sy, kx, ky, ell, bface, n_cross);
+    } else
     for (;;) {
       const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
       const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
@@ -1601,6 +1664,28 @@ __global__ void philox_probe_kernel(const uint32_t *ctr, uint32_t k0, uint32_t k
   out[4 * i + 1] = o.y;
   out[4 * i + 2] = o.z;
   out[4 * i + 3] = o.w;
+}
+
+// segment_jump on given segments: rays[7 i ..] = x0, y0, ix, iy, sx, sy, ell;
+// out[3 i ..] = absorbed (0/1), final cell or wall face, crossings
+__global__ void segment_probe_kernel(Mesh m, const double *rays, long long n, long long *out)
+{
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double *r = rays + 7 * i;
+  const double x0 = r[0], y0 = r[1], sx = r[4], sy = r[5], ell = r[6];
+  int ix = static_cast<int>(r[2]), iy = static_cast<int>(r[3]);
+  const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+  const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+  const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+  const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+  const int kx = (stx > 0) ? ix + 1 : ix, ky = (sty > 0) ? iy + 1 : iy;
+  int bface = -1;
+  unsigned long long nc = 0;
+  segment_jump(m, x0, y0, ix, iy, stx, sty, inv_sx, inv_sy, kx, ky, ell, bface, nc);
+  out[3 * i] = bface >= 0 ? 1 : 0;
+  out[3 * i + 1] = bface >= 0 ? bface : ix + m.nx * iy;
+  out[3 * i + 2] = static_cast<long long>(nc);
 }
 
 __global__ void math_probe_kernel(int op, const double *x, const double *y, double *out,

@@ -190,6 +190,19 @@ def dev_philox(ctr: torch.Tensor, key0: int, key1: int) -> torch.Tensor:
     return out
 
 
+def dev_segments(dim: int, nx: int, ny: int, dx: float, dy: float,
+                 rays: torch.Tensor) -> torch.Tensor:
+    """Closed-form segment walks on the device: rays (n, 7) float64 rows
+    (x0, y0, ix, iy, sx, sy, ell) -> (n, 3) int64 (absorbed, cell or face, crossings)."""
+    rays = rays.to(torch.float64).contiguous()
+    out = torch.empty((rays.shape[0], 3), dtype=torch.int64, device=rays.device)
+    L.check(L.lib().iugkp_dev_segments(int(dim), int(nx), int(ny), float(dx), float(dy),
+                                       rays.data_ptr(), rays.shape[0], out.data_ptr(),
+                                       C.c_void_p(_stream_handle(rays.device))),
+            "iugkp_dev_segments")
+    return out
+
+
 def dev_math(op: int, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
     x = x.contiguous()
     out = torch.empty_like(x)
