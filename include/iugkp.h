@@ -105,6 +105,9 @@ typedef struct iugkp_options {
   int tally_faces;              /* IUGKP_FACES_* */
   int avg_iters;                /* iterations averaged for the outputs after stopping (>= 0) */
   int block_size;               /* transport kernel workgroup size: 0 (= 256), 64..1024 */
+  int march;                    /* single solves, iterations with face tallies on 2D meshes:
+                                   0 automatic, 1 emitter tiles, 2 row stripes (long free
+                                   paths); the result does not depend on it */
   int cg_waves;                 /* single solves: 256-cell tree blocks per CG workgroup, 0
                                    (= 8) or 1..12 with the CG state in registers, -1..-12 with
                                    it in global memory; the result does not depend on it */

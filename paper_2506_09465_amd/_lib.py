@@ -36,7 +36,7 @@ class Options(C.Structure):
                 ("rng_mode", C.c_int), ("rng_epoch", C.c_uint32), ("max_iters", C.c_int),
                 ("res_tol", C.c_double), ("newton", C.c_int), ("cg_tol", C.c_double),
                 ("cg_max_iters", C.c_int), ("tally_faces", C.c_int), ("avg_iters", C.c_int),
-                ("block_size", C.c_int), ("cg_waves", C.c_int)]
+                ("block_size", C.c_int), ("march", C.c_int), ("cg_waves", C.c_int)]
 
 
 class Stats(C.Structure):

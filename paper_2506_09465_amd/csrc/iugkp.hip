@@ -45,6 +45,9 @@ int fail(int code, const std::string &msg)
 constexpr int kCgGridMax = 64;               // workgroups of one CG group (barrier arrivals)
 constexpr int kCgWavesDefault = 8;           // tree blocks per CG workgroup of a single solve
 constexpr int kBarStride = 64;               // batched CG barriers 256 bytes apart (no shared lines)
+constexpr double kStripeMinCells = 64.0;     // row stripes for face tallies when lambda_min >= 64 cells
+constexpr int kStripeBlock = 1024;           // threads of a stripe workgroup
+constexpr int kStripeMinRows = 4;
 constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of a CG workgroup
 constexpr int kTileX = 8, kTileY = 8;        // emitter tile of one workgroup (cells)
 constexpr int kWallSeg = 8;                  // wall faces per workgroup
@@ -85,6 +88,9 @@ struct InstHost {
   unsigned int *cg_barrier = nullptr;
   int cg_grid = 1, cg_tb = 1, cg_reg = 1, cg_threads = 64;
   size_t cg_lds = 0;
+  // row-stripe particle step for face-tallied iterations (single solves)
+  int stripe_R = 0, stripe_S = 0, stripe_C = 0;
+  size_t stripe_lds = 0;
 
   template <class T>
   hipError_t alloc(T **p, size_t n)
@@ -134,6 +140,7 @@ int check_options(const iugkp_options *o)
   const int bs = o->block_size;
   if (bs != 0 && bs != 64 && bs != 128 && bs != 256 && bs != 512 && bs != 1024)
     return fail(IUGKP_E_INVALID_ARG, "block_size must be 0, 64, 128, 256, 512 or 1024");
+  if (o->march < 0 || o->march > 2) return fail(IUGKP_E_INVALID_ARG, "march must be 0, 1 or 2");
   if (o->cg_waves < -iugkp::kCgWavesMax || o->cg_waves > iugkp::kCgWavesMax)
     return fail(IUGKP_E_INVALID_ARG, "cg_waves must be -12..12");
   return IUGKP_OK;
@@ -472,6 +479,38 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
       ih.cg_lds = lds;
     }
   }
+  if (multi_cg && p->dim == 2 && o->tally_faces != IUGKP_FACES_OFF &&
+      (o->march == 2 ||
+       (o->march == 0 && d.lam_min >= kStripeMinCells * std::min(p->dx, p->dy)))) {
+    // row stripes: as many rows per workgroup as its LDS holds (y faces, D,
+    // W with null collisions, the walls), about two workgroups per CU
+    int dev = 0, n_cu = 0, lds_max = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const long long words = lds_max / 8 - 16;
+    const long long per_row = static_cast<long long>(m.nx) * (d.has_null ? 3 : 2);
+    const long long fixed = m.nx + (d.lds_walls ? m.n_b : 0);
+    int R = static_cast<int>((words - fixed) / per_row);
+    if (R >= kStripeMinRows || (R >= 1 && R >= m.ny)) {
+      R = std::min(R, m.ny);
+      const int S = cdiv(m.ny, R);
+      R = cdiv(m.ny, S);
+      const size_t lds = static_cast<size_t>(fixed + per_row * R) * sizeof(long long);
+      int per_cu = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>),
+          kStripeBlock, lds));
+      if (per_cu >= 1) {
+        ih.stripe_R = R;
+        ih.stripe_S = S;
+        ih.stripe_C = std::max(1, cdiv(2ll * per_cu * n_cu, S));
+        ih.stripe_lds = lds;
+      }
+    }
+    if (o->march == 2 && ih.stripe_R == 0)
+      return fail(IUGKP_E_INVALID_ARG, "row stripes do not fit this mesh");
+  }
   std::vector<long long> g(ne);
   int hflag = 0;
   HIP_TRY(hipMemcpyAsync(g.data(), d.G, ne * sizeof(long long), hipMemcpyDeviceToHost, s));
@@ -693,8 +732,16 @@ int iterate(iugkp_handle *h, int faces)
   iugkp::prepare_kernel<<<dim3(cdiv(nprep, 256), 1), 256, 0, s>>>(h->d_inst, faces, 0);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(h->ev[0], s));
-  int rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, ih.lds_bytes, h->block, faces, 0, s);
-  if (rc) return rc;
+  int rc = IUGKP_OK;
+  if (faces && ih.stripe_R > 0) {
+    iugkp::march_stripes_kernel<kStripeBlock>
+        <<<dim3(ih.stripe_C, ih.stripe_S), kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R,
+                                                                              ih.stripe_C);
+    HIP_TRY(hipGetLastError());
+  } else {
+    rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, ih.lds_bytes, h->block, faces, 0, s);
+    if (rc) return rc;
+  }
   HIP_TRY(hipEventRecord(h->ev[1], s));
   if (faces) {
     iugkp::reconstruct_y_kernel<<<dim3(cdiv(m.nx, 256), 1), 256, 0, s>>>(h->d_inst, faces, 0);

@@ -289,15 +289,15 @@ __device__ __forceinline__ int faces_before(int k0, int st, int jmax, double d, 
 }
 
 // The walk of one segment of length ell from (x0, y0) in cell (ix, iy) with
-// no face tallies, in closed form.  Crossings before ell in each direction are
+// no face tallies, in closed form (segment_end also returns the x and y faces
+// crossed, nxp and nyp, a crossed wall face included).  Crossings before ell in each direction are
 // prefixes of the face sequences (faces_before); the walk ends at the first
 // wall face in time order (x first on ties) or in the cell reached after all
 // crossings.  Same final cell, wall face (bface, else left at -1) and crossing
 // count as the face-by-face walk.  kx, ky: the first faces ahead.
-__device__ __forceinline__ void segment_jump(const Mesh &m, double x0, double y0, int &ix, int &iy,
-                                             int stx, int sty, double inv_sx, double inv_sy, int kx,
-                                             int ky, double ell, int &bface,
-                                             unsigned long long &n_cross)
+__device__ __forceinline__ void segment_end(const Mesh &m, double x0, double y0, int &ix, int &iy,
+                                            int stx, int sty, double inv_sx, double inv_sy, int kx,
+                                            int ky, double ell, int &bface, int &nxp, int &nyp)
 {
   const int jwx = (stx > 0) ? m.nx - kx : kx;   // position of the x wall in the sequence
   const int jwy = (sty > 0) ? m.ny - ky : ky;
@@ -311,19 +311,32 @@ __device__ __forceinline__ void segment_jump(const Mesh &m, double x0, double y0
     if (wx && Tx <= Ty) {
       const int nb = sty ? faces_before<true>(ky, sty, jwy, m.dy, y0, inv_sy, Tx) : 0;
       iy += sty * nb;
-      n_cross += static_cast<unsigned long long>(jwx + 1 + nb);
+      nxp = jwx + 1;
+      nyp = nb;
       bface = (kwx == 0) ? iy : m.ny + iy;
     } else {
       const int nb = stx ? faces_before<false>(kx, stx, jwx, m.dx, x0, inv_sx, Ty) : 0;
       ix += stx * nb;
-      n_cross += static_cast<unsigned long long>(jwy + 1 + nb);
+      nxp = nb;
+      nyp = jwy + 1;
       bface = (kwy == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
     }
   } else {
     ix += stx * nxc;
     iy += sty * nyc;
-    n_cross += static_cast<unsigned long long>(nxc + nyc);
+    nxp = nxc;
+    nyp = nyc;
   }
+}
+
+__device__ __forceinline__ void segment_jump(const Mesh &m, double x0, double y0, int &ix, int &iy,
+                                             int stx, int sty, double inv_sx, double inv_sy, int kx,
+                                             int ky, double ell, int &bface,
+                                             unsigned long long &n_cross)
+{
+  int nxp = 0, nyp = 0;
+  segment_end(m, x0, y0, ix, iy, stx, sty, inv_sx, inv_sy, kx, ky, ell, bface, nxp, nyp);
+  n_cross += static_cast<unsigned long long>(nxp + nyp);
 }
 
 // A segment expected to cross more faces than this is resolved in closed form
@@ -338,17 +351,17 @@ struct FlyIn {
   const double *ratio;
 };
 
-template <class Diff, class YFace, class Wall, class Cand, class Real>
-__device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long long q,
-                                    Diff &&add_diff, YFace &&add_yface, Wall &&add_wall,
-                                    Cand &&add_cand, Real &&add_real, unsigned long long &n_seg,
-                                    unsigned long long &n_cross)
+// Start point and direction of particle k of emitter e: a uniform point of the
+// cell and an isotropic 3D direction projected on the plane (cell emitters),
+// or a uniform point of the wall face and a cosine-law direction into the
+// domain (wall emitters).
+__device__ __forceinline__ void sample_particle(const FlyIn &a, uint32_t e, uint32_t k, int &ix,
+                                                int &iy, double &x0, double &y0, double &sx,
+                                                double &sy)
 {
   const Mesh &m = a.m;
   const double2 uab = draw2(0u, k, e, a.slot, a.key0, a.key1);
   const double2 ucd = draw2(1u, k, e, a.slot, a.key0, a.key1);
-  int ix, iy;
-  double x0, y0, sx, sy;
   if (e < static_cast<uint32_t>(m.n_cells)) {
     // isotropic emission from a uniformly sampled point of the cell
     iy = static_cast<int>(e) / m.nx;
@@ -381,6 +394,18 @@ __device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long
       sx = tg; sy = -cn;
     }
   }
+}
+
+template <class Diff, class YFace, class Wall, class Cand, class Real>
+__device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long long q,
+                                    Diff &&add_diff, YFace &&add_yface, Wall &&add_wall,
+                                    Cand &&add_cand, Real &&add_real, unsigned long long &n_seg,
+                                    unsigned long long &n_cross)
+{
+  const Mesh &m = a.m;
+  int ix, iy;
+  double x0, y0, sx, sy;
+  sample_particle(a, e, k, ix, iy, x0, y0, sx, sy);
   const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
   const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
   const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
@@ -588,6 +613,224 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
     atomicAdd(&a.sc->flights, s_cnt[0]);
     atomicAdd(&a.sc->segments, s_cnt[1]);
     atomicAdd(&a.sc->crossings, s_cnt[2]);
+  }
+}
+
+// Number of faces j <= jmax of the sequence k(j) = k0 + j st with
+// t(j) = (k(j) d - p0) * inv <= T, given that the first cnt are: galloping
+// from cnt, then bisection (t is non-decreasing in j).
+__device__ __forceinline__ int faces_upto_from(int cnt, int k0, int st, int jmax, double d,
+                                               double p0, double inv, double T)
+{
+  int lo = cnt, hi = jmax + 1, step = 1;
+  for (;;) {
+    const int probe = lo + step - 1;
+    if (probe > jmax) break;
+    const double t = (static_cast<double>(k0 + probe * st) * d - p0) * inv;
+    if (!(t <= T)) {
+      hi = probe;
+      break;
+    }
+    lo = probe + 1;
+    step <<= 1;
+  }
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const double t = (static_cast<double>(k0 + mid * st) * d - p0) * inv;
+    if (t <= T) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// The particle step with face tallies for long free paths, by row stripes.
+// Workgroup (chunk c, stripe s) keeps in LDS the y-face tallies of faces
+// [r0, r1f) (the last stripe also owns face ny), the deposits D (and W) of
+// rows [r0, r1) and the wall tallies, and runs every particle of its chunk:
+// sampling and each segment's end in closed form (segment_end), then only
+// the y faces it crosses inside the stripe, each in the column reached by the
+// x faces crossed first (x first on ties, as in the walk).  A particle's
+// deposits, wall absorption and counters go to the stripe holding the row
+// where that event happens.  All tallies are integer sums, so the result is
+// the tile kernel's bit for bit, and no tally leaves LDS before the final
+// row-contiguous flush.  Each lane runs a small state machine (next particle
+// / one y-face crossing / segment end), so lanes with long flights do not
+// hold the others of their wavefront.
+// ---------------------------------------------------------------------------
+template <int BS>
+__global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restrict__ insts, int R,
+                                                           int chunks)
+{
+  extern __shared__ long long lds_words[];
+  __shared__ unsigned long long s_cnt[3];
+  const Inst &in = insts[0];
+  const Mesh &m = in.m;
+  const int nx = m.nx;
+  const int r0 = static_cast<int>(blockIdx.y) * R, r1 = min(r0 + R, m.ny);
+  const int r1f = (r1 == m.ny) ? m.ny + 1 : r1;
+  const int nrow = r1 - r0, nface = r1f - r0;
+  long long *By = lds_words;                                  // [nface][nx]
+  long long *Dl = By + nface * nx;                            // [nrow][nx]
+  long long *Wl = in.has_null ? Dl + nrow * nx : nullptr;     // [nrow][nx]
+  long long *Bl = (in.has_null ? Wl : Dl) + nrow * nx;        // [n_b] when lds_walls
+  const int nwords = nface * nx + nrow * nx * (in.has_null ? 2 : 1) + (in.lds_walls ? m.n_b : 0);
+  for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  auto lds_add = [](long long *p, long long v) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
+  };
+
+  const FlyIn fa = {m, in.lam_min, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1, 1,
+                    in.has_null, in.ratio};
+  const uint32_t N = in.N;
+  const unsigned long long total = static_cast<unsigned long long>(m.n_emit) * N;
+  const unsigned long long pb = total * blockIdx.x / chunks;
+  const unsigned long long pe = total * (blockIdx.x + 1) / chunks;
+  unsigned long long pnext = pb + threadIdx.x;
+  unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
+
+  // the lane's particle
+  bool live = false;
+  uint32_t e = 0, kk = 0, j = 0;
+  long long q = 0, qy = 0;
+  int ix = 0, iy = 0, stx = 0, sty = 0;
+  double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0, inv_sx = 0.0, inv_sy = 0.0;
+  unsigned p_seg = 0, p_cross = 0;
+  // its current segment
+  double ell = 0.0, uacc = 0.0;
+  int kx0 = 0, ky0 = 0, ixs = 0, jwx = 0, k = 0, k_end = 0, cnt = 0, ixe = 0, iye = 0, bface = -1;
+
+  auto start_segment = [&]() {
+    const double2 us = draw2(2u + j, kk, e, fa.slot, fa.key0, fa.key1);
+    ell = -(fa.lam_min * log_own(1.0 - us.x));
+    uacc = us.y;
+    ++p_seg;
+    kx0 = (stx > 0) ? ix + 1 : ix;
+    ky0 = (sty > 0) ? iy + 1 : iy;
+    ixs = ix;
+    jwx = (stx > 0) ? nx - kx0 : kx0;
+    ixe = ix;
+    iye = iy;
+    bface = -1;
+    int nxp = 0, nyp = 0;
+    segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
+    p_cross += static_cast<unsigned>(nxp + nyp);
+    // the crossed y faces ky0 + k sty (k < nyp) that this stripe owns
+    if (sty > 0) {
+      k = max(0, r0 - ky0);
+      k_end = min(nyp, r1f - ky0);
+    } else if (sty < 0) {
+      k = max(0, ky0 - r1f + 1);
+      k_end = min(nyp, ky0 - r0 + 1);
+    } else {
+      k = 0;
+      k_end = 0;
+    }
+    cnt = 0;
+  };
+  auto owned = [&](int row) { return row >= r0 && row < r1; };
+  auto retire = [&]() {          // the particle ended in row iye of this stripe
+    ++n_fl;
+    n_seg += p_seg;
+    n_cross += p_cross;
+  };
+
+  for (;;) {
+    if (!live) {
+      bool got = false;
+      while (pnext < pe) {
+        const unsigned long long pc = pnext;
+        pnext += BS;
+        e = static_cast<uint32_t>(pc / N);
+        kk = static_cast<uint32_t>(pc - static_cast<unsigned long long>(e) * N);
+        q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
+        if (q != 0) {
+          got = true;
+          break;
+        }
+      }
+      if (!got) break;
+      sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
+      inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+      inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+      stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+      sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+      qy = (sty > 0) ? q : -q;
+      j = 0;
+      p_seg = 0;
+      p_cross = 0;
+      live = true;
+      start_segment();
+    }
+    if (k < k_end) {
+      // one owned y-face crossing, in the column reached by the x faces before it
+      const int kyk = ky0 + k * sty;
+      const double ty = (static_cast<double>(kyk) * m.dy - y0) * inv_sy;
+      if (stx) cnt = faces_upto_from(cnt, kx0, stx, jwx, m.dx, x0, inv_sx, ty);
+      lds_add(&By[(kyk - r0) * nx + ixs + stx * cnt], qy);
+      ++k;
+      continue;
+    }
+    // the segment's end
+    if (bface >= 0) {
+      if (owned(iye)) {
+        if (!in.lds_walls) atom_add(&in.B[bface], q);
+        else lds_add(&Bl[bface], q);
+        retire();
+      }
+      live = false;
+      continue;
+    }
+    if (!fa.has_null) {
+      if (owned(iye)) {
+        lds_add(&Dl[(iye - r0) * nx + ixe], q);
+        retire();
+      }
+      live = false;
+      continue;
+    }
+    if (owned(iye)) lds_add(&Wl[(iye - r0) * nx + ixe], q);
+    const int c = ixe + nx * iye;
+    if (uacc < fa.ratio[c] || j == kMaxSegments - 1) {
+      if (owned(iye)) {
+        lds_add(&Dl[(iye - r0) * nx + ixe], q);
+        retire();
+      }
+      live = false;
+      continue;
+    }
+    // null collision: same direction, new free path from the stopping point
+    x0 = clamp_to(x0 + ell * sx, static_cast<double>(ixe) * m.dx,
+                  static_cast<double>(ixe + 1) * m.dx);
+    y0 = clamp_to(y0 + ell * sy, static_cast<double>(iye) * m.dy,
+                  static_cast<double>(iye + 1) * m.dy);
+    ix = ixe;
+    iy = iye;
+    ++j;
+    start_segment();
+  }
+  if (n_fl) {
+    atomicAdd(&s_cnt[0], n_fl);
+    atomicAdd(&s_cnt[1], n_seg);
+    atomicAdd(&s_cnt[2], n_cross);
+  }
+  __syncthreads();
+  // row-contiguous flush
+  for (int i = threadIdx.x; i < nface * nx; i += BS)
+    if (By[i]) atom_add(&in.Phiy[r0 * nx + i], By[i]);
+  for (int i = threadIdx.x; i < nrow * nx; i += BS) {
+    if (Dl[i]) atom_add(&in.D[r0 * nx + i], Dl[i]);
+    if (Wl && Wl[i]) atom_add(&in.W[r0 * nx + i], Wl[i]);
+  }
+  if (in.lds_walls)
+    for (int b = threadIdx.x; b < m.n_b; b += BS)
+      if (Bl[b]) atom_add(&in.B[b], Bl[b]);
+  if (threadIdx.x == 0 && s_cnt[0]) {
+    atomicAdd(&in.sc->flights, s_cnt[0]);
+    atomicAdd(&in.sc->segments, s_cnt[1]);
+    atomicAdd(&in.sc->crossings, s_cnt[2]);
   }
 }
 

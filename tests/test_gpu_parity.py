@@ -33,7 +33,7 @@ def _diff(w):
     return Dx, Dy
 
 
-_LAUNCH_KEYS = ("cg_waves", "block_size")   # GPU launch shape only, no effect on results
+_LAUNCH_KEYS = ("cg_waves", "block_size", "march")   # GPU launch shape only, no effect on results
 
 
 def _pair(oracle_mod, gpu, w, **kw):

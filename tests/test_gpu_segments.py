@@ -105,3 +105,53 @@ def test_iterations_without_faces_bitwise(oracle_mod, gpu, case):
     assert (oi.flights, oi.segments, oi.crossings) == (st["flights"], st["segments"], st["crossings"])
     it, d0, E, G = s.state()
     assert np.array_equal(o.E(), _np(E)) and np.array_equal(o.G(), _np(G))
+
+
+STRIPE_CASES = {
+    # name: (workload, options) -- face-tallied iterations on the row-stripe particle step
+    "cavity_kn10": (lambda: cavity_2d(n=40, kn=10.0, particles=300_000, newton=False), {}),
+    "cavity_kn0.3_ragged": (lambda: cavity_2d(n=37, ny=23, kn=0.3, particles=200_000,
+                                              newton=False), {}),
+    "two_material_null": (lambda: two_material_2d(n=48, kn_right=0.3, ratio=10.0,
+                                                  particles=300_000), {}),
+    "strip_1x9": (lambda: cavity_2d(n=1, ny=9, kn=3.0, particles=20_000, newton=False), {}),
+    "wide_300x7": (lambda: cavity_2d(n=300, ny=7, kn=2.0, particles=200_000, newton=False), {}),
+    "tall_9x300": (lambda: cavity_2d(n=9, ny=300, kn=2.0, particles=200_000, newton=False), {}),
+    "newton_kn1": (lambda: cavity_2d(n=64, kn=1.0, particles=400_000, newton=False), "newton"),
+}
+
+
+@pytest.mark.parametrize("name", list(STRIPE_CASES))
+def test_stripe_march_bitwise(oracle_mod, gpu, name):
+    """Row stripes (forced) against the oracle, faces tallied every iteration:
+    all tallies, counters and the state bit for bit."""
+    make, extra = STRIPE_CASES[name]
+    w = make()
+    kw = dict(tally_faces=oracle_mod.FACES_EVERY)
+    if extra == "newton":
+        Dx, Dy = _diff(w)
+        kw.update(newton=True, diff_x=Dx, diff_y=Dy)
+    o, s = _pair(oracle_mod, gpu, w, march=2, **kw)
+    assert o.step(2) == 0 and s.step(2) == 0
+    to = o.tallies()
+    ts = {k: _np(v) for k, v in s.tallies().items()}
+    for k in ("D", "W", "Phix", "Phiy", "B"):
+        assert np.array_equal(to[k], ts[k]), f"{name} {k}"
+    oi, st = o.info(), s.stats()
+    assert (oi.flights, oi.segments, oi.crossings) == (st["flights"], st["segments"], st["crossings"])
+    it, d0, E, G = s.state()
+    assert np.array_equal(o.E(), _np(E)) and np.array_equal(o.G(), _np(G))
+
+
+def test_stripe_and_tile_marches_agree_256(gpu):
+    """On the 256 x 256 cavity at Kn = 10 both particle steps give identical
+    tallies (forced tiles vs forced stripes)."""
+    w = cavity_2d(n=256, kn=10.0, particles=10_000_000, newton=False)
+    out = []
+    for march in (1, 2):
+        s = gpu.Solver(w, march=march, tally_faces=gpu.FACES_EVERY)
+        assert s.step(2) == 0
+        out.append({k: _np(v) for k, v in s.tallies().items()} | {"st": s.stats()})
+    for k in ("D", "Phix", "Phiy", "B"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+    assert out[0]["st"]["crossings"] == out[1]["st"]["crossings"]
