@@ -504,7 +504,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
       if (per_cu >= 1) {
         ih.stripe_R = R;
         ih.stripe_S = S;
-        ih.stripe_C = std::max(1, cdiv(2ll * per_cu * n_cu, S));
+        ih.stripe_C = std::max(1, (2 * per_cu * n_cu) / S);   // whole rounds of resident groups
         ih.stripe_lds = lds;
       }
     }
