@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=256,
                     help="instances of the batched vs sequential comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient timing")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 256 MiB buffer three times (scales rocprofv3 FETCH_SIZE / "
+                         "WRITE_SIZE to bytes) and exit")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="particles per iteration in the CPU oracle sample")
     return ap.parse_args()
@@ -204,8 +207,22 @@ def bench_adjoint(P, dev):
             "grad_source_norm": src.grad.norm().item()}
 
 
+def copy_calibration():
+    import torch
+    n = 256 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copied_bytes_per_dispatch": n * 8, "dispatches": 3}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding is described in DESIGN.md and not built.", file=sys.stderr)
