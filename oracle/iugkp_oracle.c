@@ -568,6 +568,7 @@ int orc_create(const orc_problem *p, const orc_options *o, orc_state **out)
   *out = NULL;
   int rc = orc_validate(p);
   if (rc) return rc;
+  if (p->n_bands > 1) return ORC_E_INVALID_ARG;   /* bands: orc_bands_create */
   if (!o || o->particles_per_iter < 1 || o->max_iters < 0 || o->avg_iters < 0)
     return ORC_E_INVALID_ARG;
   if (o->newton && (!p->diff_x || (p->dim == 2 && !p->diff_y) || !(o->cg_tol > 0.0) ||
@@ -708,18 +709,37 @@ static double orc_clamp(double v, double lo, double hi)
   return v;
 }
 
+/* What a flight needs besides its counters: the mesh, the seed, the candidate
+ * mean free path |V_g| tau* of its band, the acceptance tau* / tau per cell,
+ * and the offset of the band's emitters in the Philox counter (0 when gray). */
+typedef struct {
+  const orc_problem *p;
+  int nc;
+  uint64_t seed;
+  double lam;
+  const double *ratio;
+  uint32_t e_off;
+} orc_flyctx;
+
+static orc_flyctx orc_gray_ctx(const orc_state *s)
+{
+  orc_flyctx f = {&s->p, s->nc, s->o.seed, s->lam_min, s->ratio, 0u};
+  return f;
+}
+
 /* Fly particle k of emitter e carrying q (q != 0). */
-static void orc_fly(orc_state *s, uint32_t slot, int e, uint32_t k, int64_t q, orc_tally *t,
+static void orc_fly(const orc_flyctx *f, uint32_t slot, int e, uint32_t k, int64_t q, orc_tally *t,
                     uint64_t *segs)
 {
-  const orc_problem *p = &s->p;
+  const orc_problem *p = f->p;
   int nx = p->nx, ny = p->ny;
+  uint32_t ec = (uint32_t)e + f->e_off;
   double ua, ub, uc, ud;
-  orc_draw(s->o.seed, slot, (uint32_t)e, k, 0u, &ua, &ub);
-  orc_draw(s->o.seed, slot, (uint32_t)e, k, 1u, &uc, &ud);
+  orc_draw(f->seed, slot, ec, k, 0u, &ua, &ub);
+  orc_draw(f->seed, slot, ec, k, 1u, &uc, &ud);
   int ix, iy;
   double x0, y0, sx, sy;
-  if (e < s->nc) {
+  if (e < f->nc) {
     /* equilibrium emission from a cell: uniform position, isotropic 3D direction */
     ix = e % nx;
     iy = e / nx;
@@ -730,7 +750,7 @@ static void orc_fly(orc_state *s, uint32_t slot, int e, uint32_t k, int64_t q, o
     sy = (p->dim == 2) ? sqrt((1.0 - mu) * (1.0 + mu)) * orc_cos2pi(ud) : 0.0;
   } else {
     /* wall emission (reading R1): cosine-law direction into the domain */
-    int b = e - s->nc;
+    int b = e - f->nc;
     double cn = sqrt(uc);
     double tg = (p->dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * orc_cos2pi(ud) : 0.0;
     if (b < ny) {                       /* left wall, row b */
@@ -755,9 +775,9 @@ static void orc_fly(orc_state *s, uint32_t slot, int e, uint32_t k, int64_t q, o
   double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
   for (uint32_t j = 0;; ++j) {
     double ulen, uacc;
-    orc_draw(s->o.seed, slot, (uint32_t)e, k, 2u + j, &ulen, &uacc);
+    orc_draw(f->seed, slot, ec, k, 2u + j, &ulen, &uacc);
     /* candidate free path on the common time scale: -|V_g| tau_min ln(eta) */
-    double ell = -(s->lam_min * orc_log(1.0 - ulen));
+    double ell = -(f->lam * orc_log(1.0 - ulen));
     (*segs)++;
     int bface = -1;
     if (orc_march(p, x0, y0, &ix, &iy, sx, sy, inv_sx, inv_sy, ell, q, t, &bface)) {
@@ -768,7 +788,7 @@ static void orc_fly(orc_state *s, uint32_t slot, int e, uint32_t k, int64_t q, o
     int c = ix + nx * iy;
     t->W[c] += q;
     /* accept as a real collision with probability sigma/sigma_max = tau_min/tau */
-    if (uacc < s->ratio[c] || j == ORC_MAX_SEGMENTS - 1) {
+    if (uacc < f->ratio[c] || j == ORC_MAX_SEGMENTS - 1) {
       t->D[c] += q;
       t->end = c;
       return;
@@ -822,12 +842,13 @@ static int orc_iterate(orc_state *s, int faces)
     }
   }
   uint64_t flights = 0, segs = 0;
+  const orc_flyctx fc = orc_gray_ctx(s);
   for (int e = 0; e < s->ne; ++e)
     for (uint64_t k = 0; k < s->N; ++k) {
       int64_t q = orc_split_weight(s->G[e], s->N, k);
       if (q == 0) continue;
       flights++;
-      orc_fly(s, slot, e, (uint32_t)k, q, &t, &segs);
+      orc_fly(&fc, slot, e, (uint32_t)k, q, &t, &segs);
     }
   s->flights = flights;
   s->segments = segs;
@@ -1043,9 +1064,10 @@ int orc_adjoint(orc_state *s, const double *dLdT, double *grad_wall, double *gra
   memset(&t, 0, sizeof t);
   t.D = sD; t.W = sW; t.B = sB; t.faces = 0;
   uint64_t segs = 0;
+  const orc_flyctx fc = orc_gray_ctx(s);
   for (int e = 0; e < ne; ++e)
     for (uint64_t k = 0; k < N; ++k) {
-      orc_fly(s, slot, e, (uint32_t)k, 1, &t, &segs);
+      orc_fly(&fc, slot, e, (uint32_t)k, 1, &t, &segs);
       end[(uint64_t)e * N + k] = (t.end >= 0) ? t.end : -1;
     }
   double *u = (double *)malloc(sizeof(double) * nc);
@@ -1110,4 +1132,340 @@ int orc_adjoint(orc_state *s, const double *dLdT, double *grad_wall, double *gra
   free(end); free(sD); free(sW); free(sB);
   free(u); free(psi); free(half); free(nw); free(tmp); free(r); free(x); free(vals); free(g);
   return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Frequency bands (beyond the paper's gray model)                           */
+/* ------------------------------------------------------------------------ */
+struct orc_bands {
+  orc_problem p;
+  orc_options o;
+  int K, nc, nb, ne, nfx, nfy;
+  uint64_t N;
+  int F;
+  double V, Ctot;
+  double *tau, *wall_T, *source, *bC, *bv;   /* copies; tau [K][nc] */
+  double *ts, *lam;                          /* [K] tau*_k, v_k tau*_k */
+  double *ratio;                             /* [K][nc] tau*_k / tau_k(c) */
+  double *den;                               /* [nc] sum_k C_k / tau_k(c) */
+  double *E;                                 /* energy density */
+  int64_t *G, *D, *W, *Phix, *Phiy, *B;      /* [K][ne], [K][nc] x2, [K][nfx], [K][nfy], [K][nb] */
+  uint32_t iter;
+  double d0, res;
+  uint64_t flights, segments, crossings, tot_flights, tot_segments, tot_crossings;
+};
+
+void orc_bands_destroy(orc_bands *s)
+{
+  if (!s) return;
+  free(s->tau); free(s->wall_T); free(s->source); free(s->bC); free(s->bv);
+  free(s->ts); free(s->lam); free(s->ratio); free(s->den); free(s->E);
+  free(s->G); free(s->D); free(s->W); free(s->Phix); free(s->Phiy); free(s->B);
+  free(s);
+}
+
+/* next emission of cell c for every band from the absorbed rate R */
+static void orc_bands_emit(orc_bands *s, int c, double R, int *ok)
+{
+  for (int k = 0; k < s->K; ++k) {
+    const double pk = (s->bC[k] / s->tau[(size_t)k * s->nc + c]) / s->den[c];
+    s->G[(size_t)k * s->ne + c] = orc_to_fixed((s->ts[k] * pk) * R, s->F, ok);
+  }
+}
+
+int orc_bands_create(const orc_problem *p, const orc_options *o, orc_bands **out)
+{
+  *out = NULL;
+  if (!p || p->n_bands < 2 || !p->band_C || !p->band_vg || !p->tau || !p->wall_T)
+    return ORC_E_INVALID_ARG;
+  if (p->dim != 1 && p->dim != 2) return ORC_E_INVALID_ARG;
+  if (p->nx < 1 || p->ny < 1 || (p->dim == 1 && p->ny != 1)) return ORC_E_INVALID_ARG;
+  if (!(p->dx > 0.0) || !(p->dy > 0.0) || !isfinite(p->dx) || !isfinite(p->dy) ||
+      !isfinite(p->t_ref))
+    return ORC_E_INVALID_ARG;
+  if (!o || o->particles_per_iter < 1 || o->max_iters < 0 || o->avg_iters != 0 || o->newton)
+    return ORC_E_INVALID_ARG;
+  const int K = p->n_bands, nc = p->nx * p->ny, nb = orc_nb(p);
+  for (int k = 0; k < K; ++k)
+    if (!(p->band_C[k] > 0.0) || !isfinite(p->band_C[k]) || !(p->band_vg[k] > 0.0) ||
+        !isfinite(p->band_vg[k]))
+      return ORC_E_INVALID_ARG;
+  for (int k = 0; k < K; ++k) {
+    double tmin = INFINITY, tmax = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      const double t = p->tau[(size_t)k * nc + c];
+      if (!(t > 0.0) || !isfinite(t)) return ORC_E_INVALID_ARG;
+      if (t < tmin) tmin = t;
+      if (t > tmax) tmax = t;
+    }
+    if (tmax > 1e6 * tmin) return ORC_E_INVALID_ARG;
+  }
+  for (int b = 0; b < nb; ++b)
+    if (!isfinite(p->wall_T[b])) return ORC_E_INVALID_ARG;
+  if (p->T_init)
+    for (int c = 0; c < nc; ++c)
+      if (!isfinite(p->T_init[c])) return ORC_E_INVALID_ARG;
+  if (p->source)
+    for (int c = 0; c < nc; ++c)
+      if (!isfinite(p->source[c])) return ORC_E_INVALID_ARG;
+
+  orc_bands *s = (orc_bands *)calloc(1, sizeof(orc_bands));
+  s->p = *p;
+  s->o = *o;
+  s->K = K;
+  s->nc = nc;
+  s->nb = nb;
+  s->ne = nc + nb;
+  s->nfx = p->ny * (p->nx + 1);
+  s->nfy = (p->dim == 2) ? (p->ny + 1) * p->nx : 0;
+  s->tau = orc_dup(p->tau, K * nc);
+  s->wall_T = orc_dup(p->wall_T, nb);
+  s->source = orc_dup(p->source, nc);
+  s->bC = orc_dup(p->band_C, K);
+  s->bv = orc_dup(p->band_vg, K);
+  s->p.tau = s->tau;
+  s->p.wall_T = s->wall_T;
+  s->p.source = s->source;
+  s->p.band_C = s->bC;
+  s->p.band_vg = s->bv;
+  s->p.T_init = NULL;
+  s->p.diff_x = s->p.diff_y = NULL;
+  s->N = o->particles_per_iter / ((uint64_t)s->ne * (uint64_t)K);
+  if (s->N < 1) s->N = 1;
+  s->V = p->dx * p->dy;
+  s->ts = (double *)malloc(sizeof(double) * K);
+  s->lam = (double *)malloc(sizeof(double) * K);
+  s->ratio = (double *)malloc(sizeof(double) * (size_t)K * nc);
+  s->den = (double *)calloc((size_t)nc, sizeof(double));
+  s->Ctot = 0.0;
+  for (int k = 0; k < K; ++k) {
+    double tmin = p->tau[(size_t)k * nc];
+    for (int c = 1; c < nc; ++c)
+      if (p->tau[(size_t)k * nc + c] < tmin) tmin = p->tau[(size_t)k * nc + c];
+    s->ts[k] = tmin;
+    s->lam[k] = p->band_vg[k] * tmin;
+    for (int c = 0; c < nc; ++c) s->ratio[(size_t)k * nc + c] = tmin / p->tau[(size_t)k * nc + c];
+    s->Ctot = s->Ctot + p->band_C[k];
+  }
+  for (int c = 0; c < nc; ++c)
+    for (int k = 0; k < K; ++k) s->den[c] = s->den[c] + p->band_C[k] / p->tau[(size_t)k * nc + c];
+  /* fixed-point scale: as the gray budget with the band sums (emission of the
+     cells <= C dT V per iteration, walls <= dT sum_k C_k lambda*_k A / 4), plus
+     the source raised by at most 1 + 3 (L / min lambda*)^2 iterations */
+  double dT = 0.0;
+  for (int b = 0; b < nb; ++b)
+    if (fabs(p->wall_T[b] - p->t_ref) > dT) dT = fabs(p->wall_T[b] - p->t_ref);
+  if (p->T_init)
+    for (int c = 0; c < nc; ++c)
+      if (fabs(p->T_init[c] - p->t_ref) > dT) dT = fabs(p->T_init[c] - p->t_ref);
+  double lam_sum = 0.0, lam_lo = s->lam[0], ts_hi = s->ts[0];
+  for (int k = 0; k < K; ++k) {
+    lam_sum = lam_sum + p->band_C[k] * s->lam[k];
+    if (s->lam[k] < lam_lo) lam_lo = s->lam[k];
+    if (s->ts[k] > ts_hi) ts_hi = s->ts[k];
+  }
+  const double vol = (double)nc * s->V;
+  const double area = (p->dim == 2) ? ((2.0 * (double)p->ny) * p->dy + (2.0 * (double)p->nx) * p->dx)
+                                    : 2.0;
+  double esrc = 0.0;
+  if (p->source) {
+    double smax = 0.0;
+    for (int c = 0; c < nc; ++c)
+      if (fabs(p->source[c]) > smax) smax = fabs(p->source[c]);
+    double L = (double)p->nx * p->dx;
+    if (p->dim == 2 && (double)p->ny * p->dy > L) L = (double)p->ny * p->dy;
+    const double rl = L / lam_lo;
+    esrc = (smax * ts_hi) * (1.0 + 3.0 * (rl * rl));
+  }
+  const double Bb = 4.0 * ((dT * s->Ctot + esrc) * vol + (dT * lam_sum * area) / 4.0);
+  if (Bb > 0.0) {
+    int ex;
+    double m = frexp(Bb, &ex);
+    s->F = 62 - ((m == 0.5) ? ex - 1 : ex);
+  } else {
+    s->F = 62;
+  }
+  s->E = (double *)calloc((size_t)nc, sizeof(double));
+  s->G = (int64_t *)calloc((size_t)K * s->ne, sizeof(int64_t));
+  s->D = (int64_t *)calloc((size_t)K * nc, sizeof(int64_t));
+  s->W = (int64_t *)calloc((size_t)K * nc, sizeof(int64_t));
+  s->Phix = (int64_t *)calloc((size_t)K * s->nfx, sizeof(int64_t));
+  s->Phiy = (int64_t *)calloc((size_t)K * (s->nfy ? s->nfy : 1), sizeof(int64_t));
+  s->B = (int64_t *)calloc((size_t)K * nb, sizeof(int64_t));
+  int ok = 1;
+  /* start in equilibrium at T_init: absorbed rate (T0 - t_ref) V sum_k C_k / tau_k, plus S V */
+  for (int c = 0; c < nc; ++c) {
+    const double T0 = p->T_init ? p->T_init[c] : p->t_ref;
+    s->E[c] = s->Ctot * (T0 - p->t_ref);
+    double R = ((T0 - p->t_ref) * s->V) * s->den[c];
+    if (s->source) R = R + s->source[c] * s->V;
+    orc_bands_emit(s, c, R, &ok);
+  }
+  for (int k = 0; k < K; ++k)
+    for (int b = 0; b < nb; ++b) {
+      const double A = (b < 2 * p->ny) ? p->dy : p->dx;
+      s->G[(size_t)k * s->ne + nc + b] =
+          orc_to_fixed(((p->band_C[k] * (s->wall_T[b] - p->t_ref)) * (s->lam[k] * A)) / 4.0, s->F, &ok);
+    }
+  if (!ok || !orc_check_budget(s->G, K * s->ne)) {
+    orc_bands_destroy(s);
+    return ORC_E_FIXED_OVERFLOW;
+  }
+  *out = s;
+  return ORC_OK;
+}
+
+static int orc_bands_iterate(orc_bands *s, int faces)
+{
+  const orc_problem *p = &s->p;
+  const int K = s->K, nc = s->nc, ne = s->ne, nb = s->nb;
+  uint32_t slot = (s->o.rng_mode == ORC_RNG_CRN) ? s->o.rng_epoch : s->iter;
+  memset(s->D, 0, sizeof(int64_t) * (size_t)K * nc);
+  memset(s->W, 0, sizeof(int64_t) * (size_t)K * nc);
+  memset(s->Phix, 0, sizeof(int64_t) * (size_t)K * s->nfx);
+  if (s->nfy) memset(s->Phiy, 0, sizeof(int64_t) * (size_t)K * s->nfy);
+  memset(s->B, 0, sizeof(int64_t) * (size_t)K * nb);
+  uint64_t flights = 0, segs = 0, cross = 0;
+  for (int k = 0; k < K; ++k) {
+    orc_tally t;
+    memset(&t, 0, sizeof t);
+    t.D = s->D + (size_t)k * nc;
+    t.W = s->W + (size_t)k * nc;
+    t.Phix = s->Phix + (size_t)k * s->nfx;
+    t.Phiy = s->Phiy + (size_t)k * (s->nfy ? s->nfy : 0);
+    t.B = s->B + (size_t)k * nb;
+    t.faces = faces;
+    const int64_t *G = s->G + (size_t)k * ne;
+    if (faces) {
+      int nx = p->nx, ny = p->ny;
+      for (int b = 0; b < nb; ++b) {
+        int64_t g = G[nc + b];
+        if (b < ny) t.Phix[b * (nx + 1)] += g;
+        else if (b < 2 * ny) t.Phix[(b - ny) * (nx + 1) + nx] -= g;
+        else if (b < 2 * ny + nx) t.Phiy[b - 2 * ny] += g;
+        else t.Phiy[ny * nx + (b - 2 * ny - nx)] -= g;
+      }
+    }
+    orc_flyctx fc = {p, nc, s->o.seed, s->lam[k], s->ratio + (size_t)k * nc, (uint32_t)(k * ne)};
+    for (int e = 0; e < ne; ++e)
+      for (uint64_t i = 0; i < s->N; ++i) {
+        int64_t q = orc_split_weight(G[e], s->N, i);
+        if (q == 0) continue;
+        flights++;
+        orc_fly(&fc, slot, e, (uint32_t)i, q, &t, &segs);
+      }
+    cross += t.crossings;
+  }
+  s->flights = flights;
+  s->segments = segs;
+  s->crossings = cross;
+  s->tot_flights += flights;
+  s->tot_segments += segs;
+  s->tot_crossings += cross;
+  /* energy density from the candidate tallies, re-emission of the absorbed rate */
+  double *tmp = (double *)malloc(sizeof(double) * nc);
+  int ok = 1, rc = ORC_OK;
+  for (int c = 0; c < nc; ++c) {
+    double R = 0.0, Wsum = 0.0;
+    for (int k = 0; k < K; ++k) {
+      R = R + ldexp((double)s->D[(size_t)k * nc + c], -s->F) / s->ts[k];
+      Wsum = Wsum + ldexp((double)s->W[(size_t)k * nc + c], -s->F);
+    }
+    if (s->source) R = R + s->source[c] * s->V;
+    const double En = Wsum / s->V;
+    const double d = En - s->E[c];
+    tmp[c] = d * d;
+    if (!isfinite(En)) rc = ORC_E_NONFINITE;
+    s->E[c] = En;
+    orc_bands_emit(s, c, R, &ok);
+  }
+  double dn = sqrt(orc_tree_sum(tmp, (uint64_t)nc));
+  free(tmp);
+  if (s->iter == 0) s->d0 = dn;
+  s->res = (s->d0 > 0.0) ? dn / s->d0 : 0.0;
+  s->iter++;
+  if (rc == ORC_OK && (!ok || !orc_check_budget(s->G, K * ne))) rc = ORC_E_FIXED_OVERFLOW;
+  if (rc == ORC_OK && s->iter > 1 && s->res > 1e3) rc = ORC_E_DIVERGED;
+  return rc;
+}
+
+int orc_bands_step(orc_bands *s, int n_iters, int faces)
+{
+  for (int i = 0; i < n_iters; ++i) {
+    int rc = orc_bands_iterate(s, faces);
+    if (rc) return rc;
+  }
+  return ORC_OK;
+}
+
+int orc_bands_solve(orc_bands *s, double *T_out, double *qx_out, double *qy_out)
+{
+  const orc_problem *p = &s->p;
+  int faces_each = (s->o.tally_faces == ORC_FACES_EVERY);
+  int converged = 0, rc;
+  while ((int)s->iter < s->o.max_iters) {
+    rc = orc_bands_iterate(s, faces_each);
+    if (rc) return rc;
+    if (s->res < s->o.res_tol) {
+      converged = 1;
+      break;
+    }
+  }
+  if (s->o.tally_faces == ORC_FACES_FINAL) {
+    rc = orc_bands_iterate(s, 1);
+    if (rc) return rc;
+  }
+  int faces_out = (s->o.tally_faces != ORC_FACES_OFF);
+  if (T_out)
+    for (int c = 0; c < s->nc; ++c) T_out[c] = p->t_ref + s->E[c] / s->Ctot;
+  if (qx_out)
+    for (int f = 0; f < s->nfx; ++f) {
+      double v = 0.0;
+      for (int k = 0; k < s->K; ++k)
+        v = v + ldexp((double)s->Phix[(size_t)k * s->nfx + f], -s->F) / s->ts[k];
+      qx_out[f] = faces_out ? v / p->dy : 0.0;
+    }
+  if (qy_out && s->nfy)
+    for (int f = 0; f < s->nfy; ++f) {
+      double v = 0.0;
+      for (int k = 0; k < s->K; ++k)
+        v = v + ldexp((double)s->Phiy[(size_t)k * s->nfy + f], -s->F) / s->ts[k];
+      qy_out[f] = faces_out ? v / p->dx : 0.0;
+    }
+  return converged ? ORC_OK : ORC_W_NOT_CONVERGED;
+}
+
+void orc_bands_get_info(const orc_bands *s, orc_info *info)
+{
+  memset(info, 0, sizeof *info);
+  info->iter = s->iter;
+  info->F = s->F;
+  info->n_per_emitter = s->N;
+  info->n_cells = s->nc;
+  info->n_bfaces = s->nb;
+  info->n_emitters = s->ne * s->K;
+  info->tau_min = s->ts[0];
+  info->lam_min = s->lam[0];
+  info->d0 = s->d0;
+  info->res = s->res;
+  info->flights = s->flights;
+  info->segments = s->segments;
+  info->crossings = s->crossings;
+  info->tot_flights = s->tot_flights;
+  info->tot_segments = s->tot_segments;
+  info->tot_crossings = s->tot_crossings;
+}
+
+void orc_bands_get_E(const orc_bands *s, double *E) { memcpy(E, s->E, sizeof(double) * s->nc); }
+
+void orc_bands_get_band(const orc_bands *s, int k, int64_t *D, int64_t *W, int64_t *Phix,
+                        int64_t *Phiy, int64_t *B, int64_t *G)
+{
+  if (k < 0 || k >= s->K) return;
+  if (D) memcpy(D, s->D + (size_t)k * s->nc, sizeof(int64_t) * s->nc);
+  if (W) memcpy(W, s->W + (size_t)k * s->nc, sizeof(int64_t) * s->nc);
+  if (Phix) memcpy(Phix, s->Phix + (size_t)k * s->nfx, sizeof(int64_t) * s->nfx);
+  if (Phiy && s->nfy) memcpy(Phiy, s->Phiy + (size_t)k * s->nfy, sizeof(int64_t) * s->nfy);
+  if (B) memcpy(B, s->B + (size_t)k * s->nb, sizeof(int64_t) * s->nb);
+  if (G) memcpy(G, s->G + (size_t)k * s->ne, sizeof(int64_t) * s->ne);
 }

@@ -62,6 +62,9 @@ typedef struct orc_problem {
   const double *diff_x; /* [nx*ny] per-iteration diffusion coefficient along x (Newton), or NULL */
   const double *diff_y; /* [nx*ny] along y (2D Newton), or NULL */
   const double *source; /* [nx*ny] volumetric heat source S (energy per volume and time), or NULL */
+  int n_bands;          /* 0 or 1: gray (cv, vg, tau as above); >= 2: frequency bands (orc_bands_*) */
+  const double *band_C; /* [n_bands] heat capacity per band (the total replaces cv) */
+  const double *band_vg;/* [n_bands] group speed per band (replaces vg); tau is then [n_bands][nx*ny] */
 } orc_problem;
 
 typedef struct orc_options {
@@ -139,6 +142,28 @@ int orc_set_state(orc_state *s, uint32_t iter, double d0, const double *E, const
  * correction when the state was created with newton.  *iters_out = passes. */
 int orc_adjoint(orc_state *s, const double *dLdT, double *grad_wall, double *grad_source,
                 int max_iters, double tol, int *iters_out);
+
+/* ---- frequency bands (beyond the paper's gray model) ----
+ * K bands with heat capacity C_k, group speed v_k and relaxation time
+ * tau_k(c).  Band k uses its own common time scale tau*_k = min_c tau_k(c)
+ * (candidate path v_k tau*_k, acceptance tau*_k / tau_k(c)); emitters are
+ * (band, cell or wall face), counter index k (nc + nb) + emitter.  One
+ * iteration: every band flies its emitters; per cell the absorbed rate
+ * R = sum_k D_k 2^-F / tau*_k (+ S V) is re-emitted over the bands as the
+ * equilibrium spectrum, G_k = tau*_k (C_k / tau_k) / (sum_j C_j / tau_j) R
+ * (pseudo-temperature); the energy density is E = sum_k W_k 2^-F / V and
+ * T = t_ref + E / sum_k C_k; walls emit C_k (T_w - t_ref) v_k tau*_k A / 4;
+ * the heat flux is sum_k Phi_k 2^-F / tau*_k / A.  No Newton step. */
+typedef struct orc_bands orc_bands;
+int orc_bands_create(const orc_problem *p, const orc_options *o, orc_bands **out);
+void orc_bands_destroy(orc_bands *s);
+int orc_bands_step(orc_bands *s, int n_iters, int faces);
+int orc_bands_solve(orc_bands *s, double *T_out, double *qx_out, double *qy_out);
+void orc_bands_get_info(const orc_bands *s, orc_info *info);
+void orc_bands_get_E(const orc_bands *s, double *E);
+/* band k's tallies of the last iteration and its emitter energies for the next */
+void orc_bands_get_band(const orc_bands *s, int k, int64_t *D, int64_t *W, int64_t *Phix,
+                        int64_t *Phiy, int64_t *B, int64_t *G);
 
 #ifdef __cplusplus
 }

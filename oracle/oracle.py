@@ -47,7 +47,8 @@ class _Problem(C.Structure):
                 ("dy", C.c_double), ("t_ref", C.c_double), ("cv", C.c_double),
                 ("vg", C.c_double), ("tau", C.c_void_p), ("wall_T", C.c_void_p),
                 ("T_init", C.c_void_p), ("diff_x", C.c_void_p), ("diff_y", C.c_void_p),
-                ("source", C.c_void_p)]
+                ("source", C.c_void_p), ("n_bands", C.c_int), ("band_C", C.c_void_p),
+                ("band_vg", C.c_void_p)]
 
 
 class _Options(C.Structure):
@@ -107,6 +108,13 @@ def lib():
         L.orc_get_residuals.argtypes = [P, P, C.c_int]
         L.orc_set_state.argtypes = [P, C.c_uint32, C.c_double, P, P]
         L.orc_adjoint.argtypes = [P, P, P, P, C.c_int, C.c_double, P]
+        L.orc_bands_create.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), C.POINTER(P)]
+        L.orc_bands_destroy.argtypes = [P]
+        L.orc_bands_step.argtypes = [P, C.c_int, C.c_int]
+        L.orc_bands_solve.argtypes = [P, P, P, P]
+        L.orc_bands_get_info.argtypes = [P, C.POINTER(_Info)]
+        L.orc_bands_get_E.argtypes = [P, P]
+        L.orc_bands_get_band.argtypes = [P, C.c_int, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -176,9 +184,13 @@ class _Keep:
         self.dya = None if diff_y is None else np.ascontiguousarray(diff_y, dtype=np.float64)
         S = getattr(w, "source", None)
         self.src = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
+        K = int(getattr(w, "n_bands", 1) or 1)
+        self.bC = None if K < 2 else np.ascontiguousarray(w.band_C, dtype=np.float64)
+        self.bv = None if K < 2 else np.ascontiguousarray(w.band_vg, dtype=np.float64)
         self.p = _Problem(w.dim, w.nx, w.ny, w.dx, w.dy, w.t_ref, w.cv, w.vg,
                           self.tau.ctypes.data, self.wall.ctypes.data, _ptr(self.T_init),
-                          _ptr(self.dxa), _ptr(self.dya), _ptr(self.src))
+                          _ptr(self.dxa), _ptr(self.dya), _ptr(self.src), K if K > 1 else 0,
+                          _ptr(self.bC), _ptr(self.bv))
 
 
 def fixed_exponent(w) -> int:
@@ -331,4 +343,65 @@ class Oracle:
         qx = np.zeros(self.nfx)
         qy = np.zeros(max(self.nfy, 1))
         rc = lib().orc_solve(self.h, T.ctypes.data, qx.ctypes.data, qy.ctypes.data)
+        return rc, T, qx, qy[:self.nfy]
+
+
+class Bands:
+    """The multi-band oracle (problem with n_bands >= 2): create, step, read."""
+
+    def __init__(self, w, *, seed=None, particles=None, rng_mode=FRESH, epoch=0, max_iters=None,
+                 res_tol=None, tally_faces=FACES_EVERY):
+        self.w = w
+        self._keep = _Keep(w)
+        self.opts = _Options(w.seed if seed is None else seed,
+                             w.particles_per_iter if particles is None else particles,
+                             rng_mode, epoch, w.max_iters if max_iters is None else max_iters,
+                             w.res_tol if res_tol is None else res_tol, 0, 1e-10, 1, tally_faces, 0)
+        h = C.c_void_p()
+        rc = lib().orc_bands_create(C.byref(self._keep.p), C.byref(self.opts), C.byref(h))
+        if rc != OK:
+            raise OracleError(rc, "bands_create")
+        self.h = h
+        self.K = int(w.n_bands)
+        self.nc = w.nx * w.ny
+        self.nb = w.n_bfaces
+        self.ne = self.nc + self.nb
+        self.nfx = w.ny * (w.nx + 1)
+        self.nfy = (w.ny + 1) * w.nx if w.dim == 2 else 0
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().orc_bands_destroy(h)
+            self.h = None
+
+    def info(self) -> Info:
+        i = _Info()
+        lib().orc_bands_get_info(self.h, C.byref(i))
+        return Info(*[getattr(i, f[0]) for f in _Info._fields_])
+
+    def step(self, n=1, faces=True) -> int:
+        return lib().orc_bands_step(self.h, n, int(bool(faces)))
+
+    def E(self) -> np.ndarray:
+        E = np.zeros(self.nc)
+        lib().orc_bands_get_E(self.h, E.ctypes.data)
+        return E
+
+    def band(self, k):
+        D = np.zeros(self.nc, np.int64)
+        W = np.zeros(self.nc, np.int64)
+        Px = np.zeros(self.nfx, np.int64)
+        Py = np.zeros(max(self.nfy, 1), np.int64)
+        B = np.zeros(self.nb, np.int64)
+        G = np.zeros(self.ne, np.int64)
+        lib().orc_bands_get_band(self.h, int(k), D.ctypes.data, W.ctypes.data, Px.ctypes.data,
+                                 Py.ctypes.data, B.ctypes.data, G.ctypes.data)
+        return {"D": D, "W": W, "Phix": Px, "Phiy": Py[:self.nfy], "B": B, "G": G}
+
+    def solve(self):
+        T = np.zeros(self.nc)
+        qx = np.zeros(self.nfx)
+        qy = np.zeros(max(self.nfy, 1))
+        rc = lib().orc_bands_solve(self.h, T.ctypes.data, qx.ctypes.data, qy.ctypes.data)
         return rc, T, qx, qy[:self.nfy]

@@ -42,6 +42,11 @@ class Workload:
     wall_T: np.ndarray         # (n_bfaces,) float64: left rows, right rows, bottom cols, top cols
     T_init: Optional[np.ndarray] = None   # (ny*nx,) or None -> t_ref everywhere
     source: Optional[np.ndarray] = None   # (ny*nx,) volumetric heat source or None
+    # frequency bands (n_bands >= 2): tau is then (n_bands*ny*nx,) band-major, and
+    # band_C / band_vg replace cv / vg
+    n_bands: int = 1
+    band_C: Optional[np.ndarray] = None
+    band_vg: Optional[np.ndarray] = None
     # run options
     seed: int = 0
     particles_per_iter: int = 100_000
@@ -224,3 +229,59 @@ def adjoint_case(n: int = 256, kn: float = 0.1, n_probes: int = 64, particles: i
     probes = np.sort(rng.choice(n * n, size=n_probes, replace=False)).astype(np.int64)
     target = rng.uniform(0.99, 1.01, size=n_probes)
     return AdjointCase(w, probes, target, np.array([0.99, 0.99, 0.99, 1.01]))
+
+
+def slab_1d_bands(n: int = 20, C=(0.5, 0.3, 0.2), vg=(1.0, 0.7, 0.4), kn=(2.0, 0.3, 0.05),
+                  kn_left_factor: float = 1.0, t_hot: float = 1.01, t_cold: float = 0.99,
+                  particles: int = 200_000, seed: int = 0, name: str = "slab1d_bands") -> Workload:
+    """1D film with a few frequency bands: band k has heat capacity C[k], group
+    speed vg[k] and Kn[k] = vg tau / L; the left half's tau is kn_left_factor
+    times the right half's (null collisions when != 1)."""
+    K = len(C)
+    L, d = 1.0, 1.0 / n
+    x = (np.arange(n) + 0.5) * d
+    tau = np.zeros(K * n)
+    for k in range(K):
+        t = kn[k] * L / vg[k]
+        tau[k * n:(k + 1) * n] = np.where(x < 0.5, t * kn_left_factor, t)
+    return Workload(name=name, dim=1, nx=n, ny=1, dx=d, dy=1.0, t_ref=1.0,
+                    cv=float(sum(C)), vg=float(vg[0]), tau=tau,
+                    wall_T=_walls_1d(t_hot, t_cold), seed=seed, particles_per_iter=particles,
+                    n_bands=K, band_C=np.array(C, dtype=np.float64),
+                    band_vg=np.array(vg, dtype=np.float64))
+
+
+def sine_dispersion_bands(K: int = 40, omega_cut: float = 0.57819, kn_max: float = 10.0,
+                          length: float = 1.0, v0: float = 1.0):
+    """K midpoint bands over (0, omega_cut omega_max] of the dispersion with group
+    speed v(w) = v0 cos(pi w / 2 w_max): C_k proportional to k(w)^2 / v(w) with
+    k(w) the wavenumber (the integral of dw / v), normalised to sum 1;
+    tau_k proportional to w^-2, scaled so the lowest band has Kn = kn_max
+    (the cut makes the Kn span 1e4).  Returns (C, vg, tau_right)."""
+    w = (np.arange(K) + 0.5) / K * omega_cut          # in units of w_max
+    v = v0 * np.cos(0.5 * np.pi * w)
+    kw = (2.0 / (np.pi * v0)) * np.arctanh(np.sin(0.5 * np.pi * w))
+    C = kw ** 2 / v
+    C = C / C.sum()
+    tau = (w[0] / w) ** 2
+    tau = tau * (kn_max * length / (v[0] * tau[0]))
+    return C.astype(np.float64), v.astype(np.float64), tau.astype(np.float64)
+
+
+def nongray_two_material_2d(n: int = 512, K: int = 40, ratio: float = 100.0,
+                            particles: int = 50_000_000, amp: float = 0.01, width: float = 0.05,
+                            seed: int = 0, name: str = "nongray2d") -> Workload:
+    """2D non-gray two-material square: the left half's relaxation times are
+    `ratio` times the right half's for every band (null collisions), K bands of
+    the sine dispersion (Kn 1e-3 .. 10 in the right half), hot top wall 1.01,
+    others 0.99, Gaussian source of width `width` L at the centre."""
+    C, v, tau_r = sine_dispersion_bands(K)
+    d = 1.0 / n
+    ix = np.tile(np.arange(n), n)
+    left = ix < n // 2
+    tau = np.concatenate([np.where(left, t * ratio, t) for t in tau_r]).astype(np.float64)
+    w = Workload(name=name, dim=2, nx=n, ny=n, dx=d, dy=d, t_ref=1.0, cv=1.0, vg=float(v[0]),
+                 tau=tau, wall_T=_walls_2d(n, n, 0.99, 0.99, 0.99, 1.01), seed=seed,
+                 particles_per_iter=particles, n_bands=K, band_C=C, band_vg=v)
+    w.source = gaussian_source(n, n, d, d, amp, width)
+    return w

@@ -191,3 +191,38 @@ def dsa_spectral_radius(w, D=None) -> float:
     I = np.eye(n)
     T = M + np.linalg.solve(A, M - I)
     return float(np.max(np.abs(np.linalg.eigvals(T))))
+
+
+def bands_fixed_point_1d(w, source=None):
+    """Expected steady state of the multi-band iteration on a 1D film with the
+    exact E_3 kernels of every band: the absorbed rate R solves R = R M + b with
+    M[e, i] = sum_k p_k(e) K_k[e, i] (p_k the equilibrium spectrum C_k/tau_k,
+    normalised), b = sum_k (Gw_k Pw_k) / tau*_k + S V; then E = sum_k W_k / V
+    with E[W_k] = E[D_k] / (tau*_k / tau_k).  Returns (E, R)."""
+    K, n = int(w.n_bands), w.nx
+    tau = np.asarray(w.tau, dtype=np.float64).reshape(K, n)
+    C = np.asarray(w.band_C, dtype=np.float64)
+    v = np.asarray(w.band_vg, dtype=np.float64)
+    V = w.dx * w.dy
+    ts = tau.min(axis=1)
+    den = (C[:, None] / tau).sum(axis=0)
+    M = np.zeros((n, n))
+    b = np.zeros(n) if source is None else np.asarray(source) * V
+    Ew = np.asarray(w.wall_T) - w.t_ref
+    mats = []
+    for k in range(K):
+        Kk, Pw, _, _ = cp_1d(tau[k], w.dx, v[k])
+        mats.append((Kk, Pw))
+        pk = (C[k] / tau[k]) / den
+        M += pk[:, None] * Kk
+        Gw = C[k] * Ew * v[k] * ts[k] * 1.0 / 4.0
+        b += (Gw @ Pw) / ts[k]
+    R = np.linalg.solve((np.eye(n) - M).T, b)
+    E = np.zeros(n)
+    for k in range(K):
+        Kk, Pw = mats[k]
+        Gk = ts[k] * ((C[k] / tau[k]) / den) * R
+        Gw = C[k] * Ew * v[k] * ts[k] / 4.0
+        Dk = Gk @ Kk + Gw @ Pw
+        E += Dk / (ts[k] / tau[k])
+    return E / V, R
