@@ -90,6 +90,23 @@ typedef struct iugkp_problem {
                            NULL.  Each cell emits S V tau_min more per iteration, isotropically
                            from uniform positions like its equilibrium emission (an addition to
                            the gray model of Sec. 2-3) */
+  int n_bands;          /* 0 or 1: the gray model (Sec. 2).  K >= 2: K frequency bands (an
+                           extension of the gray model): tau is then [K][n_cells] (band-major),
+                           band k carries heat capacity band_C[k] and group velocity
+                           band_vg[k] (cv and vg are not used), its own candidate time
+                           tau*_k = min_c tau_k(c), free path band_vg[k] tau*_k and acceptance
+                           tau*_k / tau_k(c).  Every cell re-emits its absorbed rate
+                           R = sum_k D_k / tau*_k (+ S V) over the bands with the equilibrium
+                           spectrum, band k taking the share (C_k / tau_k) / sum_j (C_j / tau_j),
+                           emission G_k = tau*_k share_k R; the energy density is
+                           E = sum_k W_k / V and T = t_ref + E / sum_k C_k.  Walls emit
+                           C_k (T_w - t_ref) lambda*_k A / 4 in band k.  Every emitter of
+                           every band flies N = max(1, particles_per_iter / (K (n_cells + n_b)))
+                           particles, band k's with emitter index k (n_cells + n_b) + e in the
+                           Philox counter.  No Newton correction and no output averaging; not
+                           for batches or the adjoint */
+  const double *band_C; /* [n_bands] band heat capacities (> 0), n_bands >= 2 only */
+  const double *band_vg;/* [n_bands] band group velocities (> 0), n_bands >= 2 only */
 } iugkp_problem;
 
 typedef struct iugkp_options {
@@ -168,12 +185,14 @@ int iugkp_solve(iugkp_handle *h, double *T_out, double *qx_out, double *qy_out,
 /* Tallies of the last iteration (int64, exact): D = real-collision energy per
  * cell (W^h), W = all candidate-collision energy per cell, Phi_x / Phi_y = net
  * energy through each face along +x / +y, B = energy absorbed per wall face.
- * Any pointer may be NULL.  Arrays in the problem's mem_kind. */
+ * Any pointer may be NULL.  Arrays in the problem's mem_kind.  For a problem of K
+ * frequency bands every array holds K consecutive per-band blocks (band-major). */
 int iugkp_get_tallies(iugkp_handle *h, int64_t *D, int64_t *W, int64_t *Phi_x,
                       int64_t *Phi_y, int64_t *B);
 
 /* Resumable state: iteration count, first-iteration update norm, E^n [n_cells]
- * and the next emission energies G [n_cells + n_b] (int64).  set_state restores
+ * and the next emission energies G [n_cells + n_b] (int64; [K][n_cells + n_b]
+ * for K frequency bands).  set_state restores
  * it (resume is bitwise identical to an uninterrupted run).  Arrays in the
  * problem's mem_kind. */
 int iugkp_get_state(iugkp_handle *h, uint32_t *iter, double *d0, double *E, int64_t *G);

@@ -28,7 +28,8 @@ class Problem(C.Structure):
                 ("dy", C.c_double), ("t_ref", C.c_double), ("cv", C.c_double),
                 ("vg", C.c_double), ("tau", C.c_void_p), ("wall_T", C.c_void_p),
                 ("T_init", C.c_void_p), ("diff_x", C.c_void_p), ("diff_y", C.c_void_p),
-                ("mem_kind", C.c_int), ("source", C.c_void_p)]
+                ("mem_kind", C.c_int), ("source", C.c_void_p), ("n_bands", C.c_int),
+                ("band_C", C.c_void_p), ("band_vg", C.c_void_p)]
 
 
 class Options(C.Structure):

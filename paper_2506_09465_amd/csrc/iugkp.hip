@@ -118,9 +118,13 @@ int check_problem(const iugkp_problem *p)
   if ((long long)p->nx * p->ny > (1ll << 24)) return fail(IUGKP_E_INVALID_ARG, "mesh too large");
   if (!(p->dx > 0) || !(p->dy > 0) || !std::isfinite(p->dx) || !std::isfinite(p->dy))
     return fail(IUGKP_E_INVALID_ARG, "cell sizes must be positive and finite");
-  if (!(p->cv > 0) || !(p->vg > 0) || !std::isfinite(p->cv) || !std::isfinite(p->vg) ||
-      !std::isfinite(p->t_ref))
-    return fail(IUGKP_E_INVALID_ARG, "cv, vg must be positive, t_ref finite");
+  if (p->n_bands < 0) return fail(IUGKP_E_INVALID_ARG, "n_bands must be >= 0");
+  if (!std::isfinite(p->t_ref)) return fail(IUGKP_E_INVALID_ARG, "t_ref must be finite");
+  if (p->n_bands < 2 &&
+      (!(p->cv > 0) || !(p->vg > 0) || !std::isfinite(p->cv) || !std::isfinite(p->vg)))
+    return fail(IUGKP_E_INVALID_ARG, "cv, vg must be positive and finite");
+  if (p->n_bands >= 2 && (!p->band_C || !p->band_vg))
+    return fail(IUGKP_E_INVALID_ARG, "band_C and band_vg are required for frequency bands");
   if (!p->tau || !p->wall_T) return fail(IUGKP_E_INVALID_ARG, "tau and wall_T are required");
   if (p->mem_kind != IUGKP_MEM_HOST && p->mem_kind != IUGKP_MEM_DEVICE)
     return fail(IUGKP_E_INVALID_ARG, "bad mem_kind");
@@ -261,6 +265,8 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   if (rc) return rc;
   rc = check_options(o);
   if (rc) return rc;
+  if (p->n_bands > 1)
+    return fail(IUGKP_E_INVALID_ARG, "frequency-band problems are single solves (iugkp_create)");
   const int nc = p->nx * p->ny;
   const int nb = 2 * p->ny + (p->dim == 2 ? 2 * p->nx : 0);
   std::vector<double> tau, wall, T0, src;
@@ -544,6 +550,278 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   return IUGKP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Frequency bands.  Band k is an instance of its own (tallies, emission, free
+// path v_k tau*_k, acceptance tau*_k / tau_k(c), Philox emitter offset
+// k (n_cells + n_b)) that shares the mesh, N, the scale F and the iteration
+// scalars with band 0; band 0 also owns the energy density, the residual
+// partials and the band table of the coupling kernel.
+// ---------------------------------------------------------------------------
+struct BandsHost {
+  int K = 1;
+  double Ctot = 0.0;
+  iugkp::BandDev *d_bands = nullptr;
+  long long **d_phix = nullptr, **d_phiy = nullptr;
+  double *srcV = nullptr;        // S V per cell, or null
+};
+
+double to_fixed_host(double v, int F, int *ok)
+{
+  const double x = std::ldexp(v, F);
+  if (!(std::fabs(x) <= 4611686018427387904.0)) {
+    *ok = 0;
+    return 0.0;
+  }
+  return std::rint(x);
+}
+
+// band 0 into ih0, bands 1.. into rest
+int setup_bands(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, InstHost &ih0,
+                std::vector<InstHost> &rest, BandsHost &bh)
+{
+  int rc = check_problem(p);
+  if (rc) return rc;
+  rc = check_options(o);
+  if (rc) return rc;
+  if (o->newton || o->avg_iters != 0)
+    return fail(IUGKP_E_INVALID_ARG, "frequency bands: no Newton correction, no output averaging");
+  const int K = p->n_bands;
+  const int nc = p->nx * p->ny;
+  const int nb = 2 * p->ny + (p->dim == 2 ? 2 * p->nx : 0);
+  const int ne = nc + nb;
+  std::vector<double> tau, wall, T0, src, bC, bv;
+  if ((rc = fetch_host(p->tau, static_cast<size_t>(K) * nc, p->mem_kind, tau))) return rc;
+  if ((rc = fetch_host(p->band_C, K, p->mem_kind, bC))) return rc;
+  if ((rc = fetch_host(p->band_vg, K, p->mem_kind, bv))) return rc;
+  if (p->source && (rc = fetch_host(p->source, nc, p->mem_kind, src))) return rc;
+  if ((rc = fetch_host(p->wall_T, nb, p->mem_kind, wall))) return rc;
+  if (p->T_init && (rc = fetch_host(p->T_init, nc, p->mem_kind, T0))) return rc;
+  for (int k = 0; k < K; ++k)
+    if (!(bC[k] > 0.0) || !std::isfinite(bC[k]) || !(bv[k] > 0.0) || !std::isfinite(bv[k]))
+      return fail(IUGKP_E_INVALID_ARG, "band_C and band_vg must be > 0 and finite");
+  std::vector<double> ts(K), lam(K);
+  std::vector<int> has_null(K);
+  for (int k = 0; k < K; ++k) {
+    double tmin = INFINITY, tmax = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      const double t = tau[static_cast<size_t>(k) * nc + c];
+      if (!(t > 0.0) || !std::isfinite(t)) return fail(IUGKP_E_INVALID_ARG, "tau must be > 0 and finite");
+      tmin = std::min(tmin, t);
+      tmax = std::max(tmax, t);
+    }
+    if (tmax > 1e6 * tmin) return fail(IUGKP_E_INVALID_ARG, "tau_max / tau_min exceeds 1e6 in a band");
+    ts[k] = tmin;
+    lam[k] = bv[k] * tmin;
+    has_null[k] = (tmax != tmin);
+  }
+  for (double t : wall)
+    if (!std::isfinite(t)) return fail(IUGKP_E_INVALID_ARG, "wall_T must be finite");
+  for (double t : T0)
+    if (!std::isfinite(t)) return fail(IUGKP_E_INVALID_ARG, "T_init must be finite");
+  for (double v : src)
+    if (!std::isfinite(v)) return fail(IUGKP_E_INVALID_ARG, "source must be finite");
+  uint64_t N = o->particles_per_iter / (static_cast<uint64_t>(ne) * static_cast<uint64_t>(K));
+  if (N < 1) N = 1;
+  if (N * static_cast<uint64_t>(ne) > 0xFFFFFFFFull ||
+      static_cast<uint64_t>(K) * static_cast<uint64_t>(ne) > 0xFFFFFFFFull)
+    return fail(IUGKP_E_INVALID_ARG, "particles per band iteration and emitters must stay below 2^32");
+  const double V = p->dx * p->dy;
+  double Ctot = 0.0;
+  for (int k = 0; k < K; ++k) Ctot = Ctot + bC[k];
+  std::vector<double> den(nc, 0.0);
+  for (int c = 0; c < nc; ++c)
+    for (int k = 0; k < K; ++k) den[c] = den[c] + bC[k] / tau[static_cast<size_t>(k) * nc + c];
+  // fixed-point scale: the gray budget with band sums (cells emit at most
+  // C dT V per iteration, walls dT sum_k C_k lambda*_k A / 4), the source
+  // raised by at most 1 + 3 (L / min lambda*)^2 iterations
+  double dT = 0.0;
+  for (double t : wall) dT = std::max(dT, std::fabs(t - p->t_ref));
+  for (double t : T0) dT = std::max(dT, std::fabs(t - p->t_ref));
+  double lam_sum = 0.0, lam_lo = lam[0], ts_hi = ts[0];
+  for (int k = 0; k < K; ++k) {
+    lam_sum = lam_sum + bC[k] * lam[k];
+    lam_lo = std::min(lam_lo, lam[k]);
+    ts_hi = std::max(ts_hi, ts[k]);
+  }
+  const double vol = static_cast<double>(nc) * V;
+  const double area = (p->dim == 2) ? ((2.0 * static_cast<double>(p->ny)) * p->dy +
+                                       (2.0 * static_cast<double>(p->nx)) * p->dx)
+                                    : 2.0;
+  double esrc = 0.0;
+  if (!src.empty()) {
+    double smax = 0.0;
+    for (double v : src) smax = std::max(smax, std::fabs(v));
+    double L = static_cast<double>(p->nx) * p->dx;
+    if (p->dim == 2 && static_cast<double>(p->ny) * p->dy > L) L = static_cast<double>(p->ny) * p->dy;
+    const double rl = L / lam_lo;
+    esrc = (smax * ts_hi) * (1.0 + 3.0 * (rl * rl));
+  }
+  const double Bb = 4.0 * ((dT * Ctot + esrc) * vol + (dT * lam_sum * area) / 4.0);
+  int F = 62;
+  if (Bb > 0.0) {
+    int ex = 0;
+    const double mant = std::frexp(Bb, &ex);
+    F = 62 - ((mant == 0.5) ? ex - 1 : ex);
+  }
+  // initial state: equilibrium at T_init, absorbed rate (T0 - t_ref) V den (+ S V)
+  std::vector<double> E0(nc), R0(nc);
+  for (int c = 0; c < nc; ++c) {
+    const double t0 = T0.empty() ? p->t_ref : T0[c];
+    E0[c] = Ctot * (t0 - p->t_ref);
+    double R = ((t0 - p->t_ref) * V) * den[c];
+    if (!src.empty()) R = R + src[c] * V;
+    R0[c] = R;
+  }
+
+  rest.assign(K - 1, InstHost{});
+  auto band = [&](int k) -> InstHost & { return k == 0 ? ih0 : rest[k - 1]; };
+  int ok = 1;
+  unsigned long long acc = 0, wall_acc = 0;
+  bool over = false;
+  std::vector<iugkp::BandDev> table(K);
+  std::vector<long long *> phx(K), phy(K);
+  std::vector<double> ratio(nc), share(nc);
+  std::vector<long long> g(ne);
+#define ALLOC(ih, ptr, n) \
+  if ((ih).alloc(&(ptr), (n)) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
+  for (int k = 0; k < K; ++k) {
+    InstHost &ih = band(k);
+    ih.opt = *o;
+    ih.mem_kind = p->mem_kind;
+    Inst &d = ih.d;
+    Mesh &m = d.m;
+    m.dim = p->dim;
+    m.nx = p->nx;
+    m.ny = p->ny;
+    m.n_cells = nc;
+    m.n_b = nb;
+    m.n_emit = ne;
+    m.n_fx = p->ny * (p->nx + 1);
+    m.n_fy = (p->dim == 2) ? (p->ny + 1) * p->nx : 0;
+    m.dx = p->dx;
+    m.dy = p->dy;
+    d.t_ref = p->t_ref;
+    d.cv = Ctot;
+    d.tau_min = ts[k];
+    d.lam_min = lam[k];
+    d.V = V;
+    d.N = static_cast<uint32_t>(N);
+    d.key0 = static_cast<uint32_t>(o->seed);
+    d.key1 = static_cast<uint32_t>(o->seed >> 32);
+    d.crn = (o->rng_mode == IUGKP_RNG_CRN);
+    d.epoch = o->rng_epoch;
+    d.has_null = has_null[k];
+    d.newton = 0;
+    d.faces_each = (o->tally_faces == IUGKP_FACES_EVERY);
+    d.faces_out = (o->tally_faces != IUGKP_FACES_OFF);
+    d.final_iter = (o->tally_faces == IUGKP_FACES_FINAL);
+    d.avg_iters = 0;
+    d.max_iters = o->max_iters;
+    d.res_tol = o->res_tol;
+    d.F = F;
+    d.e_off = static_cast<uint32_t>(k) * static_cast<uint32_t>(ne);
+    d.n_bands = K;
+    d.Gs = nullptr;
+    plan_tiles(ih);
+    double *dratio = nullptr, *dshare = nullptr;
+    ALLOC(ih, dratio, nc);
+    ALLOC(ih, dshare, nc);
+    d.ratio = dratio;
+    ALLOC(ih, d.G, ne);
+    ALLOC(ih, d.base, ne);
+    ALLOC(ih, d.rem, ne);
+    ALLOC(ih, d.D, nc);
+    ALLOC(ih, d.W, nc);
+    ALLOC(ih, d.Phix, m.n_fx);
+    ALLOC(ih, d.Phiy, m.n_fy);
+    ALLOC(ih, d.dB, (p->ny + 2) * p->nx);
+    ALLOC(ih, d.B, nb);
+    if (k == 0) {
+      const int nbe = cdiv(ne, iugkp::kTree);
+      ALLOC(ih, d.E, nc);
+      ALLOC(ih, d.part, nbe);
+      ALLOC(ih, d.gpart, nbe);
+      ALLOC(ih, d.sc, 1);
+      ALLOC(ih, ih.out_T, nc);
+      ALLOC(ih, ih.out_qx, m.n_fx);
+      ALLOC(ih, ih.out_qy, m.n_fy);
+      ALLOC(ih, bh.d_bands, K);
+      ALLOC(ih, bh.d_phix, K);
+      ALLOC(ih, bh.d_phiy, K);
+      if (!src.empty()) ALLOC(ih, bh.srcV, nc);
+    } else {
+      d.E = ih0.d.E;
+      d.part = ih0.d.part;
+      d.gpart = ih0.d.gpart;
+      d.sc = ih0.d.sc;
+    }
+    const double *tk = tau.data() + static_cast<size_t>(k) * nc;
+    for (int c = 0; c < nc; ++c) {
+      ratio[c] = ts[k] / tk[c];
+      share[c] = ts[k] * ((bC[k] / tk[c]) / den[c]);
+      g[c] = static_cast<long long>(to_fixed_host(share[c] * R0[c], F, &ok));
+    }
+    for (int b = 0; b < nb; ++b) {
+      const double A = (b < 2 * p->ny) ? p->dy : p->dx;
+      g[nc + b] = static_cast<long long>(
+          to_fixed_host(((bC[k] * (wall[b] - p->t_ref)) * (lam[k] * A)) / 4.0, F, &ok));
+      const unsigned long long a = static_cast<unsigned long long>(g[nc + b] < 0 ? -g[nc + b] : g[nc + b]);
+      wall_acc = std::min(wall_acc + a, iugkp::kBudgetCap);
+    }
+    for (long long v : g) {
+      const unsigned long long a = static_cast<unsigned long long>(v < 0 ? -v : v);
+      acc += a;
+      if (a > (1ull << 62) || acc > (1ull << 62)) over = true;
+      if (over) acc = 1ull << 62;
+    }
+    HIP_TRY(hipMemcpyAsync(dratio, ratio.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dshare, share.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d.G, g.data(), ne * sizeof(long long), hipMemcpyHostToDevice, s));
+    // tallies read as zero until the first iteration
+    HIP_TRY(hipMemsetAsync(d.D, 0, nc * sizeof(long long), s));
+    HIP_TRY(hipMemsetAsync(d.W, 0, nc * sizeof(long long), s));
+    HIP_TRY(hipMemsetAsync(d.Phix, 0, m.n_fx * sizeof(long long), s));
+    if (m.n_fy) HIP_TRY(hipMemsetAsync(d.Phiy, 0, m.n_fy * sizeof(long long), s));
+    HIP_TRY(hipMemsetAsync(d.B, 0, nb * sizeof(long long), s));
+    HIP_TRY(hipStreamSynchronize(s));   // the staging vectors are reused by the next band
+    table[k] = iugkp::BandDev{ts[k], dshare, d.D, d.W, d.G, d.has_null};
+    phx[k] = d.Phix;
+    phy[k] = d.Phiy;
+  }
+#undef ALLOC
+  if (!ok || over)
+    return fail(IUGKP_E_FIXED_OVERFLOW, "initial emission exceeds the fixed-point budget");
+  ih0.d.wall_budget = wall_acc;
+  bh.K = K;
+  bh.Ctot = Ctot;
+  HIP_TRY(hipMemcpyAsync(ih0.d.E, E0.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(bh.d_bands, table.data(), K * sizeof(iugkp::BandDev), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(bh.d_phix, phx.data(), K * sizeof(long long *), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(bh.d_phiy, phy.data(), K * sizeof(long long *), hipMemcpyHostToDevice, s));
+  std::vector<double> sv;
+  if (!src.empty()) {
+    sv.resize(nc);
+    for (int c = 0; c < nc; ++c) sv[c] = src[c] * V;
+    HIP_TRY(hipMemcpyAsync(bh.srcV, sv.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  DevScalars sc0{};
+  if (o->max_iters <= 0) {
+    if (ih0.d.final_iter) {
+      sc0.state = 1;
+      sc0.out_left = 1;
+      sc0.faces_now = 1;
+    } else {
+      sc0.state = 2;
+    }
+  } else {
+    sc0.faces_now = ih0.d.faces_each;
+  }
+  HIP_TRY(hipMemcpyAsync(ih0.d.sc, &sc0, sizeof(DevScalars), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 1; k < K; ++k) rest[k - 1].d.wall_budget = wall_acc;
+  return IUGKP_OK;
+}
+
 int launch_march(const Inst *d_insts, const TileDesc *d_tiles, int n_tiles, size_t lds, int block,
                  int faces_mode, int batch, hipStream_t s)
 {
@@ -639,10 +917,13 @@ int upload_inst(const InstHost &ih, int inst_index, Inst *d_inst, TileDesc *d_ti
 // ---------------------------------------------------------------------------
 struct iugkp_handle {
   hipStream_t stream = nullptr;
-  InstHost ih;
-  Inst *d_inst = nullptr;
+  InstHost ih;                    // the problem (gray), or band 0 (frequency bands)
+  std::vector<InstHost> xb;       // bands 1 .. K-1
+  BandsHost bh;
+  Inst *d_inst = nullptr;         // [K]
   TileDesc *d_tiles = nullptr;
   int n_tiles = 0;
+  size_t lds = 0;                 // march window (largest over the bands)
   int block = 256;
   DevScalars *hsc = nullptr;   // pinned host mirror
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -658,6 +939,7 @@ void free_handle(iugkp_handle *h)
 {
   if (!h) return;
   h->ih.release();
+  for (auto &b : h->xb) b.release();
   if (h->d_inst) (void)hipFree(h->d_inst);
   if (h->d_tiles) (void)hipFree(h->d_tiles);
   if (h->hsc) (void)hipHostFree(h->hsc);
@@ -729,7 +1011,8 @@ int iterate(iugkp_handle *h, int faces)
   hipStream_t s = h->stream;
   const int nprep = std::max(std::max(std::max(m.n_emit, m.n_fx), std::max(m.n_fy, m.n_cells)),
                              (m.ny + 2) * m.nx);
-  iugkp::prepare_kernel<<<dim3(cdiv(nprep, 256), 1), 256, 0, s>>>(h->d_inst, faces, 0);
+  const int K = h->bh.K;
+  iugkp::prepare_kernel<<<dim3(cdiv(nprep, 256), K), 256, 0, s>>>(h->d_inst, faces, 0);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(h->ev[0], s));
   int rc = IUGKP_OK;
@@ -739,16 +1022,19 @@ int iterate(iugkp_handle *h, int faces)
                                                                               ih.stripe_C);
     HIP_TRY(hipGetLastError());
   } else {
-    rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, ih.lds_bytes, h->block, faces, 0, s);
+    rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, h->lds, h->block, faces, 0, s);
     if (rc) return rc;
   }
   HIP_TRY(hipEventRecord(h->ev[1], s));
   if (faces) {
-    iugkp::reconstruct_y_kernel<<<dim3(cdiv(m.nx, 256), 1), 256, 0, s>>>(h->d_inst, faces, 0);
-    iugkp::reconstruct_x_kernel<<<dim3(cdiv(m.ny, 256), 1), 256, 0, s>>>(h->d_inst, faces, 0);
+    iugkp::reconstruct_y_kernel<<<dim3(cdiv(m.nx, 256), K), 256, 0, s>>>(h->d_inst, faces, 0);
+    iugkp::reconstruct_x_kernel<<<dim3(cdiv(m.ny, 256), K), 256, 0, s>>>(h->d_inst, faces, 0);
   }
   const int nbc = cdiv(m.n_cells, iugkp::kTree);
-  iugkp::update_kernel<<<dim3(nbc, 1), 256, 0, s>>>(h->d_inst, 0);
+  if (K > 1)
+    iugkp::bands_update_kernel<<<nbc, 256, 0, s>>>(h->d_inst, h->bh.d_bands, K, h->bh.srcV);
+  else
+    iugkp::update_kernel<<<dim3(nbc, 1), 256, 0, s>>>(h->d_inst, 0);
   HIP_TRY(hipGetLastError());
   if (ih.d.newton) {
     rc = enqueue_cg(ih, ih.d.rhs, ih.d.cg_x, ih.d.sc, s, h->ev[2], h->ev[3]);
@@ -789,11 +1075,40 @@ int iterate(iugkp_handle *h, int faces)
   if (ih.d.newton && sc.cg_status == -7)
     return fail(IUGKP_E_CG_NOT_CONVERGED, "CG did not converge within cg_max_iters");
   if (sc.flags & 1) return fail(IUGKP_E_NONFINITE, "non-finite energy");
-  if ((sc.flags & 2) || ((ih.d.newton || ih.d.Gs) && sc.gsum > (1ull << 62)))
+  if ((sc.flags & 2) || ((ih.d.newton || ih.d.Gs || K > 1) && sc.gsum > (1ull << 62)))
     return fail(IUGKP_E_FIXED_OVERFLOW, "emission energy exceeds the fixed-point budget");
   if (h->iter > 1 && h->res > 1e3) return fail(IUGKP_E_DIVERGED, "residual grew above 1e3");
   return IUGKP_OK;
 }
+
+// Outputs of a frequency-band problem: T = t_ref + E / sum_k C_k, q = sum over
+// the bands of the face tallies / tau*_k, per face area.
+int write_band_outputs(iugkp_handle *h, double *T_out, double *qx_out, double *qy_out)
+{
+  const InstHost &ih = h->ih;
+  const Inst &d = ih.d;
+  const Mesh &m = d.m;
+  hipStream_t s = h->stream;
+  const int nmax = std::max(std::max(m.n_cells, m.n_fx), m.n_fy);
+  const bool dev = (ih.mem_kind == IUGKP_MEM_DEVICE);
+  double *T = dev ? T_out : ih.out_T;
+  double *qx = qx_out ? (dev ? qx_out : ih.out_qx) : nullptr;
+  double *qy = (qy_out && m.n_fy) ? (dev ? qy_out : ih.out_qy) : nullptr;
+  iugkp::bands_output_kernel<<<cdiv(nmax, 256), 256, 0, s>>>(
+      m.n_cells, m.n_fx, m.n_fy, d.F, d.t_ref, h->bh.Ctot, m.dy, m.dx, d.faces_out, d.E,
+      h->bh.d_bands, h->bh.d_phix, h->bh.d_phiy, h->bh.K, T, qx, qy);
+  HIP_TRY(hipGetLastError());
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(T_out, ih.out_T, m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (qx_out)
+      HIP_TRY(hipMemcpyAsync(qx_out, ih.out_qx, m.n_fx * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (qy_out && m.n_fy)
+      HIP_TRY(hipMemcpyAsync(qy_out, ih.out_qy, m.n_fy * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  return IUGKP_OK;
+}
+
+const InstHost &band_of(const iugkp_handle *h, int k) { return k == 0 ? h->ih : h->xb[k - 1]; }
 
 }  // namespace
 
@@ -806,14 +1121,21 @@ int iugkp_create(const iugkp_problem *problem, const iugkp_options *options, voi
   *out = nullptr;
   iugkp_handle *h = new iugkp_handle();
   h->stream = static_cast<hipStream_t>(stream);
-  int rc = setup_instance(problem, options, h->stream, true, h->ih);
+  const bool bands = problem && problem->n_bands > 1;
+  int rc = bands ? setup_bands(problem, options, h->stream, h->ih, h->xb, h->bh)
+                 : setup_instance(problem, options, h->stream, true, h->ih);
   if (rc) {
     free_handle(h);
     return rc;
   }
+  const int K = h->bh.K;
   h->block = options->block_size ? options->block_size : 256;
-  h->n_tiles = static_cast<int>(h->ih.tiles.size());
-  if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), sizeof(Inst)) != hipSuccess ||
+  h->n_tiles = 0;
+  for (int k = 0; k < K; ++k) {
+    h->n_tiles += static_cast<int>(band_of(h, k).tiles.size());
+    h->lds = std::max(h->lds, band_of(h, k).lds_bytes);
+  }
+  if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), K * sizeof(Inst)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&h->d_tiles), h->n_tiles * sizeof(TileDesc)) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void **>(&h->hsc), sizeof(DevScalars)) != hipSuccess) {
     free_handle(h);
@@ -824,13 +1146,16 @@ int iugkp_create(const iugkp_problem *problem, const iugkp_options *options, voi
       free_handle(h);
       return fail(IUGKP_E_DEVICE, "hipEventCreate failed");
     }
-  if ((rc = upload_inst(h->ih, 0, h->d_inst, h->d_tiles, 0, h->stream))) {
-    free_handle(h);
-    return rc;
+  for (int k = 0, tile0 = 0; k < K; ++k) {
+    if ((rc = upload_inst(band_of(h, k), k, h->d_inst, h->d_tiles, tile0, h->stream))) {
+      free_handle(h);
+      return rc;
+    }
+    tile0 += static_cast<int>(band_of(h, k).tiles.size());
   }
   h->st.fixed_point_F = h->ih.d.F;
   h->st.n_per_emitter = h->ih.d.N;
-  h->st.n_emitters = h->ih.d.m.n_emit;
+  h->st.n_emitters = h->ih.d.m.n_emit * K;
   *out = h;
   return IUGKP_OK;
 }
@@ -873,6 +1198,14 @@ int iugkp_solve(iugkp_handle *h, double *T_out, double *qx_out, double *qy_out,
       break;
     }
   }
+  if (h->bh.K > 1) {
+    if (d.final_iter && (rc = iterate(h, 1))) return rc;
+    if ((rc = write_band_outputs(h, T_out, qx_out, qy_out))) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    h->st.status = converged ? IUGKP_OK : IUGKP_W_NOT_CONVERGED;
+    if (stats) *stats = h->st;
+    return h->st.status;
+  }
   const int nmax = std::max(std::max(m.n_cells, m.n_fx), m.n_fy);
   const dim3 grid(cdiv(nmax, 256), 1);
   double n_avg = 0.0;
@@ -898,16 +1231,21 @@ int iugkp_get_tallies(iugkp_handle *h, int64_t *D, int64_t *W, int64_t *Phi_x, i
                       int64_t *B)
 {
   if (!h) return fail(IUGKP_E_INVALID_ARG, "handle is NULL");
-  const Inst &d = h->ih.d;
-  const Mesh &m = d.m;
   const int k = h->ih.mem_kind;
   hipStream_t s = h->stream;
   int rc;
-  if ((rc = copy_out(D, d.D, m.n_cells * 8, k, s))) return rc;
-  if ((rc = copy_out(W, d.has_null ? d.W : d.D, m.n_cells * 8, k, s))) return rc;
-  if ((rc = copy_out(Phi_x, d.Phix, m.n_fx * 8, k, s))) return rc;
-  if (m.n_fy && (rc = copy_out(Phi_y, d.Phiy, m.n_fy * 8, k, s))) return rc;
-  if ((rc = copy_out(B, d.B, m.n_b * 8, k, s))) return rc;
+  for (int b = 0; b < h->bh.K; ++b) {
+    const Inst &d = band_of(h, b).d;
+    const Mesh &m = d.m;
+    const size_t o = static_cast<size_t>(b);
+    if ((rc = copy_out(D ? D + o * m.n_cells : nullptr, d.D, m.n_cells * 8, k, s))) return rc;
+    if ((rc = copy_out(W ? W + o * m.n_cells : nullptr, d.has_null ? d.W : d.D, m.n_cells * 8, k, s)))
+      return rc;
+    if ((rc = copy_out(Phi_x ? Phi_x + o * m.n_fx : nullptr, d.Phix, m.n_fx * 8, k, s))) return rc;
+    if (m.n_fy && (rc = copy_out(Phi_y ? Phi_y + o * m.n_fy : nullptr, d.Phiy, m.n_fy * 8, k, s)))
+      return rc;
+    if ((rc = copy_out(B ? B + o * m.n_b : nullptr, d.B, m.n_b * 8, k, s))) return rc;
+  }
   HIP_TRY(hipStreamSynchronize(s));
   return IUGKP_OK;
 }
@@ -920,7 +1258,10 @@ int iugkp_get_state(iugkp_handle *h, uint32_t *iter, double *d0, double *E, int6
   const Inst &d = h->ih.d;
   int rc;
   if ((rc = copy_out(E, d.E, d.m.n_cells * 8, h->ih.mem_kind, h->stream))) return rc;
-  if ((rc = copy_out(G, d.G, d.m.n_emit * 8, h->ih.mem_kind, h->stream))) return rc;
+  for (int b = 0; b < h->bh.K; ++b)
+    if ((rc = copy_out(G ? G + static_cast<size_t>(b) * d.m.n_emit : nullptr, band_of(h, b).d.G,
+                       d.m.n_emit * 8, h->ih.mem_kind, h->stream)))
+      return rc;
   HIP_TRY(hipStreamSynchronize(h->stream));
   return IUGKP_OK;
 }
@@ -930,11 +1271,12 @@ int iugkp_set_state(iugkp_handle *h, uint32_t iter, double d0, const double *E, 
   if (!h || !E || !G) return fail(IUGKP_E_INVALID_ARG, "bad arguments");
   const Inst &d = h->ih.d;
   const Mesh &m = d.m;
-  std::vector<long long> g(m.n_emit);
+  const size_t ng = static_cast<size_t>(m.n_emit) * h->bh.K;
+  std::vector<long long> g(ng);
   if (h->ih.mem_kind == IUGKP_MEM_HOST) {
-    std::memcpy(g.data(), G, m.n_emit * 8);
+    std::memcpy(g.data(), G, ng * 8);
   } else {
-    HIP_TRY(hipMemcpy(g.data(), G, m.n_emit * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(g.data(), G, ng * 8, hipMemcpyDeviceToHost));
   }
   unsigned long long acc = 0;
   for (long long v : g) {
@@ -945,7 +1287,9 @@ int iugkp_set_state(iugkp_handle *h, uint32_t iter, double d0, const double *E, 
   }
   int rc;
   if ((rc = copy_in(d.E, E, m.n_cells * 8, h->ih.mem_kind, h->stream))) return rc;
-  HIP_TRY(hipMemcpyAsync(d.G, g.data(), m.n_emit * 8, hipMemcpyHostToDevice, h->stream));
+  for (int b = 0; b < h->bh.K; ++b)
+    HIP_TRY(hipMemcpyAsync(band_of(h, b).d.G, g.data() + static_cast<size_t>(b) * m.n_emit,
+                           m.n_emit * 8, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(h->hsc, d.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->hsc->iter = iter;
@@ -979,6 +1323,7 @@ int iugkp_adjoint(iugkp_handle *h, const double *dLdT, double *grad_wall, double
   if (iters_out) *iters_out = 0;
   if (!h || !dLdT || max_iters < 1 || !(tol >= 0.0))
     return fail(IUGKP_E_INVALID_ARG, "bad adjoint arguments");
+  if (h->bh.K > 1) return fail(IUGKP_E_INVALID_ARG, "the adjoint covers gray problems only");
   InstHost &ih = h->ih;
   const Inst &d = ih.d;
   const Mesh &m = d.m;

@@ -71,6 +71,8 @@ struct Inst {
   unsigned int *cg_barrier;                             // [2] barrier of the instance's group
   double *acc_E, *acc_x, *acc_y;
   const long long *Gs;          // per-cell source emission per iteration, or null
+  uint32_t e_off;               // emitter offset in the Philox counter (frequency band k: k (nc + nb))
+  int n_bands;                  // > 1: the coordinating instance of a multi-band problem
   unsigned long long wall_budget;   // saturating sum of |G| over the wall emitters
   DevScalars *sc;
 };
@@ -349,6 +351,7 @@ struct FlyIn {
   uint32_t slot, key0, key1;
   int faces, has_null;
   const double *ratio;
+  uint32_t e_off;        // added to the emitter index in the Philox counter
 };
 
 // Start point and direction of particle k of emitter e: a uniform point of the
@@ -360,8 +363,8 @@ __device__ __forceinline__ void sample_particle(const FlyIn &a, uint32_t e, uint
                                                 double &sy)
 {
   const Mesh &m = a.m;
-  const double2 uab = draw2(0u, k, e, a.slot, a.key0, a.key1);
-  const double2 ucd = draw2(1u, k, e, a.slot, a.key0, a.key1);
+  const double2 uab = draw2(0u, k, e + a.e_off, a.slot, a.key0, a.key1);
+  const double2 ucd = draw2(1u, k, e + a.e_off, a.slot, a.key0, a.key1);
   if (e < static_cast<uint32_t>(m.n_cells)) {
     // isotropic emission from a uniformly sampled point of the cell
     iy = static_cast<int>(e) / m.nx;
@@ -414,7 +417,7 @@ __device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long
   // steep segments record their y-faces as runs per column
   const bool runs = a.faces && (fabs(sy) > 2.0 * fabs(sx));
   for (uint32_t j = 0;; ++j) {
-    const double2 us = draw2(2u + j, k, e, a.slot, a.key0, a.key1);
+    const double2 us = draw2(2u + j, k, e + a.e_off, a.slot, a.key0, a.key1);
     // candidate free path on the common time scale tau_min: -|V_g| tau_min ln(eta)
     const double ell = -(a.lam_min * log_own(1.0 - us.x));
     ++n_seg;
@@ -563,7 +566,7 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
       atom_add(&a.B[b], v);
   };
 
-  const FlyIn fa = {a.m, a.lam_min, a.slot, a.key0, a.key1, a.faces, a.has_null, a.ratio};
+  const FlyIn fa = {a.m, a.lam_min, a.slot, a.key0, a.key1, a.faces, a.has_null, a.ratio, in.e_off};
   const int n_e = (td.kind == 0) ? td.ex * td.ey : td.ex;
   const uint32_t P = static_cast<uint32_t>(n_e) * a.N;
   unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
@@ -683,7 +686,7 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   };
 
   const FlyIn fa = {m, in.lam_min, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1, 1,
-                    in.has_null, in.ratio};
+                    in.has_null, in.ratio, in.e_off};
   const uint32_t N = in.N;
   const unsigned long long total = static_cast<unsigned long long>(m.n_emit) * N;
   const unsigned long long pb = total * blockIdx.x / chunks;
@@ -703,7 +706,7 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   int kx0 = 0, ky0 = 0, ixs = 0, jwx = 0, k = 0, k_end = 0, cnt = 0, ixe = 0, iye = 0, bface = -1;
 
   auto start_segment = [&]() {
-    const double2 us = draw2(2u + j, kk, e, fa.slot, fa.key0, fa.key1);
+    const double2 us = draw2(2u + j, kk, e + fa.e_off, fa.slot, fa.key0, fa.key1);
     ell = -(fa.lam_min * log_own(1.0 - us.x));
     uacc = us.y;
     ++p_seg;
@@ -1015,7 +1018,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
       g += in.gpart[i];
       if (g > kBudgetCap) g = kBudgetCap;
     }
-  } else if (in.Gs) {
+  } else if (in.Gs || in.n_bands > 1) {
     g = in.wall_budget;
     for (int i = 0; i < nbc; ++i) {
       g += in.gpart[i];
@@ -1042,7 +1045,8 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
   else if (in.newton && sc->cg_status == -6) err = kErrBreakdown;
   else if (in.newton && sc->cg_status == -7) err = kErrCgNotConverged;
   else if (sc->flags & 1) err = kErrNonfinite;
-  else if ((sc->flags & 2) || ((in.newton || in.Gs) && g > (1ull << 62))) err = kErrOverflow;
+  else if ((sc->flags & 2) || ((in.newton || in.Gs || in.n_bands > 1) && g > (1ull << 62)))
+    err = kErrOverflow;
   else if (sc->iter > 1 && res > 1e3) err = kErrDiverged;
   sc->acc_mode = 0;
   if (err) {
@@ -1883,6 +1887,100 @@ __global__ void adjoint_grad_kernel(int n_cells, int n_b, int ny, const double *
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_cells && grad_source) grad_source[i] = g[i] * fs;
   if (i < n_b && grad_wall) grad_wall[i] = g[n_cells + i] * ((i < 2 * ny) ? fw_lr : fw_bt);
+}
+
+// ---------------------------------------------------------------------------
+// Frequency bands: the coupling step.  Per cell, the absorbed rate
+// R = sum_k ldexp(D_k, -F) / tau*_k (+ S V, passed as one product per cell) is
+// re-emitted over the bands with the equilibrium spectrum,
+// G_k = rint(ldexp(share_k R, F)), share_k = tau*_k ((C_k / tau_k) / den),
+// den = sum_k C_k / tau_k (share precomputed per band and cell); the energy
+// density is E = sum_k ldexp(W_k, -F) / V (W_k = D_k for a band without null
+// collisions).  Bands summed in index order.  Squared-change and |G| budget
+// partials per 256-cell block.
+// ---------------------------------------------------------------------------
+struct BandDev {
+  double ts;                    // tau*_k
+  const double *share;          // [nc] tau*_k (C_k / tau_k) / sum_j (C_j / tau_j)
+  const long long *D, *W;       // [nc]
+  long long *G;                 // [nc + nb] (cells first)
+  int has_null;
+};
+
+__global__ __launch_bounds__(256) void bands_update_kernel(const Inst *__restrict__ main_in,
+                                                           const BandDev *__restrict__ bands,
+                                                           int K, const double *__restrict__ srcV)
+{
+  __shared__ double lds[kTree];
+  __shared__ unsigned long long lg[kTree];
+  const Inst &in = *main_in;
+  const int n = in.m.n_cells;
+  const int c = blockIdx.x * kTree + threadIdx.x;
+  double sq = 0.0;
+  unsigned long long ag = 0;
+  int flags = 0;
+  if (c < n) {
+    double R = 0.0, Wsum = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const BandDev &b = bands[k];
+      const long long d = b.D[c];
+      R = R + ldexp(static_cast<double>(d), -in.F) / b.ts;
+      Wsum = Wsum + ldexp(static_cast<double>(b.has_null ? b.W[c] : d), -in.F);
+    }
+    if (srcV) R = R + srcV[c];
+    const double En = Wsum / in.V;
+    const double dd = En - in.E[c];
+    sq = dd * dd;
+    if (!isfinite(En)) flags |= 1;
+    in.E[c] = En;
+    for (int k = 0; k < K; ++k) {
+      const BandDev &b = bands[k];
+      const double v = ldexp(b.share[c] * R, in.F);
+      long long g = 0;
+      if (!(fabs(v) <= 4611686018427387904.0)) flags |= 2;
+      else g = static_cast<long long>(rint(v));
+      b.G[c] = g;
+      const unsigned long long a = static_cast<unsigned long long>(g < 0 ? -g : g);
+      ag = (ag + a > kBudgetCap) ? kBudgetCap : ag + a;
+    }
+  }
+  if (flags) atomicOr(&in.sc->flags, flags);
+  const double s = block_tree256(sq, lds);
+  lg[threadIdx.x] = ag;
+  __syncthreads();
+  for (int st = kTree / 2; st >= 1; st >>= 1) {
+    if (threadIdx.x < st) {
+      const unsigned long long u = lg[threadIdx.x] + lg[threadIdx.x + st];
+      lg[threadIdx.x] = u > kBudgetCap ? kBudgetCap : u;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    in.part[blockIdx.x] = s;
+    in.gpart[blockIdx.x] = lg[0];
+  }
+}
+
+// Frequency bands: the outputs.  T = t_ref + E / sum_k C_k; the face fluxes
+// q = (sum_k ldexp(Phi_k, -F) / tau*_k) / A over the bands in index order.
+__global__ void bands_output_kernel(int n_cells, int n_fx, int n_fy, int F, double t_ref,
+                                    double Ctot, double ax, double ay, int faces,
+                                    const double *E, const BandDev *bands, const long long *const *phix,
+                                    const long long *const *phiy, int K, double *T, double *qx,
+                                    double *qy)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_cells) T[i] = t_ref + E[i] / Ctot;
+  if (qx && i < n_fx) {
+    double v = 0.0;
+    for (int k = 0; k < K; ++k) v = v + ldexp(static_cast<double>(phix[k][i]), -F) / bands[k].ts;
+    qx[i] = faces ? v / ax : 0.0;
+  }
+  if (qy && i < n_fy) {
+    double v = 0.0;
+    for (int k = 0; k < K; ++k) v = v + ldexp(static_cast<double>(phiy[k][i]), -F) / bands[k].ts;
+    qy[i] = faces ? v / ay : 0.0;
+  }
 }
 
 // zero a small integer array (used instead of a memset node so the sequence can

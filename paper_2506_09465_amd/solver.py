@@ -3,7 +3,8 @@
 torch provides device memory and the current HIP stream; every step of the
 method runs in the library's kernels.  A problem is any object with the
 attributes dim, nx, ny, dx, dy, t_ref, cv, vg, tau, wall_T and optionally
-T_init and source (for example a `synth.Workload`).
+T_init, source and the frequency bands n_bands, band_C, band_vg (tau then
+[n_bands][n_cells]) (for example a `synth.Workload`).
 """
 from __future__ import annotations
 
@@ -44,10 +45,14 @@ class _Marshal:
         self.dx_arr = _dev_f64(diff_x, device)
         self.dy_arr = _dev_f64(diff_y, device)
         self.src = _dev_f64(getattr(w, "source", None), device)
+        K = int(getattr(w, "n_bands", 1) or 1)
+        self.bC = _dev_f64(getattr(w, "band_C", None), device) if K > 1 else None
+        self.bv = _dev_f64(getattr(w, "band_vg", None), device) if K > 1 else None
         self.problem = L.Problem(int(w.dim), int(w.nx), int(w.ny), float(w.dx), float(w.dy),
                                  float(w.t_ref), float(w.cv), float(w.vg), _ptr(self.tau),
                                  _ptr(self.wall), _ptr(self.T_init), _ptr(self.dx_arr),
-                                 _ptr(self.dy_arr), L.MEM_DEVICE, _ptr(self.src))
+                                 _ptr(self.dy_arr), L.MEM_DEVICE, _ptr(self.src), K,
+                                 _ptr(self.bC), _ptr(self.bv))
         self.options = L.Options(int(seed), int(particles), int(rng_mode), int(epoch),
                                  int(max_iters), float(res_tol), int(bool(newton)),
                                  float(cg_tol), int(cg_max_iters), int(tally_faces),
@@ -81,6 +86,7 @@ class Solver:
         if kw:
             raise TypeError(f"unknown options {sorted(kw)}")
         self.w = w
+        self.K = int(getattr(w, "n_bands", 1) or 1)
         self.nc = int(w.nx * w.ny)
         self.nb = 2 * int(w.ny) + (2 * int(w.nx) if w.dim == 2 else 0)
         self.ne = self.nc + self.nb
@@ -127,18 +133,23 @@ class Solver:
 
     # ------------------------------------------------------------------ readers
     def tallies(self):
-        z = lambda n: torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        """Tallies of the last iteration; (K, n) per-band blocks for K frequency bands."""
+        K = self.K
+        z = lambda n: torch.empty(max(K * n, 1), dtype=torch.int64, device=self.device)
         D, W, Px, Py, B = z(self.nc), z(self.nc), z(self.nfx), z(self.nfy), z(self.nb)
         with torch.cuda.device(self.device):
             L.check(L.lib().iugkp_get_tallies(self.h, D.data_ptr(), W.data_ptr(), Px.data_ptr(),
                                               Py.data_ptr(), B.data_ptr()), "iugkp_get_tallies")
-        return {"D": D, "W": W, "Phix": Px, "Phiy": Py[:self.nfy], "B": B}
+        out = {"D": D, "W": W, "Phix": Px, "Phiy": Py[:K * self.nfy], "B": B}
+        if K > 1:
+            out = {k: v.view(K, -1) for k, v in out.items()}
+        return out
 
     def state(self):
         it = C.c_uint32(0)
         d0 = C.c_double(0.0)
         E = torch.empty(self.nc, dtype=torch.float64, device=self.device)
-        G = torch.empty(self.ne, dtype=torch.int64, device=self.device)
+        G = torch.empty(self.K * self.ne, dtype=torch.int64, device=self.device)
         with torch.cuda.device(self.device):
             L.check(L.lib().iugkp_get_state(self.h, C.addressof(it), C.addressof(d0),
                                             E.data_ptr(), G.data_ptr()), "iugkp_get_state")
