@@ -1251,19 +1251,16 @@ int orc_bands_create(const orc_problem *p, const orc_options *o, orc_bands **out
     for (int k = 0; k < K; ++k) s->den[c] = s->den[c] + p->band_C[k] / p->tau[(size_t)k * nc + c];
   /* fixed-point scale: as the gray budget with the band sums (emission of the
      cells <= C dT V per iteration, walls <= dT sum_k C_k lambda*_k A / 4), plus
-     the source raised by at most 1 + 3 (L / min lambda*)^2 iterations */
+     the source's energy density S_max times the longest residence time of a
+     band, max_k tau*_k (1 + 3 (L / lambda*_k)^2) (the gray bound per band) */
   double dT = 0.0;
   for (int b = 0; b < nb; ++b)
     if (fabs(p->wall_T[b] - p->t_ref) > dT) dT = fabs(p->wall_T[b] - p->t_ref);
   if (p->T_init)
     for (int c = 0; c < nc; ++c)
       if (fabs(p->T_init[c] - p->t_ref) > dT) dT = fabs(p->T_init[c] - p->t_ref);
-  double lam_sum = 0.0, lam_lo = s->lam[0], ts_hi = s->ts[0];
-  for (int k = 0; k < K; ++k) {
-    lam_sum = lam_sum + p->band_C[k] * s->lam[k];
-    if (s->lam[k] < lam_lo) lam_lo = s->lam[k];
-    if (s->ts[k] > ts_hi) ts_hi = s->ts[k];
-  }
+  double lam_sum = 0.0;
+  for (int k = 0; k < K; ++k) lam_sum = lam_sum + p->band_C[k] * s->lam[k];
   const double vol = (double)nc * s->V;
   const double area = (p->dim == 2) ? ((2.0 * (double)p->ny) * p->dy + (2.0 * (double)p->nx) * p->dx)
                                     : 2.0;
@@ -1274,8 +1271,13 @@ int orc_bands_create(const orc_problem *p, const orc_options *o, orc_bands **out
       if (fabs(p->source[c]) > smax) smax = fabs(p->source[c]);
     double L = (double)p->nx * p->dx;
     if (p->dim == 2 && (double)p->ny * p->dy > L) L = (double)p->ny * p->dy;
-    const double rl = L / lam_lo;
-    esrc = (smax * ts_hi) * (1.0 + 3.0 * (rl * rl));
+    double res_hi = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double rl = L / s->lam[k];
+      const double r = s->ts[k] * (1.0 + 3.0 * (rl * rl));
+      if (r > res_hi) res_hi = r;
+    }
+    esrc = smax * res_hi;
   }
   const double Bb = 4.0 * ((dT * s->Ctot + esrc) * vol + (dT * lam_sum * area) / 4.0);
   if (Bb > 0.0) {

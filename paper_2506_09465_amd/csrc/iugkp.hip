@@ -632,17 +632,14 @@ int setup_bands(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, I
   for (int c = 0; c < nc; ++c)
     for (int k = 0; k < K; ++k) den[c] = den[c] + bC[k] / tau[static_cast<size_t>(k) * nc + c];
   // fixed-point scale: the gray budget with band sums (cells emit at most
-  // C dT V per iteration, walls dT sum_k C_k lambda*_k A / 4), the source
-  // raised by at most 1 + 3 (L / min lambda*)^2 iterations
+  // C dT V per iteration, walls dT sum_k C_k lambda*_k A / 4), plus the
+  // source's energy density S_max times the longest residence time of a band,
+  // max_k tau*_k (1 + 3 (L / lambda*_k)^2) (the gray bound per band)
   double dT = 0.0;
   for (double t : wall) dT = std::max(dT, std::fabs(t - p->t_ref));
   for (double t : T0) dT = std::max(dT, std::fabs(t - p->t_ref));
-  double lam_sum = 0.0, lam_lo = lam[0], ts_hi = ts[0];
-  for (int k = 0; k < K; ++k) {
-    lam_sum = lam_sum + bC[k] * lam[k];
-    lam_lo = std::min(lam_lo, lam[k]);
-    ts_hi = std::max(ts_hi, ts[k]);
-  }
+  double lam_sum = 0.0;
+  for (int k = 0; k < K; ++k) lam_sum = lam_sum + bC[k] * lam[k];
   const double vol = static_cast<double>(nc) * V;
   const double area = (p->dim == 2) ? ((2.0 * static_cast<double>(p->ny)) * p->dy +
                                        (2.0 * static_cast<double>(p->nx)) * p->dx)
@@ -653,8 +650,12 @@ int setup_bands(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, I
     for (double v : src) smax = std::max(smax, std::fabs(v));
     double L = static_cast<double>(p->nx) * p->dx;
     if (p->dim == 2 && static_cast<double>(p->ny) * p->dy > L) L = static_cast<double>(p->ny) * p->dy;
-    const double rl = L / lam_lo;
-    esrc = (smax * ts_hi) * (1.0 + 3.0 * (rl * rl));
+    double res_hi = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double rl = L / lam[k];
+      res_hi = std::max(res_hi, ts[k] * (1.0 + 3.0 * (rl * rl)));
+    }
+    esrc = smax * res_hi;
   }
   const double Bb = 4.0 * ((dT * Ctot + esrc) * vol + (dT * lam_sum * area) / 4.0);
   int F = 62;
