@@ -12,8 +12,9 @@ problems: emitter split, sampling + flight + tallies, macroscopic update,
 Newton CG, residual.  Printed: one JSON line with flights/s over the timed
 steps, per-Kn breakdown, roofline of the dominant kernel (timed with HIP
 events on the library's stream), time-to-steady at residual 1e-6 (common
-random numbers, faces tallied on the output iteration) and the CPU oracle
-baseline on a bounded sample.
+random numbers, faces tallied on the output iteration), the batched solver
+against sequential solves, the adjoint gradient, the 40-band non-gray
+two-material problem and the CPU oracle baseline on a bounded sample.
 """
 from __future__ import annotations
 
@@ -43,6 +44,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=256,
                     help="instances of the batched vs sequential comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient timing")
+    ap.add_argument("--no-nongray", action="store_true", help="skip the 40-band timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer three times (scales rocprofv3 FETCH_SIZE / "
                          "WRITE_SIZE to bytes) and exit")
@@ -207,6 +209,45 @@ def bench_adjoint(P, dev):
             "grad_source_norm": src.grad.norm().item()}
 
 
+def bench_nongray(P, dev, steps, warmup):
+    """The non-gray workload: 512 x 512 two-material square (left half's
+    relaxation times 100x the right half's), 40 bands of the sine dispersion
+    (Kn 1e-3 .. 10), Gaussian source of width 0.05 L at the centre, 5e7
+    particles per iteration.  After `warmup` iterations from t_ref (the
+    emission spreads from walls and source) `steps` iterations are timed with
+    face tallies every iteration and again without them."""
+    import torch
+    from synth import nongray_two_material_2d
+    w = nongray_two_material_2d()
+    s = P.Solver(w, device=dev, tally_faces=P.FACES_EVERY)
+    s.step(warmup, faces=False)
+    out = {"workload": "2D non-gray two-material 512x512, 40 bands, Gaussian source, "
+                       "5e7 particles/iteration", "warmup_iterations": warmup,
+           "fixed_point_F": s.stats()["fixed_point_F"]}
+    for faces in (True, False):
+        a = s.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            assert s.step(1, faces=faces) == 0
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        b = s.stats()
+        fl = b["tot_flights"] - a["tot_flights"]
+        cr = b["tot_crossings"] - a["tot_crossings"]
+        sg = b["tot_segments"] - a["tot_segments"]
+        ms_m = (b["ms_march"] - a["ms_march"]) / steps
+        mb = march_bytes(fl, cr, sg, b["n_emitters"] * steps, True) / steps
+        out["faces_every" if faces else "faces_off"] = {
+            "flights_per_s": fl / el, "ms_per_iteration": round(el / steps * 1e3, 3),
+            "ms_march": round(ms_m, 3), "flights_per_iter": fl // steps,
+            "crossings_per_flight": round(cr / max(fl, 1), 2),
+            "segments_per_flight": round(sg / max(fl, 1), 2),
+            "march_GBs_algorithmic": round(mb / (ms_m / 1e3) / 1e9, 2) if ms_m else None}
+    s.close()
+    return out
+
+
 def copy_calibration():
     import torch
     n = 256 * 1024 * 1024 // 8
@@ -335,6 +376,9 @@ def main():
 
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(P, dev)
+
+    if not args.no_nongray:
+        out["nongray"] = bench_nongray(P, dev, args.steps, 20)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
