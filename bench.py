@@ -45,6 +45,8 @@ def parse():
                     help="instances of the batched vs sequential comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient timing")
     ap.add_argument("--no-nongray", action="store_true", help="skip the 40-band timing")
+    ap.add_argument("--nongray-only", action="store_true",
+                    help="only the 40-band timing (printed as its own JSON line; for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer three times (scales rocprofv3 FETCH_SIZE / "
                          "WRITE_SIZE to bytes) and exit")
@@ -243,9 +245,37 @@ def bench_nongray(P, dev, steps, warmup):
             "ms_march": round(ms_m, 3), "flights_per_iter": fl // steps,
             "crossings_per_flight": round(cr / max(fl, 1), 2),
             "segments_per_flight": round(sg / max(fl, 1), 2),
-            "march_GBs_algorithmic": round(mb / (ms_m / 1e3) / 1e9, 2) if ms_m else None}
+            "march_GBs_algorithmic": round(mb / (ms_m / 1e3) / 1e9, 2) if ms_m else None,
+            "roofline": {"bound": "hbm", "achieved": round(mb / (ms_m / 1e3) / 1e9, 2) if ms_m else None,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(mb / (ms_m / 1e3) / 1e9 / HBM_PEAK_GBS, 5) if ms_m else None,
+                         "traffic": None, "kernel": "march_kernel",
+                         "algorithmic_bytes_per_launch": int(mb)}}
     s.close()
     return out
+
+
+def cpu_baseline_nongray():
+    """The CPU oracle on a bounded sample of the 40-band problem: the same
+    two-material 40-band workload on a 128 x 128 mesh with one particle per
+    emitter and band, four iterations from t_ref and then one timed iteration
+    with face tallies, on one core."""
+    from oracle import oracle as O
+    from synth import nongray_two_material_2d
+    O.build()
+    n = 128
+    w = nongray_two_material_2d(n=n, particles=(n * n + 4 * n) * 40)
+    o = O.Bands(w, tally_faces=O.FACES_EVERY)
+    o.step(4, faces=False)
+    t0 = time.perf_counter()
+    o.step(1, faces=True)
+    el = time.perf_counter() - t0
+    i = o.info()
+    return {"value": i.flights / el, "unit": "flights/s", "cores": 1, "kind": "oracle",
+            "segments_per_s": i.segments / el,
+            "sample": "one face-tallied iteration of the two-material 40-band problem on a "
+                      "128x128 mesh (1 particle per emitter and band, after 4 iterations from "
+                      "t_ref), single thread"}
 
 
 def copy_calibration():
@@ -274,6 +304,9 @@ def main():
     assert torch.cuda.is_available(), "needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.nongray_only:
+        print(json.dumps(bench_nongray(P, dev, args.steps, 20)), flush=True)
+        return
 
     solvers = []
     for kn in KNS:
@@ -379,6 +412,8 @@ def main():
 
     if not args.no_nongray:
         out["nongray"] = bench_nongray(P, dev, args.steps, 20)
+        if not args.no_cpu_baseline:
+            out["nongray"]["cpu_baseline"] = cpu_baseline_nongray()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
