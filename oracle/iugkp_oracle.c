@@ -1471,3 +1471,446 @@ void orc_bands_get_band(const orc_bands *s, int k, int64_t *D, int64_t *W, int64
   if (B) memcpy(B, s->B + (size_t)k * s->nb, sizeof(int64_t) * s->nb);
   if (G) memcpy(G, s->G + (size_t)k * s->ne, sizeof(int64_t) * s->ne);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Persistent particles: the variable-tau iteration of Sec. 3.2, steps       */
+/* (1)-(6), with a fixed population kept between iterations                  */
+/* ------------------------------------------------------------------------ */
+enum { ORC_P_NULL = 0, ORC_P_REAL = 1, ORC_P_WALL = 2 };
+#define ORC_P_STREAM 0xFFFFFFFFu   /* emitter word of every persistent draw */
+#define ORC_P_CREATE 0xFFFFFFFFu   /* slot of the creation draws */
+
+struct orc_persist {
+  orc_problem p;
+  orc_options o;
+  int nc, nb, nfx, nfy;
+  uint64_t n, N;
+  int F;
+  double V, tau_min, lam_min;
+  double *tau, *wall_T, *source, *ratio, *E;
+  int64_t *Gw, *Gs;                 /* per iteration: wall emission [nb], source [nc] */
+  double *x, *y, *sx, *sy;          /* particles */
+  int64_t *q;
+  int32_t *kind, *loc;
+  int64_t *W, *Wh, *Phix, *Phiy, *B;
+  uint32_t *Nrc, *Nb;
+  int64_t *wc, *rc, *wb, *rb;       /* next weights, carried remainders */
+  uint32_t iter;
+  double d0, res;
+  uint64_t flights, segments, crossings, tot_flights, tot_segments, tot_crossings;
+};
+
+void orc_persist_destroy(orc_persist *s)
+{
+  if (!s) return;
+  free(s->tau); free(s->wall_T); free(s->source); free(s->ratio); free(s->E);
+  free(s->Gw); free(s->Gs);
+  free(s->x); free(s->y); free(s->sx); free(s->sy); free(s->q); free(s->kind); free(s->loc);
+  free(s->W); free(s->Wh); free(s->Phix); free(s->Phiy); free(s->B); free(s->Nrc); free(s->Nb);
+  free(s->wc); free(s->rc); free(s->wb); free(s->rb);
+  free(s);
+}
+
+/* a = w n + r with 0 <= r < n (n > 0) */
+static void orc_share(int64_t a, uint32_t n, int64_t *w, int64_t *r)
+{
+  int64_t nn = (int64_t)n;
+  int64_t b = a / nn;
+  if ((a % nn) != 0 && a < 0) b -= 1;
+  *w = b;
+  *r = a - b * nn;
+}
+
+static uint64_t orc_abs64(int64_t v) { return (v < 0) ? (uint64_t)0 - (uint64_t)v : (uint64_t)v; }
+
+/* isotropic 3D direction, projected on the plane (as a cell's emission) */
+static void orc_iso_dir(const orc_problem *p, double uc, double ud, double *sx, double *sy)
+{
+  double mu = 2.0 * uc - 1.0;
+  *sx = mu;
+  *sy = (p->dim == 2) ? sqrt((1.0 - mu) * (1.0 + mu)) * orc_cos2pi(ud) : 0.0;
+}
+
+int orc_persist_create(const orc_problem *p, const orc_options *o, orc_persist **out)
+{
+  *out = NULL;
+  int rc = orc_validate(p);
+  if (rc) return rc;
+  if (p->n_bands > 1 || !o || o->particles_per_iter < 1 || o->max_iters < 0 ||
+      o->avg_iters < 0 || o->newton)
+    return ORC_E_INVALID_ARG;
+  const int nc = p->nx * p->ny, nb = orc_nb(p);
+  uint64_t N = o->particles_per_iter / (uint64_t)(nc + nb);
+  if (N < 1) N = 1;
+  if (N * (uint64_t)(nc + nb) > 0xFFFFFFFEull) return ORC_E_INVALID_ARG;
+  orc_persist *s = (orc_persist *)calloc(1, sizeof(orc_persist));
+  s->p = *p;
+  s->o = *o;
+  s->nc = nc;
+  s->nb = nb;
+  s->nfx = p->ny * (p->nx + 1);
+  s->nfy = (p->dim == 2) ? (p->ny + 1) * p->nx : 0;
+  s->N = N;
+  s->n = N * (uint64_t)(nc + nb);
+  s->tau = orc_dup(p->tau, nc);
+  s->wall_T = orc_dup(p->wall_T, nb);
+  s->source = orc_dup(p->source, nc);
+  s->p.tau = s->tau;
+  s->p.wall_T = s->wall_T;
+  s->p.source = s->source;
+  s->p.T_init = NULL;
+  s->p.diff_x = s->p.diff_y = NULL;
+  s->F = orc_fixed_exponent(p, &s->tau_min);
+  s->lam_min = p->vg * s->tau_min;
+  s->V = p->dx * p->dy;
+  s->ratio = (double *)malloc(sizeof(double) * nc);
+  s->E = (double *)malloc(sizeof(double) * nc);
+  s->Gw = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+  s->Gs = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+  s->x = (double *)malloc(sizeof(double) * s->n);
+  s->y = (double *)malloc(sizeof(double) * s->n);
+  s->sx = (double *)malloc(sizeof(double) * s->n);
+  s->sy = (double *)malloc(sizeof(double) * s->n);
+  s->q = (int64_t *)malloc(sizeof(int64_t) * s->n);
+  s->kind = (int32_t *)malloc(sizeof(int32_t) * s->n);
+  s->loc = (int32_t *)malloc(sizeof(int32_t) * s->n);
+  s->W = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+  s->Wh = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+  s->Nrc = (uint32_t *)calloc((size_t)nc, sizeof(uint32_t));
+  s->Phix = (int64_t *)calloc((size_t)s->nfx, sizeof(int64_t));
+  s->Phiy = (int64_t *)calloc((size_t)(s->nfy ? s->nfy : 1), sizeof(int64_t));
+  s->B = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+  s->Nb = (uint32_t *)calloc((size_t)nb, sizeof(uint32_t));
+  s->wc = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+  s->rc = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+  s->wb = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+  s->rb = (int64_t *)calloc((size_t)nb, sizeof(int64_t));
+  int ok = 1;
+  for (int c = 0; c < nc; ++c) {
+    s->ratio[c] = s->tau_min / s->tau[c];
+    double T0 = p->T_init ? p->T_init[c] : p->t_ref;
+    s->E[c] = p->cv * (T0 - p->t_ref);
+    if (s->source) s->Gs[c] = orc_to_fixed((s->source[c] * s->V) * s->tau_min, s->F, &ok);
+  }
+  for (int b = 0; b < nb; ++b) {
+    double A = (b < 2 * p->ny) ? p->dy : p->dx;
+    double ew = p->cv * (s->wall_T[b] - p->t_ref);
+    s->Gw[b] = orc_to_fixed((ew * (s->lam_min * A)) / 4.0, s->F, &ok);
+  }
+  /* step (1): N particles per cell in the local equilibrium, the cell's energy
+     E V split over them, uniform positions and isotropic directions */
+  uint64_t acc = 0;
+  for (int c = 0; c < nc; ++c) {
+    int ix = c % p->nx, iy = c / p->nx;
+    int64_t G0 = orc_to_fixed(s->E[c] * s->V, s->F, &ok);
+    for (uint64_t k = 0; k < N; ++k) {
+      uint64_t i = (uint64_t)c * N + k;
+      double ua, ub, uc, ud;
+      orc_draw(o->seed, ORC_P_CREATE, ORC_P_STREAM, (uint32_t)i, 0u, &ua, &ub);
+      orc_draw(o->seed, ORC_P_CREATE, ORC_P_STREAM, (uint32_t)i, 1u, &uc, &ud);
+      s->x[i] = ((double)ix + ua) * p->dx;
+      s->y[i] = ((double)iy + ub) * p->dy;
+      orc_iso_dir(p, uc, ud, &s->sx[i], &s->sy[i]);
+      s->q[i] = orc_split_weight(G0, N, k);
+      s->kind[i] = ORC_P_NULL;
+      s->loc[i] = c;
+      acc += orc_abs64(s->q[i]);
+      if (acc > ((uint64_t)1 << 62)) ok = 0;
+    }
+  }
+  /* N particles per wall face, as if absorbed there: they carry the faces'
+     first emission */
+  for (int b = 0; b < nb; ++b) {
+    for (uint64_t k = 0; k < N; ++k) {
+      uint64_t i = (uint64_t)(nc + b) * N + k;
+      s->x[i] = s->y[i] = s->sx[i] = s->sy[i] = 0.0;
+      s->q[i] = 0;
+      s->kind[i] = ORC_P_WALL;
+      s->loc[i] = b;
+    }
+    orc_share(s->Gw[b], (uint32_t)N, &s->wb[b], &s->rb[b]);
+    uint64_t a = orc_abs64(s->wb[b]) * N + orc_abs64(s->rb[b]);
+    acc += a;
+    if (acc > ((uint64_t)1 << 62)) ok = 0;
+  }
+  if (!ok) {
+    orc_persist_destroy(s);
+    return ORC_E_FIXED_OVERFLOW;
+  }
+  *out = s;
+  return ORC_OK;
+}
+
+static int orc_persist_iterate(orc_persist *s, int faces)
+{
+  const orc_problem *p = &s->p;
+  const int nx = p->nx, ny = p->ny, nc = s->nc, nb = s->nb;
+  uint32_t slot = (s->o.rng_mode == ORC_RNG_CRN) ? s->o.rng_epoch : s->iter;
+  memset(s->W, 0, sizeof(int64_t) * nc);
+  memset(s->Wh, 0, sizeof(int64_t) * nc);
+  memset(s->Nrc, 0, sizeof(uint32_t) * nc);
+  memset(s->Phix, 0, sizeof(int64_t) * s->nfx);
+  if (s->nfy) memset(s->Phiy, 0, sizeof(int64_t) * s->nfy);
+  memset(s->B, 0, sizeof(int64_t) * nb);
+  memset(s->Nb, 0, sizeof(uint32_t) * nb);
+  orc_tally t;
+  memset(&t, 0, sizeof t);
+  t.Phix = s->Phix;
+  t.Phiy = s->Phiy;
+  t.faces = faces;
+  uint64_t flights = 0, nul = 0;
+  int ok = 1;
+  for (uint64_t i = 0; i < s->n; ++i) {
+    int ix, iy;
+    if (s->kind[i] == ORC_P_REAL) {
+      /* step (2): real collision -> resampled from the cell's equilibrium:
+         uniform point of the cell, isotropic direction, the cell's share */
+      int c = s->loc[i];
+      double ua, ub, uc, ud;
+      orc_draw(s->o.seed, slot, ORC_P_STREAM, (uint32_t)i, 0u, &ua, &ub);
+      orc_draw(s->o.seed, slot, ORC_P_STREAM, (uint32_t)i, 1u, &uc, &ud);
+      ix = c % nx;
+      iy = c / nx;
+      s->x[i] = ((double)ix + ua) * p->dx;
+      s->y[i] = ((double)iy + ub) * p->dy;
+      orc_iso_dir(p, uc, ud, &s->sx[i], &s->sy[i]);
+      s->q[i] = s->wc[c];
+    } else if (s->kind[i] == ORC_P_WALL) {
+      /* absorbed by a black wall face: re-emitted from it (reading R1) */
+      int b = s->loc[i];
+      double ua, ub, uc, ud;
+      orc_draw(s->o.seed, slot, ORC_P_STREAM, (uint32_t)i, 0u, &ua, &ub);
+      orc_draw(s->o.seed, slot, ORC_P_STREAM, (uint32_t)i, 1u, &uc, &ud);
+      double cn = sqrt(uc);
+      double tg = (p->dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * orc_cos2pi(ud) : 0.0;
+      int64_t w = s->wb[b];
+      s->q[i] = w;
+      if (b < ny) {
+        ix = 0; iy = b;
+        s->x[i] = 0.0; s->y[i] = ((double)iy + ua) * p->dy;
+        s->sx[i] = cn; s->sy[i] = tg;
+        if (faces) s->Phix[iy * (nx + 1)] += w;
+      } else if (b < 2 * ny) {
+        ix = nx - 1; iy = b - ny;
+        s->x[i] = (double)nx * p->dx; s->y[i] = ((double)iy + ua) * p->dy;
+        s->sx[i] = -cn; s->sy[i] = tg;
+        if (faces) s->Phix[iy * (nx + 1) + nx] -= w;
+      } else if (b < 2 * ny + nx) {
+        ix = b - 2 * ny; iy = 0;
+        s->x[i] = ((double)ix + ua) * p->dx; s->y[i] = 0.0;
+        s->sx[i] = tg; s->sy[i] = cn;
+        if (faces) s->Phiy[ix] += w;
+      } else {
+        ix = b - 2 * ny - nx; iy = ny - 1;
+        s->x[i] = ((double)ix + ua) * p->dx; s->y[i] = (double)ny * p->dy;
+        s->sx[i] = tg; s->sy[i] = -cn;
+        if (faces) s->Phiy[ny * nx + ix] -= w;
+      }
+    } else {
+      /* null collision: same position, direction and weight (step (6)) */
+      int c = s->loc[i];
+      ix = c % nx;
+      iy = c / nx;
+    }
+    int64_t q = s->q[i];
+    if (q != 0) flights++;
+    /* step (3): one candidate path on the common time scale */
+    double ulen, uacc;
+    orc_draw(s->o.seed, slot, ORC_P_STREAM, (uint32_t)i, 2u, &ulen, &uacc);
+    double ell = -(s->lam_min * orc_log(1.0 - ulen));
+    double sx = s->sx[i], sy = s->sy[i];
+    double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+    double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+    int bface = -1;
+    if (orc_march(p, s->x[i], s->y[i], &ix, &iy, sx, sy, inv_sx, inv_sy, ell, q, &t, &bface)) {
+      s->B[bface] += q;
+      s->Nb[bface] += 1u;
+      s->kind[i] = ORC_P_WALL;
+      s->loc[i] = bface;
+      continue;
+    }
+    /* steps (4)-(5): candidate collision, accepted with probability tau_min / tau */
+    int c = ix + nx * iy;
+    s->W[c] += q;
+    s->x[i] = orc_clamp(s->x[i] + ell * sx, (double)ix * p->dx, (double)(ix + 1) * p->dx);
+    if (p->dim == 2)
+      s->y[i] = orc_clamp(s->y[i] + ell * sy, (double)iy * p->dy, (double)(iy + 1) * p->dy);
+    s->loc[i] = c;
+    if (uacc < s->ratio[c]) {
+      s->Wh[c] += q;
+      s->Nrc[c] += 1u;
+      s->kind[i] = ORC_P_REAL;
+    } else {
+      s->kind[i] = ORC_P_NULL;
+      nul += orc_abs64(q);
+      if (nul > ((uint64_t)1 << 62)) nul = ((uint64_t)1 << 62) + 1;
+    }
+  }
+  s->flights = flights;
+  s->segments = s->n;
+  s->crossings = t.crossings;
+  s->tot_flights += flights;
+  s->tot_segments += s->n;
+  s->tot_crossings += t.crossings;
+  /* E = W / V; shares of the real particles and of the walls for the next iteration */
+  double *tmp = (double *)malloc(sizeof(double) * nc);
+  int rc = ORC_OK;
+  uint64_t acc = nul;
+  const uint64_t cap = ((uint64_t)1 << 62) + 1;
+  for (int c = 0; c < nc; ++c) {
+    double En = ldexp((double)s->W[c], -s->F) / s->V;
+    double d = En - s->E[c];
+    tmp[c] = d * d;
+    if (!isfinite(En)) rc = ORC_E_NONFINITE;
+    s->E[c] = En;
+    int64_t avail = orc_add(orc_add(s->Wh[c], s->Gs[c], &ok), s->rc[c], &ok);
+    if (s->Nrc[c] > 0) {
+      orc_share(avail, s->Nrc[c], &s->wc[c], &s->rc[c]);
+    } else {
+      s->wc[c] = 0;
+      s->rc[c] = avail;
+    }
+    uint64_t a = orc_abs64(s->wc[c]) * (uint64_t)s->Nrc[c] + orc_abs64(s->rc[c]);
+    acc = (acc + a > cap) ? cap : acc + a;
+  }
+  for (int b = 0; b < nb; ++b) {
+    int64_t avail = orc_add(s->Gw[b], s->rb[b], &ok);
+    if (s->Nb[b] > 0) {
+      orc_share(avail, s->Nb[b], &s->wb[b], &s->rb[b]);
+    } else {
+      s->wb[b] = 0;
+      s->rb[b] = avail;
+    }
+    uint64_t a = orc_abs64(s->wb[b]) * (uint64_t)s->Nb[b] + orc_abs64(s->rb[b]);
+    acc = (acc + a > cap) ? cap : acc + a;
+  }
+  double dn = sqrt(orc_tree_sum(tmp, (uint64_t)nc));
+  free(tmp);
+  if (s->iter == 0) s->d0 = dn;
+  s->res = (s->d0 > 0.0) ? dn / s->d0 : 0.0;
+  s->iter++;
+  if (rc == ORC_OK && (!ok || acc > ((uint64_t)1 << 62))) rc = ORC_E_FIXED_OVERFLOW;
+  if (rc == ORC_OK && s->iter > 1 && s->res > 1e3) rc = ORC_E_DIVERGED;
+  return rc;
+}
+
+int orc_persist_step(orc_persist *s, int n_iters, int faces)
+{
+  for (int i = 0; i < n_iters; ++i) {
+    int rc = orc_persist_iterate(s, faces);
+    if (rc) return rc;
+  }
+  return ORC_OK;
+}
+
+int orc_persist_solve(orc_persist *s, double *T_out, double *qx_out, double *qy_out)
+{
+  const orc_problem *p = &s->p;
+  int faces_each = (s->o.tally_faces == ORC_FACES_EVERY);
+  int faces_out = (s->o.tally_faces != ORC_FACES_OFF);
+  int converged = 0, rc;
+  while ((int)s->iter < s->o.max_iters) {
+    rc = orc_persist_iterate(s, faces_each);
+    if (rc) return rc;
+    if (s->res < s->o.res_tol) {
+      converged = 1;
+      break;
+    }
+  }
+  double *Eo = (double *)calloc((size_t)s->nc, sizeof(double));
+  double *fx = (double *)calloc((size_t)s->nfx, sizeof(double));
+  double *fy = (double *)calloc((size_t)(s->nfy ? s->nfy : 1), sizeof(double));
+  if (s->o.avg_iters > 0) {
+    for (int a = 0; a < s->o.avg_iters; ++a) {
+      rc = orc_persist_iterate(s, faces_out);
+      if (rc) { free(Eo); free(fx); free(fy); return rc; }
+      for (int c = 0; c < s->nc; ++c) Eo[c] = Eo[c] + s->E[c];
+      for (int f = 0; f < s->nfx; ++f) fx[f] = fx[f] + ldexp((double)s->Phix[f], -s->F);
+      for (int f = 0; f < s->nfy; ++f) fy[f] = fy[f] + ldexp((double)s->Phiy[f], -s->F);
+    }
+    double na = (double)s->o.avg_iters;
+    for (int c = 0; c < s->nc; ++c) Eo[c] = Eo[c] / na;
+    for (int f = 0; f < s->nfx; ++f) fx[f] = fx[f] / na;
+    for (int f = 0; f < s->nfy; ++f) fy[f] = fy[f] / na;
+  } else {
+    if (s->o.tally_faces == ORC_FACES_FINAL) {
+      rc = orc_persist_iterate(s, 1);
+      if (rc) { free(Eo); free(fx); free(fy); return rc; }
+    }
+    for (int c = 0; c < s->nc; ++c) Eo[c] = s->E[c];
+    for (int f = 0; f < s->nfx; ++f) fx[f] = ldexp((double)s->Phix[f], -s->F);
+    for (int f = 0; f < s->nfy; ++f) fy[f] = ldexp((double)s->Phiy[f], -s->F);
+  }
+  if (T_out)
+    for (int c = 0; c < s->nc; ++c) T_out[c] = p->t_ref + Eo[c] / p->cv;
+  if (qx_out) {
+    double den = p->dy * s->tau_min;
+    for (int f = 0; f < s->nfx; ++f) qx_out[f] = faces_out ? fx[f] / den : 0.0;
+  }
+  if (qy_out && s->nfy) {
+    double den = p->dx * s->tau_min;
+    for (int f = 0; f < s->nfy; ++f) qy_out[f] = faces_out ? fy[f] / den : 0.0;
+  }
+  free(Eo);
+  free(fx);
+  free(fy);
+  return converged ? ORC_OK : ORC_W_NOT_CONVERGED;
+}
+
+void orc_persist_get_info(const orc_persist *s, orc_info *info)
+{
+  memset(info, 0, sizeof *info);
+  info->iter = s->iter;
+  info->F = s->F;
+  info->n_per_emitter = s->N;
+  info->n_cells = s->nc;
+  info->n_bfaces = s->nb;
+  info->n_emitters = s->nc;
+  info->tau_min = s->tau_min;
+  info->lam_min = s->lam_min;
+  info->d0 = s->d0;
+  info->res = s->res;
+  info->flights = s->flights;
+  info->segments = s->segments;
+  info->crossings = s->crossings;
+  info->tot_flights = s->tot_flights;
+  info->tot_segments = s->tot_segments;
+  info->tot_crossings = s->tot_crossings;
+}
+
+void orc_persist_get_E(const orc_persist *s, double *E) { memcpy(E, s->E, sizeof(double) * s->nc); }
+
+uint64_t orc_persist_count(const orc_persist *s) { return s->n; }
+
+void orc_persist_get_particles(const orc_persist *s, double *x, double *y, double *sx, double *sy,
+                               int64_t *q, int32_t *kind, int32_t *loc)
+{
+  if (x) memcpy(x, s->x, sizeof(double) * s->n);
+  if (y) memcpy(y, s->y, sizeof(double) * s->n);
+  if (sx) memcpy(sx, s->sx, sizeof(double) * s->n);
+  if (sy) memcpy(sy, s->sy, sizeof(double) * s->n);
+  if (q) memcpy(q, s->q, sizeof(int64_t) * s->n);
+  if (kind) memcpy(kind, s->kind, sizeof(int32_t) * s->n);
+  if (loc) memcpy(loc, s->loc, sizeof(int32_t) * s->n);
+}
+
+void orc_persist_get_tallies(const orc_persist *s, int64_t *W, int64_t *Wh, uint32_t *Nrc,
+                             int64_t *Phix, int64_t *Phiy, int64_t *B, uint32_t *Nb)
+{
+  if (W) memcpy(W, s->W, sizeof(int64_t) * s->nc);
+  if (Wh) memcpy(Wh, s->Wh, sizeof(int64_t) * s->nc);
+  if (Nrc) memcpy(Nrc, s->Nrc, sizeof(uint32_t) * s->nc);
+  if (Phix) memcpy(Phix, s->Phix, sizeof(int64_t) * s->nfx);
+  if (Phiy && s->nfy) memcpy(Phiy, s->Phiy, sizeof(int64_t) * s->nfy);
+  if (B) memcpy(B, s->B, sizeof(int64_t) * s->nb);
+  if (Nb) memcpy(Nb, s->Nb, sizeof(uint32_t) * s->nb);
+}
+
+void orc_persist_get_shares(const orc_persist *s, int64_t *wc, int64_t *rc, int64_t *wb,
+                            int64_t *rb)
+{
+  if (wc) memcpy(wc, s->wc, sizeof(int64_t) * s->nc);
+  if (rc) memcpy(rc, s->rc, sizeof(int64_t) * s->nc);
+  if (wb) memcpy(wb, s->wb, sizeof(int64_t) * s->nb);
+  if (rb) memcpy(rb, s->rb, sizeof(int64_t) * s->nb);
+}

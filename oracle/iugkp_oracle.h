@@ -165,6 +165,49 @@ void orc_bands_get_E(const orc_bands *s, double *E);
 void orc_bands_get_band(const orc_bands *s, int k, int64_t *D, int64_t *W, int64_t *Phix,
                         int64_t *Phiy, int64_t *B, int64_t *G);
 
+/* ---- persistent particles: the paper's variable-tau iteration (Sec. 3.2
+ * steps (1)-(6)) with a fixed particle population ----
+ * N = max(1, particles_per_iter / (cells + wall faces)) particles per cell
+ * are created in equilibrium (weight: the cell's energy E V split over its N
+ * particles, uniform position, isotropic direction), and N per wall face as
+ * if just absorbed there (they carry the face's first emission); the
+ * population is kept from iteration to iteration (particle c N + k of cell
+ * c, (cells + b) N + k of wall face b).  Each iteration every particle flies one candidate path on the
+ * common time scale tau_min: a real-collision particle is first resampled
+ * from its cell's equilibrium (uniform point of the cell, isotropic
+ * direction) with the weight w_c of its cell, a particle absorbed by
+ * a wall face is re-emitted from that face (uniform point, cosine law) with
+ * the face's weight w_b, a null-collision particle keeps its position,
+ * direction and weight.  At the end of its path it is absorbed by a wall or
+ * adds its weight to W of the cell it reached and is accepted as real with
+ * probability tau_min / tau (then also to W^h and the count N_rc).  Then
+ * E = W / V, and the real particles of cell c share W^h_c + S V tau_min plus
+ * the cell's carried remainder: w_c = floor(. / N_rc), the remainder carried
+ * to the next iteration (all of it when N_rc = 0); likewise wall face b
+ * shares its emission E_w lambda_min A / 4 plus its carried remainder over
+ * the N_b particles it absorbed.  Counter of particle p's draw d in an
+ * iteration with slot s: (d, p, 0xffffffff, s); creation uses slot
+ * 0xffffffff; d = 0 position, 1 direction, 2 (free path, acceptance).
+ * Particle kinds: 0 null (moves on), 1 real (resampled in its cell),
+ * 2 absorbed by a wall face (re-emitted from it); loc = cell or wall face. */
+typedef struct orc_persist orc_persist;
+int orc_persist_create(const orc_problem *p, const orc_options *o, orc_persist **out);
+void orc_persist_destroy(orc_persist *s);
+int orc_persist_step(orc_persist *s, int n_iters, int faces);
+int orc_persist_solve(orc_persist *s, double *T_out, double *qx_out, double *qy_out);
+void orc_persist_get_info(const orc_persist *s, orc_info *info);
+void orc_persist_get_E(const orc_persist *s, double *E);
+uint64_t orc_persist_count(const orc_persist *s);
+/* particle state (any pointer may be NULL) */
+void orc_persist_get_particles(const orc_persist *s, double *x, double *y, double *sx, double *sy,
+                               int64_t *q, int32_t *kind, int32_t *loc);
+/* tallies of the last iteration: W, W^h and N_rc per cell, face fluxes, wall
+ * absorption B and count N_b; next weights and carried remainders */
+void orc_persist_get_tallies(const orc_persist *s, int64_t *W, int64_t *Wh, uint32_t *Nrc,
+                             int64_t *Phix, int64_t *Phiy, int64_t *B, uint32_t *Nb);
+void orc_persist_get_shares(const orc_persist *s, int64_t *wc, int64_t *rc, int64_t *wb,
+                            int64_t *rb);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,17 @@ def lib():
         L.orc_bands_get_info.argtypes = [P, C.POINTER(_Info)]
         L.orc_bands_get_E.argtypes = [P, P]
         L.orc_bands_get_band.argtypes = [P, C.c_int, P, P, P, P, P, P]
+        L.orc_persist_create.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), C.POINTER(P)]
+        L.orc_persist_destroy.argtypes = [P]
+        L.orc_persist_step.argtypes = [P, C.c_int, C.c_int]
+        L.orc_persist_solve.argtypes = [P, P, P, P]
+        L.orc_persist_get_info.argtypes = [P, C.POINTER(_Info)]
+        L.orc_persist_get_E.argtypes = [P, P]
+        L.orc_persist_count.argtypes = [P]
+        L.orc_persist_count.restype = C.c_uint64
+        L.orc_persist_get_particles.argtypes = [P, P, P, P, P, P, P, P]
+        L.orc_persist_get_tallies.argtypes = [P, P, P, P, P, P, P, P]
+        L.orc_persist_get_shares.argtypes = [P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -404,4 +415,81 @@ class Bands:
         qx = np.zeros(self.nfx)
         qy = np.zeros(max(self.nfy, 1))
         rc = lib().orc_bands_solve(self.h, T.ctypes.data, qx.ctypes.data, qy.ctypes.data)
+        return rc, T, qx, qy[:self.nfy]
+
+
+class Persist:
+    """The persistent-particle oracle (Sec. 3.2 steps (1)-(6) with a fixed
+    population): create, step, read particles, tallies and shares."""
+
+    def __init__(self, w, *, seed=None, particles=None, rng_mode=FRESH, epoch=0, max_iters=None,
+                 res_tol=None, tally_faces=FACES_EVERY, avg_iters=0):
+        self.w = w
+        self._keep = _Keep(w)
+        self.opts = _Options(w.seed if seed is None else seed,
+                             w.particles_per_iter if particles is None else particles,
+                             rng_mode, epoch, w.max_iters if max_iters is None else max_iters,
+                             w.res_tol if res_tol is None else res_tol, 0, 1e-10, 1, tally_faces,
+                             avg_iters)
+        h = C.c_void_p()
+        rc = lib().orc_persist_create(C.byref(self._keep.p), C.byref(self.opts), C.byref(h))
+        if rc != OK:
+            raise OracleError(rc, "persist_create")
+        self.h = h
+        self.nc = w.nx * w.ny
+        self.nb = w.n_bfaces
+        self.nfx = w.ny * (w.nx + 1)
+        self.nfy = (w.ny + 1) * w.nx if w.dim == 2 else 0
+        self.n = int(lib().orc_persist_count(h))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().orc_persist_destroy(h)
+            self.h = None
+
+    def info(self) -> Info:
+        i = _Info()
+        lib().orc_persist_get_info(self.h, C.byref(i))
+        return Info(*[getattr(i, f[0]) for f in _Info._fields_])
+
+    def step(self, n=1, faces=True) -> int:
+        return lib().orc_persist_step(self.h, n, int(bool(faces)))
+
+    def E(self) -> np.ndarray:
+        E = np.zeros(self.nc)
+        lib().orc_persist_get_E(self.h, E.ctypes.data)
+        return E
+
+    def particles(self):
+        n = self.n
+        d = {k: np.zeros(n) for k in ("x", "y", "sx", "sy")}
+        d["q"] = np.zeros(n, np.int64)
+        d["kind"] = np.zeros(n, np.int32)
+        d["loc"] = np.zeros(n, np.int32)
+        lib().orc_persist_get_particles(self.h, *[d[k].ctypes.data for k in
+                                                  ("x", "y", "sx", "sy", "q", "kind", "loc")])
+        return d
+
+    def tallies(self):
+        d = {"W": np.zeros(self.nc, np.int64), "Wh": np.zeros(self.nc, np.int64),
+             "Nrc": np.zeros(self.nc, np.uint32), "Phix": np.zeros(self.nfx, np.int64),
+             "Phiy": np.zeros(max(self.nfy, 1), np.int64), "B": np.zeros(self.nb, np.int64),
+             "Nb": np.zeros(self.nb, np.uint32)}
+        lib().orc_persist_get_tallies(self.h, *[d[k].ctypes.data for k in
+                                                ("W", "Wh", "Nrc", "Phix", "Phiy", "B", "Nb")])
+        d["Phiy"] = d["Phiy"][:self.nfy]
+        return d
+
+    def shares(self):
+        d = {"wc": np.zeros(self.nc, np.int64), "rc": np.zeros(self.nc, np.int64),
+             "wb": np.zeros(self.nb, np.int64), "rb": np.zeros(self.nb, np.int64)}
+        lib().orc_persist_get_shares(self.h, *[d[k].ctypes.data for k in ("wc", "rc", "wb", "rb")])
+        return d
+
+    def solve(self):
+        T = np.zeros(self.nc)
+        qx = np.zeros(self.nfx)
+        qy = np.zeros(max(self.nfy, 1))
+        rc = lib().orc_persist_solve(self.h, T.ctypes.data, qx.ctypes.data, qy.ctypes.data)
         return rc, T, qx, qy[:self.nfy]
