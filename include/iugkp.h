@@ -128,7 +128,29 @@ typedef struct iugkp_options {
   int cg_waves;                 /* single solves: 256-cell tree blocks per CG workgroup, 0
                                    (= 8) or 1..12 with the CG state in registers, -1..-12 with
                                    it in global memory; the result does not depend on it */
+  int scheme;                   /* IUGKP_SCHEME_EMITTERS (0): every emitter flies N fresh
+                                   particles per iteration, null collisions followed within
+                                   the iteration.  IUGKP_SCHEME_PERSISTENT (1): the variable-tau
+                                   iteration of Sec. 3.2 steps (1)-(6) with a fixed population
+                                   of N = max(1, particles_per_iter / (n_cells + n_b))
+                                   particles per cell and per wall face, kept between
+                                   iterations: each iteration every particle flies one
+                                   candidate path on the common time scale tau_min; a
+                                   real-collision particle is first resampled from its cell's
+                                   equilibrium (uniform point, isotropic direction) with the
+                                   cell's share w_c = floor((W^h_c + S V tau_min + r_c) /
+                                   N_rc), the remainder r_c carried to the next iteration (all
+                                   of it when N_rc = 0); a particle absorbed by a wall face is
+                                   re-emitted from it (uniform point, cosine law) with the
+                                   face's share of its emission E_w lambda_min A / 4 plus its
+                                   carried remainder; a null particle keeps position, direction
+                                   and weight.  E = W / V (all candidates).  Particle p's draw
+                                   d uses the counter (d, p, 0xffffffff, slot), creation slot
+                                   0xffffffff.  Gray single solves without the Newton step
+                                   only.  Tallies: D = W^h (real collisions), W, faces, B */
 } iugkp_options;
+
+enum { IUGKP_SCHEME_EMITTERS = 0, IUGKP_SCHEME_PERSISTENT = 1 };
 
 typedef struct iugkp_stats {
   int iters;                    /* iterations done since creation (or the restored state) */
@@ -192,12 +214,31 @@ int iugkp_get_tallies(iugkp_handle *h, int64_t *D, int64_t *W, int64_t *Phi_x,
 
 /* Resumable state: iteration count, first-iteration update norm, E^n [n_cells]
  * and the next emission energies G [n_cells + n_b] (int64; [K][n_cells + n_b]
- * for K frequency bands).  set_state restores
+ * for K frequency bands; the shares w_c then w_b for the persistent scheme,
+ * whose state is its population: set_state refuses it).  set_state restores
  * it (resume is bitwise identical to an uninterrupted run).  Arrays in the
  * problem's mem_kind. */
 int iugkp_get_state(iugkp_handle *h, uint32_t *iter, double *d0, double *E, int64_t *G);
 int iugkp_set_state(iugkp_handle *h, uint32_t iter, double d0, const double *E,
                     const int64_t *G);
+
+/* Persistent population (scheme IUGKP_SCHEME_PERSISTENT): the particles'
+ * position x, y, direction sx, sy, weight q (int64, 2^F units), kind (0 null,
+ * 1 real collision, 2 absorbed by a wall face) and location (cell c = ix + nx iy,
+ * or wall face) after the last iteration, n = N (n_cells + n_b) entries each
+ * (particle c N + k of cell c, (n_cells + b) N + k of wall face b at creation);
+ * any pointer may be NULL.  Arrays in the problem's mem_kind.  Returns
+ * IUGKP_E_INVALID_ARG for the emitter scheme. */
+int iugkp_get_particles(iugkp_handle *h, double *x, double *y, double *sx, double *sy,
+                        int64_t *q, int32_t *kind, int32_t *loc);
+
+/* Persistent population: real collisions per cell N_rc [n_cells] and
+ * absorptions per wall face N_b [n_b] (uint32) of the last iteration, and the
+ * shares and carried remainders for the next one: w_c, r_c [n_cells],
+ * w_b, r_b [n_b] (int64).  Any pointer may be NULL.  Arrays in the problem's
+ * mem_kind. */
+int iugkp_get_shares(iugkp_handle *h, uint32_t *n_rc, uint32_t *n_b, int64_t *w_c, int64_t *r_c,
+                     int64_t *w_b, int64_t *r_b);
 
 /* Relative residual history (host array, up to max_n entries); returns the count. */
 int iugkp_get_residuals(iugkp_handle *h, double *res, int max_n);

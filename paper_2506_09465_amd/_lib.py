@@ -21,6 +21,7 @@ E_DIVERGED = -8
 MEM_HOST, MEM_DEVICE = 0, 1
 RNG_FRESH, RNG_CRN = 0, 1
 FACES_OFF, FACES_EVERY, FACES_FINAL = 0, 1, 2
+SCHEME_EMITTERS, SCHEME_PERSISTENT = 0, 1
 
 
 class Problem(C.Structure):
@@ -37,7 +38,8 @@ class Options(C.Structure):
                 ("rng_mode", C.c_int), ("rng_epoch", C.c_uint32), ("max_iters", C.c_int),
                 ("res_tol", C.c_double), ("newton", C.c_int), ("cg_tol", C.c_double),
                 ("cg_max_iters", C.c_int), ("tally_faces", C.c_int), ("avg_iters", C.c_int),
-                ("block_size", C.c_int), ("march", C.c_int), ("cg_waves", C.c_int)]
+                ("block_size", C.c_int), ("march", C.c_int), ("cg_waves", C.c_int),
+                ("scheme", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -66,6 +68,8 @@ SIGNATURES = [
     ("iugkp_set_state", C.c_int, [P, C.c_uint32, C.c_double, P, P]),
     ("iugkp_get_residuals", C.c_int, [P, P, C.c_int]),
     ("iugkp_get_stats", C.c_int, [P, C.POINTER(Stats)]),
+    ("iugkp_get_particles", C.c_int, [P, P, P, P, P, P, P, P]),
+    ("iugkp_get_shares", C.c_int, [P, P, P, P, P, P, P]),
     ("iugkp_d_eff", C.c_double, [C.c_double, C.c_double]),
     ("iugkp_adjoint", C.c_int, [P, P, P, P, C.c_int, C.c_double, P]),
     ("iugkp_batch_create", C.c_int, [P, P, C.c_int, P, C.POINTER(P)]),

@@ -49,6 +49,7 @@ constexpr double kStripeMinCells = 64.0;     // row stripes for face tallies whe
 constexpr int kStripeBlock = 1024;           // threads of a stripe workgroup
 constexpr int kStripeMinRows = 4;
 constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of a CG workgroup
+constexpr int kPersistBlock = 256;           // particles per move workgroup
 constexpr int kTileX = 8, kTileY = 8;        // emitter tile of one workgroup (cells)
 constexpr int kWallSeg = 8;                  // wall faces per workgroup
 constexpr int kWindowHalo = 12;              // window margin around a tile (cells)
@@ -147,6 +148,10 @@ int check_options(const iugkp_options *o)
   if (o->march < 0 || o->march > 2) return fail(IUGKP_E_INVALID_ARG, "march must be 0, 1 or 2");
   if (o->cg_waves < -iugkp::kCgWavesMax || o->cg_waves > iugkp::kCgWavesMax)
     return fail(IUGKP_E_INVALID_ARG, "cg_waves must be -12..12");
+  if (o->scheme != IUGKP_SCHEME_EMITTERS && o->scheme != IUGKP_SCHEME_PERSISTENT)
+    return fail(IUGKP_E_INVALID_ARG, "bad scheme");
+  if (o->scheme == IUGKP_SCHEME_PERSISTENT && o->newton)
+    return fail(IUGKP_E_INVALID_ARG, "the persistent scheme has no Newton step");
   return IUGKP_OK;
 }
 
@@ -256,6 +261,86 @@ void plan_tiles(InstHost &ih)
   ih.lds_bytes = iugkp::window_words(d.WX, d.WY, d.has_null, d.lds_walls, m.n_b) * sizeof(long long);
 }
 
+// Persistent population: N particles per cell in equilibrium (the cell's
+// energy E V split over them) and N per wall face waiting to carry the
+// face's first emission; shares, remainders, counts and tallies.
+int setup_persistent(InstHost &ih, const std::vector<double> &T0, const std::vector<long long> &gw,
+                     hipStream_t s)
+{
+  Inst &d = ih.d;
+  const Mesh &m = d.m;
+  const int nc = m.n_cells, nb = m.n_b;
+  const uint64_t n = static_cast<uint64_t>(d.N) * static_cast<uint64_t>(nc + nb);
+  if (n > 0xFFFFFFFEull) return fail(IUGKP_E_INVALID_ARG, "persistent population above 2^32 - 2");
+  d.persist = 1;
+  d.n_part = static_cast<unsigned int>(n);
+  d.n_npart = cdiv(static_cast<long long>(n), kPersistBlock);
+  d.n_gpart = cdiv(nc, iugkp::kTree) + cdiv(nb, iugkp::kTree) + 1;
+#define PALLOC(ptr, k) \
+  if (ih.alloc(&(ptr), (k)) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
+  PALLOC(d.px, n);
+  PALLOC(d.py, n);
+  PALLOC(d.psx, n);
+  PALLOC(d.psy, n);
+  PALLOC(d.pq, n);
+  PALLOC(d.plk, n);
+  PALLOC(d.Nrc, nc);
+  PALLOC(d.Nb, nb);
+  PALLOC(d.wc, nc);
+  PALLOC(d.rc, nc);
+  PALLOC(d.wb, nb);
+  PALLOC(d.rb, nb);
+  PALLOC(d.npart, d.n_npart);
+  long long *dgw = nullptr, *dg0 = nullptr;
+  PALLOC(dgw, nb);
+  PALLOC(dg0, nc);
+#undef PALLOC
+  d.Gw = dgw;
+  // the cells' energies E V in fixed point, the walls' first shares
+  std::vector<long long> g0(nc), wb(nb), rb(nb);
+  unsigned long long acc = 0;
+  bool over = false;
+  for (int c = 0; c < nc; ++c) {
+    const double e0 = T0.empty() ? d.cv * (d.t_ref - d.t_ref) : d.cv * (T0[c] - d.t_ref);
+    const double v = std::ldexp(e0 * d.V, d.F);
+    if (!(std::fabs(v) <= 4611686018427387904.0)) return fail(IUGKP_E_FIXED_OVERFLOW, "initial energy exceeds the fixed-point range");
+    g0[c] = static_cast<long long>(std::rint(v));
+    acc += static_cast<unsigned long long>(g0[c] < 0 ? -g0[c] : g0[c]);
+    if (acc > (1ull << 62)) over = true;
+  }
+  for (int b = 0; b < nb; ++b) {
+    const long long nn = static_cast<long long>(d.N);
+    long long w = gw[b] / nn;
+    if (gw[b] % nn != 0 && gw[b] < 0) w -= 1;
+    wb[b] = w;
+    rb[b] = gw[b] - w * nn;
+    acc += static_cast<unsigned long long>(w < 0 ? -w : w) * d.N + static_cast<unsigned long long>(rb[b]);
+    if (acc > (1ull << 62)) over = true;
+  }
+  if (over) return fail(IUGKP_E_FIXED_OVERFLOW, "initial population exceeds the fixed-point budget");
+  HIP_TRY(hipMemcpyAsync(dgw, gw.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dg0, g0.data(), nc * sizeof(long long), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d.wb, wb.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d.rb, rb.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(d.wc, 0, nc * sizeof(long long), s));
+  HIP_TRY(hipMemsetAsync(d.rc, 0, nc * sizeof(long long), s));
+  HIP_TRY(hipMemsetAsync(d.Nrc, 0, nc * sizeof(uint32_t), s));
+  HIP_TRY(hipMemsetAsync(d.Nb, 0, nb * sizeof(uint32_t), s));
+  HIP_TRY(hipMemsetAsync(d.D, 0, nc * sizeof(long long), s));
+  HIP_TRY(hipMemsetAsync(d.W, 0, nc * sizeof(long long), s));
+  HIP_TRY(hipMemsetAsync(d.Phix, 0, m.n_fx * sizeof(long long), s));
+  if (m.n_fy) HIP_TRY(hipMemsetAsync(d.Phiy, 0, m.n_fy * sizeof(long long), s));
+  HIP_TRY(hipMemsetAsync(d.B, 0, nb * sizeof(long long), s));
+  // the descriptor the creation kernel reads (uploaded again by the caller)
+  Inst *dinst = nullptr;
+  if (ih.alloc(&dinst, 1) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
+  HIP_TRY(hipMemcpyAsync(dinst, &d, sizeof(Inst), hipMemcpyHostToDevice, s));
+  iugkp::persist_init_kernel<<<cdiv(static_cast<long long>(n), 256), 256, 0, s>>>(dinst, dg0);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return IUGKP_OK;
+}
+
 // Validate, allocate and initialise one instance on `s`.  multi_cg: also lay
 // out the multi-workgroup CG used by single solves.
 int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, bool multi_cg,
@@ -356,7 +441,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   ALLOC(ih.out_qx, m.n_fx);
   ALLOC(ih.out_qy, m.n_fy);
   ALLOC(d.sc, 1);
-  ALLOC(d.gpart, nbe);
+  ALLOC(d.gpart, std::max(nbe, cdiv(nc, iugkp::kTree) + cdiv(nb, iugkp::kTree) + 1));
   if (o->newton) {
     const int nbt = cdiv(nc, iugkp::kTree);
     ALLOC(d.rhs, nc);
@@ -486,6 +571,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
     }
   }
   if (multi_cg && p->dim == 2 && o->tally_faces != IUGKP_FACES_OFF &&
+      o->scheme == IUGKP_SCHEME_EMITTERS &&
       (o->march == 2 ||
        (o->march == 0 && d.lam_min >= kStripeMinCells * std::min(p->dx, p->dy)))) {
     // row stripes: as many rows per workgroup as its LDS holds (y faces, D,
@@ -516,6 +602,10 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
     }
     if (o->march == 2 && ih.stripe_R == 0)
       return fail(IUGKP_E_INVALID_ARG, "row stripes do not fit this mesh");
+  }
+  if (o->scheme == IUGKP_SCHEME_PERSISTENT) {
+    if (!multi_cg) return fail(IUGKP_E_INVALID_ARG, "the persistent scheme is for single solves");
+    if ((rc = setup_persistent(ih, T0, gw, s))) return rc;
   }
   std::vector<long long> g(ne);
   int hflag = 0;
@@ -1013,10 +1103,20 @@ int iterate(iugkp_handle *h, int faces)
   const int nprep = std::max(std::max(std::max(m.n_emit, m.n_fx), std::max(m.n_fy, m.n_cells)),
                              (m.ny + 2) * m.nx);
   const int K = h->bh.K;
+  int rc = IUGKP_OK;
+  if (ih.d.persist) {
+    const int nmax = std::max(std::max(m.n_cells, m.n_b), std::max(m.n_fx, m.n_fy));
+    iugkp::persist_prepare_kernel<<<cdiv(nmax, 256), 256, 0, s>>>(h->d_inst);
+    HIP_TRY(hipEventRecord(h->ev[0], s));
+    iugkp::persist_move_kernel<kPersistBlock>
+        <<<ih.d.n_npart, kPersistBlock, 0, s>>>(h->d_inst, faces);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(h->ev[1], s));
+    iugkp::persist_update_kernel<<<ih.d.n_gpart, 256, 0, s>>>(h->d_inst);
+  } else {
   iugkp::prepare_kernel<<<dim3(cdiv(nprep, 256), K), 256, 0, s>>>(h->d_inst, faces, 0);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(h->ev[0], s));
-  int rc = IUGKP_OK;
   if (faces && ih.stripe_R > 0) {
     iugkp::march_stripes_kernel<kStripeBlock>
         <<<dim3(ih.stripe_C, ih.stripe_S), kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R,
@@ -1042,6 +1142,7 @@ int iterate(iugkp_handle *h, int faces)
     if (rc) return rc;
     const int nbe = cdiv(m.n_emit, iugkp::kTree);
     iugkp::newton_finish_kernel<<<dim3(nbe, 1), 256, 0, s>>>(h->d_inst, 0);
+  }
   }
   iugkp::finish_kernel<<<1, 256, 0, s>>>(h->d_inst, 0);
   HIP_TRY(hipGetLastError());
@@ -1076,7 +1177,8 @@ int iterate(iugkp_handle *h, int faces)
   if (ih.d.newton && sc.cg_status == -7)
     return fail(IUGKP_E_CG_NOT_CONVERGED, "CG did not converge within cg_max_iters");
   if (sc.flags & 1) return fail(IUGKP_E_NONFINITE, "non-finite energy");
-  if ((sc.flags & 2) || ((ih.d.newton || ih.d.Gs || K > 1) && sc.gsum > (1ull << 62)))
+  if ((sc.flags & 2) ||
+      ((ih.d.newton || ih.d.Gs || K > 1 || ih.d.persist) && sc.gsum > (1ull << 62)))
     return fail(IUGKP_E_FIXED_OVERFLOW, "emission energy exceeds the fixed-point budget");
   if (h->iter > 1 && h->res > 1e3) return fail(IUGKP_E_DIVERGED, "residual grew above 1e3");
   return IUGKP_OK;
@@ -1240,7 +1342,8 @@ int iugkp_get_tallies(iugkp_handle *h, int64_t *D, int64_t *W, int64_t *Phi_x, i
     const Mesh &m = d.m;
     const size_t o = static_cast<size_t>(b);
     if ((rc = copy_out(D ? D + o * m.n_cells : nullptr, d.D, m.n_cells * 8, k, s))) return rc;
-    if ((rc = copy_out(W ? W + o * m.n_cells : nullptr, d.has_null ? d.W : d.D, m.n_cells * 8, k, s)))
+    if ((rc = copy_out(W ? W + o * m.n_cells : nullptr, (d.has_null || d.persist) ? d.W : d.D,
+                       m.n_cells * 8, k, s)))
       return rc;
     if ((rc = copy_out(Phi_x ? Phi_x + o * m.n_fx : nullptr, d.Phix, m.n_fx * 8, k, s))) return rc;
     if (m.n_fy && (rc = copy_out(Phi_y ? Phi_y + o * m.n_fy : nullptr, d.Phiy, m.n_fy * 8, k, s)))
@@ -1259,6 +1362,13 @@ int iugkp_get_state(iugkp_handle *h, uint32_t *iter, double *d0, double *E, int6
   const Inst &d = h->ih.d;
   int rc;
   if ((rc = copy_out(E, d.E, d.m.n_cells * 8, h->ih.mem_kind, h->stream))) return rc;
+  if (d.persist) {
+    if ((rc = copy_out(G, d.wc, d.m.n_cells * 8, h->ih.mem_kind, h->stream))) return rc;
+    if ((rc = copy_out(G ? G + d.m.n_cells : nullptr, d.wb, d.m.n_b * 8, h->ih.mem_kind, h->stream)))
+      return rc;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return IUGKP_OK;
+  }
   for (int b = 0; b < h->bh.K; ++b)
     if ((rc = copy_out(G ? G + static_cast<size_t>(b) * d.m.n_emit : nullptr, band_of(h, b).d.G,
                        d.m.n_emit * 8, h->ih.mem_kind, h->stream)))
@@ -1270,6 +1380,8 @@ int iugkp_get_state(iugkp_handle *h, uint32_t *iter, double *d0, double *E, int6
 int iugkp_set_state(iugkp_handle *h, uint32_t iter, double d0, const double *E, const int64_t *G)
 {
   if (!h || !E || !G) return fail(IUGKP_E_INVALID_ARG, "bad arguments");
+  if (h->ih.d.persist)
+    return fail(IUGKP_E_INVALID_ARG, "the state of the persistent scheme is its population");
   const Inst &d = h->ih.d;
   const Mesh &m = d.m;
   const size_t ng = static_cast<size_t>(m.n_emit) * h->bh.K;
@@ -1318,6 +1430,60 @@ int iugkp_get_stats(iugkp_handle *h, iugkp_stats *stats)
   return IUGKP_OK;
 }
 
+int iugkp_get_particles(iugkp_handle *h, double *x, double *y, double *sx, double *sy, int64_t *q,
+                        int32_t *kind, int32_t *loc)
+{
+  if (!h) return fail(IUGKP_E_INVALID_ARG, "handle is NULL");
+  const Inst &d = h->ih.d;
+  if (!d.persist) return fail(IUGKP_E_INVALID_ARG, "no persistent population (emitter scheme)");
+  const int k = h->ih.mem_kind;
+  hipStream_t s = h->stream;
+  const size_t n = d.n_part;
+  int rc;
+  if ((rc = copy_out(x, d.px, n * 8, k, s))) return rc;
+  if ((rc = copy_out(y, d.py, n * 8, k, s))) return rc;
+  if ((rc = copy_out(sx, d.psx, n * 8, k, s))) return rc;
+  if ((rc = copy_out(sy, d.psy, n * 8, k, s))) return rc;
+  if ((rc = copy_out(q, d.pq, n * 8, k, s))) return rc;
+  if (kind || loc) {
+    DevScratch tmp(s);
+    int32_t *dk = nullptr, *dl = nullptr;
+    if (kind) dk = (k == IUGKP_MEM_DEVICE) ? kind : tmp.get<int32_t>(n);
+    if (loc) dl = (k == IUGKP_MEM_DEVICE) ? loc : tmp.get<int32_t>(n);
+    if ((kind && !dk) || (loc && !dl)) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
+    iugkp::persist_unpack_kernel<<<cdiv(static_cast<long long>(n), 256), 256, 0, s>>>(
+        d.plk, static_cast<unsigned int>(n), dk, dl);
+    HIP_TRY(hipGetLastError());
+    if (k == IUGKP_MEM_HOST) {
+      if (kind) HIP_TRY(hipMemcpyAsync(kind, dk, n * 4, hipMemcpyDeviceToHost, s));
+      if (loc) HIP_TRY(hipMemcpyAsync(loc, dl, n * 4, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return IUGKP_OK;
+}
+
+int iugkp_get_shares(iugkp_handle *h, uint32_t *n_rc, uint32_t *n_b, int64_t *w_c, int64_t *r_c,
+                     int64_t *w_b, int64_t *r_b)
+{
+  if (!h) return fail(IUGKP_E_INVALID_ARG, "handle is NULL");
+  const Inst &d = h->ih.d;
+  if (!d.persist) return fail(IUGKP_E_INVALID_ARG, "no persistent population (emitter scheme)");
+  const int k = h->ih.mem_kind;
+  hipStream_t s = h->stream;
+  const size_t nc = d.m.n_cells, nb = d.m.n_b;
+  int rc;
+  if ((rc = copy_out(n_rc, d.Nrc, nc * 4, k, s))) return rc;
+  if ((rc = copy_out(n_b, d.Nb, nb * 4, k, s))) return rc;
+  if ((rc = copy_out(w_c, d.wc, nc * 8, k, s))) return rc;
+  if ((rc = copy_out(r_c, d.rc, nc * 8, k, s))) return rc;
+  if ((rc = copy_out(w_b, d.wb, nb * 8, k, s))) return rc;
+  if ((rc = copy_out(r_b, d.rb, nb * 8, k, s))) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  return IUGKP_OK;
+}
+
 int iugkp_adjoint(iugkp_handle *h, const double *dLdT, double *grad_wall, double *grad_source,
                   int max_iters, double tol, int *iters_out)
 {
@@ -1325,6 +1491,7 @@ int iugkp_adjoint(iugkp_handle *h, const double *dLdT, double *grad_wall, double
   if (!h || !dLdT || max_iters < 1 || !(tol >= 0.0))
     return fail(IUGKP_E_INVALID_ARG, "bad adjoint arguments");
   if (h->bh.K > 1) return fail(IUGKP_E_INVALID_ARG, "the adjoint covers gray problems only");
+  if (h->ih.d.persist) return fail(IUGKP_E_INVALID_ARG, "the adjoint covers the emitter scheme only");
   InstHost &ih = h->ih;
   const Inst &d = ih.d;
   const Mesh &m = d.m;

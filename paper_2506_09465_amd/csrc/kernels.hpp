@@ -74,6 +74,17 @@ struct Inst {
   uint32_t e_off;               // emitter offset in the Philox counter (frequency band k: k (nc + nb))
   int n_bands;                  // > 1: the coordinating instance of a multi-band problem
   unsigned long long wall_budget;   // saturating sum of |G| over the wall emitters
+  // persistent particles (one population kept between iterations)
+  int persist;
+  unsigned int n_part;          // population: N per cell, then N per wall face
+  double *px, *py, *psx, *psy;  // position, direction
+  long long *pq;                // weight
+  uint32_t *plk;                // location | kind << 30 (kind 0 null, 1 real, 2 wall)
+  uint32_t *Nrc, *Nb;           // real collisions per cell, absorptions per wall face
+  long long *wc, *rc, *wb, *rb; // next weights and carried remainders (cells, wall faces)
+  const long long *Gw;          // wall emission per iteration
+  unsigned long long *npart;    // per move workgroup: saturating sum of |q| over null particles
+  int n_npart, n_gpart;
   DevScalars *sc;
 };
 
@@ -1018,6 +1029,11 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
       g += in.gpart[i];
       if (g > kBudgetCap) g = kBudgetCap;
     }
+  } else if (in.persist) {
+    for (int i = 0; i < in.n_gpart; ++i) {
+      g += in.gpart[i];
+      if (g > kBudgetCap) g = kBudgetCap;
+    }
   } else if (in.Gs || in.n_bands > 1) {
     g = in.wall_budget;
     for (int i = 0; i < nbc; ++i) {
@@ -1045,7 +1061,8 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
   else if (in.newton && sc->cg_status == -6) err = kErrBreakdown;
   else if (in.newton && sc->cg_status == -7) err = kErrCgNotConverged;
   else if (sc->flags & 1) err = kErrNonfinite;
-  else if ((sc->flags & 2) || ((in.newton || in.Gs || in.n_bands > 1) && g > (1ull << 62)))
+  else if ((sc->flags & 2) ||
+           ((in.newton || in.Gs || in.n_bands > 1 || in.persist) && g > (1ull << 62)))
     err = kErrOverflow;
   else if (sc->iter > 1 && res > 1e3) err = kErrDiverged;
   sc->acc_mode = 0;
@@ -1981,6 +1998,353 @@ __global__ void bands_output_kernel(int n_cells, int n_fx, int n_fy, int F, doub
     for (int k = 0; k < K; ++k) v = v + ldexp(static_cast<double>(phiy[k][i]), -F) / bands[k].ts;
     qy[i] = faces ? v / ay : 0.0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent particles: the variable-tau iteration of Sec. 3.2, steps (1)-(6),
+// with a fixed population.  Every iteration each particle flies one
+// candidate path on the common time scale: real-collision particles are first
+// resampled from their cell's equilibrium (uniform point, isotropic
+// direction, the cell's share w_c), particles absorbed by a wall face are
+// re-emitted from it (uniform point of the face, cosine law, the face's share
+// w_b), null particles move on unchanged.  Counter of particle p's draw d:
+// (d, p, kPersistStream, slot); creation uses slot kPersistCreate.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPersistStream = 0xFFFFFFFFu;
+constexpr uint32_t kPersistCreate = 0xFFFFFFFFu;
+constexpr uint32_t kLocMask = 0x3FFFFFFFu;
+
+__device__ __forceinline__ void iso_direction(int dim, double2 ucd, double &sx, double &sy)
+{
+  const double mu = 2.0 * ucd.x - 1.0;
+  sx = mu;
+  sy = (dim == 2) ? sqrt((1.0 - mu) * (1.0 + mu)) * cos2pi_own(ucd.y) : 0.0;
+}
+
+// a = w n + r, 0 <= r < n (n > 0)
+__device__ __forceinline__ void share_of(long long a, uint32_t n, long long &w, long long &r)
+{
+  const long long nn = static_cast<long long>(n);
+  long long b = a / nn;
+  if (a % nn != 0 && a < 0) b -= 1;
+  w = b;
+  r = a - b * nn;
+}
+
+__device__ __forceinline__ unsigned long long abs_u64(long long v)
+{
+  return v < 0 ? 0ull - static_cast<unsigned long long>(v) : static_cast<unsigned long long>(v);
+}
+
+// Creation: particle c N + k of cell c (uniform point, isotropic direction,
+// the k-th part of the cell's energy G0[c] split over N), then N per wall face
+// waiting for re-emission.
+__global__ void persist_init_kernel(const Inst *__restrict__ insts, const long long *__restrict__ G0)
+{
+  const Inst &in = insts[0];
+  const Mesh &m = in.m;
+  const unsigned int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= in.n_part) return;
+  const unsigned int N = in.N;
+  const unsigned int cells = static_cast<unsigned int>(m.n_cells) * N;
+  if (p < cells) {
+    const unsigned int c = p / N, k = p - c * N;
+    const int iy = static_cast<int>(c) / m.nx, ix = static_cast<int>(c) - iy * m.nx;
+    const double2 uab = draw2(0u, p, kPersistStream, kPersistCreate, in.key0, in.key1);
+    const double2 ucd = draw2(1u, p, kPersistStream, kPersistCreate, in.key0, in.key1);
+    in.px[p] = (static_cast<double>(ix) + uab.x) * m.dx;
+    in.py[p] = (static_cast<double>(iy) + uab.y) * m.dy;
+    double sx, sy;
+    iso_direction(m.dim, ucd, sx, sy);
+    in.psx[p] = sx;
+    in.psy[p] = sy;
+    long long w, r;
+    share_of(G0[c], N, w, r);
+    in.pq[p] = w + ((static_cast<long long>(k) < r) ? 1 : 0);
+    in.plk[p] = c;
+  } else {
+    const unsigned int b = (p - cells) / N;
+    in.px[p] = 0.0;
+    in.py[p] = 0.0;
+    in.psx[p] = 0.0;
+    in.psy[p] = 0.0;
+    in.pq[p] = 0;
+    in.plk[p] = b | (2u << 30);
+  }
+}
+
+__global__ void persist_prepare_kernel(const Inst *__restrict__ insts)
+{
+  const Inst &in = insts[0];
+  const Mesh &m = in.m;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    in.sc->flights = 0;
+    in.sc->segments = 0;
+    in.sc->crossings = 0;
+    in.sc->gsum = 0;
+    in.sc->flags = 0;
+  }
+  if (i < m.n_cells) {
+    in.W[i] = 0;
+    in.D[i] = 0;
+    in.Nrc[i] = 0;
+  }
+  if (i < m.n_b) {
+    in.B[i] = 0;
+    in.Nb[i] = 0;
+  }
+  if (i < m.n_fx) in.Phix[i] = 0;
+  if (i < m.n_fy) in.Phiy[i] = 0;
+}
+
+// One straight path of length ell from (x0, y0) in cell (ix, iy): the walk's
+// face rules (strict crossing, x first on ties, the first wall face absorbs),
+// each crossing tallied when faces are on; without face tallies a path
+// expected to cross more than kJumpMinFaces faces is resolved in closed form.
+// Returns true when absorbed by wall face bface.
+__device__ __forceinline__ bool persist_walk(const Mesh &m, double x0, double y0, int &ix, int &iy,
+                                             double sx, double sy, double ell, int faces,
+                                             long long q, long long *Phix, long long *Phiy,
+                                             int &bface, unsigned long long &n_cross)
+{
+  const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+  const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+  const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+  const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+  int kx = (stx > 0) ? ix + 1 : ix;
+  int ky = (sty > 0) ? iy + 1 : iy;
+  bface = -1;
+  if (!faces && ell * (fabs(sx) / m.dx + fabs(sy) / m.dy) > kJumpMinFaces) {
+    segment_jump(m, x0, y0, ix, iy, stx, sty, inv_sx, inv_sy, kx, ky, ell, bface, n_cross);
+    return bface >= 0;
+  }
+  for (;;) {
+    const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
+    const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
+    const bool along_x = tx <= ty;
+    const double tt = along_x ? tx : ty;
+    if (!(tt < ell)) return false;
+    ++n_cross;
+    if (along_x) {
+      if (faces) atom_add(&Phix[iy * (m.nx + 1) + kx], stx > 0 ? q : -q);
+      if (kx == 0 || kx == m.nx) {
+        bface = (kx == 0) ? iy : m.ny + iy;
+        return true;
+      }
+      ix += stx;
+      kx += stx;
+    } else {
+      if (faces) atom_add(&Phiy[ky * m.nx + ix], sty > 0 ? q : -q);
+      if (ky == 0 || ky == m.ny) {
+        bface = (ky == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
+        return true;
+      }
+      iy += sty;
+      ky += sty;
+    }
+  }
+}
+
+// The move: one thread per particle; tallies by global atomics (W, W^h, N_rc,
+// B, N_b, crossed faces); counters and the null particles' |q| sum per
+// workgroup.
+template <int BS>
+__global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict__ insts, int faces)
+{
+  __shared__ unsigned long long s_red[3][BS / 64];
+  const Inst &in = insts[0];
+  const Mesh &m = in.m;
+  const uint32_t slot = in.crn ? in.epoch : in.sc->iter;
+  const unsigned int p = blockIdx.x * BS + threadIdx.x;
+  unsigned long long fl = 0, cr = 0, nul = 0;
+  if (p < in.n_part) {
+    const uint32_t lk = in.plk[p];
+    const uint32_t kind = lk >> 30, loc = lk & kLocMask;
+    double x, y, sx, sy;
+    long long q;
+    int ix, iy;
+    if (kind == 1) {
+      const double2 uab = draw2(0u, p, kPersistStream, slot, in.key0, in.key1);
+      const double2 ucd = draw2(1u, p, kPersistStream, slot, in.key0, in.key1);
+      iy = static_cast<int>(loc) / m.nx;
+      ix = static_cast<int>(loc) - iy * m.nx;
+      x = (static_cast<double>(ix) + uab.x) * m.dx;
+      y = (static_cast<double>(iy) + uab.y) * m.dy;
+      iso_direction(m.dim, ucd, sx, sy);
+      q = in.wc[loc];
+    } else if (kind == 2) {
+      const int b = static_cast<int>(loc);
+      const double2 uab = draw2(0u, p, kPersistStream, slot, in.key0, in.key1);
+      const double2 ucd = draw2(1u, p, kPersistStream, slot, in.key0, in.key1);
+      const double cn = sqrt(ucd.x);
+      const double tg = (m.dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * cos2pi_own(ucd.y) : 0.0;
+      q = in.wb[b];
+      if (b < m.ny) {
+        ix = 0; iy = b;
+        x = 0.0; y = (static_cast<double>(iy) + uab.x) * m.dy;
+        sx = cn; sy = tg;
+        if (faces) atom_add(&in.Phix[iy * (m.nx + 1)], q);
+      } else if (b < 2 * m.ny) {
+        ix = m.nx - 1; iy = b - m.ny;
+        x = static_cast<double>(m.nx) * m.dx; y = (static_cast<double>(iy) + uab.x) * m.dy;
+        sx = -cn; sy = tg;
+        if (faces) atom_add(&in.Phix[iy * (m.nx + 1) + m.nx], -q);
+      } else if (b < 2 * m.ny + m.nx) {
+        ix = b - 2 * m.ny; iy = 0;
+        x = (static_cast<double>(ix) + uab.x) * m.dx; y = 0.0;
+        sx = tg; sy = cn;
+        if (faces) atom_add(&in.Phiy[ix], q);
+      } else {
+        ix = b - 2 * m.ny - m.nx; iy = m.ny - 1;
+        x = (static_cast<double>(ix) + uab.x) * m.dx; y = static_cast<double>(m.ny) * m.dy;
+        sx = tg; sy = -cn;
+        if (faces) atom_add(&in.Phiy[m.ny * m.nx + ix], -q);
+      }
+    } else {
+      iy = static_cast<int>(loc) / m.nx;
+      ix = static_cast<int>(loc) - iy * m.nx;
+      x = in.px[p];
+      y = in.py[p];
+      sx = in.psx[p];
+      sy = in.psy[p];
+      q = in.pq[p];
+    }
+    if (q != 0) fl = 1;
+    const double2 us = draw2(2u, p, kPersistStream, slot, in.key0, in.key1);
+    const double ell = -(in.lam_min * log_own(1.0 - us.x));
+    int bface;
+    uint32_t nlk;
+    if (persist_walk(m, x, y, ix, iy, sx, sy, ell, faces, q, in.Phix, in.Phiy, bface, cr)) {
+      atom_add(&in.B[bface], q);
+      atomicAdd(&in.Nb[bface], 1u);
+      nlk = static_cast<uint32_t>(bface) | (2u << 30);
+    } else {
+      const int c = ix + m.nx * iy;
+      atom_add(&in.W[c], q);
+      x = clamp_to(x + ell * sx, static_cast<double>(ix) * m.dx, static_cast<double>(ix + 1) * m.dx);
+      if (m.dim == 2)
+        y = clamp_to(y + ell * sy, static_cast<double>(iy) * m.dy, static_cast<double>(iy + 1) * m.dy);
+      if (us.y < in.ratio[c]) {
+        atom_add(&in.D[c], q);
+        atomicAdd(&in.Nrc[c], 1u);
+        nlk = static_cast<uint32_t>(c) | (1u << 30);
+      } else {
+        nul = abs_u64(q);
+        nlk = static_cast<uint32_t>(c);
+      }
+    }
+    in.px[p] = x;
+    in.py[p] = y;
+    in.psx[p] = sx;
+    in.psy[p] = sy;
+    in.pq[p] = q;
+    in.plk[p] = nlk;
+  }
+  // per-wave sums (each |q| <= 2^62 and 64 of them fit in 2^68: cap first)
+  if (nul > kBudgetCap) nul = kBudgetCap;
+#pragma unroll
+  for (int st = 32; st >= 1; st >>= 1) {
+    fl += __shfl_down(fl, st, 64);
+    cr += __shfl_down(cr, st, 64);
+    const unsigned long long o = __shfl_down(nul, st, 64);
+    nul = (nul + o > kBudgetCap) ? kBudgetCap : nul + o;
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_red[0][wv] = fl;
+    s_red[1][wv] = cr;
+    s_red[2][wv] = nul;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long f = 0, c = 0, n = 0;
+    for (int i = 0; i < BS / 64; ++i) {
+      f += s_red[0][i];
+      c += s_red[1][i];
+      n = (n + s_red[2][i] > kBudgetCap) ? kBudgetCap : n + s_red[2][i];
+    }
+    if (f) atomicAdd(&in.sc->flights, f);
+    atomicAdd(&in.sc->segments, static_cast<unsigned long long>(
+                                    min(static_cast<unsigned int>(BS), in.n_part - blockIdx.x * BS)));
+    if (c) atomicAdd(&in.sc->crossings, c);
+    in.npart[blockIdx.x] = n;
+  }
+}
+
+// E = W / V, the residual partials, and the shares of the next iteration:
+// blocks [0, nbc) cells, then the wall faces, then one block that folds the
+// move's null partials; |q| budget partials into gpart.
+__global__ __launch_bounds__(256) void persist_update_kernel(const Inst *__restrict__ insts)
+{
+  __shared__ double lds[kTree];
+  __shared__ unsigned long long lg[kTree];
+  const Inst &in = insts[0];
+  const int nc = in.m.n_cells, nb = in.m.n_b;
+  const int nbc = (nc + kTree - 1) / kTree, nbw = (nb + kTree - 1) / kTree;
+  const int t = threadIdx.x;
+  double sq = 0.0;
+  unsigned long long ag = 0;
+  int flags = 0;
+  if (static_cast<int>(blockIdx.x) < nbc) {
+    const int c = blockIdx.x * kTree + t;
+    if (c < nc) {
+      const double En = ldexp(static_cast<double>(in.W[c]), -in.F) / in.V;
+      const double d = En - in.E[c];
+      sq = d * d;
+      if (!isfinite(En)) flags |= 1;
+      in.E[c] = En;
+      int over = 0;
+      const long long avail =
+          add_budget(add_budget(in.D[c], in.Gs ? in.Gs[c] : 0ll, &over), in.rc[c], &over);
+      if (over) flags |= 2;
+      const uint32_t n = in.Nrc[c];
+      long long w = 0, r = avail;
+      if (n) share_of(avail, n, w, r);
+      in.wc[c] = w;
+      in.rc[c] = r;
+      ag = abs_u64(w) * n + abs_u64(r);
+    }
+  } else if (static_cast<int>(blockIdx.x) < nbc + nbw) {
+    const int b = (blockIdx.x - nbc) * kTree + t;
+    if (b < nb) {
+      int over = 0;
+      const long long avail = add_budget(in.Gw[b], in.rb[b], &over);
+      if (over) flags |= 2;
+      const uint32_t n = in.Nb[b];
+      long long w = 0, r = avail;
+      if (n) share_of(avail, n, w, r);
+      in.wb[b] = w;
+      in.rb[b] = r;
+      ag = abs_u64(w) * n + abs_u64(r);
+    }
+  } else {
+    for (int i = t; i < in.n_npart; i += kTree) ag = (ag + in.npart[i] > kBudgetCap) ? kBudgetCap : ag + in.npart[i];
+  }
+  if (flags) atomicOr(&in.sc->flags, flags);
+  const double s = block_tree256(sq, lds);
+  lg[t] = ag > kBudgetCap ? kBudgetCap : ag;
+  __syncthreads();
+  for (int st = kTree / 2; st >= 1; st >>= 1) {
+    if (t < st) {
+      const unsigned long long u = lg[t] + lg[t + st];
+      lg[t] = u > kBudgetCap ? kBudgetCap : u;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (static_cast<int>(blockIdx.x) < nbc) in.part[blockIdx.x] = s;
+    in.gpart[blockIdx.x] = lg[0];
+  }
+}
+
+// Unpack location | kind << 30.
+__global__ void persist_unpack_kernel(const uint32_t *lk, unsigned int n, int32_t *kind, int32_t *loc)
+{
+  const unsigned int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (kind) kind[i] = static_cast<int32_t>(lk[i] >> 30);
+  if (loc) loc[i] = static_cast<int32_t>(lk[i] & kLocMask);
 }
 
 // zero a small integer array (used instead of a memset node so the sequence can

@@ -37,7 +37,7 @@ class _Marshal:
 
     def __init__(self, w, device, *, seed, particles, rng_mode, epoch, max_iters, res_tol,
                  newton, diff_x, diff_y, cg_tol, cg_max_iters, tally_faces, avg_iters,
-                 block_size, march=0, cg_waves=0, T_init=None):
+                 block_size, march=0, cg_waves=0, scheme=0, T_init=None):
         self.tau = _dev_f64(w.tau, device)
         self.wall = _dev_f64(w.wall_T, device)
         Ti = T_init if T_init is not None else getattr(w, "T_init", None)
@@ -56,7 +56,8 @@ class _Marshal:
         self.options = L.Options(int(seed), int(particles), int(rng_mode), int(epoch),
                                  int(max_iters), float(res_tol), int(bool(newton)),
                                  float(cg_tol), int(cg_max_iters), int(tally_faces),
-                                 int(avg_iters), int(block_size), int(march), int(cg_waves))
+                                 int(avg_iters), int(block_size), int(march), int(cg_waves),
+                                 int(scheme))
 
 
 def _defaults(w, kw):
@@ -72,6 +73,7 @@ def _defaults(w, kw):
                 tally_faces=kw.pop("tally_faces", L.FACES_EVERY),
                 avg_iters=kw.pop("avg_iters", 0), block_size=kw.pop("block_size", 0),
                 march=kw.pop("march", 0), cg_waves=kw.pop("cg_waves", 0),
+                scheme=kw.pop("scheme", 0),
                 T_init=kw.pop("T_init", None))
 
 
@@ -160,6 +162,34 @@ class Solver:
         G = torch.as_tensor(G).to(device=self.device, dtype=torch.int64).contiguous()
         with torch.cuda.device(self.device):
             return L.lib().iugkp_set_state(self.h, int(it), float(d0), E.data_ptr(), G.data_ptr())
+
+    def particles(self):
+        """Persistent population (scheme 1): x, y, sx, sy, q, kind, loc."""
+        st = self.stats()
+        n = int(st["n_per_emitter"]) * self.ne
+        f = lambda: torch.empty(n, dtype=torch.float64, device=self.device)
+        x, y, sx, sy = f(), f(), f(), f()
+        q = torch.empty(n, dtype=torch.int64, device=self.device)
+        kind = torch.empty(n, dtype=torch.int32, device=self.device)
+        loc = torch.empty(n, dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().iugkp_get_particles(self.h, x.data_ptr(), y.data_ptr(), sx.data_ptr(),
+                                                sy.data_ptr(), q.data_ptr(), kind.data_ptr(),
+                                                loc.data_ptr()), "iugkp_get_particles")
+        return {"x": x, "y": y, "sx": sx, "sy": sy, "q": q, "kind": kind, "loc": loc}
+
+    def shares(self):
+        """Persistent population: N_rc, N_b of the last iteration, next shares and
+        carried remainders (w_c, r_c per cell, w_b, r_b per wall face)."""
+        u = lambda n: torch.empty(n, dtype=torch.int32, device=self.device)
+        i = lambda n: torch.empty(n, dtype=torch.int64, device=self.device)
+        d = {"Nrc": u(self.nc), "Nb": u(self.nb), "wc": i(self.nc), "rc": i(self.nc),
+             "wb": i(self.nb), "rb": i(self.nb)}
+        with torch.cuda.device(self.device):
+            L.check(L.lib().iugkp_get_shares(self.h, *[d[k].data_ptr() for k in
+                                                       ("Nrc", "Nb", "wc", "rc", "wb", "rb")]),
+                    "iugkp_get_shares")
+        return d
 
     def adjoint(self, dLdT, max_iters: int = 200, tol: float = 1e-10):
         """Gradients of a loss L(T) of the steady state reached by this solver
