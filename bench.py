@@ -45,6 +45,10 @@ def parse():
                     help="instances of the batched vs sequential comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient timing")
     ap.add_argument("--no-nongray", action="store_true", help="skip the 40-band timing")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the persistent-particle timing")
+    ap.add_argument("--persistent-only", action="store_true",
+                    help="only the persistent-particle timing (its own JSON line; for profiling)")
     ap.add_argument("--nongray-only", action="store_true",
                     help="only the 40-band timing (printed as its own JSON line; for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -255,6 +259,66 @@ def bench_nongray(P, dev, steps, warmup):
     return out
 
 
+def persist_bytes(n, n_null, n_real, crossings):
+    """Algorithmic bytes of one persistent move: per particle its kind and
+    location (4 B), the state of a null particle (40 B) or the share of a
+    resampled one (8 B), the new state (44 B), the W tally (8 B) and for real
+    collisions the W^h tally (8 B); 8 B per face crossing tallied."""
+    return 48 * n + 40 * n_null + 8 * (n - n_null) + 8 * n + 8 * n_real + 8 * crossings
+
+
+def bench_persistent(P, dev, steps, warmup=3):
+    """The persistent-particle scheme (Sec. 3.2 steps (1)-(6), fixed
+    population) on the 256 x 256 cavity at each Kn with 1e7 particles, face
+    tallies every iteration: particle moves per second and the move kernel's
+    roofline."""
+    import torch
+    from synth import cavity_2d
+    out = {"workload": "2D gray square cavity 256x256, hot top wall, Kn in {0.01,0.1,1,10}, "
+                       "persistent population of 1e7 particles, face tallies every iteration"}
+    tot_moves, tot_s, tot_ms, tot_bytes, launches = 0, 0.0, 0.0, 0, 0
+    for kn in KNS:
+        w = cavity_2d(n=N_SIDE, kn=kn, particles=PARTICLES, newton=False, seed=0)
+        s = P.Solver(w, device=dev, scheme=P.SCHEME_PERSISTENT, tally_faces=P.FACES_EVERY)
+        s.step(warmup)
+        n = s.stats()["segments"]
+        t_el, ms, byt, cr = 0.0, 0.0, 0, 0
+        for _ in range(steps):
+            sh = s.shares()
+            n_real0 = int(sh["Nrc"].sum())
+            n_wall0 = int(sh["Nb"].sum())
+            a = s.stats()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            assert s.step(1) == 0
+            torch.cuda.synchronize()
+            t_el += time.perf_counter() - t0
+            b = s.stats()
+            n_real1 = int(s.shares()["Nrc"].sum())
+            dcr = b["tot_crossings"] - a["tot_crossings"]
+            ms += b["ms_march"] - a["ms_march"]
+            byt += persist_bytes(n, n - n_real0 - n_wall0, n_real1, dcr)
+            cr += dcr
+        s.close()
+        out[str(kn)] = {"moves_per_s": n * steps / t_el, "ms_per_iteration": round(t_el / steps * 1e3, 3),
+                        "ms_move": round(ms / steps, 3), "crossings_per_move": round(cr / (n * steps), 3),
+                        "move_GBs_algorithmic": round(byt / (ms / 1e3) / 1e9, 1)}
+        tot_moves += n * steps
+        tot_s += t_el
+        tot_ms += ms
+        tot_bytes += byt
+        launches += steps
+    avg_ms = tot_ms / launches
+    ach = tot_bytes / launches / (avg_ms / 1e3) / 1e9
+    out["moves_per_s"] = tot_moves / tot_s
+    out["roofline"] = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(ach / HBM_PEAK_GBS, 5),
+                       "traffic": traffic_from_profiles("persist_move_kernel", source_hash()),
+                       "kernel": "persist_move_kernel", "avg_launch_ms": round(avg_ms, 4),
+                       "algorithmic_bytes_per_launch": int(tot_bytes / launches)}
+    return out
+
+
 def cpu_baseline_nongray():
     """The CPU oracle on a bounded sample of the 40-band problem: the same
     two-material 40-band workload on a 128 x 128 mesh with one particle per
@@ -306,6 +370,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.nongray_only:
         print(json.dumps(bench_nongray(P, dev, args.steps, 20)), flush=True)
+        return
+    if args.persistent_only:
+        print(json.dumps(bench_persistent(P, dev, args.steps)), flush=True)
         return
 
     solvers = []
@@ -409,6 +476,9 @@ def main():
 
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(P, dev)
+
+    if not args.no_persistent:
+        out["persistent"] = bench_persistent(P, dev, args.steps)
 
     if not args.no_nongray:
         out["nongray"] = bench_nongray(P, dev, args.steps, 20)

@@ -291,6 +291,8 @@ int setup_persistent(InstHost &ih, const std::vector<double> &T0, const std::vec
   PALLOC(d.wb, nb);
   PALLOC(d.rb, nb);
   PALLOC(d.npart, d.n_npart);
+  PALLOC(d.pstart, nc);
+  PALLOC(d.pein, nb);
   long long *dgw = nullptr, *dg0 = nullptr;
   PALLOC(dgw, nb);
   PALLOC(dg0, nc);
@@ -322,6 +324,12 @@ int setup_persistent(InstHost &ih, const std::vector<double> &T0, const std::vec
   HIP_TRY(hipMemcpyAsync(dg0, g0.data(), nc * sizeof(long long), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(d.wb, wb.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(d.rb, rb.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
+  // the first iteration starts every cell's particles and all N per wall face
+  std::vector<long long> ein(nb);
+  for (int b = 0; b < nb; ++b)
+    ein[b] = static_cast<long long>(static_cast<unsigned long long>(wb[b]) * d.N);
+  HIP_TRY(hipMemcpyAsync(d.pein, ein.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d.pstart, g0.data(), nc * sizeof(long long), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(d.wc, 0, nc * sizeof(long long), s));
   HIP_TRY(hipMemsetAsync(d.rc, 0, nc * sizeof(long long), s));
   HIP_TRY(hipMemsetAsync(d.Nrc, 0, nc * sizeof(uint32_t), s));
@@ -1112,6 +1120,7 @@ int iterate(iugkp_handle *h, int faces)
         <<<ih.d.n_npart, kPersistBlock, 0, s>>>(h->d_inst, faces);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(h->ev[1], s));
+    if (faces) iugkp::persist_reconstruct_x_kernel<<<cdiv(m.ny, 256), 256, 0, s>>>(h->d_inst);
     iugkp::persist_update_kernel<<<ih.d.n_gpart, 256, 0, s>>>(h->d_inst);
   } else {
   iugkp::prepare_kernel<<<dim3(cdiv(nprep, 256), K), 256, 0, s>>>(h->d_inst, faces, 0);

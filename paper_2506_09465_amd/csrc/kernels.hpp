@@ -83,6 +83,8 @@ struct Inst {
   uint32_t *Nrc, *Nb;           // real collisions per cell, absorptions per wall face
   long long *wc, *rc, *wb, *rb; // next weights and carried remainders (cells, wall faces)
   const long long *Gw;          // wall emission per iteration
+  long long *pstart;            // energy starting this iteration's paths in each cell
+  long long *pein;              // energy re-emitted this iteration by each wall face
   unsigned long long *npart;    // per move workgroup: saturating sum of |q| over null particles
   int n_npart, n_gpart;
   DevScalars *sc;
@@ -2036,6 +2038,32 @@ __device__ __forceinline__ unsigned long long abs_u64(long long v)
   return v < 0 ? 0ull - static_cast<unsigned long long>(v) : static_cast<unsigned long long>(v);
 }
 
+// Runs of equal consecutive keys in a 64-lane wavefront: head = first lane of
+// its run, run = run number (heads at or below the lane).  All lanes call.
+__device__ __forceinline__ void wave_runs(int key, int &head, int &run)
+{
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1, 64);
+  head = (lane == 0 || prev != key) ? 1 : 0;
+  const unsigned long long heads = __ballot(head);
+  run = __popcll(heads & ((2ull << lane) - 1ull));
+}
+
+// Sum of v over the lanes of the same run from this lane on (the head gets the
+// run's total); integer, so exact.  All lanes call.
+__device__ __forceinline__ long long run_sum(long long v, int run)
+{
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int st = 1; st < 64; st <<= 1) {
+    const long long u = __shfl_down(v, st, 64);
+    const int r = __shfl_down(run, st, 64);
+    if (lane + st < 64 && r == run)
+      v = static_cast<long long>(static_cast<unsigned long long>(v) + static_cast<unsigned long long>(u));
+  }
+  return v;
+}
+
 // Creation: particle c N + k of cell c (uniform point, isotropic direction,
 // the k-th part of the cell's energy G0[c] split over N), then N per wall face
 // waiting for re-emission.
@@ -2100,13 +2128,14 @@ __global__ void persist_prepare_kernel(const Inst *__restrict__ insts)
 
 // One straight path of length ell from (x0, y0) in cell (ix, iy): the walk's
 // face rules (strict crossing, x first on ties, the first wall face absorbs),
-// each crossing tallied when faces are on; without face tallies a path
-// expected to cross more than kJumpMinFaces faces is resolved in closed form.
-// Returns true when absorbed by wall face bface.
+// each y-face crossing tallied when faces are on (the x faces follow from the
+// per-cell balance afterwards); without face tallies a path expected to
+// cross more than kJumpMinFaces faces is resolved in closed form.  Returns
+// true when absorbed by wall face bface.
 __device__ __forceinline__ bool persist_walk(const Mesh &m, double x0, double y0, int &ix, int &iy,
                                              double sx, double sy, double ell, int faces,
-                                             long long q, long long *Phix, long long *Phiy,
-                                             int &bface, unsigned long long &n_cross)
+                                             long long q, long long *Phiy, int &bface,
+                                             unsigned long long &n_cross)
 {
   const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
   const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
@@ -2127,7 +2156,6 @@ __device__ __forceinline__ bool persist_walk(const Mesh &m, double x0, double y0
     if (!(tt < ell)) return false;
     ++n_cross;
     if (along_x) {
-      if (faces) atom_add(&Phix[iy * (m.nx + 1) + kx], stx > 0 ? q : -q);
       if (kx == 0 || kx == m.nx) {
         bface = (kx == 0) ? iy : m.ny + iy;
         return true;
@@ -2158,6 +2186,8 @@ __global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict
   const uint32_t slot = in.crn ? in.epoch : in.sc->iter;
   const unsigned int p = blockIdx.x * BS + threadIdx.x;
   unsigned long long fl = 0, cr = 0, nul = 0;
+  int ckey = -1, wkey = -1, real = 0;   // end cell or wall face of this lane's path
+  long long qv = 0;
   if (p < in.n_part) {
     const uint32_t lk = in.plk[p];
     const uint32_t kind = lk >> 30, loc = lk & kLocMask;
@@ -2184,12 +2214,10 @@ __global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict
         ix = 0; iy = b;
         x = 0.0; y = (static_cast<double>(iy) + uab.x) * m.dy;
         sx = cn; sy = tg;
-        if (faces) atom_add(&in.Phix[iy * (m.nx + 1)], q);
       } else if (b < 2 * m.ny) {
         ix = m.nx - 1; iy = b - m.ny;
         x = static_cast<double>(m.nx) * m.dx; y = (static_cast<double>(iy) + uab.x) * m.dy;
         sx = -cn; sy = tg;
-        if (faces) atom_add(&in.Phix[iy * (m.nx + 1) + m.nx], -q);
       } else if (b < 2 * m.ny + m.nx) {
         ix = b - 2 * m.ny; iy = 0;
         x = (static_cast<double>(ix) + uab.x) * m.dx; y = 0.0;
@@ -2215,31 +2243,53 @@ __global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict
     const double ell = -(in.lam_min * log_own(1.0 - us.x));
     int bface;
     uint32_t nlk;
-    if (persist_walk(m, x, y, ix, iy, sx, sy, ell, faces, q, in.Phix, in.Phiy, bface, cr)) {
-      atom_add(&in.B[bface], q);
-      atomicAdd(&in.Nb[bface], 1u);
+    if (persist_walk(m, x, y, ix, iy, sx, sy, ell, faces, q, in.Phiy, bface, cr)) {
+      wkey = bface;
       nlk = static_cast<uint32_t>(bface) | (2u << 30);
     } else {
       const int c = ix + m.nx * iy;
-      atom_add(&in.W[c], q);
+      ckey = c;
       x = clamp_to(x + ell * sx, static_cast<double>(ix) * m.dx, static_cast<double>(ix + 1) * m.dx);
       if (m.dim == 2)
         y = clamp_to(y + ell * sy, static_cast<double>(iy) * m.dy, static_cast<double>(iy + 1) * m.dy);
       if (us.y < in.ratio[c]) {
-        atom_add(&in.D[c], q);
-        atomicAdd(&in.Nrc[c], 1u);
+        real = 1;
         nlk = static_cast<uint32_t>(c) | (1u << 30);
       } else {
         nul = abs_u64(q);
         nlk = static_cast<uint32_t>(c);
       }
     }
+    qv = q;
     in.px[p] = x;
     in.py[p] = y;
     in.psx[p] = sx;
     in.psy[p] = sy;
     in.pq[p] = q;
     in.plk[p] = nlk;
+  }
+  // end tallies, summed over runs of equal consecutive keys in the wavefront
+  // first (particles of neighbouring indices tend to end in the same cell)
+  {
+    int head, run;
+    wave_runs(ckey, head, run);
+    const long long sw = run_sum(qv, run);
+    const long long sh = run_sum(real ? qv : 0ll, run);
+    const long long sn = run_sum(static_cast<long long>(real), run);
+    if (head && ckey >= 0) {
+      atom_add(&in.W[ckey], sw);
+      if (sn) {
+        atom_add(&in.D[ckey], sh);
+        atomicAdd(&in.Nrc[ckey], static_cast<uint32_t>(sn));
+      }
+    }
+    wave_runs(wkey, head, run);
+    const long long sb = run_sum(wkey >= 0 ? qv : 0ll, run);
+    const long long sc = run_sum(wkey >= 0 ? 1ll : 0ll, run);
+    if (head && wkey >= 0) {
+      atom_add(&in.B[wkey], sb);
+      atomicAdd(&in.Nb[wkey], static_cast<uint32_t>(sc));
+    }
   }
   // per-wave sums (each |q| <= 2^62 and 64 of them fit in 2^68: cap first)
   if (nul > kBudgetCap) nul = kBudgetCap;
@@ -2304,6 +2354,11 @@ __global__ __launch_bounds__(256) void persist_update_kernel(const Inst *__restr
       in.wc[c] = w;
       in.rc[c] = r;
       ag = abs_u64(w) * n + abs_u64(r);
+      // the next iteration's paths start from this cell with the null
+      // particles' weights and the real ones' new share
+      in.pstart[c] = static_cast<long long>(static_cast<unsigned long long>(in.W[c]) -
+                                            static_cast<unsigned long long>(in.D[c]) +
+                                            static_cast<unsigned long long>(w) * n);
     }
   } else if (static_cast<int>(blockIdx.x) < nbc + nbw) {
     const int b = (blockIdx.x - nbc) * kTree + t;
@@ -2317,6 +2372,7 @@ __global__ __launch_bounds__(256) void persist_update_kernel(const Inst *__restr
       in.wb[b] = w;
       in.rb[b] = r;
       ag = abs_u64(w) * n + abs_u64(r);
+      in.pein[b] = static_cast<long long>(static_cast<unsigned long long>(w) * n);
     }
   } else {
     for (int i = t; i < in.n_npart; i += kTree) ag = (ag + in.npart[i] > kBudgetCap) ? kBudgetCap : ag + in.npart[i];
@@ -2335,6 +2391,31 @@ __global__ __launch_bounds__(256) void persist_update_kernel(const Inst *__restr
   if (t == 0) {
     if (static_cast<int>(blockIdx.x) < nbc) in.part[blockIdx.x] = s;
     in.gpart[blockIdx.x] = lg[0];
+  }
+}
+
+// x-face fluxes of a persistent iteration from the integer balance of every
+// cell, row by row: net inflow = (energy ending its path in the cell) -
+// (energy starting from it):
+//   Phix[j][0]   = (re-emitted by the left wall face j) - B_left[j]
+//   Phix[j][i+1] = Phix[j][i] + Phiy[j][i] - Phiy[j+1][i] - W[c] + start[c]
+// (arithmetic modulo 2^64, exact since every true value fits in int64).
+__global__ void persist_reconstruct_x_kernel(const Inst *__restrict__ insts)
+{
+  const Inst &in = insts[0];
+  const Mesh &m = in.m;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m.ny) return;
+  unsigned long long a = static_cast<unsigned long long>(in.pein[j]) -
+                         static_cast<unsigned long long>(in.B[j]);
+  in.Phix[j * (m.nx + 1)] = static_cast<long long>(a);
+  for (int i = 0; i < m.nx; ++i) {
+    const int c = j * m.nx + i;
+    if (m.dim == 2)
+      a += static_cast<unsigned long long>(in.Phiy[j * m.nx + i]) -
+           static_cast<unsigned long long>(in.Phiy[(j + 1) * m.nx + i]);
+    a += static_cast<unsigned long long>(in.pstart[c]) - static_cast<unsigned long long>(in.W[c]);
+    in.Phix[j * (m.nx + 1) + i + 1] = static_cast<long long>(a);
   }
 }
 
