@@ -131,6 +131,40 @@ double orc_log(double x)
 }
 
 /* ------------------------------------------------------------------------ */
+/* exp(-T), T >= 0, from + - * / and exact scaling: T = k ln2 + r with       */
+/* k = rint(T / ln2), r = (T - k ln2_hi) - k ln2_lo (Cody-Waite, ln2_hi with */
+/* trailing zero bits so k ln2_hi is exact), |r| <= ln2 / 2; exp(-r) by its  */
+/* Taylor polynomial to degree 14 in Horner form (truncation below 2^-60),   */
+/* scaled by 2^-k.  Returns 0 for T > 700 (far below any weight's unit).     */
+/* ------------------------------------------------------------------------ */
+double orc_expm(double T)
+{
+  const double ln2_hi = 6.93147180369123816490e-01;
+  const double ln2_lo = 1.90821492927058770002e-10;
+  const double inv_ln2 = 1.44269504088896338700e+00;
+  if (T > 700.0) return 0.0;
+  double kd = rint(T * inv_ln2);
+  double r = (T - kd * ln2_hi) - kd * ln2_lo;
+  double x = -r;
+  double p = 1.0 / 87178291200.0;          /* 1/14! */
+  p = p * x + 1.0 / 6227020800.0;
+  p = p * x + 1.0 / 479001600.0;
+  p = p * x + 1.0 / 39916800.0;
+  p = p * x + 1.0 / 3628800.0;
+  p = p * x + 1.0 / 362880.0;
+  p = p * x + 1.0 / 40320.0;
+  p = p * x + 1.0 / 5040.0;
+  p = p * x + 1.0 / 720.0;
+  p = p * x + 1.0 / 120.0;
+  p = p * x + 1.0 / 24.0;
+  p = p * x + 1.0 / 6.0;
+  p = p * x + 0.5;
+  p = p * x + 1.0;
+  p = p * x + 1.0;
+  return ldexp(p, -(int)kd);
+}
+
+/* ------------------------------------------------------------------------ */
 /* cos(2 pi u) for u in [0, 1): exact quarter-turn reduction t = 4u,         */
 /* q = floor(t), f = t - q, fold f > 1/2 to 1 - f, then Taylor polynomials   */
 /* of sin and cos on [0, pi/4] (to x^19 and x^18).                           */
@@ -207,6 +241,7 @@ void orc_math_batch(int op, const double *x, const double *y, double *out, uint6
         memcpy(&out[i], &v, 8);
         break;
       }
+      case 6: out[i] = orc_expm(x[i]); break;
       default: out[i] = 0.0;
     }
   }
@@ -351,6 +386,7 @@ struct orc_state {
   int64_t *G;          /* emission energies of the next iteration, per emitter */
   int64_t *D, *W, *Phix, *Phiy, *B;
   double *gx, *gy, *diag;
+  int has_null;        /* some tau_c > tau_min */
   uint32_t iter;
   double d0, res;
   double *res_hist;
@@ -569,7 +605,8 @@ int orc_create(const orc_problem *p, const orc_options *o, orc_state **out)
   int rc = orc_validate(p);
   if (rc) return rc;
   if (p->n_bands > 1) return ORC_E_INVALID_ARG;   /* bands: orc_bands_create */
-  if (!o || o->particles_per_iter < 1 || o->max_iters < 0 || o->avg_iters < 0)
+  if (!o || o->particles_per_iter < 1 || o->max_iters < 0 || o->avg_iters < 0 ||
+      (o->estimator != ORC_EST_ANALOG && o->estimator != ORC_EST_EXPECTED))
     return ORC_E_INVALID_ARG;
   if (o->newton && (!p->diff_x || (p->dim == 2 && !p->diff_y) || !(o->cg_tol > 0.0) ||
                     o->cg_max_iters < 1))
@@ -611,6 +648,7 @@ int orc_create(const orc_problem *p, const orc_options *o, orc_state **out)
   s->res_hist = (double *)calloc((size_t)s->res_cap, sizeof(double));
   for (int c = 0; c < s->nc; ++c) {
     s->ratio[c] = s->tau_min / s->tau[c];
+    if (s->ratio[c] != 1.0) s->has_null = 1;
     double T0 = p->T_init ? p->T_init[c] : p->t_ref;
     s->E[c] = p->cv * (T0 - p->t_ref);
   }
@@ -719,11 +757,12 @@ typedef struct {
   double lam;
   const double *ratio;
   uint32_t e_off;
+  int has_null;          /* some tau_c > tau_min: W tallied apart from D */
 } orc_flyctx;
 
 static orc_flyctx orc_gray_ctx(const orc_state *s)
 {
-  orc_flyctx f = {&s->p, s->nc, s->o.seed, s->lam_min, s->ratio, 0u};
+  orc_flyctx f = {&s->p, s->nc, s->o.seed, s->lam_min, s->ratio, 0u, s->has_null};
   return f;
 }
 
@@ -799,6 +838,118 @@ static void orc_fly(const orc_flyctx *f, uint32_t slot, int e, uint32_t k, int64
   }
 }
 
+/* Expected-value flight of particle k of emitter e carrying q (variance
+ * reduction; the expectation of the analog flight above).  Same start and
+ * direction; no free path is drawn.  The ray is followed cell by cell; with
+ * optical depth T(s) = sum of chord * tau_min / (lambda_min tau_c) the
+ * rounded surviving weight is S(T) = rint(q exp(-T)).  A cell's chord from
+ * depth T_a to T_b deposits D += S(T_a) - S(T_b) (the real collisions, exactly
+ * conserved) and, with null collisions, the expected candidates
+ * W += rint(q (exp(-T_a) - exp(-T_b)) / ratio_c) (W = D without them); a
+ * crossed face carries S at the face, a wall face absorbs it.  The ray ends
+ * at the first face where S has reached 0, and a ray with no direction
+ * leaves all of q in its cell. */
+static void orc_fly_expected(const orc_flyctx *f, uint32_t slot, int e, uint32_t k, int64_t q,
+                             orc_tally *t, uint64_t *segs)
+{
+  const orc_problem *p = f->p;
+  int nx = p->nx, ny = p->ny;
+  uint32_t ec = (uint32_t)e + f->e_off;
+  double ua, ub, uc, ud;
+  orc_draw(f->seed, slot, ec, k, 0u, &ua, &ub);
+  orc_draw(f->seed, slot, ec, k, 1u, &uc, &ud);
+  int ix, iy;
+  double x0, y0, sx, sy;
+  if (e < f->nc) {
+    ix = e % nx;
+    iy = e / nx;
+    x0 = ((double)ix + ua) * p->dx;
+    y0 = ((double)iy + ub) * p->dy;
+    double mu = 2.0 * uc - 1.0;
+    sx = mu;
+    sy = (p->dim == 2) ? sqrt((1.0 - mu) * (1.0 + mu)) * orc_cos2pi(ud) : 0.0;
+  } else {
+    int b = e - f->nc;
+    double cn = sqrt(uc);
+    double tg = (p->dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * orc_cos2pi(ud) : 0.0;
+    if (b < ny) {
+      ix = 0; iy = b;
+      x0 = 0.0; y0 = ((double)iy + ua) * p->dy;
+      sx = cn; sy = tg;
+    } else if (b < 2 * ny) {
+      ix = nx - 1; iy = b - ny;
+      x0 = (double)nx * p->dx; y0 = ((double)iy + ua) * p->dy;
+      sx = -cn; sy = tg;
+    } else if (b < 2 * ny + nx) {
+      ix = b - 2 * ny; iy = 0;
+      x0 = ((double)ix + ua) * p->dx; y0 = 0.0;
+      sx = tg; sy = cn;
+    } else {
+      ix = b - 2 * ny - nx; iy = ny - 1;
+      x0 = ((double)ix + ua) * p->dx; y0 = (double)ny * p->dy;
+      sx = tg; sy = -cn;
+    }
+  }
+  (*segs)++;
+  double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+  double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+  int stepx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+  int stepy = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+  int kx = (stepx > 0) ? ix + 1 : ix;
+  int ky = (stepy > 0) ? iy + 1 : iy;
+  double T = 0.0, surv = 1.0, tprev = 0.0;
+  int64_t S = q;
+  const double qd = (double)q;
+  for (;;) {
+    int c = ix + nx * iy;
+    double tx = stepx ? ((double)kx * p->dx - x0) * inv_sx : INFINITY;
+    double ty = stepy ? ((double)ky * p->dy - y0) * inv_sy : INFINITY;
+    int axis_x = (tx <= ty);
+    double tt = axis_x ? tx : ty;
+    if (!(tt < INFINITY)) {            /* no direction: everything stays here */
+      t->D[c] += S;
+      t->W[c] += f->has_null ? (int64_t)rint((qd * surv) / f->ratio[c]) : S;
+      t->end = c;
+      return;
+    }
+    double Tn = T + (tt - tprev) * (f->ratio[c] / f->lam);
+    double sn = orc_expm(Tn);
+    int64_t Sn = (int64_t)rint(qd * sn);
+    t->D[c] += S - Sn;
+    t->W[c] += f->has_null ? (int64_t)rint((qd * (surv - sn)) / f->ratio[c]) : S - Sn;
+    T = Tn;
+    surv = sn;
+    S = Sn;
+    tprev = tt;
+    if (S == 0) {
+      t->end = c;
+      return;
+    }
+    t->crossings++;
+    if (axis_x) {
+      if (t->faces) t->Phix[iy * (nx + 1) + kx] += (stepx > 0) ? S : -S;
+      if (kx == 0 || kx == nx) {
+        int b = (kx == 0) ? iy : ny + iy;
+        t->B[b] += S;
+        t->end = -1 - b;
+        return;
+      }
+      ix += stepx;
+      kx += stepx;
+    } else {
+      if (t->faces) t->Phiy[ky * nx + ix] += (stepy > 0) ? S : -S;
+      if (ky == 0 || ky == ny) {
+        int b = (ky == 0) ? 2 * ny + ix : 2 * ny + nx + ix;
+        t->B[b] += S;
+        t->end = -1 - b;
+        return;
+      }
+      iy += stepy;
+      ky += stepy;
+    }
+  }
+}
+
 int orc_trace_ray(const orc_problem *p, double x0, double y0, int ix, int iy, double sx,
                   double sy, double ell, int32_t *events, int max_events, int *end_kind,
                   int *end_cell)
@@ -848,7 +999,10 @@ static int orc_iterate(orc_state *s, int faces)
       int64_t q = orc_split_weight(s->G[e], s->N, k);
       if (q == 0) continue;
       flights++;
-      orc_fly(&fc, slot, e, (uint32_t)k, q, &t, &segs);
+      if (s->o.estimator == ORC_EST_EXPECTED)
+        orc_fly_expected(&fc, slot, e, (uint32_t)k, q, &t, &segs);
+      else
+        orc_fly(&fc, slot, e, (uint32_t)k, q, &t, &segs);
     }
   s->flights = flights;
   s->segments = segs;
@@ -1048,7 +1202,8 @@ int orc_adjoint(orc_state *s, const double *dLdT, double *grad_wall, double *gra
 {
   const orc_problem *p = &s->p;
   if (iters_out) *iters_out = 0;
-  if (s->o.rng_mode != ORC_RNG_CRN || max_iters < 1 || !(tol >= 0.0) || !dLdT)
+  if (s->o.rng_mode != ORC_RNG_CRN || s->o.estimator != ORC_EST_ANALOG || max_iters < 1 ||
+      !(tol >= 0.0) || !dLdT)
     return ORC_E_INVALID_ARG;
   for (int c = 0; c < s->nc; ++c)
     if (s->ratio[c] != 1.0 || !isfinite(dLdT[c])) return ORC_E_INVALID_ARG;
@@ -1183,7 +1338,8 @@ int orc_bands_create(const orc_problem *p, const orc_options *o, orc_bands **out
   if (!(p->dx > 0.0) || !(p->dy > 0.0) || !isfinite(p->dx) || !isfinite(p->dy) ||
       !isfinite(p->t_ref))
     return ORC_E_INVALID_ARG;
-  if (!o || o->particles_per_iter < 1 || o->max_iters < 0 || o->avg_iters != 0 || o->newton)
+  if (!o || o->particles_per_iter < 1 || o->max_iters < 0 || o->avg_iters != 0 || o->newton ||
+      o->estimator != ORC_EST_ANALOG)
     return ORC_E_INVALID_ARG;
   const int K = p->n_bands, nc = p->nx * p->ny, nb = orc_nb(p);
   for (int k = 0; k < K; ++k)
@@ -1537,7 +1693,7 @@ int orc_persist_create(const orc_problem *p, const orc_options *o, orc_persist *
   int rc = orc_validate(p);
   if (rc) return rc;
   if (p->n_bands > 1 || !o || o->particles_per_iter < 1 || o->max_iters < 0 ||
-      o->avg_iters < 0 || o->newton)
+      o->avg_iters < 0 || o->newton || o->estimator != ORC_EST_ANALOG)
     return ORC_E_INVALID_ARG;
   const int nc = p->nx * p->ny, nb = orc_nb(p);
   uint64_t N = o->particles_per_iter / (uint64_t)(nc + nb);

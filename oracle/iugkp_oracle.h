@@ -79,7 +79,11 @@ typedef struct orc_options {
   int cg_max_iters;
   int tally_faces;      /* ORC_FACES_* */
   int avg_iters;
+  int estimator;        /* ORC_EST_ANALOG: sampled collision points; ORC_EST_EXPECTED: the
+                           expected deposits along each ray (gray emitter scheme only) */
 } orc_options;
+
+enum { ORC_EST_ANALOG = 0, ORC_EST_EXPECTED = 1 };
 
 typedef struct orc_info {
   uint32_t iter;        /* iterations done */
@@ -100,9 +104,10 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 double orc_u53(uint32_t hi, uint32_t lo);
 double orc_log(double x);
 double orc_cos2pi(double u);
+double orc_expm(double T);   /* exp(-T) for T >= 0 from + - * / (0 beyond T = 700) */
 void orc_philox_batch(const uint32_t *ctr, uint64_t n, uint32_t k0, uint32_t k1, uint32_t *out);
 /* op: 0 log, 1 cos(2 pi x), 2 sqrt, 3 x / y, 4 (double) of the int64 bits of x,
- * 5 rint(ldexp(x, (int) y)) stored as int64 bits */
+ * 5 rint(ldexp(x, (int) y)) stored as int64 bits, 6 exp(-x) (orc_expm) */
 void orc_math_batch(int op, const double *x, const double *y, double *out, uint64_t n);
 int64_t orc_split_weight(int64_t G, uint64_t n, uint64_t k);
 double orc_tree_sum(const double *v, uint64_t n);

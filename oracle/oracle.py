@@ -22,6 +22,7 @@ GCC_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", 
 
 FRESH, CRN = 0, 1
 FACES_OFF, FACES_EVERY, FACES_FINAL = 0, 1, 2
+ANALOG, EXPECTED = 0, 1
 
 OK = 0
 W_NOT_CONVERGED = 1
@@ -55,7 +56,8 @@ class _Options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("particles_per_iter", C.c_uint64),
                 ("rng_mode", C.c_int), ("rng_epoch", C.c_uint32), ("max_iters", C.c_int),
                 ("res_tol", C.c_double), ("newton", C.c_int), ("cg_tol", C.c_double),
-                ("cg_max_iters", C.c_int), ("tally_faces", C.c_int), ("avg_iters", C.c_int)]
+                ("cg_max_iters", C.c_int), ("tally_faces", C.c_int), ("avg_iters", C.c_int),
+                ("estimator", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -83,6 +85,8 @@ def lib():
         L.orc_log.restype = C.c_double
         L.orc_cos2pi.argtypes = [C.c_double]
         L.orc_cos2pi.restype = C.c_double
+        L.orc_expm.argtypes = [C.c_double]
+        L.orc_expm.restype = C.c_double
         L.orc_philox_batch.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, P]
         L.orc_math_batch.argtypes = [C.c_int, P, P, P, C.c_uint64]
         L.orc_split_weight.argtypes = [C.c_int64, C.c_uint64, C.c_uint64]
@@ -171,6 +175,10 @@ def log(x: float) -> float:
 
 def cos2pi(u: float) -> float:
     return lib().orc_cos2pi(u)
+
+
+def expm(T: float) -> float:
+    return lib().orc_expm(T)
 
 
 def split_weight(G: int, n: int, k: int) -> int:
@@ -274,7 +282,7 @@ class Oracle:
     def __init__(self, w, *, seed=None, particles=None, rng_mode=FRESH, epoch=0,
                  max_iters=None, res_tol=None, newton=None, diff_x=None, diff_y=None,
                  cg_tol=None, cg_max_iters=200000, tally_faces=FACES_EVERY, avg_iters=0,
-                 T_init=None):
+                 T_init=None, estimator=0):
         self.w = w
         newton = w.newton if newton is None else newton
         self._keep = _Keep(w, diff_x, diff_y, T_init)
@@ -283,7 +291,7 @@ class Oracle:
                              rng_mode, epoch, w.max_iters if max_iters is None else max_iters,
                              w.res_tol if res_tol is None else res_tol, int(bool(newton)),
                              w.cg_tol if cg_tol is None else cg_tol, cg_max_iters, tally_faces,
-                             avg_iters)
+                             avg_iters, int(estimator))
         h = C.c_void_p()
         rc = lib().orc_create(C.byref(self._keep.p), C.byref(self.opts), C.byref(h))
         if rc != OK:

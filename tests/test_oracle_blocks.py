@@ -111,6 +111,32 @@ def test_cos2pi_accuracy_and_symmetry(oracle_mod):
     assert abs(oracle_mod.cos2pi(1.0 / 6.0) - 0.5) <= 2.3e-16
 
 
+def test_expm_accuracy(oracle_mod):
+    """exp(-T) built from + - * / and exact scaling: within 2 ulp of the long
+    double value over [0, 700], exact at 0, monotone, and zero beyond 700."""
+    rng = np.random.default_rng(5)
+    Ts = np.concatenate([rng.uniform(0.0, 1.0, 3000), rng.uniform(0.0, 50.0, 3000),
+                         rng.uniform(50.0, 700.0, 1000), np.arange(0, 60) * math.log(2.0),
+                         [1e-300, 1e-17, 0.34657359027997264, 0.3465735902799727]])
+    worst = 0.0
+    for T in Ts:
+        got = oracle_mod.expm(float(T))
+        ref = np.exp(-np.longdouble(T))
+        err = abs(np.longdouble(got) - ref) / np.longdouble(_ulp(float(ref)))
+        worst = max(worst, float(err))
+    assert worst <= 2.0
+    assert oracle_mod.expm(0.0) == 1.0
+    assert oracle_mod.expm(700.5) == 0.0 and oracle_mod.expm(1e6) == 0.0
+    g = sorted(rng.uniform(0.0, 40.0, 2000))
+    v = [oracle_mod.expm(float(t)) for t in g]
+    assert all(a >= b for a, b in zip(v, v[1:]))
+    # products: exp(-a) exp(-b) = exp(-(a + b)) to rounding (the rounded sum's
+    # error enters as a relative error of up to ulp(a + b))
+    for a_, b_ in rng.uniform(0.0, 20.0, (200, 2)):
+        lhs = oracle_mod.expm(a_) * oracle_mod.expm(b_)
+        assert abs(lhs - oracle_mod.expm(a_ + b_)) <= 4 * _ulp(lhs) + lhs * _ulp(a_ + b_)
+
+
 @pytest.mark.parametrize("G", [0, 1, 7, 149, 150, 151, -1, -7, -151, 10**17 + 3, -(10**17) - 5,
                                2**62 - 1, -(2**62) + 1])
 def test_split_weight_exact(oracle_mod, G):
