@@ -148,9 +148,23 @@ typedef struct iugkp_options {
                                    d uses the counter (d, p, 0xffffffff, slot), creation slot
                                    0xffffffff.  Gray single solves without the Newton step
                                    only.  Tallies: D = W^h (real collisions), W, faces, B */
+  int estimator;                /* IUGKP_EST_ANALOG (0): each particle ends at sampled
+                                   candidate points.  IUGKP_EST_EXPECTED (1, emitter scheme,
+                                   gray): variance reduction by the expected deposits along
+                                   each ray (the particle form of the CDF-weighted sum of
+                                   Sec. 2): no free path is drawn; with optical depth T along
+                                   the ray (T += chord tau_min / (lambda_min tau_c)) and the
+                                   rounded surviving weight S(T) = rint(q exp(-T)), a cell's
+                                   chord from T_a to T_b receives D += S(T_a) - S(T_b) (exactly
+                                   conserved) and, with null collisions, the expected
+                                   candidates W += rint(q (exp(-T_a) - exp(-T_b)) / ratio_c);
+                                   crossed faces carry S, a wall face absorbs it; the ray ends
+                                   where S reaches 0.  exp is the library's own (+ - * / and
+                                   exact scaling), bitwise reproducible */
 } iugkp_options;
 
 enum { IUGKP_SCHEME_EMITTERS = 0, IUGKP_SCHEME_PERSISTENT = 1 };
+enum { IUGKP_EST_ANALOG = 0, IUGKP_EST_EXPECTED = 1 };
 
 typedef struct iugkp_stats {
   int iters;                    /* iterations done since creation (or the restored state) */
@@ -307,7 +321,8 @@ int iugkp_dev_philox(const uint32_t *ctr, uint32_t key0, uint32_t key1, uint32_t
                      int64_t n, void *stream);
 /* iugkp_dev_math: op 0 = log(x), 1 = cos(2 pi x) for x in [0,1), 2 = sqrt(x),
  * 3 = x / y, 4 = (double) of the int64 bits of x, 5 = rint(ldexp(x, k)) as int64 bits
- * with k = (int)y; out[i] = op(x[i], y[i]). */
+ * with k = (int)y, 6 = exp(-x) for x >= 0 (the expected-value estimator's);
+ * out[i] = op(x[i], y[i]). */
 int iugkp_dev_math(int op, const double *x, const double *y, double *out, int64_t n,
                    void *stream);
 /* iugkp_dev_segments: the closed-form segment walk used when no face is tallied,

@@ -402,6 +402,7 @@ typedef struct {
   uint64_t crossings;
   int32_t *events;     /* optional crossing log */
   int n_events, max_events;
+  int bad;             /* an expected-candidate deposit beyond the 2^62 range */
 } orc_tally;
 
 /* int64 of round-to-nearest-even(ldexp(v, F)); returns 0 and sets *ok = 0 on overflow. */
@@ -849,6 +850,16 @@ static void orc_fly(const orc_flyctx *f, uint32_t slot, int e, uint32_t k, int64
  * crossed face carries S at the face, a wall face absorbs it.  The ray ends
  * at the first face where S has reached 0, and a ray with no direction
  * leaves all of q in its cell. */
+static int64_t orc_cand(double v, double ratio, orc_tally *t)
+{
+  double x = v / ratio;
+  if (!(fabs(x) <= ORC_TWO62)) {
+    t->bad = 1;
+    return 0;
+  }
+  return (int64_t)rint(x);
+}
+
 static void orc_fly_expected(const orc_flyctx *f, uint32_t slot, int e, uint32_t k, int64_t q,
                              orc_tally *t, uint64_t *segs)
 {
@@ -908,7 +919,7 @@ static void orc_fly_expected(const orc_flyctx *f, uint32_t slot, int e, uint32_t
     double tt = axis_x ? tx : ty;
     if (!(tt < INFINITY)) {            /* no direction: everything stays here */
       t->D[c] += S;
-      t->W[c] += f->has_null ? (int64_t)rint((qd * surv) / f->ratio[c]) : S;
+      t->W[c] += f->has_null ? orc_cand(qd * surv, f->ratio[c], t) : S;
       t->end = c;
       return;
     }
@@ -916,7 +927,7 @@ static void orc_fly_expected(const orc_flyctx *f, uint32_t slot, int e, uint32_t
     double sn = orc_expm(Tn);
     int64_t Sn = (int64_t)rint(qd * sn);
     t->D[c] += S - Sn;
-    t->W[c] += f->has_null ? (int64_t)rint((qd * (surv - sn)) / f->ratio[c]) : S - Sn;
+    t->W[c] += f->has_null ? orc_cand(qd * (surv - sn), f->ratio[c], t) : S - Sn;
     T = Tn;
     surv = sn;
     S = Sn;
@@ -1016,7 +1027,7 @@ static int orc_iterate(orc_state *s, int faces)
   double *tmp = (double *)malloc(sizeof(double) * s->nc);
   for (int c = 0; c < s->nc; ++c) s->E_half[c] = ldexp((double)s->W[c], -s->F) / s->V;
   int rc = ORC_OK;
-  int ok = 1;
+  int ok = !t.bad;
   if (s->o.newton) {
     double *r = (double *)malloc(sizeof(double) * s->nc);
     double *x = (double *)malloc(sizeof(double) * s->nc);

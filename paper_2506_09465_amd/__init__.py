@@ -4,13 +4,14 @@
 The compute path is the HIP library libiugkp.so (C ABI in include/iugkp.h);
 this package only marshals arguments to it.
 """
-from ._lib import (FACES_EVERY, FACES_FINAL, FACES_OFF, RNG_CRN, RNG_FRESH, SCHEME_EMITTERS,
-                   SCHEME_PERSISTENT, IugkpError, lib as library)
+from ._lib import (EST_ANALOG, EST_EXPECTED, FACES_EVERY, FACES_FINAL, FACES_OFF, RNG_CRN,
+                   RNG_FRESH, SCHEME_EMITTERS, SCHEME_PERSISTENT, IugkpError, lib as library)
 
 __all__ = ["Solver", "BatchSolver", "steady_temperature", "d_eff", "dev_philox", "dev_math",
            "dev_segments",
            "FACES_EVERY",
-           "FACES_FINAL", "FACES_OFF", "RNG_CRN", "RNG_FRESH", "SCHEME_EMITTERS",
+           "FACES_FINAL", "FACES_OFF", "RNG_CRN", "RNG_FRESH", "SCHEME_EMITTERS", "EST_ANALOG",
+           "EST_EXPECTED",
            "SCHEME_PERSISTENT", "IugkpError", "library"]
 
 

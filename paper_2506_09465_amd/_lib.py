@@ -22,6 +22,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 RNG_FRESH, RNG_CRN = 0, 1
 FACES_OFF, FACES_EVERY, FACES_FINAL = 0, 1, 2
 SCHEME_EMITTERS, SCHEME_PERSISTENT = 0, 1
+EST_ANALOG, EST_EXPECTED = 0, 1
 
 
 class Problem(C.Structure):
@@ -39,7 +40,7 @@ class Options(C.Structure):
                 ("res_tol", C.c_double), ("newton", C.c_int), ("cg_tol", C.c_double),
                 ("cg_max_iters", C.c_int), ("tally_faces", C.c_int), ("avg_iters", C.c_int),
                 ("block_size", C.c_int), ("march", C.c_int), ("cg_waves", C.c_int),
-                ("scheme", C.c_int)]
+                ("scheme", C.c_int), ("estimator", C.c_int)]
 
 
 class Stats(C.Structure):

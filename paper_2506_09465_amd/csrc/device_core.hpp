@@ -134,6 +134,39 @@ __device__ __forceinline__ double cos2pi_own(double u)
   }
 }
 
+// ---------------------------------------------------------------------------
+// exp(-T), T >= 0, from + - * / and exact scaling.  T = k ln2 + r with
+// k = rint(T / ln2) and r = (T - k ln2_hi) - k ln2_lo (Cody-Waite pair, the
+// high part with trailing zero bits), |r| <= ln2 / 2; exp(-r) by its Taylor
+// polynomial to degree 14 in Horner form, times 2^-k.  0 for T > 700.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double expm_own(double T)
+{
+  const double kLn2Hi = 6.93147180369123816490e-01;
+  const double kLn2Lo = 1.90821492927058770002e-10;
+  const double kInvLn2 = 1.44269504088896338700e+00;
+  if (T > 700.0) return 0.0;
+  const double kd = rint(T * kInvLn2);
+  const double r = (T - kd * kLn2Hi) - kd * kLn2Lo;
+  const double x = -r;
+  double p = 1.0 / 87178291200.0;
+  p = p * x + 1.0 / 6227020800.0;
+  p = p * x + 1.0 / 479001600.0;
+  p = p * x + 1.0 / 39916800.0;
+  p = p * x + 1.0 / 3628800.0;
+  p = p * x + 1.0 / 362880.0;
+  p = p * x + 1.0 / 40320.0;
+  p = p * x + 1.0 / 5040.0;
+  p = p * x + 1.0 / 720.0;
+  p = p * x + 1.0 / 120.0;
+  p = p * x + 1.0 / 24.0;
+  p = p * x + 1.0 / 6.0;
+  p = p * x + 0.5;
+  p = p * x + 1.0;
+  p = p * x + 1.0;
+  return ldexp(p, -static_cast<int>(kd));
+}
+
 // Fixed-point conversion used for emission energies: rint(ldexp(v, F)).
 __device__ __forceinline__ double fixed_scale(double v, int F) { return rint(ldexp(v, F)); }
 

@@ -152,6 +152,10 @@ int check_options(const iugkp_options *o)
     return fail(IUGKP_E_INVALID_ARG, "bad scheme");
   if (o->scheme == IUGKP_SCHEME_PERSISTENT && o->newton)
     return fail(IUGKP_E_INVALID_ARG, "the persistent scheme has no Newton step");
+  if (o->estimator != IUGKP_EST_ANALOG && o->estimator != IUGKP_EST_EXPECTED)
+    return fail(IUGKP_E_INVALID_ARG, "bad estimator");
+  if (o->estimator == IUGKP_EST_EXPECTED && o->scheme != IUGKP_SCHEME_EMITTERS)
+    return fail(IUGKP_E_INVALID_ARG, "the expected-value estimator is for the emitter scheme");
   return IUGKP_OK;
 }
 
@@ -412,6 +416,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   d.epoch = o->rng_epoch;
   d.has_null = (tmax != tmin);
   d.newton = o->newton ? 1 : 0;
+  d.estimator = o->estimator;
   d.faces_each = (o->tally_faces == IUGKP_FACES_EVERY);
   d.faces_out = (o->tally_faces != IUGKP_FACES_OFF);
   d.final_iter = (o->tally_faces == IUGKP_FACES_FINAL);
@@ -579,7 +584,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
     }
   }
   if (multi_cg && p->dim == 2 && o->tally_faces != IUGKP_FACES_OFF &&
-      o->scheme == IUGKP_SCHEME_EMITTERS &&
+      o->scheme == IUGKP_SCHEME_EMITTERS && o->estimator == IUGKP_EST_ANALOG &&
       (o->march == 2 ||
        (o->march == 0 && d.lam_min >= kStripeMinCells * std::min(p->dx, p->dy)))) {
     // row stripes: as many rows per workgroup as its LDS holds (y faces, D,
@@ -681,8 +686,10 @@ int setup_bands(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, I
   if (rc) return rc;
   rc = check_options(o);
   if (rc) return rc;
-  if (o->newton || o->avg_iters != 0)
-    return fail(IUGKP_E_INVALID_ARG, "frequency bands: no Newton correction, no output averaging");
+  if (o->newton || o->avg_iters != 0 || o->estimator != IUGKP_EST_ANALOG ||
+      o->scheme != IUGKP_SCHEME_EMITTERS)
+    return fail(IUGKP_E_INVALID_ARG,
+                "frequency bands: emitter scheme, analog estimator, no Newton, no averaging");
   const int K = p->n_bands;
   const int nc = p->nx * p->ny;
   const int nb = 2 * p->ny + (p->dim == 2 ? 2 * p->nx : 0);
@@ -1500,7 +1507,8 @@ int iugkp_adjoint(iugkp_handle *h, const double *dLdT, double *grad_wall, double
   if (!h || !dLdT || max_iters < 1 || !(tol >= 0.0))
     return fail(IUGKP_E_INVALID_ARG, "bad adjoint arguments");
   if (h->bh.K > 1) return fail(IUGKP_E_INVALID_ARG, "the adjoint covers gray problems only");
-  if (h->ih.d.persist) return fail(IUGKP_E_INVALID_ARG, "the adjoint covers the emitter scheme only");
+  if (h->ih.d.persist || h->ih.d.estimator)
+    return fail(IUGKP_E_INVALID_ARG, "the adjoint covers the emitter scheme's analog paths only");
   InstHost &ih = h->ih;
   const Inst &d = ih.d;
   const Mesh &m = d.m;
@@ -1607,7 +1615,7 @@ int iugkp_dev_philox(const uint32_t *ctr, uint32_t key0, uint32_t key1, uint32_t
 
 int iugkp_dev_math(int op, const double *x, const double *y, double *out, int64_t n, void *stream)
 {
-  if (!x || !out || n < 0 || op < 0 || op > 5 || ((op == 3 || op == 5) && !y))
+  if (!x || !out || n < 0 || op < 0 || op > 6 || ((op == 3 || op == 5) && !y))
     return fail(IUGKP_E_INVALID_ARG, "bad arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (n > 0) iugkp::math_probe_kernel<<<cdiv(n, 256), 256, 0, s>>>(op, x, y, out, n);

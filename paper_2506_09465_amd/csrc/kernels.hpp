@@ -71,6 +71,7 @@ struct Inst {
   unsigned int *cg_barrier;                             // [2] barrier of the instance's group
   double *acc_E, *acc_x, *acc_y;
   const long long *Gs;          // per-cell source emission per iteration, or null
+  int estimator;                // 0 sampled collision points, 1 expected deposits along the ray
   uint32_t e_off;               // emitter offset in the Philox counter (frequency band k: k (nc + nb))
   int n_bands;                  // > 1: the coordinating instance of a multi-band problem
   unsigned long long wall_budget;   // saturating sum of |G| over the wall emitters
@@ -502,6 +503,86 @@ __device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long
   }
 }
 
+// Expected-value flight of particle k of emitter e carrying q (variance
+// reduction; the expectation of fly()).  Same start and direction, no free
+// path: the ray is followed cell by cell with optical depth
+// T += chord tau_min / (lambda_min tau_c); with S(T) = rint(q exp(-T)) a
+// cell's chord from T_a to T_b deposits S(T_a) - S(T_b) as real collisions
+// (exactly conserved) and, with null collisions, the expected candidates
+// rint(q (exp(-T_a) - exp(-T_b)) / ratio_c); a crossed face carries S, a wall
+// face absorbs it; the ray ends at the first face where S is 0.  A candidate
+// deposit beyond 2^62 sets `bad`.
+template <class YFace, class Wall, class Cand, class Real>
+__device__ __forceinline__ void fly_expected(const FlyIn &a, uint32_t e, uint32_t k, long long q,
+                                             YFace &&add_yface, Wall &&add_wall, Cand &&add_cand,
+                                             Real &&add_real, unsigned long long &n_seg,
+                                             unsigned long long &n_cross, int &bad)
+{
+  const Mesh &m = a.m;
+  int ix, iy;
+  double x0, y0, sx, sy;
+  sample_particle(a, e, k, ix, iy, x0, y0, sx, sy);
+  ++n_seg;
+  const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+  const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+  const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+  const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+  int kx = (stx > 0) ? ix + 1 : ix;
+  int ky = (sty > 0) ? iy + 1 : iy;
+  const double qd = static_cast<double>(q);
+  double T = 0.0, surv = 1.0, tprev = 0.0;
+  long long S = q;
+  auto cand = [&](int cx, int cy, double v, double ratio) {
+    const double x = v / ratio;
+    if (!(fabs(x) <= 4611686018427387904.0)) {
+      bad = 1;
+      return;
+    }
+    const long long w = static_cast<long long>(rint(x));
+    if (w) add_cand(cx, cy, w);
+  };
+  for (;;) {
+    const int c = ix + m.nx * iy;
+    const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
+    const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
+    const bool along_x = tx <= ty;
+    const double tt = along_x ? tx : ty;
+    if (!(tt < INFINITY)) {
+      if (S) add_real(ix, iy, S);
+      if (a.has_null) cand(ix, iy, qd * surv, a.ratio[c]);
+      return;
+    }
+    const double ratio = a.has_null ? a.ratio[c] : 1.0;
+    const double Tn = T + (tt - tprev) * (ratio / a.lam_min);
+    const double sn = expm_own(Tn);
+    const long long Sn = static_cast<long long>(rint(qd * sn));
+    if (S != Sn) add_real(ix, iy, S - Sn);
+    if (a.has_null) cand(ix, iy, qd * (surv - sn), ratio);
+    T = Tn;
+    surv = sn;
+    S = Sn;
+    tprev = tt;
+    if (S == 0) return;
+    ++n_cross;
+    if (along_x) {
+      if (kx == 0 || kx == m.nx) {
+        add_wall((kx == 0) ? iy : m.ny + iy, S);
+        return;
+      }
+      ix += stx;
+      kx += stx;
+    } else {
+      if (a.faces) add_yface(ky, ix, sty > 0 ? S : -S);
+      if (ky == 0 || ky == m.ny) {
+        add_wall((ky == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix, S);
+        return;
+      }
+      iy += sty;
+      ky += sty;
+    }
+  }
+}
+
 template <int BS>
 __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ insts,
                                                    const TileDesc *__restrict__ tiles,
@@ -583,6 +664,7 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
   const int n_e = (td.kind == 0) ? td.ex * td.ey : td.ex;
   const uint32_t P = static_cast<uint32_t>(n_e) * a.N;
   unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
+  int bad = 0;
   for (uint32_t p = threadIdx.x; p < P; p += BS) {
     const uint32_t ei = p % static_cast<uint32_t>(n_e);
     const uint32_t k = p / static_cast<uint32_t>(n_e);
@@ -596,10 +678,17 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
     const long long q = a.base[e] + ((k < a.rem[e]) ? 1 : 0);
     if (q == 0) continue;
     ++n_fl;
-    fly(fa, e, k, q, add_diff, add_yface, add_wall,
-        [&](int cx, int cy, long long v) { add_cell(win.W, a.W, cx, cy, v); },
-        [&](int cx, int cy, long long v) { add_cell(win.D, a.D, cx, cy, v); }, n_seg, n_cross);
+    if (in.estimator)
+      fly_expected(fa, e, k, q, add_yface, add_wall,
+                   [&](int cx, int cy, long long v) { add_cell(win.W, a.W, cx, cy, v); },
+                   [&](int cx, int cy, long long v) { add_cell(win.D, a.D, cx, cy, v); }, n_seg,
+                   n_cross, bad);
+    else
+      fly(fa, e, k, q, add_diff, add_yface, add_wall,
+          [&](int cx, int cy, long long v) { add_cell(win.W, a.W, cx, cy, v); },
+          [&](int cx, int cy, long long v) { add_cell(win.D, a.D, cx, cy, v); }, n_seg, n_cross);
   }
+  if (bad) atomicOr(&a.sc->flags, 2);
   if (n_fl) {
     atomicAdd(&s_cnt[0], n_fl);
     atomicAdd(&s_cnt[1], n_seg);
@@ -2492,6 +2581,7 @@ __global__ void math_probe_kernel(int op, const double *x, const double *y, doub
       r = __longlong_as_double(v);
       break;
     }
+    case 6: r = expm_own(a); break;
     default: break;
   }
   out[i] = r;
