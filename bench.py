@@ -45,6 +45,10 @@ def parse():
                     help="instances of the batched vs sequential comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient timing")
     ap.add_argument("--no-nongray", action="store_true", help="skip the 40-band timing")
+    ap.add_argument("--no-expected", action="store_true",
+                    help="skip the expected-value estimator comparison")
+    ap.add_argument("--expected-only", action="store_true",
+                    help="only the expected-value comparison (its own JSON line; for profiling)")
     ap.add_argument("--no-persistent", action="store_true",
                     help="skip the persistent-particle timing")
     ap.add_argument("--persistent-only", action="store_true",
@@ -319,6 +323,48 @@ def bench_persistent(P, dev, steps, warmup=3):
     return out
 
 
+def bench_expected(P, dev, iters=6, warmup=10):
+    """The expected-value estimator against the analog one on the 256 x 256
+    cavity at each Kn (1e7 particles, Newton, no face tallies): time per
+    iteration, and the steady-state noise of E (RMS over cells of the standard
+    deviation of E across FRESH iterations after warm-up); efficiency =
+    1 / (noise^2 x time per iteration)."""
+    import numpy as np
+    import torch
+    from synth import cavity_2d
+    out = {"workload": "2D gray square cavity 256x256, hot top wall, Kn in {0.01,0.1,1,10}, "
+                       "1e7 particles/iteration, Newton, no face tallies; FRESH iterations at "
+                       "steady state"}
+    for kn in KNS:
+        row = {}
+        for name, est in (("analog", P.EST_ANALOG), ("expected", P.EST_EXPECTED)):
+            w = cavity_2d(n=N_SIDE, kn=kn, particles=PARTICLES, newton=True, seed=0)
+            s = P.Solver(w, device=dev, estimator=est, tally_faces=P.FACES_OFF)
+            s.step(warmup)
+            a = s.stats()
+            Es, el = [], 0.0
+            for _ in range(iters):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                assert s.step(1) == 0
+                torch.cuda.synchronize()
+                el += time.perf_counter() - t0
+                Es.append(s.state()[2].cpu().numpy())
+            b = s.stats()
+            s.close()
+            Es = np.array(Es)
+            noise = float(np.sqrt(np.mean(np.var(Es, axis=0, ddof=1))))
+            t_it = el / iters
+            row[name] = {"ms_per_iteration": round(t_it * 1e3, 3),
+                         "ms_march": round((b["ms_march"] - a["ms_march"]) / iters, 3),
+                         "crossings_per_flight": round((b["tot_crossings"] - a["tot_crossings"]) /
+                                                       max(1, b["tot_flights"] - a["tot_flights"]), 1),
+                         "noise_rms": noise, "efficiency": 1.0 / (noise * noise * t_it)}
+        row["efficiency_gain"] = round(row["expected"]["efficiency"] / row["analog"]["efficiency"], 3)
+        out[str(kn)] = row
+    return out
+
+
 def cpu_baseline_nongray():
     """The CPU oracle on a bounded sample of the 40-band problem: the same
     two-material 40-band workload on a 128 x 128 mesh with one particle per
@@ -373,6 +419,9 @@ def main():
         return
     if args.persistent_only:
         print(json.dumps(bench_persistent(P, dev, args.steps)), flush=True)
+        return
+    if args.expected_only:
+        print(json.dumps(bench_expected(P, dev)), flush=True)
         return
 
     solvers = []
@@ -479,6 +528,9 @@ def main():
 
     if not args.no_persistent:
         out["persistent"] = bench_persistent(P, dev, args.steps)
+
+    if not args.no_expected:
+        out["expected_value"] = bench_expected(P, dev)
 
     if not args.no_nongray:
         out["nongray"] = bench_nongray(P, dev, args.steps, 20)
