@@ -122,9 +122,11 @@ typedef struct iugkp_options {
   int tally_faces;              /* IUGKP_FACES_* */
   int avg_iters;                /* iterations averaged for the outputs after stopping (>= 0) */
   int block_size;               /* transport kernel workgroup size: 0 (= 256), 64..1024 */
-  int march;                    /* single solves, iterations with face tallies on 2D meshes:
-                                   0 automatic, 1 emitter tiles, 2 row stripes (long free
-                                   paths); the result does not depend on it */
+  int march;                    /* single solves on 2D meshes: 0 automatic (row stripes for
+                                   face-tallied iterations with long free paths, tiles
+                                   otherwise), 1 emitter tiles, 2 row stripes (also for the
+                                   expected-value estimator, with or without face tallies);
+                                   the result does not depend on it */
   int cg_waves;                 /* single solves: 256-cell tree blocks per CG workgroup, 0
                                    (= 8) or 1..12 with the CG state in registers, -1..-12 with
                                    it in global memory; the result does not depend on it */
@@ -161,6 +163,11 @@ typedef struct iugkp_options {
                                    crossed faces carry S, a wall face absorbs it; the ray ends
                                    where S reaches 0.  exp is the library's own (+ - * / and
                                    exact scaling), bitwise reproducible */
+  int own_stream;               /* 0: work is issued on the stream given to iugkp_create.
+                                   1: the handle creates a stream of its own (default priority,
+                                   ordered with the null stream) and destroys it with the
+                                   handle; the stream argument is ignored.  Handles with their
+                                   own streams advance concurrently under iugkp_step_group */
 } iugkp_options;
 
 enum { IUGKP_SCHEME_EMITTERS = 0, IUGKP_SCHEME_PERSISTENT = 1 };
@@ -203,6 +210,14 @@ void iugkp_destroy(iugkp_handle *h);
  * Face tallies are taken when tally_faces == IUGKP_FACES_EVERY.
  * Errors: FIXED_OVERFLOW, NONFINITE, CG_BREAKDOWN, CG_NOT_CONVERGED, DIVERGED, DEVICE. */
 int iugkp_step(iugkp_handle *h, int n_iters);
+
+/* n_iters iterations of each of n distinct handles, every iteration enqueued
+ * on all of them before any is waited for (independent problems on their own
+ * streams then overlap on the GPU: one's Newton CG with another's particle
+ * step).  Each handle takes its own tally_faces mode, as iugkp_step.  Returns
+ * the first error (every enqueued iteration is still completed); the results
+ * of each handle equal those of iugkp_step. */
+int iugkp_step_group(iugkp_handle *const *hs, int n, int n_iters);
 
 /* Same with the face tallies forced on (faces = 1) or off (faces = 0). */
 int iugkp_step_faces(iugkp_handle *h, int n_iters, int faces);

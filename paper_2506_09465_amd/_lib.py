@@ -40,7 +40,7 @@ class Options(C.Structure):
                 ("res_tol", C.c_double), ("newton", C.c_int), ("cg_tol", C.c_double),
                 ("cg_max_iters", C.c_int), ("tally_faces", C.c_int), ("avg_iters", C.c_int),
                 ("block_size", C.c_int), ("march", C.c_int), ("cg_waves", C.c_int),
-                ("scheme", C.c_int), ("estimator", C.c_int)]
+                ("scheme", C.c_int), ("estimator", C.c_int), ("own_stream", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -62,6 +62,7 @@ SIGNATURES = [
     ("iugkp_create", C.c_int, [C.POINTER(Problem), C.POINTER(Options), P, C.POINTER(P)]),
     ("iugkp_destroy", None, [P]),
     ("iugkp_step", C.c_int, [P, C.c_int]),
+    ("iugkp_step_group", C.c_int, [P, C.c_int, C.c_int]),
     ("iugkp_step_faces", C.c_int, [P, C.c_int, C.c_int]),
     ("iugkp_solve", C.c_int, [P, P, P, P, C.POINTER(Stats)]),
     ("iugkp_get_tallies", C.c_int, [P, P, P, P, P, P]),

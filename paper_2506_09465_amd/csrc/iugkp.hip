@@ -583,10 +583,15 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
       ih.cg_lds = lds;
     }
   }
-  if (multi_cg && p->dim == 2 && o->tally_faces != IUGKP_FACES_OFF &&
-      o->scheme == IUGKP_SCHEME_EMITTERS && o->estimator == IUGKP_EST_ANALOG &&
-      (o->march == 2 ||
-       (o->march == 0 && d.lam_min >= kStripeMinCells * std::min(p->dx, p->dy)))) {
+  // (expected-value rays: only on request, march == 2; every stripe follows a
+  // ray from its start, and that re-walk costs more than the tile kernel's
+  // global atomics on the 256^2 cavity)
+  const bool ev = (o->estimator == IUGKP_EST_EXPECTED);
+  if (multi_cg && p->dim == 2 && o->scheme == IUGKP_SCHEME_EMITTERS &&
+      ((ev && o->march == 2) ||
+       (!ev && o->tally_faces != IUGKP_FACES_OFF &&
+        (o->march == 2 ||
+         (o->march == 0 && d.lam_min >= kStripeMinCells * std::min(p->dx, p->dy)))))) {
     // row stripes: as many rows per workgroup as its LDS holds (y faces, D,
     // W with null collisions, the walls), about two workgroups per CU
     int dev = 0, n_cu = 0, lds_max = 0;
@@ -603,9 +608,10 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
       R = cdiv(m.ny, S);
       const size_t lds = static_cast<size_t>(fixed + per_row * R) * sizeof(long long);
       int per_cu = 0;
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>),
-          kStripeBlock, lds));
+      const void *kern =
+          ev ? reinterpret_cast<const void *>(iugkp::march_stripes_ev_kernel<kStripeBlock>)
+             : reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>);
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kStripeBlock, lds));
       if (per_cu >= 1) {
         ih.stripe_R = R;
         ih.stripe_S = S;
@@ -1023,6 +1029,7 @@ int upload_inst(const InstHost &ih, int inst_index, Inst *d_inst, TileDesc *d_ti
 // ---------------------------------------------------------------------------
 struct iugkp_handle {
   hipStream_t stream = nullptr;
+  bool own_stream = false;        // created (and destroyed) by the library
   InstHost ih;                    // the problem (gray), or band 0 (frequency bands)
   std::vector<InstHost> xb;       // bands 1 .. K-1
   BandsHost bh;
@@ -1044,6 +1051,7 @@ namespace {
 void free_handle(iugkp_handle *h)
 {
   if (!h) return;
+  if (h->own_stream && h->stream) (void)hipStreamSynchronize(h->stream);
   h->ih.release();
   for (auto &b : h->xb) b.release();
   if (h->d_inst) (void)hipFree(h->d_inst);
@@ -1051,6 +1059,7 @@ void free_handle(iugkp_handle *h)
   if (h->hsc) (void)hipHostFree(h->hsc);
   for (auto &e : h->ev)
     if (e) (void)hipEventDestroy(e);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
 
@@ -1109,8 +1118,9 @@ int enqueue_cg(const InstHost &ih, const double *b, double *x, DevScalars *sc, h
   return IUGKP_OK;
 }
 
-// One iteration on the handle's stream; leaves the new scalars in h->hsc.
-int iterate(iugkp_handle *h, int faces)
+// Enqueue one iteration on the handle's stream: its kernels and the copy of
+// the new scalars into h->hsc (complete_iteration waits for them).
+int enqueue_iteration(iugkp_handle *h, int faces)
 {
   const InstHost &ih = h->ih;
   const Mesh &m = ih.d.m;
@@ -1133,7 +1143,12 @@ int iterate(iugkp_handle *h, int faces)
   iugkp::prepare_kernel<<<dim3(cdiv(nprep, 256), K), 256, 0, s>>>(h->d_inst, faces, 0);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(h->ev[0], s));
-  if (faces && ih.stripe_R > 0) {
+  if (ih.d.estimator && ih.stripe_R > 0) {
+    iugkp::march_stripes_ev_kernel<kStripeBlock>
+        <<<dim3(ih.stripe_C, ih.stripe_S), kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R,
+                                                                              ih.stripe_C, faces);
+    HIP_TRY(hipGetLastError());
+  } else if (faces && ih.stripe_R > 0) {
     iugkp::march_stripes_kernel<kStripeBlock>
         <<<dim3(ih.stripe_C, ih.stripe_S), kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R,
                                                                               ih.stripe_C);
@@ -1163,6 +1178,16 @@ int iterate(iugkp_handle *h, int faces)
   iugkp::finish_kernel<<<1, 256, 0, s>>>(h->d_inst, 0);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(h->hsc, ih.d.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  return IUGKP_OK;
+}
+
+// Wait for the iteration enqueued on the handle's stream; counters, timings,
+// residual history and the error checks.
+int complete_iteration(iugkp_handle *h)
+{
+  const InstHost &ih = h->ih;
+  hipStream_t s = h->stream;
+  const int K = h->bh.K;
   HIP_TRY(hipStreamSynchronize(s));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
@@ -1198,6 +1223,13 @@ int iterate(iugkp_handle *h, int faces)
     return fail(IUGKP_E_FIXED_OVERFLOW, "emission energy exceeds the fixed-point budget");
   if (h->iter > 1 && h->res > 1e3) return fail(IUGKP_E_DIVERGED, "residual grew above 1e3");
   return IUGKP_OK;
+}
+
+// One iteration on the handle's stream; leaves the new scalars in h->hsc.
+int iterate(iugkp_handle *h, int faces)
+{
+  const int rc = enqueue_iteration(h, faces);
+  return rc ? rc : complete_iteration(h);
 }
 
 // Outputs of a frequency-band problem: T = t_ref + E / sum_k C_k, q = sum over
@@ -1240,6 +1272,16 @@ int iugkp_create(const iugkp_problem *problem, const iugkp_options *options, voi
   *out = nullptr;
   iugkp_handle *h = new iugkp_handle();
   h->stream = static_cast<hipStream_t>(stream);
+  if (options && options->own_stream) {
+    // a stream of the handle's own (default priority, ordered with the null stream)
+    hipStream_t st = nullptr;
+    if (hipStreamCreate(&st) != hipSuccess) {
+      delete h;
+      return fail(IUGKP_E_DEVICE, "hipStreamCreate failed");
+    }
+    h->stream = st;
+    h->own_stream = true;
+  }
   const bool bands = problem && problem->n_bands > 1;
   int rc = bands ? setup_bands(problem, options, h->stream, h->ih, h->xb, h->bh)
                  : setup_instance(problem, options, h->stream, true, h->ih);
@@ -1291,6 +1333,33 @@ int iugkp_step_faces(iugkp_handle *h, int n_iters, int faces)
   for (int i = 0; i < n_iters; ++i) {
     const int rc = iterate(h, faces ? 1 : 0);
     if (rc) return rc;
+  }
+  return IUGKP_OK;
+}
+
+int iugkp_step_group(iugkp_handle *const *hs, int n, int n_iters)
+{
+  if (!hs || n < 1 || n_iters < 0) return fail(IUGKP_E_INVALID_ARG, "bad handle list or count");
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i]) return fail(IUGKP_E_INVALID_ARG, "handle is NULL");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(IUGKP_E_INVALID_ARG, "a handle appears twice");
+  }
+  for (int it = 0; it < n_iters; ++it) {
+    int first = IUGKP_OK, queued = 0;
+    for (; queued < n; ++queued) {
+      const int rc = enqueue_iteration(hs[queued], hs[queued]->ih.d.faces_each);
+      if (rc) {
+        first = rc;
+        break;
+      }
+    }
+    // every enqueued iteration is waited for, whatever happened to the others
+    for (int i = 0; i < queued; ++i) {
+      const int rc = complete_iteration(hs[i]);
+      if (rc && !first) first = rc;
+    }
+    if (first) return first;
   }
   return IUGKP_OK;
 }

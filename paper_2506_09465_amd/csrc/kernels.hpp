@@ -532,6 +532,7 @@ __device__ __forceinline__ void fly_expected(const FlyIn &a, uint32_t e, uint32_
   const double qd = static_cast<double>(q);
   double T = 0.0, surv = 1.0, tprev = 0.0;
   long long S = q;
+  const double inv_lam = 1.0 / a.lam_min;   // = ratio / lambda_min where ratio is 1
   auto cand = [&](int cx, int cy, double v, double ratio) {
     const double x = v / ratio;
     if (!(fabs(x) <= 4611686018427387904.0)) {
@@ -553,7 +554,7 @@ __device__ __forceinline__ void fly_expected(const FlyIn &a, uint32_t e, uint32_
       return;
     }
     const double ratio = a.has_null ? a.ratio[c] : 1.0;
-    const double Tn = T + (tt - tprev) * (ratio / a.lam_min);
+    const double Tn = T + (tt - tprev) * (a.has_null ? ratio / a.lam_min : inv_lam);
     const double sn = expm_own(Tn);
     const long long Sn = static_cast<long long>(rint(qd * sn));
     if (S != Sn) add_real(ix, iy, S - Sn);
@@ -933,6 +934,164 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
     for (int b = threadIdx.x; b < m.n_b; b += BS)
       if (Bl[b]) atom_add(&in.B[b], Bl[b]);
   if (threadIdx.x == 0 && s_cnt[0]) {
+    atomicAdd(&in.sc->flights, s_cnt[0]);
+    atomicAdd(&in.sc->segments, s_cnt[1]);
+    atomicAdd(&in.sc->crossings, s_cnt[2]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The expected-value particle step by row stripes (2D single solves).
+// Workgroup (chunk c, stripe s) keeps in LDS the deposits D (and W with null
+// collisions) of rows [r0, r1), the y-face tallies of faces [r0, r1f) and the
+// wall tallies, and follows every ray of its chunk from its start with the
+// full arithmetic of fly_expected (optical depth, own exp, rounded surviving
+// weight), tallying only the events in its rows: the deposits of a chord in
+// an owned row, the owned y faces crossed, a wall face next to an owned row,
+// and the crossings made from an owned row; flights are counted by the stripe
+// of the start row.  A ray that has left the stripe in its direction of
+// travel (or cannot reach it) is dropped.  Integer sums, so the result equals
+// the tile kernel's bit for bit, with no global atomic before the final
+// row-contiguous flush.
+// ---------------------------------------------------------------------------
+template <int BS>
+__global__ __launch_bounds__(BS) void march_stripes_ev_kernel(const Inst *__restrict__ insts, int R,
+                                                              int chunks, int faces)
+{
+  extern __shared__ long long lds_words[];
+  __shared__ unsigned long long s_cnt[3];
+  const Inst &in = insts[0];
+  const Mesh &m = in.m;
+  const int nx = m.nx;
+  const int r0 = static_cast<int>(blockIdx.y) * R, r1 = min(r0 + R, m.ny);
+  const int r1f = (r1 == m.ny) ? m.ny + 1 : r1;
+  const int nrow = r1 - r0, nface = r1f - r0;
+  long long *By = lds_words;                                  // [nface][nx]
+  long long *Dl = By + nface * nx;                            // [nrow][nx]
+  long long *Wl = in.has_null ? Dl + nrow * nx : nullptr;     // [nrow][nx]
+  long long *Bl = (in.has_null ? Wl : Dl) + nrow * nx;        // [n_b] when lds_walls
+  const int nwords = nface * nx + nrow * nx * (in.has_null ? 2 : 1) + (in.lds_walls ? m.n_b : 0);
+  for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  auto lds_add = [](long long *p, long long v) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
+  };
+  const FlyIn fa = {m, in.lam_min, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1, faces,
+                    in.has_null, in.ratio, in.e_off};
+  const uint32_t N = in.N;
+  const unsigned long long total = static_cast<unsigned long long>(m.n_emit) * N;
+  const unsigned long long pb = total * blockIdx.x / chunks;
+  const unsigned long long pe = total * (blockIdx.x + 1) / chunks;
+  unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
+  int bad = 0;
+  auto owned = [&](int row) { return row >= r0 && row < r1; };
+  const unsigned long long ne = static_cast<unsigned long long>(m.n_emit);
+  const double inv_lam = 1.0 / fa.lam_min;   // = ratio / lambda_min where ratio is 1
+  for (unsigned long long pc = pb + threadIdx.x; pc < pe; pc += BS) {
+    // emitters fastest: neighbouring lanes start in different cells
+    const uint32_t kk = static_cast<uint32_t>(pc / ne);
+    const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * ne);
+    const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
+    if (q == 0) continue;
+    int ix, iy;
+    double x0, y0, sx, sy;
+    sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
+    if (owned(iy)) {
+      ++n_fl;
+      ++n_seg;
+    }
+    const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+    const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+    if ((sty == 0 && !owned(iy)) || (sty > 0 && iy >= r1) || (sty < 0 && iy < r0)) continue;
+    const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+    const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+    int kx = (stx > 0) ? ix + 1 : ix;
+    int ky = (sty > 0) ? iy + 1 : iy;
+    const double qd = static_cast<double>(q);
+    double T = 0.0, surv = 1.0, tprev = 0.0;
+    long long S = q;
+    auto cand = [&](int cx, int cy, double v, double ratio) {
+      const double x = v / ratio;
+      if (!(fabs(x) <= 4611686018427387904.0)) {
+        bad = 1;
+        return;
+      }
+      const long long w = static_cast<long long>(rint(x));
+      if (w) lds_add(&Wl[(cy - r0) * nx + cx], w);
+    };
+    for (;;) {
+      const bool own = owned(iy);
+      const int c = ix + nx * iy;
+      const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
+      const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
+      const bool along_x = tx <= ty;
+      const double tt = along_x ? tx : ty;
+      if (!(tt < INFINITY)) {
+        if (own) {
+          if (S) lds_add(&Dl[(iy - r0) * nx + ix], S);
+          if (fa.has_null) cand(ix, iy, qd * surv, fa.ratio[c]);
+        }
+        break;
+      }
+      const double ratio = fa.has_null ? fa.ratio[c] : 1.0;
+      const double Tn = T + (tt - tprev) * (fa.has_null ? ratio / fa.lam_min : inv_lam);
+      const double sn = expm_own(Tn);
+      const long long Sn = static_cast<long long>(rint(qd * sn));
+      if (own) {
+        if (S != Sn) lds_add(&Dl[(iy - r0) * nx + ix], S - Sn);
+        if (fa.has_null) cand(ix, iy, qd * (surv - sn), ratio);
+      }
+      T = Tn;
+      surv = sn;
+      S = Sn;
+      tprev = tt;
+      if (S == 0) break;
+      if (own) ++n_cross;
+      if (along_x) {
+        if (kx == 0 || kx == nx) {
+          if (own) {
+            const int b = (kx == 0) ? iy : m.ny + iy;
+            if (in.lds_walls) lds_add(&Bl[b], S);
+            else atom_add(&in.B[b], S);
+          }
+          break;
+        }
+        ix += stx;
+        kx += stx;
+      } else {
+        if (faces && ky >= r0 && ky < r1f) lds_add(&By[(ky - r0) * nx + ix], sty > 0 ? S : -S);
+        if (ky == 0 || ky == m.ny) {
+          if (own) {
+            const int b = (ky == 0) ? 2 * m.ny + ix : 2 * m.ny + nx + ix;
+            if (in.lds_walls) lds_add(&Bl[b], S);
+            else atom_add(&in.B[b], S);
+          }
+          break;
+        }
+        iy += sty;
+        ky += sty;
+        if ((sty > 0 && iy >= r1) || (sty < 0 && iy < r0)) break;
+      }
+    }
+  }
+  if (bad) atomicOr(&in.sc->flags, 2);
+  if (n_fl || n_cross) {
+    atomicAdd(&s_cnt[0], n_fl);
+    atomicAdd(&s_cnt[1], n_seg);
+    atomicAdd(&s_cnt[2], n_cross);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nface * nx; i += BS)
+    if (By[i]) atom_add(&in.Phiy[r0 * nx + i], By[i]);
+  for (int i = threadIdx.x; i < nrow * nx; i += BS) {
+    if (Dl[i]) atom_add(&in.D[r0 * nx + i], Dl[i]);
+    if (Wl && Wl[i]) atom_add(&in.W[r0 * nx + i], Wl[i]);
+  }
+  if (in.lds_walls)
+    for (int b = threadIdx.x; b < m.n_b; b += BS)
+      if (Bl[b]) atom_add(&in.B[b], Bl[b]);
+  if (threadIdx.x == 0 && (s_cnt[0] || s_cnt[2])) {
     atomicAdd(&in.sc->flights, s_cnt[0]);
     atomicAdd(&in.sc->segments, s_cnt[1]);
     atomicAdd(&in.sc->crossings, s_cnt[2]);

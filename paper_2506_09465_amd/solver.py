@@ -37,7 +37,8 @@ class _Marshal:
 
     def __init__(self, w, device, *, seed, particles, rng_mode, epoch, max_iters, res_tol,
                  newton, diff_x, diff_y, cg_tol, cg_max_iters, tally_faces, avg_iters,
-                 block_size, march=0, cg_waves=0, scheme=0, estimator=0, T_init=None):
+                 block_size, march=0, cg_waves=0, scheme=0, estimator=0, own_stream=False,
+                 T_init=None):
         self.tau = _dev_f64(w.tau, device)
         self.wall = _dev_f64(w.wall_T, device)
         Ti = T_init if T_init is not None else getattr(w, "T_init", None)
@@ -57,7 +58,7 @@ class _Marshal:
                                  int(max_iters), float(res_tol), int(bool(newton)),
                                  float(cg_tol), int(cg_max_iters), int(tally_faces),
                                  int(avg_iters), int(block_size), int(march), int(cg_waves),
-                                 int(scheme), int(estimator))
+                                 int(scheme), int(estimator), int(bool(own_stream)))
 
 
 def _defaults(w, kw):
@@ -74,6 +75,7 @@ def _defaults(w, kw):
                 avg_iters=kw.pop("avg_iters", 0), block_size=kw.pop("block_size", 0),
                 march=kw.pop("march", 0), cg_waves=kw.pop("cg_waves", 0),
                 scheme=kw.pop("scheme", 0), estimator=kw.pop("estimator", 0),
+                own_stream=kw.pop("own_stream", False),
                 T_init=kw.pop("T_init", None))
 
 
@@ -88,6 +90,8 @@ class Solver:
         if kw:
             raise TypeError(f"unknown options {sorted(kw)}")
         self.w = w
+        # the stream the library issues on stays referenced while the solver lives
+        self._stream = torch.cuda.current_stream(self.device)
         self.K = int(getattr(w, "n_bands", 1) or 1)
         self.nc = int(w.nx * w.ny)
         self.nb = 2 * int(w.ny) + (2 * int(w.nx) if w.dim == 2 else 0)
@@ -216,6 +220,14 @@ class Solver:
         r = np.zeros(max(n, 1))
         k = L.lib().iugkp_get_residuals(self.h, r.ctypes.data, n)
         return r[:max(k, 0)]
+
+
+def step_group(solvers: Sequence["Solver"], n: int = 1) -> int:
+    """n iterations of several independent solvers, each iteration enqueued on
+    all of them before any is waited for; with own_stream=True solvers their
+    kernels overlap on the GPU.  Results equal per-solver step()."""
+    hs = (C.c_void_p * len(solvers))(*[s.h for s in solvers])
+    return L.lib().iugkp_step_group(C.cast(hs, C.c_void_p), len(solvers), int(n))
 
 
 def d_eff(lam: float, delta: float) -> float:

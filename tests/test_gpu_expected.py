@@ -79,14 +79,26 @@ CASES = {
     "cavity_ragged": lambda: cavity_2d(n=37, ny=23, kn=0.1, particles=60_000, newton=False),
     "two_material_window": lambda: two_material_2d(n=48, kn_right=0.05, ratio=20.0,
                                                    particles=120_000),
+    # rows too long for one stripe: several row stripes
+    "wide_600x40": lambda: cavity_2d(n=600, ny=40, kn=0.05, particles=150_000, newton=False),
+    "wide_null_400x60": lambda: _two_material_wide(),
 }
+
+
+def _two_material_wide():
+    w = cavity_2d(n=400, ny=60, kn=0.02, particles=150_000, newton=False)
+    ix = np.tile(np.arange(400), 60)
+    w.tau = np.where(ix < 150, 20.0 * np.asarray(w.tau), np.asarray(w.tau))
+    return w
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("rng", ["fresh", "crn"])
-def test_expected_iterations_bitwise(oracle_mod, gpu, name, rng):
+@pytest.mark.parametrize("march", [1, 2])
+def test_expected_iterations_bitwise(oracle_mod, gpu, name, rng, march):
+    """march 1: emitter tiles (the default); march 2: row stripes on 2D meshes."""
     w = CASES[name]()
-    o, s = _pair(oracle_mod, gpu, w, newton=False,
+    o, s = _pair(oracle_mod, gpu, w, newton=False, march=march,
                  rng_mode=oracle_mod.CRN if rng == "crn" else oracle_mod.FRESH, epoch=3)
     for i, faces in enumerate([True, False, True]):
         assert o.step(1, faces=faces) == 0
