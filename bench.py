@@ -10,9 +10,10 @@ iteration.  Inputs are synthetic and seeded (seed 0).
 One step = one full iteration of the hot path for each of the four Kn
 problems: emitter split, sampling + flight + tallies, macroscopic update,
 Newton CG, residual.  The four problems are independent: each solver has a
-stream of its own and a step is enqueued on all four before any is waited
-for (iugkp_step_group), so one problem's Newton CG (a few tens of
-workgroups) overlaps the others' particle steps.  Printed: one JSON line
+stream of its own and the timed steps run through iugkp_step_group, which
+enqueues a problem's next iteration as soon as its previous one is done, so
+one problem's Newton CG (a few tens of workgroups) overlaps the others'
+particle steps.  Printed: one JSON line
 with flights/s over the timed (concurrent) steps; per-Kn breakdown and the
 roofline of the dominant kernel from a pass of the same steps one problem at
 a time (HIP events on each solver's stream); time-to-steady at residual 1e-6 (common
@@ -439,9 +440,10 @@ def main():
                                         own_stream=True)))
 
     def run_concurrent(n):
-        for _ in range(n):
-            rc = P.step_group([s for _, _, s in solvers], 1)
-            assert rc == 0, f"step failed with {rc}"
+        # n iterations of every problem; each problem's next iteration is
+        # enqueued as soon as its previous one is done
+        rc = P.step_group([s for _, _, s in solvers], n)
+        assert rc == 0, f"step failed with {rc}"
 
     run_concurrent(args.warmup)
     # kernel pass: the same steps one problem at a time, for per-kernel times
@@ -526,8 +528,8 @@ def main():
         "config": {"workload": "2D gray square cavity 256x256, hot top wall, Kn in {0.01,0.1,1,10}, "
                                "1e7 particles/iteration, Newton (FP64 CG tol 1e-10), int64 "
                                "fixed-point tallies, face tallies every iteration; one step = one "
-                               "iteration of each Kn (the four on their own streams, enqueued "
-                               "together)",
+                               "iteration of each Kn (the four on their own streams, each "
+                               "iteration enqueued as soon as the problem's previous one ends)",
                    "seed": 0, "parallelism": "single GPU"},
         "sequential": {"ms_per_step": round(seq_elapsed / K * 1e3, 3),
                        "flights_per_s": tot["flights"] / seq_elapsed,

@@ -211,12 +211,14 @@ void iugkp_destroy(iugkp_handle *h);
  * Errors: FIXED_OVERFLOW, NONFINITE, CG_BREAKDOWN, CG_NOT_CONVERGED, DIVERGED, DEVICE. */
 int iugkp_step(iugkp_handle *h, int n_iters);
 
-/* n_iters iterations of each of n distinct handles, every iteration enqueued
- * on all of them before any is waited for (independent problems on their own
- * streams then overlap on the GPU: one's Newton CG with another's particle
- * step).  Each handle takes its own tally_faces mode, as iugkp_step.  Returns
- * the first error (every enqueued iteration is still completed); the results
- * of each handle equal those of iugkp_step. */
+/* n_iters iterations of each of n distinct handles.  Every handle's
+ * iterations run back to back on its stream; the host enqueues a handle's
+ * next iteration as soon as its previous one has completed, without waiting
+ * for the others, so independent problems on their own streams overlap on
+ * the GPU (one's Newton CG with another's particle step).  Each handle takes
+ * its own tally_faces mode, as iugkp_step.  After the first error no new
+ * iteration is started (those in flight are completed) and that error is
+ * returned; the results of each handle equal those of iugkp_step. */
 int iugkp_step_group(iugkp_handle *const *hs, int n, int n_iters);
 
 /* Same with the face tallies forced on (faces = 1) or off (faces = 0). */

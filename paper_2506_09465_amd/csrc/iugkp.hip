@@ -1345,23 +1345,39 @@ int iugkp_step_group(iugkp_handle *const *hs, int n, int n_iters)
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(IUGKP_E_INVALID_ARG, "a handle appears twice");
   }
-  for (int it = 0; it < n_iters; ++it) {
-    int first = IUGKP_OK, queued = 0;
-    for (; queued < n; ++queued) {
-      const int rc = enqueue_iteration(hs[queued], hs[queued]->ih.d.faces_each);
+  // each handle runs its iterations back to back; a finished iteration is
+  // completed and the handle's next one enqueued as soon as its stream is idle
+  std::vector<int> left(n, n_iters);
+  std::vector<char> busy(n, 0);
+  int first = IUGKP_OK, n_busy = 0;
+  auto start = [&](int i) {
+    if (first || left[i] == 0) return;
+    const int rc = enqueue_iteration(hs[i], hs[i]->ih.d.faces_each);
+    if (rc) {
+      first = rc;
+      return;
+    }
+    busy[i] = 1;
+    ++n_busy;
+  };
+  for (int i = 0; i < n; ++i) start(i);
+  while (n_busy > 0) {
+    for (int i = 0; i < n; ++i) {
+      if (!busy[i]) continue;
+      const hipError_t q = hipStreamQuery(hs[i]->stream);
+      if (q == hipErrorNotReady) continue;
+      busy[i] = 0;
+      --n_busy;
+      const int rc = complete_iteration(hs[i]);   // also reports a failed stream
+      --left[i];
       if (rc) {
-        first = rc;
-        break;
+        if (!first) first = rc;
+        continue;
       }
+      start(i);
     }
-    // every enqueued iteration is waited for, whatever happened to the others
-    for (int i = 0; i < queued; ++i) {
-      const int rc = complete_iteration(hs[i]);
-      if (rc && !first) first = rc;
-    }
-    if (first) return first;
   }
-  return IUGKP_OK;
+  return first;
 }
 
 int iugkp_step(iugkp_handle *h, int n_iters)
