@@ -934,16 +934,25 @@ int setup_bands(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, I
   return IUGKP_OK;
 }
 
-int launch_march(const Inst *d_insts, const TileDesc *d_tiles, int n_tiles, size_t lds, int block,
-                 int faces_mode, int batch, hipStream_t s)
+template <bool EV>
+void launch_march_as(const Inst *d_insts, const TileDesc *d_tiles, int n_tiles, size_t lds,
+                     int block, int faces_mode, int batch, hipStream_t s)
 {
   switch (block) {
-    case 64: iugkp::march_kernel<64><<<n_tiles, 64, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
-    case 128: iugkp::march_kernel<128><<<n_tiles, 128, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
-    case 512: iugkp::march_kernel<512><<<n_tiles, 512, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
-    case 1024: iugkp::march_kernel<1024><<<n_tiles, 1024, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
-    default: iugkp::march_kernel<256><<<n_tiles, 256, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+    case 64: iugkp::march_kernel<64, EV><<<n_tiles, 64, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+    case 128: iugkp::march_kernel<128, EV><<<n_tiles, 128, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+    case 512: iugkp::march_kernel<512, EV><<<n_tiles, 512, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+    case 1024: iugkp::march_kernel<1024, EV><<<n_tiles, 1024, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+    default: iugkp::march_kernel<256, EV><<<n_tiles, 256, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
   }
+}
+
+// ev: some instance takes the expected-value estimator
+int launch_march(const Inst *d_insts, const TileDesc *d_tiles, int n_tiles, size_t lds, int block,
+                 int faces_mode, int batch, bool ev, hipStream_t s)
+{
+  if (ev) launch_march_as<true>(d_insts, d_tiles, n_tiles, lds, block, faces_mode, batch, s);
+  else launch_march_as<false>(d_insts, d_tiles, n_tiles, lds, block, faces_mode, batch, s);
   HIP_TRY(hipGetLastError());
   return IUGKP_OK;
 }
@@ -1154,7 +1163,8 @@ int enqueue_iteration(iugkp_handle *h, int faces)
                                                                               ih.stripe_C);
     HIP_TRY(hipGetLastError());
   } else {
-    rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, h->lds, h->block, faces, 0, s);
+    rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, h->lds, h->block, faces, 0,
+                      ih.d.estimator != 0, s);
     if (rc) return rc;
   }
   HIP_TRY(hipEventRecord(h->ev[1], s));
@@ -1750,6 +1760,7 @@ struct iugkp_batch {
   int n_tiles = 0;
   size_t lds_max = 0;
   int any_newton = 0;
+  bool any_ev = false;                // some instance takes the expected-value estimator
   int max_prep = 1, max_nx = 1, max_ny = 1, max_nbc = 1, max_nbe = 1, max_out = 1;
   // batched CG: a pool of resident workgroups and, per replay, the host's
   // schedule of (instance, rank) jobs on it
@@ -1796,7 +1807,7 @@ int enqueue_batch_iteration(iugkp_batch *b)
   hipStream_t s = b->own;
   const int n = static_cast<int>(b->insts.size());
   iugkp::prepare_kernel<<<dim3(cdiv(b->max_prep, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
-  int rc = launch_march(b->d_insts, b->d_tiles, b->n_tiles, b->lds_max, 256, -1, 1, s);
+  int rc = launch_march(b->d_insts, b->d_tiles, b->n_tiles, b->lds_max, 256, -1, 1, b->any_ev, s);
   if (rc) return rc;
   iugkp::reconstruct_y_kernel<<<dim3(cdiv(b->max_nx, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
   iugkp::reconstruct_x_kernel<<<dim3(cdiv(b->max_ny, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
@@ -1905,6 +1916,7 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
     b->n_tiles += static_cast<int>(ih.tiles.size());
     b->lds_max = std::max(b->lds_max, ih.lds_bytes);
     b->any_newton |= ih.d.newton;
+    b->any_ev = b->any_ev || (ih.d.estimator != 0);
     b->max_prep = std::max({b->max_prep, m.n_emit, m.n_fx, m.n_fy, m.n_cells, (m.ny + 2) * m.nx});
     b->max_nx = std::max(b->max_nx, m.nx);
     b->max_ny = std::max(b->max_ny, m.ny);

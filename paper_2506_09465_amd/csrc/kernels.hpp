@@ -584,7 +584,9 @@ __device__ __forceinline__ void fly_expected(const FlyIn &a, uint32_t e, uint32_
   }
 }
 
-template <int BS>
+// EV: also the expected-value flights of instances that ask for them (a
+// separate instantiation, so the analog kernel keeps its register budget).
+template <int BS, bool EV>
 __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ insts,
                                                    const TileDesc *__restrict__ tiles,
                                                    int faces_mode, int batch)
@@ -679,7 +681,7 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
     const long long q = a.base[e] + ((k < a.rem[e]) ? 1 : 0);
     if (q == 0) continue;
     ++n_fl;
-    if (in.estimator)
+    if (EV && in.estimator)
       fly_expected(fa, e, k, q, add_yface, add_wall,
                    [&](int cx, int cy, long long v) { add_cell(win.W, a.W, cx, cy, v); },
                    [&](int cx, int cy, long long v) { add_cell(win.D, a.D, cx, cy, v); }, n_seg,
