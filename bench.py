@@ -492,6 +492,8 @@ def main():
             "flights_per_iter": fl // K, "crossings_per_flight": round(cr / max(fl, 1), 2),
             "ms_march": round(ms_m / K, 3), "ms_cg": round(ms_c / K, 3),
             "cg_iters": cgi // K, "flights_per_s_march": fl / (ms_m / 1e3) if ms_m else None,
+            "crossings_per_s_march": cr / (ms_m / 1e3) if ms_m else None,
+            "cg_us_per_iteration": round(ms_c * 1e3 / cgi, 3) if cgi else None,
             "march_GBs_algorithmic": mb / (ms_m / 1e3) / 1e9 if ms_m else None,
         }
         for k, v in (("flights", fl), ("crossings", cr), ("segments", sg), ("ms_march", ms_m),
@@ -540,6 +542,15 @@ def main():
         "kernels": rooflines,
         "source_hash": src,
     }
+
+    # the tally-throughput ceilings the particle step works against: int64
+    # atomic adds to random words of a 2 MB global array (the size of the
+    # cavity's tallies) and of a workgroup's LDS array
+    out["atomics_ceiling"] = {
+        "global_int64_2MB_per_s": P.dev_atomics(False, n_words=262144),
+        "lds_int64_per_s": P.dev_atomics(True),
+        "note": "particle-step tallies: one add per face crossing tallied and per deposit, in "
+                "LDS inside a tile's window or a stripe, in global memory outside"}
 
     if not args.no_tts:
         tts = {}

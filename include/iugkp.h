@@ -347,6 +347,15 @@ int iugkp_dev_math(int op, const double *x, const double *y, double *out, int64_
  * point, as doubles), sx, sy, ell; out[3i..3i+2] = 1 if a boundary face absorbs
  * the segment else 0, that face's wall index or the final cell ix + nx iy, and
  * the number of faces crossed (the wall face included). */
+/* iugkp_dev_atomics: the tally-throughput ceilings the particle step is held
+ * against.  n_threads (a multiple of 256) threads each add 1 to per_thread
+ * pseudo-random int64 words: of a global array of n_words (lds = 0; 4096 <=
+ * n_words <= 2^28, allocated here) or of a 4096-word LDS array per workgroup
+ * (lds = 1).  *ms_out = the second of two identical launches (HIP events);
+ * the rate is n_threads * per_thread / ms. */
+int iugkp_dev_atomics(int lds, int64_t n_words, int64_t per_thread, int64_t n_threads,
+                      double *ms_out, void *stream);
+
 int iugkp_dev_segments(int dim, int nx, int ny, double dx, double dy, const double *rays,
                        int64_t n, int64_t *out, void *stream);
 

@@ -1719,6 +1719,39 @@ int iugkp_dev_math(int op, const double *x, const double *y, double *out, int64_
   return IUGKP_OK;
 }
 
+int iugkp_dev_atomics(int lds, int64_t n_words, int64_t per_thread, int64_t n_threads,
+                      double *ms_out, void *stream)
+{
+  if (!ms_out || (lds != 0 && lds != 1) || n_words < 4096 || n_words > (1ll << 28) ||
+      per_thread < 1 || per_thread > 4096 || n_threads < 256 || n_threads > (1ll << 26) ||
+      n_threads % 256 != 0)
+    return fail(IUGKP_E_INVALID_ARG, "bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevScratch tmp(s);
+  long long *words = tmp.get<long long>(n_words);
+  if (!words) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
+  HIP_TRY(hipMemsetAsync(words, 0, n_words * sizeof(long long), s));
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  const int grid = static_cast<int>(n_threads / 256);
+  // one untimed launch, then the timed one
+  iugkp::atomics_probe_kernel<<<grid, 256, 0, s>>>(lds, words, static_cast<int>(n_words),
+                                                   static_cast<int>(per_thread));
+  HIP_TRY(hipEventRecord(a, s));
+  iugkp::atomics_probe_kernel<<<grid, 256, 0, s>>>(lds, words, static_cast<int>(n_words),
+                                                   static_cast<int>(per_thread));
+  HIP_TRY(hipEventRecord(b, s));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, a, b));
+  *ms_out = ms;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return IUGKP_OK;
+}
+
 int iugkp_dev_segments(int dim, int nx, int ny, double dx, double dy, const double *rays,
                        int64_t n, int64_t *out, void *stream)
 {

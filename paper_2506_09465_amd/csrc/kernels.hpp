@@ -2689,6 +2689,37 @@ __global__ void zero_u32_kernel(unsigned int *p, int n)
 // ---------------------------------------------------------------------------
 // building-block probes
 // ---------------------------------------------------------------------------
+
+// Tally-throughput ceilings: every thread adds 1 to `per_thread` pseudo-random
+// words (a multiplicative hash of thread and step) of an int64 array of
+// n_words, either in global memory (lds == 0: `words`, n_words of them) or in
+// a workgroup's LDS array (lds == 1: 4096 words, flushed to `words` at the end
+// so the work is not optimised away).
+__global__ __launch_bounds__(256) void atomics_probe_kernel(int lds, long long *words, int n_words,
+                                                            int per_thread)
+{
+  __shared__ long long tab[4096];
+  const unsigned int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lds) {
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) tab[i] = 0;
+    __syncthreads();
+  }
+  uint32_t h = t * 2654435761u + 12345u;
+  for (int i = 0; i < per_thread; ++i) {
+    h = h * 1664525u + 1013904223u;
+    if (lds)
+      atomicAdd(reinterpret_cast<unsigned long long *>(&tab[(h >> 8) & 4095u]), 1ull);
+    else
+      atomicAdd(reinterpret_cast<unsigned long long *>(&words[(h >> 4) % static_cast<uint32_t>(n_words)]),
+                1ull);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x)
+      if (tab[i]) atomicAdd(reinterpret_cast<unsigned long long *>(&words[i % n_words]),
+                            static_cast<unsigned long long>(tab[i]));
+  }
+}
 __global__ void philox_probe_kernel(const uint32_t *ctr, uint32_t k0, uint32_t k1, uint32_t *out,
                                     long long n)
 {

@@ -244,6 +244,19 @@ def dev_philox(ctr: torch.Tensor, key0: int, key1: int) -> torch.Tensor:
     return out
 
 
+def dev_atomics(lds: bool, n_words: int = 262144, per_thread: int = 64,
+                n_threads: int = 256 * 8192, device="cuda") -> float:
+    """Tally-throughput ceiling: int64 atomic adds per second to random words
+    of a global array of n_words, or of a workgroup's LDS array."""
+    ms = C.c_double(0.0)
+    dev = torch.device(device)
+    with torch.cuda.device(dev):
+        L.check(L.lib().iugkp_dev_atomics(int(bool(lds)), int(n_words), int(per_thread),
+                                          int(n_threads), C.addressof(ms),
+                                          C.c_void_p(_stream_handle(dev))), "iugkp_dev_atomics")
+    return n_threads * per_thread / (ms.value / 1e3)
+
+
 def dev_segments(dim: int, nx: int, ny: int, dx: float, dy: float,
                  rays: torch.Tensor) -> torch.Tensor:
     """Closed-form segment walks on the device: rays (n, 7) float64 rows
