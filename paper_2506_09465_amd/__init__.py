@@ -8,7 +8,7 @@ from ._lib import (EST_ANALOG, EST_EXPECTED, FACES_EVERY, FACES_FINAL, FACES_OFF
                    RNG_FRESH, SCHEME_EMITTERS, SCHEME_PERSISTENT, IugkpError, lib as library)
 
 __all__ = ["Solver", "BatchSolver", "steady_temperature", "d_eff", "dev_philox", "dev_math",
-           "dev_segments", "dev_atomics", "step_group",
+           "dev_segments", "dev_atomics", "step_group", "solve",
            "FACES_EVERY",
            "FACES_FINAL", "FACES_OFF", "RNG_CRN", "RNG_FRESH", "SCHEME_EMITTERS", "EST_ANALOG",
            "EST_EXPECTED",
@@ -18,7 +18,7 @@ __all__ = ["Solver", "BatchSolver", "steady_temperature", "d_eff", "dev_philox",
 def __getattr__(name):
     # torch is imported lazily so that the C-ABI declarations load without it
     if name in ("Solver", "d_eff", "dev_philox", "dev_math", "dev_segments", "dev_atomics",
-                "step_group"):
+                "step_group", "solve"):
         from . import solver
         return getattr(solver, name)
     if name == "BatchSolver":

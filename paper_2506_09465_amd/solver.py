@@ -222,6 +222,18 @@ class Solver:
         return r[:max(k, 0)]
 
 
+def solve(problem, device="cuda", **opts):
+    """Steady state of one problem: (T, (q_x, q_y), stats, status) with T per
+    cell and the heat flux on the x and y faces (device tensors); status is 0
+    or the not-converged warning.  Options as Solver."""
+    s = Solver(problem, device=device, **opts)
+    try:
+        rc, T, qx, qy, st = s.solve()
+    finally:
+        s.close()
+    return T, (qx, qy), st, rc
+
+
 def step_group(solvers: Sequence["Solver"], n: int = 1) -> int:
     """n iterations of several independent solvers, each iteration enqueued on
     all of them before any is waited for; with own_stream=True solvers their

@@ -174,6 +174,9 @@ def test_solve_bitwise_c0(oracle_mod, gpu):
     assert o.info().iter == st["iters"]
     assert np.array_equal(T_o, _np(T_s)) and np.array_equal(qx_o, _np(qx_s))
     assert np.array_equal(o.residuals(st["iters"]), s.residuals())
+    # the one-call form gives the same answer
+    T1, (qx1, _), st1, rc1 = gpu.solve(w, **kw)
+    assert rc1 == 0 and torch.equal(T1, T_s) and torch.equal(qx1, qx_s)
 
 
 def test_solve_bitwise_newton_avg(oracle_mod, gpu):
