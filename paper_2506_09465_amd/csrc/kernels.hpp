@@ -430,6 +430,13 @@ __device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long
   const long long qy = (sty > 0) ? q : -q;
   // steep segments record their y-faces as runs per column
   const bool runs = a.faces && (fabs(sy) > 2.0 * fabs(sx));
+  // pending candidate tallies: n candidates of weight q in cell (cand_x, cand_y)
+  int cand_x = -1, cand_y = -1;
+  long long cand_n = 0;
+  // n q modulo 2^64, the same bits as n separate integer additions
+  auto times = [](long long v, long long n) {
+    return static_cast<long long>(static_cast<unsigned long long>(v) * static_cast<unsigned long long>(n));
+  };
   for (uint32_t j = 0;; ++j) {
     const double2 us = draw2(2u + j, k, e + a.e_off, a.slot, a.key0, a.key1);
     // candidate free path on the common time scale tau_min: -|V_g| tau_min ln(eta)
@@ -488,7 +495,15 @@ __device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long
       add_real(ix, iy, q);   // every candidate is real: W == D
       break;
     }
-    add_cand(ix, iy, q);
+    // candidates in the same cell one after the other are tallied together
+    if (ix == cand_x && iy == cand_y) {
+      ++cand_n;
+    } else {
+      if (cand_n) add_cand(cand_x, cand_y, times(q, cand_n));
+      cand_x = ix;
+      cand_y = iy;
+      cand_n = 1;
+    }
     // accept with probability sigma / sigma_max = tau_min / tau_c
     const int c = ix + m.nx * iy;
     if (us.y < a.ratio[c] || j == kMaxSegments - 1) {
@@ -501,6 +516,7 @@ __device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long
       y0 = clamp_to(y0 + ell * sy, static_cast<double>(iy) * m.dy,
                     static_cast<double>(iy + 1) * m.dy);
   }
+  if (cand_n) add_cand(cand_x, cand_y, times(q, cand_n));
 }
 
 // Expected-value flight of particle k of emitter e carrying q (variance
