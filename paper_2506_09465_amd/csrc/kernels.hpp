@@ -809,7 +809,8 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   const FlyIn fa = {m, in.lam_min, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1, 1,
                     in.has_null, in.ratio, in.e_off};
   const uint32_t N = in.N;
-  const unsigned long long total = static_cast<unsigned long long>(m.n_emit) * N;
+  const unsigned long long n_emit = static_cast<unsigned long long>(m.n_emit);
+  const unsigned long long total = n_emit * N;
   const unsigned long long pb = total * blockIdx.x / chunks;
   const unsigned long long pe = total * (blockIdx.x + 1) / chunks;
   unsigned long long pnext = pb + threadIdx.x;
@@ -867,8 +868,9 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       while (pnext < pe) {
         const unsigned long long pc = pnext;
         pnext += BS;
-        e = static_cast<uint32_t>(pc / N);
-        kk = static_cast<uint32_t>(pc - static_cast<unsigned long long>(e) * N);
+        // emitters fastest: neighbouring lanes start in different cells
+        kk = static_cast<uint32_t>(pc / n_emit);
+        e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
         q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
         if (q != 0) {
           got = true;
