@@ -31,6 +31,13 @@
  *     A the conservative 3/5-point discretisation of -div(D grad .) with
  *     Robin wall terms, D per cell given as problem data.
  *  R7 Residual: res_n = ||E^{n+1} - E^n||_2 / ||E^1 - E^0||_2.
+ *  R19 The paper leaves the linear solver of the Newton step open.  Besides
+ *     plain CG, A is solved by CG preconditioned with one multigrid V-cycle:
+ *     cell-centred 2x2 (2 in 1D) aggregation down to one cell, piecewise
+ *     constant transfers, the Galerkin coarse operator (again a 3/5-point
+ *     operator: a coarse face sums the fine faces it covers), two damped
+ *     Jacobi sweeps (omega 0.8) before and after the coarse correction, the
+ *     correction scaled by 1.8, the one-cell level solved exactly.
  */
 #include "iugkp_oracle.h"
 
@@ -581,6 +588,273 @@ int orc_cg(const orc_problem *p, const double *gx, const double *gy, const doubl
   return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Multigrid V-cycle preconditioner (reading R19).                          */
+/* Level k+1 aggregates 2x2 cells of level k (NX = ceil(nx/2), NY =          */
+/* ceil(ny/2)); with P the piecewise-constant prolongation, the Galerkin     */
+/* operator P^T A P keeps the 3/5-point form: the coarse face between two    */
+/* aggregates carries the sum of the fine faces between them (a wall face the */
+/* sum of the fine wall faces), and the diagonal is again the sum of the     */
+/* cell's four faces.  The V-cycle is symmetric (the same sweeps before and  */
+/* after the correction, R = P^T), so M is a valid CG preconditioner.        */
+/* ------------------------------------------------------------------------ */
+#define ORC_MG_OMEGA 0.8
+#define ORC_MG_SCALE 1.8
+#define ORC_MG_MAX_LEVELS 64
+
+typedef struct {
+  int nx, ny, has_y;
+  const double *gx, *gy, *diag;
+  double *own[3];   /* coarse levels: the arrays allocated here */
+} orc_mg_level;
+
+typedef struct {
+  int L;
+  orc_mg_level lv[ORC_MG_MAX_LEVELS];
+} orc_mg;
+
+static void orc_mg_free(orc_mg *h)
+{
+  for (int k = 0; k < h->L; ++k)
+    for (int j = 0; j < 3; ++j) free(h->lv[k].own[j]);
+}
+
+static void orc_mg_build(const orc_problem *p, const double *gx, const double *gy,
+                         const double *diag, orc_mg *h)
+{
+  memset(h, 0, sizeof(*h));
+  h->L = 1;
+  h->lv[0].nx = p->nx;
+  h->lv[0].ny = p->ny;
+  h->lv[0].has_y = (p->dim == 2);
+  h->lv[0].gx = gx;
+  h->lv[0].gy = gy;
+  h->lv[0].diag = diag;
+  while (!(h->lv[h->L - 1].nx == 1 && h->lv[h->L - 1].ny == 1)) {
+    const orc_mg_level *f = &h->lv[h->L - 1];
+    orc_mg_level *c = &h->lv[h->L];
+    const int nx = f->nx, ny = f->ny, NX = (nx + 1) / 2, NY = (ny + 1) / 2;
+    c->nx = NX;
+    c->ny = NY;
+    c->has_y = f->has_y;
+    double *Gx = (double *)malloc(sizeof(double) * (size_t)NY * (NX + 1));
+    double *Gy = c->has_y ? (double *)malloc(sizeof(double) * (size_t)(NY + 1) * NX) : NULL;
+    double *Dg = (double *)malloc(sizeof(double) * (size_t)NY * NX);
+    for (int J = 0; J < NY; ++J)
+      for (int K = 0; K <= NX; ++K) {
+        const int k = (2 * K < nx) ? 2 * K : nx;   /* the fine face under coarse face K */
+        const double a = f->gx[(2 * J) * (nx + 1) + k];
+        const double b = (2 * J + 1 < ny) ? f->gx[(2 * J + 1) * (nx + 1) + k] : 0.0;
+        Gx[J * (NX + 1) + K] = a + b;
+      }
+    if (c->has_y)
+      for (int K = 0; K <= NY; ++K)
+        for (int I = 0; I < NX; ++I) {
+          const int k = (2 * K < ny) ? 2 * K : ny;
+          const double a = f->gy[k * nx + 2 * I];
+          const double b = (2 * I + 1 < nx) ? f->gy[k * nx + 2 * I + 1] : 0.0;
+          Gy[K * NX + I] = a + b;
+        }
+    for (int J = 0; J < NY; ++J)
+      for (int I = 0; I < NX; ++I) {
+        double d = Gx[J * (NX + 1) + I] + Gx[J * (NX + 1) + I + 1];
+        if (c->has_y) {
+          d = d + Gy[J * NX + I];
+          d = d + Gy[(J + 1) * NX + I];
+        }
+        Dg[J * NX + I] = d;
+      }
+    c->gx = c->own[0] = Gx;
+    c->gy = c->own[1] = Gy;
+    c->diag = c->own[2] = Dg;
+    h->L += 1;
+  }
+}
+
+/* (A_k v)_c in the order diag v_c - g_l v_{c-1} - g_r v_{c+1} - g_dn v_{c-nx}
+ * - g_up v_{c+nx}, absent neighbours skipped (the fine operator's order). */
+static double orc_mg_apply(const orc_mg_level *l, const double *v, int c)
+{
+  const int nx = l->nx, ny = l->ny, iy = c / nx, ix = c - iy * nx;
+  double acc = l->diag[c] * v[c];
+  if (ix > 0) acc = acc - l->gx[iy * (nx + 1) + ix] * v[c - 1];
+  if (ix < nx - 1) acc = acc - l->gx[iy * (nx + 1) + ix + 1] * v[c + 1];
+  if (iy > 0) acc = acc - l->gy[iy * nx + ix] * v[c - nx];
+  if (iy < ny - 1) acc = acc - l->gy[(iy + 1) * nx + ix] * v[c + nx];
+  return acc;
+}
+
+/* one damped Jacobi sweep y = x + omega (b - A x) / diag */
+static void orc_mg_sweep(const orc_mg_level *l, const double *b, const double *x, double *y)
+{
+  const int n = l->nx * l->ny;
+  for (int c = 0; c < n; ++c) {
+    const double t = b[c] - orc_mg_apply(l, x, c);
+    y[c] = x[c] + (ORC_MG_OMEGA * t) / l->diag[c];
+  }
+}
+
+/* x = V-cycle of level k applied to b (zero initial guess) */
+static void orc_mg_vcycle(const orc_mg *h, int k, const double *b, double *x)
+{
+  const orc_mg_level *l = &h->lv[k];
+  const int nx = l->nx, ny = l->ny, n = nx * ny;
+  if (k == h->L - 1) {                       /* one cell: exact */
+    x[0] = b[0] / l->diag[0];
+    return;
+  }
+  const orc_mg_level *cl = &h->lv[k + 1];
+  const int NX = cl->nx, NY = cl->ny, N = NX * NY;
+  double *x0 = (double *)calloc((size_t)n, sizeof(double));
+  double *x1 = (double *)malloc(sizeof(double) * (size_t)n);
+  double *res = (double *)malloc(sizeof(double) * (size_t)n);
+  double *B = (double *)malloc(sizeof(double) * (size_t)N);
+  double *e = (double *)malloc(sizeof(double) * (size_t)N);
+  orc_mg_sweep(l, b, x0, x1);                /* pre-smoothing: x0 = 0 -> x1 -> x0 */
+  orc_mg_sweep(l, b, x1, x0);
+  for (int c = 0; c < n; ++c) res[c] = b[c] - orc_mg_apply(l, x0, c);
+  /* restriction R = P^T: an aggregate sums its children's residuals,
+   * (r(2I,2J) + r(2I+1,2J)) + (r(2I,2J+1) + r(2I+1,2J+1)), absent children 0 */
+  for (int J = 0; J < NY; ++J)
+    for (int I = 0; I < NX; ++I) {
+      double q[4];
+      for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i) {
+          const int ix = 2 * I + i, iy = 2 * J + j;
+          q[2 * j + i] = (ix < nx && iy < ny) ? res[iy * nx + ix] : 0.0;
+        }
+      B[J * NX + I] = (q[0] + q[1]) + (q[2] + q[3]);
+    }
+  orc_mg_vcycle(h, k + 1, B, e);
+  /* scaled coarse correction, then post-smoothing */
+  for (int c = 0; c < n; ++c) {
+    const int iy = c / nx, ix = c - iy * nx;
+    x1[c] = x0[c] + ORC_MG_SCALE * e[(iy / 2) * NX + ix / 2];
+  }
+  orc_mg_sweep(l, b, x1, x0);
+  orc_mg_sweep(l, b, x0, x);
+  free(x0);
+  free(x1);
+  free(res);
+  free(B);
+  free(e);
+}
+
+int orc_mg_precondition(const orc_problem *p, const double *gx, const double *gy,
+                        const double *diag, const double *b, double *x)
+{
+  orc_mg h;
+  orc_mg_build(p, gx, gy, diag, &h);
+  orc_mg_vcycle(&h, 0, b, x);
+  orc_mg_free(&h);
+  return ORC_OK;
+}
+
+int orc_mg_levels(const orc_problem *p, int *nx_out, int *ny_out, int max_levels)
+{
+  int nx = p->nx, ny = p->ny, L = 0;
+  for (;;) {
+    if (L < max_levels) {
+      nx_out[L] = nx;
+      ny_out[L] = ny;
+    }
+    ++L;
+    if (nx == 1 && ny == 1) break;
+    nx = (nx + 1) / 2;
+    ny = (ny + 1) / 2;
+  }
+  return L;
+}
+
+/* Preconditioned CG in the single-reduction form (Chronopoulos and Gear) with
+ * u = M r, w = A u and s = A p carried by recurrence; one reduction of the
+ * three products (r, u), (w, u), (r, r) per iteration.
+ *   x = 0, r = b, u = M r, w = A u, gamma = (r, u), delta = (w, u),
+ *   alpha = gamma / delta
+ *   repeat: p = u + beta p, s = w + beta s (p = u, s = w the first time)
+ *           x = x + alpha p, r = r - alpha s, u = M r, w = A u
+ *           gamma' = (r, u), delta = (w, u), rho = (r, r); stop if rho <= tol^2 (b, b)
+ *           beta = gamma' / gamma, alpha = gamma' / (delta - beta gamma' / alpha)
+ * In exact arithmetic the iterates are those of preconditioned CG. */
+int orc_pcg_mg(const orc_problem *p, const double *gx, const double *gy, const double *diag,
+               const double *b, double *x, double tol, int max_iters, int *iters_out)
+{
+  const int n = p->nx * p->ny;
+  orc_mg h;
+  orc_mg_build(p, gx, gy, diag, &h);
+  const orc_mg_level *l0 = &h.lv[0];
+  double *r = (double *)malloc(sizeof(double) * n);
+  double *u = (double *)malloc(sizeof(double) * n);
+  double *w = (double *)malloc(sizeof(double) * n);
+  double *pp = (double *)malloc(sizeof(double) * n);
+  double *sv = (double *)malloc(sizeof(double) * n);
+  double *tmp = (double *)malloc(sizeof(double) * n);
+  for (int i = 0; i < n; ++i) {
+    x[i] = 0.0;
+    r[i] = b[i];
+  }
+  const double rho0 = orc_dot(r, r, n, tmp);
+  const double thr = (tol * tol) * rho0;
+  int it = 0, rc = ORC_OK, done = (rho0 == 0.0);
+  double alpha = 0.0, beta = 0.0, gamma = 0.0, delta = 0.0;
+  if (!done) {
+    orc_mg_vcycle(&h, 0, r, u);
+    for (int c = 0; c < n; ++c) w[c] = orc_mg_apply(l0, u, c);
+    gamma = orc_dot(r, u, n, tmp);
+    delta = orc_dot(w, u, n, tmp);
+    if (!(delta > 0.0)) rc = ORC_E_CG_BREAKDOWN;
+    else alpha = gamma / delta;
+  }
+  while (!done && rc == ORC_OK && it < max_iters) {
+    for (int i = 0; i < n; ++i) {
+      pp[i] = (it == 0) ? u[i] : u[i] + beta * pp[i];
+      sv[i] = (it == 0) ? w[i] : w[i] + beta * sv[i];
+      x[i] = x[i] + alpha * pp[i];
+      r[i] = r[i] - alpha * sv[i];
+    }
+    orc_mg_vcycle(&h, 0, r, u);
+    for (int c = 0; c < n; ++c) w[c] = orc_mg_apply(l0, u, c);
+    const double gamma_new = orc_dot(r, u, n, tmp);
+    delta = orc_dot(w, u, n, tmp);
+    const double rho = orc_dot(r, r, n, tmp);
+    ++it;
+    if (rho <= thr) {
+      done = 1;
+      break;
+    }
+    beta = gamma_new / gamma;
+    double t = beta * gamma_new;
+    t = t / alpha;
+    const double den = delta - t;
+    if (!(den > 0.0)) {
+      rc = ORC_E_CG_BREAKDOWN;
+      break;
+    }
+    alpha = gamma_new / den;
+    gamma = gamma_new;
+  }
+  if (rc == ORC_OK && !done) rc = ORC_E_CG_NOT_CONVERGED;
+  if (iters_out) *iters_out = it;
+  free(r);
+  free(u);
+  free(w);
+  free(pp);
+  free(sv);
+  free(tmp);
+  orc_mg_free(&h);
+  return rc;
+}
+
+/* The Newton step's linear solve with the configured preconditioner. */
+static int orc_newton_solve(const orc_problem *p, const orc_options *o, const double *gx,
+                            const double *gy, const double *diag, const double *b, double *x,
+                            int *iters_out)
+{
+  if (o->cg_precond == ORC_PRECOND_MG)
+    return orc_pcg_mg(p, gx, gy, diag, b, x, o->cg_tol, o->cg_max_iters, iters_out);
+  return orc_cg(p, gx, gy, diag, b, x, o->cg_tol, o->cg_max_iters, iters_out);
+}
+
 void orc_destroy(orc_state *s)
 {
   if (!s) return;
@@ -607,7 +881,8 @@ int orc_create(const orc_problem *p, const orc_options *o, orc_state **out)
   if (rc) return rc;
   if (p->n_bands > 1) return ORC_E_INVALID_ARG;   /* bands: orc_bands_create */
   if (!o || o->particles_per_iter < 1 || o->max_iters < 0 || o->avg_iters < 0 ||
-      (o->estimator != ORC_EST_ANALOG && o->estimator != ORC_EST_EXPECTED))
+      (o->estimator != ORC_EST_ANALOG && o->estimator != ORC_EST_EXPECTED) ||
+      (o->cg_precond != ORC_PRECOND_NONE && o->cg_precond != ORC_PRECOND_MG))
     return ORC_E_INVALID_ARG;
   if (o->newton && (!p->diff_x || (p->dim == 2 && !p->diff_y) || !(o->cg_tol > 0.0) ||
                     o->cg_max_iters < 1))
@@ -1033,7 +1308,7 @@ static int orc_iterate(orc_state *s, int faces)
     double *x = (double *)malloc(sizeof(double) * s->nc);
     for (int c = 0; c < s->nc; ++c) r[c] = s->E_half[c] - s->E[c];
     int its = 0;
-    rc = orc_cg(p, s->gx, s->gy, s->diag, r, x, s->o.cg_tol, s->o.cg_max_iters, &its);
+    rc = orc_newton_solve(p, &s->o, s->gx, s->gy, s->diag, r, x, &its);
     s->cg_last = its;
     s->cg_total += its;
     for (int c = 0; c < s->nc; ++c) E_new[c] = s->E_half[c] + x[c];
@@ -1256,7 +1531,7 @@ int orc_adjoint(orc_state *s, const double *dLdT, double *grad_wall, double *gra
     if (s->o.newton) {
       for (int c = 0; c < nc; ++c) r[c] = half[c] - psi[c];
       int its = 0;
-      int crc = orc_cg(p, s->gx, s->gy, s->diag, r, x, s->o.cg_tol, s->o.cg_max_iters, &its);
+      int crc = orc_newton_solve(p, &s->o, s->gx, s->gy, s->diag, r, x, &its);
       if (crc) {
         rc = crc;
         break;

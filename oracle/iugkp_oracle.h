@@ -81,7 +81,10 @@ typedef struct orc_options {
   int avg_iters;
   int estimator;        /* ORC_EST_ANALOG: sampled collision points; ORC_EST_EXPECTED: the
                            expected deposits along each ray (gray emitter scheme only) */
+  int cg_precond;       /* ORC_PRECOND_NONE: plain CG; ORC_PRECOND_MG: multigrid V-cycle PCG */
 } orc_options;
+
+enum { ORC_PRECOND_NONE = 0, ORC_PRECOND_MG = 1 };
 
 enum { ORC_EST_ANALOG = 0, ORC_EST_EXPECTED = 1 };
 
@@ -125,6 +128,14 @@ int orc_trace_ray(const orc_problem *p, double x0, double y0, int ix, int iy, do
 int orc_newton_operator(const orc_problem *p, double *gx, double *gy, double *diag);
 int orc_cg(const orc_problem *p, const double *gx, const double *gy, const double *diag,
            const double *b, double *x, double tol, int max_iters, int *iters_out);
+/* The same system by CG preconditioned with one multigrid V-cycle (reading R19). */
+int orc_pcg_mg(const orc_problem *p, const double *gx, const double *gy, const double *diag,
+               const double *b, double *x, double tol, int max_iters, int *iters_out);
+/* x = M b, the V-cycle preconditioner alone. */
+int orc_mg_precondition(const orc_problem *p, const double *gx, const double *gy,
+                        const double *diag, const double *b, double *x);
+/* Number of levels of the hierarchy and the mesh of level k (nx, ny). */
+int orc_mg_levels(const orc_problem *p, int *nx_out, int *ny_out, int max_levels);
 
 /* ---- the iteration ---- */
 int orc_create(const orc_problem *p, const orc_options *o, orc_state **out);

@@ -23,6 +23,7 @@ GCC_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", 
 FRESH, CRN = 0, 1
 FACES_OFF, FACES_EVERY, FACES_FINAL = 0, 1, 2
 ANALOG, EXPECTED = 0, 1
+PRECOND_NONE, PRECOND_MG = 0, 1
 
 OK = 0
 W_NOT_CONVERGED = 1
@@ -57,7 +58,7 @@ class _Options(C.Structure):
                 ("rng_mode", C.c_int), ("rng_epoch", C.c_uint32), ("max_iters", C.c_int),
                 ("res_tol", C.c_double), ("newton", C.c_int), ("cg_tol", C.c_double),
                 ("cg_max_iters", C.c_int), ("tally_faces", C.c_int), ("avg_iters", C.c_int),
-                ("estimator", C.c_int)]
+                ("estimator", C.c_int), ("cg_precond", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -101,6 +102,9 @@ def lib():
         L.orc_trace_ray.restype = C.c_int
         L.orc_newton_operator.argtypes = [C.POINTER(_Problem), P, P, P]
         L.orc_cg.argtypes = [C.POINTER(_Problem), P, P, P, P, P, C.c_double, C.c_int, P]
+        L.orc_pcg_mg.argtypes = [C.POINTER(_Problem), P, P, P, P, P, C.c_double, C.c_int, P]
+        L.orc_mg_precondition.argtypes = [C.POINTER(_Problem), P, P, P, P, P]
+        L.orc_mg_levels.argtypes = [C.POINTER(_Problem), P, P, C.c_int]
         L.orc_create.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), C.POINTER(P)]
         L.orc_destroy.argtypes = [P]
         L.orc_step.argtypes = [P, C.c_int, C.c_int]
@@ -236,15 +240,36 @@ def newton_operator(w, diff_x, diff_y=None):
     return gx, gy, dg
 
 
-def cg(w, diff_x, diff_y, b, tol=1e-10, max_iters=100000):
+def cg(w, diff_x, diff_y, b, tol=1e-10, max_iters=100000, precond=PRECOND_NONE):
     k = _Keep(w, diff_x, diff_y)
     gx, gy, dg = newton_operator(w, diff_x, diff_y)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros_like(b)
     its = C.c_int(0)
-    rc = lib().orc_cg(C.byref(k.p), gx.ctypes.data, gy.ctypes.data, dg.ctypes.data,
-                      b.ctypes.data, x.ctypes.data, tol, max_iters, C.addressof(its))
+    f = lib().orc_pcg_mg if precond == PRECOND_MG else lib().orc_cg
+    rc = f(C.byref(k.p), gx.ctypes.data, gy.ctypes.data, dg.ctypes.data,
+           b.ctypes.data, x.ctypes.data, tol, max_iters, C.addressof(its))
     return rc, x, its.value
+
+
+def mg_precondition(w, diff_x, diff_y, b):
+    """x = M b: one V-cycle of the multigrid preconditioner."""
+    k = _Keep(w, diff_x, diff_y)
+    gx, gy, dg = newton_operator(w, diff_x, diff_y)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    lib().orc_mg_precondition(C.byref(k.p), gx.ctypes.data, gy.ctypes.data, dg.ctypes.data,
+                              b.ctypes.data, x.ctypes.data)
+    return x
+
+
+def mg_levels(w):
+    """(nx, ny) of every level of the multigrid hierarchy."""
+    k = _Keep(w, None, None)
+    nx = np.zeros(64, dtype=np.int32)
+    ny = np.zeros(64, dtype=np.int32)
+    L = lib().orc_mg_levels(C.byref(k.p), nx.ctypes.data, ny.ctypes.data, 64)
+    return list(zip(nx[:L].tolist(), ny[:L].tolist()))
 
 
 # ---------------------------------------------------------------- the iteration
@@ -282,7 +307,7 @@ class Oracle:
     def __init__(self, w, *, seed=None, particles=None, rng_mode=FRESH, epoch=0,
                  max_iters=None, res_tol=None, newton=None, diff_x=None, diff_y=None,
                  cg_tol=None, cg_max_iters=200000, tally_faces=FACES_EVERY, avg_iters=0,
-                 T_init=None, estimator=0):
+                 T_init=None, estimator=0, cg_precond=0):
         self.w = w
         newton = w.newton if newton is None else newton
         self._keep = _Keep(w, diff_x, diff_y, T_init)
@@ -291,7 +316,7 @@ class Oracle:
                              rng_mode, epoch, w.max_iters if max_iters is None else max_iters,
                              w.res_tol if res_tol is None else res_tol, int(bool(newton)),
                              w.cg_tol if cg_tol is None else cg_tol, cg_max_iters, tally_faces,
-                             avg_iters, int(estimator))
+                             avg_iters, int(estimator), int(cg_precond))
         h = C.c_void_p()
         rc = lib().orc_create(C.byref(self._keep.p), C.byref(self.opts), C.byref(h))
         if rc != OK:
