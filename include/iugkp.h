@@ -168,7 +168,16 @@ typedef struct iugkp_options {
                                    ordered with the null stream) and destroys it with the
                                    handle; the stream argument is ignored.  Handles with their
                                    own streams advance concurrently under iugkp_step_group */
+  int cg_precond;               /* linear solver of the Newton step (Sec. 3.3 leaves it open):
+                                   IUGKP_PRECOND_NONE (0) plain CG; IUGKP_PRECOND_MG (1), single
+                                   solves only: CG preconditioned with one multigrid V-cycle
+                                   (2x2 aggregation down to one cell, Galerkin coarse
+                                   operators, two damped Jacobi sweeps with weight 0.8 before
+                                   and after the coarse correction scaled by 1.8, the one-cell
+                                   level solved exactly).  Both stop at the same rule */
 } iugkp_options;
+
+enum { IUGKP_PRECOND_NONE = 0, IUGKP_PRECOND_MG = 1 };
 
 enum { IUGKP_SCHEME_EMITTERS = 0, IUGKP_SCHEME_PERSISTENT = 1 };
 enum { IUGKP_EST_ANALOG = 0, IUGKP_EST_EXPECTED = 1 };

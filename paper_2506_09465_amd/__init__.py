@@ -4,14 +4,15 @@
 The compute path is the HIP library libiugkp.so (C ABI in include/iugkp.h);
 this package only marshals arguments to it.
 """
-from ._lib import (EST_ANALOG, EST_EXPECTED, FACES_EVERY, FACES_FINAL, FACES_OFF, RNG_CRN,
-                   RNG_FRESH, SCHEME_EMITTERS, SCHEME_PERSISTENT, IugkpError, lib as library)
+from ._lib import (EST_ANALOG, EST_EXPECTED, FACES_EVERY, FACES_FINAL, FACES_OFF, PRECOND_MG,
+                   PRECOND_NONE, RNG_CRN, RNG_FRESH, SCHEME_EMITTERS, SCHEME_PERSISTENT,
+                   IugkpError, lib as library)
 
 __all__ = ["Solver", "BatchSolver", "steady_temperature", "d_eff", "dev_philox", "dev_math",
            "dev_segments", "dev_atomics", "step_group", "solve",
            "FACES_EVERY",
            "FACES_FINAL", "FACES_OFF", "RNG_CRN", "RNG_FRESH", "SCHEME_EMITTERS", "EST_ANALOG",
-           "EST_EXPECTED",
+           "EST_EXPECTED", "PRECOND_NONE", "PRECOND_MG",
            "SCHEME_PERSISTENT", "IugkpError", "library"]
 
 

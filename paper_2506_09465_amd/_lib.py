@@ -23,6 +23,7 @@ RNG_FRESH, RNG_CRN = 0, 1
 FACES_OFF, FACES_EVERY, FACES_FINAL = 0, 1, 2
 SCHEME_EMITTERS, SCHEME_PERSISTENT = 0, 1
 EST_ANALOG, EST_EXPECTED = 0, 1
+PRECOND_NONE, PRECOND_MG = 0, 1
 
 
 class Problem(C.Structure):
@@ -40,7 +41,8 @@ class Options(C.Structure):
                 ("res_tol", C.c_double), ("newton", C.c_int), ("cg_tol", C.c_double),
                 ("cg_max_iters", C.c_int), ("tally_faces", C.c_int), ("avg_iters", C.c_int),
                 ("block_size", C.c_int), ("march", C.c_int), ("cg_waves", C.c_int),
-                ("scheme", C.c_int), ("estimator", C.c_int), ("own_stream", C.c_int)]
+                ("scheme", C.c_int), ("estimator", C.c_int), ("own_stream", C.c_int),
+                ("cg_precond", C.c_int)]
 
 
 class Stats(C.Structure):

@@ -24,6 +24,7 @@
 #include "../../include/iugkp.h"
 #include "host_math.hpp"
 #include "kernels.hpp"
+#include "mgcg.hpp"
 
 namespace {
 
@@ -89,6 +90,10 @@ struct InstHost {
   unsigned int *cg_barrier = nullptr;
   int cg_grid = 1, cg_tb = 1, cg_reg = 1, cg_threads = 64;
   size_t cg_lds = 0;
+  // multigrid-preconditioned CG (cg_precond == IUGKP_PRECOND_MG): level table
+  int mg_L = 0, mg_Lg = 0, mg_grid = 1, mg_threads = 64;
+  size_t mg_lds = 0;
+  iugkp::MGLevel *mg_lv = nullptr;
   // row-stripe particle step for face-tallied iterations (single solves)
   int stripe_R = 0, stripe_S = 0, stripe_C = 0;
   size_t stripe_lds = 0;
@@ -156,6 +161,8 @@ int check_options(const iugkp_options *o)
     return fail(IUGKP_E_INVALID_ARG, "bad estimator");
   if (o->estimator == IUGKP_EST_EXPECTED && o->scheme != IUGKP_SCHEME_EMITTERS)
     return fail(IUGKP_E_INVALID_ARG, "the expected-value estimator is for the emitter scheme");
+  if (o->cg_precond != IUGKP_PRECOND_NONE && o->cg_precond != IUGKP_PRECOND_MG)
+    return fail(IUGKP_E_INVALID_ARG, "bad cg_precond");
   return IUGKP_OK;
 }
 
@@ -350,6 +357,106 @@ int setup_persistent(InstHost &ih, const std::vector<double> &T0, const std::vec
   iugkp::persist_init_kernel<<<cdiv(static_cast<long long>(n), 256), 256, 0, s>>>(dinst, dg0);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
+  return IUGKP_OK;
+}
+
+// The multigrid hierarchy of the Newton operator: level sizes (halved, rounded
+// up, down to one cell), the coarse operators built on the device, the
+// vectors of the levels spread over the group, the LDS layout of the small
+// levels, and the group's launch shape.
+int setup_mg(InstHost &ih, const iugkp_options *o, hipStream_t s)
+{
+  const Mesh &m = ih.d.m;
+  const int has_y = (m.dim == 2) ? 1 : 0;
+  std::vector<iugkp::MGLevel> lv;
+  for (int nx = m.nx, ny = m.ny;;) {
+    iugkp::MGLevel l{};
+    l.nx = nx;
+    l.ny = ny;
+    l.n = nx * ny;
+    l.has_y = has_y;
+    lv.push_back(l);
+    if (nx == 1 && ny == 1) break;
+    nx = (nx + 1) / 2;
+    ny = (ny + 1) / 2;
+  }
+  const int L = static_cast<int>(lv.size());
+  if (L > iugkp::kMgLevelsMax) return fail(IUGKP_E_INVALID_ARG, "mesh too large for the multigrid");
+  // the levels from Lg on live in every workgroup's LDS (three vectors and
+  // the five row coefficients per cell): from the first of at most
+  // kMgLocalMax cells, or a later one when LDS is short
+  int dev = 0, n_cu = 0, lds_max = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const size_t lds_budget = static_cast<size_t>(lds_max) - 8 * 1024;   // static: reductions
+  auto local_bytes = [&](int from) {
+    size_t w = 0;
+    for (int k = from; k < L; ++k) w += 8 * static_cast<size_t>(lv[k].n);
+    return w * sizeof(double);
+  };
+  int Lg = 0;
+  while (Lg < L && lv[Lg].n > iugkp::kMgLocalMax) ++Lg;
+  while (Lg < L - 1 && local_bytes(Lg) > lds_budget) ++Lg;
+  if (local_bytes(Lg) > lds_budget) return fail(IUGKP_E_DEVICE, "no LDS for the multigrid");
+#define ALLOC(ptr, cnt) \
+  do { if (ih.alloc(&(ptr), (cnt)) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed"); } while (0)
+  lv[0].gx = ih.gx;
+  lv[0].gy = ih.gy;
+  lv[0].diag = ih.diag;
+  for (int k = 1; k < L; ++k) {
+    double *gx = nullptr, *gy = nullptr, *dg = nullptr;
+    ALLOC(gx, static_cast<size_t>(lv[k].ny) * (lv[k].nx + 1));
+    if (has_y) ALLOC(gy, static_cast<size_t>(lv[k].ny + 1) * lv[k].nx);
+    ALLOC(dg, lv[k].n);
+    lv[k].gx = gx;
+    lv[k].gy = has_y ? gy : ih.gy;      // 1D: a valid array that is never read from
+    lv[k].diag = dg;
+  }
+  ALLOC(lv[0].b, lv[0].n);                 // r, read by the whole group
+  for (int k = 0; k < Lg; ++k) {
+    if (k > 0) ALLOC(lv[k].b, lv[k].n);
+    ALLOC(lv[k].xa, lv[k].n);
+    ALLOC(lv[k].xb, lv[k].n);
+    ALLOC(lv[k].xd, lv[k].n);
+    ALLOC(lv[k].e, lv[k].n);
+  }
+  if (Lg > 0) ALLOC(lv[Lg].b, lv[Lg].n);
+  int off = 0;
+  for (int k = Lg; k < L; ++k) {
+    lv[k].lb = off;
+    lv[k].lx = off + lv[k].n;
+    lv[k].lt = off + 2 * lv[k].n;
+    lv[k].lc = off + 3 * lv[k].n;
+    off += 8 * lv[k].n;
+  }
+  for (int k = 0; k + 1 < L; ++k) {
+    const int nf = std::max(lv[k + 1].ny * (lv[k + 1].nx + 1), (lv[k + 1].ny + 1) * lv[k + 1].nx);
+    iugkp::mg_coarsen_faces_kernel<<<cdiv(nf, 256), 256, 0, s>>>(
+        lv[k], lv[k + 1], has_y, const_cast<double *>(lv[k + 1].gx),
+        const_cast<double *>(lv[k + 1].gy));
+    iugkp::mg_coarsen_diag_kernel<<<cdiv(lv[k + 1].n, 256), 256, 0, s>>>(
+        lv[k + 1], has_y, const_cast<double *>(lv[k + 1].diag));
+  }
+  HIP_TRY(hipGetLastError());
+  ALLOC(ih.mg_lv, L);
+#undef ALLOC
+  HIP_TRY(hipMemcpyAsync(ih.mg_lv, lv.data(), L * sizeof(iugkp::MGLevel), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int waves = o->cg_waves != 0 ? std::abs(o->cg_waves) : kCgWavesDefault;
+  const int nb0 = cdiv(lv[0].n, iugkp::kTree);
+  const int G = std::max(1, std::min(std::min(cdiv(nb0, waves), kCgGridMax), n_cu));
+  const size_t lds = static_cast<size_t>(off) * sizeof(double);
+  int per_cu = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void *>(iugkp::mgcg_kernel), 64 * waves, lds));
+  if (per_cu < 1 || G > per_cu * n_cu)
+    return fail(IUGKP_E_DEVICE, "multigrid CG workgroups cannot all be resident");
+  ih.mg_L = L;
+  ih.mg_Lg = Lg;
+  ih.mg_grid = G;
+  ih.mg_threads = 64 * waves;
+  ih.mg_lds = lds;
   return IUGKP_OK;
 }
 
@@ -581,6 +688,9 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
       ih.cg_reg = reg;
       ih.cg_threads = threads;
       ih.cg_lds = lds;
+      if (o->cg_precond == IUGKP_PRECOND_MG && (rc = setup_mg(ih, o, s))) return rc;
+    } else if (o->cg_precond == IUGKP_PRECOND_MG) {
+      return fail(IUGKP_E_INVALID_ARG, "the multigrid preconditioner is for single solves");
     }
   }
   // (expected-value rays: only on request, march == 2; every stripe follows a
@@ -1098,6 +1208,29 @@ struct DevScratch {
 int enqueue_cg(const InstHost &ih, const double *b, double *x, DevScalars *sc, hipStream_t s,
                hipEvent_t ev_a, hipEvent_t ev_b)
 {
+  if (ih.mg_L > 0) {
+    iugkp::MGArgs ma;
+    ma.lv = ih.mg_lv;
+    ma.L = ih.mg_L;
+    ma.Lg = ih.mg_Lg;
+    ma.b = b;
+    ma.x = x;
+    ma.p = ih.d.cg_p;
+    ma.s = ih.d.cg_s;
+    ma.w = ih.d.cg_w;
+    ma.part = ih.cg_mpart;
+    ma.tol2 = ih.d.tol2;
+    ma.max_iters = ih.d.cg_max;
+    ma.barrier = ih.cg_barrier;
+    ma.sc = sc;
+    iugkp::zero_u32_kernel<<<1, 64, 0, s>>>(ih.cg_barrier, 2);
+    if (ev_a) HIP_TRY(hipEventRecord(ev_a, s));
+    void *args[] = {&ma};
+    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(iugkp::mgcg_kernel),
+                                       dim3(ih.mg_grid), dim3(ih.mg_threads), args, ih.mg_lds, s));
+    if (ev_b) HIP_TRY(hipEventRecord(ev_b, s));
+    return IUGKP_OK;
+  }
   iugkp::CGArgs ca;
   ca.m = ih.d.m;
   ca.gx = ih.gx;

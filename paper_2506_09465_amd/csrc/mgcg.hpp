@@ -1,0 +1,639 @@
+// mgcg.hpp -- the Newton system A x = b (Sec. 3.3) solved by conjugate
+// gradients preconditioned with one multigrid V-cycle, as one persistent
+// cooperative launch.
+//
+// The hierarchy: level k+1 aggregates 2x2 cells of level k (NX = ceil(nx/2),
+// NY = ceil(ny/2)) down to one cell; the coarse operator is the Galerkin
+// product P^T A P for the piecewise-constant prolongation P, again a 3/5-point
+// operator whose faces sum the fine faces they cover.  The V-cycle: two damped
+// Jacobi sweeps (omega 0.8) from zero, the residual summed over each
+// aggregate, the coarser V-cycle, the correction scaled by 1.8, two sweeps
+// again; the one-cell level is solved exactly.  The CG is the single-reduction
+// form of Chronopoulos and Gear with u = M r:
+//   x = 0, r = b, u = M r, w = A u, gamma = (r, u), delta = (w, u)
+//   repeat: p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s,
+//           u = M r, w = A u, gamma' = (r, u), delta = (w, u), rho = (r, r);
+//           stop if rho <= tol^2 (b, b); beta = gamma' / gamma,
+//           alpha = gamma' / (delta - beta gamma' / alpha)
+// Every operation is written in the order the host-side definition fixes, so
+// the result does not depend on the launch shape.
+//
+// Work split.  Levels with more than kMgLocalMax cells ("grid levels") are
+// spread over all G workgroups: wave v of the group takes the 256-cell blocks
+// v, v + G waves, ... of the level, lane l the cells l + 64 q of a block.  A
+// phase reads what other workgroups wrote in the phase before it, behind a
+// group barrier, with coherent loads (xld / xst).  Per grid level the descent
+// takes two phases (second pre-sweep; residual and restriction, which also
+// does the first sweep of the next level) and the ascent two (correction with
+// the first post-sweep; second post-sweep).  The remaining small levels run
+// redundantly in every workgroup's LDS, so the coarse solve needs no barrier
+// of its own and its result is at hand wherever the next grid level needs it.
+#pragma once
+
+#include <type_traits>
+
+namespace iugkp {
+
+constexpr double kMgOmega = 0.8;        // damped Jacobi weight
+constexpr double kMgScale = 1.8;        // coarse-correction scale
+constexpr int kMgLevelsMax = 40;
+constexpr int kMgLocalMax = 1024;       // levels up to this size live in LDS
+
+struct MGLevel {
+  int nx, ny, n, has_y;
+  const double *gx, *gy, *diag;         // operator of the level
+  double *b, *xa, *xb, *xd, *e;         // grid levels (level 0: b = r, e = u)
+  int lb, lx, lt, lc;                   // LDS levels: offsets (doubles) of b, x, t and
+                                        // of the rows (5 doubles per cell)
+};
+
+struct MGArgs {
+  const MGLevel *lv;                    // [L] level table
+  int L, Lg;                            // levels; levels 0..Lg-1 are grid levels
+  const double *b;                      // right-hand side
+  double *x, *p, *s, *w;                // solution and the own-cell CG state
+  double *part;                         // [nb][3] block sums of (r, u), (w, u), (r, r)
+  double tol2;
+  int max_iters;
+  unsigned int *barrier;                // [2], zero at the start of the solve
+  DevScalars *sc;
+};
+
+// Row c of A_k: the diagonal, the four face conductances and the neighbour
+// indices, an absent neighbour's index clamped to c itself.  Every load is
+// unconditional, so a cell's loads issue together instead of one latency per
+// neighbour.
+struct MGRow {
+  double dg, gl, gr, gd, gu;
+  int jl, jr, jd, ju;
+  unsigned m;                           // left, right, down, up neighbour present
+};
+
+__device__ __forceinline__ MGRow mg_row(const MGLevel &l, int c)
+{
+  const int nx = l.nx, iy = c / nx, ix = c - iy * nx;
+  MGRow r;
+  r.m = (ix > 0 ? 1u : 0u) | (ix < nx - 1 ? 2u : 0u) | (iy > 0 ? 4u : 0u) |
+        (iy < l.ny - 1 ? 8u : 0u);
+  r.jl = (r.m & 1u) ? c - 1 : c;
+  r.jr = (r.m & 2u) ? c + 1 : c;
+  r.jd = (r.m & 4u) ? c - nx : c;
+  r.ju = (r.m & 8u) ? c + nx : c;
+  const int fx = iy * (nx + 1) + ix;
+  r.dg = l.diag[c];
+  r.gl = l.gx[fx];
+  r.gr = l.gx[fx + 1];
+  r.gd = l.gy[l.has_y ? iy * nx + ix : 0];       // (1D: a valid dummy, never used)
+  r.gu = l.gy[l.has_y ? (iy + 1) * nx + ix : 0];
+  return r;
+}
+
+// the same row of an LDS level, whose coefficients sit in LDS
+__device__ __forceinline__ MGRow mg_row_lds(const MGLevel &l, const double *lds, int c)
+{
+  const int nx = l.nx, iy = c / nx, ix = c - iy * nx;
+  MGRow r;
+  r.m = (ix > 0 ? 1u : 0u) | (ix < nx - 1 ? 2u : 0u) | (iy > 0 ? 4u : 0u) |
+        (iy < l.ny - 1 ? 8u : 0u);
+  r.jl = (r.m & 1u) ? c - 1 : c;
+  r.jr = (r.m & 2u) ? c + 1 : c;
+  r.jd = (r.m & 4u) ? c - nx : c;
+  r.ju = (r.m & 8u) ? c + nx : c;
+  const double *k = lds + l.lc + 5 * c;
+  r.dg = k[0];
+  r.gl = k[1];
+  r.gr = k[2];
+  r.gd = k[3];
+  r.gu = k[4];
+  return r;
+}
+
+// (A_k v)_c: diag v_c - g_l v_{c-1} - g_r v_{c+1} - g_dn v_{c-nx} - g_up v_{c+nx},
+// absent neighbours skipped (their term computed on a clamped value and
+// discarded)
+template <class Get>
+__device__ __forceinline__ double mg_apply_row(const MGRow &r, int c, Get v)
+{
+  const double vc = v(c), vl = v(r.jl), vr = v(r.jr), vd = v(r.jd), vu = v(r.ju);
+  double acc = r.dg * vc;
+  const double a1 = acc - r.gl * vl;
+  acc = (r.m & 1u) ? a1 : acc;
+  const double a2 = acc - r.gr * vr;
+  acc = (r.m & 2u) ? a2 : acc;
+  const double a3 = acc - r.gd * vd;
+  acc = (r.m & 4u) ? a3 : acc;
+  const double a4 = acc - r.gu * vu;
+  acc = (r.m & 8u) ? a4 : acc;
+  return acc;
+}
+
+// the same on values already loaded: v = {v_c, v_l, v_r, v_dn, v_up}
+__device__ __forceinline__ double mg_apply_vals(const MGRow &r, const double (&v)[5])
+{
+  double acc = r.dg * v[0];
+  const double a1 = acc - r.gl * v[1];
+  acc = (r.m & 1u) ? a1 : acc;
+  const double a2 = acc - r.gr * v[2];
+  acc = (r.m & 2u) ? a2 : acc;
+  const double a3 = acc - r.gd * v[3];
+  acc = (r.m & 4u) ? a3 : acc;
+  const double a4 = acc - r.gu * v[4];
+  acc = (r.m & 8u) ? a4 : acc;
+  return acc;
+}
+
+template <class Get>
+__device__ __forceinline__ double mg_apply(const MGLevel &l, int c, Get v)
+{
+  return mg_apply_row(mg_row(l, c), c, v);
+}
+
+// aggregate of cell c of level f on the next level (nxc columns)
+__device__ __forceinline__ int mg_parent(int c, int nxf, int nxc)
+{
+  const int iy = c / nxf, ix = c - iy * nxf;
+  return (iy >> 1) * nxc + (ix >> 1);
+}
+
+// Sum over an aggregate of the children's values, (v(2I,2J) + v(2I+1,2J)) +
+// (v(2I,2J+1) + v(2I+1,2J+1)), absent children 0 (evaluated on a clamped
+// child and discarded, so the loads of all four issue together).
+template <class Get>
+__device__ __forceinline__ double mg_restrict(int C, int nxc, int nxf, int nyf, Get v)
+{
+  const int J = C / nxc, I = C - J * nxc;
+  double q[4];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int ix = 2 * I + i, iy = 2 * J + j;
+      const bool in = (ix < nxf && iy < nyf);
+      const double val = v(in ? iy * nxf + ix : (2 * J) * nxf + 2 * I);
+      q[2 * j + i] = in ? val : 0.0;
+    }
+  return (q[0] + q[1]) + (q[2] + q[3]);
+}
+
+// Sums of the nb published NV-tuples (layout [nb][NV]) in the fixed order of
+// the host-side definition: the 256-element tree over each chunk, then over
+// the chunk sums (nb <= 65536).  Every thread gets every result.
+template <int NV>
+__device__ __forceinline__ void group_tree_n(const double *part, int nb, double *red,
+                                             double (&out)[NV])
+{
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int nch = (nb + kTree - 1) / kTree;
+  auto chunk = [&](int k, double (&r)[NV]) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = k * kTree + lane + 64 * q;
+        v[q] = i < nb ? xld(&part[NV * i + j]) : 0.0;
+      }
+      r[j] = wave_tree256(v[0], v[1], v[2], v[3]);
+    }
+  };
+  if (nch == 1) {
+    double r[NV];
+    chunk(0, r);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) out[j] = lane0(r[j]);
+    return;
+  }
+  for (int k = wave; k < nch; k += nw) {
+    double r[NV];
+    chunk(k, r);
+    if (lane == 0)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) red[j * kTree + k] = r[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = lane + 64 * q;
+      v[q] = k < nch ? red[j * kTree + k] : 0.0;
+    }
+    out[j] = lane0(wave_tree256(v[0], v[1], v[2], v[3]));
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
+{
+  extern __shared__ double lds[];
+  __shared__ double red[3 * kTree];
+  const int G = gridDim.x;
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gwv = blockIdx.x * nw + wave, gstride = G * nw;
+  const int L = a.L, Lg = a.Lg;
+  const MGLevel *lv = a.lv;
+  const MGLevel L0 = lv[0];
+  const int n = L0.n, nb = (n + kTree - 1) / kTree;
+  unsigned int epoch = 0;
+
+  auto bar = [&]() -> bool {
+    if (G == 1) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      return true;
+    }
+    return grid_barrier(a.barrier, epoch, G);
+  };
+  // The cells of a grid level this thread owns, Q of a block at a time: the Q
+  // are computed first (an index past the end replaced by the block's first
+  // cell), then the valid ones stored, so a batch's loads issue before its
+  // first store.  Q trades loads in flight against registers.
+  auto for_cells = [&](auto Qc, int nl, auto compute, auto store) {
+    constexpr int Q = decltype(Qc)::value;
+    const int nbl = (nl + kTree - 1) / kTree;
+    for (int blk = gwv; blk < nbl; blk += gstride)
+#pragma unroll 1
+      for (int q0 = 0; q0 < 4; q0 += Q) {
+        using R = decltype(compute(0));
+        R v[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int c = blk * kTree + lane + 64 * (q0 + q);
+          v[q] = compute(c < nl ? c : blk * kTree);
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int c = blk * kTree + lane + 64 * (q0 + q);
+          if (c < nl) store(c, v[q]);
+        }
+      }
+  };
+  using Q1 = std::integral_constant<int, 1>;
+  using Q2 = std::integral_constant<int, 2>;
+  using Q4 = std::integral_constant<int, 4>;
+  // A phase that touches no own-cell state: the cells of the level spread
+  // over every thread of the group (consecutive threads, consecutive cells),
+  // two at a time when the level has more cells than the group has threads.
+  const int nthr = G * static_cast<int>(blockDim.x);
+  const int tid = blockIdx.x * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
+  auto for_flat = [&](auto Qmax, int nl, auto compute, auto store) {
+    auto run = [&](auto Qc) {
+      constexpr int Q = decltype(Qc)::value;
+      for (int c0 = tid; c0 < nl; c0 += Q * nthr) {
+        using R = decltype(compute(0));
+        R v[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int c = c0 + q * nthr;
+          v[q] = compute(c < nl ? c : c0);
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int c = c0 + q * nthr;
+          if (c < nl) store(c, v[q]);
+        }
+      }
+    };
+    if (decltype(Qmax)::value > 1 && nl > nthr) run(std::integral_constant<int, 2>{});
+    else run(std::integral_constant<int, 1>{});
+  };
+  // an LDS level, one cell per thread at a time, then a workgroup barrier
+  auto for_local = [&](int nl, auto compute, auto store) {
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) store(i, compute(i));
+    __syncthreads();
+  };
+  auto sweep_first = [&](double bv, double dg) { return 0.0 + (kMgOmega * bv) / dg; };
+  struct V2 {
+    double a, b;
+  };
+
+  // rows of the LDS levels, once per solve
+  for (int k = Lg; k < L; ++k) {
+    const MGLevel F = lv[k];
+    for (int i = threadIdx.x; i < F.n; i += blockDim.x) {
+      const MGRow r = mg_row(F, i);
+      double *dst = lds + F.lc + 5 * i;
+      dst[0] = r.dg;
+      dst[1] = r.gl;
+      dst[2] = r.gr;
+      dst[3] = r.gd;
+      dst[4] = r.gu;
+    }
+  }
+  __syncthreads();
+
+  // the V-cycle on r (published as lv[0].b, and lv[0].xa = the first sweep
+  // when level 0 is a grid level); u ends in lv[0].e, or in LDS when Lg = 0
+  auto vcycle = [&]() -> bool {
+    for (int k = 0; k < Lg; ++k) {
+      const MGLevel F = lv[k];
+      for_flat(
+          Q2{}, F.n,
+          [&](int c) {
+            auto xa = [&](int j) { return xld(&F.xa[j]); };
+            const MGRow r = mg_row(F, c);
+            const double t = xld(&F.b[c]) - mg_apply_row(r, c, xa);
+            return xa(c) + (kMgOmega * t) / r.dg;
+          },
+          [&](int c, double v) { xst(&F.xb[c], v); });
+      if (!bar()) return false;
+      const MGLevel Cl = lv[k + 1];
+      const bool grid_next = (k + 1 < Lg);
+      for_flat(
+          Q1{}, Cl.n,
+          [&](int C) {
+            // the four children (absent ones clamped to the first and
+            // discarded): every row and value loaded before any arithmetic
+            const int J = C / Cl.nx, I = C - J * Cl.nx;
+            MGRow rw[4];
+            double bv[4], xv[4][5];
+            bool in[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int ix = 2 * I + (k & 1), iy = 2 * J + (k >> 1);
+              in[k] = (ix < F.nx && iy < F.ny);
+              const int f = in[k] ? iy * F.nx + ix : (2 * J) * F.nx + 2 * I;
+              rw[k] = mg_row(F, f);
+              bv[k] = xld(&F.b[f]);
+              xv[k][0] = xld(&F.xb[f]);
+              xv[k][1] = xld(&F.xb[rw[k].jl]);
+              xv[k][2] = xld(&F.xb[rw[k].jr]);
+              xv[k][3] = xld(&F.xb[rw[k].jd]);
+              xv[k][4] = xld(&F.xb[rw[k].ju]);
+            }
+            double q[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const double res = bv[k] - mg_apply_vals(rw[k], xv[k]);
+              q[k] = in[k] ? res : 0.0;
+            }
+            const double B = (q[0] + q[1]) + (q[2] + q[3]);
+            return V2{B, sweep_first(B, Cl.diag[C])};
+          },
+          [&](int C, V2 v) {
+            xst(&Cl.b[C], v.a);
+            if (grid_next) xst(&Cl.xa[C], v.b);
+          });
+      if (!bar()) return false;
+    }
+    // the LDS levels, in every workgroup.  Descent: b of level Lg loaded
+    // with its first sweep; per level the second sweep, then the restriction
+    // with the next level's first sweep (the one-cell level: its exact
+    // solve).  Ascent: the correction fused into the first post-sweep (the
+    // neighbours' corrected values recomputed), the second post-sweep.  Each
+    // level's result ends in its t vector.
+    {
+      const MGLevel T = lv[Lg];
+      for_local(
+          T.n,
+          [&](int i) {
+            const double bv = xld(&T.b[i]);
+            return V2{bv, sweep_first(bv, lds[T.lc + 5 * i])};
+          },
+          [&](int i, V2 v) {
+            lds[T.lb + i] = v.a;
+            if (L - 1 > Lg) lds[T.lx + i] = v.b;
+            else lds[T.lt + i] = v.a / lds[T.lc + 5 * i];
+          });
+      for (int k = Lg; k < L - 1; ++k) {
+        const MGLevel F = lv[k], Cl = lv[k + 1];
+        const double *B = lds + F.lb, *X = lds + F.lx;
+        double *Tm = lds + F.lt;
+        for_local(
+            F.n,
+            [&](int i) {
+              const MGRow r = mg_row_lds(F, lds, i);
+              const double t = B[i] - mg_apply_row(r, i, [&](int j) { return X[j]; });
+              return X[i] + (kMgOmega * t) / r.dg;
+            },
+            [&](int i, double v) { Tm[i] = v; });
+        const bool last = (k + 1 == L - 1);
+        for_local(
+            Cl.n,
+            [&](int C) {
+              return mg_restrict(C, Cl.nx, F.nx, F.ny, [&](int f) {
+                return B[f] - mg_apply_row(mg_row_lds(F, lds, f), f, [&](int j) { return Tm[j]; });
+              });
+            },
+            [&](int C, double v) {
+              lds[Cl.lb + C] = v;
+              const double dg = lds[Cl.lc + 5 * C];
+              if (last) lds[Cl.lt + C] = v / dg;
+              else lds[Cl.lx + C] = sweep_first(v, dg);
+            });
+      }
+      for (int k = L - 2; k >= Lg; --k) {
+        const MGLevel F = lv[k], Cl = lv[k + 1];
+        const double *B = lds + F.lb, *E = lds + Cl.lt;
+        double *X = lds + F.lx, *Tm = lds + F.lt;
+        for_local(
+            F.n,
+            [&](int i) {
+              const MGRow r = mg_row_lds(F, lds, i);
+              auto xc = [&](int j) { return Tm[j] + kMgScale * E[mg_parent(j, F.nx, Cl.nx)]; };
+              const double t = B[i] - mg_apply_row(r, i, xc);
+              return xc(i) + (kMgOmega * t) / r.dg;
+            },
+            [&](int i, double v) { X[i] = v; });
+        for_local(
+            F.n,
+            [&](int i) {
+              const MGRow r = mg_row_lds(F, lds, i);
+              const double t = B[i] - mg_apply_row(r, i, [&](int j) { return X[j]; });
+              return X[i] + (kMgOmega * t) / r.dg;
+            },
+            [&](int i, double v) { Tm[i] = v; });
+      }
+    }
+    for (int k = Lg - 1; k >= 0; --k) {
+      const MGLevel F = lv[k], Cl = lv[k + 1];
+      auto post1 = [&](auto FromLds) {
+        for_flat(
+            Q2{}, F.n,
+            [&](int c) {
+              // x after the coarse correction, x_b + s e(parent), on the cell
+              // and its neighbours: loads first, then the arithmetic
+              const MGRow r = mg_row(F, c);
+              const int js[5] = {c, r.jl, r.jr, r.jd, r.ju};
+              double xb5[5], e5[5];
+#pragma unroll
+              for (int q = 0; q < 5; ++q) {
+                const int pc = mg_parent(js[q], F.nx, Cl.nx);
+                xb5[q] = xld(&F.xb[js[q]]);
+                if constexpr (decltype(FromLds)::value) e5[q] = lds[Cl.lt + pc];
+                else e5[q] = xld(&Cl.e[pc]);
+              }
+              const double bc = xld(&F.b[c]);
+              double xc5[5];
+#pragma unroll
+              for (int q = 0; q < 5; ++q) xc5[q] = xb5[q] + kMgScale * e5[q];
+              const double t = bc - mg_apply_vals(r, xc5);
+              return xc5[0] + (kMgOmega * t) / r.dg;
+            },
+            [&](int c, double v) { xst(&F.xd[c], v); });
+      };
+      if (k + 1 == Lg) post1(std::true_type{});
+      else post1(std::false_type{});
+      if (!bar()) return false;
+      for_flat(
+          Q2{}, F.n,
+          [&](int c) {
+            auto xd = [&](int j) { return xld(&F.xd[j]); };
+            const MGRow r = mg_row(F, c);
+            const double t = xld(&F.b[c]) - mg_apply_row(r, c, xd);
+            return xd(c) + (kMgOmega * t) / r.dg;
+          },
+          [&](int c, double v) { xst(&F.e[c], v); });
+      if (!bar()) return false;
+    }
+    return true;
+  };
+  auto uget = [&](int j) { return Lg == 0 ? lds[L0.lt + j] : xld(&L0.e[j]); };
+  // w = A u on the own cells and the block sums of (r, u), (w, u), (r, r)
+  auto matvec = [&]() -> bool {
+    for (int blk = gwv; blk < nb; blk += gstride) {
+      double g[4], d[4], rr[4], wq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c0 = blk * kTree + lane + 64 * q;
+        const int c = c0 < n ? c0 : blk * kTree;
+        const double uc = uget(c);
+        const double wv = mg_apply(L0, c, uget);
+        const double rv = xld(&L0.b[c]);
+        const bool in = c0 < n;
+        wq[q] = wv;
+        g[q] = in ? rv * uc : 0.0;
+        d[q] = in ? wv * uc : 0.0;
+        rr[q] = in ? rv * rv : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = blk * kTree + lane + 64 * q;
+        if (c < n) a.w[c] = wq[q];
+      }
+      const double sg = wave_tree256(g[0], g[1], g[2], g[3]);
+      const double sd = wave_tree256(d[0], d[1], d[2], d[3]);
+      const double sr = wave_tree256(rr[0], rr[1], rr[2], rr[3]);
+      if (lane == 0) {
+        xst(&a.part[3 * blk], sg);
+        xst(&a.part[3 * blk + 1], sd);
+        xst(&a.part[3 * blk + 2], sr);
+      }
+    }
+    return bar();
+  };
+
+  int status = -7, it = 0;
+  double alpha = 0.0, beta = 0.0, gamma = 0.0, delta = 0.0, thr = 0.0;
+  // start: x = 0, r = b
+  for_cells(
+      Q4{}, n, [&](int c) { return V2{a.b[c], sweep_first(a.b[c], L0.diag[c])}; },
+      [&](int c, V2 v) {
+        a.x[c] = 0.0;
+        xst(&L0.b[c], v.a);
+        if (Lg > 0) xst(&L0.xa[c], v.b);
+      });
+  if (!bar() || !vcycle() || !matvec()) {
+    status = -3;
+  } else {
+    double s3[3];
+    group_tree_n<3>(a.part, nb, red, s3);
+    gamma = s3[0];
+    delta = s3[1];
+    thr = a.tol2 * s3[2];
+    if (s3[2] == 0.0) status = 0;
+    else if (!(delta > 0.0)) status = -6;
+    else alpha = gamma / delta;
+  }
+  while (status == -7 && it < a.max_iters) {
+    const bool first = (it == 0);
+    struct U5 {
+      double p, s, x, r, xa;
+    };
+    for_cells(
+        Q4{}, n,
+        [&](int c) {
+          const double uc = uget(c);
+          const double wv = a.w[c];
+          const double pv = first ? uc : uc + beta * a.p[c];
+          const double sv = first ? wv : wv + beta * a.s[c];
+          const double xv = a.x[c] + alpha * pv;
+          const double rv = xld(&L0.b[c]) - alpha * sv;
+          return U5{pv, sv, xv, rv, sweep_first(rv, L0.diag[c])};
+        },
+        [&](int c, U5 v) {
+          a.p[c] = v.p;
+          a.s[c] = v.s;
+          a.x[c] = v.x;
+          xst(&L0.b[c], v.r);
+          if (Lg > 0) xst(&L0.xa[c], v.xa);
+        });
+    if (!bar() || !vcycle() || !matvec()) {
+      status = -3;
+      break;
+    }
+    ++it;
+    double s3[3];
+    group_tree_n<3>(a.part, nb, red, s3);
+    const double gamma_new = s3[0];
+    delta = s3[1];
+    if (s3[2] <= thr) {
+      status = 0;
+      break;
+    }
+    beta = gamma_new / gamma;
+    double tq = beta * gamma_new;
+    tq = tq / alpha;
+    const double den = delta - tq;
+    if (!(den > 0.0)) {
+      status = -6;
+      break;
+    }
+    alpha = gamma_new / den;
+    gamma = gamma_new;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.sc->cg_iters = it;
+    a.sc->cg_status = status;
+  }
+}
+
+// Level k+1's faces from level k's: a coarse x face sums the fine x faces of
+// its two rows at the fine face under it, a coarse y face the fine y faces of
+// its two columns (an absent row or column adds 0).
+__global__ void mg_coarsen_faces_kernel(MGLevel f, MGLevel c, int has_y, double *gx, double *gy)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nfx = c.ny * (c.nx + 1);
+  if (i < nfx) {
+    const int J = i / (c.nx + 1), K = i - J * (c.nx + 1);
+    const int k = (2 * K < f.nx) ? 2 * K : f.nx;
+    const double a = f.gx[(2 * J) * (f.nx + 1) + k];
+    const double b = (2 * J + 1 < f.ny) ? f.gx[(2 * J + 1) * (f.nx + 1) + k] : 0.0;
+    gx[i] = a + b;
+  }
+  if (has_y && i < (c.ny + 1) * c.nx) {
+    const int K = i / c.nx, I = i - K * c.nx;
+    const int k = (2 * K < f.ny) ? 2 * K : f.ny;
+    const double a = f.gy[k * f.nx + 2 * I];
+    const double b = (2 * I + 1 < f.nx) ? f.gy[k * f.nx + 2 * I + 1] : 0.0;
+    gy[i] = a + b;
+  }
+}
+
+// diagonal = the sum of the cell's faces: (left + right) + down + up
+__global__ void mg_coarsen_diag_kernel(MGLevel c, int has_y, double *diag)
+{
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n) return;
+  const int J = i / c.nx, I = i - J * c.nx;
+  double d = c.gx[J * (c.nx + 1) + I] + c.gx[J * (c.nx + 1) + I + 1];
+  if (has_y) {
+    d = d + c.gy[J * c.nx + I];
+    d = d + c.gy[(J + 1) * c.nx + I];
+  }
+  diag[i] = d;
+}
+
+}  // namespace iugkp

@@ -38,7 +38,7 @@ class _Marshal:
     def __init__(self, w, device, *, seed, particles, rng_mode, epoch, max_iters, res_tol,
                  newton, diff_x, diff_y, cg_tol, cg_max_iters, tally_faces, avg_iters,
                  block_size, march=0, cg_waves=0, scheme=0, estimator=0, own_stream=False,
-                 T_init=None):
+                 cg_precond=0, T_init=None):
         self.tau = _dev_f64(w.tau, device)
         self.wall = _dev_f64(w.wall_T, device)
         Ti = T_init if T_init is not None else getattr(w, "T_init", None)
@@ -58,7 +58,8 @@ class _Marshal:
                                  int(max_iters), float(res_tol), int(bool(newton)),
                                  float(cg_tol), int(cg_max_iters), int(tally_faces),
                                  int(avg_iters), int(block_size), int(march), int(cg_waves),
-                                 int(scheme), int(estimator), int(bool(own_stream)))
+                                 int(scheme), int(estimator), int(bool(own_stream)),
+                                 int(cg_precond))
 
 
 def _defaults(w, kw):
@@ -76,6 +77,7 @@ def _defaults(w, kw):
                 march=kw.pop("march", 0), cg_waves=kw.pop("cg_waves", 0),
                 scheme=kw.pop("scheme", 0), estimator=kw.pop("estimator", 0),
                 own_stream=kw.pop("own_stream", False),
+                cg_precond=kw.pop("cg_precond", L.PRECOND_NONE),
                 T_init=kw.pop("T_init", None))
 
 
