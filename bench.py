@@ -86,9 +86,34 @@ def cg_bytes(cg_iters, n_cells):
     return 13 * 8 * n_cells * cg_iters
 
 
+MG_LOCAL_MAX = 1024   # levels of at most this many cells stay in LDS
+
+
+def mgcg_bytes(cg_iters, nx, ny):
+    """Per iteration of the multigrid-preconditioned CG, each vector a phase
+    reads or writes counted once per cell (a row of the operator as diagonal
+    plus two faces): the CG update 12 doubles per fine cell (u, w, p, s, x, r
+    and the diagonal read; p, s, x, r and the first sweep written), w = A u 6
+    (u, r, row; w); per level spread over the GPU 24 per cell (second
+    pre-sweep 6, residual for the restriction 5, corrected post-sweep 7, last
+    post-sweep 6) and 3 per aggregate written by the restriction.  The levels
+    kept in LDS cost no memory traffic."""
+    sizes = []
+    while True:
+        sizes.append(nx * ny)
+        if nx == 1 and ny == 1:
+            break
+        nx, ny = (nx + 1) // 2, (ny + 1) // 2
+    Lg = 0
+    while Lg < len(sizes) and sizes[Lg] > MG_LOCAL_MAX:
+        Lg += 1
+    doubles = 18 * sizes[0] + 24 * sum(sizes[:Lg]) + 3 * sum(sizes[1:Lg + 1])
+    return 8 * doubles * cg_iters
+
+
 def source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "device_core.hpp", "iugkp.hip"):
+    for f in ("kernels.hpp", "device_core.hpp", "mgcg.hpp", "iugkp.hip"):
         with open(os.path.join(ROOT, "paper_2506_09465_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -128,7 +153,8 @@ def cpu_baseline(sample):
         lam = w.vg * w.tau
         D = np.full(w.n_cells, cp.d_eff(float(lam[0]), w.dx))
         # the Newton-accelerated state: every cell emits after the first iteration
-        o = O.Oracle(w, newton=True, diff_x=D, diff_y=D, tally_faces=O.FACES_EVERY)
+        o = O.Oracle(w, newton=True, diff_x=D, diff_y=D, tally_faces=O.FACES_EVERY,
+                     cg_precond=O.PRECOND_MG)
         o.step(2)
         t0 = time.perf_counter()
         o.step(1)
@@ -437,7 +463,7 @@ def main():
     for kn in KNS:
         w = cavity_2d(n=N_SIDE, kn=kn, particles=PARTICLES, newton=True, seed=0)
         solvers.append((kn, w, P.Solver(w, device=dev, tally_faces=P.FACES_EVERY,
-                                        own_stream=True)))
+                                        own_stream=True, cg_precond=P.PRECOND_MG)))
 
     def run_concurrent(n):
         # n iterations of every problem; each problem's next iteration is
@@ -487,7 +513,7 @@ def main():
         ms_c = b["ms_cg"] - a["ms_cg"]
         cgi = b["cg_iters_total"] - a["cg_iters_total"]
         mb = march_bytes(fl, cr, sg, b["n_emitters"] * K, False)
-        cb = cg_bytes(cgi, w.n_cells)
+        cb = mgcg_bytes(cgi, w.nx, w.ny)
         per_kn[str(kn)] = {
             "flights_per_iter": fl // K, "crossings_per_flight": round(cr / max(fl, 1), 2),
             "ms_march": round(ms_m / K, 3), "ms_cg": round(ms_c / K, 3),
@@ -504,7 +530,7 @@ def main():
     src = source_hash()
     kernels = {
         "march_kernel": {"ms": tot["ms_march"], "bytes": tot["march_bytes"], "launches": tot["launches"]},
-        "cg_kernel": {"ms": tot["ms_cg"], "bytes": tot["cg_bytes"], "launches": tot["launches"]},
+        "mgcg_kernel": {"ms": tot["ms_cg"], "bytes": tot["cg_bytes"], "launches": tot["launches"]},
     }
     rooflines = {}
     for name, k in kernels.items():
@@ -528,7 +554,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+int64",
         "data": "synthetic",
         "config": {"workload": "2D gray square cavity 256x256, hot top wall, Kn in {0.01,0.1,1,10}, "
-                               "1e7 particles/iteration, Newton (FP64 CG tol 1e-10), int64 "
+                               "1e7 particles/iteration, Newton (FP64 CG tol 1e-10, multigrid "
+                               "V-cycle preconditioner), int64 "
                                "fixed-point tallies, face tallies every iteration; one step = one "
                                "iteration of each Kn (the four on their own streams, each "
                                "iteration enqueued as soon as the problem's previous one ends)",
@@ -557,7 +584,7 @@ def main():
         for kn in KNS:
             w = cavity_2d(n=N_SIDE, kn=kn, particles=PARTICLES, newton=True, seed=0)
             s = P.Solver(w, device=dev, rng_mode=P.RNG_CRN, tally_faces=P.FACES_FINAL,
-                         max_iters=100, res_tol=1e-6)
+                         max_iters=100, res_tol=1e-6, cg_precond=P.PRECOND_MG)
             torch.cuda.synchronize()
             a = time.perf_counter()
             rc, T, qx, qy, st = s.solve()

@@ -66,19 +66,28 @@ struct MGArgs {
 struct MGRow {
   double dg, gl, gr, gd, gu;
   int jl, jr, jd, ju;
+  int ix, iy;
   unsigned m;                           // left, right, down, up neighbour present
 };
 
-__device__ __forceinline__ MGRow mg_row(const MGLevel &l, int c)
+__device__ __forceinline__ void mg_row_index(MGRow &r, int nx, int ny, int ix, int iy)
 {
-  const int nx = l.nx, iy = c / nx, ix = c - iy * nx;
-  MGRow r;
+  const int c = iy * nx + ix;
+  r.ix = ix;
+  r.iy = iy;
   r.m = (ix > 0 ? 1u : 0u) | (ix < nx - 1 ? 2u : 0u) | (iy > 0 ? 4u : 0u) |
-        (iy < l.ny - 1 ? 8u : 0u);
+        (iy < ny - 1 ? 8u : 0u);
   r.jl = (r.m & 1u) ? c - 1 : c;
   r.jr = (r.m & 2u) ? c + 1 : c;
   r.jd = (r.m & 4u) ? c - nx : c;
   r.ju = (r.m & 8u) ? c + nx : c;
+}
+
+__device__ __forceinline__ MGRow mg_row_at(const MGLevel &l, int ix, int iy)
+{
+  const int nx = l.nx, c = iy * nx + ix;
+  MGRow r;
+  mg_row_index(r, nx, l.ny, ix, iy);
   const int fx = iy * (nx + 1) + ix;
   r.dg = l.diag[c];
   r.gl = l.gx[fx];
@@ -88,24 +97,42 @@ __device__ __forceinline__ MGRow mg_row(const MGLevel &l, int c)
   return r;
 }
 
-// the same row of an LDS level, whose coefficients sit in LDS
-__device__ __forceinline__ MGRow mg_row_lds(const MGLevel &l, const double *lds, int c)
+__device__ __forceinline__ MGRow mg_row(const MGLevel &l, int c)
 {
-  const int nx = l.nx, iy = c / nx, ix = c - iy * nx;
+  const int iy = c / l.nx;
+  return mg_row_at(l, c - iy * l.nx, iy);
+}
+
+// the same row of an LDS level, whose coefficients sit in LDS
+__device__ __forceinline__ MGRow mg_row_lds_at(const MGLevel &l, const double *lds, int ix, int iy)
+{
   MGRow r;
-  r.m = (ix > 0 ? 1u : 0u) | (ix < nx - 1 ? 2u : 0u) | (iy > 0 ? 4u : 0u) |
-        (iy < l.ny - 1 ? 8u : 0u);
-  r.jl = (r.m & 1u) ? c - 1 : c;
-  r.jr = (r.m & 2u) ? c + 1 : c;
-  r.jd = (r.m & 4u) ? c - nx : c;
-  r.ju = (r.m & 8u) ? c + nx : c;
-  const double *k = lds + l.lc + 5 * c;
+  mg_row_index(r, l.nx, l.ny, ix, iy);
+  const double *k = lds + l.lc + 5 * (iy * l.nx + ix);
   r.dg = k[0];
   r.gl = k[1];
   r.gr = k[2];
   r.gd = k[3];
   r.gu = k[4];
   return r;
+}
+
+__device__ __forceinline__ MGRow mg_row_lds(const MGLevel &l, const double *lds, int c)
+{
+  const int iy = c / l.nx;
+  return mg_row_lds_at(l, lds, c - iy * l.nx, iy);
+}
+
+// aggregates (on a level of nxc columns) of the cell of row r and of its
+// four neighbours (an absent one: the cell's own)
+__device__ __forceinline__ void mg_parents(const MGRow &r, int nxc, int (&pc)[5])
+{
+  const int px = r.ix >> 1, py = r.iy >> 1;
+  pc[0] = py * nxc + px;
+  pc[1] = (r.m & 1u) ? py * nxc + ((r.ix - 1) >> 1) : pc[0];
+  pc[2] = (r.m & 2u) ? py * nxc + ((r.ix + 1) >> 1) : pc[0];
+  pc[3] = (r.m & 4u) ? ((r.iy - 1) >> 1) * nxc + px : pc[0];
+  pc[4] = (r.m & 8u) ? ((r.iy + 1) >> 1) * nxc + px : pc[0];
 }
 
 // (A_k v)_c: diag v_c - g_l v_{c-1} - g_r v_{c+1} - g_dn v_{c-nx} - g_up v_{c+nx},
@@ -146,33 +173,6 @@ template <class Get>
 __device__ __forceinline__ double mg_apply(const MGLevel &l, int c, Get v)
 {
   return mg_apply_row(mg_row(l, c), c, v);
-}
-
-// aggregate of cell c of level f on the next level (nxc columns)
-__device__ __forceinline__ int mg_parent(int c, int nxf, int nxc)
-{
-  const int iy = c / nxf, ix = c - iy * nxf;
-  return (iy >> 1) * nxc + (ix >> 1);
-}
-
-// Sum over an aggregate of the children's values, (v(2I,2J) + v(2I+1,2J)) +
-// (v(2I,2J+1) + v(2I+1,2J+1)), absent children 0 (evaluated on a clamped
-// child and discarded, so the loads of all four issue together).
-template <class Get>
-__device__ __forceinline__ double mg_restrict(int C, int nxc, int nxf, int nyf, Get v)
-{
-  const int J = C / nxc, I = C - J * nxc;
-  double q[4];
-#pragma unroll
-  for (int j = 0; j < 2; ++j)
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int ix = 2 * I + i, iy = 2 * J + j;
-      const bool in = (ix < nxf && iy < nyf);
-      const double val = v(in ? iy * nxf + ix : (2 * J) * nxf + 2 * I);
-      q[2 * j + i] = in ? val : 0.0;
-    }
-  return (q[0] + q[1]) + (q[2] + q[3]);
 }
 
 // Sums of the nb published NV-tuples (layout [nb][NV]) in the fixed order of
@@ -298,9 +298,17 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
     if (decltype(Qmax)::value > 1 && nl > nthr) run(std::integral_constant<int, 2>{});
     else run(std::integral_constant<int, 1>{});
   };
-  // an LDS level, one cell per thread at a time, then a workgroup barrier
+  // an LDS level, two cells per thread at a time (computed, then stored),
+  // then a workgroup barrier
   auto for_local = [&](int nl, auto compute, auto store) {
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) store(i, compute(i));
+    const int bd = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < nl; i0 += 2 * bd) {
+      const int i1 = i0 + bd;
+      const auto v0 = compute(i0);
+      const auto v1 = compute(i1 < nl ? i1 : i0);
+      store(i0, v0);
+      if (i1 < nl) store(i1, v1);
+    }
     __syncthreads();
   };
   auto sweep_first = [&](double bv, double dg) { return 0.0 + (kMgOmega * bv) / dg; };
@@ -353,8 +361,9 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
             for (int k = 0; k < 4; ++k) {
               const int ix = 2 * I + (k & 1), iy = 2 * J + (k >> 1);
               in[k] = (ix < F.nx && iy < F.ny);
-              const int f = in[k] ? iy * F.nx + ix : (2 * J) * F.nx + 2 * I;
-              rw[k] = mg_row(F, f);
+              const int cx = in[k] ? ix : 2 * I, cy = in[k] ? iy : 2 * J;
+              const int f = cy * F.nx + cx;
+              rw[k] = mg_row_at(F, cx, cy);
               bv[k] = xld(&F.b[f]);
               xv[k][0] = xld(&F.xb[f]);
               xv[k][1] = xld(&F.xb[rw[k].jl]);
@@ -412,9 +421,19 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
         for_local(
             Cl.n,
             [&](int C) {
-              return mg_restrict(C, Cl.nx, F.nx, F.ny, [&](int f) {
-                return B[f] - mg_apply_row(mg_row_lds(F, lds, f), f, [&](int j) { return Tm[j]; });
-              });
+              const int J = C / Cl.nx, I = C - J * Cl.nx;
+              double q[4];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const int ix = 2 * I + (k & 1), iy = 2 * J + (k >> 1);
+                const bool in = (ix < F.nx && iy < F.ny);
+                const int cx = in ? ix : 2 * I, cy = in ? iy : 2 * J;
+                const int f = cy * F.nx + cx;
+                const MGRow r = mg_row_lds_at(F, lds, cx, cy);
+                const double res = B[f] - mg_apply_row(r, f, [&](int j) { return Tm[j]; });
+                q[k] = in ? res : 0.0;
+              }
+              return (q[0] + q[1]) + (q[2] + q[3]);
             },
             [&](int C, double v) {
               lds[Cl.lb + C] = v;
@@ -431,9 +450,14 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
             F.n,
             [&](int i) {
               const MGRow r = mg_row_lds(F, lds, i);
-              auto xc = [&](int j) { return Tm[j] + kMgScale * E[mg_parent(j, F.nx, Cl.nx)]; };
-              const double t = B[i] - mg_apply_row(r, i, xc);
-              return xc(i) + (kMgOmega * t) / r.dg;
+              int pc[5];
+              mg_parents(r, Cl.nx, pc);
+              const int js[5] = {i, r.jl, r.jr, r.jd, r.ju};
+              double xc5[5];
+#pragma unroll
+              for (int q = 0; q < 5; ++q) xc5[q] = Tm[js[q]] + kMgScale * E[pc[q]];
+              const double t = B[i] - mg_apply_vals(r, xc5);
+              return xc5[0] + (kMgOmega * t) / r.dg;
             },
             [&](int i, double v) { X[i] = v; });
         for_local(
@@ -456,13 +480,14 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
               // and its neighbours: loads first, then the arithmetic
               const MGRow r = mg_row(F, c);
               const int js[5] = {c, r.jl, r.jr, r.jd, r.ju};
+              int pc[5];
+              mg_parents(r, Cl.nx, pc);
               double xb5[5], e5[5];
 #pragma unroll
               for (int q = 0; q < 5; ++q) {
-                const int pc = mg_parent(js[q], F.nx, Cl.nx);
                 xb5[q] = xld(&F.xb[js[q]]);
-                if constexpr (decltype(FromLds)::value) e5[q] = lds[Cl.lt + pc];
-                else e5[q] = xld(&Cl.e[pc]);
+                if constexpr (decltype(FromLds)::value) e5[q] = lds[Cl.lt + pc[q]];
+                else e5[q] = xld(&Cl.e[pc[q]]);
               }
               const double bc = xld(&F.b[c]);
               double xc5[5];
