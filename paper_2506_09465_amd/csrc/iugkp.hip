@@ -702,14 +702,15 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
        (!ev && o->tally_faces != IUGKP_FACES_OFF &&
         (o->march == 2 ||
          (o->march == 0 && d.lam_min >= kStripeMinCells * std::min(p->dx, p->dy)))))) {
-    // row stripes: as many rows per workgroup as its LDS holds (y faces, D,
-    // W with null collisions, the walls), about two workgroups per CU
+    // row stripes: as many rows per workgroup as its LDS holds (y faces and
+    // the walls; the expected-value kernel also D, and W with null
+    // collisions), about two workgroups per CU
     int dev = 0, n_cu = 0, lds_max = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const long long words = lds_max / 8 - 16;
-    const long long per_row = static_cast<long long>(m.nx) * (d.has_null ? 3 : 2);
+    const long long per_row = static_cast<long long>(m.nx) * (ev ? (d.has_null ? 3 : 2) : 1);
     const long long fixed = m.nx + (d.lds_walls ? m.n_b : 0);
     int R = static_cast<int>((words - fixed) / per_row);
     if (R >= kStripeMinRows || (R >= 1 && R >= m.ny)) {

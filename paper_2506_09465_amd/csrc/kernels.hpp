@@ -770,15 +770,16 @@ __device__ __forceinline__ int faces_upto_from(int cnt, int k0, int st, int jmax
 // ---------------------------------------------------------------------------
 // The particle step with face tallies for long free paths, by row stripes.
 // Workgroup (chunk c, stripe s) keeps in LDS the y-face tallies of faces
-// [r0, r1f) (the last stripe also owns face ny), the deposits D (and W) of
-// rows [r0, r1) and the wall tallies, and runs every particle of its chunk:
+// [r0, r1f) (the last stripe also owns face ny) and the wall tallies, and
+// runs every particle of its chunk:
 // sampling and each segment's end in closed form (segment_end), then only
 // the y faces it crosses inside the stripe, each in the column reached by the
 // x faces crossed first (x first on ties, as in the walk).  A particle's
 // deposits, wall absorption and counters go to the stripe holding the row
-// where that event happens.  All tallies are integer sums, so the result is
-// the tile kernel's bit for bit, and no tally leaves LDS before the final
-// row-contiguous flush.  Each lane runs a small state machine (next particle
+// where that event happens; the deposits (one per particle, one W per null
+// segment) go straight to global memory, which leaves the LDS to the y faces
+// and so halves the number of stripes every particle is sampled in.  All
+// tallies are integer sums, so the result is the tile kernel's bit for bit.  Each lane runs a small state machine (next particle
 // / one y-face crossing / segment end), so lanes with long flights do not
 // hold the others of their wavefront.
 // ---------------------------------------------------------------------------
@@ -795,10 +796,8 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   const int r1f = (r1 == m.ny) ? m.ny + 1 : r1;
   const int nrow = r1 - r0, nface = r1f - r0;
   long long *By = lds_words;                                  // [nface][nx]
-  long long *Dl = By + nface * nx;                            // [nrow][nx]
-  long long *Wl = in.has_null ? Dl + nrow * nx : nullptr;     // [nrow][nx]
-  long long *Bl = (in.has_null ? Wl : Dl) + nrow * nx;        // [n_b] when lds_walls
-  const int nwords = nface * nx + nrow * nx * (in.has_null ? 2 : 1) + (in.lds_walls ? m.n_b : 0);
+  long long *Bl = By + nface * nx;                            // [n_b] when lds_walls
+  const int nwords = nface * nx + (in.lds_walls ? m.n_b : 0);
   for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
   if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -909,19 +908,19 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       live = false;
       continue;
     }
+    const int c = ixe + nx * iye;
     if (!fa.has_null) {
       if (owned(iye)) {
-        lds_add(&Dl[(iye - r0) * nx + ixe], q);
+        atom_add(&in.D[c], q);
         retire();
       }
       live = false;
       continue;
     }
-    if (owned(iye)) lds_add(&Wl[(iye - r0) * nx + ixe], q);
-    const int c = ixe + nx * iye;
+    if (owned(iye)) atom_add(&in.W[c], q);
     if (uacc < fa.ratio[c] || j == kMaxSegments - 1) {
       if (owned(iye)) {
-        lds_add(&Dl[(iye - r0) * nx + ixe], q);
+        atom_add(&in.D[c], q);
         retire();
       }
       live = false;
@@ -946,10 +945,6 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   // row-contiguous flush
   for (int i = threadIdx.x; i < nface * nx; i += BS)
     if (By[i]) atom_add(&in.Phiy[r0 * nx + i], By[i]);
-  for (int i = threadIdx.x; i < nrow * nx; i += BS) {
-    if (Dl[i]) atom_add(&in.D[r0 * nx + i], Dl[i]);
-    if (Wl && Wl[i]) atom_add(&in.W[r0 * nx + i], Wl[i]);
-  }
   if (in.lds_walls)
     for (int b = threadIdx.x; b < m.n_b; b += BS)
       if (Bl[b]) atom_add(&in.B[b], Bl[b]);
