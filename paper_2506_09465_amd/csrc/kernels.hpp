@@ -826,10 +826,12 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   double ell = 0.0, uacc = 0.0;
   int kx0 = 0, ky0 = 0, ixs = 0, jwx = 0, k = 0, k_end = 0, cnt = 0, ixe = 0, iye = 0, bface = -1;
 
-  auto start_segment = [&]() {
+  auto draw_path = [&]() {
     const double2 us = draw2(2u + j, kk, e + fa.e_off, fa.slot, fa.key0, fa.key1);
     ell = -(fa.lam_min * log_own(1.0 - us.x));
     uacc = us.y;
+  };
+  auto start_segment = [&]() {
     ++p_seg;
     kx0 = (stx > 0) ? ix + 1 : ix;
     ky0 = (sty > 0) ? iy + 1 : iy;
@@ -871,22 +873,25 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
         kk = static_cast<uint32_t>(pc / n_emit);
         e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
         q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
-        if (q != 0) {
-          got = true;
-          break;
-        }
+        if (q == 0) continue;
+        sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
+        sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+        // a particle moving away from the stripe (or along a row outside
+        // it) crosses none of its faces and ends in none of its rows
+        if ((sty > 0 && iy >= r1) || (sty < 0 && iy < r0) || (sty == 0 && !owned(iy))) continue;
+        got = true;
+        break;
       }
       if (!got) break;
-      sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
       inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
       inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
       stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
-      sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
       qy = (sty > 0) ? q : -q;
       j = 0;
       p_seg = 0;
       p_cross = 0;
       live = true;
+      draw_path();
       start_segment();
     }
     if (k < k_end) {
@@ -934,6 +939,7 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
     ix = ixe;
     iy = iye;
     ++j;
+    draw_path();
     start_segment();
   }
   if (n_fl) {
