@@ -459,11 +459,15 @@ def main():
     # own and every step is enqueued on all four before any is waited for, so
     # one problem's Newton CG (a few tens of workgroups) overlaps the others'
     # particle steps
+    # (created longest particle step first: streams are spread over the
+    # hardware queues in creation order, and the two long steps should not
+    # share one)
     solvers = []
-    for kn in KNS:
+    for kn in sorted(KNS, reverse=True):
         w = cavity_2d(n=N_SIDE, kn=kn, particles=PARTICLES, newton=True, seed=0)
         solvers.append((kn, w, P.Solver(w, device=dev, tally_faces=P.FACES_EVERY,
                                         own_stream=True, cg_precond=P.PRECOND_MG)))
+    solvers.sort(key=lambda t: t[0])
 
     def run_concurrent(n):
         # n iterations of every problem; each problem's next iteration is

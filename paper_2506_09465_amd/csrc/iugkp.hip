@@ -1227,8 +1227,8 @@ int enqueue_cg(const InstHost &ih, const double *b, double *x, DevScalars *sc, h
     iugkp::zero_u32_kernel<<<1, 64, 0, s>>>(ih.cg_barrier, 2);
     if (ev_a) HIP_TRY(hipEventRecord(ev_a, s));
     void *args[] = {&ma};
-    HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(iugkp::mgcg_kernel),
-                                       dim3(ih.mg_grid), dim3(ih.mg_threads), args, ih.mg_lds, s));
+    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void *>(iugkp::mgcg_kernel), dim3(ih.mg_grid),
+                            dim3(ih.mg_threads), args, ih.mg_lds, s));
     if (ev_b) HIP_TRY(hipEventRecord(ev_b, s));
     return IUGKP_OK;
   }
@@ -1252,10 +1252,16 @@ int enqueue_cg(const InstHost &ih, const double *b, double *x, DevScalars *sc, h
   ca.sc = sc;
   iugkp::zero_u32_kernel<<<1, 64, 0, s>>>(ih.cg_barrier, 2);
   if (ev_a) HIP_TRY(hipEventRecord(ev_a, s));
-  // every workgroup must be resident for the grid barrier: the cooperative
-  // launch refuses a grid that does not fit instead of letting it hang
+  // Every workgroup must become resident for the group barrier.  Set-up
+  // checked that the group fits the device; a plain launch (not a
+  // cooperative one, which HIP serialises on one device-wide queue) lets the
+  // CG of one handle run beside the CGs and particle steps of others: a
+  // workgroup that is resident early waits in the barrier until the rest are
+  // dispatched as other kernels' workgroups retire (none of them waits for the
+  // CG), and a wait beyond the barrier's spin limit ends the solve with an
+  // error instead of hanging.
   void *args[] = {&ca};
-  HIP_TRY(hipLaunchCooperativeKernel(cg_kernel_for(ih.cg_reg), dim3(ih.cg_grid),
+  HIP_TRY(hipLaunchKernel(cg_kernel_for(ih.cg_reg), dim3(ih.cg_grid),
                                      dim3(ih.cg_threads), args, ih.cg_lds, s));
   if (ev_b) HIP_TRY(hipEventRecord(ev_b, s));
   return IUGKP_OK;
