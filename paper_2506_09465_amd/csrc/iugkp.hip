@@ -1286,7 +1286,7 @@ int enqueue_iteration(iugkp_handle *h, int faces)
         <<<ih.d.n_npart, kPersistBlock, 0, s>>>(h->d_inst, faces);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(h->ev[1], s));
-    if (faces) iugkp::persist_reconstruct_x_kernel<<<cdiv(m.ny, 256), 256, 0, s>>>(h->d_inst);
+    if (faces) iugkp::persist_reconstruct_x_kernel<<<cdiv(m.ny, 4), 256, 0, s>>>(h->d_inst);
     iugkp::persist_update_kernel<<<ih.d.n_gpart, 256, 0, s>>>(h->d_inst);
   } else {
   iugkp::prepare_kernel<<<dim3(cdiv(nprep, 256), K), 256, 0, s>>>(h->d_inst, faces, 0);
@@ -1309,8 +1309,8 @@ int enqueue_iteration(iugkp_handle *h, int faces)
   }
   HIP_TRY(hipEventRecord(h->ev[1], s));
   if (faces) {
-    iugkp::reconstruct_y_kernel<<<dim3(cdiv(m.nx, 256), K), 256, 0, s>>>(h->d_inst, faces, 0);
-    iugkp::reconstruct_x_kernel<<<dim3(cdiv(m.ny, 256), K), 256, 0, s>>>(h->d_inst, faces, 0);
+    iugkp::reconstruct_y_kernel<<<dim3(cdiv(m.nx, 4), K), 256, 0, s>>>(h->d_inst, faces, 0);
+    iugkp::reconstruct_x_kernel<<<dim3(cdiv(m.ny, 4), K), 256, 0, s>>>(h->d_inst, faces, 0);
   }
   const int nbc = cdiv(m.n_cells, iugkp::kTree);
   if (K > 1)
@@ -1982,8 +1982,8 @@ int enqueue_batch_iteration(iugkp_batch *b)
   iugkp::prepare_kernel<<<dim3(cdiv(b->max_prep, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
   int rc = launch_march(b->d_insts, b->d_tiles, b->n_tiles, b->lds_max, 256, -1, 1, b->any_ev, s);
   if (rc) return rc;
-  iugkp::reconstruct_y_kernel<<<dim3(cdiv(b->max_nx, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
-  iugkp::reconstruct_x_kernel<<<dim3(cdiv(b->max_ny, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
+  iugkp::reconstruct_y_kernel<<<dim3(cdiv(b->max_nx, 4), n), 256, 0, s>>>(b->d_insts, -1, 1);
+  iugkp::reconstruct_x_kernel<<<dim3(cdiv(b->max_ny, 4), n), 256, 0, s>>>(b->d_insts, -1, 1);
   iugkp::update_kernel<<<dim3(b->max_nbc, n), 256, 0, s>>>(b->d_insts, 1);
   if (b->any_newton) {
     iugkp::zero_u32_kernel<<<cdiv(kBarStride * n, 256), 256, 0, s>>>(b->d_bars, kBarStride * n);

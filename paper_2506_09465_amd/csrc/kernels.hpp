@@ -1127,39 +1127,87 @@ __global__ __launch_bounds__(BS) void march_stripes_ev_kernel(const Inst *__rest
 //   Phix[j][i+1] = Phix[j][i] + Phiy[j][i] - Phiy[j+1][i] - D[c] + G[c]
 // Integer arithmetic modulo 2^64: exact, since every true value fits in int64.
 // ---------------------------------------------------------------------------
-__global__ void reconstruct_y_kernel(const Inst *__restrict__ insts, int faces_mode, int batch)
+// One wave's running sums: put(k, carry + get(0) + ... + get(k)) for k < n, in
+// wrapping 64-bit integer arithmetic (exact and associative, so the prefix
+// sums have the bits of the sequential recurrence).  Four consecutive terms
+// per lane, 256 per round; a round's loads all issue before its stores.
+template <class Get, class Put>
+__device__ __forceinline__ void wave_prefix(int n, unsigned long long carry, Get get, Put put)
+{
+  const int lane = threadIdx.x & 63;
+  for (int k0 = 0; k0 < n; k0 += 256) {
+    unsigned long long v[4], s = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 4 * lane + q;
+      s += (k < n) ? get(k) : 0ull;
+      v[q] = s;
+    }
+    unsigned long long t = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const unsigned long long y = __shfl_up(t, d, 64);
+      if (lane >= d) t += y;
+    }
+    const unsigned long long base = carry + (t - s);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 4 * lane + q;
+      if (k < n) put(k, base + v[q]);
+    }
+    carry += __shfl(t, 63, 64);
+  }
+}
+
+// y faces from the column differences dB: one wave per column,
+// Phiy[k][i] += dB[0][i] + ... + dB[k][i]
+__global__ __launch_bounds__(256) void reconstruct_y_kernel(const Inst *__restrict__ insts,
+                                                            int faces_mode, int batch)
 {
   const Inst &in = insts[blockIdx.y];
   if (inst_idle(in, batch) || !inst_faces(in, faces_mode) || in.m.dim != 2) return;
   const Mesh &m = in.m;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= m.nx) return;
-  unsigned long long acc = 0;
-  for (int k = 0; k <= m.ny; ++k) {
-    acc += static_cast<unsigned long long>(in.dB[k * m.nx + i]);
-    in.Phiy[k * m.nx + i] =
-        static_cast<long long>(static_cast<unsigned long long>(in.Phiy[k * m.nx + i]) + acc);
-  }
+  long long *const Py = in.Phiy;
+  const long long *const dB = in.dB;
+  wave_prefix(
+      m.ny + 1, 0ull,
+      [&](int k) { return static_cast<unsigned long long>(dB[k * m.nx + i]); },
+      [&](int k, unsigned long long acc) {
+        Py[k * m.nx + i] =
+            static_cast<long long>(static_cast<unsigned long long>(Py[k * m.nx + i]) + acc);
+      });
 }
 
-__global__ void reconstruct_x_kernel(const Inst *__restrict__ insts, int faces_mode, int batch)
+// x faces from the per-cell balance along each row (one wave per row):
+// Phix[j][0] = inflow of the left wall face, then
+// Phix[j][i+1] = Phix[j][i] + (Phiy[j][i] - Phiy[j+1][i]) + (G - D)[j][i]
+__global__ __launch_bounds__(256) void reconstruct_x_kernel(const Inst *__restrict__ insts,
+                                                            int faces_mode, int batch)
 {
   const Inst &in = insts[blockIdx.y];
   if (inst_idle(in, batch) || !inst_faces(in, faces_mode)) return;
   const Mesh &m = in.m;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= m.ny) return;
-  unsigned long long a = static_cast<unsigned long long>(in.G[m.n_cells + j]) -
-                         static_cast<unsigned long long>(in.B[j]);
-  in.Phix[j * (m.nx + 1)] = static_cast<long long>(a);
-  for (int i = 0; i < m.nx; ++i) {
-    const int c = j * m.nx + i;
-    if (m.dim == 2)
-      a += static_cast<unsigned long long>(in.Phiy[j * m.nx + i]) -
-           static_cast<unsigned long long>(in.Phiy[(j + 1) * m.nx + i]);
-    a += static_cast<unsigned long long>(in.G[c]) - static_cast<unsigned long long>(in.D[c]);
-    in.Phix[j * (m.nx + 1) + i + 1] = static_cast<long long>(a);
-  }
+  const unsigned long long a0 = static_cast<unsigned long long>(in.G[m.n_cells + j]) -
+                                static_cast<unsigned long long>(in.B[j]);
+  long long *const px = in.Phix + static_cast<size_t>(j) * (m.nx + 1);
+  if ((threadIdx.x & 63) == 0) px[0] = static_cast<long long>(a0);
+  const bool two = (m.dim == 2);
+  wave_prefix(
+      m.nx, a0,
+      [&](int i) {
+        const int c = j * m.nx + i;
+        const unsigned long long dy =
+            two ? static_cast<unsigned long long>(in.Phiy[j * m.nx + i]) -
+                      static_cast<unsigned long long>(in.Phiy[(j + 1) * m.nx + i])
+                : 0ull;
+        return dy + (static_cast<unsigned long long>(in.G[c]) -
+                     static_cast<unsigned long long>(in.D[c]));
+      },
+      [&](int i, unsigned long long v) { px[i + 1] = static_cast<long long>(v); });
 }
 
 // ---------------------------------------------------------------------------
@@ -2669,23 +2717,29 @@ __global__ __launch_bounds__(256) void persist_update_kernel(const Inst *__restr
 //   Phix[j][0]   = (re-emitted by the left wall face j) - B_left[j]
 //   Phix[j][i+1] = Phix[j][i] + Phiy[j][i] - Phiy[j+1][i] - W[c] + start[c]
 // (arithmetic modulo 2^64, exact since every true value fits in int64).
-__global__ void persist_reconstruct_x_kernel(const Inst *__restrict__ insts)
+__global__ __launch_bounds__(256) void persist_reconstruct_x_kernel(const Inst *__restrict__ insts)
 {
   const Inst &in = insts[0];
   const Mesh &m = in.m;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= m.ny) return;
-  unsigned long long a = static_cast<unsigned long long>(in.pein[j]) -
-                         static_cast<unsigned long long>(in.B[j]);
-  in.Phix[j * (m.nx + 1)] = static_cast<long long>(a);
-  for (int i = 0; i < m.nx; ++i) {
-    const int c = j * m.nx + i;
-    if (m.dim == 2)
-      a += static_cast<unsigned long long>(in.Phiy[j * m.nx + i]) -
-           static_cast<unsigned long long>(in.Phiy[(j + 1) * m.nx + i]);
-    a += static_cast<unsigned long long>(in.pstart[c]) - static_cast<unsigned long long>(in.W[c]);
-    in.Phix[j * (m.nx + 1) + i + 1] = static_cast<long long>(a);
-  }
+  const unsigned long long a0 = static_cast<unsigned long long>(in.pein[j]) -
+                                static_cast<unsigned long long>(in.B[j]);
+  long long *const px = in.Phix + static_cast<size_t>(j) * (m.nx + 1);
+  if ((threadIdx.x & 63) == 0) px[0] = static_cast<long long>(a0);
+  const bool two = (m.dim == 2);
+  wave_prefix(
+      m.nx, a0,
+      [&](int i) {
+        const int c = j * m.nx + i;
+        const unsigned long long dy =
+            two ? static_cast<unsigned long long>(in.Phiy[j * m.nx + i]) -
+                      static_cast<unsigned long long>(in.Phiy[(j + 1) * m.nx + i])
+                : 0ull;
+        return dy + (static_cast<unsigned long long>(in.pstart[c]) -
+                     static_cast<unsigned long long>(in.W[c]));
+      },
+      [&](int i, unsigned long long v) { px[i + 1] = static_cast<long long>(v); });
 }
 
 // Unpack location | kind << 30.
