@@ -743,8 +743,8 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
 // Number of faces j <= jmax of the sequence k(j) = k0 + j st with
 // t(j) = (k(j) d - p0) * inv <= T, given that the first cnt are: galloping
 // from cnt, then bisection (t is non-decreasing in j).
-__device__ __forceinline__ int faces_upto_from(int cnt, int k0, int st, int jmax, double d,
-                                               double p0, double inv, double T)
+__device__ __attribute__((noinline)) int faces_upto_from(int cnt, int k0, int st, int jmax,
+                                                        double d, double p0, double inv, double T)
 {
   int lo = cnt, hi = jmax + 1, step = 1;
   for (;;) {
@@ -765,6 +765,37 @@ __device__ __forceinline__ int faces_upto_from(int cnt, int k0, int st, int jmax
     else hi = mid;
   }
   return lo;
+}
+
+// The same count, estimated from the coordinate reached at T, pos = p0 + T s
+// (faces at or before pos: floor(pos / d - k0) + 1 for st > 0,
+// floor(k0 - pos / d) + 1 for st < 0), moved by at most one step each way
+// against the walk's own times, then checked: the count c is right when
+// t(c - 1) <= T (or c = cnt) and t(c) > T (or c > jmax).  Rounding in the
+// estimate moves it by at most one face on any mesh whose cells are far wider
+// than the rounding of a coordinate, so the check holds; should it fail, the
+// search above (kept out of line) decides.  No loop on the common path: a
+// loop there costs the whole wavefront at every crossing.
+__device__ __forceinline__ int faces_upto_near(int cnt, int k0, int st, int jmax, double d,
+                                               double inv_d, double p0, double inv, double s,
+                                               double T)
+{
+  const double pos = p0 + T * s;
+  const double jr = (st > 0) ? pos * inv_d - static_cast<double>(k0)
+                             : static_cast<double>(k0) - pos * inv_d;
+  int lo;
+  if (!(jr < static_cast<double>(jmax))) lo = jmax + 1;
+  else if (!(jr >= static_cast<double>(cnt))) lo = cnt;
+  else lo = static_cast<int>(floor(jr)) + 1;
+  // (t at an index outside [0, jmax] is plain arithmetic, its result unused)
+  auto t = [&](int j) { return (static_cast<double>(k0 + j * st) * d - p0) * inv; };
+  const double ta = t(lo - 1), tb = t(lo);
+  const bool down = lo > cnt && !(ta <= T);
+  const bool up = !down && lo <= jmax && tb <= T;
+  const double tc = t(down ? lo - 2 : lo + 1);
+  lo += up ? 1 : (down ? -1 : 0);
+  const bool ok = down ? (lo == cnt || tc <= T) : (!up || lo > jmax || !(tc <= T));
+  return ok ? lo : faces_upto_from(cnt, k0, st, jmax, d, p0, inv, T);
 }
 
 // ---------------------------------------------------------------------------
@@ -814,6 +845,7 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   const unsigned long long pe = total * (blockIdx.x + 1) / chunks;
   unsigned long long pnext = pb + threadIdx.x;
   unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
+  const double inv_dx = 1.0 / m.dx;       // (only to estimate a face count)
 
   // the lane's particle
   bool live = false;
@@ -898,7 +930,7 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       // one owned y-face crossing, in the column reached by the x faces before it
       const int kyk = ky0 + k * sty;
       const double ty = (static_cast<double>(kyk) * m.dy - y0) * inv_sy;
-      if (stx) cnt = faces_upto_from(cnt, kx0, stx, jwx, m.dx, x0, inv_sx, ty);
+      if (stx) cnt = faces_upto_near(cnt, kx0, stx, jwx, m.dx, inv_dx, x0, inv_sx, sx, ty);
       lds_add(&By[(kyk - r0) * nx + ixs + stx * cnt], qy);
       ++k;
       continue;
