@@ -769,13 +769,13 @@ __device__ __attribute__((noinline)) int faces_upto_from(int cnt, int k0, int st
 
 // The same count, estimated from the coordinate reached at T, pos = p0 + T s
 // (faces at or before pos: floor(pos / d - k0) + 1 for st > 0,
-// floor(k0 - pos / d) + 1 for st < 0), moved by at most one step each way
-// against the walk's own times, then checked: the count c is right when
-// t(c - 1) <= T (or c = cnt) and t(c) > T (or c > jmax).  Rounding in the
-// estimate moves it by at most one face on any mesh whose cells are far wider
-// than the rounding of a coordinate, so the check holds; should it fail, the
-// search above (kept out of line) decides.  No loop on the common path: a
-// loop there costs the whole wavefront at every crossing.
+// floor(k0 - pos / d) + 1 for st < 0) and checked against the walk's own
+// times: the estimate c is the count when t(c - 1) <= T (or c = cnt) and
+// t(c) > T (or c > jmax).  Rounding in the estimate and in the walk's
+// comparisons place the crossing point within a few units in the last place
+// of a coordinate, so a miss is rare; it is settled by the search above
+// (kept out of line).  No loop on the common path: a loop there costs the
+// whole wavefront its slowest lane's trip count at every crossing.
 __device__ __forceinline__ int faces_upto_near(int cnt, int k0, int st, int jmax, double d,
                                                double inv_d, double p0, double inv, double s,
                                                double T)
@@ -790,11 +790,7 @@ __device__ __forceinline__ int faces_upto_near(int cnt, int k0, int st, int jmax
   // (t at an index outside [0, jmax] is plain arithmetic, its result unused)
   auto t = [&](int j) { return (static_cast<double>(k0 + j * st) * d - p0) * inv; };
   const double ta = t(lo - 1), tb = t(lo);
-  const bool down = lo > cnt && !(ta <= T);
-  const bool up = !down && lo <= jmax && tb <= T;
-  const double tc = t(down ? lo - 2 : lo + 1);
-  lo += up ? 1 : (down ? -1 : 0);
-  const bool ok = down ? (lo == cnt || tc <= T) : (!up || lo > jmax || !(tc <= T));
+  const bool ok = (lo == cnt || ta <= T) && (lo > jmax || !(tb <= T));
   return ok ? lo : faces_upto_from(cnt, k0, st, jmax, d, p0, inv, T);
 }
 
