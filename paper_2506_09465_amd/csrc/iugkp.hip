@@ -97,6 +97,7 @@ struct InstHost {
   // row-stripe particle step for face-tallied iterations (single solves)
   int stripe_R = 0, stripe_S = 0, stripe_C = 0;
   size_t stripe_lds = 0;
+  iugkp::StripeRec rec{};            // first segments, sampled once for all stripes
 
   template <class T>
   hipError_t alloc(T **p, size_t n)
@@ -723,7 +724,22 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
           ev ? reinterpret_cast<const void *>(iugkp::march_stripes_ev_kernel<kStripeBlock>)
              : reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>);
       HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kStripeBlock, lds));
-      if (per_cu >= 1) {
+      // (the analog kernel reads every particle's first segment from records
+      // of about 70 bytes per particle; without the memory, tiles are used)
+      bool recs = true;
+      if (!ev) {
+        const size_t np = static_cast<size_t>(m.n_emit) * static_cast<size_t>(d.N);
+        iugkp::StripeRec &r = ih.rec;
+        recs = ih.alloc(&r.x0, np) == hipSuccess && ih.alloc(&r.y0, np) == hipSuccess &&
+               ih.alloc(&r.sx, np) == hipSuccess && ih.alloc(&r.sy, np) == hipSuccess &&
+               ih.alloc(&r.ell, np) == hipSuccess && ih.alloc(&r.uacc, np) == hipSuccess &&
+               ih.alloc(&r.q, np) == hipSuccess && ih.alloc(&r.ix, np) == hipSuccess &&
+               ih.alloc(&r.iy, np) == hipSuccess && ih.alloc(&r.ixe, np) == hipSuccess &&
+               ih.alloc(&r.iye, np) == hipSuccess && ih.alloc(&r.bface, np) == hipSuccess &&
+               ih.alloc(&r.nyp, np) == hipSuccess && ih.alloc(&r.ncross, np) == hipSuccess;
+        if (!recs) (void)hipGetLastError();
+      }
+      if (per_cu >= 1 && recs) {
         ih.stripe_R = R;
         ih.stripe_S = S;
         ih.stripe_C = std::max(1, (2 * per_cu * n_cu) / S);   // whole rounds of resident groups
@@ -1298,9 +1314,13 @@ int enqueue_iteration(iugkp_handle *h, int faces)
                                                                               ih.stripe_C, faces);
     HIP_TRY(hipGetLastError());
   } else if (faces && ih.stripe_R > 0) {
+    const unsigned long long np =
+        static_cast<unsigned long long>(m.n_emit) * static_cast<unsigned long long>(ih.d.N);
+    iugkp::stripe_presample_kernel<256>
+        <<<static_cast<unsigned int>((np + 255) / 256), 256, 0, s>>>(h->d_inst, ih.rec);
     iugkp::march_stripes_kernel<kStripeBlock>
         <<<dim3(ih.stripe_C, ih.stripe_S), kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R,
-                                                                              ih.stripe_C);
+                                                                              ih.stripe_C, ih.rec);
     HIP_TRY(hipGetLastError());
   } else {
     rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, h->lds, h->block, faces, 0,

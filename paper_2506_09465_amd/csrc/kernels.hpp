@@ -798,9 +798,10 @@ __device__ __forceinline__ int faces_upto_near(int cnt, int k0, int st, int jmax
 // The particle step with face tallies for long free paths, by row stripes.
 // Workgroup (chunk c, stripe s) keeps in LDS the y-face tallies of faces
 // [r0, r1f) (the last stripe also owns face ny) and the wall tallies, and
-// runs every particle of its chunk:
-// sampling and each segment's end in closed form (segment_end), then only
-// the y faces it crosses inside the stripe, each in the column reached by the
+// runs every particle of its chunk: start and first segment from the
+// records sampled once for all stripes (stripe_presample_kernel), later
+// segments' ends in closed form (segment_end), then only the y faces it
+// crosses inside the stripe, each in the column reached by the
 // x faces crossed first (x first on ties, as in the walk).  A particle's
 // deposits, wall absorption and counters go to the stripe holding the row
 // where that event happens; the deposits (one per particle, one W per null
@@ -810,9 +811,66 @@ __device__ __forceinline__ int faces_upto_near(int cnt, int k0, int st, int jmax
 // / one y-face crossing / segment end), so lanes with long flights do not
 // hold the others of their wavefront.
 // ---------------------------------------------------------------------------
+// Every particle's start and first segment, sampled once per iteration for
+// all row stripes (structure of arrays, indexed by the particle's place in
+// the enumeration, emitters fastest): weight (0: no particle), start cell
+// and point, direction, free path and acceptance draw, and the segment's end
+// in closed form (end cell, wall face or -1, y faces crossed, all faces
+// crossed).
+struct StripeRec {
+  double *x0, *y0, *sx, *sy, *ell, *uacc;
+  long long *q;
+  int *ix, *iy, *ixe, *iye, *bface, *nyp, *ncross;
+};
+
+template <int BS>
+__global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__restrict__ insts,
+                                                              StripeRec rec)
+{
+  const Inst &in = insts[0];
+  const Mesh &m = in.m;
+  const FlyIn fa = {m, in.lam_min, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1, 1,
+                    in.has_null, in.ratio, in.e_off};
+  const unsigned long long n_emit = static_cast<unsigned long long>(m.n_emit);
+  const unsigned long long total = n_emit * in.N;
+  const unsigned long long pc = static_cast<unsigned long long>(blockIdx.x) * BS + threadIdx.x;
+  if (pc >= total) return;
+  const uint32_t kk = static_cast<uint32_t>(pc / n_emit);
+  const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
+  const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
+  rec.q[pc] = q;
+  if (q == 0) return;
+  int ix = 0, iy = 0;
+  double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
+  sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
+  const double2 us = draw2(2u, kk, e + fa.e_off, fa.slot, fa.key0, fa.key1);
+  const double ell = -(fa.lam_min * log_own(1.0 - us.x));
+  const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+  const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+  const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+  const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+  const int kx0 = (stx > 0) ? ix + 1 : ix;
+  const int ky0 = (sty > 0) ? iy + 1 : iy;
+  int ixe = ix, iye = iy, bface = -1, nxp = 0, nyp = 0;
+  segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
+  rec.x0[pc] = x0;
+  rec.y0[pc] = y0;
+  rec.sx[pc] = sx;
+  rec.sy[pc] = sy;
+  rec.ell[pc] = ell;
+  rec.uacc[pc] = us.y;
+  rec.ix[pc] = ix;
+  rec.iy[pc] = iy;
+  rec.ixe[pc] = ixe;
+  rec.iye[pc] = iye;
+  rec.bface[pc] = bface;
+  rec.nyp[pc] = nyp;
+  rec.ncross[pc] = nxp + nyp;
+}
+
 template <int BS>
 __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restrict__ insts, int R,
-                                                           int chunks)
+                                                           int chunks, StripeRec rec)
 {
   extern __shared__ long long lds_words[];
   __shared__ unsigned long long s_cnt[3];
@@ -859,18 +917,15 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
     ell = -(fa.lam_min * log_own(1.0 - us.x));
     uacc = us.y;
   };
-  auto start_segment = [&]() {
-    ++p_seg;
+  // a segment from (x0, y0) in cell (ix, iy): its first faces; then, given the
+  // y faces it crosses, those this stripe owns
+  auto segment_faces = [&]() {
     kx0 = (stx > 0) ? ix + 1 : ix;
     ky0 = (sty > 0) ? iy + 1 : iy;
     ixs = ix;
     jwx = (stx > 0) ? nx - kx0 : kx0;
-    ixe = ix;
-    iye = iy;
-    bface = -1;
-    int nxp = 0, nyp = 0;
-    segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
-    p_cross += static_cast<unsigned>(nxp + nyp);
+  };
+  auto owned_faces = [&](int nyp) {
     // the crossed y faces ky0 + k sty (k < nyp) that this stripe owns
     if (sty > 0) {
       k = max(0, r0 - ky0);
@@ -884,6 +939,17 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
     }
     cnt = 0;
   };
+  auto start_segment = [&]() {      // a later segment (after a null collision)
+    ++p_seg;
+    segment_faces();
+    ixe = ix;
+    iye = iy;
+    bface = -1;
+    int nxp = 0, nyp = 0;
+    segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
+    p_cross += static_cast<unsigned>(nxp + nyp);
+    owned_faces(nyp);
+  };
   auto owned = [&](int row) { return row >= r0 && row < r1; };
   auto retire = [&]() {          // the particle ended in row iye of this stripe
     ++n_fl;
@@ -894,33 +960,57 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   for (;;) {
     if (!live) {
       bool got = false;
+      unsigned long long pc = 0;
       while (pnext < pe) {
-        const unsigned long long pc = pnext;
+        pc = pnext;
         pnext += BS;
-        // emitters fastest: neighbouring lanes start in different cells
-        kk = static_cast<uint32_t>(pc / n_emit);
-        e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
-        q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
+        q = rec.q[pc];
         if (q == 0) continue;
-        sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
+        iy = rec.iy[pc];
+        iye = rec.iye[pc];
+        sy = rec.sy[pc];
         sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
-        // a particle moving away from the stripe (or along a row outside
-        // it) crosses none of its faces and ends in none of its rows
-        if ((sty > 0 && iy >= r1) || (sty < 0 && iy < r0) || (sty == 0 && !owned(iy))) continue;
+        // without null collisions the first segment is the whole flight: a
+        // stripe outside its rows has nothing of it (a flight absorbed by a y
+        // wall keeps its start row as end row, but spans the rows up to the
+        // wall); with them, a particle moving away from the stripe (or along
+        // a row outside it) never reaches it
+        if (!fa.has_null) {
+          int lo = min(iy, iye), hi = max(iy, iye);
+          if (rec.bface[pc] >= 2 * m.ny) {
+            if (sty > 0) hi = m.ny - 1;
+            else lo = 0;
+          }
+          if (hi < r0 || lo >= r1) continue;
+        } else if ((sty > 0 && iy >= r1) || (sty < 0 && iy < r0) || (sty == 0 && !owned(iy))) {
+          continue;
+        }
         got = true;
         break;
       }
       if (!got) break;
+      // emitters fastest: neighbouring lanes start in different cells
+      kk = static_cast<uint32_t>(pc / n_emit);
+      e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
+      ix = rec.ix[pc];
+      x0 = rec.x0[pc];
+      y0 = rec.y0[pc];
+      sx = rec.sx[pc];
+      ell = rec.ell[pc];
+      uacc = rec.uacc[pc];
+      ixe = rec.ixe[pc];
+      bface = rec.bface[pc];
+      const int nyp = rec.nyp[pc];
       inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
       inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
       stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
       qy = (sty > 0) ? q : -q;
       j = 0;
-      p_seg = 0;
-      p_cross = 0;
+      p_seg = 1;
+      p_cross = static_cast<unsigned>(rec.ncross[pc]);
       live = true;
-      draw_path();
-      start_segment();
+      segment_faces();
+      owned_faces(nyp);
     }
     if (k < k_end) {
       // one owned y-face crossing, in the column reached by the x faces before it

@@ -118,7 +118,19 @@ STRIPE_CASES = {
     "wide_300x7": (lambda: cavity_2d(n=300, ny=7, kn=2.0, particles=200_000, newton=False), {}),
     "tall_9x300": (lambda: cavity_2d(n=9, ny=300, kn=2.0, particles=200_000, newton=False), {}),
     "newton_kn1": (lambda: cavity_2d(n=64, kn=1.0, particles=400_000, newton=False), "newton"),
+    # rows 2400 cells long: a few rows per stripe, several stripes, flights
+    # crossing them and ending on the y walls (without and with null collisions)
+    "wide_2400x30_stripes": (lambda: cavity_2d(n=2400, ny=30, kn=0.05, particles=300_000,
+                                               newton=False), {}),
+    "wide_2400x30_null": (lambda: _wide_null(), {}),
 }
+
+
+def _wide_null():
+    w = cavity_2d(n=2400, ny=30, kn=0.05, particles=300_000, newton=False)
+    ix = np.tile(np.arange(2400), 30)
+    w.tau = np.where(ix < 800, 10.0 * np.asarray(w.tau), np.asarray(w.tau))
+    return w
 
 
 @pytest.mark.parametrize("name", list(STRIPE_CASES))
