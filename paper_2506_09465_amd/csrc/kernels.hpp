@@ -879,7 +879,7 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   const int nx = m.nx;
   const int r0 = static_cast<int>(blockIdx.y) * R, r1 = min(r0 + R, m.ny);
   const int r1f = (r1 == m.ny) ? m.ny + 1 : r1;
-  const int nrow = r1 - r0, nface = r1f - r0;
+  const int nface = r1f - r0;
   long long *By = lds_words;                                  // [nface][nx]
   long long *Bl = By + nface * nx;                            // [n_b] when lds_walls
   const int nwords = nface * nx + (in.lds_walls ? m.n_b : 0);
