@@ -724,19 +724,12 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
           ev ? reinterpret_cast<const void *>(iugkp::march_stripes_ev_kernel<kStripeBlock>)
              : reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>);
       HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kStripeBlock, lds));
-      // (the analog kernel reads every particle's first segment from records
-      // of about 70 bytes per particle; without the memory, tiles are used)
+      // (the analog kernel reads every particle's first segment from a
+      // 96-byte record per particle; without the memory, tiles are used)
       bool recs = true;
       if (!ev) {
         const size_t np = static_cast<size_t>(m.n_emit) * static_cast<size_t>(d.N);
-        iugkp::StripeRec &r = ih.rec;
-        recs = ih.alloc(&r.x0, np) == hipSuccess && ih.alloc(&r.y0, np) == hipSuccess &&
-               ih.alloc(&r.sx, np) == hipSuccess && ih.alloc(&r.sy, np) == hipSuccess &&
-               ih.alloc(&r.ell, np) == hipSuccess && ih.alloc(&r.uacc, np) == hipSuccess &&
-               ih.alloc(&r.q, np) == hipSuccess && ih.alloc(&r.ix, np) == hipSuccess &&
-               ih.alloc(&r.iy, np) == hipSuccess && ih.alloc(&r.ixe, np) == hipSuccess &&
-               ih.alloc(&r.iye, np) == hipSuccess && ih.alloc(&r.bface, np) == hipSuccess &&
-               ih.alloc(&r.nyp, np) == hipSuccess && ih.alloc(&r.ncross, np) == hipSuccess;
+        recs = ih.alloc(&ih.rec.r, np) == hipSuccess;
         if (!recs) (void)hipGetLastError();
       }
       if (per_cu >= 1 && recs) {

@@ -812,15 +812,19 @@ __device__ __forceinline__ int faces_upto_near(int cnt, int k0, int st, int jmax
 // hold the others of their wavefront.
 // ---------------------------------------------------------------------------
 // Every particle's start and first segment, sampled once per iteration for
-// all row stripes (structure of arrays, indexed by the particle's place in
-// the enumeration, emitters fastest): weight (0: no particle), start cell
-// and point, direction, free path and acceptance draw, and the segment's end
-// in closed form (end cell, wall face or -1, y faces crossed, all faces
-// crossed).
+// all row stripes (one 96-byte record per particle, indexed by its place in
+// the enumeration, emitters fastest: the lanes of a stripe wavefront drift
+// apart in that order, so a particle's fields share one or two cache lines):
+// weight (0: no particle), start cell and point, direction, free path and
+// acceptance draw, and the segment's end in closed form (end cell, wall face
+// or -1, y faces crossed, all faces crossed).
+struct alignas(32) PRec {
+  long long q;
+  double sy, x0, y0, sx, ell, uacc;
+  int iy, iye, bface, ix, ixe, nyp, ncross, pad;
+};
 struct StripeRec {
-  double *x0, *y0, *sx, *sy, *ell, *uacc;
-  long long *q;
-  int *ix, *iy, *ixe, *iye, *bface, *nyp, *ncross;
+  PRec *r;
 };
 
 template <int BS>
@@ -838,7 +842,8 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
   const uint32_t kk = static_cast<uint32_t>(pc / n_emit);
   const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
   const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
-  rec.q[pc] = q;
+  PRec &out = rec.r[pc];
+  out.q = q;
   if (q == 0) return;
   int ix = 0, iy = 0;
   double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
@@ -853,19 +858,19 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
   const int ky0 = (sty > 0) ? iy + 1 : iy;
   int ixe = ix, iye = iy, bface = -1, nxp = 0, nyp = 0;
   segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
-  rec.x0[pc] = x0;
-  rec.y0[pc] = y0;
-  rec.sx[pc] = sx;
-  rec.sy[pc] = sy;
-  rec.ell[pc] = ell;
-  rec.uacc[pc] = us.y;
-  rec.ix[pc] = ix;
-  rec.iy[pc] = iy;
-  rec.ixe[pc] = ixe;
-  rec.iye[pc] = iye;
-  rec.bface[pc] = bface;
-  rec.nyp[pc] = nyp;
-  rec.ncross[pc] = nxp + nyp;
+  out.sy = sy;
+  out.x0 = x0;
+  out.y0 = y0;
+  out.sx = sx;
+  out.ell = ell;
+  out.uacc = us.y;
+  out.iy = iy;
+  out.iye = iye;
+  out.bface = bface;
+  out.ix = ix;
+  out.ixe = ixe;
+  out.nyp = nyp;
+  out.ncross = nxp + nyp;
 }
 
 template <int BS>
@@ -964,11 +969,12 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       while (pnext < pe) {
         pc = pnext;
         pnext += BS;
-        q = rec.q[pc];
+        const PRec &rp = rec.r[pc];
+        q = rp.q;
         if (q == 0) continue;
-        iy = rec.iy[pc];
-        iye = rec.iye[pc];
-        sy = rec.sy[pc];
+        iy = rp.iy;
+        iye = rp.iye;
+        sy = rp.sy;
         sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
         // without null collisions the first segment is the whole flight: a
         // stripe outside its rows has nothing of it (a flight absorbed by a y
@@ -977,7 +983,7 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
         // a row outside it) never reaches it
         if (!fa.has_null) {
           int lo = min(iy, iye), hi = max(iy, iye);
-          if (rec.bface[pc] >= 2 * m.ny) {
+          if (rp.bface >= 2 * m.ny) {
             if (sty > 0) hi = m.ny - 1;
             else lo = 0;
           }
@@ -992,22 +998,23 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       // emitters fastest: neighbouring lanes start in different cells
       kk = static_cast<uint32_t>(pc / n_emit);
       e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
-      ix = rec.ix[pc];
-      x0 = rec.x0[pc];
-      y0 = rec.y0[pc];
-      sx = rec.sx[pc];
-      ell = rec.ell[pc];
-      uacc = rec.uacc[pc];
-      ixe = rec.ixe[pc];
-      bface = rec.bface[pc];
-      const int nyp = rec.nyp[pc];
+      const PRec &rp = rec.r[pc];
+      ix = rp.ix;
+      x0 = rp.x0;
+      y0 = rp.y0;
+      sx = rp.sx;
+      ell = rp.ell;
+      uacc = rp.uacc;
+      ixe = rp.ixe;
+      bface = rp.bface;
+      const int nyp = rp.nyp;
       inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
       inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
       stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
       qy = (sty > 0) ? q : -q;
       j = 0;
       p_seg = 1;
-      p_cross = static_cast<unsigned>(rec.ncross[pc]);
+      p_cross = static_cast<unsigned>(rp.ncross);
       live = true;
       segment_faces();
       owned_faces(nyp);
