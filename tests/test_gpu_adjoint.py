@@ -67,14 +67,18 @@ def test_batch_with_source_equals_single(gpu):
         assert torch.equal(T, Tb) and torch.equal(qx, qxb) and torch.equal(qy, qyb)
 
 
-@pytest.mark.parametrize("newton", [False, True])
+@pytest.mark.parametrize("newton", [False, True, "mg"])
 def test_adjoint_bitwise_vs_oracle(oracle_mod, gpu, newton):
+    """Forward solve and adjoint against the oracle, without the Newton step,
+    with it (plain CG) and with the multigrid-preconditioned CG."""
     w = _with_source(cavity_2d(n=14, ny=11, kn=0.3, particles=50_000, newton=False))
     kw = dict(rng_mode=oracle_mod.CRN, max_iters=400, res_tol=1e-10,
               tally_faces=oracle_mod.FACES_OFF)
     if newton:
         Dx, Dy = _diff(w)
         kw.update(newton=True, diff_x=Dx, diff_y=Dy)
+    if newton == "mg":
+        kw.update(cg_precond=oracle_mod.PRECOND_MG)
     o, s = _pair(oracle_mod, gpu, w, **kw)
     rc_o, To, _, _ = o.solve()
     rc, T, _, _, _ = s.solve()
