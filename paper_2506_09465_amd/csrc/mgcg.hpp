@@ -25,7 +25,9 @@
 // group barrier, with coherent loads (xld / xst).  Per grid level the descent
 // takes two phases (second pre-sweep; residual and restriction, which also
 // does the first sweep of the next level) and the ascent two (correction with
-// the first post-sweep; second post-sweep).  The remaining small levels run
+// the first post-sweep; second post-sweep, which for a level whose finer
+// level has at most one cell per thread is recomputed where that level reads
+// it instead).  The remaining small levels run
 // redundantly in every workgroup's LDS, so the coarse solve needs no barrier
 // of its own and its result is at hand wherever the next grid level needs it.
 #pragma once
@@ -470,11 +472,35 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
             [&](int i, double v) { Tm[i] = v; });
       }
     }
+    // Ascent.  The last sweep of a grid level whose finer level has at most
+    // one cell per thread is not stored: that finer level's first post-sweep
+    // recomputes it at the (at most three) aggregates its cell and neighbours
+    // use, with the same operations, so it needs no phase and no barrier of
+    // its own.
+    auto fused = [&](int k) { return k >= 1 && lv[k - 1].n <= nthr; };
     for (int k = Lg - 1; k >= 0; --k) {
       const MGLevel F = lv[k], Cl = lv[k + 1];
+      const bool recompute = (k + 1 < Lg) && fused(k + 1);
+      // the coarse level's final value at aggregate P: from LDS, or the
+      // second post-sweep of a grid level evaluated here
+      auto e_grid = [&](int P) {
+        const MGRow rc = mg_row(Cl, P);
+        const double b = xld(&Cl.b[P]);
+        double v5[5];
+        v5[0] = xld(&Cl.xd[P]);
+        v5[1] = xld(&Cl.xd[rc.jl]);
+        v5[2] = xld(&Cl.xd[rc.jr]);
+        v5[3] = xld(&Cl.xd[rc.jd]);
+        v5[4] = xld(&Cl.xd[rc.ju]);
+        const double t = b - mg_apply_vals(rc, v5);
+        return v5[0] + (kMgOmega * t) / rc.dg;
+      };
       auto post1 = [&](auto FromLds) {
+        // (one cell at a time when the coarse values are recomputed: three
+        // rows and stencils of loads per cell)
+        using QP = std::conditional_t<decltype(FromLds)::value == 2, Q1, Q2>;
         for_flat(
-            Q2{}, F.n,
+            QP{}, F.n,
             [&](int c) {
               // x after the coarse correction, x_b + s e(parent), on the cell
               // and its neighbours: loads first, then the arithmetic
@@ -484,10 +510,24 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
               mg_parents(r, Cl.nx, pc);
               double xb5[5], e5[5];
 #pragma unroll
-              for (int q = 0; q < 5; ++q) {
-                xb5[q] = xld(&F.xb[js[q]]);
-                if constexpr (decltype(FromLds)::value) e5[q] = lds[Cl.lt + pc[q]];
-                else e5[q] = xld(&Cl.e[pc[q]]);
+              for (int q = 0; q < 5; ++q) xb5[q] = xld(&F.xb[js[q]]);
+              if constexpr (decltype(FromLds)::value == 1) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) e5[q] = lds[Cl.lt + pc[q]];
+              } else if constexpr (decltype(FromLds)::value == 0) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) e5[q] = xld(&Cl.e[pc[q]]);
+              } else {
+                // distinct aggregates: the cell's own, the one across an x
+                // face (left or right) and the one across a y face
+                const int px = (pc[1] != pc[0]) ? pc[1] : pc[2];
+                const int py = (pc[3] != pc[0]) ? pc[3] : pc[4];
+                const double e0 = e_grid(pc[0]), ex = e_grid(px), ey = e_grid(py);
+                e5[0] = e0;
+                e5[1] = (pc[1] == pc[0]) ? e0 : ex;
+                e5[2] = (pc[2] == pc[0]) ? e0 : ex;
+                e5[3] = (pc[3] == pc[0]) ? e0 : ey;
+                e5[4] = (pc[4] == pc[0]) ? e0 : ey;
               }
               const double bc = xld(&F.b[c]);
               double xc5[5];
@@ -498,9 +538,12 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
             },
             [&](int c, double v) { xst(&F.xd[c], v); });
       };
-      if (k + 1 == Lg) post1(std::true_type{});
-      else post1(std::false_type{});
+      // e of the coarse level: 1 from LDS, 0 stored by its last sweep, 2 recomputed
+      if (k + 1 == Lg) post1(std::integral_constant<int, 1>{});
+      else if (recompute) post1(std::integral_constant<int, 2>{});
+      else post1(std::integral_constant<int, 0>{});
       if (!bar()) return false;
+      if (fused(k)) continue;               // (recomputed by the next level)
       for_flat(
           Q2{}, F.n,
           [&](int c) {
