@@ -129,7 +129,9 @@ typedef struct iugkp_options {
                                    the result does not depend on it */
   int cg_waves;                 /* single solves: 256-cell tree blocks per CG workgroup, 0
                                    (= 8) or 1..12 with the CG state in registers, -1..-12 with
-                                   it in global memory; the result does not depend on it */
+                                   it in global memory (with IUGKP_PRECOND_MG: |cg_waves|
+                                   wavefronts per workgroup); the result does not depend on
+                                   it */
   int scheme;                   /* IUGKP_SCHEME_EMITTERS (0): every emitter flies N fresh
                                    particles per iteration, null collisions followed within
                                    the iteration.  IUGKP_SCHEME_PERSISTENT (1): the variable-tau
