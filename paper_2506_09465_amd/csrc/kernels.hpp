@@ -1020,12 +1020,15 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       owned_faces(nyp);
     }
     if (k < k_end) {
-      // one owned y-face crossing, in the column reached by the x faces before it
-      const int kyk = ky0 + k * sty;
-      const double ty = (static_cast<double>(kyk) * m.dy - y0) * inv_sy;
-      if (stx) cnt = faces_upto_near(cnt, kx0, stx, jwx, m.dx, inv_dx, x0, inv_sx, sx, ty);
-      lds_add(&By[(kyk - r0) * nx + ixs + stx * cnt], qy);
-      ++k;
+      // all the segment's owned y-face crossings, each in the column reached
+      // by the x faces before it, in one trip through the state machine
+      // (one trip per crossing cost a fifth more)
+      for (; k < k_end; ++k) {
+        const int kyk = ky0 + k * sty;
+        const double ty = (static_cast<double>(kyk) * m.dy - y0) * inv_sy;
+        if (stx) cnt = faces_upto_near(cnt, kx0, stx, jwx, m.dx, inv_dx, x0, inv_sx, sx, ty);
+        lds_add(&By[(kyk - r0) * nx + ixs + stx * cnt], qy);
+      }
       continue;
     }
     // the segment's end
