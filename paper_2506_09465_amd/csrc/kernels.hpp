@@ -1019,7 +1019,7 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       segment_faces();
       owned_faces(nyp);
     }
-    if (k < k_end) {
+    {
       // all the segment's owned y-face crossings, each in the column reached
       // by the x faces before it, in one trip through the state machine
       // (one trip per crossing cost a fifth more)
@@ -1029,9 +1029,8 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
         if (stx) cnt = faces_upto_near(cnt, kx0, stx, jwx, m.dx, inv_dx, x0, inv_sx, sx, ty);
         lds_add(&By[(kyk - r0) * nx + ixs + stx * cnt], qy);
       }
-      continue;
     }
-    // the segment's end
+    // the segment's end (in the same trip)
     if (bface >= 0) {
       if (owned(iye)) {
         if (!in.lds_walls) atom_add(&in.B[bface], q);
