@@ -823,8 +823,14 @@ struct alignas(32) PRec {
   double sy, x0, y0, sx, ell, uacc;
   int iy, iye, bface, ix, ixe, nyp, ncross, pad;
 };
+// and, beside it, the rows that stripes must run the particle in (lo, hi:
+// empty for no particle): the rows of a first segment that is the whole
+// flight (up to the wall for an absorption on a y wall), or with null
+// collisions every row in its direction of travel.  A stripe reads 8 bytes
+// per particle to skip those outside its rows, not the whole record.
 struct StripeRec {
   PRec *r;
+  int2 *key;
 };
 
 template <int BS>
@@ -844,7 +850,10 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
   const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
   PRec &out = rec.r[pc];
   out.q = q;
-  if (q == 0) return;
+  if (q == 0) {
+    rec.key[pc] = make_int2(m.ny, -1);
+    return;
+  }
   int ix = 0, iy = 0;
   double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
   sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
@@ -871,6 +880,15 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
   out.ixe = ixe;
   out.nyp = nyp;
   out.ncross = nxp + nyp;
+  int lo = min(iy, iye), hi = max(iy, iye);
+  if (fa.has_null) {
+    lo = (sty < 0) ? 0 : iy;
+    hi = (sty > 0) ? m.ny - 1 : iy;
+  } else if (bface >= 2 * m.ny) {
+    if (sty > 0) hi = m.ny - 1;
+    else lo = 0;
+  }
+  rec.key[pc] = make_int2(lo, hi);
 }
 
 template <int BS>
@@ -969,28 +987,9 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       while (pnext < pe) {
         pc = pnext;
         pnext += BS;
-        const PRec &rp = rec.r[pc];
-        q = rp.q;
-        if (q == 0) continue;
-        iy = rp.iy;
-        iye = rp.iye;
-        sy = rp.sy;
-        sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
-        // without null collisions the first segment is the whole flight: a
-        // stripe outside its rows has nothing of it (a flight absorbed by a y
-        // wall keeps its start row as end row, but spans the rows up to the
-        // wall); with them, a particle moving away from the stripe (or along
-        // a row outside it) never reaches it
-        if (!fa.has_null) {
-          int lo = min(iy, iye), hi = max(iy, iye);
-          if (rp.bface >= 2 * m.ny) {
-            if (sty > 0) hi = m.ny - 1;
-            else lo = 0;
-          }
-          if (hi < r0 || lo >= r1) continue;
-        } else if ((sty > 0 && iy >= r1) || (sty < 0 && iy < r0) || (sty == 0 && !owned(iy))) {
-          continue;
-        }
+        // a stripe outside the rows the particle can reach has nothing of it
+        const int2 key = rec.key[pc];
+        if (key.y < r0 || key.x >= r1) continue;
         got = true;
         break;
       }
@@ -999,6 +998,11 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       kk = static_cast<uint32_t>(pc / n_emit);
       e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
       const PRec &rp = rec.r[pc];
+      q = rp.q;
+      iy = rp.iy;
+      iye = rp.iye;
+      sy = rp.sy;
+      sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
       ix = rp.ix;
       x0 = rp.x0;
       y0 = rp.y0;
