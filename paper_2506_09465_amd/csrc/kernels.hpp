@@ -898,14 +898,18 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   extern __shared__ long long lds_words[];
   __shared__ unsigned long long s_cnt[3];
   const Inst &in = insts[0];
-  const Mesh &m = in.m;
+  // (the mesh and the tally pointers in registers: reloaded inside the state
+  // machine, each load would also wait for the lane's pending LDS atomics)
+  const Mesh m = in.m;
+  long long *const gD = in.D, *const gW = in.W, *const gB = in.B, *const gPhiy = in.Phiy;
+  const bool lds_walls = in.lds_walls != 0;
   const int nx = m.nx;
   const int r0 = static_cast<int>(blockIdx.y) * R, r1 = min(r0 + R, m.ny);
   const int r1f = (r1 == m.ny) ? m.ny + 1 : r1;
   const int nface = r1f - r0;
   long long *By = lds_words;                                  // [nface][nx]
   long long *Bl = By + nface * nx;                            // [n_b] when lds_walls
-  const int nwords = nface * nx + (in.lds_walls ? m.n_b : 0);
+  const int nwords = nface * nx + (lds_walls ? m.n_b : 0);
   for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
   if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -923,6 +927,9 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   unsigned long long pnext = pb + threadIdx.x;
   unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
   const double inv_dx = 1.0 / m.dx;       // (only to estimate a face count)
+  // the row range of the lane's next candidate, loaded one particle ahead
+  const int2 none = make_int2(m.ny, -1);
+  int2 nkey = (pnext < pe) ? rec.key[pnext] : none;
 
   // the lane's particle
   bool live = false;
@@ -988,7 +995,8 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
         pc = pnext;
         pnext += BS;
         // a stripe outside the rows the particle can reach has nothing of it
-        const int2 key = rec.key[pc];
+        const int2 key = nkey;
+        nkey = (pnext < pe) ? rec.key[pnext] : none;
         if (key.y < r0 || key.x >= r1) continue;
         got = true;
         break;
@@ -1037,7 +1045,7 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
     // the segment's end (in the same trip)
     if (bface >= 0) {
       if (owned(iye)) {
-        if (!in.lds_walls) atom_add(&in.B[bface], q);
+        if (!lds_walls) atom_add(&gB[bface], q);
         else lds_add(&Bl[bface], q);
         retire();
       }
@@ -1047,16 +1055,16 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
     const int c = ixe + nx * iye;
     if (!fa.has_null) {
       if (owned(iye)) {
-        atom_add(&in.D[c], q);
+        atom_add(&gD[c], q);
         retire();
       }
       live = false;
       continue;
     }
-    if (owned(iye)) atom_add(&in.W[c], q);
+    if (owned(iye)) atom_add(&gW[c], q);
     if (uacc < fa.ratio[c] || j == kMaxSegments - 1) {
       if (owned(iye)) {
-        atom_add(&in.D[c], q);
+        atom_add(&gD[c], q);
         retire();
       }
       live = false;
@@ -1081,10 +1089,10 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   __syncthreads();
   // row-contiguous flush
   for (int i = threadIdx.x; i < nface * nx; i += BS)
-    if (By[i]) atom_add(&in.Phiy[r0 * nx + i], By[i]);
-  if (in.lds_walls)
+    if (By[i]) atom_add(&gPhiy[r0 * nx + i], By[i]);
+  if (lds_walls)
     for (int b = threadIdx.x; b < m.n_b; b += BS)
-      if (Bl[b]) atom_add(&in.B[b], Bl[b]);
+      if (Bl[b]) atom_add(&gB[b], Bl[b]);
   if (threadIdx.x == 0 && s_cnt[0]) {
     atomicAdd(&in.sc->flights, s_cnt[0]);
     atomicAdd(&in.sc->segments, s_cnt[1]);
