@@ -837,58 +837,73 @@ template <int BS>
 __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__restrict__ insts,
                                                               StripeRec rec)
 {
+  // the workgroup's records are built in LDS and written out as contiguous
+  // 16-byte stores (a lane storing its own record field by field writes
+  // 8 bytes every 96)
+  __shared__ PRec srec[BS];
   const Inst &in = insts[0];
   const Mesh &m = in.m;
   const FlyIn fa = {m, in.lam_min, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1, 1,
                     in.has_null, in.ratio, in.e_off};
   const unsigned long long n_emit = static_cast<unsigned long long>(m.n_emit);
   const unsigned long long total = n_emit * in.N;
-  const unsigned long long pc = static_cast<unsigned long long>(blockIdx.x) * BS + threadIdx.x;
-  if (pc >= total) return;
-  const uint32_t kk = static_cast<uint32_t>(pc / n_emit);
-  const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
-  const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
-  PRec &out = rec.r[pc];
-  out.q = q;
-  if (q == 0) {
-    rec.key[pc] = make_int2(m.ny, -1);
-    return;
+  const unsigned long long p0 = static_cast<unsigned long long>(blockIdx.x) * BS;
+  const unsigned long long pc = p0 + threadIdx.x;
+  if (pc < total) {
+    const uint32_t kk = static_cast<uint32_t>(pc / n_emit);
+    const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
+    const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
+    PRec &out = srec[threadIdx.x];
+    out.q = q;
+    if (q == 0) {
+      rec.key[pc] = make_int2(m.ny, -1);
+    } else {
+      int ix = 0, iy = 0;
+      double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
+      sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
+      const double2 us = draw2(2u, kk, e + fa.e_off, fa.slot, fa.key0, fa.key1);
+      const double ell = -(fa.lam_min * log_own(1.0 - us.x));
+      const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+      const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+      const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+      const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+      const int kx0 = (stx > 0) ? ix + 1 : ix;
+      const int ky0 = (sty > 0) ? iy + 1 : iy;
+      int ixe = ix, iye = iy, bface = -1, nxp = 0, nyp = 0;
+      segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
+      out.sy = sy;
+      out.x0 = x0;
+      out.y0 = y0;
+      out.sx = sx;
+      out.ell = ell;
+      out.uacc = us.y;
+      out.iy = iy;
+      out.iye = iye;
+      out.bface = bface;
+      out.ix = ix;
+      out.ixe = ixe;
+      out.nyp = nyp;
+      out.ncross = nxp + nyp;
+      int lo = min(iy, iye), hi = max(iy, iye);
+      if (fa.has_null) {
+        lo = (sty < 0) ? 0 : iy;
+        hi = (sty > 0) ? m.ny - 1 : iy;
+      } else if (bface >= 2 * m.ny) {
+        if (sty > 0) hi = m.ny - 1;
+        else lo = 0;
+      }
+      rec.key[pc] = make_int2(lo, hi);
+    }
   }
-  int ix = 0, iy = 0;
-  double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
-  sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
-  const double2 us = draw2(2u, kk, e + fa.e_off, fa.slot, fa.key0, fa.key1);
-  const double ell = -(fa.lam_min * log_own(1.0 - us.x));
-  const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
-  const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
-  const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
-  const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
-  const int kx0 = (stx > 0) ? ix + 1 : ix;
-  const int ky0 = (sty > 0) ? iy + 1 : iy;
-  int ixe = ix, iye = iy, bface = -1, nxp = 0, nyp = 0;
-  segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
-  out.sy = sy;
-  out.x0 = x0;
-  out.y0 = y0;
-  out.sx = sx;
-  out.ell = ell;
-  out.uacc = us.y;
-  out.iy = iy;
-  out.iye = iye;
-  out.bface = bface;
-  out.ix = ix;
-  out.ixe = ixe;
-  out.nyp = nyp;
-  out.ncross = nxp + nyp;
-  int lo = min(iy, iye), hi = max(iy, iye);
-  if (fa.has_null) {
-    lo = (sty < 0) ? 0 : iy;
-    hi = (sty > 0) ? m.ny - 1 : iy;
-  } else if (bface >= 2 * m.ny) {
-    if (sty > 0) hi = m.ny - 1;
-    else lo = 0;
-  }
-  rec.key[pc] = make_int2(lo, hi);
+  __syncthreads();
+  // (a record without a particle is never read past its weight)
+  constexpr int kWords = static_cast<int>(sizeof(PRec) / sizeof(uint4));
+  static_assert(sizeof(PRec) % sizeof(uint4) == 0, "records are whole 16-byte words");
+  const unsigned long long left = (p0 < total) ? total - p0 : 0;
+  const int n = static_cast<int>(left < BS ? left : BS) * kWords;
+  const uint4 *src = reinterpret_cast<const uint4 *>(srec);
+  uint4 *dst = reinterpret_cast<uint4 *>(rec.r + p0);
+  for (int i = threadIdx.x; i < n; i += BS) dst[i] = src[i];
 }
 
 template <int BS>
