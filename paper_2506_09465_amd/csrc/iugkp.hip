@@ -46,7 +46,7 @@ int fail(int code, const std::string &msg)
 constexpr int kCgGridMax = 64;               // workgroups of one CG group (barrier arrivals)
 constexpr int kCgWavesDefault = 8;           // tree blocks per CG workgroup of a single solve
 constexpr int kBarStride = 64;               // batched CG barriers 256 bytes apart (no shared lines)
-constexpr double kStripeMinCells = 12.0;     // row stripes for face tallies when lambda_min >= 12 cells
+constexpr double kStripeMinCells = 7.0;      // row stripes for face tallies when lambda_min >= 7 cells
 constexpr int kStripeBlock = 1024;           // threads of a stripe workgroup
 constexpr int kStripeMinRows = 4;
 constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of a CG workgroup
