@@ -313,6 +313,16 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
     }
     __syncthreads();
   };
+  // a level of at most one cell per lane, run by wavefront 0 alone: its LDS
+  // operations execute in order, so a pass needs no workgroup barrier
+  auto for_wave = [&](int nl, auto compute, auto store) {
+    const int i = static_cast<int>(threadIdx.x);
+    const auto v = compute(i < nl ? i : 0);
+    if (i < nl) store(i, v);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
   auto sweep_first = [&](double bv, double dg) { return 0.0 + (kMgOmega * bv) / dg; };
   struct V2 {
     double a, b;
@@ -407,11 +417,14 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
             if (L - 1 > Lg) lds[T.lx + i] = v.b;
             else lds[T.lt + i] = v.a / lds[T.lc + 5 * i];
           });
-      for (int k = Lg; k < L - 1; ++k) {
+      // descent step at level k (second sweep, restriction with the next
+      // level's first sweep) and ascent step (corrected first post-sweep,
+      // second post-sweep), with `run` one of the two pass forms
+      auto down = [&](int k, auto run) {
         const MGLevel F = lv[k], Cl = lv[k + 1];
         const double *B = lds + F.lb, *X = lds + F.lx;
         double *Tm = lds + F.lt;
-        for_local(
+        run(
             F.n,
             [&](int i) {
               const MGRow r = mg_row_lds(F, lds, i);
@@ -420,7 +433,7 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
             },
             [&](int i, double v) { Tm[i] = v; });
         const bool last = (k + 1 == L - 1);
-        for_local(
+        run(
             Cl.n,
             [&](int C) {
               const int J = C / Cl.nx, I = C - J * Cl.nx;
@@ -443,12 +456,12 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
               if (last) lds[Cl.lt + C] = v / dg;
               else lds[Cl.lx + C] = sweep_first(v, dg);
             });
-      }
-      for (int k = L - 2; k >= Lg; --k) {
+      };
+      auto up = [&](int k, auto run) {
         const MGLevel F = lv[k], Cl = lv[k + 1];
         const double *B = lds + F.lb, *E = lds + Cl.lt;
         double *X = lds + F.lx, *Tm = lds + F.lt;
-        for_local(
+        run(
             F.n,
             [&](int i) {
               const MGRow r = mg_row_lds(F, lds, i);
@@ -462,7 +475,7 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
               return xc5[0] + (kMgOmega * t) / r.dg;
             },
             [&](int i, double v) { X[i] = v; });
-        for_local(
+        run(
             F.n,
             [&](int i) {
               const MGRow r = mg_row_lds(F, lds, i);
@@ -470,7 +483,19 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
               return X[i] + (kMgOmega * t) / r.dg;
             },
             [&](int i, double v) { Tm[i] = v; });
+      };
+      // the levels of at most 64 cells (from ks on) by wavefront 0 alone
+      int ks = Lg;
+      while (ks < L - 1 && lv[ks].n > 64) ++ks;
+      for (int k = Lg; k < ks; ++k) down(k, for_local);
+      if (ks < L - 1) {
+        if (threadIdx.x < 64) {
+          for (int k = ks; k < L - 1; ++k) down(k, for_wave);
+          for (int k = L - 2; k >= ks; --k) up(k, for_wave);
+        }
+        __syncthreads();
       }
+      for (int k = ks - 1; k >= Lg; --k) up(k, for_local);
     }
     // Ascent.  The last sweep of a grid level whose finer level has at most
     // one cell per thread is not stored: that finer level's first post-sweep
