@@ -806,10 +806,12 @@ __device__ __forceinline__ int faces_upto_near(int cnt, int k0, int st, int jmax
 // deposits, wall absorption and counters go to the stripe holding the row
 // where that event happens; the deposits (one per particle, one W per null
 // segment) go straight to global memory, which leaves the LDS to the y faces
-// and so halves the number of stripes every particle is sampled in.  All
-// tallies are integer sums, so the result is the tile kernel's bit for bit.  Each lane runs a small state machine (next particle
-// / one y-face crossing / segment end), so lanes with long flights do not
-// hold the others of their wavefront.
+// and so roughly halves the number of stripes that read each particle.  All
+// tallies are integer sums, so the result is the tile kernel's bit for bit.
+// Each lane runs a small state machine, one trip per segment (an idle lane
+// takes its next particle; then the segment's owned y-face crossings and its
+// end), so a lane with a long flight holds the others of its wavefront for
+// one segment at a time.
 // ---------------------------------------------------------------------------
 // Every particle's start and first segment, sampled once per iteration for
 // all row stripes (one 96-byte record per particle, indexed by its place in
