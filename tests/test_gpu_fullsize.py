@@ -8,7 +8,8 @@ bench.py times, checked through properties that hold exactly at any size
   * emission: the next emission is rint(2^F (E V) tau_min / tau) after the
     Newton step (uniform tau: ratio 1), or D without it;
   * the 2D gray cavity's four Kn problems stepped as a group equal the same
-    problems stepped alone.
+    problems stepped alone;
+  * the emitter-tile and row-stripe particle steps give equal tallies.
 """
 import numpy as np
 import pytest
@@ -47,7 +48,8 @@ def test_cavity_256_grouped_bench_configuration(gpu):
     problem and iteration, the Newton emission rule, and bitwise equality with
     the same problems stepped one at a time."""
     ws = [cavity_2d(n=256, kn=kn, particles=10_000_000, newton=True, seed=0) for kn in KNS]
-    grouped = [gpu.Solver(w, tally_faces=gpu.FACES_EVERY, own_stream=True) for w in ws]
+    grouped = [gpu.Solver(w, tally_faces=gpu.FACES_EVERY, own_stream=True,
+                          cg_precond=gpu.PRECOND_MG) for w in ws]
     for it in range(2):
         G0 = [s.state()[3] for s in grouped]
         assert gpu.step_group(grouped, 1) == 0
@@ -60,12 +62,34 @@ def test_cavity_256_grouped_bench_configuration(gpu):
             _, _, E, G1 = s.state()
             want = torch.round(torch.ldexp(E * (w.dx * w.dy), torch.tensor(F, device=E.device)))
             assert torch.equal(G1[: w.nx * w.ny], want.to(torch.int64))
-    single = [gpu.Solver(w, tally_faces=gpu.FACES_EVERY) for w in ws]
+    single = [gpu.Solver(w, tally_faces=gpu.FACES_EVERY, cg_precond=gpu.PRECOND_MG) for w in ws]
     for s in single:
         assert s.step(2) == 0
     for a, b in zip(grouped, single):
         sa, sb = a.state(), b.state()
         assert torch.equal(sa[2], sb[2]) and torch.equal(sa[3], sb[3])
+
+
+@pytest.mark.parametrize("kn", (0.03, 0.1, 1.0))
+def test_cavity_256_tiles_equal_stripes(gpu, kn):
+    """The two particle-step kernels on the 256^2 cavity at 1e7 particles,
+    from the same state: emitter tiles walking every flight face by face, and
+    row stripes marching pre-sampled records with closed-form segment ends
+    (the automatic choice from Kn 0.03 here).  Two Newton iterations give
+    bitwise equal cell, wall and face tallies, energy and emission."""
+    w = cavity_2d(n=256, kn=kn, particles=10_000_000, newton=True, seed=0)
+    a = gpu.Solver(w, tally_faces=gpu.FACES_EVERY, cg_precond=gpu.PRECOND_MG, march=1)
+    b = gpu.Solver(w, tally_faces=gpu.FACES_EVERY, cg_precond=gpu.PRECOND_MG, march=2)
+    for it in range(2):
+        assert a.step(1) == 0 and b.step(1) == 0
+        ta, tb = a.tallies(), b.tallies()
+        for k in ("D", "B", "Phix", "Phiy"):
+            assert torch.equal(ta[k], tb[k]), (kn, it, k)
+        sa, sb = a.state(), b.state()
+        assert torch.equal(sa[2], sb[2]) and torch.equal(sa[3], sb[3]), (kn, it)
+        assert a.stats()["flights"] == b.stats()["flights"]
+    a.close()
+    b.close()
 
 
 def test_two_material_512_gray_full_size(gpu):
