@@ -725,10 +725,11 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
              : reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>);
       HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kStripeBlock, lds));
       // (the analog kernel reads every particle's first segment from a
-      // 96-byte record and an 8-byte row range per particle; without the
-      // memory, tiles are used)
+      // 96-byte record and a 4-byte row range per particle; without the
+      // memory, or beyond 65534 rows, tiles are used)
       bool recs = true;
-      if (!ev) {
+      if (!ev && m.ny > 0xfffe) recs = false;     // (rows in 16 bits)
+      else if (!ev) {
         const size_t np = static_cast<size_t>(m.n_emit) * static_cast<size_t>(d.N);
         recs = ih.alloc(&ih.rec.r, np) == hipSuccess && ih.alloc(&ih.rec.key, np) == hipSuccess;
         if (!recs) (void)hipGetLastError();

@@ -828,12 +828,17 @@ struct alignas(32) PRec {
 // and, beside it, the rows that stripes must run the particle in (lo, hi:
 // empty for no particle): the rows of a first segment that is the whole
 // flight (up to the wall for an absorption on a y wall), or with null
-// collisions every row in its direction of travel.  A stripe reads 8 bytes
+// collisions every row in its direction of travel, as two 16-bit rows (lo
+// in the high half; no particle: lo 0xffff, hi 0).  A stripe reads 4 bytes
 // per particle to skip those outside its rows, not the whole record.
 struct StripeRec {
   PRec *r;
-  int2 *key;
+  uint32_t *key;
 };
+__device__ __forceinline__ uint32_t row_range(int lo, int hi)
+{
+  return (static_cast<uint32_t>(lo) << 16) | static_cast<uint32_t>(hi);
+}
 
 template <int BS>
 __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__restrict__ insts,
@@ -858,7 +863,7 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
     PRec &out = srec[threadIdx.x];
     out.q = q;
     if (q == 0) {
-      rec.key[pc] = make_int2(m.ny, -1);
+      rec.key[pc] = row_range(0xffff, 0);
     } else {
       int ix = 0, iy = 0;
       double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
@@ -894,7 +899,7 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
         if (sty > 0) hi = m.ny - 1;
         else lo = 0;
       }
-      rec.key[pc] = make_int2(lo, hi);
+      rec.key[pc] = row_range(lo, hi);
     }
   }
   __syncthreads();
@@ -945,8 +950,8 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
   const double inv_dx = 1.0 / m.dx;       // (only to estimate a face count)
   // the row range of the lane's next candidate, loaded one particle ahead
-  const int2 none = make_int2(m.ny, -1);
-  int2 nkey = (pnext < pe) ? rec.key[pnext] : none;
+  const uint32_t none = row_range(0xffff, 0);
+  uint32_t nkey = (pnext < pe) ? rec.key[pnext] : none;
 
   // the lane's particle
   bool live = false;
@@ -1012,9 +1017,9 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
         pc = pnext;
         pnext += BS;
         // a stripe outside the rows the particle can reach has nothing of it
-        const int2 key = nkey;
+        const uint32_t key = nkey;
         nkey = (pnext < pe) ? rec.key[pnext] : none;
-        if (key.y < r0 || key.x >= r1) continue;
+        if (static_cast<int>(key & 0xffffu) < r0 || static_cast<int>(key >> 16) >= r1) continue;
         got = true;
         break;
       }
