@@ -396,6 +396,7 @@ struct orc_state {
   int has_null;        /* some tau_c > tau_min */
   uint32_t iter;
   double d0, res;
+  double res_p1, res_p2;   /* residuals of the two preceding iterations (+inf: none) */
   double *res_hist;
   int res_cap;
   uint64_t flights, segments, crossings, tot_flights, tot_segments, tot_crossings;
@@ -922,6 +923,7 @@ int orc_create(const orc_problem *p, const orc_options *o, orc_state **out)
   s->B = (int64_t *)calloc((size_t)s->nb, sizeof(int64_t));
   s->res_cap = o->max_iters + o->avg_iters + 8;
   s->res_hist = (double *)calloc((size_t)s->res_cap, sizeof(double));
+  s->res_p1 = s->res_p2 = HUGE_VAL;
   for (int c = 0; c < s->nc; ++c) {
     s->ratio[c] = s->tau_min / s->tau[c];
     if (s->ratio[c] != 1.0) s->has_null = 1;
@@ -1335,7 +1337,16 @@ static int orc_iterate(orc_state *s, int faces)
   s->iter++;
   free(E_new);
   free(tmp);
-  if (rc == ORC_OK && (!ok || !orc_check_budget(s->G, s->ne))) rc = ORC_E_FIXED_OVERFLOW;
+  int over = (!ok || !orc_check_budget(s->G, s->ne));
+  /* Growth rule of the Newton iteration (reading R6): the update has grown
+   * beyond the first one (res > 1) and either the next emission left the
+   * fixed-point range or the residual rose in two consecutive iterations. */
+  int grew = s->o.newton && s->res > 1.0 &&
+             (over || (s->res > s->res_p1 && s->res_p1 > s->res_p2));
+  s->res_p2 = s->res_p1;
+  s->res_p1 = s->res;
+  if (rc == ORC_OK && grew) rc = ORC_E_DIVERGED;
+  if (rc == ORC_OK && over) rc = ORC_E_FIXED_OVERFLOW;
   if (rc == ORC_OK && s->iter > 1 && s->res > 1e3) rc = ORC_E_DIVERGED;
   return rc;
 }
@@ -1448,6 +1459,7 @@ int orc_set_state(orc_state *s, uint32_t iter, double d0, const double *E, const
 {
   s->iter = iter;
   s->d0 = d0;
+  s->res_p1 = s->res_p2 = HUGE_VAL;
   memcpy(s->E, E, sizeof(double) * s->nc);
   memcpy(s->G, G, sizeof(int64_t) * s->ne);
   return orc_check_budget(s->G, s->ne) ? ORC_OK : ORC_E_FIXED_OVERFLOW;

@@ -753,6 +753,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   HIP_TRY(hipMemcpyAsync(g.data(), d.G, ne * sizeof(long long), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
   DevScalars sc0{};
+  sc0.res_p1 = sc0.res_p2 = HUGE_VAL;
   // iteration control: nothing to iterate -> straight to the output iterations
   if (o->max_iters <= 0) {
     if (o->avg_iters > 0) {
@@ -1039,6 +1040,7 @@ int setup_bands(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, I
     HIP_TRY(hipMemcpyAsync(bh.srcV, sv.data(), nc * sizeof(double), hipMemcpyHostToDevice, s));
   }
   DevScalars sc0{};
+  sc0.res_p1 = sc0.res_p2 = HUGE_VAL;
   if (o->max_iters <= 0) {
     if (ih0.d.final_iter) {
       sc0.state = 1;
@@ -1383,6 +1385,8 @@ int complete_iteration(iugkp_handle *h)
   if (ih.d.newton && sc.cg_status == -7)
     return fail(IUGKP_E_CG_NOT_CONVERGED, "CG did not converge within cg_max_iters");
   if (sc.flags & 1) return fail(IUGKP_E_NONFINITE, "non-finite energy");
+  if (sc.grew)
+    return fail(IUGKP_E_DIVERGED, "Newton iteration diverged: the update grew beyond the first one");
   if ((sc.flags & 2) ||
       ((ih.d.newton || ih.d.Gs || K > 1 || ih.d.persist) && sc.gsum > (1ull << 62)))
     return fail(IUGKP_E_FIXED_OVERFLOW, "emission energy exceeds the fixed-point budget");
@@ -1673,6 +1677,7 @@ int iugkp_set_state(iugkp_handle *h, uint32_t iter, double d0, const double *E, 
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->hsc->iter = iter;
   h->hsc->d0 = d0;
+  h->hsc->res_p1 = h->hsc->res_p2 = HUGE_VAL;
   HIP_TRY(hipMemcpyAsync(d.sc, h->hsc, sizeof(DevScalars), hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->iter = iter;

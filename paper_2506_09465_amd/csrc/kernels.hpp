@@ -39,6 +39,8 @@ struct DevScalars {
   unsigned long long tot_flights, tot_segments, tot_crossings;
   unsigned long long gsum;      // saturating sum of |G| (Newton emission budget)
   double dn, d0, res;
+  double res_p1, res_p2;        // residuals of the two preceding iterations (+inf: none)
+  int grew;                     // the Newton iteration's growth rule fired this iteration
   int flags;                    // bit 0: non-finite energy, bit 1: fixed-point overflow
   int cg_iters, cg_status, cg_iters_total;
   unsigned int iter;            // iterations done
@@ -1529,6 +1531,15 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
   const double d0 = sc->d0;
   const double res = (d0 > 0.0) ? dn / d0 : 0.0;
   sc->res = res;
+  // Growth rule of the Newton iteration: the update has grown beyond the
+  // first one (res > 1) and either the next emission left the fixed-point
+  // range or the residual rose in two consecutive iterations.
+  const bool over = (sc->flags & 2) ||
+                    ((in.newton || in.Gs || in.n_bands > 1 || in.persist) && g > (1ull << 62));
+  sc->grew = (in.newton && res > 1.0 && (over || (res > sc->res_p1 && sc->res_p1 > sc->res_p2)))
+                 ? 1 : 0;
+  sc->res_p2 = sc->res_p1;
+  sc->res_p1 = res;
   sc->iter += 1;
   sc->tot_flights += sc->flights;
   sc->tot_segments += sc->segments;
@@ -1541,9 +1552,8 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
   else if (in.newton && sc->cg_status == -6) err = kErrBreakdown;
   else if (in.newton && sc->cg_status == -7) err = kErrCgNotConverged;
   else if (sc->flags & 1) err = kErrNonfinite;
-  else if ((sc->flags & 2) ||
-           ((in.newton || in.Gs || in.n_bands > 1 || in.persist) && g > (1ull << 62)))
-    err = kErrOverflow;
+  else if (sc->grew) err = kErrDiverged;
+  else if (over) err = kErrOverflow;
   else if (sc->iter > 1 && res > 1e3) err = kErrDiverged;
   sc->acc_mode = 0;
   if (err) {

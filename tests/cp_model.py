@@ -226,3 +226,97 @@ def bands_fixed_point_1d(w, source=None):
         Dk = Gk @ Kk + Gw @ Pw
         E += Dk / (ts[k] / tau[k])
     return E / V, R
+
+
+# ------------------------------------------------------------------ 2D flat cells
+# A particle emitted uniformly in a square cell with a 3D-isotropic direction
+# and an exponential path of mean lambda (cell units) moves in the plane by a
+# radially symmetric displacement whose radial density is the Bickley form
+#     f(rho) = (1/lambda) int_0^{pi/2} exp(-rho / (lambda sin th)) d th
+# (the in-plane length is the 3D length times sin th).  A uniform start in the
+# cell and binning of the end point by cell make the cell-to-cell probability
+# the expectation of the 2D tent T(u - m) T(v - n) over the displacement (u, v).
+# In a convex domain a straight flight between two interior cells never leaves
+# it, so the expected one-iteration map of a uniform-tau square mesh is this
+# infinite-medium kernel restricted to the mesh (walls absorb the rest).
+
+def bickley_density(rho: np.ndarray, lam: float, nth: int = 400) -> np.ndarray:
+    x, w = np.polynomial.legendre.leggauss(nth)
+    th = (x + 1.0) * np.pi / 4.0
+    w = w * np.pi / 4.0
+    s = np.sin(th)
+    return (np.exp(-np.asarray(rho)[:, None] / (lam * s[None, :])) @ w) / lam
+
+
+def transfer_2d_real(lam: float, R: int, panels: int = 300, gauss: int = 10,
+                     nphi: int = 8192) -> np.ndarray:
+    """P[m, n], 0 <= m, n <= R: probability of a displacement by (m, n) cells,
+    by quadrature of the radial density (Gauss panels in rho, midpoint in the
+    angle) and bilinear (tent) binning."""
+    rmax = min(40.0 * lam + 2.0, np.hypot(R, R) + 2.0)
+    edges = np.linspace(0.0, rmax, panels + 1)
+    x, w = np.polynomial.legendre.leggauss(gauss)
+    half = (edges[1:] - edges[:-1])[:, None] / 2.0
+    rho = ((edges[1:] + edges[:-1])[:, None] / 2.0 + half * x[None, :]).ravel()
+    wr = (half * w[None, :]).ravel()
+    fr = bickley_density(rho, lam) * wr
+    phi = (np.arange(nphi) + 0.5) * 2.0 * np.pi / nphi
+    P = np.zeros((R + 3, R + 3))
+    for i0 in range(0, rho.size, 200):
+        r = rho[i0:i0 + 200, None]
+        wt = np.broadcast_to(fr[i0:i0 + 200, None] / nphi, (r.shape[0], nphi))
+        u = np.abs(r * np.cos(phi)[None, :])
+        v = np.abs(r * np.sin(phi)[None, :])
+        mu, mv = np.floor(u).astype(int), np.floor(v).astype(int)
+        fu, fv = u - mu, v - mv
+        for dm, wu in ((0, 1.0 - fu), (1, fu)):
+            for dn, wv in ((0, 1.0 - fv), (1, fv)):
+                mm, nn = mu + dm, mv + dn
+                ok = (mm <= R + 2) & (nn <= R + 2)
+                np.add.at(P, (mm[ok], nn[ok]), (wt * wu * wv)[ok])
+    # |u| and |v| fold both signs of a nonzero offset onto one entry
+    P[1:, :] /= 2.0
+    P[:, 1:] /= 2.0
+    return P[:R + 1, :R + 1]
+
+
+def transfer_2d_fourier(lam: float, R: int, nk: int = 256, aliases: int = 24) -> np.ndarray:
+    """The same P[m, n] from its discrete-time Fourier transform: the
+    characteristic function of a 3D-isotropic exponential flight at an in-plane
+    wave vector xi is arctan(lambda |xi|) / (lambda |xi|); the tent contributes
+    sinc^2 per axis; aliases xi = k + 2 pi j are summed for |j| <= aliases
+    (accurate when lambda is not small against a cell)."""
+    k = 2.0 * np.pi * (np.arange(nk) - nk // 2) / nk
+    KX, KY = np.meshgrid(k, k, indexing="ij")
+    Kh = np.zeros_like(KX)
+    for jx in range(-aliases, aliases + 1):
+        ax = KX + 2.0 * np.pi * jx
+        sx = np.sinc(ax / (2.0 * np.pi)) ** 2
+        for jy in range(-aliases, aliases + 1):
+            ay = KY + 2.0 * np.pi * jy
+            z = lam * np.hypot(ax, ay)
+            zs = np.where(z > 0.0, z, 1.0)
+            Kh += np.where(z > 0.0, np.arctan(zs) / zs, 1.0) * sx * np.sinc(ay / (2.0 * np.pi)) ** 2
+    P = np.real(np.fft.ifft2(np.fft.ifftshift(Kh)))
+    return P[:R + 1, :R + 1]
+
+
+def transfer_2d(lam: float, R: int) -> np.ndarray:
+    return transfer_2d_real(lam, R) if lam <= 1.0 else transfer_2d_fourier(lam, R)
+
+
+def dense_transfer_2d(nx: int, ny: int, lam: float) -> np.ndarray:
+    """Expected one-iteration map E -> E_half of a uniform-tau nx x ny cavity
+    (cells c = ix + nx iy; lam in cell units, square cells)."""
+    P = transfer_2d(lam, max(nx, ny) - 1)
+    ix = np.tile(np.arange(nx), ny)
+    iy = np.repeat(np.arange(ny), nx)
+    return P[np.abs(ix[:, None] - ix[None, :]), np.abs(iy[:, None] - iy[None, :])]
+
+
+def flat_cell_jump_1d(lam: float, m: int) -> float:
+    """Probability of a 1D flat-cell jump by m >= 0 cells (lam in cell units)."""
+    a = 1.0 / lam
+    if m == 0:
+        return float(1.0 - lam * (0.5 - E3(a)))
+    return float((lam / 2.0) * (E3((m - 1) * a) - 2.0 * E3(m * a) + E3((m + 1) * a)))

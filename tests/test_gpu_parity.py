@@ -330,3 +330,39 @@ def test_batch_solver_wrapper(gpu):
         assert torch.equal(T, T1) and torch.equal(qx, qx1) and torch.equal(qy, qy1)
         assert st["iters"] == st1["iters"]
     assert rc == (min(statuses) if min(statuses) < 0 else max(statuses))
+
+
+def test_divergence_rule_matches_oracle(gpu, oracle_mod):
+    """Under-resolved sampled maps (few particles leave a cell per iteration):
+    the single solve, the batch and the oracle stop at the same iteration with
+    DIVERGED and the same residual history; a resolved instance in the same
+    batch converges as its single solve does."""
+    import cp_model as cp
+    ws = [slab_1d(n=100, kn=0.0003, particles=10 * 102, newton=True),
+          cavity_2d(n=41, kn=0.00995, particles=10 * (41 * 41 + 164), newton=True, seed=13),
+          slab_1d(n=100, kn=0.01, particles=100 * 102, newton=True)]
+    kws = []
+    for w in ws:
+        lam = float(w.vg * w.tau[0])
+        D = np.full(w.n_cells, cp.d_eff(lam, w.dx))
+        kws.append(dict(rng_mode=1, newton=True, diff_x=D, diff_y=D if w.dim == 2 else None,
+                        max_iters=60, res_tol=1e-6, tally_faces=2))
+    expect = []
+    for w, k in zip(ws, kws):
+        o = oracle_mod.Oracle(w, **k)
+        rc_o, To, _, _ = o.solve()
+        it = o.info().iter
+        expect.append((rc_o, it, o.residuals(it)))
+        s = gpu.Solver(w, **k)
+        try:
+            rc_s = s.solve()[0]
+        except gpu.IugkpError as e:
+            rc_s = e.code
+        assert rc_s == rc_o and s.stats()["iters"] == it
+        assert np.array_equal(s.residuals(), o.residuals(it))
+    assert [e[0] for e in expect] == [oracle_mod.E_DIVERGED, oracle_mod.E_DIVERGED, 0]
+    bs = gpu.BatchSolver(ws, per_instance=kws)
+    rc, outs = bs.solve()
+    assert rc == oracle_mod.E_DIVERGED
+    for (rc_o, it, _), (_, _, _, st) in zip(expect, outs):
+        assert st["status"] == rc_o and st["iters"] == it

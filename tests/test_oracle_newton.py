@@ -146,3 +146,106 @@ def test_newton_2d_runs_and_conserves(oracle_mod):
     n = w.nx
     top_in = -qy.reshape(n + 1, n)[n].sum()
     assert top_in > 0
+
+
+# ------------------------------------------------------------------ 2D reading
+def test_2d_transfer_kernel_constructions():
+    """The 2D flat-cell kernel (quadrature of the Bickley radial density, and its
+    Fourier form) against what fixes it independently: its x marginal is the
+    exact 1D flat-cell kernel (E_3 form), it sums to one, and the two
+    constructions agree where both are accurate."""
+    for lam in (0.03, 0.3, 1.0, 3.0, 10.0):
+        R = 40 if lam <= 1.0 else 127
+        P = cp.transfer_2d(lam, R)
+        full_rows = P[:, 0] + 2.0 * P[:, 1:].sum(axis=1)      # sum over n of P(m, n)
+        tol = 2e-5 if lam <= 1.0 else 1e-4      # Fourier form: truncated alias sum
+        for m in range(4):
+            assert full_rows[m] == pytest.approx(cp.flat_cell_jump_1d(lam, m), rel=tol, abs=1e-9)
+        total = full_rows[0] + 2.0 * full_rows[1:].sum()
+        assert total == pytest.approx(1.0, abs=2e-5 if lam <= 3.0 else 2e-3)
+    a = cp.transfer_2d_real(1.0, 6)
+    b = cp.transfer_2d_fourier(1.0, 6)
+    assert np.abs(a - b).max() < 1e-4      # the Fourier form's alias tail
+
+
+def _oracle_dense_operator(oracle_mod, w, D):
+    gx, gy, dg = oracle_mod.newton_operator(w, D, D)
+    nx, ny = w.nx, w.ny
+    A = np.diag(dg.copy())
+    for iy in range(ny):
+        for k in range(1, nx):
+            g = gx[iy * (nx + 1) + k]
+            a, b = iy * nx + k - 1, iy * nx + k
+            A[a, b] -= g
+            A[b, a] -= g
+    for k in range(1, ny):
+        for ix in range(nx):
+            g = gy[k * nx + ix]
+            a, b = (k - 1) * nx + ix, k * nx + ix
+            A[a, b] -= g
+            A[b, a] -= g
+    return A
+
+
+@pytest.mark.parametrize("lam_cells", [0.03, 0.3, 1.0, 10.0])
+def test_dsa_2d_expected_contraction(oracle_mod, lam_cells):
+    """Reading R6 in 2D: on a 32 x 32 cavity the accelerated map
+    E -> E_half + A^-1 (E_half - E) of the exact expected flat-cell kernel, with
+    the operator the oracle assembles, contracts by less than 1/2 per iteration
+    (the survey's 1D bound carried to 2D with walls)."""
+    M = 32
+    w = cavity_2d(n=M, kn=lam_cells / M, particles=1000)
+    D = np.full(M * M, cp.d_eff(lam_cells / M, w.dx))
+    A = _oracle_dense_operator(oracle_mod, w, D)
+    K = cp.dense_transfer_2d(M, M, lam_cells)
+    I = np.eye(M * M)
+    T = K + np.linalg.solve(A, K - I)
+    rho = float(np.max(np.abs(np.linalg.eigvals(T))))
+    assert rho < 0.5, rho
+
+
+# ------------------------------------------------------------------ sampled map
+@pytest.mark.parametrize("lam_dx", [0.03, 0.1, 0.3, 1.0])
+@pytest.mark.parametrize("n_per", [10, 100])
+def test_crn_newton_converges_or_reports_divergence(oracle_mod, lam_dx, n_per):
+    """Under common random numbers the Newton iteration iterates one sampled map.
+    Where few particles leave each cell that map is far from its expectation
+    and the correction can amplify the difference; the solve must then stop
+    with DIVERGED within 10 iterations (growth rule of reading R6), never run
+    into the fixed-point budget, and converge otherwise."""
+    n = 100
+    w = slab_1d(n=n, kn=lam_dx / n, particles=n_per * (n + 2), newton=True)
+    Dx, _ = _deff_arrays(w)
+    o = oracle_mod.Oracle(w, rng_mode=oracle_mod.CRN, newton=True, diff_x=Dx, res_tol=1e-6,
+                          max_iters=80, tally_faces=oracle_mod.FACES_OFF)
+    rc, _, _, _ = o.solve()
+    it = o.info().iter
+    r = o.residuals(it)
+    assert rc in (oracle_mod.OK, oracle_mod.E_DIVERGED), rc
+    if rc == oracle_mod.E_DIVERGED:
+        assert it <= 10
+        assert r[-1] > 1.0 and r[-1] > r[-2]
+    else:
+        assert r[-1] < 1e-6
+    if lam_dx == 1.0 and n_per == 100:
+        assert rc == oracle_mod.OK
+
+
+def test_growth_rule_precedes_budget(oracle_mod):
+    """A diverging Newton iteration whose next emission also leaves the
+    fixed-point range reports DIVERGED, and the plain iteration on the same
+    sampled map (a sub-stochastic map: it cannot grow) is not stopped by it."""
+    n = 100
+    w = slab_1d(n=n, kn=0.03 / n, particles=10 * (n + 2), newton=True)
+    Dx, _ = _deff_arrays(w)
+    o = oracle_mod.Oracle(w, rng_mode=oracle_mod.CRN, newton=True, diff_x=Dx, max_iters=80,
+                          tally_faces=oracle_mod.FACES_OFF)
+    rc, _, _, _ = o.solve()
+    assert rc == oracle_mod.E_DIVERGED
+    # the same iterate with the budget check alone would have overflowed
+    G = o.G()
+    assert np.abs(G.astype(np.float64)).sum() > 2.0 ** 62
+    p = oracle_mod.Oracle(w, rng_mode=oracle_mod.CRN, newton=False, max_iters=40,
+                          tally_faces=oracle_mod.FACES_OFF)
+    rc, _, _, _ = p.solve()
+    assert rc == oracle_mod.W_NOT_CONVERGED
