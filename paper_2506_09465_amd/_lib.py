@@ -1,8 +1,11 @@
 """ctypes declarations of the C ABI in include/iugkp.h (argument marshalling only)."""
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libiugkp.so")
@@ -104,6 +107,35 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+# Live solver and batch objects.  They are closed by an exit hook that runs at
+# the start of interpreter shutdown, while torch and the HIP runtime are still
+# up; a handle reached only by the garbage collector later in the shutdown is
+# left to the process exit instead of being destroyed then (its streams,
+# events and device memory would be released after the runtime, or a
+# profiler attached to it, may already have shut down).
+_live = weakref.WeakSet()
+
+
+def register(obj) -> None:
+    """Track an object with a close() method until it is closed or collected."""
+    _live.add(obj)
+
+
+def _close_all() -> None:
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_all)
+
+
+def finalizing() -> bool:
+    return sys.is_finalizing()
 
 
 class IugkpError(RuntimeError):

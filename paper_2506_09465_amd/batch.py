@@ -39,6 +39,7 @@ class BatchSolver:
                                                C.c_void_p(_stream_handle(self.device)),
                                                C.byref(h)), "iugkp_batch_create")
         self.h = h
+        L.register(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -46,6 +47,8 @@ class BatchSolver:
             self.h = None
 
     def __del__(self):
+        if L.finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -107,6 +107,7 @@ class Solver:
                                          C.c_void_p(_stream_handle(self.device)), C.byref(h)),
                     "iugkp_create")
         self.h = h
+        L.register(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -114,6 +115,8 @@ class Solver:
             self.h = None
 
     def __del__(self):
+        if L.finalizing():
+            return
         try:
             self.close()
         except Exception:
