@@ -285,3 +285,11 @@ def nongray_two_material_2d(n: int = 512, K: int = 40, ratio: float = 100.0,
                  particles_per_iter=particles, n_bands=K, band_C=C, band_vg=v)
     w.source = gaussian_source(n, n, d, d, amp, width)
     return w
+
+
+def seeded_temperature(n_cells: int, seed: int = 512, t_ref: float = 1.0,
+                       amp: float = 0.01) -> np.ndarray:
+    """Initial temperature field t_ref + amp * U(-1, 1) per cell
+    (numpy default_rng(seed)): every cell emits from the first iteration on."""
+    rng = np.random.default_rng(seed)
+    return t_ref + amp * rng.uniform(-1.0, 1.0, size=n_cells)
