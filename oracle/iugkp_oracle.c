@@ -1340,9 +1340,12 @@ static int orc_iterate(orc_state *s, int faces)
   int over = (!ok || !orc_check_budget(s->G, s->ne));
   /* Growth rule of the Newton iteration (reading R6): the update has grown
    * beyond the first one (res > 1) and either the next emission left the
-   * fixed-point range or the residual rose in two consecutive iterations. */
+   * fixed-point range or, with common random numbers (one fixed map, so a
+   * rise is the map's and not sampling noise), the residual rose in two
+   * consecutive iterations. */
   int grew = s->o.newton && s->res > 1.0 &&
-             (over || (s->res > s->res_p1 && s->res_p1 > s->res_p2));
+             (over || (s->o.rng_mode == ORC_RNG_CRN && s->res > s->res_p1 &&
+                       s->res_p1 > s->res_p2));
   s->res_p2 = s->res_p1;
   s->res_p1 = s->res;
   if (rc == ORC_OK && grew) rc = ORC_E_DIVERGED;
