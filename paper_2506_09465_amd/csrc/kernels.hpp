@@ -1533,10 +1533,13 @@ __global__ __launch_bounds__(256) void finish_kernel(const Inst *__restrict__ in
   sc->res = res;
   // Growth rule of the Newton iteration: the update has grown beyond the
   // first one (res > 1) and either the next emission left the fixed-point
-  // range or the residual rose in two consecutive iterations.
+  // range or, with common random numbers (one fixed map, so a rise is the
+  // map's and not sampling noise), the residual rose in two consecutive
+  // iterations.
   const bool over = (sc->flags & 2) ||
                     ((in.newton || in.Gs || in.n_bands > 1 || in.persist) && g > (1ull << 62));
-  sc->grew = (in.newton && res > 1.0 && (over || (res > sc->res_p1 && sc->res_p1 > sc->res_p2)))
+  sc->grew = (in.newton && res > 1.0 &&
+              (over || (in.crn && res > sc->res_p1 && sc->res_p1 > sc->res_p2)))
                  ? 1 : 0;
   sc->res_p2 = sc->res_p1;
   sc->res_p1 = res;

@@ -276,7 +276,7 @@ def _batch_cases():
     ws.append(w); kw.append(dict(rng_mode=1, tally_faces=2, newton=False, max_iters=60, res_tol=1e-6))
     w = two_material_2d(n=24, kn_right=0.05, ratio=20.0, particles=80_000, seed=9)
     ws.append(w); kw.append(dict(rng_mode=0, tally_faces=0, newton=True, max_iters=3, res_tol=0.0))
-    w = cavity_2d(n=64, kn=0.003, particles=400_000, seed=2)
+    w = cavity_2d(n=64, kn=0.003, particles=2_000_000, seed=2)   # resolved: converges in 18
     ws.append(w); kw.append(dict(rng_mode=1, tally_faces=2, newton=True, max_iters=40, res_tol=1e-6))
     w = cavity_2d(n=9, ny=31, kn=0.5, particles=30_000, newton=False, seed=77)
     ws.append(w); kw.append(dict(rng_mode=1, tally_faces=1, newton=False, max_iters=0, res_tol=1e-6, avg_iters=2))
