@@ -318,6 +318,27 @@ int iugkp_adjoint(iugkp_handle *h, const double *dLdT, double *grad_wall, double
  * lam^2 / 3 for lam >> delta and lam delta / 4 for lam << delta.  Host function. */
 double iugkp_d_eff(double lam, double delta);
 
+/* The increment equation of the Newton step (Sec. 3.3: the diffusion-type
+ * operator div(-kappa grad dT) applied to the energy increment), solved on its
+ * own: A x = b with A the conservative 3-point (1D) or 5-point (2D) operator
+ * -div(D grad) of the nx x ny mesh (cell c = ix + nx iy, sizes dx, dy),
+ * harmonic-mean face conductances 2 D_a D_b / (D_a + D_b) / delta^2 and Robin
+ * walls D / (delta (delta / 2 + 2 lambda / 3)) with lambda = vg tau, in the
+ * per-iteration units of iugkp_solve.  Plain FP64 CG from x = 0 (single
+ * reduction form of Chronopoulos and Gear, dot products in the fixed order of
+ * blocks of 256), stopped when (r, r) <= tol^2 (b, b) or after max_iters
+ * iterations: the same iterates, bit for bit, as the CG inside iugkp_step.
+ * tau, D_x, D_y (2D only; NULL in 1D), b: [nx ny] device arrays, read only;
+ * x: [nx ny] device array, written.  *iters_out (optional, host) = CG
+ * iterations.  Work is issued on `stream` and completed before return; the
+ * library allocates its scratch (operator, CG vectors, partials) for the call
+ * and frees it before returning.  Returns IUGKP_OK, INVALID_ARG, NOMEM, DEVICE,
+ * CG_BREAKDOWN or CG_NOT_CONVERGED (x then holds the last iterate). */
+int iugkp_diffusion_solve(int dim, int nx, int ny, double dx, double dy, double vg,
+                          const double *tau, const double *D_x, const double *D_y,
+                          const double *b, double *x, double tol, int max_iters, int *iters_out,
+                          void *stream);
+
 /* Batched solves: n independent problems advanced together, one launch per phase
  * for all of them (the particle step over the emitter tiles of every instance,
  * one workgroup per instance for the Newton CG), the per-iteration sequence

@@ -8,7 +8,8 @@ from ._lib import (EST_ANALOG, EST_EXPECTED, FACES_EVERY, FACES_FINAL, FACES_OFF
                    PRECOND_NONE, RNG_CRN, RNG_FRESH, SCHEME_EMITTERS, SCHEME_PERSISTENT,
                    IugkpError, lib as library)
 
-__all__ = ["Solver", "BatchSolver", "steady_temperature", "d_eff", "dev_philox", "dev_math",
+__all__ = ["Solver", "BatchSolver", "steady_temperature", "d_eff", "diffusion_solve",
+           "dev_philox", "dev_math",
            "dev_segments", "dev_atomics", "step_group", "solve",
            "FACES_EVERY",
            "FACES_FINAL", "FACES_OFF", "RNG_CRN", "RNG_FRESH", "SCHEME_EMITTERS", "EST_ANALOG",
@@ -18,7 +19,7 @@ __all__ = ["Solver", "BatchSolver", "steady_temperature", "d_eff", "dev_philox",
 
 def __getattr__(name):
     # torch is imported lazily so that the C-ABI declarations load without it
-    if name in ("Solver", "d_eff", "dev_philox", "dev_math", "dev_segments", "dev_atomics",
+    if name in ("Solver", "d_eff", "diffusion_solve", "dev_philox", "dev_math", "dev_segments", "dev_atomics",
                 "step_group", "solve"):
         from . import solver
         return getattr(solver, name)

@@ -86,6 +86,8 @@ SIGNATURES = [
     ("iugkp_last_error", C.c_char_p, []),
     ("iugkp_dev_philox", C.c_int, [P, C.c_uint32, C.c_uint32, P, C.c_int64, P]),
     ("iugkp_dev_math", C.c_int, [C.c_int, P, P, P, C.c_int64, P]),
+    ("iugkp_diffusion_solve", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                        C.c_double, P, P, P, P, P, C.c_double, C.c_int, P, P]),
     ("iugkp_dev_atomics", C.c_int, [C.c_int, C.c_int64, C.c_int64, C.c_int64, P, P]),
     ("iugkp_dev_segments", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, P,
                                      C.c_int64, P, P]),

@@ -65,6 +65,48 @@ void *cg_kernel_for(int reg)
              : reinterpret_cast<void *>(iugkp::cg_kernel<false>);
 }
 
+// Launch shape of the single-solve CG on a mesh: a group of at most
+// kCgGridMax resident workgroups (the barrier cost grows with the arrivals) of
+// cg_waves tree blocks each (0: the default); the register form when every
+// block has its own wave and the rows fit in LDS (cg_waves < 0 forces the
+// global-memory form).
+struct CgPlan {
+  int grid = 1, tb = 1, reg = 1, threads = 64;
+  size_t lds = 0;
+};
+
+int plan_cg(const iugkp::Mesh &m, int cg_waves, CgPlan &out)
+{
+  int dev = 0, n_cu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int nbt = cdiv(m.n_cells, iugkp::kTree);
+  const int hw = (m.dim == 2) ? m.nx : 1;
+  const int want = cg_waves != 0 ? std::abs(cg_waves) : kCgWavesDefault;
+  int G = std::max(1, std::min(std::min(cdiv(nbt, want), kCgGridMax), n_cu));
+  // more workgroups rather than the global form, while one per CU suffices
+  if (cdiv(nbt, G) > iugkp::kCgWavesMax && cdiv(nbt, iugkp::kCgWavesMax) <= n_cu)
+    G = cdiv(nbt, iugkp::kCgWavesMax);
+  const int TB = cdiv(nbt, G);
+  G = cdiv(nbt, TB);
+  size_t lds = (static_cast<size_t>(TB) * iugkp::kTree + 2 * static_cast<size_t>(hw)) *
+               sizeof(double);
+  int reg = (cg_waves >= 0 && TB <= iugkp::kCgWavesMax && lds <= kCgLdsMax) ? 1 : 0;
+  if (!reg) lds = 2 * static_cast<size_t>(hw) * sizeof(double);
+  if (lds > kCgLdsMax) return fail(IUGKP_E_INVALID_ARG, "mesh rows too long for the Newton CG");
+  const int threads = 64 * (reg ? TB : std::min(TB, iugkp::kCgWavesMax));
+  int per_cu = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cg_kernel_for(reg), threads, lds));
+  if (per_cu < 1 || G > per_cu * n_cu)
+    return fail(IUGKP_E_DEVICE, "CG workgroups cannot all be resident");
+  out.grid = G;
+  out.tb = TB;
+  out.reg = reg;
+  out.threads = threads;
+  out.lds = lds;
+  return IUGKP_OK;
+}
+
 }  // namespace
 
 using iugkp::DevScalars;
@@ -659,36 +701,13 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
                                                                  ih.gx, ih.gy, ih.diag);
     iugkp::newton_diag_kernel<<<cdiv(nc, 256), 256, 0, s>>>(m, ih.gx, ih.gy, ih.diag);
     if (multi_cg) {
-      // a group of at most kCgGridMax resident workgroups (the barrier cost
-      // grows with the arrivals) of cg_waves tree blocks each; the register
-      // form when every block has its own wave and the rows fit in LDS
-      int dev = 0, n_cu = 0;
-      HIP_TRY(hipGetDevice(&dev));
-      HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-      const int nbt = cdiv(nc, iugkp::kTree);
-      const int hw = (p->dim == 2) ? p->nx : 1;
-      const int want = o->cg_waves != 0 ? std::abs(o->cg_waves) : kCgWavesDefault;
-      int G = std::max(1, std::min(std::min(cdiv(nbt, want), kCgGridMax), n_cu));
-      // more workgroups rather than the global form, while one per CU suffices
-      if (cdiv(nbt, G) > iugkp::kCgWavesMax && cdiv(nbt, iugkp::kCgWavesMax) <= n_cu)
-        G = cdiv(nbt, iugkp::kCgWavesMax);
-      const int TB = cdiv(nbt, G);
-      G = cdiv(nbt, TB);
-      size_t lds = (static_cast<size_t>(TB) * iugkp::kTree + 2 * static_cast<size_t>(hw)) *
-                   sizeof(double);
-      int reg = (o->cg_waves >= 0 && TB <= iugkp::kCgWavesMax && lds <= kCgLdsMax) ? 1 : 0;
-      if (!reg) lds = 2 * static_cast<size_t>(hw) * sizeof(double);
-      if (lds > kCgLdsMax) return fail(IUGKP_E_INVALID_ARG, "mesh rows too long for the Newton CG");
-      const int threads = 64 * (reg ? TB : std::min(TB, iugkp::kCgWavesMax));
-      int per_cu = 0;
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cg_kernel_for(reg), threads, lds));
-      if (per_cu < 1 || G > per_cu * n_cu)
-        return fail(IUGKP_E_DEVICE, "CG workgroups cannot all be resident");
-      ih.cg_grid = G;
-      ih.cg_tb = TB;
-      ih.cg_reg = reg;
-      ih.cg_threads = threads;
-      ih.cg_lds = lds;
+      CgPlan cp;
+      if ((rc = plan_cg(m, o->cg_waves, cp))) return rc;
+      ih.cg_grid = cp.grid;
+      ih.cg_tb = cp.tb;
+      ih.cg_reg = cp.reg;
+      ih.cg_threads = cp.threads;
+      ih.cg_lds = cp.lds;
       if (o->cg_precond == IUGKP_PRECOND_MG && (rc = setup_mg(ih, o, s))) return rc;
     } else if (o->cg_precond == IUGKP_PRECOND_MG) {
       return fail(IUGKP_E_INVALID_ARG, "the multigrid preconditioner is for single solves");
@@ -1837,6 +1856,141 @@ int iugkp_adjoint(iugkp_handle *h, const double *dLdT, double *grad_wall, double
 }
 
 double iugkp_d_eff(double lam, double delta) { return iugkp::d_eff(lam, delta); }
+
+}  // extern "C"
+
+namespace {
+
+// Device buffers of one stateless diffusion solve, carved from one region.
+struct DiffusionBufs {
+  double *gx, *gy, *diag, *gr, *gw, *gp, *gs, *pub, *part;
+  unsigned int *barrier;
+  DevScalars *sc;
+};
+
+// Bytes of DiffusionBufs for a mesh (every piece 256-byte aligned).
+size_t diffusion_bytes(const Mesh &m)
+{
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t nc = m.n_cells, nbt = cdiv(m.n_cells, iugkp::kTree);
+  return up(8 * static_cast<size_t>(m.n_fx)) + up(8 * std::max<size_t>(m.n_fy, 1)) +
+         5 * up(8 * nc) + up(8 * 6 * nc) + up(8 * 4 * nbt) + up(8) + up(sizeof(DevScalars));
+}
+
+DiffusionBufs carve_diffusion(const Mesh &m, unsigned char *base)
+{
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t nc = m.n_cells, nbt = cdiv(m.n_cells, iugkp::kTree);
+  DiffusionBufs b;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char *q = base + o;
+    o += up(bytes);
+    return q;
+  };
+  b.gx = reinterpret_cast<double *>(take(8 * static_cast<size_t>(m.n_fx)));
+  b.gy = reinterpret_cast<double *>(take(8 * std::max<size_t>(m.n_fy, 1)));
+  b.diag = reinterpret_cast<double *>(take(8 * nc));
+  b.gr = reinterpret_cast<double *>(take(8 * nc));
+  b.gw = reinterpret_cast<double *>(take(8 * nc));
+  b.gp = reinterpret_cast<double *>(take(8 * nc));
+  b.gs = reinterpret_cast<double *>(take(8 * nc));
+  b.pub = reinterpret_cast<double *>(take(8 * 6 * nc));
+  b.part = reinterpret_cast<double *>(take(8 * 4 * nbt));
+  b.barrier = reinterpret_cast<unsigned int *>(take(8));
+  b.sc = reinterpret_cast<DevScalars *>(take(sizeof(DevScalars)));
+  return b;
+}
+
+int diffusion_mesh(int dim, int nx, int ny, double dx, double dy, double vg, const double *tau,
+                   const double *D_x, const double *D_y, const double *b, double *x, double tol,
+                   int max_iters, Mesh &m)
+{
+  if ((dim != 1 && dim != 2) || nx < 1 || ny < 1 || (dim == 1 && ny != 1) || !(dx > 0.0) ||
+      !(dy > 0.0) || !(vg > 0.0) || !tau || !D_x || (dim == 2 && !D_y) || !b || !x ||
+      !(tol > 0.0) || max_iters < 1 || static_cast<long long>(nx) * ny > (1ll << 28))
+    return fail(IUGKP_E_INVALID_ARG, "bad arguments");
+  m = Mesh{};
+  m.dim = dim;
+  m.nx = nx;
+  m.ny = ny;
+  m.n_cells = nx * ny;
+  m.n_b = 2 * ny + (dim == 2 ? 2 * nx : 0);
+  m.n_emit = m.n_cells + m.n_b;
+  m.n_fx = ny * (nx + 1);
+  m.n_fy = (dim == 2) ? (ny + 1) * nx : 0;
+  m.dx = dx;
+  m.dy = dy;
+  return IUGKP_OK;
+}
+
+// Assemble the Newton operator into the buffers and run the plain CG from
+// x = 0; status and iteration count read back before returning.
+int diffusion_run(const Mesh &m, const CgPlan &cp, const DiffusionBufs &q, double vg,
+                  const double *tau, const double *D_x, const double *D_y, const double *b,
+                  double *x, double tol, int max_iters, int *iters_out, hipStream_t s)
+{
+  const int nf = std::max(m.n_fx, m.n_fy);
+  const int sc_words = static_cast<int>(sizeof(DevScalars) / 4);
+  iugkp::zero_u32_kernel<<<cdiv(sc_words, 64), 64, 0, s>>>(reinterpret_cast<unsigned int *>(q.sc),
+                                                           sc_words);
+  iugkp::newton_operator_kernel<<<cdiv(nf, 256), 256, 0, s>>>(m, vg, tau, D_x,
+                                                               m.dim == 2 ? D_y : D_x, q.gx,
+                                                               q.gy, q.diag);
+  iugkp::newton_diag_kernel<<<cdiv(m.n_cells, 256), 256, 0, s>>>(m, q.gx, q.gy, q.diag);
+  iugkp::CGArgs ca;
+  ca.m = m;
+  ca.gx = q.gx;
+  ca.gy = q.gy;
+  ca.diag = q.diag;
+  ca.b = b;
+  ca.x = x;
+  ca.gr = q.gr;
+  ca.gw = q.gw;
+  ca.gp = q.gp;
+  ca.gs = q.gs;
+  ca.pub = q.pub;
+  ca.part = q.part;
+  ca.TB = cp.tb;
+  ca.tol2 = tol * tol;
+  ca.max_iters = max_iters;
+  ca.barrier = q.barrier;
+  ca.sc = q.sc;
+  iugkp::zero_u32_kernel<<<1, 64, 0, s>>>(q.barrier, 2);
+  void *args[] = {&ca};
+  HIP_TRY(hipLaunchKernel(cg_kernel_for(cp.reg), dim3(cp.grid), dim3(cp.threads), args, cp.lds, s));
+  HIP_TRY(hipGetLastError());
+  int head[2] = {0, 0};      // cg_iters, cg_status
+  HIP_TRY(hipMemcpyAsync(head, &q.sc->cg_iters, sizeof(head), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (iters_out) *iters_out = head[0];
+  if (head[1] == -3) return fail(IUGKP_E_DEVICE, "CG grid barrier timed out");
+  if (head[1] == -6) return fail(IUGKP_E_CG_BREAKDOWN, "CG breakdown");
+  if (head[1] == -7) return fail(IUGKP_E_CG_NOT_CONVERGED, "CG did not converge within max_iters");
+  return IUGKP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int iugkp_diffusion_solve(int dim, int nx, int ny, double dx, double dy, double vg,
+                          const double *tau, const double *D_x, const double *D_y,
+                          const double *b, double *x, double tol, int max_iters, int *iters_out,
+                          void *stream)
+{
+  Mesh m;
+  int rc = diffusion_mesh(dim, nx, ny, dx, dy, vg, tau, D_x, D_y, b, x, tol, max_iters, m);
+  if (rc) return rc;
+  CgPlan cp;
+  if ((rc = plan_cg(m, 0, cp))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevScratch tmp(s);
+  unsigned char *base = tmp.get<unsigned char>(diffusion_bytes(m));
+  if (!base) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
+  return diffusion_run(m, cp, carve_diffusion(m, base), vg, tau, D_x, D_y, b, x, tol, max_iters,
+                       iters_out, s);
+}
 
 const char *iugkp_strerror(int code)
 {

@@ -227,6 +227,29 @@ class Solver:
         return r[:max(k, 0)]
 
 
+def diffusion_solve(problem, D_x, D_y, b, tol: float = 1e-10, max_iters: int = 200_000,
+                    device="cuda"):
+    """x with A x = b for the Newton operator of `problem` (its mesh, tau and
+    vg) with the diffusion coefficients D_x, D_y per cell (D_y unused in 1D):
+    (rc, x, cg_iterations); rc is 0, or the library's error code when the CG
+    broke down or did not converge (x then holds the last iterate)."""
+    dev = torch.device(device)
+    tau = _dev_f64(problem.tau, dev)
+    dx_ = _dev_f64(D_x, dev)
+    dy_ = _dev_f64(D_y, dev) if int(problem.dim) == 2 else None
+    bb = _dev_f64(b, dev)
+    x = torch.empty_like(bb)
+    its = C.c_int(0)
+    with torch.cuda.device(dev):
+        rc = L.lib().iugkp_diffusion_solve(int(problem.dim), int(problem.nx), int(problem.ny),
+                float(problem.dx), float(problem.dy), float(problem.vg), tau.data_ptr(),
+                dx_.data_ptr(), _ptr(dy_), bb.data_ptr(), x.data_ptr(), float(tol),
+                int(max_iters), C.addressof(its), C.c_void_p(_stream_handle(dev)))
+    if rc not in (L.OK, L.E_CG_NOT_CONVERGED, L.E_CG_BREAKDOWN):
+        L.check(rc, "iugkp_diffusion_solve")
+    return rc, x, its.value
+
+
 def solve(problem, device="cuda", **opts):
     """Steady state of one problem: (T, (q_x, q_y), stats, status) with T per
     cell and the heat flux on the x and y faces (device tensors); status is 0
