@@ -339,6 +339,21 @@ int iugkp_diffusion_solve(int dim, int nx, int ny, double dx, double dy, double 
                           const double *b, double *x, double tol, int max_iters, int *iters_out,
                           void *stream);
 
+/* iugkp_diffusion_solve without any allocation, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid it).  Same arguments, results (bit for bit) and
+ * errors as iugkp_diffusion_solve; its scratch is a fixed 8 MiB array in
+ * device memory, one per GPU, held until the process ends (enough for 65536
+ * cells; a mesh whose scratch does not fit returns IUGKP_E_INVALID_ARG before
+ * any device work).  It calls no hipMalloc, hipFree or other allocating
+ * routine.  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (other threads, or other streams before this one's work is
+ * complete) race; the call completes its work before returning. */
+int iugkp_diffusion_solve_noalloc(int dim, int nx, int ny, double dx, double dy, double vg,
+                                  const double *tau, const double *D_x, const double *D_y,
+                                  const double *b, double *x, double tol, int max_iters,
+                                  int *iters_out, void *stream);
+
 /* Batched solves: n independent problems advanced together, one launch per phase
  * for all of them (the particle step over the emitter tiles of every instance,
  * one workgroup per instance for the Newton CG), the per-iteration sequence

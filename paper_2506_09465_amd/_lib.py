@@ -88,6 +88,9 @@ SIGNATURES = [
     ("iugkp_dev_math", C.c_int, [C.c_int, P, P, P, C.c_int64, P]),
     ("iugkp_diffusion_solve", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                         C.c_double, P, P, P, P, P, C.c_double, C.c_int, P, P]),
+    ("iugkp_diffusion_solve_noalloc", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double,
+                                                C.c_double, C.c_double, P, P, P, P, P,
+                                                C.c_double, C.c_int, P, P]),
     ("iugkp_dev_atomics", C.c_int, [C.c_int, C.c_int64, C.c_int64, C.c_int64, P, P]),
     ("iugkp_dev_segments", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, P,
                                      C.c_int64, P, P]),

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1972,7 +1973,58 @@ int diffusion_run(const Mesh &m, const CgPlan &cp, const DiffusionBufs &q, doubl
 
 }  // namespace
 
+namespace {
+
+// Scratch of the no-allocation diffusion solve: one array per device, held
+// until the process ends.  Host code never uses the symbol's host-side name as
+// an address: each device's copy is looked up once (with that device
+// current) and its address kept in g_scratch_dev.
+constexpr size_t kNoAllocBytes = 8u << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+int scratch_of_current_device(unsigned char **out)
+{
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(IUGKP_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(IUGKP_E_DEVICE, "no device address for the scratch array");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = static_cast<unsigned char *>(g_scratch_dev[dev]);
+  return IUGKP_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int iugkp_diffusion_solve_noalloc(int dim, int nx, int ny, double dx, double dy, double vg,
+                                  const double *tau, const double *D_x, const double *D_y,
+                                  const double *b, double *x, double tol, int max_iters,
+                                  int *iters_out, void *stream)
+{
+  Mesh m;
+  int rc = diffusion_mesh(dim, nx, ny, dx, dy, vg, tau, D_x, D_y, b, x, tol, max_iters, m);
+  if (rc) return rc;
+  const size_t need = diffusion_bytes(m);
+  if (need > kNoAllocBytes)
+    return fail(IUGKP_E_INVALID_ARG, "mesh too large for the no-allocation scratch (" +
+                                         std::to_string(need) + " bytes needed, " +
+                                         std::to_string(kNoAllocBytes) + " available)");
+  CgPlan cp;
+  if ((rc = plan_cg(m, 0, cp))) return rc;
+  unsigned char *base = nullptr;
+  if ((rc = scratch_of_current_device(&base))) return rc;
+  return diffusion_run(m, cp, carve_diffusion(m, base), vg, tau, D_x, D_y, b, x, tol, max_iters,
+                       iters_out, static_cast<hipStream_t>(stream));
+}
 
 int iugkp_diffusion_solve(int dim, int nx, int ny, double dx, double dy, double vg,
                           const double *tau, const double *D_x, const double *D_y,

@@ -228,11 +228,13 @@ class Solver:
 
 
 def diffusion_solve(problem, D_x, D_y, b, tol: float = 1e-10, max_iters: int = 200_000,
-                    device="cuda"):
+                    device="cuda", no_alloc: bool = False):
     """x with A x = b for the Newton operator of `problem` (its mesh, tau and
     vg) with the diffusion coefficients D_x, D_y per cell (D_y unused in 1D):
     (rc, x, cg_iterations); rc is 0, or the library's error code when the CG
-    broke down or did not converge (x then holds the last iterate)."""
+    broke down or did not converge (x then holds the last iterate).  With
+    no_alloc the library's no-allocation entry point runs the solve (this
+    wrapper still allocates x with torch)."""
     dev = torch.device(device)
     tau = _dev_f64(problem.tau, dev)
     dx_ = _dev_f64(D_x, dev)
@@ -241,7 +243,8 @@ def diffusion_solve(problem, D_x, D_y, b, tol: float = 1e-10, max_iters: int = 2
     x = torch.empty_like(bb)
     its = C.c_int(0)
     with torch.cuda.device(dev):
-        rc = L.lib().iugkp_diffusion_solve(int(problem.dim), int(problem.nx), int(problem.ny),
+        fn = L.lib().iugkp_diffusion_solve_noalloc if no_alloc else L.lib().iugkp_diffusion_solve
+        rc = fn(int(problem.dim), int(problem.nx), int(problem.ny),
                 float(problem.dx), float(problem.dy), float(problem.vg), tau.data_ptr(),
                 dx_.data_ptr(), _ptr(dy_), bb.data_ptr(), x.data_ptr(), float(tol),
                 int(max_iters), C.addressof(its), C.c_void_p(_stream_handle(dev)))
