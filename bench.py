@@ -30,6 +30,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -49,6 +51,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=256,
                     help="instances of the batched vs sequential comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint gradient timing")
+    ap.add_argument("--no-c0", action="store_true", help="skip the 1D slab time-to-steady")
+    ap.add_argument("--no-c2-gray", action="store_true",
+                    help="skip the 512^2 gray two-material throughput")
     ap.add_argument("--no-nongray", action="store_true", help="skip the 40-band timing")
     ap.add_argument("--no-expected", action="store_true",
                     help="skip the expected-value estimator comparison")
@@ -396,6 +401,142 @@ def bench_expected(P, dev, iters=6, warmup=10):
     return out
 
 
+def host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def _oracle_particle_sample(sample, barrier=None, queue=None):
+    """One copy of the all-core sample: one face-tallied iteration without the
+    Newton CG per Kn of the 256^2 cavity from the seeded temperature field,
+    `sample` particles, timed after every copy has set up (barrier); returns
+    or queues (flights, seconds)."""
+    from oracle import oracle as O
+    from synth import cavity_2d, seeded_temperature
+    os_ = []
+    for kn in KNS:
+        w = cavity_2d(n=N_SIDE, kn=kn, particles=sample, newton=False)
+        os_.append(O.Oracle(w, newton=False, tally_faces=O.FACES_EVERY,
+                            T_init=seeded_temperature(N_SIDE * N_SIDE)))
+    if barrier is not None:
+        barrier.wait()
+    t0 = time.perf_counter()
+    for o in os_:
+        o.step(1)
+    el = time.perf_counter() - t0
+    fl = sum(o.info().flights for o in os_)
+    if queue is not None:
+        queue.put((fl, el))
+    return fl, el
+
+
+def cpu_baseline_all_cores(sample, procs):
+    """The unmodified single-thread oracle run as `procs` concurrent copies of
+    the same particle-step sample, started together after their set-up: the
+    host's aggregate oracle throughput (all copies' flights over the longest
+    copy's time)."""
+    import multiprocessing as mp
+    from oracle import oracle as O
+    O.build()
+    one = _oracle_particle_sample(sample)              # alone, for the per-core rate
+    ctx = mp.get_context("spawn")                      # no fork of a process holding the GPU
+    barrier = ctx.Barrier(procs)
+    queue = ctx.Queue()
+    ps = [ctx.Process(target=_oracle_particle_sample, args=(sample, barrier, queue))
+          for _ in range(procs)]
+    for p in ps:
+        p.start()
+    res = [queue.get(timeout=600) for _ in ps]
+    for p in ps:
+        p.join(timeout=60)
+    fl = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
+    return {"value": fl / wall, "unit": "flights/s", "cores": procs, "kind": "oracle",
+            "single_core_flights_per_s": one[0] / one[1],
+            "sample": f"{procs} concurrent copies of the single-thread oracle, each one "
+                      f"face-tallied iteration per Kn of the 256x256 cavity without the Newton "
+                      f"CG, {sample} particles, from a seeded temperature field, timed together "
+                      f"after set-up; value = all copies' flights / the longest copy's time"}
+
+
+def bench_c0_time_to_steady(P, dev):
+    """The 1D slab of 100 cells at Kn = 1 (walls 1.01 / 0.99), 1e5 particles per
+    iteration, common random numbers (seed 0), no Newton step, to residual
+    1e-6: the GPU solve and the CPU oracle's solve of the same problem (the
+    same iterations, bit for bit)."""
+    import torch
+    from synth import slab_1d
+    w = slab_1d(n=100, kn=1.0, particles=100_000, seed=0)
+    kw = dict(rng_mode=P.RNG_CRN, tally_faces=P.FACES_FINAL, max_iters=500, res_tol=1e-6)
+    P.Solver(w, device=dev, **kw).solve()          # first launches, outside the timing
+    s = P.Solver(w, device=dev, **kw)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    rc, T, qx, qy, st = s.solve()
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - a
+    s.close()
+    out = {"workload": "1D gray slab, 100 cells, Kn = 1, walls 1.01/0.99, 1e5 particles per "
+                       "iteration, CRN seed 0, no Newton, residual 1e-6",
+           "seconds": round(gpu_s, 5), "iterations": st["iters"], "rc": rc,
+           "final_res": st["res"], "flights_total": st["tot_flights"],
+           "flights_per_s": st["tot_flights"] / gpu_s}
+    from oracle import oracle as O
+    O.build()
+    o = O.Oracle(w, rng_mode=O.CRN, tally_faces=O.FACES_FINAL, max_iters=500, res_tol=1e-6)
+    a = time.perf_counter()
+    rco, To, _, _ = o.solve()
+    cpu_s = time.perf_counter() - a
+    out["oracle"] = {"seconds": round(cpu_s, 4), "iterations": o.info().iter, "rc": rco,
+                     "cores": 1, "same_T": bool(np.array_equal(To, T.cpu().numpy()))}
+    return out
+
+
+def bench_c2_gray(P, dev, steps):
+    """The 512 x 512 gray two-material square (left half's relaxation time 100x
+    the right half's, Kn 0.01 on the right: about 99 of 100 candidate
+    collisions in the left half are null), 5e7 particles per iteration, face
+    tallies every iteration, no Newton step, from the seeded temperature field
+    (every cell emits): one warm-up iteration, then `steps` timed."""
+    import torch
+    from synth import seeded_temperature, two_material_2d
+    w = two_material_2d(n=512, kn_right=0.01, ratio=100.0, particles=50_000_000, seed=0)
+    s = P.Solver(w, device=dev, tally_faces=P.FACES_EVERY, T_init=seeded_temperature(512 * 512))
+    assert s.step(1) == 0
+    a = s.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    assert s.step(steps) == 0
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    b = s.stats()
+    s.close()
+    fl = b["tot_flights"] - a["tot_flights"]
+    sg = b["tot_segments"] - a["tot_segments"]
+    cr = b["tot_crossings"] - a["tot_crossings"]
+    ms_m = (b["ms_march"] - a["ms_march"]) / steps
+    return {"workload": "2D gray two-material 512x512 (tau_left = 100 tau_right, Kn_right "
+                        "0.01), 5e7 particles/iteration, face tallies, no Newton",
+            "flights_per_s": fl / el, "ms_per_iteration": round(el / steps * 1e3, 3),
+            "ms_march": round(ms_m, 3), "flights_per_iter": fl // steps,
+            "segments_per_flight": round(sg / max(fl, 1), 2),
+            "crossings_per_flight": round(cr / max(fl, 1), 2),
+            "segments_per_s": sg / el}
+
+
 def cpu_baseline_nongray():
     """The CPU oracle on a bounded sample of the 40-band problem: the same
     two-material 40-band workload on a 128 x 128 mesh with one particle per
@@ -616,8 +757,18 @@ def main():
         if not args.no_cpu_baseline:
             out["nongray"]["cpu_baseline"] = cpu_baseline_nongray()
 
+    if not args.no_c0:
+        out["c0_time_to_steady"] = bench_c0_time_to_steady(P, dev)
+
+    if not args.no_c2_gray:
+        out["c2_gray"] = bench_c2_gray(P, dev, 3)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        host = host_cpu()
+        out["cpu_baseline"]["host"] = host
+        procs = max(1, min(16, host["usable_cores"] or 1))
+        out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(args.cpu_sample // 4, procs)
     print(json.dumps(out), flush=True)
 
 
