@@ -72,7 +72,7 @@ void *cg_kernel_for(int reg)
 // block has its own wave and the rows fit in LDS (cg_waves < 0 forces the
 // global-memory form).
 struct CgPlan {
-  int grid = 1, tb = 1, reg = 1, threads = 64;
+  int grid = 1, tb = 1, reg = 1, threads = 64, per_cu = 1;
   size_t lds = 0;
 };
 
@@ -105,6 +105,7 @@ int plan_cg(const iugkp::Mesh &m, int cg_waves, CgPlan &out)
   out.reg = reg;
   out.threads = threads;
   out.lds = lds;
+  out.per_cu = per_cu;
   return IUGKP_OK;
 }
 
@@ -133,6 +134,9 @@ struct InstHost {
   unsigned int *cg_barrier = nullptr;
   int cg_grid = 1, cg_tb = 1, cg_reg = 1, cg_threads = 64;
   size_t cg_lds = 0;
+  // the CG group's footprint in compute units (workgroups / resident ones per
+  // CU): grouped stepping keeps the CGs in flight within the device
+  double cg_cus = 0.0;
   // multigrid-preconditioned CG (cg_precond == IUGKP_PRECOND_MG): level table
   int mg_L = 0, mg_Lg = 0, mg_grid = 1, mg_threads = 64;
   size_t mg_lds = 0;
@@ -498,6 +502,7 @@ int setup_mg(InstHost &ih, const iugkp_options *o, hipStream_t s)
     return fail(IUGKP_E_DEVICE, "multigrid CG workgroups cannot all be resident");
   ih.mg_L = L;
   ih.mg_Lg = Lg;
+  ih.cg_cus = static_cast<double>(G) / per_cu;
   ih.mg_grid = G;
   ih.mg_threads = 64 * waves;
   ih.mg_lds = lds;
@@ -709,9 +714,11 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
       ih.cg_reg = cp.reg;
       ih.cg_threads = cp.threads;
       ih.cg_lds = cp.lds;
+      ih.cg_cus = static_cast<double>(cp.grid) / cp.per_cu;
       if (o->cg_precond == IUGKP_PRECOND_MG && (rc = setup_mg(ih, o, s))) return rc;
     } else if (o->cg_precond == IUGKP_PRECOND_MG) {
-      return fail(IUGKP_E_INVALID_ARG, "the multigrid preconditioner is for single solves");
+      // batched: the hierarchy only; one workgroup runs the instance's solve
+      if ((rc = setup_mg(ih, o, s))) return rc;
     }
   }
   // (expected-value rays: only on request, march == 2; every stripe follows a
@@ -1535,35 +1542,53 @@ int iugkp_step_group(iugkp_handle *const *hs, int n, int n_iters)
       if (hs[j] == hs[i]) return fail(IUGKP_E_INVALID_ARG, "a handle appears twice");
   }
   // each handle runs its iterations back to back; a finished iteration is
-  // completed and the handle's next one enqueued as soon as its stream is idle
+  // completed and the handle's next one enqueued as soon as its stream is idle.
+  // Every CG group waits at its barriers for all its workgroups, so the CGs
+  // that can be in flight together must fit on the device at once: an
+  // iteration is enqueued only while the CG footprints (in compute units) of
+  // the iterations in flight leave room for its own.  (Particle-step
+  // workgroups never wait for a CG, so they only delay residency.)
+  int dev = 0, n_cu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  const double room = static_cast<double>(n_cu);
   std::vector<int> left(n, n_iters);
   std::vector<char> busy(n, 0);
   int first = IUGKP_OK, n_busy = 0;
-  auto start = [&](int i) {
-    if (first || left[i] == 0) return;
+  double in_flight = 0.0;
+  auto cus = [&](int i) { return hs[i]->ih.d.newton ? hs[i]->ih.cg_cus : 0.0; };
+  auto start = [&](int i) -> bool {
+    if (first || left[i] == 0 || busy[i]) return false;
+    if (n_busy > 0 && in_flight + cus(i) > room) return false;     // wait for room
     const int rc = enqueue_iteration(hs[i], hs[i]->ih.d.faces_each);
     if (rc) {
       first = rc;
-      return;
+      return false;
     }
     busy[i] = 1;
     ++n_busy;
+    in_flight += cus(i);
+    return true;
   };
   for (int i = 0; i < n; ++i) start(i);
+  int next = 0;                        // round-robin start of the waiting handles
   while (n_busy > 0) {
+    bool freed = false;
     for (int i = 0; i < n; ++i) {
       if (!busy[i]) continue;
       const hipError_t q = hipStreamQuery(hs[i]->stream);
       if (q == hipErrorNotReady) continue;
       busy[i] = 0;
       --n_busy;
+      in_flight -= cus(i);
+      freed = true;
       const int rc = complete_iteration(hs[i]);   // also reports a failed stream
       --left[i];
-      if (rc) {
-        if (!first) first = rc;
-        continue;
-      }
-      start(i);
+      if (rc && !first) first = rc;
+    }
+    if (freed) {
+      for (int j = 0; j < n; ++j) start((next + j) % n);
+      next = (next + 1) % n;
     }
   }
   return first;
@@ -2163,12 +2188,17 @@ struct iugkp_batch {
   int max_prep = 1, max_nx = 1, max_ny = 1, max_nbc = 1, max_nbe = 1, max_out = 1;
   // batched CG: a pool of resident workgroups and, per replay, the host's
   // schedule of (instance, rank) jobs on it
-  int cg_pool = 1;
-  size_t cg_lds = 0;
+  struct Pool {
+    int size = 0;                    // resident workgroups
+    size_t lds = 0;
+    int *d_off = nullptr, *h_off = nullptr;
+    iugkp::CgJob *d_jobs = nullptr, *h_jobs = nullptr;
+    int max_jobs = 0;
+    bool used = false;
+  };
+  Pool pool, mg_pool;                // plain CG; multigrid-preconditioned CG
   std::vector<int> cg_G, cg_tb;      // per instance: group size, blocks per workgroup | form bit
-  int *d_off = nullptr, *h_off = nullptr;
-  iugkp::CgJob *d_jobs = nullptr, *h_jobs = nullptr;
-  int max_jobs = 0;
+  iugkp::MGArgs *d_mg_args = nullptr;   // the multigrid jobs' arguments, per instance
   DevScalars *d_scs = nullptr;       // every instance's scalars, contiguous
   unsigned int *d_bars = nullptr;    // every instance's CG barrier [2], kBarStride apart
   DevScalars *hsc = nullptr;
@@ -2188,12 +2218,15 @@ void free_batch(iugkp_batch *b)
   if (b->d_insts) (void)hipFree(b->d_insts);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->hsc) (void)hipHostFree(b->hsc);
-  if (b->h_off) (void)hipHostFree(b->h_off);
-  if (b->h_jobs) (void)hipHostFree(b->h_jobs);
-  if (b->d_off) (void)hipFree(b->d_off);
-  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  for (auto *q : {&b->pool, &b->mg_pool}) {
+    if (q->h_off) (void)hipHostFree(q->h_off);
+    if (q->h_jobs) (void)hipHostFree(q->h_jobs);
+    if (q->d_off) (void)hipFree(q->d_off);
+    if (q->d_jobs) (void)hipFree(q->d_jobs);
+  }
   if (b->d_scs) (void)hipFree(b->d_scs);
   if (b->d_bars) (void)hipFree(b->d_bars);
+  if (b->d_mg_args) (void)hipFree(b->d_mg_args);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->own) (void)hipStreamDestroy(b->own);
@@ -2213,8 +2246,12 @@ int enqueue_batch_iteration(iugkp_batch *b)
   iugkp::update_kernel<<<dim3(b->max_nbc, n), 256, 0, s>>>(b->d_insts, 1);
   if (b->any_newton) {
     iugkp::zero_u32_kernel<<<cdiv(kBarStride * n, 256), 256, 0, s>>>(b->d_bars, kBarStride * n);
-    iugkp::cg_batch_kernel<<<b->cg_pool, iugkp::kCgThreadsMax, b->cg_lds, s>>>(b->d_insts, b->d_off,
-                                                                               b->d_jobs);
+    if (b->pool.used)
+      iugkp::cg_batch_kernel<<<b->pool.size, iugkp::kCgThreadsMax, b->pool.lds, s>>>(
+          b->d_insts, b->pool.d_off, b->pool.d_jobs);
+    if (b->mg_pool.used)
+      iugkp::mgcg_batch_kernel<<<b->mg_pool.size, 64 * iugkp::kMgPoolWaves, b->mg_pool.lds, s>>>(
+          b->mg_pool.d_off, b->mg_pool.d_jobs, b->d_mg_args);
     iugkp::newton_finish_kernel<<<dim3(b->max_nbe, n), 256, 0, s>>>(b->d_insts, 1);
   }
   iugkp::finish_kernel<<<n, 256, 0, s>>>(b->d_insts, 1);
@@ -2228,10 +2265,11 @@ int enqueue_batch_iteration(iugkp_batch *b)
 // earliest (estimated from the previous CG iteration count of the instance, or
 // four CG iterations per mesh row before the first one), and is appended to
 // their job lists in that global order.  Returns the number of entries.
-int schedule_cg(iugkp_batch *b)
+int schedule_cg(iugkp_batch *b, bool mg_jobs)
 {
   const int n = static_cast<int>(b->insts.size());
-  const int P = b->cg_pool;
+  iugkp_batch::Pool &pool = mg_jobs ? b->mg_pool : b->pool;
+  const int P = pool.size;
   struct Job {
     double cost;
     int inst;
@@ -2240,10 +2278,15 @@ int schedule_cg(iugkp_batch *b)
   for (int i = 0; i < n; ++i) {
     const InstHost &ih = b->insts[i];
     const DevScalars &sc = b->hsc[i];
-    if (!ih.d.newton || sc.state == 2) continue;
-    const int prior = 4 * std::max(ih.d.m.nx, ih.d.m.ny);
+    if (!ih.d.newton || sc.state == 2 || (ih.mg_L > 0) != mg_jobs) continue;
+    // a multigrid iteration passes 4 Lg + 2 group barriers (Lg grid levels),
+    // a plain one one; before the first solve: 20 multigrid iterations, or
+    // four plain ones per mesh row
+    const bool mg = ih.mg_L > 0;
+    const int prior = mg ? 20 : 4 * std::max(ih.d.m.nx, ih.d.m.ny);
     const double its = sc.iter > 0 ? std::max(sc.cg_iters, 1) : std::min(prior, ih.d.cg_max);
-    jobs.push_back({its * (b->cg_G[i] > 1 ? 3.0 : 1.0), i});
+    const double per = mg ? 4.0 * ih.mg_Lg + 2.0 : 1.0;
+    jobs.push_back({its * per * (b->cg_G[i] > 1 ? 3.0 : 1.0), i});
   }
   std::stable_sort(jobs.begin(), jobs.end(), [](const Job &x, const Job &y) { return x.cost > y.cost; });
   std::vector<double> load(P, 0.0);
@@ -2275,10 +2318,10 @@ int schedule_cg(iugkp_batch *b)
   }
   int e = 0;
   for (int k = 0; k < P; ++k) {
-    b->h_off[k] = e;
-    for (const auto &x : lists[k]) b->h_jobs[e++] = x;
+    pool.h_off[k] = e;
+    for (const auto &x : lists[k]) pool.h_jobs[e++] = x;
   }
-  b->h_off[P] = e;
+  pool.h_off[P] = e;
   return e;
 }
 
@@ -2326,12 +2369,14 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
   b->cg_G.assign(n, 0);
   b->cg_tb.assign(n, 0);
   if (b->any_newton) {
-    // the pool: every workgroup resident at once (occupancy times CUs), so the
+    // the pools: every workgroup resident at once (occupancy times CUs), so the
     // instance groups' barriers always make progress.  An instance's group:
     // one wave per tree block and at most kCgWavesMax blocks per workgroup
     // (register form), or, for rows too long for the LDS staging or groups
-    // beyond one workgroup per CU, the global form on kCgGridMax workgroups.
-    int dev = 0, n_cu = 0, per_cu = 0;
+    // beyond one workgroup per CU, the global form on kCgGridMax workgroups;
+    // with the multigrid preconditioner at most kCgGridMax workgroups of one
+    // wave per 256-cell block of the finest level.
+    int dev = 0, n_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     for (int i = 0; i < n; ++i) {
@@ -2339,6 +2384,16 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
       if (!ih.d.newton) continue;
       const Mesh &m = ih.d.m;
       const int nbt = cdiv(m.n_cells, iugkp::kTree);
+      if (ih.mg_L > 0) {
+        const int G = std::max(1, std::min(std::min(cdiv(nbt, iugkp::kMgPoolWaves), kCgGridMax),
+                                           n_cu));
+        b->cg_G[i] = G;
+        b->cg_tb[i] = 0;
+        b->mg_pool.lds = std::max(b->mg_pool.lds, ih.mg_lds);
+        b->mg_pool.max_jobs += G;
+        b->mg_pool.used = true;
+        continue;
+      }
       const size_t hw = (m.dim == 2) ? m.nx : 1;
       int G = cdiv(nbt, iugkp::kCgWavesMax);
       int TB = cdiv(nbt, G);
@@ -2357,34 +2412,47 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
       }
       b->cg_G[i] = G;
       b->cg_tb[i] = TB | (reg ? iugkp::kCgJobReg : 0);
-      b->cg_lds = std::max(b->cg_lds, lds);
-      b->max_jobs += G;
+      b->pool.lds = std::max(b->pool.lds, lds);
+      b->pool.max_jobs += G;
+      b->pool.used = true;
     }
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(iugkp::cg_batch_kernel), iugkp::kCgThreadsMax,
-        b->cg_lds));
-    if (per_cu < 1) {
-      free_batch(b);
-      return fail(IUGKP_E_DEVICE, "the batched CG kernel does not fit on a CU");
+    for (auto *q : {&b->pool, &b->mg_pool}) {
+      if (!q->used) continue;
+      const void *kern = (q == &b->pool)
+                             ? reinterpret_cast<const void *>(iugkp::cg_batch_kernel)
+                             : reinterpret_cast<const void *>(iugkp::mgcg_batch_kernel);
+      const int threads = (q == &b->pool) ? iugkp::kCgThreadsMax : 64 * iugkp::kMgPoolWaves;
+      int per_cu = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, q->lds));
+      if (per_cu < 1) {
+        free_batch(b);
+        return fail(IUGKP_E_DEVICE, "the batched CG kernel does not fit on a CU");
+      }
+      q->size = per_cu * n_cu;
+      if (hipMalloc(reinterpret_cast<void **>(&q->d_off), (q->size + 1) * sizeof(int)) != hipSuccess ||
+          hipMalloc(reinterpret_cast<void **>(&q->d_jobs),
+                    std::max(q->max_jobs, 1) * sizeof(iugkp::CgJob)) != hipSuccess ||
+          hipHostMalloc(reinterpret_cast<void **>(&q->h_off), (q->size + 1) * sizeof(int)) !=
+              hipSuccess ||
+          hipHostMalloc(reinterpret_cast<void **>(&q->h_jobs),
+                        std::max(q->max_jobs, 1) * sizeof(iugkp::CgJob)) != hipSuccess) {
+        free_batch(b);
+        return fail(IUGKP_E_NOMEM, "allocation failed");
+      }
     }
-    b->cg_pool = per_cu * n_cu;
-    for (int i = 0; i < n; ++i)
-      if (b->cg_G[i] > b->cg_pool) {
+    for (int i = 0; i < n; ++i) {
+      const InstHost &ih = b->insts[i];
+      if (ih.d.newton && b->cg_G[i] > (ih.mg_L > 0 ? b->mg_pool.size : b->pool.size)) {
         free_batch(b);
         return fail(IUGKP_E_DEVICE, "a CG group exceeds the resident workgroups");
       }
+    }
   }
   if (hipMalloc(reinterpret_cast<void **>(&b->d_insts), n * sizeof(Inst)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&b->d_tiles), b->n_tiles * sizeof(TileDesc)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&b->d_scs), n * sizeof(DevScalars)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&b->d_bars), kBarStride * n * sizeof(unsigned int)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void **>(&b->d_off), (b->cg_pool + 1) * sizeof(int)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void **>(&b->d_jobs),
-                std::max(b->max_jobs, 1) * sizeof(iugkp::CgJob)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void **>(&b->hsc), n * sizeof(DevScalars)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void **>(&b->h_off), (b->cg_pool + 1) * sizeof(int)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void **>(&b->h_jobs),
-                    std::max(b->max_jobs, 1) * sizeof(iugkp::CgJob)) != hipSuccess) {
+      hipHostMalloc(reinterpret_cast<void **>(&b->hsc), n * sizeof(DevScalars)) != hipSuccess) {
     free_batch(b);
     return fail(IUGKP_E_NOMEM, "allocation failed");
   }
@@ -2398,6 +2466,41 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
     ih.d.cg_barrier = b->d_bars + kBarStride * i;
   }
   HIP_TRY(hipStreamSynchronize(b->stream));
+  {
+    // the multigrid jobs' arguments, one entry per instance (used by the
+    // multigrid instances only)
+    std::vector<iugkp::MGArgs> args(n);
+    bool any_mg = false;
+    for (int i = 0; i < n; ++i) {
+      const InstHost &ih = b->insts[i];
+      if (!ih.d.newton || ih.mg_L == 0) continue;
+      any_mg = true;
+      iugkp::MGArgs &ma = args[i];
+      ma.lv = ih.mg_lv;
+      ma.L = ih.mg_L;
+      ma.Lg = ih.mg_Lg;
+      ma.b = ih.d.rhs;
+      ma.x = ih.d.cg_x;
+      ma.p = ih.d.cg_p;
+      ma.s = ih.d.cg_s;
+      ma.w = ih.d.cg_w;
+      ma.part = ih.cg_mpart;
+      ma.tol2 = ih.d.tol2;
+      ma.max_iters = ih.d.cg_max;
+      ma.barrier = ih.d.cg_barrier;
+      ma.sc = ih.d.sc;
+    }
+    if (any_mg) {
+      if (hipMalloc(reinterpret_cast<void **>(&b->d_mg_args), n * sizeof(iugkp::MGArgs)) !=
+          hipSuccess) {
+        free_batch(b);
+        return fail(IUGKP_E_NOMEM, "allocation failed");
+      }
+      HIP_TRY(hipMemcpyAsync(b->d_mg_args, args.data(), n * sizeof(iugkp::MGArgs),
+                             hipMemcpyHostToDevice, b->stream));
+      HIP_TRY(hipStreamSynchronize(b->stream));
+    }
+  }
   if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
@@ -2455,12 +2558,13 @@ int iugkp_batch_solve(iugkp_batch *b, double *const *T_out, double *const *qx_ou
     bool all_done = true;
     for (int i = 0; i < n; ++i) all_done = all_done && (b->hsc[i].state == 2);
     if (all_done) break;
-    if (b->any_newton) {
-      const int ne = schedule_cg(b);
-      HIP_TRY(hipMemcpyAsync(b->d_off, b->h_off, (b->cg_pool + 1) * sizeof(int),
+    for (auto *q : {&b->pool, &b->mg_pool}) {
+      if (!q->used) continue;
+      const int ne = schedule_cg(b, q == &b->mg_pool);
+      HIP_TRY(hipMemcpyAsync(q->d_off, q->h_off, (q->size + 1) * sizeof(int),
                              hipMemcpyHostToDevice, s));
       if (ne > 0)
-        HIP_TRY(hipMemcpyAsync(b->d_jobs, b->h_jobs, ne * sizeof(iugkp::CgJob),
+        HIP_TRY(hipMemcpyAsync(q->d_jobs, q->h_jobs, ne * sizeof(iugkp::CgJob),
                                hipMemcpyHostToDevice, s));
     }
     HIP_TRY(hipGraphLaunch(b->exec, s));

@@ -2218,51 +2218,6 @@ __global__ __launch_bounds__(kCgThreadsMax) void cg_kernel(CGArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Batched CG over a pool of resident workgroups.  The host hands every active
-// Newton instance a group of workgroups and writes, per workgroup, the list of
-// (instance, rank) jobs it takes part in; all lists follow one global job
-// order, so the earliest unfinished job always has every member at hand and
-// the pool cannot deadlock.  The solve of an instance does not depend on how
-// many workgroups serve it or where.
-// ---------------------------------------------------------------------------
-struct CgJob {
-  int inst, rank, G, tb;     // tb: blocks per workgroup, bit 30 = register form
-};
-constexpr int kCgJobReg = 1 << 30;
-
-__global__ __launch_bounds__(kCgThreadsMax) void cg_batch_kernel(const Inst *__restrict__ insts,
-                                                                 const int *__restrict__ off,
-                                                                 const CgJob *__restrict__ jobs)
-{
-  const int e0 = off[blockIdx.x], e1 = off[blockIdx.x + 1];
-  for (int e = e0; e < e1; ++e) {
-    const CgJob jb = jobs[e];
-    const Inst &in = insts[jb.inst];
-    CGArgs a;
-    a.m = in.m;
-    a.gx = in.gx;
-    a.gy = in.gy;
-    a.diag = in.diag;
-    a.b = in.rhs;
-    a.x = in.cg_x;
-    a.gr = in.cg_r;
-    a.gw = in.cg_w;
-    a.gp = in.cg_p;
-    a.gs = in.cg_s;
-    a.pub = in.cg_pub;
-    a.part = in.cg_mpart;
-    a.TB = jb.tb & (kCgJobReg - 1);
-    a.tol2 = in.tol2;
-    a.max_iters = in.cg_max;
-    a.barrier = in.cg_barrier;
-    a.sc = in.sc;
-    if (jb.tb & kCgJobReg) cg_run<true>(a, jb.rank, jb.G);
-    else cg_run<false>(a, jb.rank, jb.G);
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Adjoint of the steady state (uniform relaxation time, common random numbers).
 // For fixed counters the paths do not depend on the weights, so one
 // iteration is linear in the emission energies, D = T_cc G_cells + T_cw G_walls

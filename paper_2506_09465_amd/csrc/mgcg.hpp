@@ -22,7 +22,7 @@
 // spread over all G workgroups: wave v of the group takes the 256-cell blocks
 // v, v + G waves, ... of the level, lane l the cells l + 64 q of a block.  A
 // phase reads what other workgroups wrote in the phase before it, behind a
-// group barrier, with coherent loads (xld / xst).  Per grid level the descent
+// group barrier, with coherent loads and stores.  Per grid level the descent
 // takes two phases (second pre-sweep; residual and restriction, which also
 // does the first sweep of the next level) and the ascent two (correction with
 // the first post-sweep; second post-sweep, which for a level whose finer
@@ -177,10 +177,24 @@ __device__ __forceinline__ double mg_apply(const MGLevel &l, int c, Get v)
   return mg_apply_row(mg_row(l, c), c, v);
 }
 
+// Loads and stores of values other workgroups (SC = agent scope) or only the
+// waves of this workgroup (SC = workgroup scope, a solve run by a single
+// workgroup) write between barriers.
+template <int SC>
+__device__ __forceinline__ double mld(const double *p)
+{
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, SC);
+}
+template <int SC>
+__device__ __forceinline__ void mst(double *p, double v)
+{
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, SC);
+}
+
 // Sums of the nb published NV-tuples (layout [nb][NV]) in the fixed order of
 // the host-side definition: the 256-element tree over each chunk, then over
 // the chunk sums (nb <= 65536).  Every thread gets every result.
-template <int NV>
+template <int NV, int SC>
 __device__ __forceinline__ void group_tree_n(const double *part, int nb, double *red,
                                              double (&out)[NV])
 {
@@ -193,7 +207,7 @@ __device__ __forceinline__ void group_tree_n(const double *part, int nb, double 
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = k * kTree + lane + 64 * q;
-        v[q] = i < nb ? xld(&part[NV * i + j]) : 0.0;
+        v[q] = i < nb ? mld<SC>(&part[NV * i + j]) : 0.0;
       }
       r[j] = wave_tree256(v[0], v[1], v[2], v[3]);
     }
@@ -226,13 +240,15 @@ __device__ __forceinline__ void group_tree_n(const double *part, int nb, double 
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
+// The preconditioned CG of one system, run by the G workgroups of a group of
+// which this one is number bid (G = 1: one workgroup alone, its exchanges
+// through workgroup-scope memory operations and workgroup barriers).
+template <int SC>
+__device__ __forceinline__ void mgcg_solve(const MGArgs &a, int G, int bid, double *lds,
+                                           double *red)
 {
-  extern __shared__ double lds[];
-  __shared__ double red[3 * kTree];
-  const int G = gridDim.x;
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int gwv = blockIdx.x * nw + wave, gstride = G * nw;
+  const int gwv = bid * nw + wave, gstride = G * nw;
   const int L = a.L, Lg = a.Lg;
   const MGLevel *lv = a.lv;
   const MGLevel L0 = lv[0];
@@ -278,7 +294,7 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
   // over every thread of the group (consecutive threads, consecutive cells),
   // two at a time when the level has more cells than the group has threads.
   const int nthr = G * static_cast<int>(blockDim.x);
-  const int tid = blockIdx.x * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
+  const int tid = bid * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
   auto for_flat = [&](auto Qmax, int nl, auto compute, auto store) {
     auto run = [&](auto Qc) {
       constexpr int Q = decltype(Qc)::value;
@@ -351,12 +367,12 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
       for_flat(
           Q2{}, F.n,
           [&](int c) {
-            auto xa = [&](int j) { return xld(&F.xa[j]); };
+            auto xa = [&](int j) { return mld<SC>(&F.xa[j]); };
             const MGRow r = mg_row(F, c);
-            const double t = xld(&F.b[c]) - mg_apply_row(r, c, xa);
+            const double t = mld<SC>(&F.b[c]) - mg_apply_row(r, c, xa);
             return xa(c) + (kMgOmega * t) / r.dg;
           },
-          [&](int c, double v) { xst(&F.xb[c], v); });
+          [&](int c, double v) { mst<SC>(&F.xb[c], v); });
       if (!bar()) return false;
       const MGLevel Cl = lv[k + 1];
       const bool grid_next = (k + 1 < Lg);
@@ -376,12 +392,12 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
               const int cx = in[k] ? ix : 2 * I, cy = in[k] ? iy : 2 * J;
               const int f = cy * F.nx + cx;
               rw[k] = mg_row_at(F, cx, cy);
-              bv[k] = xld(&F.b[f]);
-              xv[k][0] = xld(&F.xb[f]);
-              xv[k][1] = xld(&F.xb[rw[k].jl]);
-              xv[k][2] = xld(&F.xb[rw[k].jr]);
-              xv[k][3] = xld(&F.xb[rw[k].jd]);
-              xv[k][4] = xld(&F.xb[rw[k].ju]);
+              bv[k] = mld<SC>(&F.b[f]);
+              xv[k][0] = mld<SC>(&F.xb[f]);
+              xv[k][1] = mld<SC>(&F.xb[rw[k].jl]);
+              xv[k][2] = mld<SC>(&F.xb[rw[k].jr]);
+              xv[k][3] = mld<SC>(&F.xb[rw[k].jd]);
+              xv[k][4] = mld<SC>(&F.xb[rw[k].ju]);
             }
             double q[4];
 #pragma unroll
@@ -393,8 +409,8 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
             return V2{B, sweep_first(B, Cl.diag[C])};
           },
           [&](int C, V2 v) {
-            xst(&Cl.b[C], v.a);
-            if (grid_next) xst(&Cl.xa[C], v.b);
+            mst<SC>(&Cl.b[C], v.a);
+            if (grid_next) mst<SC>(&Cl.xa[C], v.b);
           });
       if (!bar()) return false;
     }
@@ -409,7 +425,7 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
       for_local(
           T.n,
           [&](int i) {
-            const double bv = xld(&T.b[i]);
+            const double bv = mld<SC>(&T.b[i]);
             return V2{bv, sweep_first(bv, lds[T.lc + 5 * i])};
           },
           [&](int i, V2 v) {
@@ -510,13 +526,13 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
       // second post-sweep of a grid level evaluated here
       auto e_grid = [&](int P) {
         const MGRow rc = mg_row(Cl, P);
-        const double b = xld(&Cl.b[P]);
+        const double b = mld<SC>(&Cl.b[P]);
         double v5[5];
-        v5[0] = xld(&Cl.xd[P]);
-        v5[1] = xld(&Cl.xd[rc.jl]);
-        v5[2] = xld(&Cl.xd[rc.jr]);
-        v5[3] = xld(&Cl.xd[rc.jd]);
-        v5[4] = xld(&Cl.xd[rc.ju]);
+        v5[0] = mld<SC>(&Cl.xd[P]);
+        v5[1] = mld<SC>(&Cl.xd[rc.jl]);
+        v5[2] = mld<SC>(&Cl.xd[rc.jr]);
+        v5[3] = mld<SC>(&Cl.xd[rc.jd]);
+        v5[4] = mld<SC>(&Cl.xd[rc.ju]);
         const double t = b - mg_apply_vals(rc, v5);
         return v5[0] + (kMgOmega * t) / rc.dg;
       };
@@ -535,13 +551,13 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
               mg_parents(r, Cl.nx, pc);
               double xb5[5], e5[5];
 #pragma unroll
-              for (int q = 0; q < 5; ++q) xb5[q] = xld(&F.xb[js[q]]);
+              for (int q = 0; q < 5; ++q) xb5[q] = mld<SC>(&F.xb[js[q]]);
               if constexpr (decltype(FromLds)::value == 1) {
 #pragma unroll
                 for (int q = 0; q < 5; ++q) e5[q] = lds[Cl.lt + pc[q]];
               } else if constexpr (decltype(FromLds)::value == 0) {
 #pragma unroll
-                for (int q = 0; q < 5; ++q) e5[q] = xld(&Cl.e[pc[q]]);
+                for (int q = 0; q < 5; ++q) e5[q] = mld<SC>(&Cl.e[pc[q]]);
               } else {
                 // distinct aggregates: the cell's own, the one across an x
                 // face (left or right) and the one across a y face
@@ -554,14 +570,14 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
                 e5[3] = (pc[3] == pc[0]) ? e0 : ey;
                 e5[4] = (pc[4] == pc[0]) ? e0 : ey;
               }
-              const double bc = xld(&F.b[c]);
+              const double bc = mld<SC>(&F.b[c]);
               double xc5[5];
 #pragma unroll
               for (int q = 0; q < 5; ++q) xc5[q] = xb5[q] + kMgScale * e5[q];
               const double t = bc - mg_apply_vals(r, xc5);
               return xc5[0] + (kMgOmega * t) / r.dg;
             },
-            [&](int c, double v) { xst(&F.xd[c], v); });
+            [&](int c, double v) { mst<SC>(&F.xd[c], v); });
       };
       // e of the coarse level: 1 from LDS, 0 stored by its last sweep, 2 recomputed
       if (k + 1 == Lg) post1(std::integral_constant<int, 1>{});
@@ -572,17 +588,17 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
       for_flat(
           Q2{}, F.n,
           [&](int c) {
-            auto xd = [&](int j) { return xld(&F.xd[j]); };
+            auto xd = [&](int j) { return mld<SC>(&F.xd[j]); };
             const MGRow r = mg_row(F, c);
-            const double t = xld(&F.b[c]) - mg_apply_row(r, c, xd);
+            const double t = mld<SC>(&F.b[c]) - mg_apply_row(r, c, xd);
             return xd(c) + (kMgOmega * t) / r.dg;
           },
-          [&](int c, double v) { xst(&F.e[c], v); });
+          [&](int c, double v) { mst<SC>(&F.e[c], v); });
       if (!bar()) return false;
     }
     return true;
   };
-  auto uget = [&](int j) { return Lg == 0 ? lds[L0.lt + j] : xld(&L0.e[j]); };
+  auto uget = [&](int j) { return Lg == 0 ? lds[L0.lt + j] : mld<SC>(&L0.e[j]); };
   // w = A u on the own cells and the block sums of (r, u), (w, u), (r, r)
   auto matvec = [&]() -> bool {
     for (int blk = gwv; blk < nb; blk += gstride) {
@@ -593,7 +609,7 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
         const int c = c0 < n ? c0 : blk * kTree;
         const double uc = uget(c);
         const double wv = mg_apply(L0, c, uget);
-        const double rv = xld(&L0.b[c]);
+        const double rv = mld<SC>(&L0.b[c]);
         const bool in = c0 < n;
         wq[q] = wv;
         g[q] = in ? rv * uc : 0.0;
@@ -609,9 +625,9 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
       const double sd = wave_tree256(d[0], d[1], d[2], d[3]);
       const double sr = wave_tree256(rr[0], rr[1], rr[2], rr[3]);
       if (lane == 0) {
-        xst(&a.part[3 * blk], sg);
-        xst(&a.part[3 * blk + 1], sd);
-        xst(&a.part[3 * blk + 2], sr);
+        mst<SC>(&a.part[3 * blk], sg);
+        mst<SC>(&a.part[3 * blk + 1], sd);
+        mst<SC>(&a.part[3 * blk + 2], sr);
       }
     }
     return bar();
@@ -624,14 +640,14 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
       Q4{}, n, [&](int c) { return V2{a.b[c], sweep_first(a.b[c], L0.diag[c])}; },
       [&](int c, V2 v) {
         a.x[c] = 0.0;
-        xst(&L0.b[c], v.a);
-        if (Lg > 0) xst(&L0.xa[c], v.b);
+        mst<SC>(&L0.b[c], v.a);
+        if (Lg > 0) mst<SC>(&L0.xa[c], v.b);
       });
   if (!bar() || !vcycle() || !matvec()) {
     status = -3;
   } else {
     double s3[3];
-    group_tree_n<3>(a.part, nb, red, s3);
+    group_tree_n<3, SC>(a.part, nb, red, s3);
     gamma = s3[0];
     delta = s3[1];
     thr = a.tol2 * s3[2];
@@ -652,15 +668,15 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
           const double pv = first ? uc : uc + beta * a.p[c];
           const double sv = first ? wv : wv + beta * a.s[c];
           const double xv = a.x[c] + alpha * pv;
-          const double rv = xld(&L0.b[c]) - alpha * sv;
+          const double rv = mld<SC>(&L0.b[c]) - alpha * sv;
           return U5{pv, sv, xv, rv, sweep_first(rv, L0.diag[c])};
         },
         [&](int c, U5 v) {
           a.p[c] = v.p;
           a.s[c] = v.s;
           a.x[c] = v.x;
-          xst(&L0.b[c], v.r);
-          if (Lg > 0) xst(&L0.xa[c], v.xa);
+          mst<SC>(&L0.b[c], v.r);
+          if (Lg > 0) mst<SC>(&L0.xa[c], v.xa);
         });
     if (!bar() || !vcycle() || !matvec()) {
       status = -3;
@@ -668,7 +684,7 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
     }
     ++it;
     double s3[3];
-    group_tree_n<3>(a.part, nb, red, s3);
+    group_tree_n<3, SC>(a.part, nb, red, s3);
     const double gamma_new = s3[0];
     delta = s3[1];
     if (s3[2] <= thr) {
@@ -686,9 +702,84 @@ __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
     alpha = gamma_new / den;
     gamma = gamma_new;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bid == 0 && threadIdx.x == 0) {
     a.sc->cg_iters = it;
     a.sc->cg_status = status;
+  }
+}
+
+__global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
+{
+  extern __shared__ double lds[];
+  __shared__ double red[3 * kTree];
+  mgcg_solve<__HIP_MEMORY_SCOPE_AGENT>(a, static_cast<int>(gridDim.x),
+                                       static_cast<int>(blockIdx.x), lds, red);
+}
+
+// ---------------------------------------------------------------------------
+// Batched CG over a pool of resident workgroups.  The host hands every active
+// Newton instance a group of workgroups and writes, per workgroup, the list of
+// (instance, rank) jobs it takes part in; all lists follow one global job
+// order, so the earliest unfinished job always has every member at hand and
+// the pool cannot deadlock.  The solve of an instance does not depend on how
+// many workgroups serve it or where.  Instances with the plain CG and those
+// with the multigrid-preconditioned one have pools of their own, launched one
+// after the other (one body with both would need more registers than a lane
+// has).
+// ---------------------------------------------------------------------------
+struct CgJob {
+  int inst, rank, G, tb;     // tb: blocks per workgroup, bit 30 = register form
+};
+constexpr int kCgJobReg = 1 << 30;
+
+__global__ __launch_bounds__(kCgThreadsMax) void cg_batch_kernel(const Inst *__restrict__ insts,
+                                                                 const int *__restrict__ off,
+                                                                 const CgJob *__restrict__ jobs)
+{
+  const int e0 = off[blockIdx.x], e1 = off[blockIdx.x + 1];
+  for (int e = e0; e < e1; ++e) {
+    const CgJob jb = jobs[e];
+    const Inst &in = insts[jb.inst];
+    CGArgs a;
+    a.m = in.m;
+    a.gx = in.gx;
+    a.gy = in.gy;
+    a.diag = in.diag;
+    a.b = in.rhs;
+    a.x = in.cg_x;
+    a.gr = in.cg_r;
+    a.gw = in.cg_w;
+    a.gp = in.cg_p;
+    a.gs = in.cg_s;
+    a.pub = in.cg_pub;
+    a.part = in.cg_mpart;
+    a.TB = jb.tb & (kCgJobReg - 1);
+    a.tol2 = in.tol2;
+    a.max_iters = in.cg_max;
+    a.barrier = in.cg_barrier;
+    a.sc = in.sc;
+    if (jb.tb & kCgJobReg) cg_run<true>(a, jb.rank, jb.G);
+    else cg_run<false>(a, jb.rank, jb.G);
+    __syncthreads();
+  }
+}
+
+// the multigrid instances' pool: job (instance, rank) runs member `rank` of
+// the instance's group of G workgroups (mg: the instances' arguments); 8-wave
+// workgroups, whose lanes have the registers the solve takes when its
+// arguments come from memory
+constexpr int kMgPoolWaves = 8;
+__global__ __launch_bounds__(64 * kMgPoolWaves) void mgcg_batch_kernel(const int *__restrict__ off,
+                                                                   const CgJob *__restrict__ jobs,
+                                                                   const MGArgs *__restrict__ mg)
+{
+  extern __shared__ double lds[];
+  __shared__ double red[3 * kTree];
+  const int e0 = off[blockIdx.x], e1 = off[blockIdx.x + 1];
+  for (int e = e0; e < e1; ++e) {
+    const CgJob jb = jobs[e];
+    mgcg_solve<__HIP_MEMORY_SCOPE_AGENT>(mg[jb.inst], jb.G, jb.rank, lds, red);
+    __syncthreads();
   }
 }
 

@@ -64,3 +64,29 @@ def test_group_arguments(gpu):
     assert gpu.step_group([s, s], 1) == L.E_INVALID_ARG
     assert gpu.step_group([s], 2) == 0
     assert s.stats()["iters"] == 2
+
+
+def test_group_larger_than_the_device(gpu):
+    """More multigrid CGs than fit on the device at once (ten 256^2 cavities,
+    32 workgroups of one compute unit each): grouped stepping admits an
+    iteration only while the CGs in flight fit, so every problem steps without
+    a barrier time-out and equals the same problem stepped alone."""
+    import cp_model as cp
+    ws = [cavity_2d(n=256, kn=kn, particles=300_000, seed=i)
+          for i, kn in enumerate((0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0, 5.0, 10.0))]
+    kws = []
+    for w in ws:
+        D = np.full(w.n_cells, cp.d_eff(float(w.vg * w.tau[0]), w.dx))
+        kws.append(dict(newton=True, diff_x=D, diff_y=D, tally_faces=gpu.FACES_EVERY,
+                        cg_precond=gpu.PRECOND_MG))
+    grouped = [gpu.Solver(w, own_stream=True, **k) for w, k in zip(ws, kws)]
+    assert gpu.step_group(grouped, 3) == 0
+    for w, k, a in zip(ws, kws, grouped):
+        b = gpu.Solver(w, **k)
+        assert b.step(3) == 0
+        sa, sb = a.state(), b.state()
+        assert torch.equal(sa[2], sb[2]) and torch.equal(sa[3], sb[3])
+        assert a.stats()["cg_iters_total"] == b.stats()["cg_iters_total"]
+        b.close()
+    for a in grouped:
+        a.close()

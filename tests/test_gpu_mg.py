@@ -118,5 +118,49 @@ def test_mg_rejections(gpu):
     Dx, _ = _diff(w)
     with pytest.raises(L.IugkpError):
         gpu.Solver(w, newton=True, diff_x=Dx, cg_precond=2)
-    with pytest.raises(L.IugkpError):
-        gpu.BatchSolver([w, w], newton=True, diff_x=Dx, cg_precond=gpu.PRECOND_MG)
+
+
+def test_mg_batch_equals_single_solves(gpu, oracle_mod):
+    """Batched solves with the multigrid-preconditioned CG (one workgroup per
+    instance) beside instances with the plain CG pool and without Newton:
+    every instance's status, iteration count, CG iterations, T and q equal its
+    own single solve (a group of 8-wave workgroups), and the first instance
+    equals the oracle's multigrid solve."""
+    ws = [cavity_2d(n=48, ny=40, kn=0.01, particles=100_000, seed=3),
+          cavity_2d(n=100, ny=77, kn=0.003, particles=400_000, seed=4),
+          slab_1d(n=3000, kn=0.001, particles=60_000, seed=5),
+          cavity_2d(n=256, kn=0.05, particles=600_000, seed=6),
+          cavity_2d(n=33, kn=0.2, particles=40_000, seed=7),
+          cavity_2d(n=40, kn=1.0, particles=60_000, seed=8)]
+    kws = []
+    for i, w in enumerate(ws):
+        Dx, Dy = _diff(w)
+        kw = dict(newton=True, diff_x=Dx, diff_y=Dy, rng_mode=oracle_mod.CRN, max_iters=30,
+                  res_tol=1e-6, tally_faces=oracle_mod.FACES_FINAL)
+        if i == 4:
+            kw["cg_precond"] = oracle_mod.PRECOND_NONE        # the pool beside the multigrid
+        elif i == 5:
+            kw["newton"] = False
+        else:
+            kw["cg_precond"] = oracle_mod.PRECOND_MG
+        kws.append(kw)
+    singles = []
+    for w, k in zip(ws, kws):
+        s = gpu.Solver(w, **k)
+        try:
+            rc, T, qx, qy, st = s.solve()
+        except gpu.IugkpError as e:
+            rc, T, qx, qy, st = e.code, None, None, None, s.stats()
+        singles.append((rc, T, qx, qy, st))
+    bs = gpu.BatchSolver(ws, per_instance=kws)
+    rc, outs = bs.solve()
+    for i, ((rc1, T1, qx1, qy1, st1), (Tb, qxb, qyb, stb)) in enumerate(zip(singles, outs)):
+        assert stb["status"] == rc1, f"instance {i}"
+        assert stb["iters"] == st1["iters"], f"instance {i}"
+        assert stb["cg_iters_total"] == st1["cg_iters_total"], f"instance {i}"
+        if rc1 >= 0:
+            assert torch.equal(Tb, T1) and torch.equal(qxb, qx1) and torch.equal(qyb, qy1), i
+    o = oracle_mod.Oracle(ws[0], **kws[0])
+    rco, To, qxo, qyo = o.solve()
+    assert rco == singles[0][0] and o.info().cg_iters_total == outs[0][3]["cg_iters_total"]
+    assert np.array_equal(To, _np(outs[0][0])) and np.array_equal(qxo, _np(outs[0][1]))
