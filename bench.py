@@ -65,6 +65,12 @@ def parse():
                     help="only the persistent-particle timing (its own JSON line; for profiling)")
     ap.add_argument("--nongray-only", action="store_true",
                     help="only the 40-band timing (printed as its own JSON line; for profiling)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched vs sequential comparison (its own JSON line)")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="only the kernel pass that the counter collection profiles")
+    ap.add_argument("--no-counters", action="store_true",
+                    help="skip the rocprofv3 counter passes (HBM bytes, atomics, occupancy)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer three times (scales rocprofv3 FETCH_SIZE / "
                          "WRITE_SIZE to bytes) and exit")
@@ -187,14 +193,16 @@ def cpu_baseline(sample):
 
 def bench_batch(P, dev, count):
     """Uneven batch of independent cavities (sides 32..256, Kn log-uniform in
-    [1e-3, 10], random walls, 1e4..1e6 particles, Newton, CRN, residual 1e-6):
+    [1e-3, 10], random walls, 1e4..1e6 particles, Newton with the multigrid-
+    preconditioned CG, CRN, residual 1e-6):
     the same problems solved one by one through iugkp_solve, then together
     through iugkp_batch_solve.  Both paths do identical work per instance
     (bitwise equal results, same iteration counts and statuses)."""
     import torch
     from synth import batch_workloads
     ws = batch_workloads(count=count)
-    kw = dict(rng_mode=P.RNG_CRN, tally_faces=P.FACES_FINAL, max_iters=60, res_tol=1e-6)
+    kw = dict(rng_mode=P.RNG_CRN, tally_faces=P.FACES_FINAL, max_iters=60, res_tol=1e-6,
+              cg_precond=P.PRECOND_MG)
     seq_status = []
     solvers = [P.Solver(w, device=dev, **kw) for w in ws]
     torch.cuda.synchronize()
@@ -223,6 +231,7 @@ def bench_batch(P, dev, count):
             "converged": sum(1 for x in bat_status if x == 0),
             "not_converged": sum(1 for x in bat_status if x == 1),
             "failed": sum(1 for x in bat_status if x < 0),
+            "statuses": {str(c): bat_status.count(c) for c in sorted(set(bat_status))},
             "iterations_total": int(sum(iters)), "flights_total": int(flights),
             "batched_flights_per_s": flights / bat,
             "note": "per-instance setup (allocation, Newton operator) excluded from both timings"}
@@ -560,6 +569,142 @@ def cpu_baseline_nongray():
                       "t_ref), single thread"}
 
 
+# kernels of the particle step (between the step's HIP events) and of the Newton CG
+PS_KERNELS = ("march_kernel", "stripe_presample_kernel", "march_stripes_kernel")
+CG_KERNELS = ("mgcg_kernel",)
+PROFILE_ITERS = 2
+# rocprofv3 counter passes (each within one pass's hardware limits: TCC <= 4,
+# SQ <= 8, TCP <= 4); FETCH_SIZE and WRITE_SIZE in KiB per dispatch
+COUNTER_PASSES = (("FETCH_SIZE",),
+                  ("WRITE_SIZE", "TCC_EA0_ATOMIC_sum"),
+                  ("SQ_INSTS_LDS", "SQ_WAVES", "MeanOccupancyPerActiveCU",
+                   "TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum"))
+
+
+def profile_pass():
+    """What collect_counters profiles: a 256 MiB device copy three times (to
+    scale FETCH_SIZE / WRITE_SIZE to bytes), then the benchmark's four Kn
+    problems one at a time, PROFILE_ITERS iterations each, started from the
+    seeded temperature field so that every iteration emits from every cell as
+    the benchmark's steady iterations do."""
+    import torch
+    import paper_2506_09465_amd as P
+    from synth import cavity_2d, seeded_temperature
+    dev = torch.device("cuda:0")
+    n = 256 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    for kn in KNS:
+        w = cavity_2d(n=N_SIDE, kn=kn, particles=PARTICLES, newton=True, seed=0)
+        s = P.Solver(w, device=dev, tally_faces=P.FACES_EVERY, cg_precond=P.PRECOND_MG,
+                     T_init=seeded_temperature(N_SIDE * N_SIDE))
+        assert s.step(PROFILE_ITERS) == 0
+        torch.cuda.synchronize()
+        s.close()
+    print(json.dumps({"profile_pass": "done"}), flush=True)
+
+
+def _read_counter_csv(root):
+    """[(kernel name, grid size, {counter: value})] per dispatch, in dispatch
+    order, from every *counter_collection.csv under root."""
+    import csv
+    import glob
+    rows = {}
+    for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                d = rows.setdefault(int(r["Dispatch_Id"]),
+                                    (r["Kernel_Name"], int(r.get("Grid_Size", 0) or 0), {}))
+                d[2][r["Counter_Name"]] = d[2].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [rows[k] for k in sorted(rows)]
+
+
+def _kernel_is(name, kernels):
+    return any(k + "<" in name or k + "(" in name or name.endswith(k) for k in kernels)
+
+
+def collect_counters(timeout_s=240):
+    """Run profile_pass under rocprofv3 once per counter pass and reduce the
+    per-dispatch counters to per-launch figures of the particle step (all
+    its kernels of one iteration) and of the multigrid CG.  Each pass is
+    reduced on its own (by kernel name), so the passes need not number their
+    dispatches alike."""
+    import shutil
+    import subprocess
+    import tempfile
+    prof = shutil.which("rocprofv3") or "/opt/rocm/bin/rocprofv3"
+    if not os.path.exists(prof):
+        return {"error": "rocprofv3 not found"}
+    env = dict(os.environ, TMPDIR="/tmp")
+    launches = len(KNS) * PROFILE_ITERS
+    groups = {"particle_step": PS_KERNELS, "mgcg_kernel": CG_KERNELS}
+    tot = {g: {} for g in groups}
+    ndisp = {g: 0 for g in groups}
+    occ = {g: [] for g in groups}
+    copy = {}
+    cmds = []
+    for counters in COUNTER_PASSES:
+        out = tempfile.mkdtemp(prefix="iugkp_pmc_", dir="/tmp")
+        cmd = [prof, "--pmc", *counters, "-d", out, "-o", "run", "--output-format", "csv", "--",
+               sys.executable, os.path.join(ROOT, "bench.py"), "--profile-pass"]
+        cmds.append(" ".join(["rocprofv3", "--pmc", *counters, "-d", "<dir>", "-o", "run",
+                              "--output-format", "csv", "--", "python3", "bench.py",
+                              "--profile-pass"]))
+        try:
+            r = subprocess.run(cmd, cwd="/tmp", env=env, timeout=timeout_s,
+                               stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+        except subprocess.TimeoutExpired:
+            return {"error": f"counter pass {counters} timed out"}
+        rows = _read_counter_csv(out)
+        shutil.rmtree(out, ignore_errors=True)
+        if not rows:
+            return {"error": f"counter pass {counters} produced no data (rc {r.returncode})"}
+        # the calibration copies: the three largest copy dispatches
+        cp = sorted([d for d in rows if "copyBuffer" in d[0]], key=lambda d: -d[1])[:3]
+        for d in cp:
+            for k, v in d[2].items():
+                copy[k] = copy.get(k, 0.0) + v / len(cp)
+        for g, names in groups.items():
+            ds = [d for d in rows if _kernel_is(d[0], names)]
+            if counters == COUNTER_PASSES[0]:
+                ndisp[g] = len(ds)
+            for d in ds:
+                for k, v in d[2].items():
+                    if k == "MeanOccupancyPerActiveCU":
+                        occ[g].append(v)
+                    else:
+                        tot[g][k] = tot[g].get(k, 0.0) + v
+    nbytes = 256 * 1024 * 1024
+    fk, wk = copy.get("FETCH_SIZE", 0.0), copy.get("WRITE_SIZE", 0.0)
+    f_fac = nbytes / (fk * 1024.0) if fk > 0 else None
+    w_fac = nbytes / (wk * 1024.0) if wk > 0 else None
+
+    def reduce(g):
+        t = tot[g]
+        r = {"dispatches": ndisp[g], "launches": launches,
+             "fetch_kib": t.get("FETCH_SIZE", 0.0) / launches,
+             "write_kib": t.get("WRITE_SIZE", 0.0) / launches,
+             "ea_atomic_requests": t.get("TCC_EA0_ATOMIC_sum", 0.0) / launches,
+             "tcp_atomic_requests": t.get("TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum", 0.0) / launches,
+             "lds_wave_instructions": t.get("SQ_INSTS_LDS", 0.0) / launches,
+             "waves": t.get("SQ_WAVES", 0.0) / launches,
+             "mean_occupancy_waves_per_active_cu":
+                 (sum(occ[g]) / len(occ[g])) if occ[g] else None}
+        if f_fac and w_fac:
+            r["hbm_bytes"] = (r["fetch_kib"] * f_fac + r["write_kib"] * w_fac) * 1024.0
+        return r
+
+    return {"source": "rocprofv3 --pmc, run by this benchmark (profile_pass: the four Kn "
+                      f"problems, {PROFILE_ITERS} iterations each, from a seeded temperature "
+                      "field)",
+            "commands": cmds, "fetch_factor": f_fac, "write_factor": w_fac,
+            "particle_step": reduce("particle_step"), "mgcg_kernel": reduce("mgcg_kernel")}
+
+
 def copy_calibration():
     import torch
     n = 256 * 1024 * 1024 // 8
@@ -575,6 +720,9 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.profile_pass:
+        profile_pass()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -594,6 +742,9 @@ def main():
         return
     if args.expected_only:
         print(json.dumps(bench_expected(P, dev)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(bench_batch(P, dev, args.batch)), flush=True)
         return
 
     # the four Kn problems are independent: each solver has a stream of its
@@ -673,22 +824,75 @@ def main():
         tot["launches"] += K
 
     src = source_hash()
-    kernels = {
-        "march_kernel": {"ms": tot["ms_march"], "bytes": tot["march_bytes"], "launches": tot["launches"]},
-        "mgcg_kernel": {"ms": tot["ms_cg"], "bytes": tot["cg_bytes"], "launches": tot["launches"]},
-    }
-    rooflines = {}
-    for name, k in kernels.items():
-        avg_ms = k["ms"] / k["launches"]
-        per_launch = k["bytes"] / k["launches"]
-        achieved = per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
-        traffic = traffic_from_profiles(name, src)
-        rooflines[name] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                           "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),
-                           "algorithmic_bytes_per_launch": int(per_launch),
-                           "share_of_sequential_step": round(k["ms"] / (elapsed * 1e3), 3)}
-    dominant = max(kernels, key=lambda n: kernels[n]["ms"])
+    # the tally-throughput ceilings the particle step works against: int64
+    # atomic adds to random words of a 2 MB global array (the size of the
+    # cavity's tallies) and of a workgroup's LDS array
+    ceil = {"global_int64_2MB_per_s": P.dev_atomics(False, n_words=262144),
+            "lds_int64_per_s": P.dev_atomics(True),
+            "note": "int64 atomic adds to random words, every lane of full wavefronts: of a "
+                    "2 MB global array, and of a 4096-word LDS array per workgroup"}
+    counters = None if args.no_counters else collect_counters()
+    cnt_ok = counters is not None and "error" not in counters
+    n_l = tot["launches"]
+    ps_ms = tot["ms_march"] / n_l
+    cg_ms = tot["ms_cg"] / n_l
+    # particle step: the algorithmic tally updates (one per face crossed and one
+    # deposit or wall absorption per flight) against the LDS int64-atomic
+    # ceiling, the best rate any placement of the tallies can reach
+    tallies = (tot["crossings"] + tot["flights"]) / n_l
+    ps_rate = tallies / (ps_ms / 1e3)
+    ps = {"bound": "atomics", "achieved": ps_rate, "peak": ceil["lds_int64_per_s"],
+          "unit": "tally atomics/s", "frac": round(ps_rate / ceil["lds_int64_per_s"], 5),
+          "traffic": None, "avg_launch_ms": round(ps_ms, 4),
+          "algorithmic_atomics_per_launch": int(tallies),
+          "algorithmic_bytes_per_launch": int(tot["march_bytes"] / n_l),
+          "share_of_sequential_step": round(tot["ms_march"] / (elapsed * 1e3), 3),
+          "kernels": list(PS_KERNELS)}
+    cg_b = tot["cg_bytes"] / n_l
+    cg_rate = cg_b / (cg_ms / 1e3) / 1e9
+    cg = {"bound": "hbm", "achieved": round(cg_rate, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+          "frac": round(cg_rate / HBM_PEAK_GBS, 5), "traffic": None,
+          "avg_launch_ms": round(cg_ms, 4), "algorithmic_bytes_per_launch": int(cg_b),
+          "us_per_cg_iteration": round(tot["ms_cg"] * 1e3 / max(tot["cg_iters"], 1), 3),
+          "share_of_sequential_step": round(tot["ms_cg"] / (elapsed * 1e3), 3),
+          "note": "latency-bound: group barriers and the fixed-order reductions of every "
+                  "iteration, not bandwidth"}
+    if cnt_ok:
+        c = counters["particle_step"]
+        sec = ps_ms / 1e3
+        hb = c.get("hbm_bytes")
+        ps["traffic"] = int(hb) if hb else None
+        ps["measured"] = {
+            "hbm": {"bytes_per_launch": hb, "achieved_GBs": hb / sec / 1e9 if hb else None,
+                    "peak_GBs": HBM_PEAK_GBS,
+                    "frac": round(hb / sec / 1e9 / HBM_PEAK_GBS, 5) if hb else None},
+            "global_atomics": {"requests_per_launch": c["tcp_atomic_requests"],
+                               "to_memory_per_launch": c["ea_atomic_requests"],
+                               "achieved_per_s": c["tcp_atomic_requests"] / sec,
+                               "peak_per_s": ceil["global_int64_2MB_per_s"],
+                               "frac": round(c["tcp_atomic_requests"] / sec /
+                                             ceil["global_int64_2MB_per_s"], 5),
+                               "note": "atomic requests from the vector caches to L2 "
+                                       "(TCP_TCC_ATOMIC_WITHOUT_RET_REQ) against int64 adds "
+                                       "to random words, one request per lane"},
+            "lds": {"wave_instructions_per_launch": c["lds_wave_instructions"],
+                    "achieved_per_s": c["lds_wave_instructions"] / sec,
+                    "peak_per_s": ceil["lds_int64_per_s"] / 64.0,
+                    "frac": round(c["lds_wave_instructions"] / sec /
+                                  (ceil["lds_int64_per_s"] / 64.0), 5),
+                    "note": "every LDS instruction of the step (tally atomics, the tally "
+                            "tiles' zeroing and flush, the pre-pass staging) against the "
+                            "rate of full-wavefront LDS int64 atomics"},
+            "occupancy": {"mean_waves_per_active_cu": c["mean_occupancy_waves_per_active_cu"],
+                          "waves_per_launch": c["waves"]}}
+        g = counters["mgcg_kernel"]
+        cg["traffic"] = int(g["hbm_bytes"]) if g.get("hbm_bytes") else None
+        cg["measured"] = {"occupancy": {"mean_waves_per_active_cu":
+                                        g["mean_occupancy_waves_per_active_cu"],
+                                        "waves_per_launch": g["waves"]},
+                          "lds_wave_instructions_per_launch": g["lds_wave_instructions"]}
+    rooflines = {"particle_step": ps, "mgcg_kernel": cg}
+    dominant = "particle_step" if tot["ms_march"] >= tot["ms_cg"] else "mgcg_kernel"
     roof = dict(rooflines[dominant])
     roof["kernel"] = dominant
 
@@ -715,14 +919,8 @@ def main():
         "source_hash": src,
     }
 
-    # the tally-throughput ceilings the particle step works against: int64
-    # atomic adds to random words of a 2 MB global array (the size of the
-    # cavity's tallies) and of a workgroup's LDS array
-    out["atomics_ceiling"] = {
-        "global_int64_2MB_per_s": P.dev_atomics(False, n_words=262144),
-        "lds_int64_per_s": P.dev_atomics(True),
-        "note": "particle-step tallies: one add per face crossing tallied and per deposit, in "
-                "LDS inside a tile's window or a stripe, in global memory outside"}
+    out["atomics_ceiling"] = ceil
+    out["counters"] = counters
 
     if not args.no_tts:
         tts = {}
