@@ -139,8 +139,8 @@ def _close_all() -> None:
 atexit.register(_close_all)
 
 
-def finalizing() -> bool:
-    return sys.is_finalizing()
+def finalizing(_is_finalizing=sys.is_finalizing) -> bool:
+    return _is_finalizing()
 
 
 class IugkpError(RuntimeError):

@@ -46,10 +46,11 @@ class BatchSolver:
             L.lib().iugkp_batch_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if L.finalizing():
-            return
+    def __del__(self, _finalizing=L.finalizing):
+        # (module globals may already be gone when the collector runs at shutdown)
         try:
+            if _finalizing():
+                return
             self.close()
         except Exception:
             pass

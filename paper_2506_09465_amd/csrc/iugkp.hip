@@ -752,13 +752,17 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
              : reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>);
       HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kStripeBlock, lds));
       // (the analog kernel reads every particle's first segment from a
-      // 96-byte record and a 4-byte row range per particle; without the
-      // memory, or beyond 65534 rows, tiles are used)
+      // 64-byte record (80 with null collisions) and a 4-byte row range per
+      // particle; without the memory, or beyond 65534 rows or 65535
+      // columns, tiles are used)
       bool recs = true;
-      if (!ev && m.ny > 0xfffe) recs = false;     // (rows in 16 bits)
+      if (!ev && (m.ny > 0xfffe || m.nx > 0xffff)) recs = false;   // (16-bit rows, columns)
       else if (!ev) {
         const size_t np = static_cast<size_t>(m.n_emit) * static_cast<size_t>(d.N);
-        recs = ih.alloc(&ih.rec.r, np) == hipSuccess && ih.alloc(&ih.rec.key, np) == hipSuccess;
+        const size_t rb = d.has_null ? sizeof(iugkp::PRecN) : sizeof(iugkp::PRec);
+        unsigned char *r = nullptr;
+        recs = ih.alloc(&r, np * rb) == hipSuccess && ih.alloc(&ih.rec.key, np) == hipSuccess;
+        ih.rec.r = r;
         if (!recs) (void)hipGetLastError();
       }
       if (per_cu >= 1 && recs) {
@@ -1340,11 +1344,14 @@ int enqueue_iteration(iugkp_handle *h, int faces)
   } else if (faces && ih.stripe_R > 0) {
     const unsigned long long np =
         static_cast<unsigned long long>(m.n_emit) * static_cast<unsigned long long>(ih.d.N);
-    iugkp::stripe_presample_kernel<256>
-        <<<static_cast<unsigned int>((np + 255) / 256), 256, 0, s>>>(h->d_inst, ih.rec);
+    const unsigned int pg = static_cast<unsigned int>((np + 255) / 256);
+    const dim3 sg(ih.stripe_C, ih.stripe_S);
+    if (ih.d.has_null)
+      iugkp::stripe_presample_kernel<256, true><<<pg, 256, 0, s>>>(h->d_inst, ih.rec);
+    else
+      iugkp::stripe_presample_kernel<256, false><<<pg, 256, 0, s>>>(h->d_inst, ih.rec);
     iugkp::march_stripes_kernel<kStripeBlock>
-        <<<dim3(ih.stripe_C, ih.stripe_S), kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R,
-                                                                              ih.stripe_C, ih.rec);
+        <<<sg, kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
     HIP_TRY(hipGetLastError());
   } else {
     rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, h->lds, h->block, faces, 0,

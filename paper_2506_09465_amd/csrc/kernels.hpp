@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "device_core.hpp"
 
 namespace iugkp {
@@ -816,17 +818,25 @@ __device__ __forceinline__ int faces_upto_near(int cnt, int k0, int st, int jmax
 // one segment at a time.
 // ---------------------------------------------------------------------------
 // Every particle's start and first segment, sampled once per iteration for
-// all row stripes (one 96-byte record per particle, indexed by its place in
-// the enumeration, emitters fastest: the lanes of a stripe wavefront drift
-// apart in that order, so a particle's fields share one or two cache lines):
-// weight (0: no particle), start cell and point, direction, free path and
-// acceptance draw, and the segment's end in closed form (end cell, wall face
-// or -1, y faces crossed, all faces crossed).
-struct alignas(32) PRec {
+// all row stripes, one record per particle indexed by its place in the
+// enumeration, emitters fastest (the lanes of a stripe wavefront drift apart
+// in that order, so a particle's fields share one cache line): weight (0: no
+// particle), start point and direction, start and end cells (16-bit columns
+// and rows), the wall face that absorbs the segment or -1, the y faces and
+// all faces it crosses; with null collisions also the free path and the
+// acceptance draw.  64 bytes, or 80 with null collisions.
+struct alignas(16) PRec {
   long long q;
-  double sy, x0, y0, sx, ell, uacc;
-  int iy, iye, bface, ix, ixe, nyp, ncross, pad;
+  double x0, y0, sx, sy;
+  uint32_t cell, cell_e;     // ix | iy << 16, ixe | iye << 16
+  int bface;
+  uint32_t nyp, ncross, pad;
 };
+struct alignas(16) PRecN {   // with null collisions
+  PRec c;
+  double ell, uacc;
+};
+static_assert(sizeof(PRec) == 64 && sizeof(PRecN) == 80, "record sizes");
 // and, beside it, the rows that stripes must run the particle in (lo, hi:
 // empty for no particle): the rows of a first segment that is the whole
 // flight (up to the wall for an absorption on a y wall), or with null
@@ -834,7 +844,7 @@ struct alignas(32) PRec {
 // in the high half; no particle: lo 0xffff, hi 0).  A stripe reads 4 bytes
 // per particle to skip those outside its rows, not the whole record.
 struct StripeRec {
-  PRec *r;
+  void *r;                   // PRec, or PRecN with null collisions [particles]
   uint32_t *key;
 };
 __device__ __forceinline__ uint32_t row_range(int lo, int hi)
@@ -842,14 +852,16 @@ __device__ __forceinline__ uint32_t row_range(int lo, int hi)
   return (static_cast<uint32_t>(lo) << 16) | static_cast<uint32_t>(hi);
 }
 
-template <int BS>
+template <int BS, bool NUL>
 __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__restrict__ insts,
                                                               StripeRec rec)
 {
   // the workgroup's records are built in LDS and written out as contiguous
   // 16-byte stores (a lane storing its own record field by field writes
-  // 8 bytes every 96)
-  __shared__ PRec srec[BS];
+  // 8 bytes every record)
+  using Rec = typename std::conditional<NUL, PRecN, PRec>::type;
+  __shared__ Rec srec[BS];
+  __shared__ uint32_t skey[BS];
   const Inst &in = insts[0];
   const Mesh &m = in.m;
   const FlyIn fa = {m, in.lam_min, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1, 1,
@@ -862,10 +874,11 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
     const uint32_t kk = static_cast<uint32_t>(pc / n_emit);
     const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
     const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
-    PRec &out = srec[threadIdx.x];
+    Rec &rec_out = srec[threadIdx.x];
+    PRec &out = *reinterpret_cast<PRec *>(&rec_out);     // (the common part comes first)
     out.q = q;
     if (q == 0) {
-      rec.key[pc] = row_range(0xffff, 0);
+      skey[threadIdx.x] = row_range(0xffff, 0);
     } else {
       int ix = 0, iy = 0;
       double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
@@ -880,19 +893,19 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
       const int ky0 = (sty > 0) ? iy + 1 : iy;
       int ixe = ix, iye = iy, bface = -1, nxp = 0, nyp = 0;
       segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
-      out.sy = sy;
       out.x0 = x0;
       out.y0 = y0;
       out.sx = sx;
-      out.ell = ell;
-      out.uacc = us.y;
-      out.iy = iy;
-      out.iye = iye;
+      out.sy = sy;
+      out.cell = static_cast<uint32_t>(ix) | (static_cast<uint32_t>(iy) << 16);
+      out.cell_e = static_cast<uint32_t>(ixe) | (static_cast<uint32_t>(iye) << 16);
       out.bface = bface;
-      out.ix = ix;
-      out.ixe = ixe;
-      out.nyp = nyp;
-      out.ncross = nxp + nyp;
+      out.nyp = static_cast<uint32_t>(nyp);
+      out.ncross = static_cast<uint32_t>(nxp + nyp);
+      if constexpr (NUL) {
+        rec_out.ell = ell;
+        rec_out.uacc = us.y;
+      }
       int lo = min(iy, iye), hi = max(iy, iye);
       if (fa.has_null) {
         lo = (sty < 0) ? 0 : iy;
@@ -901,18 +914,19 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
         if (sty > 0) hi = m.ny - 1;
         else lo = 0;
       }
-      rec.key[pc] = row_range(lo, hi);
+      skey[threadIdx.x] = row_range(lo, hi);
     }
   }
   __syncthreads();
   // (a record without a particle is never read past its weight)
-  constexpr int kWords = static_cast<int>(sizeof(PRec) / sizeof(uint4));
-  static_assert(sizeof(PRec) % sizeof(uint4) == 0, "records are whole 16-byte words");
+  constexpr int kWords = static_cast<int>(sizeof(Rec) / sizeof(uint4));
+  static_assert(sizeof(Rec) % sizeof(uint4) == 0, "records are whole 16-byte words");
   const unsigned long long left = (p0 < total) ? total - p0 : 0;
-  const int n = static_cast<int>(left < BS ? left : BS) * kWords;
+  const int cnt = static_cast<int>(left < BS ? left : BS);
+  if (static_cast<int>(threadIdx.x) < cnt) rec.key[pc] = skey[threadIdx.x];
   const uint4 *src = reinterpret_cast<const uint4 *>(srec);
-  uint4 *dst = reinterpret_cast<uint4 *>(rec.r + p0);
-  for (int i = threadIdx.x; i < n; i += BS) dst[i] = src[i];
+  uint4 *dst = reinterpret_cast<uint4 *>(static_cast<Rec *>(rec.r) + p0);
+  for (int i = threadIdx.x; i < cnt * kWords; i += BS) dst[i] = src[i];
 }
 
 template <int BS>
@@ -1029,21 +1043,28 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       // emitters fastest: neighbouring lanes start in different cells
       kk = static_cast<uint32_t>(pc / n_emit);
       e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
-      const PRec &rp = rec.r[pc];
+      // (the record's common part comes first in both forms)
+      const unsigned char *rb = static_cast<const unsigned char *>(rec.r) +
+                                pc * (fa.has_null ? sizeof(PRecN) : sizeof(PRec));
+      const PRec &rp = *reinterpret_cast<const PRec *>(rb);
       q = rp.q;
-      iy = rp.iy;
-      iye = rp.iye;
+      const uint32_t cs = rp.cell, ce = rp.cell_e;
+      ix = static_cast<int>(cs & 0xffffu);
+      iy = static_cast<int>(cs >> 16);
+      ixe = static_cast<int>(ce & 0xffffu);
+      iye = static_cast<int>(ce >> 16);
       sy = rp.sy;
       sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
-      ix = rp.ix;
       x0 = rp.x0;
       y0 = rp.y0;
       sx = rp.sx;
-      ell = rp.ell;
-      uacc = rp.uacc;
-      ixe = rp.ixe;
+      if (fa.has_null) {
+        const PRecN &rn = *reinterpret_cast<const PRecN *>(rb);
+        ell = rn.ell;
+        uacc = rn.uacc;
+      }
       bface = rp.bface;
-      const int nyp = rp.nyp;
+      const int nyp = static_cast<int>(rp.nyp);
       inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
       inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
       stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
