@@ -223,6 +223,7 @@ def bench_batch(P, dev, count):
     rc, outs = bs.solve()
     torch.cuda.synchronize()
     bat = time.perf_counter() - a
+    tune_a, tune_c, groups = bs.tuning()
     bat_status = [o[3]["status"] for o in outs]
     iters = [o[3]["iters"] for o in outs]
     flights = sum(o[3]["tot_flights"] for o in outs)
@@ -234,6 +235,13 @@ def bench_batch(P, dev, count):
             "statuses": {str(c): bat_status.count(c) for c in sorted(set(bat_status))},
             "iterations_total": int(sum(iters)), "flights_total": int(flights),
             "batched_flights_per_s": flights / bat,
+            "autotuner": {"model_us_per_iteration": round(tune_a, 3),
+                          "model_us_per_cell_per_workgroup": round(tune_c, 6),
+                          "multigrid_groups_last_replay": {str(int(g)): int((groups == g).sum())
+                                                           for g in sorted(set(groups.tolist()))
+                                                           if g > 0},
+                          "note": "group sizes of the multigrid pool chosen before every replay "
+                                  "from a fit of the measured job durations"},
             "note": "per-instance setup (allocation, Newton operator) excluded from both timings"}
 
 

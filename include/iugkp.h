@@ -373,6 +373,16 @@ int iugkp_batch_create(const iugkp_problem *const *problems,
 int iugkp_batch_solve(iugkp_batch *b, double *const *T_out, double *const *qx_out,
                       double *const *qy_out, iugkp_stats *stats);
 void iugkp_batch_destroy(iugkp_batch *b);
+/* The autotuner of the batch's multigrid CG pool.  Before every replay the
+ * library picks each multigrid instance's group of workgroups from a model of
+ * one CG iteration, per_iter_us + per_cell_us * cells / group microseconds,
+ * fitted to the measured duration of every multigrid job so far in this
+ * process (the fit is kept for later batches); results do not depend on the
+ * groups.  Writes the current fit (either pointer may be NULL) and, when
+ * groups is not NULL, groups[i] = the group size of instance i in the last
+ * replay (0 without a Newton step; plain-CG instances keep their fixed group).
+ * Host pointers.  Returns IUGKP_OK or IUGKP_E_INVALID_ARG. */
+int iugkp_batch_tuning(iugkp_batch *b, double *per_iter_us, double *per_cell_us, int *groups);
 
 const char *iugkp_strerror(int code);
 const char *iugkp_last_error(void);

@@ -79,3 +79,14 @@ class BatchSolver:
             nfy = (w.ny + 1) * w.nx if w.dim == 2 else 0
             out.append((Ts[i], qxs[i], qys[i][:nfy], st[i].as_dict()))
         return rc, out
+
+    def tuning(self):
+        """The multigrid pool's autotuner: (per-iteration us, per-cell us, group
+        size of each instance in the last replay)."""
+        import numpy as np
+        a = C.c_double(0.0)
+        c = C.c_double(0.0)
+        g = np.zeros(len(self.ws), dtype=np.int32)
+        L.check(L.lib().iugkp_batch_tuning(self.h, C.addressof(a), C.addressof(c),
+                                           g.ctypes.data), "iugkp_batch_tuning")
+        return a.value, c.value, g

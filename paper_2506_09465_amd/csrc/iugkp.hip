@@ -2205,6 +2205,10 @@ struct iugkp_batch {
   };
   Pool pool, mg_pool;                // plain CG; multigrid-preconditioned CG
   std::vector<int> cg_G, cg_tb;      // per instance: group size, blocks per workgroup | form bit
+  // the multigrid pool's autotuned group sizes: per instance the largest
+  // group, the group of the last replay (0: not run), and the clock rate
+  std::vector<int> mg_gmax, mg_last;
+  double clock_khz = 0.0;
   iugkp::MGArgs *d_mg_args = nullptr;   // the multigrid jobs' arguments, per instance
   DevScalars *d_scs = nullptr;       // every instance's scalars, contiguous
   unsigned int *d_bars = nullptr;    // every instance's CG barrier [2], kBarStride apart
@@ -2267,6 +2271,87 @@ int enqueue_batch_iteration(iugkp_batch *b)
   return IUGKP_OK;
 }
 
+// Autotuned group sizes of the multigrid pool.  One iteration of an instance
+// of n cells on a group of G workgroups is modelled as a + c n / G
+// microseconds (a: the group barriers and the levels every workgroup keeps,
+// c: one finest-level cell on one workgroup); a and c are fitted by least
+// squares to the measured duration of every multigrid job of every replay
+// (the device clock at the job's start and end) and kept for the process,
+// so a later batch starts from them.  Before a replay the groups are chosen
+// for the shortest makespan M the pool can reach: an instance takes the
+// smallest group that finishes its iterations within M, and M grows until
+// the total work fits the pool (at 75% packing); the result of an instance
+// does not depend on its group.
+struct MgModel {
+  double sx = 0, sy = 0, sxx = 0, sxy = 0, n = 0;   // fit sums, x = cells / G, y = us per iteration
+  double a = 40.0, c = 0.02;                       // defaults before any measurement
+  void add(double x, double y)
+  {
+    sx += x;
+    sy += y;
+    sxx += x * x;
+    sxy += x * y;
+    n += 1.0;
+    const double det = n * sxx - sx * sx;
+    if (n >= 3.0 && det > 1e-12 * n * sxx) {
+      const double cf = (n * sxy - sx * sy) / det;
+      const double af = (sy - cf * sx) / n;
+      if (cf > 0.0 && af > 0.0) {
+        a = af;
+        c = cf;
+      }
+    }
+  }
+};
+std::mutex g_mg_model_mu;
+MgModel g_mg_model;                  // the process's fit, shared by every batch
+
+void choose_mg_groups(iugkp_batch *b, const MgModel &mdl)
+{
+  const int n = static_cast<int>(b->insts.size());
+  const double P = static_cast<double>(b->mg_pool.size);
+  struct J {
+    int i;
+    double its, cells;
+    int gmax;
+  };
+  std::vector<J> js;
+  for (int i = 0; i < n; ++i) {
+    const InstHost &ih = b->insts[i];
+    const DevScalars &sc = b->hsc[i];
+    if (!ih.d.newton || ih.mg_L == 0 || sc.state == 2) continue;
+    const double its = sc.iter > 0 ? std::max(sc.cg_iters, 1) : std::min(20, ih.d.cg_max);
+    js.push_back({i, its, static_cast<double>(ih.d.m.n_cells), b->mg_gmax[i]});
+  }
+  if (js.empty()) return;
+  auto t = [&](const J &j, int G) { return mdl.a + mdl.c * j.cells / G; };
+  auto group_for = [&](const J &j, double M) {
+    const double per = M / j.its - mdl.a;
+    if (!(per > 0.0)) return j.gmax;
+    const int g = static_cast<int>(std::ceil(mdl.c * j.cells / per));
+    return std::max(1, std::min(j.gmax, g));
+  };
+  auto work = [&](double M) {
+    double w = 0.0;
+    for (const J &j : js) {
+      const int g = group_for(j, M);
+      w += j.its * g * t(j, g);
+    }
+    return w;
+  };
+  double lo = 0.0;
+  for (const J &j : js) lo = std::max(lo, j.its * t(j, j.gmax));
+  double hi = lo;
+  while (work(hi) > 0.75 * P * hi) hi *= 2.0;
+  if (hi > lo)
+    for (int k = 0; k < 40; ++k) {
+      const double mid = 0.5 * (lo + hi);
+      if (work(mid) > 0.75 * P * mid) lo = mid;
+      else hi = mid;
+    }
+  for (const J &j : js) b->cg_G[j.i] = group_for(j, hi);
+}
+
 // List scheduling of the CG jobs of the instances still iterating onto the
 // pool, longest first: each job takes the G contiguous workgroups that free up
 // earliest (estimated from the previous CG iteration count of the instance, or
@@ -2292,8 +2377,14 @@ int schedule_cg(iugkp_batch *b, bool mg_jobs)
     const bool mg = ih.mg_L > 0;
     const int prior = mg ? 20 : 4 * std::max(ih.d.m.nx, ih.d.m.ny);
     const double its = sc.iter > 0 ? std::max(sc.cg_iters, 1) : std::min(prior, ih.d.cg_max);
-    const double per = mg ? 4.0 * ih.mg_Lg + 2.0 : 1.0;
-    jobs.push_back({its * per * (b->cg_G[i] > 1 ? 3.0 : 1.0), i});
+    double cost;
+    if (mg) {
+      std::lock_guard<std::mutex> lock(g_mg_model_mu);
+      cost = its * (g_mg_model.a + g_mg_model.c * ih.d.m.n_cells / b->cg_G[i]);
+    } else {
+      cost = its * (b->cg_G[i] > 1 ? 3.0 : 1.0) * 4.5;     // (a plain iteration: about 4.5 us)
+    }
+    jobs.push_back({cost, i});
   }
   std::stable_sort(jobs.begin(), jobs.end(), [](const Job &x, const Job &y) { return x.cost > y.cost; });
   std::vector<double> load(P, 0.0);
@@ -2375,6 +2466,8 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
   }
   b->cg_G.assign(n, 0);
   b->cg_tb.assign(n, 0);
+  b->mg_gmax.assign(n, 0);
+  b->mg_last.assign(n, 0);
   if (b->any_newton) {
     // the pools: every workgroup resident at once (occupancy times CUs), so the
     // instance groups' barriers always make progress.  An instance's group:
@@ -2383,9 +2476,11 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
     // beyond one workgroup per CU, the global form on kCgGridMax workgroups;
     // with the multigrid preconditioner at most kCgGridMax workgroups of one
     // wave per 256-cell block of the finest level.
-    int dev = 0, n_cu = 0;
+    int dev = 0, n_cu = 0, khz = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    b->clock_khz = static_cast<double>(khz);
     for (int i = 0; i < n; ++i) {
       const InstHost &ih = b->insts[i];
       if (!ih.d.newton) continue;
@@ -2395,6 +2490,7 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
         const int G = std::max(1, std::min(std::min(cdiv(nbt, iugkp::kMgPoolWaves), kCgGridMax),
                                            n_cu));
         b->cg_G[i] = G;
+        b->mg_gmax[i] = G;
         b->cg_tb[i] = 0;
         b->mg_pool.lds = std::max(b->mg_pool.lds, ih.mg_lds);
         b->mg_pool.max_jobs += G;
@@ -2533,6 +2629,20 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
   return IUGKP_OK;
 }
 
+int iugkp_batch_tuning(iugkp_batch *b, double *per_iter_us, double *per_cell_us, int *groups)
+{
+  if (!b) return fail(IUGKP_E_INVALID_ARG, "batch is NULL");
+  {
+    std::lock_guard<std::mutex> lock(g_mg_model_mu);
+    if (per_iter_us) *per_iter_us = g_mg_model.a;
+    if (per_cell_us) *per_cell_us = g_mg_model.c;
+  }
+  if (groups)
+    for (size_t i = 0; i < b->insts.size(); ++i)
+      groups[i] = b->insts[i].d.newton ? b->cg_G[i] : 0;
+  return IUGKP_OK;
+}
+
 int iugkp_batch_solve(iugkp_batch *b, double *const *T_out, double *const *qx_out,
                       double *const *qy_out, iugkp_stats *stats)
 {
@@ -2564,6 +2674,24 @@ int iugkp_batch_solve(iugkp_batch *b, double *const *T_out, double *const *qx_ou
     HIP_TRY(hipStreamSynchronize(s));
     bool all_done = true;
     for (int i = 0; i < n; ++i) all_done = all_done && (b->hsc[i].state == 2);
+    if (b->mg_pool.used) {
+      std::lock_guard<std::mutex> lock(g_mg_model_mu);
+      for (int i = 0; i < n; ++i) {
+        const DevScalars &sc = b->hsc[i];
+        if (b->mg_last[i] > 0 && sc.cg_t1 > sc.cg_t0 && sc.cg_iters > 0 && b->clock_khz > 0.0) {
+          const double us = static_cast<double>(sc.cg_t1 - sc.cg_t0) * 1e3 / b->clock_khz;
+          g_mg_model.add(static_cast<double>(b->insts[i].d.m.n_cells) / b->mg_last[i],
+                         us / sc.cg_iters);
+        }
+        b->mg_last[i] = 0;
+      }
+      if (!all_done) {
+        choose_mg_groups(b, g_mg_model);
+        for (int i = 0; i < n; ++i)
+          if (b->insts[i].mg_L > 0 && b->insts[i].d.newton && b->hsc[i].state != 2)
+            b->mg_last[i] = b->cg_G[i];
+      }
+    }
     if (all_done) break;
     for (auto *q : {&b->pool, &b->mg_pool}) {
       if (!q->used) continue;

@@ -45,6 +45,7 @@ struct DevScalars {
   int grew;                     // the Newton iteration's growth rule fired this iteration
   int flags;                    // bit 0: non-finite energy, bit 1: fixed-point overflow
   int cg_iters, cg_status, cg_iters_total;
+  unsigned long long cg_t0, cg_t1;   // device wall clock at the multigrid CG's start and end
   unsigned int iter;            // iterations done
   int state;                    // 0 iterating, 1 output iterations, 2 done
   int out_left;                 // output iterations still to run (state 1)

@@ -249,6 +249,7 @@ __device__ __forceinline__ void mgcg_solve(const MGArgs &a, int G, int bid, doub
 {
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gwv = bid * nw + wave, gstride = G * nw;
+  if (bid == 0 && threadIdx.x == 0) a.sc->cg_t0 = static_cast<unsigned long long>(wall_clock64());
   const int L = a.L, Lg = a.Lg;
   const MGLevel *lv = a.lv;
   const MGLevel L0 = lv[0];
@@ -705,6 +706,7 @@ __device__ __forceinline__ void mgcg_solve(const MGArgs &a, int G, int bid, doub
   if (bid == 0 && threadIdx.x == 0) {
     a.sc->cg_iters = it;
     a.sc->cg_status = status;
+    a.sc->cg_t1 = static_cast<unsigned long long>(wall_clock64());
   }
 }
 
