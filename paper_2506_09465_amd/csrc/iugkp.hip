@@ -141,6 +141,9 @@ struct InstHost {
   int mg_L = 0, mg_Lg = 0, mg_grid = 1, mg_threads = 64;
   size_t mg_lds = 0;
   iugkp::MGLevel *mg_lv = nullptr;
+  // its banded form: the second buffers of r and s, the LDS layout
+  int mg_band = 0, mg_stage0 = 0, mg_stage_n = 0;
+  double *mg_r2 = nullptr, *mg_s2 = nullptr;
   // row-stripe particle step for face-tallied iterations (single solves)
   int stripe_R = 0, stripe_S = 0, stripe_C = 0;
   size_t stripe_lds = 0;
@@ -412,7 +415,7 @@ int setup_persistent(InstHost &ih, const std::vector<double> &T0, const std::vec
 // up, down to one cell), the coarse operators built on the device, the
 // vectors of the levels spread over the group, the LDS layout of the small
 // levels, and the group's launch shape.
-int setup_mg(InstHost &ih, const iugkp_options *o, hipStream_t s)
+int setup_mg(InstHost &ih, const iugkp_options *o, hipStream_t s, bool single)
 {
   const Mesh &m = ih.d.m;
   const int has_y = (m.dim == 2) ? 1 : 0;
@@ -437,16 +440,51 @@ int setup_mg(InstHost &ih, const iugkp_options *o, hipStream_t s)
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  const size_t lds_budget = static_cast<size_t>(lds_max) - 8 * 1024;   // static: reductions
+  const size_t lds_budget = static_cast<size_t>(lds_max) - 12 * 1024;  // static: reductions, level table
   auto local_bytes = [&](int from) {
     size_t w = 0;
-    for (int k = from; k < L; ++k) w += 8 * static_cast<size_t>(lv[k].n);
+    for (int k = from; k < L; ++k) w += 6 * static_cast<size_t>(lv[k].n);
     return w * sizeof(double);
   };
   int Lg = 0;
   while (Lg < L && lv[Lg].n > iugkp::kMgLocalMax) ++Lg;
   while (Lg < L - 1 && local_bytes(Lg) > lds_budget) ++Lg;
   if (local_bytes(Lg) > lds_budget) return fail(IUGKP_E_DEVICE, "no LDS for the multigrid");
+  const int waves = o->cg_waves != 0 ? std::abs(o->cg_waves) : kCgWavesDefault;
+  const int nb0 = cdiv(lv[0].n, iugkp::kTree);
+  const int G = std::max(1, std::min(std::min(cdiv(nb0, waves), kCgGridMax), n_cu));
+  // The banded form (2D meshes, or no grid level): LDS for the level Lg
+  // result kept through a band phase, then the LDS levels or the staging of
+  // a band window, whichever is larger.  Its windows for a group of Gp
+  // members (one window per phase when the budget allows; a batch instance's
+  // group changes from replay to replay, so it takes the largest stage), and
+  // the smallest stage with one row (one block) per window.
+  // (the LDS levels' rows, 3 doubles per cell, stay for the whole solve; their
+  // vectors, 3 per cell, share the stage with the band windows)
+  const long long levels_words = static_cast<long long>(local_bytes(Lg) / sizeof(double)) / 2;
+  const long long rows_words = levels_words;
+  auto band_need = [&](int Gp) {
+    long long w = levels_words;
+    for (int k = 0; k < Lg; ++k) {
+      const long long nxk = lv[k].nx;
+      w = std::max(w, (6ll * cdiv(lv[k + 1].ny, Gp) + 10) * nxk);
+      if (k >= 1) w = std::max(w, (3ll * cdiv(lv[k].ny, Gp) + 8) * nxk);
+    }
+    if (Lg >= 1) {
+      const long long nx0 = lv[0].nx;
+      const long long rmax = 2 + (static_cast<long long>(iugkp::kTree) * cdiv(nb0, Gp) - 1 + nx0 - 1) / nx0;
+      w = std::max(w, (3 * rmax + 14) * nx0);
+    }
+    return w;
+  };
+  const long long e_words = (Lg >= 1) ? lv[Lg].n : 0;
+  const long long band_budget =
+      static_cast<long long>(lds_budget / sizeof(double)) - e_words - rows_words;
+  const bool band = (Lg == 0 || has_y) && 64 * waves <= iugkp::kMgBandThreads &&
+                    band_need(1 << 20) <= band_budget;
+  const int stage0 = band ? static_cast<int>(e_words + rows_words) : 0;
+  const long long stage_n =
+      band ? std::min(band_budget, band_need(single ? G : 1)) : 0;
 #define ALLOC(ptr, cnt) \
   do { if (ih.alloc(&(ptr), (cnt)) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed"); } while (0)
   lv[0].gx = ih.gx;
@@ -462,6 +500,11 @@ int setup_mg(InstHost &ih, const iugkp_options *o, hipStream_t s)
     lv[k].diag = dg;
   }
   ALLOC(lv[0].b, lv[0].n);                 // r, read by the whole group
+  if (band) {
+    ALLOC(ih.mg_r2, lv[0].n);
+    ALLOC(ih.mg_s2, lv[0].n);
+    if (Lg == 0) ALLOC(lv[0].e, lv[0].n);  // u, read by its owner in the next update
+  }
   for (int k = 0; k < Lg; ++k) {
     if (k > 0) ALLOC(lv[k].b, lv[k].n);
     ALLOC(lv[k].xa, lv[k].n);
@@ -470,13 +513,21 @@ int setup_mg(InstHost &ih, const iugkp_options *o, hipStream_t s)
     ALLOC(lv[k].e, lv[k].n);
   }
   if (Lg > 0) ALLOC(lv[Lg].b, lv[Lg].n);
-  int off = 0;
+  // LDS offsets: banded, [E][rows of every LDS level][vectors | staging];
+  // otherwise each level's vectors and rows together
+  int off = stage0, roff = static_cast<int>(e_words);
   for (int k = Lg; k < L; ++k) {
     lv[k].lb = off;
     lv[k].lx = off + lv[k].n;
     lv[k].lt = off + 2 * lv[k].n;
-    lv[k].lc = off + 3 * lv[k].n;
-    off += 8 * lv[k].n;
+    off += 3 * lv[k].n;
+    if (band) {
+      lv[k].lc = roff;
+      roff += 3 * lv[k].n;
+    } else {
+      lv[k].lc = off;
+      off += 3 * lv[k].n;
+    }
   }
   for (int k = 0; k + 1 < L; ++k) {
     const int nf = std::max(lv[k + 1].ny * (lv[k + 1].nx + 1), (lv[k + 1].ny + 1) * lv[k + 1].nx);
@@ -491,17 +542,21 @@ int setup_mg(InstHost &ih, const iugkp_options *o, hipStream_t s)
 #undef ALLOC
   HIP_TRY(hipMemcpyAsync(ih.mg_lv, lv.data(), L * sizeof(iugkp::MGLevel), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  const int waves = o->cg_waves != 0 ? std::abs(o->cg_waves) : kCgWavesDefault;
-  const int nb0 = cdiv(lv[0].n, iugkp::kTree);
-  const int G = std::max(1, std::min(std::min(cdiv(nb0, waves), kCgGridMax), n_cu));
-  const size_t lds = static_cast<size_t>(off) * sizeof(double);
+  const size_t lds = band ? static_cast<size_t>(stage0 + stage_n) * sizeof(double)
+                          : static_cast<size_t>(off) * sizeof(double);
   int per_cu = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void *>(iugkp::mgcg_kernel), 64 * waves, lds));
+      &per_cu,
+      band ? reinterpret_cast<const void *>(iugkp::mgcg_band_kernel)
+           : reinterpret_cast<const void *>(iugkp::mgcg_kernel),
+      64 * waves, lds));
   if (per_cu < 1 || G > per_cu * n_cu)
     return fail(IUGKP_E_DEVICE, "multigrid CG workgroups cannot all be resident");
   ih.mg_L = L;
   ih.mg_Lg = Lg;
+  ih.mg_band = band ? 1 : 0;
+  ih.mg_stage0 = stage0;
+  ih.mg_stage_n = static_cast<int>(stage_n);
   ih.cg_cus = static_cast<double>(G) / per_cu;
   ih.mg_grid = G;
   ih.mg_threads = 64 * waves;
@@ -715,10 +770,10 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
       ih.cg_threads = cp.threads;
       ih.cg_lds = cp.lds;
       ih.cg_cus = static_cast<double>(cp.grid) / cp.per_cu;
-      if (o->cg_precond == IUGKP_PRECOND_MG && (rc = setup_mg(ih, o, s))) return rc;
+      if (o->cg_precond == IUGKP_PRECOND_MG && (rc = setup_mg(ih, o, s, true))) return rc;
     } else if (o->cg_precond == IUGKP_PRECOND_MG) {
       // batched: the hierarchy only; one workgroup runs the instance's solve
-      if ((rc = setup_mg(ih, o, s))) return rc;
+      if ((rc = setup_mg(ih, o, s, false))) return rc;
     }
   }
   // (expected-value rays: only on request, march == 2; every stripe follows a
@@ -1268,11 +1323,17 @@ int enqueue_cg(const InstHost &ih, const double *b, double *x, DevScalars *sc, h
     ma.max_iters = ih.d.cg_max;
     ma.barrier = ih.cg_barrier;
     ma.sc = sc;
+    ma.r2 = ih.mg_r2;
+    ma.s2 = ih.mg_s2;
+    ma.band = ih.mg_band;
+    ma.stage0 = ih.mg_stage0;
+    ma.stage_n = ih.mg_stage_n;
     iugkp::zero_u32_kernel<<<1, 64, 0, s>>>(ih.cg_barrier, 2);
     if (ev_a) HIP_TRY(hipEventRecord(ev_a, s));
     void *args[] = {&ma};
-    HIP_TRY(hipLaunchKernel(reinterpret_cast<const void *>(iugkp::mgcg_kernel), dim3(ih.mg_grid),
-                            dim3(ih.mg_threads), args, ih.mg_lds, s));
+    HIP_TRY(hipLaunchKernel(ih.mg_band ? reinterpret_cast<const void *>(iugkp::mgcg_band_kernel)
+                                       : reinterpret_cast<const void *>(iugkp::mgcg_kernel),
+                            dim3(ih.mg_grid), dim3(ih.mg_threads), args, ih.mg_lds, s));
     if (ev_b) HIP_TRY(hipEventRecord(ev_b, s));
     return IUGKP_OK;
   }
@@ -2592,6 +2653,11 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
       ma.max_iters = ih.d.cg_max;
       ma.barrier = ih.d.cg_barrier;
       ma.sc = ih.d.sc;
+      ma.r2 = ih.mg_r2;
+      ma.s2 = ih.mg_s2;
+      ma.band = ih.mg_band;
+      ma.stage0 = ih.mg_stage0;
+      ma.stage_n = ih.mg_stage_n;
     }
     if (any_mg) {
       if (hipMalloc(reinterpret_cast<void **>(&b->d_mg_args), n * sizeof(iugkp::MGArgs)) !=

@@ -46,7 +46,7 @@ struct MGLevel {
   const double *gx, *gy, *diag;         // operator of the level
   double *b, *xa, *xb, *xd, *e;         // grid levels (level 0: b = r, e = u)
   int lb, lx, lt, lc;                   // LDS levels: offsets (doubles) of b, x, t and
-                                        // of the rows (5 doubles per cell)
+                                        // of the rows (3 doubles per cell)
 };
 
 struct MGArgs {
@@ -59,6 +59,11 @@ struct MGArgs {
   int max_iters;
   unsigned int *barrier;                // [2], zero at the start of the solve
   DevScalars *sc;
+  // the banded form (mgband.hpp): second buffers of r and s, and the dynamic
+  // LDS layout, [stage0) the coarse result kept across a band phase, then
+  // stage_n doubles holding the LDS levels or a band window's staging
+  double *r2, *s2;
+  int band, stage0, stage_n;
 };
 
 // Row c of A_k: the diagonal, the four face conductances and the neighbour
@@ -105,17 +110,21 @@ __device__ __forceinline__ MGRow mg_row(const MGLevel &l, int c)
   return mg_row_at(l, c - iy * l.nx, iy);
 }
 
-// the same row of an LDS level, whose coefficients sit in LDS
+// the same row of an LDS level, whose coefficients sit in LDS as three per
+// cell: the diagonal and the right and upper faces (a cell's left face is
+// its left neighbour's right face, its lower face the one below's upper face;
+// an absent neighbour's face is read at the cell itself and never used)
 __device__ __forceinline__ MGRow mg_row_lds_at(const MGLevel &l, const double *lds, int ix, int iy)
 {
   MGRow r;
   mg_row_index(r, l.nx, l.ny, ix, iy);
-  const double *k = lds + l.lc + 5 * (iy * l.nx + ix);
-  r.dg = k[0];
-  r.gl = k[1];
-  r.gr = k[2];
-  r.gd = k[3];
-  r.gu = k[4];
+  const double *k = lds + l.lc;
+  const int c = iy * l.nx + ix;
+  r.dg = k[3 * c];
+  r.gr = k[3 * c + 1];
+  r.gu = k[3 * c + 2];
+  r.gl = k[3 * r.jl + 1];
+  r.gd = k[3 * r.jd + 2];
   return r;
 }
 
@@ -201,16 +210,16 @@ __device__ __forceinline__ void group_tree_n(const double *part, int nb, double 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int nch = (nb + kTree - 1) / kTree;
   auto chunk = [&](int k, double (&r)[NV]) {
+    // (every load issued before the first tree)
+    double v[NV][4];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      double v[4];
+    for (int q = 0; q < 4; ++q) {
+      const int i = k * kTree + lane + 64 * q;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = k * kTree + lane + 64 * q;
-        v[q] = i < nb ? mld<SC>(&part[NV * i + j]) : 0.0;
-      }
-      r[j] = wave_tree256(v[0], v[1], v[2], v[3]);
+      for (int j = 0; j < NV; ++j) v[j][q] = i < nb ? mld<SC>(&part[NV * i + j]) : 0.0;
     }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) r[j] = wave_tree256(v[j][0], v[j][1], v[j][2], v[j][3]);
   };
   if (nch == 1) {
     double r[NV];
@@ -240,18 +249,210 @@ __device__ __forceinline__ void group_tree_n(const double *part, int nb, double 
   __syncthreads();
 }
 
+// the first damped Jacobi sweep, from zero: 0 + (omega b) / diag
+__device__ __forceinline__ double mg_sweep_first(double bv, double dg)
+{
+  return 0.0 + (kMgOmega * bv) / dg;
+}
+struct MgV2 {
+  double a, b;
+};
+
+// The level table copied into LDS (read from global memory at every pass, a
+// descriptor cost a memory round trip before the pass could load its data).
+// Ends with a workgroup barrier; the one before it waits for a previous solve
+// of this workgroup to be done with the table.
+__device__ __forceinline__ void mg_stage_levels(const MGLevel *src, int L, MGLevel *dst)
+{
+  constexpr int kW = static_cast<int>(sizeof(MGLevel) / sizeof(int));
+  static_assert(sizeof(MGLevel) % sizeof(int) == 0, "level descriptors are whole words");
+  __syncthreads();
+  const int *from = reinterpret_cast<const int *>(src);
+  int *to = reinterpret_cast<int *>(dst);
+  for (int i = threadIdx.x; i < L * kW; i += blockDim.x) to[i] = from[i];
+  __syncthreads();
+}
+
+// The cells i = tid, tid + nt, ... of [0, N), Q per thread at a time: the Q
+// loads first (an index past the end replaced by the first), then the Q
+// finishes, so that a thread's loads are in flight together.
+template <int Q, class Ld, class Fin>
+__device__ __forceinline__ void mg_cells(int N, Ld load, Fin finish)
+{
+  const int nt = static_cast<int>(blockDim.x);
+  for (int i0 = static_cast<int>(threadIdx.x); i0 < N; i0 += Q * nt) {
+    using V = decltype(load(0));
+    V v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int i = i0 + q * nt;
+      v[q] = load(i < N ? i : i0);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int i = i0 + q * nt;
+      if (i < N) finish(i, v[q]);
+    }
+  }
+}
+
+// the five row coefficients of every cell of the LDS levels (no barrier)
+__device__ __forceinline__ void mg_lds_rows(const MGLevel *lv, int Lg, int L, double *lds)
+{
+  for (int k = Lg; k < L; ++k) {
+    const MGLevel F = lv[k];
+    mg_cells<4>(
+        F.n, [&](int i) { return mg_row(F, i); },
+        [&](int i, const MGRow &r) {
+          double *dst = lds + F.lc + 3 * i;
+          dst[0] = r.dg;
+          dst[1] = r.gr;
+          dst[2] = r.gu;
+        });
+  }
+}
+
+// The V-cycle of the LDS levels Lg..L-1, run by every workgroup on its own
+// copy: b of level Lg from global memory (b_global) or already in LDS; its
+// result ends in level Lg's t vector.  Descent: b loaded with the first
+// sweep; per level the second sweep, then the restriction with the next
+// level's first sweep (the one-cell level: its exact solve).  Ascent: the
+// correction fused into the first post-sweep (the neighbours' corrected
+// values recomputed), the second post-sweep.  Each level's result ends in its
+// t vector.
+template <int SC>
+__device__ __forceinline__ void mg_lds_cycle(const MGLevel *lv, int Lg, int L, double *lds,
+                                             bool b_global)
+{
+  // an LDS level, two cells per thread at a time (computed, then stored),
+  // then a workgroup barrier
+  auto for_local = [&](int nl, auto compute, auto store) {
+    const int bd = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < nl; i0 += 2 * bd) {
+      const int i1 = i0 + bd;
+      const auto v0 = compute(i0);
+      const auto v1 = compute(i1 < nl ? i1 : i0);
+      store(i0, v0);
+      if (i1 < nl) store(i1, v1);
+    }
+    __syncthreads();
+  };
+  // a level of at most one cell per lane, run by wavefront 0 alone: its LDS
+  // operations execute in order, so a pass needs no workgroup barrier
+  auto for_wave = [&](int nl, auto compute, auto store) {
+    const int i = static_cast<int>(threadIdx.x);
+    const auto v = compute(i < nl ? i : 0);
+    if (i < nl) store(i, v);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  const MGLevel T = lv[Lg];
+  for_local(
+      T.n,
+      [&](int i) {
+        const double bv = b_global ? mld<SC>(&T.b[i]) : lds[T.lb + i];
+        return MgV2{bv, mg_sweep_first(bv, lds[T.lc + 3 * i])};
+      },
+      [&](int i, MgV2 v) {
+        lds[T.lb + i] = v.a;
+        if (L - 1 > Lg) lds[T.lx + i] = v.b;
+        else lds[T.lt + i] = v.a / lds[T.lc + 3 * i];
+      });
+  // descent step at level k (second sweep, restriction with the next
+  // level's first sweep) and ascent step (corrected first post-sweep,
+  // second post-sweep), with `run` one of the two pass forms
+  auto down = [&](int k, auto run) {
+    const MGLevel F = lv[k], Cl = lv[k + 1];
+    const double *B = lds + F.lb, *X = lds + F.lx;
+    double *Tm = lds + F.lt;
+    run(
+        F.n,
+        [&](int i) {
+          const MGRow r = mg_row_lds(F, lds, i);
+          const double t = B[i] - mg_apply_row(r, i, [&](int j) { return X[j]; });
+          return X[i] + (kMgOmega * t) / r.dg;
+        },
+        [&](int i, double v) { Tm[i] = v; });
+    const bool last = (k + 1 == L - 1);
+    run(
+        Cl.n,
+        [&](int C) {
+          const int J = C / Cl.nx, I = C - J * Cl.nx;
+          double q[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int ix = 2 * I + (k & 1), iy = 2 * J + (k >> 1);
+            const bool in = (ix < F.nx && iy < F.ny);
+            const int cx = in ? ix : 2 * I, cy = in ? iy : 2 * J;
+            const int f = cy * F.nx + cx;
+            const MGRow r = mg_row_lds_at(F, lds, cx, cy);
+            const double res = B[f] - mg_apply_row(r, f, [&](int j) { return Tm[j]; });
+            q[k] = in ? res : 0.0;
+          }
+          return (q[0] + q[1]) + (q[2] + q[3]);
+        },
+        [&](int C, double v) {
+          lds[Cl.lb + C] = v;
+          const double dg = lds[Cl.lc + 3 * C];
+          if (last) lds[Cl.lt + C] = v / dg;
+          else lds[Cl.lx + C] = mg_sweep_first(v, dg);
+        });
+  };
+  auto up = [&](int k, auto run) {
+    const MGLevel F = lv[k], Cl = lv[k + 1];
+    const double *B = lds + F.lb, *E = lds + Cl.lt;
+    double *X = lds + F.lx, *Tm = lds + F.lt;
+    run(
+        F.n,
+        [&](int i) {
+          const MGRow r = mg_row_lds(F, lds, i);
+          int pc[5];
+          mg_parents(r, Cl.nx, pc);
+          const int js[5] = {i, r.jl, r.jr, r.jd, r.ju};
+          double xc5[5];
+#pragma unroll
+          for (int q = 0; q < 5; ++q) xc5[q] = Tm[js[q]] + kMgScale * E[pc[q]];
+          const double t = B[i] - mg_apply_vals(r, xc5);
+          return xc5[0] + (kMgOmega * t) / r.dg;
+        },
+        [&](int i, double v) { X[i] = v; });
+    run(
+        F.n,
+        [&](int i) {
+          const MGRow r = mg_row_lds(F, lds, i);
+          const double t = B[i] - mg_apply_row(r, i, [&](int j) { return X[j]; });
+          return X[i] + (kMgOmega * t) / r.dg;
+        },
+        [&](int i, double v) { Tm[i] = v; });
+  };
+  // the levels of at most 64 cells (from ks on) by wavefront 0 alone
+  int ks = Lg;
+  while (ks < L - 1 && lv[ks].n > 64) ++ks;
+  for (int k = Lg; k < ks; ++k) down(k, for_local);
+  if (ks < L - 1) {
+    if (threadIdx.x < 64) {
+      for (int k = ks; k < L - 1; ++k) down(k, for_wave);
+      for (int k = L - 2; k >= ks; --k) up(k, for_wave);
+    }
+    __syncthreads();
+  }
+  for (int k = ks - 1; k >= Lg; --k) up(k, for_local);
+}
+
 // The preconditioned CG of one system, run by the G workgroups of a group of
 // which this one is number bid (G = 1: one workgroup alone, its exchanges
 // through workgroup-scope memory operations and workgroup barriers).
 template <int SC>
 __device__ __forceinline__ void mgcg_solve(const MGArgs &a, int G, int bid, double *lds,
-                                           double *red)
+                                           double *red, MGLevel *s_lv)
 {
   const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gwv = bid * nw + wave, gstride = G * nw;
   if (bid == 0 && threadIdx.x == 0) a.sc->cg_t0 = static_cast<unsigned long long>(wall_clock64());
   const int L = a.L, Lg = a.Lg;
-  const MGLevel *lv = a.lv;
+  mg_stage_levels(a.lv, L, s_lv);
+  const MGLevel *lv = s_lv;
   const MGLevel L0 = lv[0];
   const int n = L0.n, nb = (n + kTree - 1) / kTree;
   unsigned int epoch = 0;
@@ -317,47 +518,11 @@ __device__ __forceinline__ void mgcg_solve(const MGArgs &a, int G, int bid, doub
     if (decltype(Qmax)::value > 1 && nl > nthr) run(std::integral_constant<int, 2>{});
     else run(std::integral_constant<int, 1>{});
   };
-  // an LDS level, two cells per thread at a time (computed, then stored),
-  // then a workgroup barrier
-  auto for_local = [&](int nl, auto compute, auto store) {
-    const int bd = blockDim.x;
-    for (int i0 = threadIdx.x; i0 < nl; i0 += 2 * bd) {
-      const int i1 = i0 + bd;
-      const auto v0 = compute(i0);
-      const auto v1 = compute(i1 < nl ? i1 : i0);
-      store(i0, v0);
-      if (i1 < nl) store(i1, v1);
-    }
-    __syncthreads();
-  };
-  // a level of at most one cell per lane, run by wavefront 0 alone: its LDS
-  // operations execute in order, so a pass needs no workgroup barrier
-  auto for_wave = [&](int nl, auto compute, auto store) {
-    const int i = static_cast<int>(threadIdx.x);
-    const auto v = compute(i < nl ? i : 0);
-    if (i < nl) store(i, v);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  };
-  auto sweep_first = [&](double bv, double dg) { return 0.0 + (kMgOmega * bv) / dg; };
-  struct V2 {
-    double a, b;
-  };
+  auto sweep_first = [&](double bv, double dg) { return mg_sweep_first(bv, dg); };
+  using V2 = MgV2;
 
   // rows of the LDS levels, once per solve
-  for (int k = Lg; k < L; ++k) {
-    const MGLevel F = lv[k];
-    for (int i = threadIdx.x; i < F.n; i += blockDim.x) {
-      const MGRow r = mg_row(F, i);
-      double *dst = lds + F.lc + 5 * i;
-      dst[0] = r.dg;
-      dst[1] = r.gl;
-      dst[2] = r.gr;
-      dst[3] = r.gd;
-      dst[4] = r.gu;
-    }
-  }
+  mg_lds_rows(lv, Lg, L, lds);
   __syncthreads();
 
   // the V-cycle on r (published as lv[0].b, and lv[0].xa = the first sweep
@@ -415,105 +580,8 @@ __device__ __forceinline__ void mgcg_solve(const MGArgs &a, int G, int bid, doub
           });
       if (!bar()) return false;
     }
-    // the LDS levels, in every workgroup.  Descent: b of level Lg loaded
-    // with its first sweep; per level the second sweep, then the restriction
-    // with the next level's first sweep (the one-cell level: its exact
-    // solve).  Ascent: the correction fused into the first post-sweep (the
-    // neighbours' corrected values recomputed), the second post-sweep.  Each
-    // level's result ends in its t vector.
-    {
-      const MGLevel T = lv[Lg];
-      for_local(
-          T.n,
-          [&](int i) {
-            const double bv = mld<SC>(&T.b[i]);
-            return V2{bv, sweep_first(bv, lds[T.lc + 5 * i])};
-          },
-          [&](int i, V2 v) {
-            lds[T.lb + i] = v.a;
-            if (L - 1 > Lg) lds[T.lx + i] = v.b;
-            else lds[T.lt + i] = v.a / lds[T.lc + 5 * i];
-          });
-      // descent step at level k (second sweep, restriction with the next
-      // level's first sweep) and ascent step (corrected first post-sweep,
-      // second post-sweep), with `run` one of the two pass forms
-      auto down = [&](int k, auto run) {
-        const MGLevel F = lv[k], Cl = lv[k + 1];
-        const double *B = lds + F.lb, *X = lds + F.lx;
-        double *Tm = lds + F.lt;
-        run(
-            F.n,
-            [&](int i) {
-              const MGRow r = mg_row_lds(F, lds, i);
-              const double t = B[i] - mg_apply_row(r, i, [&](int j) { return X[j]; });
-              return X[i] + (kMgOmega * t) / r.dg;
-            },
-            [&](int i, double v) { Tm[i] = v; });
-        const bool last = (k + 1 == L - 1);
-        run(
-            Cl.n,
-            [&](int C) {
-              const int J = C / Cl.nx, I = C - J * Cl.nx;
-              double q[4];
-#pragma unroll
-              for (int k = 0; k < 4; ++k) {
-                const int ix = 2 * I + (k & 1), iy = 2 * J + (k >> 1);
-                const bool in = (ix < F.nx && iy < F.ny);
-                const int cx = in ? ix : 2 * I, cy = in ? iy : 2 * J;
-                const int f = cy * F.nx + cx;
-                const MGRow r = mg_row_lds_at(F, lds, cx, cy);
-                const double res = B[f] - mg_apply_row(r, f, [&](int j) { return Tm[j]; });
-                q[k] = in ? res : 0.0;
-              }
-              return (q[0] + q[1]) + (q[2] + q[3]);
-            },
-            [&](int C, double v) {
-              lds[Cl.lb + C] = v;
-              const double dg = lds[Cl.lc + 5 * C];
-              if (last) lds[Cl.lt + C] = v / dg;
-              else lds[Cl.lx + C] = sweep_first(v, dg);
-            });
-      };
-      auto up = [&](int k, auto run) {
-        const MGLevel F = lv[k], Cl = lv[k + 1];
-        const double *B = lds + F.lb, *E = lds + Cl.lt;
-        double *X = lds + F.lx, *Tm = lds + F.lt;
-        run(
-            F.n,
-            [&](int i) {
-              const MGRow r = mg_row_lds(F, lds, i);
-              int pc[5];
-              mg_parents(r, Cl.nx, pc);
-              const int js[5] = {i, r.jl, r.jr, r.jd, r.ju};
-              double xc5[5];
-#pragma unroll
-              for (int q = 0; q < 5; ++q) xc5[q] = Tm[js[q]] + kMgScale * E[pc[q]];
-              const double t = B[i] - mg_apply_vals(r, xc5);
-              return xc5[0] + (kMgOmega * t) / r.dg;
-            },
-            [&](int i, double v) { X[i] = v; });
-        run(
-            F.n,
-            [&](int i) {
-              const MGRow r = mg_row_lds(F, lds, i);
-              const double t = B[i] - mg_apply_row(r, i, [&](int j) { return X[j]; });
-              return X[i] + (kMgOmega * t) / r.dg;
-            },
-            [&](int i, double v) { Tm[i] = v; });
-      };
-      // the levels of at most 64 cells (from ks on) by wavefront 0 alone
-      int ks = Lg;
-      while (ks < L - 1 && lv[ks].n > 64) ++ks;
-      for (int k = Lg; k < ks; ++k) down(k, for_local);
-      if (ks < L - 1) {
-        if (threadIdx.x < 64) {
-          for (int k = ks; k < L - 1; ++k) down(k, for_wave);
-          for (int k = L - 2; k >= ks; --k) up(k, for_wave);
-        }
-        __syncthreads();
-      }
-      for (int k = ks - 1; k >= Lg; --k) up(k, for_local);
-    }
+    // the LDS levels, in every workgroup
+    mg_lds_cycle<SC>(lv, Lg, L, lds, true);
     // Ascent.  The last sweep of a grid level whose finer level has at most
     // one cell per thread is not stored: that finer level's first post-sweep
     // recomputes it at the (at most three) aggregates its cell and neighbours
@@ -710,12 +778,32 @@ __device__ __forceinline__ void mgcg_solve(const MGArgs &a, int G, int bid, doub
   }
 }
 
+}  // namespace iugkp
+
+#include "mgband.hpp"
+
+namespace iugkp {
+
 __global__ __launch_bounds__(kCgThreadsMax) void mgcg_kernel(MGArgs a)
 {
   extern __shared__ double lds[];
   __shared__ double red[3 * kTree];
+  __shared__ MGLevel s_lv[kMgLevelsMax];
   mgcg_solve<__HIP_MEMORY_SCOPE_AGENT>(a, static_cast<int>(gridDim.x),
-                                       static_cast<int>(blockIdx.x), lds, red);
+                                       static_cast<int>(blockIdx.x), lds, red, s_lv);
+}
+
+// the banded form (mgband.hpp), for the meshes whose rows fit its windows;
+// workgroups of at most kMgBandThreads threads, whose lanes then have the
+// registers its batched loads take
+constexpr int kMgBandThreads = 512;
+__global__ __launch_bounds__(kMgBandThreads) void mgcg_band_kernel(MGArgs a)
+{
+  extern __shared__ double lds[];
+  __shared__ double red[3 * kTree];
+  __shared__ MGLevel s_lv[kMgLevelsMax];
+  mgcg_band_solve<__HIP_MEMORY_SCOPE_AGENT>(a, static_cast<int>(gridDim.x),
+                                            static_cast<int>(blockIdx.x), lds, red, s_lv);
 }
 
 // ---------------------------------------------------------------------------
@@ -777,10 +865,13 @@ __global__ __launch_bounds__(64 * kMgPoolWaves) void mgcg_batch_kernel(const int
 {
   extern __shared__ double lds[];
   __shared__ double red[3 * kTree];
+  __shared__ MGLevel s_lv[kMgLevelsMax];
   const int e0 = off[blockIdx.x], e1 = off[blockIdx.x + 1];
   for (int e = e0; e < e1; ++e) {
     const CgJob jb = jobs[e];
-    mgcg_solve<__HIP_MEMORY_SCOPE_AGENT>(mg[jb.inst], jb.G, jb.rank, lds, red);
+    const MGArgs &a = mg[jb.inst];
+    if (a.band) mgcg_band_solve<__HIP_MEMORY_SCOPE_AGENT>(a, jb.G, jb.rank, lds, red, s_lv);
+    else mgcg_solve<__HIP_MEMORY_SCOPE_AGENT>(a, jb.G, jb.rank, lds, red, s_lv);
     __syncthreads();
   }
 }
