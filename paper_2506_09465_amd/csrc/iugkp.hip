@@ -792,7 +792,8 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const long long words = lds_max / 8 - 16;
+    // (less the static LDS: the march's segment table, 8.3 KB)
+    const long long words = lds_max / 8 - 1100;
     const long long per_row = static_cast<long long>(m.nx) * (ev ? (d.has_null ? 3 : 2) : 1);
     const long long fixed = m.nx + (d.lds_walls ? m.n_b : 0);
     int R = static_cast<int>((words - fixed) / per_row);
@@ -810,14 +811,58 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
       // 64-byte record (80 with null collisions) and a 4-byte row range per
       // particle; without the memory, or beyond 65534 rows or 65535
       // columns, tiles are used)
+      // The records are binned by start stripe and pre-pass block (sub-bin k
+      // of stripe t: the particles that start in t among those of pre-pass
+      // blocks k, k + K, ...; counted here exactly): beyond kStripeBinMax / 2
+      // stripes or 2^32 particles, tiles are used.
       bool recs = true;
-      if (!ev && (m.ny > 0xfffe || m.nx > 0xffff)) recs = false;   // (16-bit rows, columns)
+      const size_t np = static_cast<size_t>(m.n_emit) * static_cast<size_t>(d.N);
+      if (!ev && (m.ny > 0xfffe || m.nx > 0xffff || 2 * S > iugkp::kStripeBinMax ||
+                  np > 0xffffffffull))
+        recs = false;   // (16-bit rows and columns, 32-bit slots)
       else if (!ev) {
-        const size_t np = static_cast<size_t>(m.n_emit) * static_cast<size_t>(d.N);
         const size_t rb = d.has_null ? sizeof(iugkp::PRecN) : sizeof(iugkp::PRec);
+        const int K = std::max(1, std::min(32, iugkp::kStripeSegMax / (S + 1)));
+        const long long per_block = static_cast<long long>(iugkp::kPresampleBlock) * iugkp::kPresamplePer;
+        const long long nblk = (static_cast<long long>(np) + per_block - 1) / per_block;
+        const long long ne = m.n_emit, nc = m.n_cells;
+        // emitters of stripe t in [e0, e1): its rows' cells and left and right
+        // wall faces, the bottom wall (first stripe), the top wall (last)
+        auto in_stripe = [&](int t, long long e0, long long e1) {
+          const long long y0 = static_cast<long long>(t) * R, y1 = std::min<long long>(m.ny, y0 + R);
+          auto ov = [&](long long a, long long b) {
+            return std::max(0ll, std::min(b, e1) - std::max(a, e0));
+          };
+          long long c = ov(y0 * m.nx, y1 * m.nx) + ov(nc + y0, nc + y1) + ov(nc + m.ny + y0, nc + m.ny + y1);
+          if (t == 0) c += ov(nc + 2ll * m.ny, nc + 2ll * m.ny + m.nx);
+          if (t == S - 1) c += ov(nc + 2ll * m.ny + m.nx, nc + 2ll * m.ny + 2ll * m.nx);
+          return c;
+        };
+        std::vector<unsigned long long> cap(static_cast<size_t>(S) * K, 0);
+        for (long long b = 0; b < nblk; ++b) {
+          const long long p0 = b * per_block, p1 = std::min<long long>(p0 + per_block, np);
+          for (long long p = p0; p < p1;) {
+            const long long kk = p / ne, e0 = p - kk * ne;
+            const long long e1 = std::min(ne, e0 + (p1 - p));
+            for (int t = 0; t < S; ++t) cap[static_cast<size_t>(t) * K + (b % K)] += in_stripe(t, e0, e1);
+            p += e1 - e0;
+          }
+        }
+        std::vector<uint32_t> base(static_cast<size_t>(S) * K + 1, 0);
+        for (size_t i = 0; i < cap.size(); ++i) base[i + 1] = base[i] + static_cast<uint32_t>(cap[i]);
         unsigned char *r = nullptr;
-        recs = ih.alloc(&r, np * rb) == hipSuccess && ih.alloc(&ih.rec.key, np) == hipSuccess;
+        uint32_t *db = nullptr;
+        recs = ih.alloc(&r, np * rb) == hipSuccess && ih.alloc(&ih.rec.key, np) == hipSuccess &&
+               ih.alloc(&ih.rec.cnt, 2 * cap.size()) == hipSuccess &&
+               ih.alloc(&db, base.size()) == hipSuccess;
+        if (recs && base.back() != np) return fail(IUGKP_E_DEVICE, "stripe bins do not cover the particles");
+        if (recs) HIP_TRY(hipMemcpyAsync(db, base.data(), base.size() * sizeof(uint32_t),
+                                         hipMemcpyHostToDevice, s));
         ih.rec.r = r;
+        ih.rec.base = db;
+        ih.rec.R = R;
+        ih.rec.S = S;
+        ih.rec.K = K;
         if (!recs) (void)hipGetLastError();
       }
       if (per_cu >= 1 && recs) {
@@ -1405,12 +1450,17 @@ int enqueue_iteration(iugkp_handle *h, int faces)
   } else if (faces && ih.stripe_R > 0) {
     const unsigned long long np =
         static_cast<unsigned long long>(m.n_emit) * static_cast<unsigned long long>(ih.d.N);
-    const unsigned int pg = static_cast<unsigned int>((np + 255) / 256);
+    constexpr unsigned int per_block = iugkp::kPresampleBlock * iugkp::kPresamplePer;
+    const unsigned int pg = static_cast<unsigned int>((np + per_block - 1) / per_block);
     const dim3 sg(ih.stripe_C, ih.stripe_S);
+    const int ncnt = 2 * ih.rec.S * ih.rec.K;
+    iugkp::zero_u32_kernel<<<cdiv(ncnt, 256), 256, 0, s>>>(ih.rec.cnt, ncnt);
     if (ih.d.has_null)
-      iugkp::stripe_presample_kernel<256, true><<<pg, 256, 0, s>>>(h->d_inst, ih.rec);
+      iugkp::stripe_presample_kernel<iugkp::kPresampleBlock, true>
+          <<<pg, iugkp::kPresampleBlock, 0, s>>>(h->d_inst, ih.rec);
     else
-      iugkp::stripe_presample_kernel<256, false><<<pg, 256, 0, s>>>(h->d_inst, ih.rec);
+      iugkp::stripe_presample_kernel<iugkp::kPresampleBlock, false>
+          <<<pg, iugkp::kPresampleBlock, 0, s>>>(h->d_inst, ih.rec);
     iugkp::march_stripes_kernel<kStripeBlock>
         <<<sg, kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
     HIP_TRY(hipGetLastError());

@@ -819,34 +819,48 @@ __device__ __forceinline__ int faces_upto_near(int cnt, int k0, int st, int jmax
 // one segment at a time.
 // ---------------------------------------------------------------------------
 // Every particle's start and first segment, sampled once per iteration for
-// all row stripes, one record per particle indexed by its place in the
-// enumeration, emitters fastest (the lanes of a stripe wavefront drift apart
-// in that order, so a particle's fields share one cache line): weight (0: no
-// particle), start point and direction, start and end cells (16-bit columns
-// and rows), the wall face that absorbs the segment or -1, the y faces and
-// all faces it crosses; with null collisions also the free path and the
-// acceptance draw.  64 bytes, or 80 with null collisions.
+// all row stripes: weight, start point and direction, start and end cells
+// (16-bit columns and rows), the wall face that absorbs the segment or -1,
+// the y faces and all faces it crosses, and the particle's place in the
+// enumeration (its random-number counters); with null collisions also the
+// free path and the acceptance draw.  64 bytes, or 80 with null collisions.
+// The records are binned by start stripe and direction of travel: start
+// stripe t owns K sub-bins of slots, sub-bin k for the particles that pre-pass
+// blocks k, k + K, ... sample (the host counts them exactly), each filled from
+// the front by the particles whose rows stay inside the stripe and from the
+// back by those that leave it.  A stripe reads the particles that start in it
+// without a check, and only the other stripes' leavers against its rows.  A
+// block claims its slots of a bin with one atomic; the K sub-bins spread
+// those atomics over K counters per bin (one counter per bin took 3.5 ms per
+// launch to serialise the claims of 1e7 particles).
 struct alignas(16) PRec {
   long long q;
   double x0, y0, sx, sy;
   uint32_t cell, cell_e;     // ix | iy << 16, ixe | iye << 16
   int bface;
-  uint32_t nyp, ncross, pad;
+  uint32_t nyp, ncross, pc;
 };
 struct alignas(16) PRecN {   // with null collisions
   PRec c;
   double ell, uacc;
 };
 static_assert(sizeof(PRec) == 64 && sizeof(PRecN) == 80, "record sizes");
-// and, beside it, the rows that stripes must run the particle in (lo, hi:
-// empty for no particle): the rows of a first segment that is the whole
-// flight (up to the wall for an absorption on a y wall), or with null
-// collisions every row in its direction of travel, as two 16-bit rows (lo
-// in the high half; no particle: lo 0xffff, hi 0).  A stripe reads 4 bytes
-// per particle to skip those outside its rows, not the whole record.
+// and, beside a leaver's record, the rows that stripes must run the particle
+// in (lo, hi): the rows of a first segment that is the whole flight (up to the
+// wall for an absorption on a y wall), or with null collisions every row in
+// its direction of travel, as two 16-bit rows (lo in the high half).  A
+// stripe reads these 4 bytes to skip another stripe's leaver that does not
+// reach its rows, not the whole record.
+constexpr int kStripeSegMax = 1024;   // (S + 1) K segments at most (the march's segment table)
+constexpr int kStripeBinMax = 64;     // bins (start stripe, direction) of a pre-pass block
+constexpr int kPresampleBlock = 256;  // pre-pass threads per block,
+constexpr int kPresamplePer = 4;      // particles per thread
 struct StripeRec {
   void *r;                   // PRec, or PRecN with null collisions [particles]
-  uint32_t *key;
+  uint32_t *key;             // [particles]
+  uint32_t *cnt;             // [S K][2]: per sub-bin, records filled from the front, from the back
+  const uint32_t *base;      // [S K + 1]: first slot of sub-bin t K + k
+  int R, S, K;               // rows per stripe, stripes, sub-bins per stripe
 };
 __device__ __forceinline__ uint32_t row_range(int lo, int hi)
 {
@@ -857,77 +871,109 @@ template <int BS, bool NUL>
 __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__restrict__ insts,
                                                               StripeRec rec)
 {
-  // the workgroup's records are built in LDS and written out as contiguous
-  // 16-byte stores (a lane storing its own record field by field writes
-  // 8 bytes every record)
   using Rec = typename std::conditional<NUL, PRecN, PRec>::type;
-  __shared__ Rec srec[BS];
-  __shared__ uint32_t skey[BS];
+  constexpr int PER = kPresamplePer;
+  __shared__ uint32_t s_n[kStripeBinMax], s_g[kStripeBinMax];
   const Inst &in = insts[0];
   const Mesh &m = in.m;
   const FlyIn fa = {m, in.lam_min, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1, 1,
                     in.has_null, in.ratio, in.e_off};
   const unsigned long long n_emit = static_cast<unsigned long long>(m.n_emit);
   const unsigned long long total = n_emit * in.N;
-  const unsigned long long p0 = static_cast<unsigned long long>(blockIdx.x) * BS;
-  const unsigned long long pc = p0 + threadIdx.x;
-  if (pc < total) {
-    const uint32_t kk = static_cast<uint32_t>(pc / n_emit);
-    const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
-    const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
-    Rec &rec_out = srec[threadIdx.x];
-    PRec &out = *reinterpret_cast<PRec *>(&rec_out);     // (the common part comes first)
-    out.q = q;
-    if (q == 0) {
-      skey[threadIdx.x] = row_range(0xffff, 0);
-    } else {
-      int ix = 0, iy = 0;
-      double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
-      sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
-      const double2 us = draw2(2u, kk, e + fa.e_off, fa.slot, fa.key0, fa.key1);
-      const double ell = -(fa.lam_min * log_own(1.0 - us.x));
-      const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
-      const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
-      const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
-      const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
-      const int kx0 = (stx > 0) ? ix + 1 : ix;
-      const int ky0 = (sty > 0) ? iy + 1 : iy;
-      int ixe = ix, iye = iy, bface = -1, nxp = 0, nyp = 0;
-      segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
-      out.x0 = x0;
-      out.y0 = y0;
-      out.sx = sx;
-      out.sy = sy;
-      out.cell = static_cast<uint32_t>(ix) | (static_cast<uint32_t>(iy) << 16);
-      out.cell_e = static_cast<uint32_t>(ixe) | (static_cast<uint32_t>(iye) << 16);
-      out.bface = bface;
-      out.nyp = static_cast<uint32_t>(nyp);
-      out.ncross = static_cast<uint32_t>(nxp + nyp);
-      if constexpr (NUL) {
-        rec_out.ell = ell;
-        rec_out.uacc = us.y;
+  const int nbin = 2 * rec.S, k = static_cast<int>(blockIdx.x % static_cast<unsigned>(rec.K));
+  for (int b = threadIdx.x; b < nbin; b += BS) s_n[b] = 0;
+  __syncthreads();
+  Rec rc_out[PER];
+  uint32_t key[PER], rank[PER];
+  int bin[PER];
+  const int lane = static_cast<int>(threadIdx.x & 63);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const unsigned long long pc =
+        (static_cast<unsigned long long>(blockIdx.x) * PER + u) * BS + threadIdx.x;
+    PRec &out = *reinterpret_cast<PRec *>(&rc_out[u]);     // (the common part comes first)
+    bin[u] = -1;
+    key[u] = 0;
+    rank[u] = 0;
+    if (pc < total) {
+      const uint32_t kk = static_cast<uint32_t>(pc / n_emit);
+      const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
+      const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
+      if (q != 0) {
+        int ix = 0, iy = 0;
+        double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
+        sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
+        const double2 us = draw2(2u, kk, e + fa.e_off, fa.slot, fa.key0, fa.key1);
+        const double ell = -(fa.lam_min * log_own(1.0 - us.x));
+        const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+        const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+        const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+        const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+        const int kx0 = (stx > 0) ? ix + 1 : ix;
+        const int ky0 = (sty > 0) ? iy + 1 : iy;
+        int ixe = ix, iye = iy, bface = -1, nxp = 0, nyp = 0;
+        segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
+        out.q = q;
+        out.x0 = x0;
+        out.y0 = y0;
+        out.sx = sx;
+        out.sy = sy;
+        out.cell = static_cast<uint32_t>(ix) | (static_cast<uint32_t>(iy) << 16);
+        out.cell_e = static_cast<uint32_t>(ixe) | (static_cast<uint32_t>(iye) << 16);
+        out.bface = bface;
+        out.nyp = static_cast<uint32_t>(nyp);
+        out.ncross = static_cast<uint32_t>(nxp + nyp);
+        out.pc = static_cast<uint32_t>(pc);
+        if constexpr (NUL) {
+          rc_out[u].ell = ell;
+          rc_out[u].uacc = us.y;
+        }
+        int lo = min(iy, iye), hi = max(iy, iye);
+        if (fa.has_null) {
+          lo = (sty < 0) ? 0 : iy;
+          hi = (sty > 0) ? m.ny - 1 : iy;
+        } else if (bface >= 2 * m.ny) {
+          if (sty > 0) hi = m.ny - 1;
+          else lo = 0;
+        }
+        key[u] = row_range(lo, hi);
+        bin[u] = 2 * (iy / rec.R) + ((lo / rec.R != hi / rec.R) ? 1 : 0);
       }
-      int lo = min(iy, iye), hi = max(iy, iye);
-      if (fa.has_null) {
-        lo = (sty < 0) ? 0 : iy;
-        hi = (sty > 0) ? m.ny - 1 : iy;
-      } else if (bface >= 2 * m.ny) {
-        if (sty > 0) hi = m.ny - 1;
-        else lo = 0;
-      }
-      skey[threadIdx.x] = row_range(lo, hi);
+    }
+    // the particle's rank in its bin within the block: one LDS atomic per
+    // bin and wavefront
+    unsigned long long pending = __ballot(bin[u] >= 0);
+    while (pending) {
+      const int lead = __ffsll(static_cast<long long>(pending)) - 1;
+      const int bl = __shfl(bin[u], lead, 64);
+      const unsigned long long mine = __ballot(bin[u] == bl);
+      uint32_t first = 0;
+      if (lane == lead) first = atomicAdd(&s_n[bl], static_cast<uint32_t>(__popcll(mine)));
+      first = static_cast<uint32_t>(__shfl(static_cast<int>(first), lead, 64));
+      if ((mine >> lane) & 1ull)
+        rank[u] = first + static_cast<uint32_t>(__popcll(mine & ((1ull << lane) - 1ull)));
+      pending &= ~mine;
     }
   }
   __syncthreads();
-  // (a record without a particle is never read past its weight)
+  // the block's slots: one atomic per bin on sub-bin k's counter
+  for (int b = threadIdx.x; b < nbin; b += BS)
+    s_g[b] = s_n[b] ? atomicAdd(&rec.cnt[2 * ((b >> 1) * rec.K + k) + (b & 1)], s_n[b]) : 0u;
+  __syncthreads();
   constexpr int kWords = static_cast<int>(sizeof(Rec) / sizeof(uint4));
   static_assert(sizeof(Rec) % sizeof(uint4) == 0, "records are whole 16-byte words");
-  const unsigned long long left = (p0 < total) ? total - p0 : 0;
-  const int cnt = static_cast<int>(left < BS ? left : BS);
-  if (static_cast<int>(threadIdx.x) < cnt) rec.key[pc] = skey[threadIdx.x];
-  const uint4 *src = reinterpret_cast<const uint4 *>(srec);
-  uint4 *dst = reinterpret_cast<uint4 *>(static_cast<Rec *>(rec.r) + p0);
-  for (int i = threadIdx.x; i < cnt * kWords; i += BS) dst[i] = src[i];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    if (bin[u] < 0) continue;
+    const int sb = (bin[u] >> 1) * rec.K + k;
+    const uint32_t r = s_g[bin[u]] + rank[u];
+    const uint32_t slot = (bin[u] & 1) ? rec.base[sb + 1] - 1u - r : rec.base[sb] + r;
+    const uint4 *src = reinterpret_cast<const uint4 *>(&rc_out[u]);
+    uint4 *dst = reinterpret_cast<uint4 *>(static_cast<Rec *>(rec.r) + slot);
+#pragma unroll
+    for (int i = 0; i < kWords; ++i) dst[i] = src[i];
+    if (bin[u] & 1) rec.key[slot] = key[u];
+  }
 }
 
 template <int BS>
@@ -936,6 +982,12 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
 {
   extern __shared__ long long lds_words[];
   __shared__ unsigned long long s_cnt[3];
+  // the stripe's candidates as segments of slots: its own stayers, its own
+  // leavers, then every other start stripe's leavers (checked against the
+  // rows); s_pre: their starts in one running count
+  static_assert(BS >= kStripeSegMax, "one thread per segment");
+  __shared__ uint32_t s_pre[kStripeSegMax + 1], s_slot[kStripeSegMax];
+  __shared__ uint32_t s_wsum[BS / 64];
   const Inst &in = insts[0];
   // (the mesh and the tally pointers in registers: reloaded inside the state
   // machine, each load would also wait for the lane's pending LDS atomics)
@@ -951,6 +1003,47 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   const int nwords = nface * nx + (lds_walls ? m.n_b : 0);
   for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
   if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  // segment i of the (S + 1) K: i < 2K this stripe's sub-bin i / 2, its front
+  // (stayers) or back (leavers); then, for each other stripe in order, its K
+  // sub-bins' leavers; their starts by a workgroup scan of the counts
+  const int K = rec.K, nseg = (rec.S + 1) * K, nown = 2 * K;
+  {
+    const int sb = static_cast<int>(blockIdx.y);
+    const int i = static_cast<int>(threadIdx.x);
+    uint32_t cnt = 0, first = 0;
+    if (i < nseg) {
+      int t, kb, back;
+      if (i < nown) {
+        t = sb;
+        kb = i >> 1;
+        back = i & 1;
+      } else {
+        const int j = i - nown;
+        t = j / K;
+        kb = j - t * K;
+        if (t >= sb) ++t;
+        back = 1;
+      }
+      const int sub = t * K + kb;
+      cnt = rec.cnt[2 * sub + back];
+      first = back ? rec.base[sub + 1] - cnt : rec.base[sub];
+      s_slot[i] = first;
+    }
+    // exclusive scan of the counts over the workgroup (BS >= nseg)
+    const int lane = i & 63, w = i >> 6;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = static_cast<uint32_t>(__shfl_up(static_cast<int>(incl), d, 64));
+      if (lane >= d) incl += o;
+    }
+    if (lane == 63) s_wsum[w] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int v = 0; v < w; ++v) off += s_wsum[v];
+    if (i < nseg) s_pre[i] = off + incl - cnt;
+    if (i == nseg - 1) s_pre[nseg] = off + incl;
+  }
   __syncthreads();
   auto lds_add = [](long long *p, long long v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
@@ -958,17 +1051,25 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
 
   const FlyIn fa = {m, in.lam_min, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1, 1,
                     in.has_null, in.ratio, in.e_off};
-  const uint32_t N = in.N;
   const unsigned long long n_emit = static_cast<unsigned long long>(m.n_emit);
-  const unsigned long long total = n_emit * N;
-  const unsigned long long pb = total * blockIdx.x / chunks;
-  const unsigned long long pe = total * (blockIdx.x + 1) / chunks;
-  unsigned long long pnext = pb + threadIdx.x;
+  const uint32_t V = s_pre[nseg];
+  const uint32_t vb = static_cast<uint32_t>(static_cast<unsigned long long>(V) * blockIdx.x / chunks);
+  const uint32_t ve = static_cast<uint32_t>(static_cast<unsigned long long>(V) * (blockIdx.x + 1) / chunks);
   unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
   const double inv_dx = 1.0 / m.dx;       // (only to estimate a face count)
-  // the row range of the lane's next candidate, loaded one particle ahead
-  const uint32_t none = row_range(0xffff, 0);
-  uint32_t nkey = (pnext < pe) ? rec.key[pnext] : none;
+  // the lane's next candidate, located (segment, slot) and, for another
+  // stripe's leaver, its row range loaded, one particle ahead
+  uint32_t vnext = vb + threadIdx.x;
+  int sg = 0;
+  uint32_t nslot = 0, nkey = 0;
+  bool nchk = false;
+  auto locate = [&](uint32_t v) {
+    while (sg + 1 < nseg && v >= s_pre[sg + 1]) ++sg;
+    nslot = s_slot[sg] + (v - s_pre[sg]);
+    nchk = sg >= nown;
+    nkey = nchk ? rec.key[nslot] : 0u;
+  };
+  if (vnext < ve) locate(vnext);
 
   // the lane's particle
   bool live = false;
@@ -1029,25 +1130,27 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   for (;;) {
     if (!live) {
       bool got = false;
-      unsigned long long pc = 0;
-      while (pnext < pe) {
-        pc = pnext;
-        pnext += BS;
-        // a stripe outside the rows the particle can reach has nothing of it
+      uint32_t slot = 0;
+      while (vnext < ve) {
+        slot = nslot;
         const uint32_t key = nkey;
-        nkey = (pnext < pe) ? rec.key[pnext] : none;
-        if (static_cast<int>(key & 0xffffu) < r0 || static_cast<int>(key >> 16) >= r1) continue;
+        const bool chk = nchk;
+        vnext += BS;
+        if (vnext < ve) locate(vnext);
+        // another stripe's leaver that cannot reach these rows has nothing here
+        if (chk && (static_cast<int>(key & 0xffffu) < r0 || static_cast<int>(key >> 16) >= r1))
+          continue;
         got = true;
         break;
       }
       if (!got) break;
-      // emitters fastest: neighbouring lanes start in different cells
-      kk = static_cast<uint32_t>(pc / n_emit);
-      e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
       // (the record's common part comes first in both forms)
       const unsigned char *rb = static_cast<const unsigned char *>(rec.r) +
-                                pc * (fa.has_null ? sizeof(PRecN) : sizeof(PRec));
+                                static_cast<size_t>(slot) * (fa.has_null ? sizeof(PRecN) : sizeof(PRec));
       const PRec &rp = *reinterpret_cast<const PRec *>(rb);
+      const unsigned long long pc = rp.pc;
+      kk = static_cast<uint32_t>(pc / n_emit);
+      e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
       q = rp.q;
       const uint32_t cs = rp.cell, ce = rp.cell_e;
       ix = static_cast<int>(cs & 0xffffu);
