@@ -1455,12 +1455,15 @@ int enqueue_iteration(iugkp_handle *h, int faces)
     const dim3 sg(ih.stripe_C, ih.stripe_S);
     const int ncnt = 2 * ih.rec.S * ih.rec.K;
     iugkp::zero_u32_kernel<<<cdiv(ncnt, 256), 256, 0, s>>>(ih.rec.cnt, ncnt);
+    constexpr size_t ps_lds = static_cast<size_t>(iugkp::kPresampleBlock) * sizeof(uint32_t);
     if (ih.d.has_null)
       iugkp::stripe_presample_kernel<iugkp::kPresampleBlock, true>
-          <<<pg, iugkp::kPresampleBlock, 0, s>>>(h->d_inst, ih.rec);
+          <<<pg, iugkp::kPresampleBlock, iugkp::kPresampleBlock * sizeof(iugkp::PRecN) + ps_lds, s>>>(
+              h->d_inst, ih.rec);
     else
       iugkp::stripe_presample_kernel<iugkp::kPresampleBlock, false>
-          <<<pg, iugkp::kPresampleBlock, 0, s>>>(h->d_inst, ih.rec);
+          <<<pg, iugkp::kPresampleBlock, iugkp::kPresampleBlock * sizeof(iugkp::PRec) + ps_lds, s>>>(
+              h->d_inst, ih.rec);
     iugkp::march_stripes_kernel<kStripeBlock>
         <<<sg, kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
     HIP_TRY(hipGetLastError());

@@ -853,8 +853,8 @@ static_assert(sizeof(PRec) == 64 && sizeof(PRecN) == 80, "record sizes");
 // reach its rows, not the whole record.
 constexpr int kStripeSegMax = 1024;   // (S + 1) K segments at most (the march's segment table)
 constexpr int kStripeBinMax = 64;     // bins (start stripe, direction) of a pre-pass block
-constexpr int kPresampleBlock = 256;  // pre-pass threads per block,
-constexpr int kPresamplePer = 4;      // particles per thread
+constexpr int kPresampleBlock = 1024; // pre-pass threads per block,
+constexpr int kPresamplePer = 1;      // particles per thread
 struct StripeRec {
   void *r;                   // PRec, or PRecN with null collisions [particles]
   uint32_t *key;             // [particles]
@@ -867,13 +867,18 @@ __device__ __forceinline__ uint32_t row_range(int lo, int hi)
   return (static_cast<uint32_t>(lo) << 16) | static_cast<uint32_t>(hi);
 }
 
+// (dynamic LDS: the block's records, sorted by bin, then their slots)
 template <int BS, bool NUL>
 __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__restrict__ insts,
                                                               StripeRec rec)
 {
   using Rec = typename std::conditional<NUL, PRecN, PRec>::type;
-  constexpr int PER = kPresamplePer;
-  __shared__ uint32_t s_n[kStripeBinMax], s_g[kStripeBinMax];
+  constexpr int kWords = static_cast<int>(sizeof(Rec) / sizeof(uint4));
+  static_assert(sizeof(Rec) % sizeof(uint4) == 0, "records are whole 16-byte words");
+  static_assert(kPresamplePer == 1, "one particle per thread");
+  extern __shared__ uint4 srec[];                                   // [BS][kWords]
+  uint32_t *const s_dst = reinterpret_cast<uint32_t *>(srec + BS * kWords);   // [BS]
+  __shared__ uint32_t s_n[kStripeBinMax], s_g[kStripeBinMax], s_off[kStripeBinMax + 1];
   const Inst &in = insts[0];
   const Mesh &m = in.m;
   const FlyIn fa = {m, in.lam_min, in.crn ? in.epoch : in.sc->iter, in.key0, in.key1, 1,
@@ -883,96 +888,107 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
   const int nbin = 2 * rec.S, k = static_cast<int>(blockIdx.x % static_cast<unsigned>(rec.K));
   for (int b = threadIdx.x; b < nbin; b += BS) s_n[b] = 0;
   __syncthreads();
-  Rec rc_out[PER];
-  uint32_t key[PER], rank[PER];
-  int bin[PER];
+  Rec rc_out;
+  PRec &out = *reinterpret_cast<PRec *>(&rc_out);     // (the common part comes first)
+  uint32_t key = 0, rank = 0;
+  int bin = -1;
   const int lane = static_cast<int>(threadIdx.x & 63);
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const unsigned long long pc =
-        (static_cast<unsigned long long>(blockIdx.x) * PER + u) * BS + threadIdx.x;
-    PRec &out = *reinterpret_cast<PRec *>(&rc_out[u]);     // (the common part comes first)
-    bin[u] = -1;
-    key[u] = 0;
-    rank[u] = 0;
-    if (pc < total) {
-      const uint32_t kk = static_cast<uint32_t>(pc / n_emit);
-      const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
-      const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
-      if (q != 0) {
-        int ix = 0, iy = 0;
-        double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
-        sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
-        const double2 us = draw2(2u, kk, e + fa.e_off, fa.slot, fa.key0, fa.key1);
-        const double ell = -(fa.lam_min * log_own(1.0 - us.x));
-        const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
-        const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
-        const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
-        const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
-        const int kx0 = (stx > 0) ? ix + 1 : ix;
-        const int ky0 = (sty > 0) ? iy + 1 : iy;
-        int ixe = ix, iye = iy, bface = -1, nxp = 0, nyp = 0;
-        segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
-        out.q = q;
-        out.x0 = x0;
-        out.y0 = y0;
-        out.sx = sx;
-        out.sy = sy;
-        out.cell = static_cast<uint32_t>(ix) | (static_cast<uint32_t>(iy) << 16);
-        out.cell_e = static_cast<uint32_t>(ixe) | (static_cast<uint32_t>(iye) << 16);
-        out.bface = bface;
-        out.nyp = static_cast<uint32_t>(nyp);
-        out.ncross = static_cast<uint32_t>(nxp + nyp);
-        out.pc = static_cast<uint32_t>(pc);
-        if constexpr (NUL) {
-          rc_out[u].ell = ell;
-          rc_out[u].uacc = us.y;
-        }
-        int lo = min(iy, iye), hi = max(iy, iye);
-        if (fa.has_null) {
-          lo = (sty < 0) ? 0 : iy;
-          hi = (sty > 0) ? m.ny - 1 : iy;
-        } else if (bface >= 2 * m.ny) {
-          if (sty > 0) hi = m.ny - 1;
-          else lo = 0;
-        }
-        key[u] = row_range(lo, hi);
-        bin[u] = 2 * (iy / rec.R) + ((lo / rec.R != hi / rec.R) ? 1 : 0);
+  const unsigned long long pc = static_cast<unsigned long long>(blockIdx.x) * BS + threadIdx.x;
+  if (pc < total) {
+    const uint32_t kk = static_cast<uint32_t>(pc / n_emit);
+    const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
+    const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
+    if (q != 0) {
+      int ix = 0, iy = 0;
+      double x0 = 0.0, y0 = 0.0, sx = 0.0, sy = 0.0;
+      sample_particle(fa, e, kk, ix, iy, x0, y0, sx, sy);
+      const double2 us = draw2(2u, kk, e + fa.e_off, fa.slot, fa.key0, fa.key1);
+      const double ell = -(fa.lam_min * log_own(1.0 - us.x));
+      const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+      const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+      const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+      const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+      const int kx0 = (stx > 0) ? ix + 1 : ix;
+      const int ky0 = (sty > 0) ? iy + 1 : iy;
+      int ixe = ix, iye = iy, bface = -1, nxp = 0, nyp = 0;
+      segment_end(m, x0, y0, ixe, iye, stx, sty, inv_sx, inv_sy, kx0, ky0, ell, bface, nxp, nyp);
+      out.q = q;
+      out.x0 = x0;
+      out.y0 = y0;
+      out.sx = sx;
+      out.sy = sy;
+      out.cell = static_cast<uint32_t>(ix) | (static_cast<uint32_t>(iy) << 16);
+      out.cell_e = static_cast<uint32_t>(ixe) | (static_cast<uint32_t>(iye) << 16);
+      out.bface = bface;
+      out.nyp = static_cast<uint32_t>(nyp);
+      out.ncross = static_cast<uint32_t>(nxp + nyp);
+      out.pc = static_cast<uint32_t>(pc);
+      if constexpr (NUL) {
+        rc_out.ell = ell;
+        rc_out.uacc = us.y;
       }
-    }
-    // the particle's rank in its bin within the block: one LDS atomic per
-    // bin and wavefront
-    unsigned long long pending = __ballot(bin[u] >= 0);
-    while (pending) {
-      const int lead = __ffsll(static_cast<long long>(pending)) - 1;
-      const int bl = __shfl(bin[u], lead, 64);
-      const unsigned long long mine = __ballot(bin[u] == bl);
-      uint32_t first = 0;
-      if (lane == lead) first = atomicAdd(&s_n[bl], static_cast<uint32_t>(__popcll(mine)));
-      first = static_cast<uint32_t>(__shfl(static_cast<int>(first), lead, 64));
-      if ((mine >> lane) & 1ull)
-        rank[u] = first + static_cast<uint32_t>(__popcll(mine & ((1ull << lane) - 1ull)));
-      pending &= ~mine;
+      int lo = min(iy, iye), hi = max(iy, iye);
+      if (fa.has_null) {
+        lo = (sty < 0) ? 0 : iy;
+        hi = (sty > 0) ? m.ny - 1 : iy;
+      } else if (bface >= 2 * m.ny) {
+        if (sty > 0) hi = m.ny - 1;
+        else lo = 0;
+      }
+      key = row_range(lo, hi);
+      bin = 2 * (iy / rec.R) + ((lo / rec.R != hi / rec.R) ? 1 : 0);
     }
   }
+  // the particle's rank in its bin within the block: one LDS atomic per bin
+  // and wavefront
+  unsigned long long pending = __ballot(bin >= 0);
+  while (pending) {
+    const int lead = __ffsll(static_cast<long long>(pending)) - 1;
+    const int bl = __shfl(bin, lead, 64);
+    const unsigned long long mine = __ballot(bin == bl);
+    uint32_t first = 0;
+    if (lane == lead) first = atomicAdd(&s_n[bl], static_cast<uint32_t>(__popcll(mine)));
+    first = static_cast<uint32_t>(__shfl(static_cast<int>(first), lead, 64));
+    if ((mine >> lane) & 1ull)
+      rank = first + static_cast<uint32_t>(__popcll(mine & ((1ull << lane) - 1ull)));
+    pending &= ~mine;
+  }
   __syncthreads();
-  // the block's slots: one atomic per bin on sub-bin k's counter
+  // the block's slots (one atomic per bin on sub-bin k's counter) and the
+  // bins' places in the block's sorted records (a scan by wavefront 0)
   for (int b = threadIdx.x; b < nbin; b += BS)
     s_g[b] = s_n[b] ? atomicAdd(&rec.cnt[2 * ((b >> 1) * rec.K + k) + (b & 1)], s_n[b]) : 0u;
+  if (threadIdx.x < 64) {
+    const uint32_t v = (lane < nbin) ? s_n[lane] : 0u;
+    uint32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = static_cast<uint32_t>(__shfl_up(static_cast<int>(incl), d, 64));
+      if (lane >= d) incl += o;
+    }
+    s_off[lane] = incl - v;
+    if (lane == 63) s_off[64] = incl;
+  }
   __syncthreads();
-  constexpr int kWords = static_cast<int>(sizeof(Rec) / sizeof(uint4));
-  static_assert(sizeof(Rec) % sizeof(uint4) == 0, "records are whole 16-byte words");
+  if (bin >= 0) {
+    const int sb = (bin >> 1) * rec.K + k;
+    const uint32_t r = s_g[bin] + rank;
+    const uint32_t slot = (bin & 1) ? rec.base[sb + 1] - 1u - r : rec.base[sb] + r;
+    const uint32_t j = s_off[bin] + rank;
+    const uint4 *src = reinterpret_cast<const uint4 *>(&rc_out);
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    if (bin[u] < 0) continue;
-    const int sb = (bin[u] >> 1) * rec.K + k;
-    const uint32_t r = s_g[bin[u]] + rank[u];
-    const uint32_t slot = (bin[u] & 1) ? rec.base[sb + 1] - 1u - r : rec.base[sb] + r;
-    const uint4 *src = reinterpret_cast<const uint4 *>(&rc_out[u]);
-    uint4 *dst = reinterpret_cast<uint4 *>(static_cast<Rec *>(rec.r) + slot);
-#pragma unroll
-    for (int i = 0; i < kWords; ++i) dst[i] = src[i];
-    if (bin[u] & 1) rec.key[slot] = key[u];
+    for (int i = 0; i < kWords; ++i) srec[j * kWords + i] = src[i];
+    s_dst[j] = slot;
+    if (bin & 1) rec.key[slot] = key;
+  }
+  __syncthreads();
+  // out as 16-byte words, consecutive threads on consecutive words of the
+  // sorted records (the runs of one bin are consecutive slots)
+  const int nw = static_cast<int>(s_off[64]) * kWords;
+  Rec *const dst = static_cast<Rec *>(rec.r);
+  for (int i = threadIdx.x; i < nw; i += BS) {
+    const int j = i / kWords, w = i - j * kWords;
+    reinterpret_cast<uint4 *>(dst + s_dst[j])[w] = srec[i];
   }
 }
 
