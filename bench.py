@@ -67,6 +67,8 @@ def parse():
                     help="only the 40-band timing (printed as its own JSON line; for profiling)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched vs sequential comparison (its own JSON line)")
+    ap.add_argument("--forms", default=None,
+                    help="(with --profile-pass) JSON {kn: particle-step form} to run the problems in")
     ap.add_argument("--profile-pass", action="store_true",
                     help="only the kernel pass that the counter collection profiles")
     ap.add_argument("--no-counters", action="store_true",
@@ -589,7 +591,12 @@ COUNTER_PASSES = (("FETCH_SIZE",),
                    "TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum"))
 
 
-def profile_pass():
+# a particle-step form as Solver options (the form search keeps the fastest)
+FORM_OPTS = {"tiles256": dict(march=1, block_size=256), "tiles512": dict(march=1, block_size=512),
+             "stripes": dict(march=2)}
+
+
+def profile_pass(forms=None):
     """What collect_counters profiles: a 256 MiB device copy three times (to
     scale FETCH_SIZE / WRITE_SIZE to bytes), then the benchmark's four Kn
     problems one at a time, PROFILE_ITERS iterations each, started from the
@@ -608,8 +615,12 @@ def profile_pass():
     del a, b
     for kn in KNS:
         w = cavity_2d(n=N_SIDE, kn=kn, particles=PARTICLES, newton=True, seed=0)
+        # the form the benchmark's search chose, else the planner's (a set
+        # block size: no search)
+        f = (forms or {}).get(str(kn))
+        opts = FORM_OPTS[f] if f in FORM_OPTS else dict(block_size=256)
         s = P.Solver(w, device=dev, tally_faces=P.FACES_EVERY, cg_precond=P.PRECOND_MG,
-                     T_init=seeded_temperature(N_SIDE * N_SIDE))
+                     T_init=seeded_temperature(N_SIDE * N_SIDE), **opts)
         assert s.step(PROFILE_ITERS) == 0
         torch.cuda.synchronize()
         s.close()
@@ -635,7 +646,7 @@ def _kernel_is(name, kernels):
     return any(k + "<" in name or k + "(" in name or name.endswith(k) for k in kernels)
 
 
-def collect_counters(timeout_s=240):
+def collect_counters(forms=None, timeout_s=240):
     """Run profile_pass under rocprofv3 once per counter pass and reduce the
     per-dispatch counters to per-launch figures of the particle step (all
     its kernels of one iteration) and of the multigrid CG.  Each pass is
@@ -659,6 +670,8 @@ def collect_counters(timeout_s=240):
         out = tempfile.mkdtemp(prefix="iugkp_pmc_", dir="/tmp")
         cmd = [prof, "--pmc", *counters, "-d", out, "-o", "run", "--output-format", "csv", "--",
                sys.executable, os.path.join(ROOT, "bench.py"), "--profile-pass"]
+        if forms:
+            cmd += ["--forms", json.dumps(forms)]
         cmds.append(" ".join(["rocprofv3", "--pmc", *counters, "-d", "<dir>", "-o", "run",
                               "--output-format", "csv", "--", "python3", "bench.py",
                               "--profile-pass"]))
@@ -730,7 +743,7 @@ def main():
         copy_calibration()
         return
     if args.profile_pass:
-        profile_pass()
+        profile_pass(json.loads(args.forms) if args.forms else None)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -775,6 +788,11 @@ def main():
         rc = P.step_group([s for _, _, s in solvers], n)
         assert rc == 0, f"step failed with {rc}"
 
+    # the particle-step form search of each problem (an untimed iteration, then
+    # one per form: tiles of 256 and 512 threads, row stripes), one problem at
+    # a time so that each measurement has the GPU to itself
+    for _, _, s in solvers:
+        assert s.step(4) == 0
     run_concurrent(args.warmup)
     # kernel pass: the same steps one problem at a time, for per-kernel times
     # (HIP events on each solver's stream) free of the other problems' kernels
@@ -802,6 +820,7 @@ def main():
     K = args.steps
     # release the four solvers (and their streams' work) before anything else
     st_final = [s.stats() for _, _, s in solvers]
+    tuning = {kn: s.march_tuning() for kn, _, s in solvers}
     for _, _, s in solvers:
         s.close()
     torch.cuda.synchronize()
@@ -825,6 +844,9 @@ def main():
             "crossings_per_s_march": cr / (ms_m / 1e3) if ms_m else None,
             "cg_us_per_iteration": round(ms_c * 1e3 / cgi, 3) if cgi else None,
             "march_GBs_algorithmic": mb / (ms_m / 1e3) / 1e9 if ms_m else None,
+            "march_form": tuning[kn][0],
+            "march_form_ms": {f: (round(v, 3) if v is not None else None)
+                              for f, v in tuning[kn][1].items()},
         }
         for k, v in (("flights", fl), ("crossings", cr), ("segments", sg), ("ms_march", ms_m),
                      ("ms_cg", ms_c), ("march_bytes", mb), ("cg_bytes", cb), ("cg_iters", cgi)):
@@ -839,7 +861,8 @@ def main():
             "lds_int64_per_s": P.dev_atomics(True),
             "note": "int64 atomic adds to random words, every lane of full wavefronts: of a "
                     "2 MB global array, and of a 4096-word LDS array per workgroup"}
-    counters = None if args.no_counters else collect_counters()
+    counters = None if args.no_counters else collect_counters(
+        {k: v["march_form"] for k, v in per_kn.items() if v.get("march_form")})
     cnt_ok = counters is not None and "error" not in counters
     n_l = tot["launches"]
     ps_ms = tot["ms_march"] / n_l

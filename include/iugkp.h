@@ -287,6 +287,19 @@ int iugkp_get_residuals(iugkp_handle *h, double *res, int max_n);
 
 int iugkp_get_stats(iugkp_handle *h, iugkp_stats *stats);
 
+/* The particle step's form for the face-tallied iterations (the A4 march of
+ * Sec. 3.1; how it is run is an implementation choice, not the paper's): 0 =
+ * emitter tiles of 256 threads, 1 = emitter tiles of 512 threads, 2 = row
+ * stripes; -1 while the handle still measures them.  A 2D gray single solve
+ * with the automatic march and the default block size times one face-tallied
+ * iteration in each form (after an untimed first one) and keeps the fastest;
+ * later handles of the same mesh, particles per emitter, null-collision
+ * setting and free path in cells (to half an octave) start with it.  Every
+ * form gives the same tallies bit for bit.  ms (NULL or host float[3]): the
+ * measured particle-step milliseconds per form, -1 where not measured.
+ * Returns 0, or IUGKP_E_INVALID_ARG for a NULL handle. */
+int iugkp_march_tuning(iugkp_handle *h, int *form, float *ms);
+
 /* Adjoint of the steady state reached by this handle (an addition to the
  * paper, which has no adjoint): given dL/dT per cell for a loss L(T), the
  * gradient of L with respect to every wall face's temperature and every

@@ -75,6 +75,7 @@ SIGNATURES = [
     ("iugkp_set_state", C.c_int, [P, C.c_uint32, C.c_double, P, P]),
     ("iugkp_get_residuals", C.c_int, [P, P, C.c_int]),
     ("iugkp_get_stats", C.c_int, [P, C.POINTER(Stats)]),
+    ("iugkp_march_tuning", C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_float)]),
     ("iugkp_get_particles", C.c_int, [P, P, P, P, P, P, P, P]),
     ("iugkp_get_shares", C.c_int, [P, P, P, P, P, P, P]),
     ("iugkp_d_eff", C.c_double, [C.c_double, C.c_double]),

@@ -147,6 +147,7 @@ struct InstHost {
   // row-stripe particle step for face-tallied iterations (single solves)
   int stripe_R = 0, stripe_S = 0, stripe_C = 0;
   size_t stripe_lds = 0;
+  int stripe_pref = 0;               // the planner's choice (stripes set up for a search too)
   iugkp::StripeRec rec{};            // first segments, sampled once for all stripes
 
   template <class T>
@@ -779,12 +780,14 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   // (expected-value rays: only on request, march == 2; every stripe follows a
   // ray from its start, and that re-walk costs more than the tile kernel's
   // global atomics on the 256^2 cavity)
+  // (an automatic march with the default block size also sets stripes up for
+  // the particle-step form search of the handle)
   const bool ev = (o->estimator == IUGKP_EST_EXPECTED);
+  const bool lam_stripes = d.lam_min >= kStripeMinCells * std::min(p->dx, p->dy);
   if (multi_cg && p->dim == 2 && o->scheme == IUGKP_SCHEME_EMITTERS &&
       ((ev && o->march == 2) ||
        (!ev && o->tally_faces != IUGKP_FACES_OFF &&
-        (o->march == 2 ||
-         (o->march == 0 && d.lam_min >= kStripeMinCells * std::min(p->dx, p->dy)))))) {
+        (o->march == 2 || (o->march == 0 && (lam_stripes || o->block_size == 0)))))) {
     // row stripes: as many rows per workgroup as its LDS holds (y faces and
     // the walls; the expected-value kernel also D, and W with null
     // collisions), about two workgroups per CU
@@ -870,6 +873,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
         ih.stripe_S = S;
         ih.stripe_C = std::max(1, (2 * per_cu * n_cu) / S);   // whole rounds of resident groups
         ih.stripe_lds = lds;
+        ih.stripe_pref = (o->march == 2 || lam_stripes) ? 1 : 0;
       }
     }
     if (o->march == 2 && ih.stripe_R == 0)
@@ -1302,6 +1306,14 @@ struct iugkp_handle {
   int n_tiles = 0;
   size_t lds = 0;                 // march window (largest over the bands)
   int block = 256;
+  // the particle-step form of face-tallied iterations (pick_form)
+  bool form_search = false;
+  int form = -1;                  // chosen (kForm*), -1 while searching
+  int form_default = 0;
+  bool form_warm = false;         // the first face-tallied iteration has run
+  int form_next = 0;              // candidates measured so far
+  int form_last = -1;             // candidate of the iteration in flight
+  float form_ms[3] = {-1.f, -1.f, -1.f};
   DevScalars *hsc = nullptr;   // pinned host mirror
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   uint32_t iter = 0;
@@ -1417,6 +1429,68 @@ int enqueue_cg(const InstHost &ih, const double *b, double *x, DevScalars *sc, h
   return IUGKP_OK;
 }
 
+// The particle step's form for the face-tallied iterations of a 2D gray
+// single solve with the automatic march and the default block size: emitter
+// tiles with 256 or 512 threads per workgroup, or row stripes.  Measured,
+// not guessed: the first face-tallied iteration runs the planner's choice
+// (not timed: first launches), the next three one candidate each (timed by
+// the step's events), then the fastest, which every later handle of the
+// same class (mesh, particles per emitter, null collisions, free path in
+// cells to half an octave) takes from its first iteration.  The forms give
+// the same tallies bit for bit, so the search changes only the time.
+enum : int { kFormTiles256 = 0, kFormTiles512 = 1, kFormStripes = 2, kForms = 3 };
+struct FormKey {
+  int nx, ny, N, has_null, lam2;
+  bool operator<(const FormKey &o) const
+  {
+    if (nx != o.nx) return nx < o.nx;
+    if (ny != o.ny) return ny < o.ny;
+    if (N != o.N) return N < o.N;
+    if (has_null != o.has_null) return has_null < o.has_null;
+    return lam2 < o.lam2;
+  }
+};
+std::mutex g_form_mu;
+std::map<FormKey, int> g_form_choice;
+
+FormKey form_key(const InstHost &ih)
+{
+  const Mesh &m = ih.d.m;
+  const double cells = ih.d.lam_min / std::min(m.dx, m.dy);
+  return FormKey{m.nx, m.ny, static_cast<int>(ih.d.N), ih.d.has_null,
+                 static_cast<int>(std::lround(2.0 * std::log2(cells)))};
+}
+
+// the form of the next face-tallied iteration (h->form_last: the candidate
+// it measures, or -1)
+int pick_form(iugkp_handle *h)
+{
+  h->form_last = -1;
+  if (h->form >= 0) return h->form;
+  if (!h->form_search) return h->form_default;
+  if (!h->form_warm) {
+    h->form_warm = true;
+    return h->form_default;
+  }
+  h->form_last = h->form_next;
+  return h->form_next;
+}
+
+// after the iteration: its particle-step time for the candidate it measured
+void record_form(iugkp_handle *h, float ms)
+{
+  if (h->form_last < 0) return;
+  h->form_ms[h->form_last] = ms;
+  h->form_last = -1;
+  if (++h->form_next < kForms) return;
+  int best = 0;
+  for (int f = 1; f < kForms; ++f)
+    if (h->form_ms[f] < h->form_ms[best]) best = f;
+  h->form = best;
+  std::lock_guard<std::mutex> lock(g_form_mu);
+  g_form_choice[form_key(h->ih)] = best;
+}
+
 // Enqueue one iteration on the handle's stream: its kernels and the copy of
 // the new scalars into h->hsc (complete_iteration waits for them).
 int enqueue_iteration(iugkp_handle *h, int faces)
@@ -1428,6 +1502,8 @@ int enqueue_iteration(iugkp_handle *h, int faces)
                              (m.ny + 2) * m.nx);
   const int K = h->bh.K;
   int rc = IUGKP_OK;
+  int form = -1;
+  h->form_last = -1;
   if (ih.d.persist) {
     const int nmax = std::max(std::max(m.n_cells, m.n_b), std::max(m.n_fx, m.n_fy));
     iugkp::persist_prepare_kernel<<<cdiv(nmax, 256), 256, 0, s>>>(h->d_inst);
@@ -1447,7 +1523,7 @@ int enqueue_iteration(iugkp_handle *h, int faces)
         <<<dim3(ih.stripe_C, ih.stripe_S), kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R,
                                                                               ih.stripe_C, faces);
     HIP_TRY(hipGetLastError());
-  } else if (faces && ih.stripe_R > 0) {
+  } else if (faces && ih.stripe_R > 0 && (form = pick_form(h)) == kFormStripes) {
     const unsigned long long np =
         static_cast<unsigned long long>(m.n_emit) * static_cast<unsigned long long>(ih.d.N);
     constexpr unsigned int per_block = iugkp::kPresampleBlock * iugkp::kPresamplePer;
@@ -1468,7 +1544,8 @@ int enqueue_iteration(iugkp_handle *h, int faces)
         <<<sg, kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
     HIP_TRY(hipGetLastError());
   } else {
-    rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, h->lds, h->block, faces, 0,
+    const int block = (form == kFormTiles512) ? 512 : h->block;
+    rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, h->lds, block, faces, 0,
                       ih.d.estimator != 0, s);
     if (rc) return rc;
   }
@@ -1507,6 +1584,7 @@ int complete_iteration(iugkp_handle *h)
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
   h->st.ms_march += ms;
+  record_form(h, ms);
   if (ih.d.newton) {
     HIP_TRY(hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
     h->st.ms_cg += ms;
@@ -1608,6 +1686,15 @@ int iugkp_create(const iugkp_problem *problem, const iugkp_options *options, voi
   }
   const int K = h->bh.K;
   h->block = options->block_size ? options->block_size : 256;
+  if (!bands && h->ih.stripe_R > 0 && !h->ih.d.estimator) {
+    h->form_default = h->ih.stripe_pref ? kFormStripes : kFormTiles256;
+    h->form_search = (options->march == 0 && options->block_size == 0);
+    if (h->form_search) {
+      std::lock_guard<std::mutex> lock(g_form_mu);
+      const auto it = g_form_choice.find(form_key(h->ih));
+      if (it != g_form_choice.end()) h->form = it->second;
+    }
+  }
   h->n_tiles = 0;
   for (int k = 0; k < K; ++k) {
     h->n_tiles += static_cast<int>(band_of(h, k).tiles.size());
@@ -1864,6 +1951,15 @@ int iugkp_get_stats(iugkp_handle *h, iugkp_stats *stats)
 {
   if (!h || !stats) return fail(IUGKP_E_INVALID_ARG, "bad arguments");
   *stats = h->st;
+  return IUGKP_OK;
+}
+
+int iugkp_march_tuning(iugkp_handle *h, int *form, float *ms)
+{
+  if (!h) return fail(IUGKP_E_INVALID_ARG, "handle is NULL");
+  if (form) *form = h->form >= 0 ? h->form : (h->form_search ? -1 : h->form_default);
+  if (ms)
+    for (int f = 0; f < kForms; ++f) ms[f] = h->form_ms[f];
   return IUGKP_OK;
 }
 

@@ -221,6 +221,18 @@ class Solver:
         L.check(L.lib().iugkp_get_stats(self.h, C.byref(st)), "iugkp_get_stats")
         return st.as_dict()
 
+    def march_tuning(self):
+        """(form, ms): the particle step's form for face-tallied iterations
+        ("tiles256", "tiles512", "stripes", or None while the handle still
+        measures them) and the measured milliseconds per form (None where not
+        measured)."""
+        form = C.c_int(0)
+        ms = (C.c_float * 3)()
+        L.check(L.lib().iugkp_march_tuning(self.h, C.byref(form), ms), "iugkp_march_tuning")
+        names = ("tiles256", "tiles512", "stripes")
+        return (names[form.value] if form.value >= 0 else None,
+                {n: (float(v) if v >= 0 else None) for n, v in zip(names, ms)})
+
     def residuals(self) -> np.ndarray:
         n = self.stats()["iters"]
         r = np.zeros(max(n, 1))
