@@ -132,21 +132,6 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, src_hash):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    try:
-        with open(path) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
-        return None
-    e = d.get(kernel)
-    if not e or e.get("source_hash") != src_hash:
-        return None
-    return e.get("bytes_per_launch")
-
-
 def cpu_baseline(sample):
     """The CPU oracle on a bounded sample of the same step: for each Kn one
     iteration with `sample` particles, once with and once without the Newton
@@ -372,7 +357,7 @@ def bench_persistent(P, dev, steps, warmup=3):
     out["moves_per_s"] = tot_moves / tot_s
     out["roofline"] = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(ach / HBM_PEAK_GBS, 5),
-                       "traffic": traffic_from_profiles("persist_move_kernel", source_hash()),
+                       "traffic": None,
                        "kernel": "persist_move_kernel", "avg_launch_ms": round(avg_ms, 4),
                        "algorithmic_bytes_per_launch": int(tot_bytes / launches)}
     return out
@@ -529,12 +514,14 @@ def bench_c2_gray(P, dev, steps):
     the right half's, Kn 0.01 on the right: about 99 of 100 candidate
     collisions in the left half are null), 5e7 particles per iteration, face
     tallies every iteration, no Newton step, from the seeded temperature field
-    (every cell emits): one warm-up iteration, then `steps` timed."""
+    (every cell emits): four warm-up iterations (the particle-step form
+    search: an untimed iteration, then one per form), then `steps` timed."""
     import torch
     from synth import seeded_temperature, two_material_2d
     w = two_material_2d(n=512, kn_right=0.01, ratio=100.0, particles=50_000_000, seed=0)
     s = P.Solver(w, device=dev, tally_faces=P.FACES_EVERY, T_init=seeded_temperature(512 * 512))
-    assert s.step(1) == 0
+    assert s.step(4) == 0
+    form, form_ms = s.march_tuning()
     a = s.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -553,7 +540,9 @@ def bench_c2_gray(P, dev, steps):
             "ms_march": round(ms_m, 3), "flights_per_iter": fl // steps,
             "segments_per_flight": round(sg / max(fl, 1), 2),
             "crossings_per_flight": round(cr / max(fl, 1), 2),
-            "segments_per_s": sg / el}
+            "segments_per_s": sg / el, "march_form": form,
+            "march_form_ms": {f: (round(v, 3) if v is not None else None)
+                              for f, v in form_ms.items()}}
 
 
 def cpu_baseline_nongray():

@@ -363,6 +363,11 @@ __device__ __forceinline__ void segment_jump(const Mesh &m, double x0, double y0
 // A segment expected to cross more faces than this is resolved in closed form
 // when no face is tallied (same outcome as the walk, see fly()).
 constexpr double kJumpMinFaces = 6.0;
+// idle lanes of a wavefront that start new particles together (tile march
+// with null collisions), and the particles per lane of a tile from which the
+// lanes refill at all (below it each lane flies its few particles in turn)
+constexpr int kRefillLanes = 32;
+constexpr uint32_t kRefillMinPer = 4;
 
 struct FlyIn {
   Mesh m;
@@ -418,110 +423,152 @@ __device__ __forceinline__ void sample_particle(const FlyIn &a, uint32_t e, uint
   }
 }
 
+// An analog flight's state between two segments: fly() runs one to its end,
+// the tile march's lanes with null collisions run theirs a segment at a time
+// and take the next particle when one ends.
+struct Flight {
+  uint32_t e, k, j;
+  long long q, qy;
+  int ix, iy, stx, sty;
+  double x0, y0, sx, sy, inv_sx, inv_sy;
+  bool runs;
+  // pending candidate tallies: n candidates of weight q in cell (cand_x, cand_y)
+  int cand_x, cand_y;
+  long long cand_n;
+};
+
+__device__ __forceinline__ void flight_start(const FlyIn &a, uint32_t e, uint32_t k, long long q,
+                                             Flight &f)
+{
+  sample_particle(a, e, k, f.ix, f.iy, f.x0, f.y0, f.sx, f.sy);
+  f.e = e;
+  f.k = k;
+  f.j = 0;
+  f.q = q;
+  f.inv_sx = (f.sx != 0.0) ? 1.0 / f.sx : 0.0;
+  f.inv_sy = (f.sy != 0.0) ? 1.0 / f.sy : 0.0;
+  f.stx = (f.sx > 0.0) ? 1 : ((f.sx < 0.0) ? -1 : 0);
+  f.sty = (f.sy > 0.0) ? 1 : ((f.sy < 0.0) ? -1 : 0);
+  f.qy = (f.sty > 0) ? q : -q;
+  // steep segments record their y-faces as runs per column
+  f.runs = a.faces && (fabs(f.sy) > 2.0 * fabs(f.sx));
+  f.cand_x = -1;
+  f.cand_y = -1;
+  f.cand_n = 0;
+}
+
+// The flight's next segment and its tallies: true after a null collision
+// (another segment follows), false when the flight ended (its pending
+// candidates tallied).
+template <class Diff, class YFace, class Wall, class Cand, class Real>
+__device__ __forceinline__ bool flight_segment(const FlyIn &a, Flight &f, Diff &&add_diff,
+                                               YFace &&add_yface, Wall &&add_wall, Cand &&add_cand,
+                                               Real &&add_real, unsigned long long &n_seg,
+                                               unsigned long long &n_cross)
+{
+  const Mesh &m = a.m;
+  // n q modulo 2^64, the same bits as n separate integer additions
+  auto times = [](long long v, long long n) {
+    return static_cast<long long>(static_cast<unsigned long long>(v) * static_cast<unsigned long long>(n));
+  };
+  const uint32_t j = f.j;
+  const double2 us = draw2(2u + j, f.k, f.e + a.e_off, a.slot, a.key0, a.key1);
+  // candidate free path on the common time scale tau_min: -|V_g| tau_min ln(eta)
+  const double ell = -(a.lam_min * log_own(1.0 - us.x));
+  ++n_seg;
+  const int stx = f.stx, sty = f.sty;
+  int ix = f.ix, iy = f.iy;
+  int kx = (stx > 0) ? ix + 1 : ix;
+  int ky = (sty > 0) ? iy + 1 : iy;
+  int bface = -1;
+  int run_a = -1, run_b = -1;   // first and last y-face of the open run
+  if (!a.faces && ell * (fabs(f.sx) / m.dx + fabs(f.sy) / m.dy) > kJumpMinFaces) {
+    segment_jump(m, f.x0, f.y0, ix, iy, stx, sty, f.inv_sx, f.inv_sy, kx, ky, ell, bface, n_cross);
+  } else
+  for (;;) {
+    const double tx = stx ? (static_cast<double>(kx) * m.dx - f.x0) * f.inv_sx : INFINITY;
+    const double ty = sty ? (static_cast<double>(ky) * m.dy - f.y0) * f.inv_sy : INFINITY;
+    const bool along_x = tx <= ty;
+    const double tt = along_x ? tx : ty;
+    if (!(tt < ell)) break;
+    ++n_cross;
+    if (along_x) {
+      if (run_a >= 0) {
+        add_diff(min(run_a, run_b), ix, f.qy);
+        add_diff(max(run_a, run_b) + 1, ix, -f.qy);
+        run_a = -1;
+      }
+      if (kx == 0 || kx == m.nx) {
+        bface = (kx == 0) ? iy : m.ny + iy;
+        break;
+      }
+      ix += stx;
+      kx += stx;
+    } else {
+      if (f.runs) {
+        if (run_a < 0) run_a = ky;
+        run_b = ky;
+      } else if (a.faces) {
+        add_yface(ky, ix, f.qy);
+      }
+      if (ky == 0 || ky == m.ny) {
+        bface = (ky == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
+        break;
+      }
+      iy += sty;
+      ky += sty;
+    }
+  }
+  if (run_a >= 0) {
+    add_diff(min(run_a, run_b), ix, f.qy);
+    add_diff(max(run_a, run_b) + 1, ix, -f.qy);
+  }
+  f.ix = ix;
+  f.iy = iy;
+  bool more = false;
+  if (bface >= 0) {
+    add_wall(bface, f.q);
+  } else if (!a.has_null) {
+    add_real(ix, iy, f.q);   // every candidate is real: W == D
+  } else {
+    // candidates in the same cell one after the other are tallied together
+    if (ix == f.cand_x && iy == f.cand_y) {
+      ++f.cand_n;
+    } else {
+      if (f.cand_n) add_cand(f.cand_x, f.cand_y, times(f.q, f.cand_n));
+      f.cand_x = ix;
+      f.cand_y = iy;
+      f.cand_n = 1;
+    }
+    // accept with probability sigma / sigma_max = tau_min / tau_c
+    const int c = ix + m.nx * iy;
+    if (us.y < a.ratio[c] || j == kMaxSegments - 1) {
+      add_real(ix, iy, f.q);
+    } else {
+      // null collision: keep the direction, restart from the stopping point
+      f.x0 = clamp_to(f.x0 + ell * f.sx, static_cast<double>(ix) * m.dx,
+                      static_cast<double>(ix + 1) * m.dx);
+      if (m.dim == 2)
+        f.y0 = clamp_to(f.y0 + ell * f.sy, static_cast<double>(iy) * m.dy,
+                        static_cast<double>(iy + 1) * m.dy);
+      f.j = j + 1;
+      more = true;
+    }
+  }
+  if (!more && f.cand_n) add_cand(f.cand_x, f.cand_y, times(f.q, f.cand_n));
+  return more;
+}
+
 template <class Diff, class YFace, class Wall, class Cand, class Real>
 __device__ __forceinline__ void fly(const FlyIn &a, uint32_t e, uint32_t k, long long q,
                                     Diff &&add_diff, YFace &&add_yface, Wall &&add_wall,
                                     Cand &&add_cand, Real &&add_real, unsigned long long &n_seg,
                                     unsigned long long &n_cross)
 {
-  const Mesh &m = a.m;
-  int ix, iy;
-  double x0, y0, sx, sy;
-  sample_particle(a, e, k, ix, iy, x0, y0, sx, sy);
-  const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
-  const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
-  const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
-  const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
-  const long long qy = (sty > 0) ? q : -q;
-  // steep segments record their y-faces as runs per column
-  const bool runs = a.faces && (fabs(sy) > 2.0 * fabs(sx));
-  // pending candidate tallies: n candidates of weight q in cell (cand_x, cand_y)
-  int cand_x = -1, cand_y = -1;
-  long long cand_n = 0;
-  // n q modulo 2^64, the same bits as n separate integer additions
-  auto times = [](long long v, long long n) {
-    return static_cast<long long>(static_cast<unsigned long long>(v) * static_cast<unsigned long long>(n));
-  };
-  for (uint32_t j = 0;; ++j) {
-    const double2 us = draw2(2u + j, k, e + a.e_off, a.slot, a.key0, a.key1);
-    // candidate free path on the common time scale tau_min: -|V_g| tau_min ln(eta)
-    const double ell = -(a.lam_min * log_own(1.0 - us.x));
-    ++n_seg;
-    int kx = (stx > 0) ? ix + 1 : ix;
-    int ky = (sty > 0) ? iy + 1 : iy;
-    int bface = -1;
-    int run_a = -1, run_b = -1;   // first and last y-face of the open run
-    if (!a.faces && ell * (fabs(sx) / m.dx + fabs(sy) / m.dy) > kJumpMinFaces) {
-      segment_jump(m, x0, y0, ix, iy, stx, sty, inv_sx, inv_sy, kx, ky, ell, bface, n_cross);
-    } else
-    for (;;) {
-      const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
-      const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
-      const bool along_x = tx <= ty;
-      const double tt = along_x ? tx : ty;
-      if (!(tt < ell)) break;
-      ++n_cross;
-      if (along_x) {
-        if (run_a >= 0) {
-          add_diff(min(run_a, run_b), ix, qy);
-          add_diff(max(run_a, run_b) + 1, ix, -qy);
-          run_a = -1;
-        }
-        if (kx == 0 || kx == m.nx) {
-          bface = (kx == 0) ? iy : m.ny + iy;
-          break;
-        }
-        ix += stx;
-        kx += stx;
-      } else {
-        if (runs) {
-          if (run_a < 0) run_a = ky;
-          run_b = ky;
-        } else if (a.faces) {
-          add_yface(ky, ix, qy);
-        }
-        if (ky == 0 || ky == m.ny) {
-          bface = (ky == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
-          break;
-        }
-        iy += sty;
-        ky += sty;
-      }
-    }
-    if (run_a >= 0) {
-      add_diff(min(run_a, run_b), ix, qy);
-      add_diff(max(run_a, run_b) + 1, ix, -qy);
-    }
-    if (bface >= 0) {
-      add_wall(bface, q);
-      break;
-    }
-    if (!a.has_null) {
-      add_real(ix, iy, q);   // every candidate is real: W == D
-      break;
-    }
-    // candidates in the same cell one after the other are tallied together
-    if (ix == cand_x && iy == cand_y) {
-      ++cand_n;
-    } else {
-      if (cand_n) add_cand(cand_x, cand_y, times(q, cand_n));
-      cand_x = ix;
-      cand_y = iy;
-      cand_n = 1;
-    }
-    // accept with probability sigma / sigma_max = tau_min / tau_c
-    const int c = ix + m.nx * iy;
-    if (us.y < a.ratio[c] || j == kMaxSegments - 1) {
-      add_real(ix, iy, q);
-      break;
-    }
-    // null collision: keep the direction, restart from the stopping point
-    x0 = clamp_to(x0 + ell * sx, static_cast<double>(ix) * m.dx, static_cast<double>(ix + 1) * m.dx);
-    if (m.dim == 2)
-      y0 = clamp_to(y0 + ell * sy, static_cast<double>(iy) * m.dy,
-                    static_cast<double>(iy + 1) * m.dy);
+  Flight f;
+  flight_start(a, e, k, q, f);
+  while (flight_segment(a, f, add_diff, add_yface, add_wall, add_cand, add_real, n_seg, n_cross)) {
   }
-  if (cand_n) add_cand(cand_x, cand_y, times(q, cand_n));
 }
 
 // Expected-value flight of particle k of emitter e carrying q (variance
@@ -614,6 +661,7 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
 {
   extern __shared__ long long lds_words[];
   __shared__ unsigned long long s_cnt[3];
+  __shared__ uint32_t s_next;          // the tile's next unclaimed particle (null collisions)
   const TileDesc td = tiles[blockIdx.x];
   const Inst &in = insts[td.inst];
   if (inst_idle(in, batch)) return;
@@ -651,6 +699,7 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
   const int nwords = static_cast<int>(window_words(win.WX, win.WY, a.has_null, in.lds_walls, m.n_b));
   for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
   if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_next = 0;
   __syncthreads();
 
   auto add_cell = [&](long long *lds_arr, long long *glob, int ix, int iy, long long v) {
@@ -689,28 +738,71 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
   const uint32_t P = static_cast<uint32_t>(n_e) * a.N;
   unsigned long long n_fl = 0, n_seg = 0, n_cross = 0;
   int bad = 0;
-  for (uint32_t p = threadIdx.x; p < P; p += BS) {
+  // particle p of the tile: emitter (tile order) fastest
+  auto emitter_of = [&](uint32_t p, uint32_t &e, uint32_t &k) {
     const uint32_t ei = p % static_cast<uint32_t>(n_e);
-    const uint32_t k = p / static_cast<uint32_t>(n_e);
-    uint32_t e;
+    k = p / static_cast<uint32_t>(n_e);
     if (td.kind == 0) {
       const int ty = static_cast<int>(ei) / td.ex;
       e = static_cast<uint32_t>((td.y0 + ty) * m.nx + td.x0 + (static_cast<int>(ei) - ty * td.ex));
     } else {
       e = static_cast<uint32_t>(m.n_cells + td.x0) + ei;
     }
+  };
+  auto add_w = [&](int cx, int cy, long long v) { add_cell(win.W, a.W, cx, cy, v); };
+  auto add_d = [&](int cx, int cy, long long v) { add_cell(win.D, a.D, cx, cy, v); };
+  if (!(EV && in.estimator) && a.has_null && P >= kRefillMinPer * BS) {
+    // Null collisions make a flight a chain of segments of geometric length:
+    // each lane runs its flight a segment per trip, and the idle lanes of a
+    // wavefront claim the tile's next particles (one LDS atomic per
+    // wavefront) once kRefillLanes of them are idle (or no lane is busy), so
+    // that a wavefront is not held by its longest chain and the sampling of
+    // new particles runs once for many lanes.
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    Flight f;
+    bool live = false, done = false;
+    for (;;) {
+      const unsigned long long busy = __ballot(live);
+      const unsigned long long idle = __ballot(!live && !done);
+      if (!busy && !idle) break;
+      if (!live && !done && (__popcll(idle) >= kRefillLanes || !busy)) {
+        bool got = false;
+        for (;;) {
+          const unsigned long long want = __ballot(true);
+          const int lead = __ffsll(static_cast<long long>(want)) - 1;
+          uint32_t first = 0;
+          if (lane == lead) first = atomicAdd(&s_next, static_cast<uint32_t>(__popcll(want)));
+          first = static_cast<uint32_t>(__shfl(static_cast<int>(first), lead, 64));
+          const uint32_t p = first + static_cast<uint32_t>(__popcll(want & ((1ull << lane) - 1ull)));
+          if (p >= P) break;
+          uint32_t e, k;
+          emitter_of(p, e, k);
+          const long long q = a.base[e] + ((k < a.rem[e]) ? 1 : 0);
+          if (q == 0) continue;
+          flight_start(fa, e, k, q, f);
+          got = true;
+          break;
+        }
+        if (got) {
+          ++n_fl;
+          live = true;
+        } else {
+          done = true;
+        }
+      }
+      if (live) live = flight_segment(fa, f, add_diff, add_yface, add_wall, add_w, add_d, n_seg, n_cross);
+    }
+  } else
+  for (uint32_t p = threadIdx.x; p < P; p += BS) {
+    uint32_t e, k;
+    emitter_of(p, e, k);
     const long long q = a.base[e] + ((k < a.rem[e]) ? 1 : 0);
     if (q == 0) continue;
     ++n_fl;
     if (EV && in.estimator)
-      fly_expected(fa, e, k, q, add_yface, add_wall,
-                   [&](int cx, int cy, long long v) { add_cell(win.W, a.W, cx, cy, v); },
-                   [&](int cx, int cy, long long v) { add_cell(win.D, a.D, cx, cy, v); }, n_seg,
-                   n_cross, bad);
+      fly_expected(fa, e, k, q, add_yface, add_wall, add_w, add_d, n_seg, n_cross, bad);
     else
-      fly(fa, e, k, q, add_diff, add_yface, add_wall,
-          [&](int cx, int cy, long long v) { add_cell(win.W, a.W, cx, cy, v); },
-          [&](int cx, int cy, long long v) { add_cell(win.D, a.D, cx, cy, v); }, n_seg, n_cross);
+      fly(fa, e, k, q, add_diff, add_yface, add_wall, add_w, add_d, n_seg, n_cross);
   }
   if (bad) atomicOr(&a.sc->flags, 2);
   if (n_fl) {
