@@ -191,7 +191,10 @@ def bench_batch(P, dev, count):
     kw = dict(rng_mode=P.RNG_CRN, tally_faces=P.FACES_FINAL, max_iters=60, res_tol=1e-6,
               cg_precond=P.PRECOND_MG)
     seq_status = []
-    solvers = [P.Solver(w, device=dev, **kw) for w in ws]
+    # (the sequential solves take the planner's particle-step form: every
+    # instance is a class of its own, and a form search per solve would only
+    # add its candidate iterations to the sequential time)
+    solvers = [P.Solver(w, device=dev, block_size=256, **kw) for w in ws]
     torch.cuda.synchronize()
     a = time.perf_counter()
     for s in solvers:
@@ -211,6 +214,7 @@ def bench_batch(P, dev, count):
     torch.cuda.synchronize()
     bat = time.perf_counter() - a
     tune_a, tune_c, groups = bs.tuning()
+    edges = bs.tile_edges()
     bat_status = [o[3]["status"] for o in outs]
     iters = [o[3]["iters"] for o in outs]
     flights = sum(o[3]["tot_flights"] for o in outs)
@@ -227,8 +231,12 @@ def bench_batch(P, dev, count):
                           "multigrid_groups_last_replay": {str(int(g)): int((groups == g).sum())
                                                            for g in sorted(set(groups.tolist()))
                                                            if g > 0},
+                          "tile_edges": {str(int(e)): int((edges == e).sum())
+                                         for e in sorted(set(edges.tolist()))},
                           "note": "group sizes of the multigrid pool chosen before every replay "
-                                  "from a fit of the measured job durations"},
+                                  "from a fit of the measured job durations; tile edges of the "
+                                  "tile march chosen per instance class from the device time per "
+                                  "flight of a replay with each (the second and third replays)"},
             "note": "per-instance setup (allocation, Newton operator) excluded from both timings"}
 
 

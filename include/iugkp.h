@@ -386,6 +386,17 @@ int iugkp_batch_create(const iugkp_problem *const *problems,
 int iugkp_batch_solve(iugkp_batch *b, double *const *T_out, double *const *qx_out,
                       double *const *qy_out, iugkp_stats *stats);
 void iugkp_batch_destroy(iugkp_batch *b);
+/* Tile edges of a batch's particle step (cells per side of an emitter tile,
+ * 8 or 16; the A4 march of Sec. 3.1 run over every instance's tiles in one
+ * launch): edges (host int[n]) receives each instance's.  An instance whose
+ * class (mesh, particles per emitter, null collisions, free path in cells to
+ * half an octave) no earlier batch of the process measured runs its second
+ * replay with 8 and its third with 16, the device timing each workgroup, and
+ * keeps the edge with the smaller device time per flight; the process keeps
+ * the choice for the class.  The tallies do not depend on the tiles.
+ * Returns 0, or IUGKP_E_INVALID_ARG for NULL arguments. */
+int iugkp_batch_tiles(iugkp_batch *b, int *edges);
+
 /* The autotuner of the batch's multigrid CG pool.  Before every replay the
  * library picks each multigrid instance's group of workgroups from a model of
  * one CG iteration, per_iter_us + per_cell_us * cells / group microseconds,

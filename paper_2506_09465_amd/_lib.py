@@ -88,6 +88,7 @@ SIGNATURES = [
     ("iugkp_dev_philox", C.c_int, [P, C.c_uint32, C.c_uint32, P, C.c_int64, P]),
     ("iugkp_dev_math", C.c_int, [C.c_int, P, P, P, C.c_int64, P]),
     ("iugkp_batch_tuning", C.c_int, [P, P, P, P]),
+    ("iugkp_batch_tiles", C.c_int, [P, P]),
     ("iugkp_diffusion_solve", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                         C.c_double, P, P, P, P, P, C.c_double, C.c_int, P, P]),
     ("iugkp_diffusion_solve_noalloc", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double,

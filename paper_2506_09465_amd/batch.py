@@ -90,3 +90,10 @@ class BatchSolver:
         L.check(L.lib().iugkp_batch_tuning(self.h, C.addressof(a), C.addressof(c),
                                            g.ctypes.data), "iugkp_batch_tuning")
         return a.value, c.value, g
+
+    def tile_edges(self):
+        """The tile march's autotuned tile edge (8 or 16 cells) of each instance."""
+        import numpy as np
+        e = np.zeros(len(self.ws), dtype=np.int32)
+        L.check(L.lib().iugkp_batch_tiles(self.h, e.ctypes.data), "iugkp_batch_tiles")
+        return e

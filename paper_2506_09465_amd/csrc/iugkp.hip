@@ -52,8 +52,8 @@ constexpr int kStripeBlock = 1024;           // threads of a stripe workgroup
 constexpr int kStripeMinRows = 4;
 constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of a CG workgroup
 constexpr int kPersistBlock = 256;           // particles per move workgroup
-constexpr int kTileX = 8, kTileY = 8;        // emitter tile of one workgroup (cells)
-constexpr int kWallSeg = 8;                  // wall faces per workgroup
+constexpr int kTileX = 8;                    // emitter tile of one workgroup (cells per side;
+                                             // wall faces per workgroup); batches also 16
 constexpr int kWindowHalo = 12;              // window margin around a tile (cells)
 constexpr size_t kLdsWordsMax = 6144;        // 48 KB of 64-bit tallies per workgroup
 constexpr int kLdsWallsMax = 1024;
@@ -261,7 +261,10 @@ int scale_exponent(const iugkp_problem *p, double tau_min, const std::vector<dou
 
 // Tile table and LDS window: the whole domain when its tallies fit in LDS,
 // otherwise a window of the tile plus a margin, placed inside the domain.
-void plan_tiles(InstHost &ih)
+// Emitter tiles of edge x edge cells (and wall segments of edge faces), each
+// with its LDS window: the whole domain when it fits, else the tile and
+// kWindowHalo cells around it.
+void plan_tiles(InstHost &ih, int edge = kTileX)
 {
   Inst &d = ih.d;
   const Mesh &m = d.m;
@@ -272,8 +275,8 @@ void plan_tiles(InstHost &ih)
     d.WX = m.nx;
     d.WY = m.ny;
   } else {
-    d.WX = std::min(m.nx, kTileX + 2 * kWindowHalo);
-    d.WY = std::min(m.ny, kTileY + 2 * kWindowHalo);
+    d.WX = std::min(m.nx, edge + 2 * kWindowHalo);
+    d.WY = std::min(m.ny, edge + 2 * kWindowHalo);
   }
   auto place = [](int lo, int extent, int W, int n) {
     int w0 = lo - (W - extent) / 2;
@@ -282,25 +285,25 @@ void plan_tiles(InstHost &ih)
     return w0;
   };
   ih.tiles.clear();
-  for (int ty = 0; ty < m.ny; ty += kTileY)
-    for (int tx = 0; tx < m.nx; tx += kTileX) {
+  for (int ty = 0; ty < m.ny; ty += edge)
+    for (int tx = 0; tx < m.nx; tx += edge) {
       TileDesc t{};
       t.kind = 0;
       t.x0 = tx;
       t.y0 = ty;
-      t.ex = std::min(kTileX, m.nx - tx);
-      t.ey = std::min(kTileY, m.ny - ty);
+      t.ex = std::min(edge, m.nx - tx);
+      t.ey = std::min(edge, m.ny - ty);
       t.wx0 = whole_domain ? 0 : place(tx, t.ex, d.WX, m.nx);
       t.wy0 = whole_domain ? 0 : place(ty, t.ey, d.WY, m.ny);
       ih.tiles.push_back(t);
     }
   // wall segments: left rows, right rows, bottom columns, top columns
   auto wall = [&](int b_first, int count, int along_x, int side_hi) {
-    for (int s0 = 0; s0 < count; s0 += kWallSeg) {
+    for (int s0 = 0; s0 < count; s0 += edge) {
       TileDesc t{};
       t.kind = 1;
       t.x0 = b_first + s0;
-      t.ex = std::min(kWallSeg, count - s0);
+      t.ex = std::min(edge, count - s0);
       t.ey = 1;
       if (whole_domain) {
         t.wx0 = 0;
@@ -1195,23 +1198,23 @@ int setup_bands(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, I
 
 template <bool EV>
 void launch_march_as(const Inst *d_insts, const TileDesc *d_tiles, int n_tiles, size_t lds,
-                     int block, int faces_mode, int batch, hipStream_t s)
+                     int block, int faces_mode, int batch, unsigned long long *clk, hipStream_t s)
 {
   switch (block) {
-    case 64: iugkp::march_kernel<64, EV><<<n_tiles, 64, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
-    case 128: iugkp::march_kernel<128, EV><<<n_tiles, 128, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
-    case 512: iugkp::march_kernel<512, EV><<<n_tiles, 512, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
-    case 1024: iugkp::march_kernel<1024, EV><<<n_tiles, 1024, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
-    default: iugkp::march_kernel<256, EV><<<n_tiles, 256, lds, s>>>(d_insts, d_tiles, faces_mode, batch); break;
+    case 64: iugkp::march_kernel<64, EV><<<n_tiles, 64, lds, s>>>(d_insts, d_tiles, faces_mode, batch, clk); break;
+    case 128: iugkp::march_kernel<128, EV><<<n_tiles, 128, lds, s>>>(d_insts, d_tiles, faces_mode, batch, clk); break;
+    case 512: iugkp::march_kernel<512, EV><<<n_tiles, 512, lds, s>>>(d_insts, d_tiles, faces_mode, batch, clk); break;
+    case 1024: iugkp::march_kernel<1024, EV><<<n_tiles, 1024, lds, s>>>(d_insts, d_tiles, faces_mode, batch, clk); break;
+    default: iugkp::march_kernel<256, EV><<<n_tiles, 256, lds, s>>>(d_insts, d_tiles, faces_mode, batch, clk); break;
   }
 }
 
 // ev: some instance takes the expected-value estimator
 int launch_march(const Inst *d_insts, const TileDesc *d_tiles, int n_tiles, size_t lds, int block,
-                 int faces_mode, int batch, bool ev, hipStream_t s)
+                 int faces_mode, int batch, bool ev, hipStream_t s, unsigned long long *clk = nullptr)
 {
-  if (ev) launch_march_as<true>(d_insts, d_tiles, n_tiles, lds, block, faces_mode, batch, s);
-  else launch_march_as<false>(d_insts, d_tiles, n_tiles, lds, block, faces_mode, batch, s);
+  if (ev) launch_march_as<true>(d_insts, d_tiles, n_tiles, lds, block, faces_mode, batch, clk, s);
+  else launch_march_as<false>(d_insts, d_tiles, n_tiles, lds, block, faces_mode, batch, clk, s);
   HIP_TRY(hipGetLastError());
   return IUGKP_OK;
 }
@@ -2419,6 +2422,16 @@ struct iugkp_batch {
   // group, the group of the last replay (0: not run), and the clock rate
   std::vector<int> mg_gmax, mg_last;
   double clock_khz = 0.0;
+  // the autotuned tile sizes: per instance the tile edge (8 or 16 cells), its
+  // range of the tile table, the measured device time per flight with each
+  // edge (-1: not measured); the search phase (0: first replay, 1: edge 8
+  // timed, 2: edge 16 timed, 3: chosen); the workgroups' clock stamps
+  std::vector<int> edge, tile_first, tile_count;
+  std::vector<double> cost8, cost16;
+  std::vector<char> edge_known;      // the class's edge came from an earlier batch
+  int tile_phase = 3;
+  unsigned long long *d_clk = nullptr;
+  std::vector<unsigned long long> h_clk;
   iugkp::MGArgs *d_mg_args = nullptr;   // the multigrid jobs' arguments, per instance
   DevScalars *d_scs = nullptr;       // every instance's scalars, contiguous
   unsigned int *d_bars = nullptr;    // every instance's CG barrier [2], kBarStride apart
@@ -2448,10 +2461,92 @@ void free_batch(iugkp_batch *b)
   if (b->d_scs) (void)hipFree(b->d_scs);
   if (b->d_bars) (void)hipFree(b->d_bars);
   if (b->d_mg_args) (void)hipFree(b->d_mg_args);
+  if (b->d_clk) (void)hipFree(b->d_clk);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->own) (void)hipStreamDestroy(b->own);
   delete b;
+}
+
+// Tile sizes of a batch (A9's autotuner for the tile march).  One launch runs
+// every instance's tiles; an instance's tiles are edge x edge emitter cells
+// with 8 or 16 cells.  The device stamps each workgroup's start and end and
+// its flights; for every instance of a class not yet measured the second
+// replay runs edge 8 and the third edge 16, and the instance keeps the edge
+// with the smaller device time per flight (the sum of its workgroups'
+// durations over its flights: the compute-unit time it takes while the batch
+// fills the GPU), which the process keeps for the class (the same key as the
+// particle-step form).  The tallies do not depend on the tiles.
+std::mutex g_tile_mu;
+std::map<FormKey, int> g_tile_choice;
+
+// every instance's tiles with its edge, the instances and the tile table
+// uploaded, the largest instances first (their workgroups start early)
+int batch_layout(iugkp_batch *b)
+{
+  const int n = static_cast<int>(b->insts.size());
+  for (int i = 0; i < n; ++i) plan_tiles(b->insts[i], b->edge[i]);
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return b->insts[a].tiles.size() * b->insts[a].d.N > b->insts[c].tiles.size() * b->insts[c].d.N;
+  });
+  int tile0 = 0;
+  for (int i : order) {
+    const int rc = upload_inst(b->insts[i], i, b->d_insts, b->d_tiles, tile0, b->stream);
+    if (rc) return rc;
+    b->tile_first[i] = tile0;
+    b->tile_count[i] = static_cast<int>(b->insts[i].tiles.size());
+    tile0 += b->tile_count[i];
+  }
+  b->n_tiles = tile0;
+  return IUGKP_OK;
+}
+
+// device time per flight of each instance that ran in the last replay (its
+// workgroups' stamps), into cost (-1 where no flight)
+int read_tile_costs(iugkp_batch *b, const std::vector<char> &ran, std::vector<double> &cost)
+{
+  const int n = static_cast<int>(b->insts.size());
+  HIP_TRY(hipMemcpy(b->h_clk.data(), b->d_clk, 3 * static_cast<size_t>(b->n_tiles) *
+                                                  sizeof(unsigned long long),
+                    hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) {
+    if (!ran[i]) continue;
+    double t = 0.0, f = 0.0;
+    for (int k = b->tile_first[i]; k < b->tile_first[i] + b->tile_count[i]; ++k) {
+      const unsigned long long *c = &b->h_clk[3 * static_cast<size_t>(k)];
+      if (c[1] > c[0]) t += static_cast<double>(c[1] - c[0]);
+      f += static_cast<double>(c[2]);
+    }
+    cost[i] = (f > 0.0) ? t / f : -1.0;
+  }
+  return IUGKP_OK;
+}
+
+int enqueue_batch_iteration(iugkp_batch *b);
+
+// capture one iteration of the whole batch into b->exec (again after a
+// change of tiles)
+int capture_batch(iugkp_batch *b)
+{
+  hipStream_t s = b->own;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_batch_iteration(b);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(s, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  HIP_TRY(ce);
+  b->graph = g;
+  HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return IUGKP_OK;
 }
 
 // The per-iteration sequence of a batch; every kernel skips finished instances.
@@ -2460,7 +2555,8 @@ int enqueue_batch_iteration(iugkp_batch *b)
   hipStream_t s = b->own;
   const int n = static_cast<int>(b->insts.size());
   iugkp::prepare_kernel<<<dim3(cdiv(b->max_prep, 256), n), 256, 0, s>>>(b->d_insts, -1, 1);
-  int rc = launch_march(b->d_insts, b->d_tiles, b->n_tiles, b->lds_max, 256, -1, 1, b->any_ev, s);
+  int rc = launch_march(b->d_insts, b->d_tiles, b->n_tiles, b->lds_max, 256, -1, 1, b->any_ev, s,
+                        b->d_clk);
   if (rc) return rc;
   iugkp::reconstruct_y_kernel<<<dim3(cdiv(b->max_nx, 4), n), 256, 0, s>>>(b->d_insts, -1, 1);
   iugkp::reconstruct_x_kernel<<<dim3(cdiv(b->max_ny, 4), n), 256, 0, s>>>(b->d_insts, -1, 1);
@@ -2661,8 +2757,12 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
       free_batch(b);
       return rc;
     }
-    const InstHost &ih = b->insts[i];
+    InstHost &ih = b->insts[i];
     const Mesh &m = ih.d.m;
+    // (the table holds the edge-8 tiles, the most; the LDS window of either edge)
+    plan_tiles(ih, 16);
+    b->lds_max = std::max(b->lds_max, ih.lds_bytes);
+    plan_tiles(ih, kTileX);
     b->n_tiles += static_cast<int>(ih.tiles.size());
     b->lds_max = std::max(b->lds_max, ih.lds_bytes);
     b->any_newton |= ih.d.newton;
@@ -2825,22 +2925,47 @@ int iugkp_batch_create(const iugkp_problem *const *problems, const iugkp_options
     free_batch(b);
     return fail(IUGKP_E_DEVICE, "stream or event creation failed");
   }
-  // the largest instances first in the tile table, so their workgroups start early
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-    return b->insts[a].tiles.size() * b->insts[a].d.N > b->insts[c].tiles.size() * b->insts[c].d.N;
-  });
-  int tile0 = 0;
-  for (int i : order) {
-    const int rc = upload_inst(b->insts[i], i, b->d_insts, b->d_tiles, tile0, b->stream);
-    if (rc) {
-      free_batch(b);
-      return rc;
+  // tile edges: a class already measured in this process takes its edge; the
+  // others are measured on the second and third replays
+  const int max_tiles = b->n_tiles;
+  b->edge.assign(n, kTileX);
+  b->tile_first.assign(n, 0);
+  b->tile_count.assign(n, 0);
+  b->cost8.assign(n, -1.0);
+  b->cost16.assign(n, -1.0);
+  b->edge_known.assign(n, 0);
+  b->tile_phase = 3;
+  {
+    std::lock_guard<std::mutex> lock(g_tile_mu);
+    for (int i = 0; i < n; ++i) {
+      const auto it = g_tile_choice.find(form_key(b->insts[i]));
+      if (it != g_tile_choice.end()) {
+        b->edge[i] = it->second;
+        b->edge_known[i] = 1;
+      } else {
+        b->tile_phase = 0;
+      }
     }
-    tile0 += static_cast<int>(b->insts[i].tiles.size());
+  }
+  if (hipMalloc(reinterpret_cast<void **>(&b->d_clk), 3 * static_cast<size_t>(max_tiles) *
+                                                          sizeof(unsigned long long)) != hipSuccess) {
+    free_batch(b);
+    return fail(IUGKP_E_NOMEM, "allocation failed");
+  }
+  b->h_clk.assign(3 * static_cast<size_t>(max_tiles), 0);
+  const int rc = batch_layout(b);
+  if (rc) {
+    free_batch(b);
+    return rc;
   }
   *out = b;
+  return IUGKP_OK;
+}
+
+int iugkp_batch_tiles(iugkp_batch *b, int *edges)
+{
+  if (!b || !edges) return fail(IUGKP_E_INVALID_ARG, "bad arguments");
+  for (size_t i = 0; i < b->edge.size(); ++i) edges[i] = b->edge[i];
   return IUGKP_OK;
 }
 
@@ -2871,24 +2996,43 @@ int iugkp_batch_solve(iugkp_batch *b, double *const *T_out, double *const *qx_ou
   HIP_TRY(hipEventRecord(b->ev_in, b->stream));
   HIP_TRY(hipStreamWaitEvent(s, b->ev_in, 0));
   // capture one iteration of the whole batch, replay until every instance is done
-  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  int rc = enqueue_batch_iteration(b);
-  hipGraph_t g = nullptr;
-  const hipError_t ce = hipStreamEndCapture(s, &g);
-  if (rc) {
-    if (g) (void)hipGraphDestroy(g);
-    return rc;
-  }
-  HIP_TRY(ce);
-  b->graph = g;
-  HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  int rc = capture_batch(b);
+  if (rc) return rc;
   int cap = 0;
   for (const auto &ih : b->insts) cap = std::max(cap, ih.d.max_iters + ih.d.avg_iters + 2);
+  std::vector<char> ran(n, 0);          // instances that ran in the last replay
   for (int it = 0; it <= cap; ++it) {
     HIP_TRY(hipMemcpyAsync(b->hsc, b->d_scs, n * sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     bool all_done = true;
     for (int i = 0; i < n; ++i) all_done = all_done && (b->hsc[i].state == 2);
+    // tile sizes: the costs of the replay just run, then the next phase
+    if (it > 0 && b->tile_phase < 3 && !all_done) {
+      if (b->tile_phase == 0) {
+        b->tile_phase = 1;                   // (the first replay: first launches, not used)
+      } else if (b->tile_phase == 1) {
+        if ((rc = read_tile_costs(b, ran, b->cost8))) return rc;
+        for (int i = 0; i < n; ++i)
+          if (!b->edge_known[i]) b->edge[i] = 16;
+        if ((rc = batch_layout(b)) || (rc = capture_batch(b))) return rc;
+        b->tile_phase = 2;
+      } else {
+        if ((rc = read_tile_costs(b, ran, b->cost16))) return rc;
+        std::lock_guard<std::mutex> lock(g_tile_mu);
+        for (int i = 0; i < n; ++i) {
+          if (b->edge_known[i]) continue;
+          if (b->cost8[i] >= 0.0 && b->cost16[i] >= 0.0) {
+            b->edge[i] = (b->cost16[i] < b->cost8[i]) ? 16 : kTileX;
+            g_tile_choice[form_key(b->insts[i])] = b->edge[i];
+          } else {
+            b->edge[i] = kTileX;
+          }
+        }
+        if ((rc = batch_layout(b)) || (rc = capture_batch(b))) return rc;
+        b->tile_phase = 3;
+      }
+    }
+    for (int i = 0; i < n; ++i) ran[i] = (b->hsc[i].state != 2) ? 1 : 0;
     if (b->mg_pool.used) {
       std::lock_guard<std::mutex> lock(g_mg_model_mu);
       for (int i = 0; i < n; ++i) {

@@ -657,7 +657,8 @@ __device__ __forceinline__ void fly_expected(const FlyIn &a, uint32_t e, uint32_
 template <int BS, bool EV>
 __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ insts,
                                                    const TileDesc *__restrict__ tiles,
-                                                   int faces_mode, int batch)
+                                                   int faces_mode, int batch,
+                                                   unsigned long long *__restrict__ clk)
 {
   extern __shared__ long long lds_words[];
   __shared__ unsigned long long s_cnt[3];
@@ -665,6 +666,9 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
   const TileDesc td = tiles[blockIdx.x];
   const Inst &in = insts[td.inst];
   if (inst_idle(in, batch)) return;
+  // (clk: the workgroup's start and end on the device clock and its flights,
+  // for the batch's tile-size choice)
+  const unsigned long long t_start = clk ? static_cast<unsigned long long>(wall_clock64()) : 0ull;
   struct {
     Mesh m;
     double lam_min;
@@ -834,6 +838,14 @@ __global__ __launch_bounds__(BS) void march_kernel(const Inst *__restrict__ inst
     atomicAdd(&a.sc->flights, s_cnt[0]);
     atomicAdd(&a.sc->segments, s_cnt[1]);
     atomicAdd(&a.sc->crossings, s_cnt[2]);
+  }
+  if (clk) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      clk[3 * blockIdx.x] = t_start;
+      clk[3 * blockIdx.x + 1] = static_cast<unsigned long long>(wall_clock64());
+      clk[3 * blockIdx.x + 2] = s_cnt[0];
+    }
   }
 }
 

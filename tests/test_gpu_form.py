@@ -62,3 +62,34 @@ def test_form_search_equals_tiles_and_is_kept(gpu, make):
     assert f4 is not None and all(v is None for v in ms4.values())
     for h in (s, ref, s2, s3, s4):
         h.close()
+
+
+def test_batch_tile_edges_are_measured_then_kept(gpu):
+    """A batch measures the tile edge of each instance class (8 or 16 cells,
+    replays two and three), a second batch of the same classes starts with
+    the edges, and both batches give the single solves' temperatures."""
+    ws = [cavity_2d(n=71, ny=43, kn=0.02, particles=150_000, seed=31),
+          two_material_2d(n=57, kn_right=0.05, ratio=20.0, particles=150_000, seed=32),
+          cavity_2d(n=37, ny=29, kn=0.3, particles=60_000, seed=33)]
+    kw = dict(rng_mode=gpu.RNG_CRN, tally_faces=gpu.FACES_FINAL, max_iters=8, res_tol=0.0,
+              newton=False)
+    singles = []
+    for w in ws:
+        s = gpu.Solver(w, block_size=256, **kw)
+        rc, T, qx, qy, _ = s.solve()
+        singles.append((rc, T.cpu().numpy(), qx.cpu().numpy(), qy.cpu().numpy()))
+        s.close()
+    edges = []
+    for _ in range(2):
+        bs = gpu.BatchSolver(ws, **kw)
+        rc, outs = bs.solve()
+        e = bs.tile_edges()
+        assert set(e.tolist()) <= {8, 16}
+        edges.append(e.tolist())
+        for (rc1, T1, qx1, qy1), (T2, qx2, qy2, st) in zip(singles, outs):
+            assert st["status"] == rc1
+            assert np.array_equal(T1, T2.cpu().numpy())
+            assert np.array_equal(qx1, qx2.cpu().numpy())
+            assert np.array_equal(qy1[:len(qy2)], qy2.cpu().numpy()[:len(qy1)])
+        bs.close()
+    assert edges[0] == edges[1]
