@@ -671,7 +671,8 @@ def collect_counters(forms=None, timeout_s=240):
             cmd += ["--forms", json.dumps(forms)]
         cmds.append(" ".join(["rocprofv3", "--pmc", *counters, "-d", "<dir>", "-o", "run",
                               "--output-format", "csv", "--", "python3", "bench.py",
-                              "--profile-pass"]))
+                              "--profile-pass"] +
+                             (["--forms", "'" + json.dumps(forms) + "'"] if forms else [])))
         try:
             r = subprocess.run(cmd, cwd="/tmp", env=env, timeout=timeout_s,
                                stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
