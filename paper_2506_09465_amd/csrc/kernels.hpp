@@ -999,8 +999,10 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
   const int lane = static_cast<int>(threadIdx.x & 63);
   const unsigned long long pc = static_cast<unsigned long long>(blockIdx.x) * BS + threadIdx.x;
   if (pc < total) {
-    const uint32_t kk = static_cast<uint32_t>(pc / n_emit);
-    const uint32_t e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
+    // (32-bit: the planner keeps the particles below 2^32)
+    const uint32_t pc32 = static_cast<uint32_t>(pc), ne32 = static_cast<uint32_t>(n_emit);
+    const uint32_t kk = pc32 / ne32;
+    const uint32_t e = pc32 - kk * ne32;
     const long long q = in.base[e] + ((kk < in.rem[e]) ? 1 : 0);
     if (q != 0) {
       int ix = 0, iy = 0;
@@ -1268,9 +1270,9 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
       const unsigned char *rb = static_cast<const unsigned char *>(rec.r) +
                                 static_cast<size_t>(slot) * (fa.has_null ? sizeof(PRecN) : sizeof(PRec));
       const PRec &rp = *reinterpret_cast<const PRec *>(rb);
-      const unsigned long long pc = rp.pc;
-      kk = static_cast<uint32_t>(pc / n_emit);
-      e = static_cast<uint32_t>(pc - static_cast<unsigned long long>(kk) * n_emit);
+      const uint32_t pc = rp.pc, ne32 = static_cast<uint32_t>(n_emit);
+      kk = pc / ne32;
+      e = pc - kk * ne32;
       q = rp.q;
       const uint32_t cs = rp.cell, ce = rp.cell_e;
       ix = static_cast<int>(cs & 0xffffu);
