@@ -267,7 +267,29 @@ def bench_adjoint(P, dev):
             "grad_source_norm": src.grad.norm().item()}
 
 
-def bench_nongray(P, dev, steps, warmup):
+def tally_roofline(ceil, tallies, launches, ms_launch, bytes_launch, kernel):
+    """A particle step's roofline: its algorithmic tally updates (one per face
+    crossed, per candidate and per final deposit or absorption) per second
+    against the LDS int64-atomic ceiling."""
+    t = tallies / launches
+    rate = t / (ms_launch / 1e3) if ms_launch else None
+    return {"bound": "atomics", "achieved": rate, "peak": ceil["lds_int64_per_s"],
+            "unit": "tally atomics/s", "frac": round(rate / ceil["lds_int64_per_s"], 5) if rate else None,
+            "traffic": None, "kernel": kernel, "avg_launch_ms": round(ms_launch, 4),
+            "algorithmic_atomics_per_launch": int(t), "algorithmic_bytes_per_launch": int(bytes_launch)}
+
+
+def atomics_ceiling(P):
+    """The tally-throughput ceilings a particle step works against: int64
+    atomic adds to random words of a 2 MB global array (the size of the
+    cavity's tallies) and of a workgroup's LDS array."""
+    return {"global_int64_2MB_per_s": P.dev_atomics(False, n_words=262144),
+            "lds_int64_per_s": P.dev_atomics(True),
+            "note": "int64 atomic adds to random words, every lane of full wavefronts: of a "
+                    "2 MB global array, and of a 4096-word LDS array per workgroup"}
+
+
+def bench_nongray(P, dev, steps, warmup, ceil):
     """The non-gray workload: 512 x 512 two-material square (left half's
     relaxation times 100x the right half's), 40 bands of the sine dispersion
     (Kn 1e-3 .. 10), Gaussian source of width 0.05 L at the centre, 5e7
@@ -302,11 +324,7 @@ def bench_nongray(P, dev, steps, warmup):
             "crossings_per_flight": round(cr / max(fl, 1), 2),
             "segments_per_flight": round(sg / max(fl, 1), 2),
             "march_GBs_algorithmic": round(mb / (ms_m / 1e3) / 1e9, 2) if ms_m else None,
-            "roofline": {"bound": "hbm", "achieved": round(mb / (ms_m / 1e3) / 1e9, 2) if ms_m else None,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(mb / (ms_m / 1e3) / 1e9 / HBM_PEAK_GBS, 5) if ms_m else None,
-                         "traffic": None, "kernel": "march_kernel",
-                         "algorithmic_bytes_per_launch": int(mb)}}
+            "roofline": tally_roofline(ceil, cr + sg + fl, steps, ms_m, mb, "march_kernel")}
     s.close()
     return out
 
@@ -517,7 +535,7 @@ def bench_c0_time_to_steady(P, dev):
     return out
 
 
-def bench_c2_gray(P, dev, steps):
+def bench_c2_gray(P, dev, steps, ceil):
     """The 512 x 512 gray two-material square (left half's relaxation time 100x
     the right half's, Kn 0.01 on the right: about 99 of 100 candidate
     collisions in the left half are null), 5e7 particles per iteration, face
@@ -550,7 +568,10 @@ def bench_c2_gray(P, dev, steps):
             "crossings_per_flight": round(cr / max(fl, 1), 2),
             "segments_per_s": sg / el, "march_form": form,
             "march_form_ms": {f: (round(v, 3) if v is not None else None)
-                              for f, v in form_ms.items()}}
+                              for f, v in form_ms.items()},
+            "roofline": tally_roofline(ceil, cr + sg + fl, steps, ms_m,
+                                       march_bytes(fl, cr, sg, b["n_emitters"] * steps, True) / steps,
+                                       "march_stripes_kernel" if form == "stripes" else "march_kernel")}
 
 
 def cpu_baseline_nongray():
@@ -754,7 +775,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.nongray_only:
-        print(json.dumps(bench_nongray(P, dev, args.steps, 20)), flush=True)
+        print(json.dumps(bench_nongray(P, dev, args.steps, 20, atomics_ceiling(P))), flush=True)
         return
     if args.persistent_only:
         print(json.dumps(bench_persistent(P, dev, args.steps)), flush=True)
@@ -852,13 +873,7 @@ def main():
         tot["launches"] += K
 
     src = source_hash()
-    # the tally-throughput ceilings the particle step works against: int64
-    # atomic adds to random words of a 2 MB global array (the size of the
-    # cavity's tallies) and of a workgroup's LDS array
-    ceil = {"global_int64_2MB_per_s": P.dev_atomics(False, n_words=262144),
-            "lds_int64_per_s": P.dev_atomics(True),
-            "note": "int64 atomic adds to random words, every lane of full wavefronts: of a "
-                    "2 MB global array, and of a 4096-word LDS array per workgroup"}
+    ceil = atomics_ceiling(P)
     counters = None if args.no_counters else collect_counters(
         {k: v["march_form"] for k, v in per_kn.items() if v.get("march_form")})
     cnt_ok = counters is not None and "error" not in counters
@@ -981,7 +996,7 @@ def main():
         out["expected_value"] = bench_expected(P, dev)
 
     if not args.no_nongray:
-        out["nongray"] = bench_nongray(P, dev, args.steps, 20)
+        out["nongray"] = bench_nongray(P, dev, args.steps, 20, ceil)
         if not args.no_cpu_baseline:
             out["nongray"]["cpu_baseline"] = cpu_baseline_nongray()
 
@@ -989,7 +1004,7 @@ def main():
         out["c0_time_to_steady"] = bench_c0_time_to_steady(P, dev)
 
     if not args.no_c2_gray:
-        out["c2_gray"] = bench_c2_gray(P, dev, 3)
+        out["c2_gray"] = bench_c2_gray(P, dev, 3, ceil)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

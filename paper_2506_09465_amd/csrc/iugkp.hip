@@ -1508,14 +1508,19 @@ int enqueue_iteration(iugkp_handle *h, int faces)
   int form = -1;
   h->form_last = -1;
   if (ih.d.persist) {
-    const int nmax = std::max(std::max(m.n_cells, m.n_b), std::max(m.n_fx, m.n_fy));
+    const int nmax = std::max(std::max(std::max(m.n_cells, m.n_b), std::max(m.n_fx, m.n_fy)),
+                              (m.ny + 2) * m.nx);
     iugkp::persist_prepare_kernel<<<cdiv(nmax, 256), 256, 0, s>>>(h->d_inst);
     HIP_TRY(hipEventRecord(h->ev[0], s));
     iugkp::persist_move_kernel<kPersistBlock>
         <<<ih.d.n_npart, kPersistBlock, 0, s>>>(h->d_inst, faces);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(h->ev[1], s));
-    if (faces) iugkp::persist_reconstruct_x_kernel<<<cdiv(m.ny, 4), 256, 0, s>>>(h->d_inst);
+    if (faces) {
+      if (m.dim == 2)
+        iugkp::reconstruct_y_kernel<<<dim3(cdiv(m.nx, 4), 1), 256, 0, s>>>(h->d_inst, 1, 0);
+      iugkp::persist_reconstruct_x_kernel<<<cdiv(m.ny, 4), 256, 0, s>>>(h->d_inst);
+    }
     iugkp::persist_update_kernel<<<ih.d.n_gpart, 256, 0, s>>>(h->d_inst);
   } else {
   iugkp::prepare_kernel<<<dim3(cdiv(nprep, 256), K), 256, 0, s>>>(h->d_inst, faces, 0);

@@ -2817,18 +2817,23 @@ __global__ void persist_prepare_kernel(const Inst *__restrict__ insts)
   }
   if (i < m.n_fx) in.Phix[i] = 0;
   if (i < m.n_fy) in.Phiy[i] = 0;
+  if (i < (m.ny + 2) * m.nx) in.dB[i] = 0;
 }
 
 // One straight path of length ell from (x0, y0) in cell (ix, iy): the walk's
 // face rules (strict crossing, x first on ties, the first wall face absorbs),
-// each y-face crossing tallied when faces are on (the x faces follow from the
+// the y-face crossings tallied when faces are on (the x faces follow from the
 // per-cell balance afterwards); without face tallies a path expected to
-// cross more than kJumpMinFaces faces is resolved in closed form.  Returns
-// true when absorbed by wall face bface.
+// cross more than kJumpMinFaces faces is resolved in closed form.  The y faces
+// a path crosses inside one column form a run; a run of three or more faces
+// is recorded as +q at its first and -q past its last face of the column
+// difference array dB (completed by a column prefix sum), a shorter one face
+// by face, so a path costs at most two atomics per column it crosses faces in.
+// Returns true when absorbed by wall face bface.
 __device__ __forceinline__ bool persist_walk(const Mesh &m, double x0, double y0, int &ix, int &iy,
                                              double sx, double sy, double ell, int faces,
-                                             long long q, long long *Phiy, int &bface,
-                                             unsigned long long &n_cross)
+                                             long long q, long long *Phiy, long long *dB,
+                                             int &bface, unsigned long long &n_cross)
 {
   const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
   const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
@@ -2841,30 +2846,51 @@ __device__ __forceinline__ bool persist_walk(const Mesh &m, double x0, double y0
     segment_jump(m, x0, y0, ix, iy, stx, sty, inv_sx, inv_sy, kx, ky, ell, bface, n_cross);
     return bface >= 0;
   }
+  const long long qy = sty > 0 ? q : -q;
+  int run_a = 0, run_n = 0;   // first y face and length of the open run in column ix
+  auto close_run = [&]() {
+    if (run_n >= 3) {
+      const int lo = sty > 0 ? run_a : run_a - (run_n - 1);
+      atom_add(&dB[lo * m.nx + ix], qy);
+      atom_add(&dB[(lo + run_n) * m.nx + ix], -qy);
+    } else {
+      for (int r = 0; r < run_n; ++r) atom_add(&Phiy[(run_a + r * sty) * m.nx + ix], qy);
+    }
+    run_n = 0;
+  };
+  bool absorbed = false;
   for (;;) {
     const double tx = stx ? (static_cast<double>(kx) * m.dx - x0) * inv_sx : INFINITY;
     const double ty = sty ? (static_cast<double>(ky) * m.dy - y0) * inv_sy : INFINITY;
     const bool along_x = tx <= ty;
     const double tt = along_x ? tx : ty;
-    if (!(tt < ell)) return false;
+    if (!(tt < ell)) break;
     ++n_cross;
     if (along_x) {
+      if (run_n) close_run();
       if (kx == 0 || kx == m.nx) {
         bface = (kx == 0) ? iy : m.ny + iy;
-        return true;
+        absorbed = true;
+        break;
       }
       ix += stx;
       kx += stx;
     } else {
-      if (faces) atom_add(&Phiy[ky * m.nx + ix], sty > 0 ? q : -q);
+      if (faces) {
+        if (run_n == 0) run_a = ky;
+        ++run_n;
+      }
       if (ky == 0 || ky == m.ny) {
         bface = (ky == 0) ? 2 * m.ny + ix : 2 * m.ny + m.nx + ix;
-        return true;
+        absorbed = true;
+        break;
       }
       iy += sty;
       ky += sty;
     }
   }
+  if (run_n) close_run();
+  return absorbed;
 }
 
 // The move: one thread per particle; tallies by global atomics (W, W^h, N_rc,
@@ -2936,7 +2962,7 @@ __global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict
     const double ell = -(in.lam_min * log_own(1.0 - us.x));
     int bface;
     uint32_t nlk;
-    if (persist_walk(m, x, y, ix, iy, sx, sy, ell, faces, q, in.Phiy, bface, cr)) {
+    if (persist_walk(m, x, y, ix, iy, sx, sy, ell, faces, q, in.Phiy, in.dB, bface, cr)) {
       wkey = bface;
       nlk = static_cast<uint32_t>(bface) | (2u << 30);
     } else {

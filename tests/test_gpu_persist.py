@@ -71,6 +71,9 @@ CASES = {
     "cavity_long_paths": lambda: cavity_2d(n=20, kn=3.0, particles=40_000, newton=False, seed=4),
     "ragged_rect_src": lambda: _source(cavity_2d(n=37, ny=13, kn=0.1, particles=50_000,
                                                  newton=False, seed=5)),
+    # tall cells crossed by long paths: many columns with runs of three or more y faces
+    "tall_long_paths": lambda: cavity_2d(n=11, ny=41, kn=2.0, particles=40_000, newton=False,
+                                         seed=8),
 }
 
 
