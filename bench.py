@@ -337,7 +337,7 @@ def persist_bytes(n, n_null, n_real, crossings):
     return 48 * n + 40 * n_null + 8 * (n - n_null) + 8 * n + 8 * n_real + 8 * crossings
 
 
-def bench_persistent(P, dev, steps, warmup=3):
+def bench_persistent(P, dev, steps, ceil, warmup=3):
     """The persistent-particle scheme (Sec. 3.2 steps (1)-(6), fixed
     population) on the 256 x 256 cavity at each Kn with 1e7 particles, face
     tallies every iteration: particle moves per second and the move kernel's
@@ -346,7 +346,7 @@ def bench_persistent(P, dev, steps, warmup=3):
     from synth import cavity_2d
     out = {"workload": "2D gray square cavity 256x256, hot top wall, Kn in {0.01,0.1,1,10}, "
                        "persistent population of 1e7 particles, face tallies every iteration"}
-    tot_moves, tot_s, tot_ms, tot_bytes, launches = 0, 0.0, 0.0, 0, 0
+    tot_moves, tot_s, tot_ms, tot_bytes, tot_cr, launches = 0, 0.0, 0.0, 0, 0, 0
     for kn in KNS:
         w = cavity_2d(n=N_SIDE, kn=kn, particles=PARTICLES, newton=False, seed=0)
         s = P.Solver(w, device=dev, scheme=P.SCHEME_PERSISTENT, tally_faces=P.FACES_EVERY)
@@ -377,15 +377,15 @@ def bench_persistent(P, dev, steps, warmup=3):
         tot_s += t_el
         tot_ms += ms
         tot_bytes += byt
+        tot_cr += cr
         launches += steps
     avg_ms = tot_ms / launches
-    ach = tot_bytes / launches / (avg_ms / 1e3) / 1e9
     out["moves_per_s"] = tot_moves / tot_s
-    out["roofline"] = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(ach / HBM_PEAK_GBS, 5),
-                       "traffic": None,
-                       "kernel": "persist_move_kernel", "avg_launch_ms": round(avg_ms, 4),
-                       "algorithmic_bytes_per_launch": int(tot_bytes / launches)}
+    # one end tally per move and one per face crossed, as the emitter scheme's
+    # particle step counts them
+    out["roofline"] = tally_roofline(ceil, tot_cr + tot_moves, launches, avg_ms,
+                                     tot_bytes / launches,
+                                     "persist_move_kernel + persist_faces_kernel")
     return out
 
 
@@ -778,7 +778,7 @@ def main():
         print(json.dumps(bench_nongray(P, dev, args.steps, 20, atomics_ceiling(P))), flush=True)
         return
     if args.persistent_only:
-        print(json.dumps(bench_persistent(P, dev, args.steps)), flush=True)
+        print(json.dumps(bench_persistent(P, dev, args.steps, atomics_ceiling(P))), flush=True)
         return
     if args.expected_only:
         print(json.dumps(bench_expected(P, dev)), flush=True)
@@ -990,7 +990,7 @@ def main():
         out["adjoint"] = bench_adjoint(P, dev)
 
     if not args.no_persistent:
-        out["persistent"] = bench_persistent(P, dev, args.steps)
+        out["persistent"] = bench_persistent(P, dev, args.steps, ceil)
 
     if not args.no_expected:
         out["expected_value"] = bench_expected(P, dev)

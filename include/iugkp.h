@@ -125,8 +125,11 @@ typedef struct iugkp_options {
   int march;                    /* single solves on 2D meshes: 0 automatic (row stripes for
                                    face-tallied iterations with long free paths, tiles
                                    otherwise), 1 emitter tiles, 2 row stripes (also for the
-                                   expected-value estimator, with or without face tallies);
-                                   the result does not depend on it */
+                                   expected-value estimator, with or without face tallies).
+                                   Persistent scheme: the y faces of face-tallied moves by a
+                                   row-stripe pass (2, or 0 with long free paths) or as
+                                   global atomics in the move (1).  The result does not
+                                   depend on it */
   int cg_waves;                 /* single solves: 256-cell tree blocks per CG workgroup, 0
                                    (= 8) or 1..12 with the CG state in registers, -1..-12 with
                                    it in global memory (with IUGKP_PRECOND_MG: |cg_waves|

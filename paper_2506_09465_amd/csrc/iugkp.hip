@@ -52,6 +52,7 @@ constexpr int kStripeBlock = 1024;           // threads of a stripe workgroup
 constexpr int kStripeMinRows = 4;
 constexpr size_t kCgLdsMax = 48 * 1024;      // dynamic LDS of a CG workgroup
 constexpr int kPersistBlock = 256;           // particles per move workgroup
+constexpr int kPersistFacesBlock = 1024;     // threads per workgroup of the row-stripe face pass
 constexpr int kTileX = 8;                    // emitter tile of one workgroup (cells per side;
                                              // wall faces per workgroup); batches also 16
 constexpr int kWindowHalo = 12;              // window margin around a tile (cells)
@@ -148,6 +149,10 @@ struct InstHost {
   int stripe_R = 0, stripe_S = 0, stripe_C = 0;
   size_t stripe_lds = 0;
   int stripe_pref = 0;               // the planner's choice (stripes set up for a search too)
+  // the persistent scheme's row-stripe face pass (rows per stripe, stripes,
+  // chunks, LDS bytes; 0 rows: y faces as global atomics in the move)
+  int pst_R = 0, pst_S = 0, pst_C = 0;
+  size_t pst_lds = 0;
   iugkp::StripeRec rec{};            // first segments, sampled once for all stripes
 
   template <class T>
@@ -363,6 +368,37 @@ int setup_persistent(InstHost &ih, const std::vector<double> &T0, const std::vec
   PALLOC(dgw, nb);
   PALLOC(dg0, nc);
 #undef PALLOC
+  // the y faces of face-tallied moves by row stripes (2D, free paths of at
+  // least kStripeMinCells cells or march 2; march 1 keeps them as global
+  // atomics in the move): as many rows per workgroup as its LDS holds, about
+  // two workgroups per CU
+  const bool lam_stripes = d.lam_min >= kStripeMinCells * std::min(m.dx, m.dy);
+  if (m.dim == 2 && (ih.opt.march == 2 || (ih.opt.march == 0 && lam_stripes)) &&
+      m.ny <= 0xfffe && m.nx <= 0xffff) {
+    int dev = 0, n_cu = 0, lds_max = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    int R = static_cast<int>((lds_max / 8 - 64) / m.nx) - 1;   // nface <= R + 1 rows of faces
+    if (R >= 1) {
+      R = std::min(R, m.ny);
+      const int S = cdiv(m.ny, R);
+      R = cdiv(m.ny, S);
+      const size_t lds = static_cast<size_t>(R + 1) * m.nx * sizeof(long long);
+      int per_cu = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void *>(iugkp::persist_faces_kernel<kPersistFacesBlock>),
+          kPersistFacesBlock, lds));
+      if (per_cu >= 1 && ih.alloc(&d.pf, n) == hipSuccess && ih.alloc(&d.pkey, n) == hipSuccess) {
+        ih.pst_R = R;
+        ih.pst_S = S;
+        ih.pst_C = std::max(1, (2 * per_cu * n_cu) / S);
+        ih.pst_lds = lds;
+      } else {
+        (void)hipGetLastError();   // (without the memory: global atomics)
+      }
+    }
+  }
   d.Gw = dgw;
   // the cells' energies E V in fixed point, the walls' first shares
   std::vector<long long> g0(nc), wb(nb), rb(nb);
@@ -1512,12 +1548,19 @@ int enqueue_iteration(iugkp_handle *h, int faces)
                               (m.ny + 2) * m.nx);
     iugkp::persist_prepare_kernel<<<cdiv(nmax, 256), 256, 0, s>>>(h->d_inst);
     HIP_TRY(hipEventRecord(h->ev[0], s));
+    const int stripes = (faces && ih.pst_R > 0) ? 1 : 0;
     iugkp::persist_move_kernel<kPersistBlock>
-        <<<ih.d.n_npart, kPersistBlock, 0, s>>>(h->d_inst, faces);
+        <<<ih.d.n_npart, kPersistBlock, 0, s>>>(h->d_inst, faces, stripes);
     HIP_TRY(hipGetLastError());
+    if (stripes) {
+      iugkp::persist_faces_kernel<kPersistFacesBlock>
+          <<<dim3(ih.pst_C, ih.pst_S), kPersistFacesBlock, ih.pst_lds, s>>>(h->d_inst, ih.pst_R,
+                                                                          ih.pst_C);
+      HIP_TRY(hipGetLastError());
+    }
     HIP_TRY(hipEventRecord(h->ev[1], s));
     if (faces) {
-      if (m.dim == 2)
+      if (m.dim == 2 && !stripes)
         iugkp::reconstruct_y_kernel<<<dim3(cdiv(m.nx, 4), 1), 256, 0, s>>>(h->d_inst, 1, 0);
       iugkp::persist_reconstruct_x_kernel<<<cdiv(m.ny, 4), 256, 0, s>>>(h->d_inst);
     }

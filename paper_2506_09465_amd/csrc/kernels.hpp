@@ -55,6 +55,16 @@ struct DevScalars {
   int err;                      // first error of the solve (negative code) or 0
 };
 
+// A persistent particle's straight path of one move, kept for the row-stripe
+// pass of its y-face tallies: start point, direction (s_x and the two
+// reciprocals of the walk), weight, start cell (column | row << 16) and the
+// number of y faces crossed.
+struct PFace {
+  double x0, y0, sx, inv_sx, inv_sy;
+  long long q;
+  uint32_t cell, nyp;
+};
+
 // Everything the per-iteration kernels need about one problem instance.
 struct Inst {
   Mesh m;
@@ -91,6 +101,8 @@ struct Inst {
   const long long *Gw;          // wall emission per iteration
   long long *pstart;            // energy starting this iteration's paths in each cell
   long long *pein;              // energy re-emitted this iteration by each wall face
+  PFace *pf;                    // row-stripe face pass: each move's path, and its crossed
+  uint32_t *pkey;               //   y faces' range (first | last << 16; kNoFaces if none)
   unsigned long long *npart;    // per move workgroup: saturating sum of |q| over null particles
   int n_npart, n_gpart;
   DevScalars *sc;
@@ -2896,8 +2908,13 @@ __device__ __forceinline__ bool persist_walk(const Mesh &m, double x0, double y0
 // The move: one thread per particle; tallies by global atomics (W, W^h, N_rc,
 // B, N_b, crossed faces); counters and the null particles' |q| sum per
 // workgroup.
+// (no y face crossed: an empty range, first > last for every row count up to
+// 65534)
+constexpr uint32_t kNoFaces = 0x0000FFFFu;
+
 template <int BS>
-__global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict__ insts, int faces)
+__global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict__ insts, int faces,
+                                                          int stripes)
 {
   __shared__ unsigned long long s_red[3][BS / 64];
   const Inst &in = insts[0];
@@ -2962,7 +2979,40 @@ __global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict
     const double ell = -(in.lam_min * log_own(1.0 - us.x));
     int bface;
     uint32_t nlk;
-    if (persist_walk(m, x, y, ix, iy, sx, sy, ell, faces, q, in.Phiy, in.dB, bface, cr)) {
+    bool absorbed;
+    if (faces && stripes) {
+      // the walk in closed form; its y faces are tallied by persist_faces_kernel
+      const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+      const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+      const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+      const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+      const int kx = (stx > 0) ? ix + 1 : ix, ky = (sty > 0) ? iy + 1 : iy;
+      const uint32_t cell = static_cast<uint32_t>(ix) | (static_cast<uint32_t>(iy) << 16);
+      int nxp = 0, nyp = 0;
+      bface = -1;
+      segment_end(m, x, y, ix, iy, stx, sty, inv_sx, inv_sy, kx, ky, ell, bface, nxp, nyp);
+      cr += static_cast<unsigned long long>(nxp + nyp);
+      absorbed = bface >= 0;
+      uint32_t key = kNoFaces;
+      if (nyp > 0) {
+        const int kl = ky + (nyp - 1) * sty;
+        key = static_cast<uint32_t>(min(ky, kl)) | (static_cast<uint32_t>(max(ky, kl)) << 16);
+        PFace r;
+        r.x0 = x;
+        r.y0 = y;
+        r.sx = sx;
+        r.inv_sx = inv_sx;
+        r.inv_sy = inv_sy;
+        r.q = q;
+        r.cell = cell;
+        r.nyp = static_cast<uint32_t>(nyp);
+        in.pf[p] = r;
+      }
+      in.pkey[p] = key;
+    } else {
+      absorbed = persist_walk(m, x, y, ix, iy, sx, sy, ell, faces, q, in.Phiy, in.dB, bface, cr);
+    }
+    if (absorbed) {
       wkey = bface;
       nlk = static_cast<uint32_t>(bface) | (2u << 30);
     } else {
@@ -3039,6 +3089,68 @@ __global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict
     if (c) atomicAdd(&in.sc->crossings, c);
     in.npart[blockIdx.x] = n;
   }
+}
+
+// The y-face tallies of a face-tallied persistent move, by row stripes:
+// workgroup (chunk c, stripe s) keeps in LDS the tallies of faces [r0, r1f)
+// (the last stripe also owns face ny) and runs the paths of its chunk of the
+// population whose crossed y faces reach those rows; each owned crossing is
+// tallied in the column reached by the x faces crossed before it (x first on
+// ties, as in the walk), then the stripe is added to the global tallies row by
+// row.  Integer sums: the tallies of the face-by-face walk, bit for bit.
+template <int BS>
+__global__ __launch_bounds__(BS) void persist_faces_kernel(const Inst *__restrict__ insts, int R,
+                                                           int chunks)
+{
+  extern __shared__ long long lds_words[];
+  const Inst &in = insts[0];
+  const Mesh m = in.m;
+  const int nx = m.nx;
+  const int r0 = static_cast<int>(blockIdx.y) * R, r1 = min(r0 + R, m.ny);
+  const int r1f = (r1 == m.ny) ? m.ny + 1 : r1;
+  const int nface = r1f - r0;
+  long long *By = lds_words;                                  // [nface][nx]
+  for (int i = threadIdx.x; i < nface * nx; i += BS) By[i] = 0;
+  __syncthreads();
+  const PFace *__restrict__ pf = in.pf;
+  const uint32_t *__restrict__ pkey = in.pkey;
+  const unsigned long long n = in.n_part;
+  const unsigned int pb = static_cast<unsigned int>(n * blockIdx.x / chunks);
+  const unsigned int pe = static_cast<unsigned int>(n * (blockIdx.x + 1) / chunks);
+  const double inv_dx = 1.0 / m.dx;       // (only to estimate a face count)
+  for (unsigned int p = pb + threadIdx.x; p < pe; p += BS) {
+    const uint32_t key = pkey[p];
+    if (static_cast<int>(key >> 16) < r0 || static_cast<int>(key & 0xffffu) >= r1f) continue;
+    const PFace r = pf[p];
+    const int ix0 = static_cast<int>(r.cell & 0xffffu), iy0 = static_cast<int>(r.cell >> 16);
+    const int nyp = static_cast<int>(r.nyp);
+    const int stx = (r.sx > 0.0) ? 1 : ((r.sx < 0.0) ? -1 : 0);
+    const int sty = (r.inv_sy > 0.0) ? 1 : -1;               // (a y face crossed: s_y != 0)
+    const int kx0 = (stx > 0) ? ix0 + 1 : ix0, ky0 = (sty > 0) ? iy0 + 1 : iy0;
+    const int jwx = (stx > 0) ? nx - kx0 : kx0;
+    const long long qy = (sty > 0) ? r.q : -r.q;
+    // the crossed faces ky0 + k sty (k < nyp) this stripe owns
+    int k, k_end;
+    if (sty > 0) {
+      k = max(0, r0 - ky0);
+      k_end = min(nyp, r1f - ky0);
+    } else {
+      k = max(0, ky0 - r1f + 1);
+      k_end = min(nyp, ky0 - r0 + 1);
+    }
+    int cnt = 0;
+    for (; k < k_end; ++k) {
+      const int kyk = ky0 + k * sty;
+      const double ty = (static_cast<double>(kyk) * m.dy - r.y0) * r.inv_sy;
+      if (stx) cnt = faces_upto_near(cnt, kx0, stx, jwx, m.dx, inv_dx, r.x0, r.inv_sx, r.sx, ty);
+      atomicAdd(reinterpret_cast<unsigned long long *>(&By[(kyk - r0) * nx + ix0 + stx * cnt]),
+                static_cast<unsigned long long>(qy));
+    }
+  }
+  __syncthreads();
+  long long *const gPhiy = in.Phiy;
+  for (int i = threadIdx.x; i < nface * nx; i += BS)
+    if (By[i]) atom_add(&gPhiy[r0 * nx + i], By[i]);
 }
 
 // E = W / V, the residual partials, and the shares of the next iteration:

@@ -74,15 +74,22 @@ CASES = {
     # tall cells crossed by long paths: many columns with runs of three or more y faces
     "tall_long_paths": lambda: cavity_2d(n=11, ny=41, kn=2.0, particles=40_000, newton=False,
                                          seed=8),
+    # 4000 columns: the row-stripe face pass holds four rows of faces per
+    # workgroup, so 25 rows make seven stripes (the last one short)
+    "wide_many_stripes": lambda: cavity_2d(n=4000, ny=25, kn=0.002, particles=120_000,
+                                           newton=False, seed=9),
 }
 
 
+# march 2: y faces of face-tallied moves by the row-stripe pass (2D);
+# march 1: as global atomics in the move
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("rng", ["fresh", "crn"])
-def test_persist_iterations_bitwise(oracle_mod, gpu, name, rng):
+@pytest.mark.parametrize("march", [1, 2])
+def test_persist_iterations_bitwise(oracle_mod, gpu, name, rng, march):
     w = CASES[name]()
     o, s = _pair(oracle_mod, gpu, w, rng_mode=oracle_mod.CRN if rng == "crn" else oracle_mod.FRESH,
-                 epoch=7)
+                 epoch=7, march=march)
     _same(o, s, f"{name} creation", tallies=False)
     for i, faces in enumerate([True, False, True, False]):
         assert o.step(1, faces=faces) == 0
@@ -156,3 +163,24 @@ def test_persist_full_size_bookkeeping(gpu):
         assert bool(((x >= ix * w.dx) & (x <= (ix + 1) * w.dx)).all())
     st = s.stats()
     assert st["segments"] == st["n_per_emitter"] * (nc + nb)
+
+
+@pytest.mark.parametrize("kn", [0.1, 10.0])
+def test_persist_full_size_stripes_equal_atomics(gpu, kn):
+    """The benchmark's persistent configuration (256^2 cavity, 1e7 particles,
+    faces every iteration): the row-stripe face pass and the move's global
+    atomics give the same population and tallies bit for bit."""
+    w = cavity_2d(n=256, kn=kn, particles=10_000_000, newton=False)
+    a = gpu.Solver(w, scheme=gpu.SCHEME_PERSISTENT, tally_faces=gpu.FACES_EVERY)
+    b = gpu.Solver(w, scheme=gpu.SCHEME_PERSISTENT, tally_faces=gpu.FACES_EVERY, march=1)
+    for it in range(2):
+        assert a.step(1) == 0 and b.step(1) == 0
+        ta, tb = a.tallies(), b.tallies()
+        for k in ta:
+            assert torch.equal(ta[k], tb[k]), f"iteration {it}: tally {k} differs"
+        pa, pb = a.particles(), b.particles()
+        for k in pa:
+            assert torch.equal(pa[k], pb[k]), f"iteration {it}: particle {k} differs"
+    assert a.stats()["tot_crossings"] == b.stats()["tot_crossings"]
+    a.close()
+    b.close()
