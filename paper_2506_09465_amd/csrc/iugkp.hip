@@ -379,7 +379,8 @@ int setup_persistent(InstHost &ih, const std::vector<double> &T0, const std::vec
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    int R = static_cast<int>((lds_max / 8 - 64) / m.nx) - 1;   // nface <= R + 1 rows of faces
+    // (less the static LDS: the list of paths and their pieces, 16 KB)
+    int R = static_cast<int>((lds_max / 8 - 64 - iugkp::kPersistScan) / m.nx) - 1;   // nface <= R + 1
     if (R >= 1) {
       R = std::min(R, m.ny);
       const int S = cdiv(m.ny, R);

@@ -3093,16 +3093,30 @@ __global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict
 
 // The y-face tallies of a face-tallied persistent move, by row stripes:
 // workgroup (chunk c, stripe s) keeps in LDS the tallies of faces [r0, r1f)
-// (the last stripe also owns face ny) and runs the paths of its chunk of the
-// population whose crossed y faces reach those rows; each owned crossing is
-// tallied in the column reached by the x faces crossed before it (x first on
-// ties, as in the walk), then the stripe is added to the global tallies row by
-// row.  Integer sums: the tallies of the face-by-face walk, bit for bit.
+// (the last stripe also owns face ny) and tallies the crossings of its
+// chunk's paths with those faces, each in the column reached by the x faces
+// crossed before it (x first on ties, as in the walk); then the stripe is
+// added to the global tallies row by row.  The chunk is scanned kPersistScan
+// ranges at a time: the paths that meet the stripe are listed in LDS, and
+// their owned crossings are cut into pieces of at most kPersistPiece
+// consecutive faces (a workgroup prefix sum over the list numbers them), one
+// piece per lane, so the lanes of a wavefront do nearly equal work whatever
+// the spread of path lengths.  A crossing's column needs no earlier crossing
+// of its path (faces_upto_near from its own time).  Integer sums: the tallies
+// of the face-by-face walk, bit for bit.
+constexpr int kPersistScan = 2048;
+constexpr int kPersistPiece = 16;
+
 template <int BS>
 __global__ __launch_bounds__(BS) void persist_faces_kernel(const Inst *__restrict__ insts, int R,
                                                            int chunks)
 {
+  static_assert(2 * BS >= kPersistScan, "two listed paths per thread in the piece count scan");
   extern __shared__ long long lds_words[];
+  __shared__ uint32_t s_list[kPersistScan];      // listed paths (population index)
+  __shared__ uint32_t s_pre[kPersistScan + 1];   // first piece of each listed path
+  __shared__ uint32_t s_wsum[BS / 64];
+  __shared__ uint32_t s_n;
   const Inst &in = insts[0];
   const Mesh m = in.m;
   const int nx = m.nx;
@@ -3111,43 +3125,90 @@ __global__ __launch_bounds__(BS) void persist_faces_kernel(const Inst *__restric
   const int nface = r1f - r0;
   long long *By = lds_words;                                  // [nface][nx]
   for (int i = threadIdx.x; i < nface * nx; i += BS) By[i] = 0;
-  __syncthreads();
   const PFace *__restrict__ pf = in.pf;
   const uint32_t *__restrict__ pkey = in.pkey;
   const unsigned long long n = in.n_part;
-  const unsigned int pb = static_cast<unsigned int>(n * blockIdx.x / chunks);
-  const unsigned int pe = static_cast<unsigned int>(n * (blockIdx.x + 1) / chunks);
+  const unsigned long long pb = n * blockIdx.x / chunks, pe = n * (blockIdx.x + 1) / chunks;
   const double inv_dx = 1.0 / m.dx;       // (only to estimate a face count)
-  for (unsigned int p = pb + threadIdx.x; p < pe; p += BS) {
-    const uint32_t key = pkey[p];
-    if (static_cast<int>(key >> 16) < r0 || static_cast<int>(key & 0xffffu) >= r1f) continue;
-    const PFace r = pf[p];
-    const int ix0 = static_cast<int>(r.cell & 0xffffu), iy0 = static_cast<int>(r.cell >> 16);
-    const int nyp = static_cast<int>(r.nyp);
-    const int stx = (r.sx > 0.0) ? 1 : ((r.sx < 0.0) ? -1 : 0);
-    const int sty = (r.inv_sy > 0.0) ? 1 : -1;               // (a y face crossed: s_y != 0)
-    const int kx0 = (stx > 0) ? ix0 + 1 : ix0, ky0 = (sty > 0) ? iy0 + 1 : iy0;
-    const int jwx = (stx > 0) ? nx - kx0 : kx0;
-    const long long qy = (sty > 0) ? r.q : -r.q;
-    // the crossed faces ky0 + k sty (k < nyp) this stripe owns
-    int k, k_end;
-    if (sty > 0) {
-      k = max(0, r0 - ky0);
-      k_end = min(nyp, r1f - ky0);
-    } else {
-      k = max(0, ky0 - r1f + 1);
-      k_end = min(nyp, ky0 - r0 + 1);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // owned crossed faces [max(lo, r0), min(hi, r1f - 1)] of a range lo | hi << 16
+  auto owned_lo = [&](uint32_t key) { return max(static_cast<int>(key & 0xffffu), r0); };
+  auto owned_n = [&](uint32_t key) {
+    return min(static_cast<int>(key >> 16), r1f - 1) - owned_lo(key) + 1;
+  };
+  for (unsigned long long base = pb; base < pe; base += kPersistScan) {
+    const unsigned long long end = min(pe, base + kPersistScan);
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    // the ranges that meet the stripe, listed (one LDS atomic per wavefront)
+    for (unsigned long long p0 = base; p0 < end; p0 += BS) {
+      const unsigned long long p = p0 + threadIdx.x;
+      bool hit = false;
+      if (p < end) {
+        const uint32_t key = pkey[p];
+        hit = static_cast<int>(key >> 16) >= r0 && static_cast<int>(key & 0xffffu) < r1f;
+      }
+      const unsigned long long mask = __ballot(hit);
+      if (mask) {
+        uint32_t off = 0;
+        if (lane == 0) off = atomicAdd(&s_n, static_cast<uint32_t>(__popcll(mask)));
+        off = __shfl(off, 0, 64);
+        if (hit) s_list[off + __popcll(mask & ((1ull << lane) - 1ull))] = static_cast<uint32_t>(p);
+      }
     }
-    int cnt = 0;
-    for (; k < k_end; ++k) {
-      const int kyk = ky0 + k * sty;
-      const double ty = (static_cast<double>(kyk) * m.dy - r.y0) * r.inv_sy;
-      if (stx) cnt = faces_upto_near(cnt, kx0, stx, jwx, m.dx, inv_dx, r.x0, r.inv_sx, r.sx, ty);
-      atomicAdd(reinterpret_cast<unsigned long long *>(&By[(kyk - r0) * nx + ix0 + stx * cnt]),
-                static_cast<unsigned long long>(qy));
+    __syncthreads();
+    const int nl = static_cast<int>(s_n);
+    // pieces per listed path, numbered by an exclusive prefix sum
+    {
+      const int i0 = 2 * static_cast<int>(threadIdx.x), i1 = i0 + 1;
+      const uint32_t c0 = (i0 < nl) ? (owned_n(pkey[s_list[i0]]) + kPersistPiece - 1) / kPersistPiece : 0u;
+      const uint32_t c1 = (i1 < nl) ? (owned_n(pkey[s_list[i1]]) + kPersistPiece - 1) / kPersistPiece : 0u;
+      uint32_t incl = c0 + c1;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = static_cast<uint32_t>(__shfl_up(static_cast<int>(incl), d, 64));
+        if (lane >= d) incl += o;
+      }
+      if (lane == 63) s_wsum[wv] = incl;
+      __syncthreads();
+      uint32_t off = 0;
+      for (int v = 0; v < wv; ++v) off += s_wsum[v];
+      const uint32_t ex = off + incl - c0 - c1;
+      if (i0 < nl) s_pre[i0] = ex;
+      if (i1 < nl) s_pre[i1] = ex + c0;
+      if (i0 < nl && i1 >= nl - 1) s_pre[nl] = ex + c0 + c1;
+      if (nl == 0 && threadIdx.x == 0) s_pre[0] = 0;
     }
+    __syncthreads();
+    const uint32_t n_piece = s_pre[nl];
+    for (uint32_t u = threadIdx.x; u < n_piece; u += BS) {
+      // the listed path of piece u: the last i with s_pre[i] <= u
+      int a = 0, b = nl - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (s_pre[mid] <= u) a = mid;
+        else b = mid - 1;
+      }
+      const uint32_t pi = s_list[a];
+      const uint32_t key = pkey[pi];
+      const PFace r = pf[pi];
+      const int ix0 = static_cast<int>(r.cell & 0xffffu);
+      const int stx = (r.sx > 0.0) ? 1 : ((r.sx < 0.0) ? -1 : 0);
+      const long long qy = (r.inv_sy > 0.0) ? r.q : -r.q;     // (a y face crossed: s_y != 0)
+      const int kx0 = (stx > 0) ? ix0 + 1 : ix0;
+      const int jwx = (stx > 0) ? nx - kx0 : kx0;
+      const int f0 = owned_lo(key) + static_cast<int>(u - s_pre[a]) * kPersistPiece;
+      const int f1 = min(owned_lo(key) + owned_n(key), f0 + kPersistPiece);
+      for (int kyk = f0; kyk < f1; ++kyk) {
+        const double ty = (static_cast<double>(kyk) * m.dy - r.y0) * r.inv_sy;
+        const int cnt = stx ? faces_upto_near(0, kx0, stx, jwx, m.dx, inv_dx, r.x0, r.inv_sx, r.sx, ty) : 0;
+        atomicAdd(reinterpret_cast<unsigned long long *>(&By[(kyk - r0) * nx + ix0 + stx * cnt]),
+                  static_cast<unsigned long long>(qy));
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  __syncthreads();   // (an empty chunk: the zeroed tallies)
   long long *const gPhiy = in.Phiy;
   for (int i = threadIdx.x; i < nface * nx; i += BS)
     if (By[i]) atom_add(&gPhiy[r0 * nx + i], By[i]);
