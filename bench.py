@@ -571,7 +571,9 @@ def bench_c2_gray(P, dev, steps, ceil):
                               for f, v in form_ms.items()},
             "roofline": tally_roofline(ceil, cr + sg + fl, steps, ms_m,
                                        march_bytes(fl, cr, sg, b["n_emitters"] * steps, True) / steps,
-                                       "march_stripes_kernel" if form == "stripes" else "march_kernel")}
+                                       {"stripes": "march_stripes_kernel",
+                                        "stripes_pieces": "march_stripes_pieces_kernel"}.get(
+                                           form, "march_kernel"))}
 
 
 def cpu_baseline_nongray():
@@ -598,7 +600,8 @@ def cpu_baseline_nongray():
 
 
 # kernels of the particle step (between the step's HIP events) and of the Newton CG
-PS_KERNELS = ("march_kernel", "stripe_presample_kernel", "march_stripes_kernel")
+PS_KERNELS = ("march_kernel", "stripe_presample_kernel", "march_stripes_kernel",
+              "march_stripes_pieces_kernel")
 CG_KERNELS = ("mgcg_kernel", "mgcg_band_kernel")
 PROFILE_ITERS = 2
 # rocprofv3 counter passes (each within one pass's hardware limits: TCC <= 4,
@@ -611,7 +614,7 @@ COUNTER_PASSES = (("FETCH_SIZE",),
 
 # a particle-step form as Solver options (the form search keeps the fastest)
 FORM_OPTS = {"tiles256": dict(march=1, block_size=256), "tiles512": dict(march=1, block_size=512),
-             "stripes": dict(march=2)}
+             "stripes": dict(march=2), "stripes_pieces": dict(march=3)}
 
 
 def profile_pass(forms=None):
@@ -808,10 +811,11 @@ def main():
         assert rc == 0, f"step failed with {rc}"
 
     # the particle-step form search of each problem (an untimed iteration, then
-    # one per form: tiles of 256 and 512 threads, row stripes), one problem at
-    # a time so that each measurement has the GPU to itself
+    # one per form: tiles of 256 and 512 threads, row stripes, row stripes in
+    # pieces), one problem at a time so that each measurement has the GPU to
+    # itself
     for _, _, s in solvers:
-        assert s.step(4) == 0
+        assert s.step(5) == 0
     run_concurrent(args.warmup)
     # kernel pass: the same steps one problem at a time, for per-kernel times
     # (HIP events on each solver's stream) free of the other problems' kernels

@@ -124,10 +124,12 @@ typedef struct iugkp_options {
   int block_size;               /* transport kernel workgroup size: 0 (= 256), 64..1024 */
   int march;                    /* single solves on 2D meshes: 0 automatic (row stripes for
                                    face-tallied iterations with long free paths, tiles
-                                   otherwise), 1 emitter tiles, 2 row stripes (also for the
-                                   expected-value estimator, with or without face tallies).
+                                   otherwise; see iugkp_march_tuning), 1 emitter tiles, 2 row
+                                   stripes (also for the expected-value estimator, with or
+                                   without face tallies), 3 row stripes with the y faces cut
+                                   into pieces (without null collisions; else as 2).
                                    Persistent scheme: the y faces of face-tallied moves by a
-                                   row-stripe pass (2, or 0 with long free paths) or as
+                                   row-stripe pass (2 or 3, or 0 with long free paths) or as
                                    global atomics in the move (1).  The result does not
                                    depend on it */
   int cg_waves;                 /* single solves: 256-cell tree blocks per CG workgroup, 0
@@ -293,12 +295,13 @@ int iugkp_get_stats(iugkp_handle *h, iugkp_stats *stats);
 /* The particle step's form for the face-tallied iterations (the A4 march of
  * Sec. 3.1; how it is run is an implementation choice, not the paper's): 0 =
  * emitter tiles of 256 threads, 1 = emitter tiles of 512 threads, 2 = row
- * stripes; -1 while the handle still measures them.  A 2D gray single solve
+ * stripes, 3 = row stripes with the y faces in pieces (without null
+ * collisions); -1 while the handle still measures them.  A 2D gray single solve
  * with the automatic march and the default block size times one face-tallied
  * iteration in each form (after an untimed first one) and keeps the fastest;
  * later handles of the same mesh, particles per emitter, null-collision
  * setting and free path in cells (to half an octave) start with it.  Every
- * form gives the same tallies bit for bit.  ms (NULL or host float[3]): the
+ * form gives the same tallies bit for bit.  ms (NULL or host float[4]): the
  * measured particle-step milliseconds per form, -1 where not measured.
  * Returns 0, or IUGKP_E_INVALID_ARG for a NULL handle. */
 int iugkp_march_tuning(iugkp_handle *h, int *form, float *ms);

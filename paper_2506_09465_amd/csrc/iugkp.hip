@@ -207,7 +207,7 @@ int check_options(const iugkp_options *o)
   const int bs = o->block_size;
   if (bs != 0 && bs != 64 && bs != 128 && bs != 256 && bs != 512 && bs != 1024)
     return fail(IUGKP_E_INVALID_ARG, "block_size must be 0, 64, 128, 256, 512 or 1024");
-  if (o->march < 0 || o->march > 2) return fail(IUGKP_E_INVALID_ARG, "march must be 0, 1 or 2");
+  if (o->march < 0 || o->march > 3) return fail(IUGKP_E_INVALID_ARG, "march must be 0, 1, 2 or 3");
   if (o->cg_waves < -iugkp::kCgWavesMax || o->cg_waves > iugkp::kCgWavesMax)
     return fail(IUGKP_E_INVALID_ARG, "cg_waves must be -12..12");
   if (o->scheme != IUGKP_SCHEME_EMITTERS && o->scheme != IUGKP_SCHEME_PERSISTENT)
@@ -373,7 +373,7 @@ int setup_persistent(InstHost &ih, const std::vector<double> &T0, const std::vec
   // atomics in the move): as many rows per workgroup as its LDS holds, about
   // two workgroups per CU
   const bool lam_stripes = d.lam_min >= kStripeMinCells * std::min(m.dx, m.dy);
-  if (m.dim == 2 && (ih.opt.march == 2 || (ih.opt.march == 0 && lam_stripes)) &&
+  if (m.dim == 2 && (ih.opt.march >= 2 || (ih.opt.march == 0 && lam_stripes)) &&
       m.ny <= 0xfffe && m.nx <= 0xffff) {
     int dev = 0, n_cu = 0, lds_max = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -825,9 +825,9 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   const bool ev = (o->estimator == IUGKP_EST_EXPECTED);
   const bool lam_stripes = d.lam_min >= kStripeMinCells * std::min(p->dx, p->dy);
   if (multi_cg && p->dim == 2 && o->scheme == IUGKP_SCHEME_EMITTERS &&
-      ((ev && o->march == 2) ||
+      ((ev && o->march >= 2) ||
        (!ev && o->tally_faces != IUGKP_FACES_OFF &&
-        (o->march == 2 || (o->march == 0 && (lam_stripes || o->block_size == 0)))))) {
+        (o->march >= 2 || (o->march == 0 && (lam_stripes || o->block_size == 0)))))) {
     // row stripes: as many rows per workgroup as its LDS holds (y faces and
     // the walls; the expected-value kernel also D, and W with null
     // collisions), about two workgroups per CU
@@ -835,8 +835,10 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    // (less the static LDS: the march's segment table, 8.3 KB)
-    const long long words = lds_max / 8 - 1100;
+    // (less the static LDS: the march's segment table, 8.3 KB, and for flights
+    // without null collisions the pieces' lists, 8.2 KB more)
+    const bool pieces = !ev && !d.has_null;
+    const long long words = lds_max / 8 - (pieces ? 2200 : 1100);
     const long long per_row = static_cast<long long>(m.nx) * (ev ? (d.has_null ? 3 : 2) : 1);
     const long long fixed = m.nx + (d.lds_walls ? m.n_b : 0);
     int R = static_cast<int>((words - fixed) / per_row);
@@ -848,7 +850,8 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
       int per_cu = 0;
       const void *kern =
           ev ? reinterpret_cast<const void *>(iugkp::march_stripes_ev_kernel<kStripeBlock>)
-             : reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>);
+          : pieces ? reinterpret_cast<const void *>(iugkp::march_stripes_pieces_kernel<kStripeBlock>)
+                   : reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>);
       HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kStripeBlock, lds));
       // (the analog kernel reads every particle's first segment from a
       // 64-byte record (80 with null collisions) and a 4-byte row range per
@@ -913,10 +916,10 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
         ih.stripe_S = S;
         ih.stripe_C = std::max(1, (2 * per_cu * n_cu) / S);   // whole rounds of resident groups
         ih.stripe_lds = lds;
-        ih.stripe_pref = (o->march == 2 || lam_stripes) ? 1 : 0;
+        ih.stripe_pref = (o->march >= 2 || lam_stripes) ? 1 : 0;
       }
     }
-    if (o->march == 2 && ih.stripe_R == 0)
+    if (o->march >= 2 && ih.stripe_R == 0)
       return fail(IUGKP_E_INVALID_ARG, "row stripes do not fit this mesh");
   }
   if (o->scheme == IUGKP_SCHEME_PERSISTENT) {
@@ -1353,7 +1356,7 @@ struct iugkp_handle {
   bool form_warm = false;         // the first face-tallied iteration has run
   int form_next = 0;              // candidates measured so far
   int form_last = -1;             // candidate of the iteration in flight
-  float form_ms[3] = {-1.f, -1.f, -1.f};
+  float form_ms[4] = {-1.f, -1.f, -1.f, -1.f};
   DevScalars *hsc = nullptr;   // pinned host mirror
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   uint32_t iter = 0;
@@ -1478,7 +1481,9 @@ int enqueue_cg(const InstHost &ih, const double *b, double *x, DevScalars *sc, h
 // same class (mesh, particles per emitter, null collisions, free path in
 // cells to half an octave) takes from its first iteration.  The forms give
 // the same tallies bit for bit, so the search changes only the time.
-enum : int { kFormTiles256 = 0, kFormTiles512 = 1, kFormStripes = 2, kForms = 3 };
+enum : int { kFormTiles256 = 0, kFormTiles512 = 1, kFormStripes = 2, kFormPieces = 3, kForms = 4 };
+// (row stripes in pieces only without null collisions)
+int n_forms(const InstHost &ih) { return ih.d.has_null ? kFormPieces : kForms; }
 struct FormKey {
   int nx, ny, N, has_null, lam2;
   bool operator<(const FormKey &o) const
@@ -1522,9 +1527,9 @@ void record_form(iugkp_handle *h, float ms)
   if (h->form_last < 0) return;
   h->form_ms[h->form_last] = ms;
   h->form_last = -1;
-  if (++h->form_next < kForms) return;
+  if (++h->form_next < n_forms(h->ih)) return;
   int best = 0;
-  for (int f = 1; f < kForms; ++f)
+  for (int f = 1; f < n_forms(h->ih); ++f)
     if (h->form_ms[f] < h->form_ms[best]) best = f;
   h->form = best;
   std::lock_guard<std::mutex> lock(g_form_mu);
@@ -1575,7 +1580,8 @@ int enqueue_iteration(iugkp_handle *h, int faces)
         <<<dim3(ih.stripe_C, ih.stripe_S), kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R,
                                                                               ih.stripe_C, faces);
     HIP_TRY(hipGetLastError());
-  } else if (faces && ih.stripe_R > 0 && (form = pick_form(h)) == kFormStripes) {
+  } else if (faces && ih.stripe_R > 0 &&
+             ((form = pick_form(h)) == kFormStripes || form == kFormPieces)) {
     const unsigned long long np =
         static_cast<unsigned long long>(m.n_emit) * static_cast<unsigned long long>(ih.d.N);
     constexpr unsigned int per_block = iugkp::kPresampleBlock * iugkp::kPresamplePer;
@@ -1592,8 +1598,12 @@ int enqueue_iteration(iugkp_handle *h, int faces)
       iugkp::stripe_presample_kernel<iugkp::kPresampleBlock, false>
           <<<pg, iugkp::kPresampleBlock, iugkp::kPresampleBlock * sizeof(iugkp::PRec) + ps_lds, s>>>(
               h->d_inst, ih.rec);
-    iugkp::march_stripes_kernel<kStripeBlock>
-        <<<sg, kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
+    if (!ih.d.has_null && form == kFormPieces)
+      iugkp::march_stripes_pieces_kernel<kStripeBlock>
+          <<<sg, kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
+    else
+      iugkp::march_stripes_kernel<kStripeBlock>
+          <<<sg, kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
     HIP_TRY(hipGetLastError());
   } else {
     const int block = (form == kFormTiles512) ? 512 : h->block;
@@ -1739,7 +1749,8 @@ int iugkp_create(const iugkp_problem *problem, const iugkp_options *options, voi
   const int K = h->bh.K;
   h->block = options->block_size ? options->block_size : 256;
   if (!bands && h->ih.stripe_R > 0 && !h->ih.d.estimator) {
-    h->form_default = h->ih.stripe_pref ? kFormStripes : kFormTiles256;
+    h->form_default = !h->ih.stripe_pref ? kFormTiles256
+                      : (options->march == 3 && !h->ih.d.has_null) ? kFormPieces : kFormStripes;
     h->form_search = (options->march == 0 && options->block_size == 0);
     if (h->form_search) {
       std::lock_guard<std::mutex> lock(g_form_mu);

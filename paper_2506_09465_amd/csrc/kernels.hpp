@@ -1110,36 +1110,17 @@ __global__ __launch_bounds__(BS) void stripe_presample_kernel(const Inst *__rest
   }
 }
 
+// The segment table of a stripe's candidates (one thread per segment):
+// segment i < 2K is this stripe's sub-bin i / 2, its front (stayers) or back
+// (leavers); then, for each other stripe in order, its K sub-bins' leavers.
+// s_slot: the first slot of each; s_pre: their starts in one running count
+// (a workgroup scan of the counts), s_pre[(S + 1) K] the total.  Ends with a
+// barrier.
 template <int BS>
-__global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restrict__ insts, int R,
-                                                           int chunks, StripeRec rec)
+__device__ __forceinline__ void stripe_segment_table(const StripeRec &rec, uint32_t *s_pre,
+                                                     uint32_t *s_slot, uint32_t *s_wsum)
 {
-  extern __shared__ long long lds_words[];
-  __shared__ unsigned long long s_cnt[3];
-  // the stripe's candidates as segments of slots: its own stayers, its own
-  // leavers, then every other start stripe's leavers (checked against the
-  // rows); s_pre: their starts in one running count
   static_assert(BS >= kStripeSegMax, "one thread per segment");
-  __shared__ uint32_t s_pre[kStripeSegMax + 1], s_slot[kStripeSegMax];
-  __shared__ uint32_t s_wsum[BS / 64];
-  const Inst &in = insts[0];
-  // (the mesh and the tally pointers in registers: reloaded inside the state
-  // machine, each load would also wait for the lane's pending LDS atomics)
-  const Mesh m = in.m;
-  long long *const gD = in.D, *const gW = in.W, *const gB = in.B, *const gPhiy = in.Phiy;
-  const bool lds_walls = in.lds_walls != 0;
-  const int nx = m.nx;
-  const int r0 = static_cast<int>(blockIdx.y) * R, r1 = min(r0 + R, m.ny);
-  const int r1f = (r1 == m.ny) ? m.ny + 1 : r1;
-  const int nface = r1f - r0;
-  long long *By = lds_words;                                  // [nface][nx]
-  long long *Bl = By + nface * nx;                            // [n_b] when lds_walls
-  const int nwords = nface * nx + (lds_walls ? m.n_b : 0);
-  for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
-  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
-  // segment i of the (S + 1) K: i < 2K this stripe's sub-bin i / 2, its front
-  // (stayers) or back (leavers); then, for each other stripe in order, its K
-  // sub-bins' leavers; their starts by a workgroup scan of the counts
   const int K = rec.K, nseg = (rec.S + 1) * K, nown = 2 * K;
   {
     const int sb = static_cast<int>(blockIdx.y);
@@ -1179,6 +1160,39 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
     if (i == nseg - 1) s_pre[nseg] = off + incl;
   }
   __syncthreads();
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restrict__ insts, int R,
+                                                           int chunks, StripeRec rec)
+{
+  extern __shared__ long long lds_words[];
+  __shared__ unsigned long long s_cnt[3];
+  // the stripe's candidates as segments of slots: its own stayers, its own
+  // leavers, then every other start stripe's leavers (checked against the
+  // rows); s_pre: their starts in one running count
+  static_assert(BS >= kStripeSegMax, "one thread per segment");
+  __shared__ uint32_t s_pre[kStripeSegMax + 1], s_slot[kStripeSegMax];
+  __shared__ uint32_t s_wsum[BS / 64];
+  const Inst &in = insts[0];
+  // (the mesh and the tally pointers in registers: reloaded inside the state
+  // machine, each load would also wait for the lane's pending LDS atomics)
+  const Mesh m = in.m;
+  long long *const gD = in.D, *const gW = in.W, *const gB = in.B, *const gPhiy = in.Phiy;
+  const bool lds_walls = in.lds_walls != 0;
+  const int nx = m.nx;
+  const int r0 = static_cast<int>(blockIdx.y) * R, r1 = min(r0 + R, m.ny);
+  const int r1f = (r1 == m.ny) ? m.ny + 1 : r1;
+  const int nface = r1f - r0;
+  long long *By = lds_words;                                  // [nface][nx]
+  long long *Bl = By + nface * nx;                            // [n_b] when lds_walls
+  const int nwords = nface * nx + (lds_walls ? m.n_b : 0);
+  for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  // the candidates: segments of slots (this stripe's stayers and leavers, then
+  // the other stripes' leavers), their starts in one running count
+  const int K = rec.K, nseg = (rec.S + 1) * K, nown = 2 * K;
+  stripe_segment_table<BS>(rec, s_pre, s_slot, s_wsum);
   auto lds_add = [](long long *p, long long v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
   };
@@ -1367,6 +1381,189 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
   if (n_fl) {
     atomicAdd(&s_cnt[0], n_fl);
     atomicAdd(&s_cnt[1], n_seg);
+    atomicAdd(&s_cnt[2], n_cross);
+  }
+  __syncthreads();
+  // row-contiguous flush
+  for (int i = threadIdx.x; i < nface * nx; i += BS)
+    if (By[i]) atom_add(&gPhiy[r0 * nx + i], By[i]);
+  if (lds_walls)
+    for (int b = threadIdx.x; b < m.n_b; b += BS)
+      if (Bl[b]) atom_add(&gB[b], Bl[b]);
+  if (threadIdx.x == 0 && s_cnt[0]) {
+    atomicAdd(&in.sc->flights, s_cnt[0]);
+    atomicAdd(&in.sc->segments, s_cnt[1]);
+    atomicAdd(&in.sc->crossings, s_cnt[2]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same particle step for flights without null collisions (each record's
+// first segment is the whole flight), with the y-face work cut into pieces:
+// workgroup (chunk c, stripe s) takes its candidates kStripeScan at a time,
+// one per thread: a candidate that meets the stripe tallies its end (deposit
+// or wall absorption, and the counters) if that happens in the stripe's rows,
+// and is listed with its number of pieces, at most kStripePiece consecutive
+// owned y faces each; a workgroup prefix sum numbers the pieces and every lane
+// takes one (a binary search finds its particle), so the lanes of a wavefront
+// do nearly equal work whatever the spread of path lengths (with one
+// particle per lane they waited for the longest: 28% / 52% / 61% VALU lane
+// utilisation at Kn 0.1 / 1 / 10 on the 256^2 cavity).  Each crossing is
+// tallied in the column reached by the x faces before it, from its own time
+// (faces_upto_near), so a piece needs no earlier crossing of its particle.
+// Integer sums: the same tallies as the tile kernel, bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int kStripeScan = 1024;
+constexpr int kStripePiece = 16;
+
+template <int BS>
+__global__ __launch_bounds__(BS) void march_stripes_pieces_kernel(const Inst *__restrict__ insts,
+                                                                  int R, int chunks, StripeRec rec)
+{
+  static_assert(BS == kStripeScan, "one candidate per thread per round");
+  extern __shared__ long long lds_words[];
+  __shared__ unsigned long long s_cnt[3];
+  __shared__ uint32_t s_pre[kStripeSegMax + 1], s_slot[kStripeSegMax];
+  __shared__ uint32_t s_wsum[BS / 64];
+  __shared__ uint32_t s_list[kStripeScan], s_ppre[kStripeScan + 1];
+  __shared__ uint32_t s_n;
+  const Inst &in = insts[0];
+  const Mesh m = in.m;
+  long long *const gD = in.D, *const gB = in.B, *const gPhiy = in.Phiy;
+  const bool lds_walls = in.lds_walls != 0;
+  const int nx = m.nx;
+  const int r0 = static_cast<int>(blockIdx.y) * R, r1 = min(r0 + R, m.ny);
+  const int r1f = (r1 == m.ny) ? m.ny + 1 : r1;
+  const int nface = r1f - r0;
+  long long *By = lds_words;                                  // [nface][nx]
+  long long *Bl = By + nface * nx;                            // [n_b] when lds_walls
+  const int nwords = nface * nx + (lds_walls ? m.n_b : 0);
+  for (int i = threadIdx.x; i < nwords; i += BS) lds_words[i] = 0;
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  const int K = rec.K, nseg = (rec.S + 1) * K, nown = 2 * K;
+  stripe_segment_table<BS>(rec, s_pre, s_slot, s_wsum);
+  auto lds_add = [](long long *p, long long v) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
+  };
+  const uint32_t V = s_pre[nseg];
+  const uint32_t vb = static_cast<uint32_t>(static_cast<unsigned long long>(V) * blockIdx.x / chunks);
+  const uint32_t ve = static_cast<uint32_t>(static_cast<unsigned long long>(V) * (blockIdx.x + 1) / chunks);
+  const double inv_dx = 1.0 / m.dx;       // (only to estimate a face count)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const PRec *const recs = static_cast<const PRec *>(rec.r);
+  // the owned crossed y faces of a record: first face and count (0: none)
+  auto owned_faces = [&](uint32_t cell, double sy, uint32_t nyp, int &f_lo) {
+    if (nyp == 0u) return 0;
+    const int sty = (sy > 0.0) ? 1 : -1;
+    const int iy = static_cast<int>(cell >> 16);
+    const int ky0 = (sty > 0) ? iy + 1 : iy;
+    const int kl = ky0 + (static_cast<int>(nyp) - 1) * sty;
+    f_lo = max(min(ky0, kl), r0);
+    return max(0, min(max(ky0, kl), r1f - 1) - f_lo + 1);
+  };
+  unsigned long long n_fl = 0, n_cross = 0;
+  int sg = 0;
+  for (unsigned long long v0 = vb; v0 < ve; v0 += kStripeScan) {
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const uint32_t v = static_cast<uint32_t>(min(v0 + threadIdx.x, static_cast<unsigned long long>(ve)));
+    bool hit = false;
+    uint32_t slot = 0, npc = 0;
+    if (v < ve) {
+      while (sg + 1 < nseg && v >= s_pre[sg + 1]) ++sg;
+      slot = s_slot[sg] + (v - s_pre[sg]);
+      bool go = true;
+      if (sg >= nown) {   // another stripe's leaver: only if it reaches these rows
+        const uint32_t key = rec.key[slot];
+        go = !(static_cast<int>(key & 0xffffu) < r0 || static_cast<int>(key >> 16) >= r1);
+      }
+      if (go) {
+        const PRec rp = recs[slot];
+        const int ixe = static_cast<int>(rp.cell_e & 0xffffu), iye = static_cast<int>(rp.cell_e >> 16);
+        if (iye >= r0 && iye < r1) {      // the flight ends in this stripe's rows
+          if (rp.bface >= 0) {
+            if (!lds_walls) atom_add(&gB[rp.bface], rp.q);
+            else lds_add(&Bl[rp.bface], rp.q);
+          } else {
+            atom_add(&gD[ixe + nx * iye], rp.q);
+          }
+          ++n_fl;
+          n_cross += rp.ncross;
+        }
+        int f_lo = 0;
+        const int c = owned_faces(rp.cell, rp.sy, rp.nyp, f_lo);
+        npc = static_cast<uint32_t>((c + kStripePiece - 1) / kStripePiece);
+        hit = npc > 0u;
+      }
+    }
+    // listed with their piece counts (one LDS atomic per wavefront)
+    const unsigned long long mask = __ballot(hit);
+    if (mask) {
+      uint32_t off = 0;
+      if (lane == 0) off = atomicAdd(&s_n, static_cast<uint32_t>(__popcll(mask)));
+      off = __shfl(off, 0, 64);
+      if (hit) {
+        const uint32_t pos = off + static_cast<uint32_t>(__popcll(mask & ((1ull << lane) - 1ull)));
+        s_list[pos] = slot;
+        s_ppre[pos] = npc;
+      }
+    }
+    __syncthreads();
+    const int nl = static_cast<int>(s_n);
+    {
+      // exclusive prefix of the piece counts, in place (one entry per thread)
+      const int i = static_cast<int>(threadIdx.x);
+      const uint32_t c = (i < nl) ? s_ppre[i] : 0u;
+      uint32_t incl = c;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = static_cast<uint32_t>(__shfl_up(static_cast<int>(incl), d, 64));
+        if (lane >= d) incl += o;
+      }
+      if (lane == 63) s_wsum[wv] = incl;
+      __syncthreads();
+      uint32_t off = 0;
+      for (int w = 0; w < wv; ++w) off += s_wsum[w];
+      if (i < nl) s_ppre[i] = off + incl - c;
+      if (i == nl - 1) s_ppre[nl] = off + incl;
+      if (nl == 0 && i == 0) s_ppre[0] = 0u;
+    }
+    __syncthreads();
+    const uint32_t n_piece = s_ppre[nl];
+    for (uint32_t u = threadIdx.x; u < n_piece; u += BS) {
+      // the listed particle of piece u: the last i with s_ppre[i] <= u
+      int a = 0, b = nl - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (s_ppre[mid] <= u) a = mid;
+        else b = mid - 1;
+      }
+      const PRec &rp = recs[s_list[a]];
+      const uint32_t cell = rp.cell, nyp = rp.nyp;
+      const double x0 = rp.x0, y0 = rp.y0, sx = rp.sx, sy = rp.sy;
+      const long long q = rp.q;
+      int f_lo = 0;
+      const int c = owned_faces(cell, sy, nyp, f_lo);
+      const int f0 = f_lo + static_cast<int>(u - s_ppre[a]) * kStripePiece;
+      const int f1 = min(f_lo + c, f0 + kStripePiece);
+      const int ix0 = static_cast<int>(cell & 0xffffu);
+      const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+      const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+      const double inv_sy = 1.0 / sy;                        // (a y face crossed: s_y != 0)
+      const long long qy = (sy > 0.0) ? q : -q;
+      const int kx0 = (stx > 0) ? ix0 + 1 : ix0;
+      const int jwx = (stx > 0) ? nx - kx0 : kx0;
+      for (int kyk = f0; kyk < f1; ++kyk) {
+        const double ty = (static_cast<double>(kyk) * m.dy - y0) * inv_sy;
+        const int cnt = stx ? faces_upto_near(0, kx0, stx, jwx, m.dx, inv_dx, x0, inv_sx, sx, ty) : 0;
+        lds_add(&By[(kyk - r0) * nx + ix0 + stx * cnt], qy);
+      }
+    }
+    __syncthreads();
+  }
+  if (n_fl) {
+    atomicAdd(&s_cnt[0], n_fl);
+    atomicAdd(&s_cnt[1], n_fl);        // (one segment per flight)
     atomicAdd(&s_cnt[2], n_cross);
   }
   __syncthreads();

@@ -223,13 +223,13 @@ class Solver:
 
     def march_tuning(self):
         """(form, ms): the particle step's form for face-tallied iterations
-        ("tiles256", "tiles512", "stripes", or None while the handle still
-        measures them) and the measured milliseconds per form (None where not
-        measured)."""
+        ("tiles256", "tiles512", "stripes", "stripes_pieces", or None while the
+        handle still measures them) and the measured milliseconds per form
+        (None where not measured)."""
         form = C.c_int(0)
-        ms = (C.c_float * 3)()
+        ms = (C.c_float * 4)()
         L.check(L.lib().iugkp_march_tuning(self.h, C.byref(form), ms), "iugkp_march_tuning")
-        names = ("tiles256", "tiles512", "stripes")
+        names = ("tiles256", "tiles512", "stripes", "stripes_pieces")
         return (names[form.value] if form.value >= 0 else None,
                 {n: (float(v) if v >= 0 else None) for n, v in zip(names, ms)})
 

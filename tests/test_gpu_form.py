@@ -1,5 +1,6 @@
 """The particle-step form search of a single solve (emitter tiles of 256 or
-512 threads, or row stripes, timed one iteration each, then the fastest):
+512 threads, row stripes, or row stripes with the crossings in pieces, timed
+one iteration each, then the fastest):
 every form gives the tallies of the forced tile march bit for bit, the choice
 is kept for later handles of the same class, and a handle with a set block
 size or march does not search."""
@@ -29,26 +30,27 @@ def _same_tallies(a, b):
         assert np.array_equal(ta[k].cpu().numpy(), tb[k].cpu().numpy()), k
 
 
-@pytest.mark.parametrize("make", [
-    lambda: cavity_2d(n=61, ny=47, kn=0.05, particles=200_000, newton=False, seed=21),
-    lambda: two_material_2d(n=53, kn_right=0.2, ratio=10.0, particles=200_000, seed=22),
+# (row stripes in pieces are a form only without null collisions)
+@pytest.mark.parametrize("make,n_forms", [
+    (lambda: cavity_2d(n=61, ny=47, kn=0.05, particles=200_000, newton=False, seed=21), 4),
+    (lambda: two_material_2d(n=53, kn_right=0.2, ratio=10.0, particles=200_000, seed=22), 3),
 ], ids=["cavity_61x47", "two_material_53"])
-def test_form_search_equals_tiles_and_is_kept(gpu, make):
+def test_form_search_equals_tiles_and_is_kept(gpu, make, n_forms):
     w = make()
     kw = dict(tally_faces=gpu.FACES_EVERY, rng_mode=gpu.RNG_CRN, newton=False)
     s = gpu.Solver(w, **kw)
     ref = gpu.Solver(w, march=1, **kw)               # the tile march, forced
     form, ms = s.march_tuning()
     assert form is None and all(v is None for v in ms.values())
-    for it in range(5):
+    for it in range(n_forms + 2):
         assert s.step(1) == 0 and ref.step(1) == 0
         _same_tallies(s, ref)
-        if it < 3:
+        if it < n_forms:
             assert s.march_tuning()[0] is None       # still measuring
     form, ms = s.march_tuning()
-    assert form in ("tiles256", "tiles512", "stripes")
-    assert all(v is not None and v > 0.0 for v in ms.values())
-    assert ms[form] == min(ms.values())
+    measured = {k: v for k, v in ms.items() if v is not None}
+    assert len(measured) == n_forms and all(v > 0.0 for v in measured.values())
+    assert form in measured and ms[form] == min(measured.values())
     # a later handle of the same class starts with the choice
     s2 = gpu.Solver(w, **kw)
     assert s2.march_tuning()[0] == form

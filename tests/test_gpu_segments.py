@@ -133,8 +133,11 @@ def _wide_null():
     return w
 
 
+# march 2: each lane runs its particles' crossings; march 3: the crossings cut
+# into pieces, one per lane (flights without null collisions; with them as 2)
 @pytest.mark.parametrize("name", list(STRIPE_CASES))
-def test_stripe_march_bitwise(oracle_mod, gpu, name):
+@pytest.mark.parametrize("march", [2, 3])
+def test_stripe_march_bitwise(oracle_mod, gpu, name, march):
     """Row stripes (forced) against the oracle, faces tallied every iteration:
     all tallies, counters and the state bit for bit."""
     make, extra = STRIPE_CASES[name]
@@ -143,7 +146,7 @@ def test_stripe_march_bitwise(oracle_mod, gpu, name):
     if extra == "newton":
         Dx, Dy = _diff(w)
         kw.update(newton=True, diff_x=Dx, diff_y=Dy)
-    o, s = _pair(oracle_mod, gpu, w, march=2, **kw)
+    o, s = _pair(oracle_mod, gpu, w, march=march, **kw)
     assert o.step(2) == 0 and s.step(2) == 0
     to = o.tallies()
     ts = {k: _np(v) for k, v in s.tallies().items()}
@@ -160,10 +163,11 @@ def test_stripe_and_tile_marches_agree_256(gpu):
     tallies (forced tiles vs forced stripes)."""
     w = cavity_2d(n=256, kn=10.0, particles=10_000_000, newton=False)
     out = []
-    for march in (1, 2):
+    for march in (1, 2, 3):
         s = gpu.Solver(w, march=march, tally_faces=gpu.FACES_EVERY)
         assert s.step(2) == 0
         out.append({k: _np(v) for k, v in s.tallies().items()} | {"st": s.stats()})
-    for k in ("D", "Phix", "Phiy", "B"):
-        assert np.array_equal(out[0][k], out[1][k]), k
-    assert out[0]["st"]["crossings"] == out[1]["st"]["crossings"]
+    for o in out[1:]:
+        for k in ("D", "Phix", "Phiy", "B"):
+            assert np.array_equal(out[0][k], o[k]), k
+        assert out[0]["st"]["crossings"] == o["st"]["crossings"]
