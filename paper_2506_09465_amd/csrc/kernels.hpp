@@ -1462,39 +1462,67 @@ __global__ __launch_bounds__(BS) void march_stripes_pieces_kernel(const Inst *__
     return max(0, min(max(ky0, kl), r1f - 1) - f_lo + 1);
   };
   unsigned long long n_fl = 0, n_cross = 0;
+  // the thread's candidate of the next round, loaded while the current
+  // round's pieces run: its slot, row range (another stripe's leaver) and
+  // record (whether or not the range lets it in)
   int sg = 0;
+  uint32_t c_slot = 0, c_key = 0;
+  bool c_valid = false, c_foreign = false;
+  PRec c_rec{};
+  auto fetch = [&](unsigned long long vv) {
+    c_valid = vv < ve;
+    if (!c_valid) return;
+    const uint32_t v = static_cast<uint32_t>(vv);
+    while (sg + 1 < nseg && v >= s_pre[sg + 1]) ++sg;
+    c_slot = s_slot[sg] + (v - s_pre[sg]);
+    c_foreign = sg >= nown;
+    c_key = c_foreign ? rec.key[c_slot] : 0u;
+    c_rec = recs[c_slot];
+  };
+  // a piece's particle: what its crossings need
+  struct Piece {
+    double x0, y0, sx, sy;
+    long long q;
+    uint32_t cell, nyp;
+  };
+  auto piece_of = [&](uint32_t slot) {
+    const PRec &rp = recs[slot];
+    return Piece{rp.x0, rp.y0, rp.sx, rp.sy, rp.q, rp.cell, rp.nyp};
+  };
+  auto piece_item = [&](uint32_t u) {       // the last listed i with s_ppre[i] <= u
+    int lo = 0, hi = static_cast<int>(s_n) - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_ppre[mid] <= u) lo = mid;
+      else hi = mid - 1;
+    }
+    return lo;
+  };
+  fetch(static_cast<unsigned long long>(vb) + threadIdx.x);
   for (unsigned long long v0 = vb; v0 < ve; v0 += kStripeScan) {
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
-    const uint32_t v = static_cast<uint32_t>(min(v0 + threadIdx.x, static_cast<unsigned long long>(ve)));
     bool hit = false;
-    uint32_t slot = 0, npc = 0;
-    if (v < ve) {
-      while (sg + 1 < nseg && v >= s_pre[sg + 1]) ++sg;
-      slot = s_slot[sg] + (v - s_pre[sg]);
-      bool go = true;
-      if (sg >= nown) {   // another stripe's leaver: only if it reaches these rows
-        const uint32_t key = rec.key[slot];
-        go = !(static_cast<int>(key & 0xffffu) < r0 || static_cast<int>(key >> 16) >= r1);
-      }
-      if (go) {
-        const PRec rp = recs[slot];
-        const int ixe = static_cast<int>(rp.cell_e & 0xffffu), iye = static_cast<int>(rp.cell_e >> 16);
-        if (iye >= r0 && iye < r1) {      // the flight ends in this stripe's rows
-          if (rp.bface >= 0) {
-            if (!lds_walls) atom_add(&gB[rp.bface], rp.q);
-            else lds_add(&Bl[rp.bface], rp.q);
-          } else {
-            atom_add(&gD[ixe + nx * iye], rp.q);
-          }
-          ++n_fl;
-          n_cross += rp.ncross;
+    uint32_t slot = c_slot, npc = 0;
+    if (c_valid &&
+        !(c_foreign && (static_cast<int>(c_key & 0xffffu) < r0 || static_cast<int>(c_key >> 16) >= r1))) {
+      // (another stripe's leaver enters only if it reaches these rows)
+      const PRec &rp = c_rec;
+      const int ixe = static_cast<int>(rp.cell_e & 0xffffu), iye = static_cast<int>(rp.cell_e >> 16);
+      if (iye >= r0 && iye < r1) {      // the flight ends in this stripe's rows
+        if (rp.bface >= 0) {
+          if (!lds_walls) atom_add(&gB[rp.bface], rp.q);
+          else lds_add(&Bl[rp.bface], rp.q);
+        } else {
+          atom_add(&gD[ixe + nx * iye], rp.q);
         }
-        int f_lo = 0;
-        const int c = owned_faces(rp.cell, rp.sy, rp.nyp, f_lo);
-        npc = static_cast<uint32_t>((c + kStripePiece - 1) / kStripePiece);
-        hit = npc > 0u;
+        ++n_fl;
+        n_cross += rp.ncross;
       }
+      int f_lo = 0;
+      const int c = owned_faces(rp.cell, rp.sy, rp.nyp, f_lo);
+      npc = static_cast<uint32_t>((c + kStripePiece - 1) / kStripePiece);
+      hit = npc > 0u;
     }
     // listed with their piece counts (one LDS atomic per wavefront)
     const unsigned long long mask = __ballot(hit);
@@ -1529,35 +1557,44 @@ __global__ __launch_bounds__(BS) void march_stripes_pieces_kernel(const Inst *__
       if (nl == 0 && i == 0) s_ppre[0] = 0u;
     }
     __syncthreads();
+    fetch(v0 + kStripeScan + threadIdx.x);          // (in flight during the pieces)
     const uint32_t n_piece = s_ppre[nl];
-    for (uint32_t u = threadIdx.x; u < n_piece; u += BS) {
-      // the listed particle of piece u: the last i with s_ppre[i] <= u
-      int a = 0, b = nl - 1;
-      while (a < b) {
-        const int mid = (a + b + 1) >> 1;
-        if (s_ppre[mid] <= u) a = mid;
-        else b = mid - 1;
+    // the lane's pieces u, u + BS, ...: the next one's record loaded while the
+    // current one's crossings run
+    uint32_t u = threadIdx.x;
+    int ia = 0;
+    Piece cur{};
+    if (u < n_piece) {
+      ia = piece_item(u);
+      cur = piece_of(s_list[ia]);
+    }
+    while (u < n_piece) {
+      const uint32_t un = u + BS;
+      int ib = 0;
+      Piece nxt{};
+      if (un < n_piece) {
+        ib = piece_item(un);
+        nxt = piece_of(s_list[ib]);
       }
-      const PRec &rp = recs[s_list[a]];
-      const uint32_t cell = rp.cell, nyp = rp.nyp;
-      const double x0 = rp.x0, y0 = rp.y0, sx = rp.sx, sy = rp.sy;
-      const long long q = rp.q;
       int f_lo = 0;
-      const int c = owned_faces(cell, sy, nyp, f_lo);
-      const int f0 = f_lo + static_cast<int>(u - s_ppre[a]) * kStripePiece;
+      const int c = owned_faces(cur.cell, cur.sy, cur.nyp, f_lo);
+      const int f0 = f_lo + static_cast<int>(u - s_ppre[ia]) * kStripePiece;
       const int f1 = min(f_lo + c, f0 + kStripePiece);
-      const int ix0 = static_cast<int>(cell & 0xffffu);
-      const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
-      const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
-      const double inv_sy = 1.0 / sy;                        // (a y face crossed: s_y != 0)
-      const long long qy = (sy > 0.0) ? q : -q;
+      const int ix0 = static_cast<int>(cur.cell & 0xffffu);
+      const int stx = (cur.sx > 0.0) ? 1 : ((cur.sx < 0.0) ? -1 : 0);
+      const double inv_sx = (cur.sx != 0.0) ? 1.0 / cur.sx : 0.0;
+      const double inv_sy = 1.0 / cur.sy;                    // (a y face crossed: s_y != 0)
+      const long long qy = (cur.sy > 0.0) ? cur.q : -cur.q;
       const int kx0 = (stx > 0) ? ix0 + 1 : ix0;
       const int jwx = (stx > 0) ? nx - kx0 : kx0;
       for (int kyk = f0; kyk < f1; ++kyk) {
-        const double ty = (static_cast<double>(kyk) * m.dy - y0) * inv_sy;
-        const int cnt = stx ? faces_upto_near(0, kx0, stx, jwx, m.dx, inv_dx, x0, inv_sx, sx, ty) : 0;
+        const double ty = (static_cast<double>(kyk) * m.dy - cur.y0) * inv_sy;
+        const int cnt = stx ? faces_upto_near(0, kx0, stx, jwx, m.dx, inv_dx, cur.x0, inv_sx, cur.sx, ty) : 0;
         lds_add(&By[(kyk - r0) * nx + ix0 + stx * cnt], qy);
       }
+      u = un;
+      ia = ib;
+      cur = nxt;
     }
     __syncthreads();
   }
