@@ -3275,12 +3275,14 @@ __global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict
   // first (particles of neighbouring indices tend to end in the same cell)
   {
     int head, run;
+    // (W takes the null particles' weights only here; persist_update_kernel
+    // adds W^h, so a real collision costs two atomics, not three)
     wave_runs(ckey, head, run);
-    const long long sw = run_sum(qv, run);
+    const long long sw = run_sum(real ? 0ll : qv, run);
     const long long sh = run_sum(real ? qv : 0ll, run);
     const long long sn = run_sum(static_cast<long long>(real), run);
     if (head && ckey >= 0) {
-      atom_add(&in.W[ckey], sw);
+      if (sw) atom_add(&in.W[ckey], sw);   // (adding 0 changes nothing)
       if (sn) {
         atom_add(&in.D[ckey], sh);
         atomicAdd(&in.Nrc[ckey], static_cast<uint32_t>(sn));
@@ -3465,7 +3467,11 @@ __global__ __launch_bounds__(256) void persist_update_kernel(const Inst *__restr
   if (static_cast<int>(blockIdx.x) < nbc) {
     const int c = blockIdx.x * kTree + t;
     if (c < nc) {
-      const double En = ldexp(static_cast<double>(in.W[c]), -in.F) / in.V;
+      // W: the move tallied the null particles' weights, W^h the real ones'
+      const long long Wc = static_cast<long long>(static_cast<unsigned long long>(in.W[c]) +
+                                                  static_cast<unsigned long long>(in.D[c]));
+      in.W[c] = Wc;
+      const double En = ldexp(static_cast<double>(Wc), -in.F) / in.V;
       const double d = En - in.E[c];
       sq = d * d;
       if (!isfinite(En)) flags |= 1;
@@ -3482,7 +3488,7 @@ __global__ __launch_bounds__(256) void persist_update_kernel(const Inst *__restr
       ag = abs_u64(w) * n + abs_u64(r);
       // the next iteration's paths start from this cell with the null
       // particles' weights and the real ones' new share
-      in.pstart[c] = static_cast<long long>(static_cast<unsigned long long>(in.W[c]) -
+      in.pstart[c] = static_cast<long long>(static_cast<unsigned long long>(Wc) -
                                             static_cast<unsigned long long>(in.D[c]) +
                                             static_cast<unsigned long long>(w) * n);
     }
@@ -3545,8 +3551,9 @@ __global__ __launch_bounds__(256) void persist_reconstruct_x_kernel(const Inst *
             two ? static_cast<unsigned long long>(in.Phiy[j * m.nx + i]) -
                       static_cast<unsigned long long>(in.Phiy[(j + 1) * m.nx + i])
                 : 0ull;
+        // (W is still the null part here: the cell's end weight is W + W^h)
         return dy + (static_cast<unsigned long long>(in.pstart[c]) -
-                     static_cast<unsigned long long>(in.W[c]));
+                     static_cast<unsigned long long>(in.W[c]) - static_cast<unsigned long long>(in.D[c]));
       },
       [&](int i, unsigned long long v) { px[i + 1] = static_cast<long long>(v); });
 }
