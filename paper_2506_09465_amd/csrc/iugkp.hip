@@ -345,7 +345,7 @@ int setup_persistent(InstHost &ih, const std::vector<double> &T0, const std::vec
   if (n > 0xFFFFFFFEull) return fail(IUGKP_E_INVALID_ARG, "persistent population above 2^32 - 2");
   d.persist = 1;
   d.n_part = static_cast<unsigned int>(n);
-  d.n_npart = cdiv(static_cast<long long>(n), kPersistBlock);
+  d.n_npart = cdiv(static_cast<long long>(n), kPersistBlock * iugkp::kPersistPer);
   d.n_gpart = cdiv(nc, iugkp::kTree) + cdiv(nb, iugkp::kTree) + 1;
 #define PALLOC(ptr, k) \
   if (ih.alloc(&(ptr), (k)) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
@@ -1555,8 +1555,12 @@ int enqueue_iteration(iugkp_handle *h, int faces)
     iugkp::persist_prepare_kernel<<<cdiv(nmax, 256), 256, 0, s>>>(h->d_inst);
     HIP_TRY(hipEventRecord(h->ev[0], s));
     const int stripes = (faces && ih.pst_R > 0) ? 1 : 0;
+    // (the wall tallies in LDS up to 16 KB: 1365 wall faces)
+    const size_t wall_lds = static_cast<size_t>(m.n_b) * (sizeof(long long) + sizeof(uint32_t));
+    const int lds_walls = wall_lds <= 16384 ? 1 : 0;
     iugkp::persist_move_kernel<kPersistBlock>
-        <<<ih.d.n_npart, kPersistBlock, 0, s>>>(h->d_inst, faces, stripes);
+        <<<ih.d.n_npart, kPersistBlock, lds_walls ? wall_lds : 0, s>>>(h->d_inst, faces, stripes,
+                                                                         lds_walls);
     HIP_TRY(hipGetLastError());
     if (stripes) {
       iugkp::persist_faces_kernel<kPersistFacesBlock>

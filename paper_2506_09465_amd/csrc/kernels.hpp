@@ -3139,161 +3139,192 @@ __device__ __forceinline__ bool persist_walk(const Mesh &m, double x0, double y0
   return absorbed;
 }
 
-// The move: one thread per particle; tallies by global atomics (W, W^h, N_rc,
-// B, N_b, crossed faces); counters and the null particles' |q| sum per
-// workgroup.
+// The move: kPersistPer particles per thread, consecutive wavefront-wide
+// blocks of the population; tallies by global atomics (W, W^h, N_rc, and
+// the crossed faces unless the row-stripe pass takes them), the wall faces'
+// B and N_b in LDS when lds_walls (a workgroup's 2048 particles then cost one
+// global atomic per wall face they reach, not per particle); counters and
+// the null particles' |q| sum per workgroup.
 // (no y face crossed: an empty range, first > last for every row count up to
 // 65534)
 constexpr uint32_t kNoFaces = 0x0000FFFFu;
+constexpr int kPersistPer = 8;
 
 template <int BS>
 __global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict__ insts, int faces,
-                                                          int stripes)
+                                                          int stripes, int lds_walls)
 {
+  extern __shared__ long long s_walls[];   // lds_walls: B [n_b], then N_b [n_b] (32-bit)
   __shared__ unsigned long long s_red[3][BS / 64];
   const Inst &in = insts[0];
   const Mesh &m = in.m;
   const uint32_t slot = in.crn ? in.epoch : in.sc->iter;
-  const unsigned int p = blockIdx.x * BS + threadIdx.x;
-  unsigned long long fl = 0, cr = 0, nul = 0;
-  int ckey = -1, wkey = -1, real = 0;   // end cell or wall face of this lane's path
-  long long qv = 0;
-  if (p < in.n_part) {
-    const uint32_t lk = in.plk[p];
-    const uint32_t kind = lk >> 30, loc = lk & kLocMask;
-    double x, y, sx, sy;
-    long long q;
-    int ix, iy;
-    if (kind == 1) {
-      const double2 uab = draw2(0u, p, kPersistStream, slot, in.key0, in.key1);
-      const double2 ucd = draw2(1u, p, kPersistStream, slot, in.key0, in.key1);
-      iy = static_cast<int>(loc) / m.nx;
-      ix = static_cast<int>(loc) - iy * m.nx;
-      x = (static_cast<double>(ix) + uab.x) * m.dx;
-      y = (static_cast<double>(iy) + uab.y) * m.dy;
-      iso_direction(m.dim, ucd, sx, sy);
-      q = in.wc[loc];
-    } else if (kind == 2) {
-      const int b = static_cast<int>(loc);
-      const double2 uab = draw2(0u, p, kPersistStream, slot, in.key0, in.key1);
-      const double2 ucd = draw2(1u, p, kPersistStream, slot, in.key0, in.key1);
-      const double cn = sqrt(ucd.x);
-      const double tg = (m.dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * cos2pi_own(ucd.y) : 0.0;
-      q = in.wb[b];
-      if (b < m.ny) {
-        ix = 0; iy = b;
-        x = 0.0; y = (static_cast<double>(iy) + uab.x) * m.dy;
-        sx = cn; sy = tg;
-      } else if (b < 2 * m.ny) {
-        ix = m.nx - 1; iy = b - m.ny;
-        x = static_cast<double>(m.nx) * m.dx; y = (static_cast<double>(iy) + uab.x) * m.dy;
-        sx = -cn; sy = tg;
-      } else if (b < 2 * m.ny + m.nx) {
-        ix = b - 2 * m.ny; iy = 0;
-        x = (static_cast<double>(ix) + uab.x) * m.dx; y = 0.0;
-        sx = tg; sy = cn;
-        if (faces) atom_add(&in.Phiy[ix], q);
-      } else {
-        ix = b - 2 * m.ny - m.nx; iy = m.ny - 1;
-        x = (static_cast<double>(ix) + uab.x) * m.dx; y = static_cast<double>(m.ny) * m.dy;
-        sx = tg; sy = -cn;
-        if (faces) atom_add(&in.Phiy[m.ny * m.nx + ix], -q);
-      }
-    } else {
-      iy = static_cast<int>(loc) / m.nx;
-      ix = static_cast<int>(loc) - iy * m.nx;
-      x = in.px[p];
-      y = in.py[p];
-      sx = in.psx[p];
-      sy = in.psy[p];
-      q = in.pq[p];
+  long long *const sB = s_walls;
+  uint32_t *const sNb = reinterpret_cast<uint32_t *>(s_walls + m.n_b);
+  if (lds_walls) {
+    for (int b = threadIdx.x; b < m.n_b; b += BS) {
+      sB[b] = 0;
+      sNb[b] = 0u;
     }
-    if (q != 0) fl = 1;
-    const double2 us = draw2(2u, p, kPersistStream, slot, in.key0, in.key1);
-    const double ell = -(in.lam_min * log_own(1.0 - us.x));
-    int bface;
-    uint32_t nlk;
-    bool absorbed;
-    if (faces && stripes) {
-      // the walk in closed form; its y faces are tallied by persist_faces_kernel
-      const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
-      const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
-      const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
-      const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
-      const int kx = (stx > 0) ? ix + 1 : ix, ky = (sty > 0) ? iy + 1 : iy;
-      const uint32_t cell = static_cast<uint32_t>(ix) | (static_cast<uint32_t>(iy) << 16);
-      int nxp = 0, nyp = 0;
-      bface = -1;
-      segment_end(m, x, y, ix, iy, stx, sty, inv_sx, inv_sy, kx, ky, ell, bface, nxp, nyp);
-      cr += static_cast<unsigned long long>(nxp + nyp);
-      absorbed = bface >= 0;
-      uint32_t key = kNoFaces;
-      if (nyp > 0) {
-        const int kl = ky + (nyp - 1) * sty;
-        key = static_cast<uint32_t>(min(ky, kl)) | (static_cast<uint32_t>(max(ky, kl)) << 16);
-        PFace r;
-        r.x0 = x;
-        r.y0 = y;
-        r.sx = sx;
-        r.inv_sx = inv_sx;
-        r.inv_sy = inv_sy;
-        r.q = q;
-        r.cell = cell;
-        r.nyp = static_cast<uint32_t>(nyp);
-        in.pf[p] = r;
-      }
-      in.pkey[p] = key;
-    } else {
-      absorbed = persist_walk(m, x, y, ix, iy, sx, sy, ell, faces, q, in.Phiy, in.dB, bface, cr);
-    }
-    if (absorbed) {
-      wkey = bface;
-      nlk = static_cast<uint32_t>(bface) | (2u << 30);
-    } else {
-      const int c = ix + m.nx * iy;
-      ckey = c;
-      x = clamp_to(x + ell * sx, static_cast<double>(ix) * m.dx, static_cast<double>(ix + 1) * m.dx);
-      if (m.dim == 2)
-        y = clamp_to(y + ell * sy, static_cast<double>(iy) * m.dy, static_cast<double>(iy + 1) * m.dy);
-      if (us.y < in.ratio[c]) {
-        real = 1;
-        nlk = static_cast<uint32_t>(c) | (1u << 30);
-      } else {
-        nul = abs_u64(q);
-        nlk = static_cast<uint32_t>(c);
-      }
-    }
-    qv = q;
-    in.px[p] = x;
-    in.py[p] = y;
-    in.psx[p] = sx;
-    in.psy[p] = sy;
-    in.pq[p] = q;
-    in.plk[p] = nlk;
+    __syncthreads();
   }
-  // end tallies, summed over runs of equal consecutive keys in the wavefront
-  // first (particles of neighbouring indices tend to end in the same cell)
-  {
-    int head, run;
-    // (W takes the null particles' weights only here; persist_update_kernel
-    // adds W^h, so a real collision costs two atomics, not three)
-    wave_runs(ckey, head, run);
-    const long long sw = run_sum(real ? 0ll : qv, run);
-    const long long sh = run_sum(real ? qv : 0ll, run);
-    const long long sn = run_sum(static_cast<long long>(real), run);
-    if (head && ckey >= 0) {
-      if (sw) atom_add(&in.W[ckey], sw);   // (adding 0 changes nothing)
-      if (sn) {
-        atom_add(&in.D[ckey], sh);
-        atomicAdd(&in.Nrc[ckey], static_cast<uint32_t>(sn));
+  unsigned long long fl = 0, cr = 0, nul = 0;
+  const unsigned long long p_first = static_cast<unsigned long long>(blockIdx.x) * (BS * kPersistPer);
+  for (int it = 0; it < kPersistPer; ++it) {
+    const unsigned long long pp = p_first + static_cast<unsigned long long>(it) * BS + threadIdx.x;
+    const unsigned int p = static_cast<unsigned int>(pp);
+    int ckey = -1, wkey = -1, real = 0;   // end cell or wall face of this lane's path
+    long long qv = 0;
+    if (pp < in.n_part) {
+      const uint32_t lk = in.plk[p];
+      const uint32_t kind = lk >> 30, loc = lk & kLocMask;
+      double x, y, sx, sy;
+      long long q;
+      int ix, iy;
+      if (kind == 1) {
+        const double2 uab = draw2(0u, p, kPersistStream, slot, in.key0, in.key1);
+        const double2 ucd = draw2(1u, p, kPersistStream, slot, in.key0, in.key1);
+        iy = static_cast<int>(loc) / m.nx;
+        ix = static_cast<int>(loc) - iy * m.nx;
+        x = (static_cast<double>(ix) + uab.x) * m.dx;
+        y = (static_cast<double>(iy) + uab.y) * m.dy;
+        iso_direction(m.dim, ucd, sx, sy);
+        q = in.wc[loc];
+      } else if (kind == 2) {
+        const int b = static_cast<int>(loc);
+        const double2 uab = draw2(0u, p, kPersistStream, slot, in.key0, in.key1);
+        const double2 ucd = draw2(1u, p, kPersistStream, slot, in.key0, in.key1);
+        const double cn = sqrt(ucd.x);
+        const double tg = (m.dim == 2) ? sqrt((1.0 - cn) * (1.0 + cn)) * cos2pi_own(ucd.y) : 0.0;
+        q = in.wb[b];
+        if (b < m.ny) {
+          ix = 0; iy = b;
+          x = 0.0; y = (static_cast<double>(iy) + uab.x) * m.dy;
+          sx = cn; sy = tg;
+        } else if (b < 2 * m.ny) {
+          ix = m.nx - 1; iy = b - m.ny;
+          x = static_cast<double>(m.nx) * m.dx; y = (static_cast<double>(iy) + uab.x) * m.dy;
+          sx = -cn; sy = tg;
+        } else if (b < 2 * m.ny + m.nx) {
+          ix = b - 2 * m.ny; iy = 0;
+          x = (static_cast<double>(ix) + uab.x) * m.dx; y = 0.0;
+          sx = tg; sy = cn;
+          if (faces) atom_add(&in.Phiy[ix], q);
+        } else {
+          ix = b - 2 * m.ny - m.nx; iy = m.ny - 1;
+          x = (static_cast<double>(ix) + uab.x) * m.dx; y = static_cast<double>(m.ny) * m.dy;
+          sx = tg; sy = -cn;
+          if (faces) atom_add(&in.Phiy[m.ny * m.nx + ix], -q);
+        }
+      } else {
+        iy = static_cast<int>(loc) / m.nx;
+        ix = static_cast<int>(loc) - iy * m.nx;
+        x = in.px[p];
+        y = in.py[p];
+        sx = in.psx[p];
+        sy = in.psy[p];
+        q = in.pq[p];
+      }
+      if (q != 0) ++fl;
+      const double2 us = draw2(2u, p, kPersistStream, slot, in.key0, in.key1);
+      const double ell = -(in.lam_min * log_own(1.0 - us.x));
+      int bface;
+      uint32_t nlk;
+      bool absorbed;
+      if (faces && stripes) {
+        // the walk in closed form; its y faces are tallied by persist_faces_kernel
+        const double inv_sx = (sx != 0.0) ? 1.0 / sx : 0.0;
+        const double inv_sy = (sy != 0.0) ? 1.0 / sy : 0.0;
+        const int stx = (sx > 0.0) ? 1 : ((sx < 0.0) ? -1 : 0);
+        const int sty = (sy > 0.0) ? 1 : ((sy < 0.0) ? -1 : 0);
+        const int kx = (stx > 0) ? ix + 1 : ix, ky = (sty > 0) ? iy + 1 : iy;
+        const uint32_t cell = static_cast<uint32_t>(ix) | (static_cast<uint32_t>(iy) << 16);
+        int nxp = 0, nyp = 0;
+        bface = -1;
+        segment_end(m, x, y, ix, iy, stx, sty, inv_sx, inv_sy, kx, ky, ell, bface, nxp, nyp);
+        cr += static_cast<unsigned long long>(nxp + nyp);
+        absorbed = bface >= 0;
+        uint32_t key = kNoFaces;
+        if (nyp > 0) {
+          const int kl = ky + (nyp - 1) * sty;
+          key = static_cast<uint32_t>(min(ky, kl)) | (static_cast<uint32_t>(max(ky, kl)) << 16);
+          PFace r;
+          r.x0 = x;
+          r.y0 = y;
+          r.sx = sx;
+          r.inv_sx = inv_sx;
+          r.inv_sy = inv_sy;
+          r.q = q;
+          r.cell = cell;
+          r.nyp = static_cast<uint32_t>(nyp);
+          in.pf[p] = r;
+        }
+        in.pkey[p] = key;
+      } else {
+        absorbed = persist_walk(m, x, y, ix, iy, sx, sy, ell, faces, q, in.Phiy, in.dB, bface, cr);
+      }
+      if (absorbed) {
+        wkey = bface;
+        nlk = static_cast<uint32_t>(bface) | (2u << 30);
+      } else {
+        const int c = ix + m.nx * iy;
+        ckey = c;
+        x = clamp_to(x + ell * sx, static_cast<double>(ix) * m.dx, static_cast<double>(ix + 1) * m.dx);
+        if (m.dim == 2)
+          y = clamp_to(y + ell * sy, static_cast<double>(iy) * m.dy, static_cast<double>(iy + 1) * m.dy);
+        if (us.y < in.ratio[c]) {
+          real = 1;
+          nlk = static_cast<uint32_t>(c) | (1u << 30);
+        } else {
+          nul += abs_u64(q);                    // (each term <= 2^62: capped below)
+          if (nul > kBudgetCap) nul = kBudgetCap;
+          nlk = static_cast<uint32_t>(c);
+        }
+      }
+      qv = q;
+      in.px[p] = x;
+      in.py[p] = y;
+      in.psx[p] = sx;
+      in.psy[p] = sy;
+      in.pq[p] = q;
+      in.plk[p] = nlk;
+    }
+    // end tallies, summed over runs of equal consecutive keys in the wavefront
+    // first (particles of neighbouring indices tend to end in the same cell)
+    {
+      int head, run;
+      // (W takes the null particles' weights only here; persist_update_kernel
+      // adds W^h, so a real collision costs two atomics, not three)
+      wave_runs(ckey, head, run);
+      const long long sw = run_sum(real ? 0ll : qv, run);
+      const long long sh = run_sum(real ? qv : 0ll, run);
+      const long long sn = run_sum(static_cast<long long>(real), run);
+      if (head && ckey >= 0) {
+        if (sw) atom_add(&in.W[ckey], sw);   // (adding 0 changes nothing)
+        if (sn) {
+          atom_add(&in.D[ckey], sh);
+          atomicAdd(&in.Nrc[ckey], static_cast<uint32_t>(sn));
+        }
+      }
+      wave_runs(wkey, head, run);
+      const long long sb = run_sum(wkey >= 0 ? qv : 0ll, run);
+      const long long sc = run_sum(wkey >= 0 ? 1ll : 0ll, run);
+      if (head && wkey >= 0) {
+        if (lds_walls) {
+          atomicAdd(reinterpret_cast<unsigned long long *>(&sB[wkey]), static_cast<unsigned long long>(sb));
+          atomicAdd(&sNb[wkey], static_cast<uint32_t>(sc));
+        } else {
+          atom_add(&in.B[wkey], sb);
+          atomicAdd(&in.Nb[wkey], static_cast<uint32_t>(sc));
+        }
       }
     }
-    wave_runs(wkey, head, run);
-    const long long sb = run_sum(wkey >= 0 ? qv : 0ll, run);
-    const long long sc = run_sum(wkey >= 0 ? 1ll : 0ll, run);
-    if (head && wkey >= 0) {
-      atom_add(&in.B[wkey], sb);
-      atomicAdd(&in.Nb[wkey], static_cast<uint32_t>(sc));
+  }
+  if (lds_walls) {
+    __syncthreads();
+    for (int b = threadIdx.x; b < m.n_b; b += BS) {
+      if (sB[b]) atom_add(&in.B[b], sB[b]);
+      if (sNb[b]) atomicAdd(&in.Nb[b], sNb[b]);
     }
   }
   // per-wave sums (each |q| <= 2^62 and 64 of them fit in 2^68: cap first)
@@ -3320,8 +3351,8 @@ __global__ __launch_bounds__(BS) void persist_move_kernel(const Inst *__restrict
       n = (n + s_red[2][i] > kBudgetCap) ? kBudgetCap : n + s_red[2][i];
     }
     if (f) atomicAdd(&in.sc->flights, f);
-    atomicAdd(&in.sc->segments, static_cast<unsigned long long>(
-                                    min(static_cast<unsigned int>(BS), in.n_part - blockIdx.x * BS)));
+    atomicAdd(&in.sc->segments, min(static_cast<unsigned long long>(BS * kPersistPer),
+                                    static_cast<unsigned long long>(in.n_part) - p_first));
     if (c) atomicAdd(&in.sc->crossings, c);
     in.npart[blockIdx.x] = n;
   }
