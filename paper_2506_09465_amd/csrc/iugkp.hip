@@ -607,6 +607,109 @@ int setup_mg(InstHost &ih, const iugkp_options *o, hipStream_t s, bool single)
 
 // Validate, allocate and initialise one instance on `s`.  multi_cg: also lay
 // out the multi-workgroup CG used by single solves.
+// Row stripes for the face-tallied iterations of one instance (a single solve,
+// or one frequency band): rows per workgroup, stripes and chunks, and for the
+// analog particle step the records and their bins (ih.stripe_*, ih.rec);
+// stripe_R stays 0 where they do not fit (tiles are used).  pref: the
+// planner's choice for the form search.
+int plan_stripes(InstHost &ih, hipStream_t s, bool ev, bool pref)
+{
+  Inst &d = ih.d;
+  const Mesh &m = d.m;
+  // row stripes: as many rows per workgroup as its LDS holds (y faces and
+  // the walls; the expected-value kernel also D, and W with null
+  // collisions), about two workgroups per CU
+  int dev = 0, n_cu = 0, lds_max = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  // (less the static LDS: the march's segment table, 8.3 KB, and for flights
+  // without null collisions the pieces' lists, 8.2 KB more)
+  const bool pieces = !ev && !d.has_null;
+  const long long words = lds_max / 8 - (pieces ? 2200 : 1100);
+  const long long per_row = static_cast<long long>(m.nx) * (ev ? (d.has_null ? 3 : 2) : 1);
+  const long long fixed = m.nx + (d.lds_walls ? m.n_b : 0);
+  int R = static_cast<int>((words - fixed) / per_row);
+  if (R >= kStripeMinRows || (R >= 1 && R >= m.ny)) {
+    R = std::min(R, m.ny);
+    const int S = cdiv(m.ny, R);
+    R = cdiv(m.ny, S);
+    const size_t lds = static_cast<size_t>(fixed + per_row * R) * sizeof(long long);
+    int per_cu = 0;
+    const void *kern =
+        ev ? reinterpret_cast<const void *>(iugkp::march_stripes_ev_kernel<kStripeBlock>)
+        : pieces ? reinterpret_cast<const void *>(iugkp::march_stripes_pieces_kernel<kStripeBlock>)
+                 : reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>);
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kStripeBlock, lds));
+    // (the analog kernel reads every particle's first segment from a
+    // 64-byte record (80 with null collisions) and a 4-byte row range per
+    // particle; without the memory, or beyond 65534 rows or 65535
+    // columns, tiles are used)
+    // The records are binned by start stripe and pre-pass block (sub-bin k
+    // of stripe t: the particles that start in t among those of pre-pass
+    // blocks k, k + K, ...; counted here exactly): beyond kStripeBinMax / 2
+    // stripes or 2^32 particles, tiles are used.
+    bool recs = true;
+    const size_t np = static_cast<size_t>(m.n_emit) * static_cast<size_t>(d.N);
+    if (!ev && (m.ny > 0xfffe || m.nx > 0xffff || 2 * S > iugkp::kStripeBinMax ||
+                np > 0xffffffffull))
+      recs = false;   // (16-bit rows and columns, 32-bit slots)
+    else if (!ev) {
+      const size_t rb = d.has_null ? sizeof(iugkp::PRecN) : sizeof(iugkp::PRec);
+      const int K = std::max(1, std::min(32, iugkp::kStripeSegMax / (S + 1)));
+      const long long per_block = static_cast<long long>(iugkp::kPresampleBlock) * iugkp::kPresamplePer;
+      const long long nblk = (static_cast<long long>(np) + per_block - 1) / per_block;
+      const long long ne = m.n_emit, nc = m.n_cells;
+      // emitters of stripe t in [e0, e1): its rows' cells and left and right
+      // wall faces, the bottom wall (first stripe), the top wall (last)
+      auto in_stripe = [&](int t, long long e0, long long e1) {
+        const long long y0 = static_cast<long long>(t) * R, y1 = std::min<long long>(m.ny, y0 + R);
+        auto ov = [&](long long a, long long b) {
+          return std::max(0ll, std::min(b, e1) - std::max(a, e0));
+        };
+        long long c = ov(y0 * m.nx, y1 * m.nx) + ov(nc + y0, nc + y1) + ov(nc + m.ny + y0, nc + m.ny + y1);
+        if (t == 0) c += ov(nc + 2ll * m.ny, nc + 2ll * m.ny + m.nx);
+        if (t == S - 1) c += ov(nc + 2ll * m.ny + m.nx, nc + 2ll * m.ny + 2ll * m.nx);
+        return c;
+      };
+      std::vector<unsigned long long> cap(static_cast<size_t>(S) * K, 0);
+      for (long long b = 0; b < nblk; ++b) {
+        const long long p0 = b * per_block, p1 = std::min<long long>(p0 + per_block, np);
+        for (long long p = p0; p < p1;) {
+          const long long kk = p / ne, e0 = p - kk * ne;
+          const long long e1 = std::min(ne, e0 + (p1 - p));
+          for (int t = 0; t < S; ++t) cap[static_cast<size_t>(t) * K + (b % K)] += in_stripe(t, e0, e1);
+          p += e1 - e0;
+        }
+      }
+      std::vector<uint32_t> base(static_cast<size_t>(S) * K + 1, 0);
+      for (size_t i = 0; i < cap.size(); ++i) base[i + 1] = base[i] + static_cast<uint32_t>(cap[i]);
+      unsigned char *r = nullptr;
+      uint32_t *db = nullptr;
+      recs = ih.alloc(&r, np * rb) == hipSuccess && ih.alloc(&ih.rec.key, np) == hipSuccess &&
+             ih.alloc(&ih.rec.cnt, 2 * cap.size()) == hipSuccess &&
+             ih.alloc(&db, base.size()) == hipSuccess;
+      if (recs && base.back() != np) return fail(IUGKP_E_DEVICE, "stripe bins do not cover the particles");
+      if (recs) HIP_TRY(hipMemcpyAsync(db, base.data(), base.size() * sizeof(uint32_t),
+                                       hipMemcpyHostToDevice, s));
+      ih.rec.r = r;
+      ih.rec.base = db;
+      ih.rec.R = R;
+      ih.rec.S = S;
+      ih.rec.K = K;
+      if (!recs) (void)hipGetLastError();
+    }
+    if (per_cu >= 1 && recs) {
+      ih.stripe_R = R;
+      ih.stripe_S = S;
+      ih.stripe_C = std::max(1, (2 * per_cu * n_cu) / S);   // whole rounds of resident groups
+      ih.stripe_lds = lds;
+      ih.stripe_pref = pref ? 1 : 0;
+    }
+  }
+  return IUGKP_OK;
+}
+
 int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, bool multi_cg,
                    InstHost &ih)
 {
@@ -828,97 +931,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
       ((ev && o->march >= 2) ||
        (!ev && o->tally_faces != IUGKP_FACES_OFF &&
         (o->march >= 2 || (o->march == 0 && (lam_stripes || o->block_size == 0)))))) {
-    // row stripes: as many rows per workgroup as its LDS holds (y faces and
-    // the walls; the expected-value kernel also D, and W with null
-    // collisions), about two workgroups per CU
-    int dev = 0, n_cu = 0, lds_max = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    // (less the static LDS: the march's segment table, 8.3 KB, and for flights
-    // without null collisions the pieces' lists, 8.2 KB more)
-    const bool pieces = !ev && !d.has_null;
-    const long long words = lds_max / 8 - (pieces ? 2200 : 1100);
-    const long long per_row = static_cast<long long>(m.nx) * (ev ? (d.has_null ? 3 : 2) : 1);
-    const long long fixed = m.nx + (d.lds_walls ? m.n_b : 0);
-    int R = static_cast<int>((words - fixed) / per_row);
-    if (R >= kStripeMinRows || (R >= 1 && R >= m.ny)) {
-      R = std::min(R, m.ny);
-      const int S = cdiv(m.ny, R);
-      R = cdiv(m.ny, S);
-      const size_t lds = static_cast<size_t>(fixed + per_row * R) * sizeof(long long);
-      int per_cu = 0;
-      const void *kern =
-          ev ? reinterpret_cast<const void *>(iugkp::march_stripes_ev_kernel<kStripeBlock>)
-          : pieces ? reinterpret_cast<const void *>(iugkp::march_stripes_pieces_kernel<kStripeBlock>)
-                   : reinterpret_cast<const void *>(iugkp::march_stripes_kernel<kStripeBlock>);
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kStripeBlock, lds));
-      // (the analog kernel reads every particle's first segment from a
-      // 64-byte record (80 with null collisions) and a 4-byte row range per
-      // particle; without the memory, or beyond 65534 rows or 65535
-      // columns, tiles are used)
-      // The records are binned by start stripe and pre-pass block (sub-bin k
-      // of stripe t: the particles that start in t among those of pre-pass
-      // blocks k, k + K, ...; counted here exactly): beyond kStripeBinMax / 2
-      // stripes or 2^32 particles, tiles are used.
-      bool recs = true;
-      const size_t np = static_cast<size_t>(m.n_emit) * static_cast<size_t>(d.N);
-      if (!ev && (m.ny > 0xfffe || m.nx > 0xffff || 2 * S > iugkp::kStripeBinMax ||
-                  np > 0xffffffffull))
-        recs = false;   // (16-bit rows and columns, 32-bit slots)
-      else if (!ev) {
-        const size_t rb = d.has_null ? sizeof(iugkp::PRecN) : sizeof(iugkp::PRec);
-        const int K = std::max(1, std::min(32, iugkp::kStripeSegMax / (S + 1)));
-        const long long per_block = static_cast<long long>(iugkp::kPresampleBlock) * iugkp::kPresamplePer;
-        const long long nblk = (static_cast<long long>(np) + per_block - 1) / per_block;
-        const long long ne = m.n_emit, nc = m.n_cells;
-        // emitters of stripe t in [e0, e1): its rows' cells and left and right
-        // wall faces, the bottom wall (first stripe), the top wall (last)
-        auto in_stripe = [&](int t, long long e0, long long e1) {
-          const long long y0 = static_cast<long long>(t) * R, y1 = std::min<long long>(m.ny, y0 + R);
-          auto ov = [&](long long a, long long b) {
-            return std::max(0ll, std::min(b, e1) - std::max(a, e0));
-          };
-          long long c = ov(y0 * m.nx, y1 * m.nx) + ov(nc + y0, nc + y1) + ov(nc + m.ny + y0, nc + m.ny + y1);
-          if (t == 0) c += ov(nc + 2ll * m.ny, nc + 2ll * m.ny + m.nx);
-          if (t == S - 1) c += ov(nc + 2ll * m.ny + m.nx, nc + 2ll * m.ny + 2ll * m.nx);
-          return c;
-        };
-        std::vector<unsigned long long> cap(static_cast<size_t>(S) * K, 0);
-        for (long long b = 0; b < nblk; ++b) {
-          const long long p0 = b * per_block, p1 = std::min<long long>(p0 + per_block, np);
-          for (long long p = p0; p < p1;) {
-            const long long kk = p / ne, e0 = p - kk * ne;
-            const long long e1 = std::min(ne, e0 + (p1 - p));
-            for (int t = 0; t < S; ++t) cap[static_cast<size_t>(t) * K + (b % K)] += in_stripe(t, e0, e1);
-            p += e1 - e0;
-          }
-        }
-        std::vector<uint32_t> base(static_cast<size_t>(S) * K + 1, 0);
-        for (size_t i = 0; i < cap.size(); ++i) base[i + 1] = base[i] + static_cast<uint32_t>(cap[i]);
-        unsigned char *r = nullptr;
-        uint32_t *db = nullptr;
-        recs = ih.alloc(&r, np * rb) == hipSuccess && ih.alloc(&ih.rec.key, np) == hipSuccess &&
-               ih.alloc(&ih.rec.cnt, 2 * cap.size()) == hipSuccess &&
-               ih.alloc(&db, base.size()) == hipSuccess;
-        if (recs && base.back() != np) return fail(IUGKP_E_DEVICE, "stripe bins do not cover the particles");
-        if (recs) HIP_TRY(hipMemcpyAsync(db, base.data(), base.size() * sizeof(uint32_t),
-                                         hipMemcpyHostToDevice, s));
-        ih.rec.r = r;
-        ih.rec.base = db;
-        ih.rec.R = R;
-        ih.rec.S = S;
-        ih.rec.K = K;
-        if (!recs) (void)hipGetLastError();
-      }
-      if (per_cu >= 1 && recs) {
-        ih.stripe_R = R;
-        ih.stripe_S = S;
-        ih.stripe_C = std::max(1, (2 * per_cu * n_cu) / S);   // whole rounds of resident groups
-        ih.stripe_lds = lds;
-        ih.stripe_pref = (o->march >= 2 || lam_stripes) ? 1 : 0;
-      }
-    }
+    if ((rc = plan_stripes(ih, s, ev, o->march >= 2 || lam_stripes))) return rc;
     if (o->march >= 2 && ih.stripe_R == 0)
       return fail(IUGKP_E_INVALID_ARG, "row stripes do not fit this mesh");
   }
@@ -1136,6 +1149,17 @@ int setup_bands(const iugkp_problem *p, const iugkp_options *o, hipStream_t s, I
     d.n_bands = K;
     d.Gs = nullptr;
     plan_tiles(ih);
+    // row stripes for a band's face-tallied iterations when its free paths
+    // reach half the domain's height (and 7 cells): a band with shorter ones
+    // has long chains of null collisions wherever its relaxation time is
+    // above the minimum, which the tile march handles better (march 1 keeps
+    // every band on tiles)
+    if (p->dim == 2 && o->tally_faces != IUGKP_FACES_OFF && o->march != 1 &&
+        o->estimator == IUGKP_EST_ANALOG && lam[k] >= kStripeMinCells * std::min(p->dx, p->dy) &&
+        lam[k] >= 0.5 * p->ny * p->dy) {
+      const int rc = plan_stripes(ih, s, false, true);
+      if (rc) return rc;
+    }
     double *dratio = nullptr, *dshare = nullptr;
     ALLOC(ih, dratio, nc);
     ALLOC(ih, dshare, nc);
@@ -1345,8 +1369,10 @@ struct iugkp_handle {
   std::vector<InstHost> xb;       // bands 1 .. K-1
   BandsHost bh;
   Inst *d_inst = nullptr;         // [K]
-  TileDesc *d_tiles = nullptr;
+  TileDesc *d_tiles = nullptr;    // the tiles of the bands without row stripes first
   int n_tiles = 0;
+  int n_tiles_f = 0;              // face-tallied iterations: tiles of those bands only
+  std::vector<int> stripe_bands;  // bands whose face-tallied iterations run row stripes
   size_t lds = 0;                 // march window (largest over the bands)
   int block = 256;
   // the particle-step form of face-tallied iterations (pick_form)
@@ -1536,6 +1562,38 @@ void record_form(iugkp_handle *h, float ms)
   g_form_choice[form_key(h->ih)] = best;
 }
 
+// The row-stripe particle step of one instance (ih, its descriptor at
+// d_inst): the records' bin counters cleared, the pre-pass, then the march
+// (in pieces when asked and the flights have no null collisions).
+int launch_stripes(const InstHost &ih, const Inst *d_inst, bool pieces, hipStream_t s)
+{
+  const Mesh &m = ih.d.m;
+  const unsigned long long np =
+      static_cast<unsigned long long>(m.n_emit) * static_cast<unsigned long long>(ih.d.N);
+  constexpr unsigned int per_block = iugkp::kPresampleBlock * iugkp::kPresamplePer;
+  const unsigned int pg = static_cast<unsigned int>((np + per_block - 1) / per_block);
+  const dim3 sg(ih.stripe_C, ih.stripe_S);
+  const int ncnt = 2 * ih.rec.S * ih.rec.K;
+  iugkp::zero_u32_kernel<<<cdiv(ncnt, 256), 256, 0, s>>>(ih.rec.cnt, ncnt);
+  constexpr size_t ps_lds = static_cast<size_t>(iugkp::kPresampleBlock) * sizeof(uint32_t);
+  if (ih.d.has_null)
+    iugkp::stripe_presample_kernel<iugkp::kPresampleBlock, true>
+        <<<pg, iugkp::kPresampleBlock, iugkp::kPresampleBlock * sizeof(iugkp::PRecN) + ps_lds, s>>>(
+            d_inst, ih.rec);
+  else
+    iugkp::stripe_presample_kernel<iugkp::kPresampleBlock, false>
+        <<<pg, iugkp::kPresampleBlock, iugkp::kPresampleBlock * sizeof(iugkp::PRec) + ps_lds, s>>>(
+            d_inst, ih.rec);
+  if (!ih.d.has_null && pieces)
+    iugkp::march_stripes_pieces_kernel<kStripeBlock>
+        <<<sg, kStripeBlock, ih.stripe_lds, s>>>(d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
+  else
+    iugkp::march_stripes_kernel<kStripeBlock>
+        <<<sg, kStripeBlock, ih.stripe_lds, s>>>(d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
+  HIP_TRY(hipGetLastError());
+  return IUGKP_OK;
+}
+
 // Enqueue one iteration on the handle's stream: its kernels and the copy of
 // the new scalars into h->hsc (complete_iteration waits for them).
 int enqueue_iteration(iugkp_handle *h, int faces)
@@ -1584,31 +1642,19 @@ int enqueue_iteration(iugkp_handle *h, int faces)
         <<<dim3(ih.stripe_C, ih.stripe_S), kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R,
                                                                               ih.stripe_C, faces);
     HIP_TRY(hipGetLastError());
+  } else if (K > 1 && faces && !h->stripe_bands.empty()) {
+    // frequency bands: the long-path bands by row stripes, the others' tiles
+    if (h->n_tiles_f > 0) {
+      rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles_f, h->lds, h->block, faces, 0, false, s);
+      if (rc) return rc;
+    }
+    for (int k : h->stripe_bands) {
+      const InstHost &bk = (k == 0) ? h->ih : h->xb[k - 1];
+      if ((rc = launch_stripes(bk, h->d_inst + k, !bk.d.has_null, s))) return rc;
+    }
   } else if (faces && ih.stripe_R > 0 &&
              ((form = pick_form(h)) == kFormStripes || form == kFormPieces)) {
-    const unsigned long long np =
-        static_cast<unsigned long long>(m.n_emit) * static_cast<unsigned long long>(ih.d.N);
-    constexpr unsigned int per_block = iugkp::kPresampleBlock * iugkp::kPresamplePer;
-    const unsigned int pg = static_cast<unsigned int>((np + per_block - 1) / per_block);
-    const dim3 sg(ih.stripe_C, ih.stripe_S);
-    const int ncnt = 2 * ih.rec.S * ih.rec.K;
-    iugkp::zero_u32_kernel<<<cdiv(ncnt, 256), 256, 0, s>>>(ih.rec.cnt, ncnt);
-    constexpr size_t ps_lds = static_cast<size_t>(iugkp::kPresampleBlock) * sizeof(uint32_t);
-    if (ih.d.has_null)
-      iugkp::stripe_presample_kernel<iugkp::kPresampleBlock, true>
-          <<<pg, iugkp::kPresampleBlock, iugkp::kPresampleBlock * sizeof(iugkp::PRecN) + ps_lds, s>>>(
-              h->d_inst, ih.rec);
-    else
-      iugkp::stripe_presample_kernel<iugkp::kPresampleBlock, false>
-          <<<pg, iugkp::kPresampleBlock, iugkp::kPresampleBlock * sizeof(iugkp::PRec) + ps_lds, s>>>(
-              h->d_inst, ih.rec);
-    if (!ih.d.has_null && form == kFormPieces)
-      iugkp::march_stripes_pieces_kernel<kStripeBlock>
-          <<<sg, kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
-    else
-      iugkp::march_stripes_kernel<kStripeBlock>
-          <<<sg, kStripeBlock, ih.stripe_lds, s>>>(h->d_inst, ih.stripe_R, ih.stripe_C, ih.rec);
-    HIP_TRY(hipGetLastError());
+    if ((rc = launch_stripes(ih, h->d_inst, form == kFormPieces, s))) return rc;
   } else {
     const int block = (form == kFormTiles512) ? 512 : h->block;
     rc = launch_march(h->d_inst, h->d_tiles, h->n_tiles, h->lds, block, faces, 0,
@@ -1766,6 +1812,7 @@ int iugkp_create(const iugkp_problem *problem, const iugkp_options *options, voi
   for (int k = 0; k < K; ++k) {
     h->n_tiles += static_cast<int>(band_of(h, k).tiles.size());
     h->lds = std::max(h->lds, band_of(h, k).lds_bytes);
+    if (bands && band_of(h, k).stripe_R > 0) h->stripe_bands.push_back(k);
   }
   if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), K * sizeof(Inst)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void **>(&h->d_tiles), h->n_tiles * sizeof(TileDesc)) != hipSuccess ||
@@ -1778,13 +1825,22 @@ int iugkp_create(const iugkp_problem *problem, const iugkp_options *options, voi
       free_handle(h);
       return fail(IUGKP_E_DEVICE, "hipEventCreate failed");
     }
-  for (int k = 0, tile0 = 0; k < K; ++k) {
+  // (the bands without row stripes first: a face-tallied iteration marches
+  // the first n_tiles_f tiles, the others run their stripes)
+  std::vector<int> order;
+  for (int k = 0; k < K; ++k)
+    if (!(bands && band_of(h, k).stripe_R > 0)) order.push_back(k);
+  for (int k : h->stripe_bands) order.push_back(k);
+  for (int i = 0, tile0 = 0; i < K; ++i) {
+    const int k = order[i];
     if ((rc = upload_inst(band_of(h, k), k, h->d_inst, h->d_tiles, tile0, h->stream))) {
       free_handle(h);
       return rc;
     }
     tile0 += static_cast<int>(band_of(h, k).tiles.size());
+    if (i + 1 == K - static_cast<int>(h->stripe_bands.size())) h->n_tiles_f = tile0;
   }
+  if (h->stripe_bands.empty()) h->n_tiles_f = h->n_tiles;
   h->st.fixed_point_F = h->ih.d.F;
   h->st.n_per_emitter = h->ih.d.N;
   h->st.n_emitters = h->ih.d.m.n_emit * K;

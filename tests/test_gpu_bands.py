@@ -93,12 +93,16 @@ def _ragged():
     return w
 
 
+# march 0: bands whose free paths reach half the domain's height run their
+# face-tallied iterations by row stripes (in the 2D cases here: the first two;
+# band 0 of mixed_40 without null collisions); march 1: every band on tiles
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("rng", ["fresh", "crn"])
-def test_band_iterations_bitwise(oracle_mod, gpu, name, rng):
+@pytest.mark.parametrize("march", [0, 1])
+def test_band_iterations_bitwise(oracle_mod, gpu, name, rng, march):
     w = CASES[name]()
     kw = dict(rng_mode=oracle_mod.CRN if rng == "crn" else oracle_mod.FRESH, epoch=9)
-    o, s = _pair(oracle_mod, gpu, w, **kw)
+    o, s = _pair(oracle_mod, gpu, w, march=march, **kw)
     _same_state(o, s, "initial")
     for i, faces in enumerate([True, False, True]):
         assert o.step(1, faces=faces) == 0
@@ -192,3 +196,23 @@ def test_band_full_size_properties(gpu):
         Wsum = Wsum + np.ldexp(W[k].astype(np.float64), -F)
     _, _, E, _ = s.state()
     assert np.array_equal(Wsum / V, _np(E))
+
+
+def test_band_full_size_stripes_equal_tiles(gpu):
+    """The 512^2, 40-band problem with face tallies in the benchmark's launch
+    configuration: its two long-path bands by row stripes (march 0) give the
+    tallies of every band on emitter tiles (march 1) bit for bit."""
+    w = nongray_two_material_2d()
+    a = gpu.Solver(w, tally_faces=gpu.FACES_EVERY)
+    b = gpu.Solver(w, tally_faces=gpu.FACES_EVERY, march=1)
+    for it in range(2):
+        assert a.step(1, faces=True) == 0 and b.step(1, faces=True) == 0
+        ta, tb = a.tallies(), b.tallies()
+        for k in ta:
+            assert torch.equal(ta[k], tb[k]), (it, k)
+        assert torch.equal(a.state()[2], b.state()[2])
+    sa, sb = a.stats(), b.stats()
+    assert (sa["flights"], sa["segments"], sa["crossings"]) == (sb["flights"], sb["segments"],
+                                                              sb["crossings"])
+    a.close()
+    b.close()
