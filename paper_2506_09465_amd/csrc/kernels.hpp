@@ -321,6 +321,29 @@ __device__ __forceinline__ int faces_before(int k0, int st, int jmax, double d, 
   return lo;
 }
 
+// The same count, estimated from the coordinate reached at T (direction
+// component from the hardware's approximate reciprocal of inv: an estimate
+// only) and checked against the walk's own times t(lo - 1) and t(lo); a miss
+// (a crossing within rounding of a face, or a poor estimate) falls back to the
+// search, so the result is always faces_before's.
+template <bool STRICT>
+__device__ __forceinline__ int faces_before_near(int k0, int st, int jmax, double d, double inv_d,
+                                                 double p0, double inv, double T)
+{
+  const double pos = p0 + T * __builtin_amdgcn_rcp(inv);
+  const double jr = (st > 0) ? pos * inv_d - static_cast<double>(k0)
+                             : static_cast<double>(k0) - pos * inv_d;
+  int lo;
+  if (!(jr < static_cast<double>(jmax))) lo = jmax + 1;
+  else if (!(jr >= 0.0)) lo = 0;
+  else lo = static_cast<int>(floor(jr)) + 1;
+  // (t at an index outside [0, jmax] is plain arithmetic, its result unused)
+  auto t = [&](int j) { return (static_cast<double>(k0 + j * st) * d - p0) * inv; };
+  auto before = [&](double tj) { return STRICT ? (tj < T) : (tj <= T); };
+  const bool ok = (lo == 0 || before(t(lo - 1))) && (lo > jmax || !before(t(lo)));
+  return ok ? lo : faces_before<STRICT>(k0, st, jmax, d, p0, inv, T);
+}
+
 // The walk of one segment of length ell from (x0, y0) in cell (ix, iy) with
 // no face tallies, in closed form (segment_end also returns the x and y faces
 // crossed, nxp and nyp, a crossed wall face included).  Crossings before ell in each direction are
@@ -334,21 +357,23 @@ __device__ __forceinline__ void segment_end(const Mesh &m, double x0, double y0,
 {
   const int jwx = (stx > 0) ? m.nx - kx : kx;   // position of the x wall in the sequence
   const int jwy = (sty > 0) ? m.ny - ky : ky;
-  const int nxc = stx ? faces_before<true>(kx, stx, jwx, m.dx, x0, inv_sx, ell) : 0;
-  const int nyc = sty ? faces_before<true>(ky, sty, jwy, m.dy, y0, inv_sy, ell) : 0;
+  // (approximate reciprocals: they only feed the estimates)
+  const double inv_dx = __builtin_amdgcn_rcp(m.dx), inv_dy = __builtin_amdgcn_rcp(m.dy);
+  const int nxc = stx ? faces_before_near<true>(kx, stx, jwx, m.dx, inv_dx, x0, inv_sx, ell) : 0;
+  const int nyc = sty ? faces_before_near<true>(ky, sty, jwy, m.dy, inv_dy, y0, inv_sy, ell) : 0;
   const bool wx = stx && nxc > jwx, wy = sty && nyc > jwy;
   if (wx || wy) {
     const int kwx = kx + jwx * stx, kwy = ky + jwy * sty;
     const double Tx = wx ? (static_cast<double>(kwx) * m.dx - x0) * inv_sx : INFINITY;
     const double Ty = wy ? (static_cast<double>(kwy) * m.dy - y0) * inv_sy : INFINITY;
     if (wx && Tx <= Ty) {
-      const int nb = sty ? faces_before<true>(ky, sty, jwy, m.dy, y0, inv_sy, Tx) : 0;
+      const int nb = sty ? faces_before_near<true>(ky, sty, jwy, m.dy, inv_dy, y0, inv_sy, Tx) : 0;
       iy += sty * nb;
       nxp = jwx + 1;
       nyp = nb;
       bface = (kwx == 0) ? iy : m.ny + iy;
     } else {
-      const int nb = stx ? faces_before<false>(kx, stx, jwx, m.dx, x0, inv_sx, Ty) : 0;
+      const int nb = stx ? faces_before_near<false>(kx, stx, jwx, m.dx, inv_dx, x0, inv_sx, Ty) : 0;
       ix += stx * nb;
       nxp = nb;
       nyp = jwy + 1;
