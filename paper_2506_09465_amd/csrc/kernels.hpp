@@ -1494,7 +1494,7 @@ __global__ __launch_bounds__(BS) void march_stripes_pieces_kernel(const Inst *__
   uint32_t c_slot = 0, c_key = 0;
   bool c_valid = false, c_foreign = false;
   PRec c_rec{};
-  auto fetch = [&](unsigned long long vv) {
+  auto fetch = [&](unsigned long long vv) {   // the slot and row range
     c_valid = vv < ve;
     if (!c_valid) return;
     const uint32_t v = static_cast<uint32_t>(vv);
@@ -1502,7 +1502,14 @@ __global__ __launch_bounds__(BS) void march_stripes_pieces_kernel(const Inst *__
     c_slot = s_slot[sg] + (v - s_pre[sg]);
     c_foreign = sg >= nown;
     c_key = c_foreign ? rec.key[c_slot] : 0u;
-    c_rec = recs[c_slot];
+  };
+  // (another stripe's leaver enters only if it reaches these rows)
+  auto accepted = [&]() {
+    return c_valid &&
+           !(c_foreign && (static_cast<int>(c_key & 0xffffu) < r0 || static_cast<int>(c_key >> 16) >= r1));
+  };
+  auto fetch_rec = [&]() {                     // the record, if the candidate enters
+    if (accepted()) c_rec = recs[c_slot];
   };
   // a piece's particle: what its crossings need
   struct Piece {
@@ -1524,14 +1531,13 @@ __global__ __launch_bounds__(BS) void march_stripes_pieces_kernel(const Inst *__
     return lo;
   };
   fetch(static_cast<unsigned long long>(vb) + threadIdx.x);
+  fetch_rec();
   for (unsigned long long v0 = vb; v0 < ve; v0 += kStripeScan) {
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
     bool hit = false;
     uint32_t slot = c_slot, npc = 0;
-    if (c_valid &&
-        !(c_foreign && (static_cast<int>(c_key & 0xffffu) < r0 || static_cast<int>(c_key >> 16) >= r1))) {
-      // (another stripe's leaver enters only if it reaches these rows)
+    if (accepted()) {
       const PRec &rp = c_rec;
       const int ixe = static_cast<int>(rp.cell_e & 0xffffu), iye = static_cast<int>(rp.cell_e >> 16);
       if (iye >= r0 && iye < r1) {      // the flight ends in this stripe's rows
@@ -1621,6 +1627,7 @@ __global__ __launch_bounds__(BS) void march_stripes_pieces_kernel(const Inst *__
       ia = ib;
       cur = nxt;
     }
+    fetch_rec();                                    // (its range has arrived by now)
     __syncthreads();
   }
   if (n_fl) {
