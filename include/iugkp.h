@@ -130,8 +130,10 @@ typedef struct iugkp_options {
                                    into pieces (without null collisions; else as 2).
                                    Persistent scheme: the y faces of face-tallied moves by a
                                    row-stripe pass (2 or 3, or 0 with long free paths) or as
-                                   global atomics in the move (1).  The result does not
-                                   depend on it */
+                                   global atomics in the move (1).  Frequency bands: bands
+                                   whose free paths reach half the domain's height run their
+                                   face-tallied iterations by row stripes unless march is 1.
+                                   The result does not depend on it */
   int cg_waves;                 /* single solves: 256-cell tree blocks per CG workgroup, 0
                                    (= 8) or 1..12 with the CG state in registers, -1..-12 with
                                    it in global memory (with IUGKP_PRECOND_MG: |cg_waves|
