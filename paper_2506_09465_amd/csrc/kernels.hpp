@@ -469,6 +469,10 @@ struct Flight {
   int ix, iy, stx, sty;
   double x0, y0, sx, sy, inv_sx, inv_sy;
   bool runs;
+  // the open run of y faces in the current column (first and last face, or
+  // run_a = -1): it stays open across null collisions, which keep the
+  // direction and the column
+  int run_a, run_b;
   // pending candidate tallies: n candidates of weight q in cell (cand_x, cand_y)
   int cand_x, cand_y;
   long long cand_n;
@@ -487,8 +491,10 @@ __device__ __forceinline__ void flight_start(const FlyIn &a, uint32_t e, uint32_
   f.stx = (f.sx > 0.0) ? 1 : ((f.sx < 0.0) ? -1 : 0);
   f.sty = (f.sy > 0.0) ? 1 : ((f.sy < 0.0) ? -1 : 0);
   f.qy = (f.sty > 0) ? q : -q;
-  // steep segments record their y-faces as runs per column
+  // steep flights record their y-faces as runs per column
   f.runs = a.faces && (fabs(f.sy) > 2.0 * fabs(f.sx));
+  f.run_a = -1;
+  f.run_b = -1;
   f.cand_x = -1;
   f.cand_y = -1;
   f.cand_n = 0;
@@ -518,7 +524,7 @@ __device__ __forceinline__ bool flight_segment(const FlyIn &a, Flight &f, Diff &
   int kx = (stx > 0) ? ix + 1 : ix;
   int ky = (sty > 0) ? iy + 1 : iy;
   int bface = -1;
-  int run_a = -1, run_b = -1;   // first and last y-face of the open run
+  int run_a = f.run_a, run_b = f.run_b;   // first and last y-face of the open run
   if (!a.faces && ell * (fabs(f.sx) / m.dx + fabs(f.sy) / m.dy) > kJumpMinFaces) {
     segment_jump(m, f.x0, f.y0, ix, iy, stx, sty, f.inv_sx, f.inv_sy, kx, ky, ell, bface, n_cross);
   } else
@@ -556,10 +562,6 @@ __device__ __forceinline__ bool flight_segment(const FlyIn &a, Flight &f, Diff &
       ky += sty;
     }
   }
-  if (run_a >= 0) {
-    add_diff(min(run_a, run_b), ix, f.qy);
-    add_diff(max(run_a, run_b) + 1, ix, -f.qy);
-  }
   f.ix = ix;
   f.iy = iy;
   bool more = false;
@@ -593,6 +595,14 @@ __device__ __forceinline__ bool flight_segment(const FlyIn &a, Flight &f, Diff &
     }
   }
   if (!more && f.cand_n) add_cand(f.cand_x, f.cand_y, times(f.q, f.cand_n));
+  // the run stays open into the next segment (same column, the next face)
+  if (!more && run_a >= 0) {
+    add_diff(min(run_a, run_b), ix, f.qy);
+    add_diff(max(run_a, run_b) + 1, ix, -f.qy);
+    run_a = -1;
+  }
+  f.run_a = run_a;
+  f.run_b = run_b;
   return more;
 }
 
