@@ -78,6 +78,10 @@ CASES = {
     # workgroup, so 25 rows make seven stripes (the last one short)
     "wide_many_stripes": lambda: cavity_2d(n=4000, ny=25, kn=0.002, particles=120_000,
                                            newton=False, seed=9),
+    # degenerate 2D meshes: one column (every y face in it), one row (only
+    # the two y walls)
+    "column_1x9": lambda: cavity_2d(n=1, ny=9, kn=3.0, particles=20_000, newton=False, seed=10),
+    "row_40x1": lambda: cavity_2d(n=40, ny=1, kn=0.5, particles=20_000, newton=False, seed=11),
 }
 
 
