@@ -1446,6 +1446,10 @@ __global__ __launch_bounds__(BS) void march_stripes_kernel(const Inst *__restric
 // utilisation at Kn 0.1 / 1 / 10 on the 256^2 cavity).  Each crossing is
 // tallied in the column reached by the x faces before it, from its own time
 // (faces_upto_near), so a piece needs no earlier crossing of its particle.
+// Each thread loads its next round's candidate (slot and row range, then the
+// record once the range lets it in) and the record of its next piece while
+// the current work runs: with one workgroup per CU (the stripe's tallies fill
+// the LDS) nothing else hides those loads behind the rounds' barriers.
 // Integer sums: the same tallies as the tile kernel, bit for bit.
 // ---------------------------------------------------------------------------
 constexpr int kStripeScan = 1024;
