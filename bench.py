@@ -65,6 +65,8 @@ def parse():
                     help="only the persistent-particle timing (its own JSON line; for profiling)")
     ap.add_argument("--nongray-only", action="store_true",
                     help="only the 40-band timing (printed as its own JSON line; for profiling)")
+    ap.add_argument("--c2-gray-only", action="store_true",
+                    help="only the 512x512 two-material gray timing (its own JSON line; for profiling)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched vs sequential comparison (its own JSON line)")
     ap.add_argument("--forms", default=None,
@@ -779,6 +781,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.nongray_only:
         print(json.dumps(bench_nongray(P, dev, args.steps, 20, atomics_ceiling(P))), flush=True)
+        return
+    if args.c2_gray_only:
+        print(json.dumps(bench_c2_gray(P, dev, args.steps, atomics_ceiling(P))), flush=True)
         return
     if args.persistent_only:
         print(json.dumps(bench_persistent(P, dev, args.steps, atomics_ceiling(P))), flush=True)
