@@ -56,6 +56,9 @@ constexpr int kPersistFacesBlock = 1024;     // threads per workgroup of the row
 constexpr int kTileX = 8;                    // emitter tile of one workgroup (cells per side;
                                              // wall faces per workgroup); batches also 16
 constexpr int kWindowHalo = 12;              // window margin around a tile (cells)
+constexpr int kWindowHaloNull = 20;          // a single solve's with null collisions (long chains;
+                                             // one launch of bands or of a batch takes the
+                                             // largest window's LDS for every workgroup)
 constexpr size_t kLdsWordsMax = 6144;        // 48 KB of 64-bit tallies per workgroup
 constexpr int kLdsWallsMax = 1024;
 
@@ -268,8 +271,8 @@ int scale_exponent(const iugkp_problem *p, double tau_min, const std::vector<dou
 // otherwise a window of the tile plus a margin, placed inside the domain.
 // Emitter tiles of edge x edge cells (and wall segments of edge faces), each
 // with its LDS window: the whole domain when it fits, else the tile and
-// kWindowHalo cells around it.
-void plan_tiles(InstHost &ih, int edge = kTileX)
+// halo cells around it.
+void plan_tiles(InstHost &ih, int edge = kTileX, int halo = kWindowHalo)
 {
   Inst &d = ih.d;
   const Mesh &m = d.m;
@@ -280,8 +283,8 @@ void plan_tiles(InstHost &ih, int edge = kTileX)
     d.WX = m.nx;
     d.WY = m.ny;
   } else {
-    d.WX = std::min(m.nx, edge + 2 * kWindowHalo);
-    d.WY = std::min(m.ny, edge + 2 * kWindowHalo);
+    d.WX = std::min(m.nx, edge + 2 * halo);
+    d.WY = std::min(m.ny, edge + 2 * halo);
   }
   auto place = [](int lo, int extent, int W, int n) {
     int w0 = lo - (W - extent) / 2;
@@ -781,7 +784,7 @@ int setup_instance(const iugkp_problem *p, const iugkp_options *o, hipStream_t s
   d.tol2 = o->cg_tol * o->cg_tol;
   d.cg_max = o->cg_max_iters;
   d.F = scale_exponent(p, tmin, wall, T0, src);
-  plan_tiles(ih);
+  plan_tiles(ih, kTileX, (multi_cg && d.has_null) ? kWindowHaloNull : kWindowHalo);
 
 #define ALLOC(ptr, n) \
   if (ih.alloc(&(ptr), (n)) != hipSuccess) return fail(IUGKP_E_NOMEM, "hipMalloc failed");
